@@ -1,0 +1,378 @@
+/*
+ * oracle.c -- plain single-threaded CPU oracle of the trace tally.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the tests, the smoke check and the benchmark's CPU
+ * baseline do.  It shares no header, helper, table or constant with the GPU
+ * path and parses the record bytes itself.
+ *
+ * What it computes (the tally of the paper's section 3.4 and the worked
+ * table of section 4.3, with the interval definition of section 3.3):
+ * every API call is an entry event followed later, on the same thread, by
+ * an exit event (section 3.2: all API entry and exit points are traced);
+ * its interval is [entry ts, exit ts] (section 3.3, interval plugins); the
+ * tally keeps, per function, the number of calls and the summed, minimum and
+ * maximum inclusive duration (the Time / Calls / Min / Max columns of the
+ * section 4.3 table, where Time is inclusive: a HIP call and the Level-Zero
+ * calls nested in it are both counted).  Threads are told apart by host,
+ * process and thread id (the record of section 1.1); LTTng may drop events
+ * (section 3.1), so unmatched events are counted, not assumed away.
+ *
+ * Per stream (chunks in submit order), per record in order:
+ *   kernel record (kind 2): if kernel_id < n_kernel_ids and end >= start,
+ *     K[stream, kernel_id] += {1, end-start}; otherwise a bad record.
+ *   entry (kind 0, fn < n_fns): ts below the thread's previous API ts counts
+ *     a ts regression; push {fn, ts, child = 0, bytes}; a stack deeper than
+ *     max_depth marks the thread as overflowed.
+ *   exit (kind 1, fn < n_fns): ts regression as above; empty stack -> orphan
+ *     exit; else pop e: e.fn != fn -> fn mismatch (not tallied, nothing added
+ *     to the parent); ts < e.ts -> negative duration (same); else
+ *     incl = ts - e.ts, self = incl - e.child (or 0 and a self underflow when
+ *     e.child > incl), T[stream, tid, fn] += {1, incl, self, e.bytes} and the
+ *     new stack top (if any) gets child += incl.
+ *   anything else: a bad record.
+ * Final flush: every entry still open counts as unclosed and is not tallied.
+ * All arithmetic is unsigned 64-bit integer (modulo 2^64).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---------------------------------------------------------------- maps */
+/* Open addressing on a (u64, u64) key.  Obviously-correct, not fast. */
+typedef struct { uint64_t a, b; int used; uint32_t val; } slot_t;
+typedef struct { slot_t *s; size_t cap, n; } map_t;
+
+static uint64_t mix(uint64_t x) {
+  x ^= x >> 33; x *= 0xff51afd7ed558ccdull; x ^= x >> 33; x *= 0xc4ceb9fe1a85ec53ull; x ^= x >> 33;
+  return x;
+}
+static void map_init(map_t *m) { m->cap = 1024; m->n = 0; m->s = (slot_t *)calloc(m->cap, sizeof(slot_t)); }
+static void map_free(map_t *m) { free(m->s); m->s = NULL; m->cap = m->n = 0; }
+static slot_t *map_find(map_t *m, uint64_t a, uint64_t b) {
+  size_t i = (size_t)(mix(a * 31 + mix(b)) & (m->cap - 1));
+  for (;;) {
+    slot_t *s = &m->s[i];
+    if (!s->used) return s;
+    if (s->a == a && s->b == b) return s;
+    i = (i + 1) & (m->cap - 1);
+  }
+}
+static void map_grow(map_t *m) {
+  map_t n; n.cap = m->cap * 2; n.n = 0; n.s = (slot_t *)calloc(n.cap, sizeof(slot_t));
+  for (size_t i = 0; i < m->cap; i++)
+    if (m->s[i].used) { slot_t *d = map_find(&n, m->s[i].a, m->s[i].b); *d = m->s[i]; n.n++; }
+  free(m->s); *m = n;
+}
+/* returns the value index for the key, inserting `fresh` when absent */
+static uint32_t map_get(map_t *m, uint64_t a, uint64_t b, uint32_t fresh, int *inserted) {
+  if ((m->n + 1) * 2 > m->cap) map_grow(m);
+  slot_t *s = map_find(m, a, b);
+  if (s->used) { *inserted = 0; return s->val; }
+  s->used = 1; s->a = a; s->b = b; s->val = fresh; m->n++;
+  *inserted = 1;
+  return fresh;
+}
+
+/* ------------------------------------------------------------- state */
+typedef struct { uint16_t fn; uint64_t ts, child, bytes; } frame_t;
+typedef struct {
+  uint32_t stream, tid;
+  frame_t *stk; size_t h, cap;
+  uint64_t last_ts; int seen; int overflowed;
+} thread_t;
+typedef struct { uint32_t trace, host, pid; uint64_t st[17]; int has_record; } stream_t;
+typedef struct { uint32_t stream, tid, fn; uint64_t v[8]; } tally_t;   /* count, incl sum/min/max, self sum/min/max, bytes */
+typedef struct { uint32_t stream, kid; uint64_t v[4]; } ktally_t;       /* count, dur sum/min/max */
+
+enum { S_RECORDS, S_ENTRIES, S_EXITS, S_KERNEL, S_ORPHAN, S_MISMATCH, S_NEGDUR, S_SELFUNDER,
+       S_TSREG, S_UNCLOSED, S_OPEN, S_DEPTH, S_BAD, S_DROPPED, S_HOSTS, S_PROCS, S_THREADS, S_N };
+
+typedef struct oracle {
+  int format; uint32_t n_fns, n_kernel_ids, max_depth;
+  uint8_t *has_size;
+  map_t smap, tmap, tally_map, kmap;
+  stream_t *streams; size_t ns, scap;
+  thread_t *threads; size_t nt, tcap;
+  tally_t *tallies; size_t ntal, talcap;
+  ktally_t *kt; size_t nkt, ktcap;
+} oracle;
+
+#define GROW(arr, n, cap) do { if ((n) == (cap)) { (cap) = (cap) ? (cap) * 2 : 64; \
+  (arr) = realloc((arr), (cap) * sizeof(*(arr))); } } while (0)
+
+oracle *oracle_new(int format, uint32_t n_fns, uint32_t n_kernel_ids, uint32_t max_depth,
+                   const uint8_t *has_size) {
+  oracle *o = (oracle *)calloc(1, sizeof(oracle));
+  o->format = format; o->n_fns = n_fns; o->n_kernel_ids = n_kernel_ids; o->max_depth = max_depth;
+  o->has_size = (uint8_t *)calloc(n_fns ? n_fns : 1, 1);
+  if (has_size) memcpy(o->has_size, has_size, n_fns);
+  map_init(&o->smap); map_init(&o->tmap); map_init(&o->tally_map); map_init(&o->kmap);
+  return o;
+}
+
+void oracle_free(oracle *o) {
+  if (!o) return;
+  for (size_t i = 0; i < o->nt; i++) free(o->threads[i].stk);
+  free(o->threads); free(o->streams); free(o->tallies); free(o->kt); free(o->has_size);
+  map_free(&o->smap); map_free(&o->tmap); map_free(&o->tally_map); map_free(&o->kmap);
+  free(o);
+}
+
+static uint64_t rd64(const uint8_t *p) { uint64_t v; memcpy(&v, p, 8); return v; }
+static uint32_t rd32(const uint8_t *p) { uint32_t v; memcpy(&v, p, 4); return v; }
+static uint16_t rd16(const uint8_t *p) { uint16_t v; memcpy(&v, p, 2); return v; }
+
+static uint32_t stream_of(oracle *o, uint32_t trace, uint32_t host, uint32_t pid) {
+  int ins;
+  uint64_t a = ((uint64_t)trace << 32) | host;
+  uint32_t id = map_get(&o->smap, a, pid, (uint32_t)o->ns, &ins);
+  if (ins) {
+    GROW(o->streams, o->ns, o->scap);
+    stream_t *s = &o->streams[o->ns++];
+    memset(s, 0, sizeof *s);
+    s->trace = trace; s->host = host; s->pid = pid;
+  }
+  return id;
+}
+static thread_t *thread_of(oracle *o, uint32_t stream, uint32_t tid) {
+  int ins;
+  uint32_t id = map_get(&o->tmap, stream, tid, (uint32_t)o->nt, &ins);
+  if (ins) {
+    GROW(o->threads, o->nt, o->tcap);
+    thread_t *t = &o->threads[o->nt++];
+    memset(t, 0, sizeof *t);
+    t->stream = stream; t->tid = tid;
+  }
+  return &o->threads[id];
+}
+static void tally_add(oracle *o, uint32_t stream, uint32_t tid, uint16_t fn,
+                      uint64_t incl, uint64_t self, uint64_t bytes) {
+  int ins;
+  uint32_t id = map_get(&o->tally_map, ((uint64_t)stream << 32) | tid, fn, (uint32_t)o->ntal, &ins);
+  if (ins) {
+    GROW(o->tallies, o->ntal, o->talcap);
+    tally_t *t = &o->tallies[o->ntal++];
+    t->stream = stream; t->tid = tid; t->fn = fn;
+    t->v[0] = 0; t->v[1] = 0; t->v[2] = UINT64_MAX; t->v[3] = 0;
+    t->v[4] = 0; t->v[5] = UINT64_MAX; t->v[6] = 0; t->v[7] = 0;
+  }
+  tally_t *t = &o->tallies[id];
+  t->v[0] += 1;
+  t->v[1] += incl; if (incl < t->v[2]) t->v[2] = incl; if (incl > t->v[3]) t->v[3] = incl;
+  t->v[4] += self; if (self < t->v[5]) t->v[5] = self; if (self > t->v[6]) t->v[6] = self;
+  t->v[7] += bytes;
+}
+static void ktally_add(oracle *o, uint32_t stream, uint16_t kid, uint64_t dur) {
+  int ins;
+  uint32_t id = map_get(&o->kmap, stream, kid, (uint32_t)o->nkt, &ins);
+  if (ins) {
+    GROW(o->kt, o->nkt, o->ktcap);
+    ktally_t *k = &o->kt[o->nkt++];
+    k->stream = stream; k->kid = kid;
+    k->v[0] = 0; k->v[1] = 0; k->v[2] = UINT64_MAX; k->v[3] = 0;
+  }
+  ktally_t *k = &o->kt[id];
+  k->v[0] += 1; k->v[1] += dur;
+  if (dur < k->v[2]) k->v[2] = dur;
+  if (dur > k->v[3]) k->v[3] = dur;
+}
+
+/* Validates a chunk like the library does; returns 0 or -1 (nothing changed). */
+static int check_chunk(const oracle *o, const uint8_t *rec, size_t rb, const uint8_t *pay, size_t pb) {
+  size_t rs = o->format == 2 ? 16 : 24;
+  if (rb % rs) return -1;
+  if (rb && !rec) return -1;
+  if (o->format == 2) {
+    uint64_t sum = 0;
+    for (size_t i = 0; i < rb / rs; i++) sum += rec[i * rs + 15];
+    if (sum != pb) return -1;
+    if (pb && !pay) return -1;
+  } else if (pb) {
+    return -1;
+  }
+  return 0;
+}
+
+int oracle_submit(oracle *o, uint32_t trace, uint32_t host, uint32_t pid,
+                  const uint8_t *rec, size_t rec_bytes, const uint8_t *pay, size_t pay_bytes) {
+  if (check_chunk(o, rec, rec_bytes, pay, pay_bytes)) return -1;
+  uint32_t sid = stream_of(o, trace, host, pid);
+  size_t rs = o->format == 2 ? 16 : 24;
+  size_t n = rec_bytes / rs;
+  uint64_t poff = 0;
+  for (size_t i = 0; i < n; i++) {
+    stream_t *st = &o->streams[sid];
+    const uint8_t *r = rec + i * rs;
+    uint64_t ts = rd64(r);
+    uint32_t tid = rd32(r + 8);
+    uint16_t fn = rd16(r + 12);
+    uint8_t kind = r[14];
+    uint32_t plen = o->format == 2 ? r[15] : 0;
+    const uint8_t *p = o->format == 2 ? pay + poff : NULL;
+    poff += plen;
+    st->st[S_RECORDS]++;
+    if (kind == 2) {
+      uint64_t end;
+      int ok = fn < o->n_kernel_ids;
+      if (o->format == 2) { ok = ok && plen >= 8; end = ok ? rd64(p) : 0; }
+      else end = rd64(r + 16);
+      if (ok && end >= ts) {
+        ktally_add(o, sid, fn, end - ts);
+        st->st[S_KERNEL]++;
+        st->has_record = 1;
+      } else {
+        st->st[S_BAD]++;
+      }
+      continue;
+    }
+    if (kind > 1 || fn >= o->n_fns) { st->st[S_BAD]++; continue; }
+    st->has_record = 1;
+    thread_t *t = thread_of(o, sid, tid);
+    st = &o->streams[sid];
+    if (t->seen && ts < t->last_ts) st->st[S_TSREG]++;
+    t->seen = 1; t->last_ts = ts;
+    if (kind == 0) {
+      st->st[S_ENTRIES]++;
+      uint64_t bytes = 0;
+      if (o->format == 2 && o->has_size[fn] && plen >= 8) bytes = rd64(p);
+      if (t->h == t->cap) { t->cap = t->cap ? t->cap * 2 : 16; t->stk = realloc(t->stk, t->cap * sizeof(frame_t)); }
+      frame_t *f = &t->stk[t->h++];
+      f->fn = fn; f->ts = ts; f->child = 0; f->bytes = bytes;
+      if (t->h > o->max_depth) t->overflowed = 1;
+    } else {
+      st->st[S_EXITS]++;
+      if (t->h == 0) { st->st[S_ORPHAN]++; continue; }
+      frame_t e = t->stk[--t->h];
+      if (e.fn != fn) { st->st[S_MISMATCH]++; continue; }
+      if (ts < e.ts) { st->st[S_NEGDUR]++; continue; }
+      uint64_t incl = ts - e.ts, self;
+      if (e.child <= incl) self = incl - e.child;
+      else { self = 0; st->st[S_SELFUNDER]++; }
+      tally_add(o, sid, tid, fn, incl, self, e.bytes);
+      if (t->h) t->stk[t->h - 1].child += incl;
+    }
+  }
+  return 0;
+}
+
+/* Final flush: open entries are counted as unclosed and dropped. */
+void oracle_finish(oracle *o) {
+  for (size_t i = 0; i < o->nt; i++) {
+    thread_t *t = &o->threads[i];
+    o->streams[t->stream].st[S_UNCLOSED] += t->h;
+    t->h = 0;
+  }
+}
+
+/* ---------------------------------------------------------------- read */
+typedef struct {
+  uint32_t trace, host, pid, tid;
+  uint16_t id; uint8_t row_kind; uint8_t pad; uint32_t pad2;
+  uint64_t count, incl_sum, incl_min, incl_max, self_sum, self_min, self_max, bytes_sum;
+} orow_t;
+
+enum { SCOPE_THREAD = 1, SCOPE_PROCESS = 2, SCOPE_FN = 3, SCOPE_KERNEL = 4 };
+#define ALL32 0xFFFFFFFFu
+
+static int row_cmp(const void *x, const void *y) {
+  const orow_t *a = (const orow_t *)x, *b = (const orow_t *)y;
+#define C(f) if (a->f != b->f) return a->f < b->f ? -1 : 1;
+  C(trace) C(host) C(pid) C(tid) C(row_kind) C(id)
+#undef C
+  return 0;
+}
+
+static void merge_into(orow_t *d, const uint64_t *v) {
+  d->count += v[0];
+  d->incl_sum += v[1]; if (v[2] < d->incl_min) d->incl_min = v[2]; if (v[3] > d->incl_max) d->incl_max = v[3];
+  d->self_sum += v[4]; if (v[5] < d->self_min) d->self_min = v[5]; if (v[6] > d->self_max) d->self_max = v[6];
+  d->bytes_sum += v[7];
+}
+
+/* All rows of a scope for a trace filter (ALL32 = every trace), in canonical
+ * order.  Returns the row count; writes at most `cap` rows. */
+size_t oracle_rows(oracle *o, int scope, uint32_t trace_filter, orow_t *out, size_t cap) {
+  orow_t *rows = NULL; size_t n = 0, rcap = 0;
+  if (scope == SCOPE_KERNEL) {
+    for (size_t i = 0; i < o->nkt; i++) {
+      ktally_t *k = &o->kt[i];
+      stream_t *s = &o->streams[k->stream];
+      if (trace_filter != ALL32 && s->trace != trace_filter) continue;
+      GROW(rows, n, rcap);
+      orow_t *r = &rows[n++];
+      memset(r, 0, sizeof *r);
+      r->trace = s->trace; r->host = s->host; r->pid = s->pid; r->tid = ALL32;
+      r->id = (uint16_t)k->kid; r->row_kind = 2;
+      r->count = k->v[0]; r->incl_sum = k->v[1]; r->incl_min = k->v[2]; r->incl_max = k->v[3];
+    }
+  } else {
+    /* one row per finest key, with the summed-away fields blanked ... */
+    for (size_t i = 0; i < o->ntal; i++) {
+      tally_t *t = &o->tallies[i];
+      stream_t *s = &o->streams[t->stream];
+      if (trace_filter != ALL32 && s->trace != trace_filter) continue;
+      GROW(rows, n, rcap);
+      orow_t *r = &rows[n++];
+      memset(r, 0, sizeof *r);
+      r->trace = s->trace; r->host = s->host; r->pid = s->pid; r->tid = t->tid;
+      if (scope == SCOPE_PROCESS) r->tid = ALL32;
+      if (scope == SCOPE_FN) { r->host = ALL32; r->pid = ALL32; r->tid = ALL32; }
+      r->id = (uint16_t)t->fn; r->row_kind = 1;
+      r->incl_min = UINT64_MAX; r->self_min = UINT64_MAX;
+      merge_into(r, t->v);
+    }
+    /* ... then sorted, and equal neighbours merged (sum, min, max) */
+    if (n) qsort(rows, n, sizeof(orow_t), row_cmp);
+    size_t m = 0;
+    for (size_t i = 0; i < n; i++) {
+      if (m && row_cmp(&rows[m - 1], &rows[i]) == 0) {
+        uint64_t v[8] = {rows[i].count, rows[i].incl_sum, rows[i].incl_min, rows[i].incl_max,
+                         rows[i].self_sum, rows[i].self_min, rows[i].self_max, rows[i].bytes_sum};
+        merge_into(&rows[m - 1], v);
+      } else {
+        rows[m++] = rows[i];
+      }
+    }
+    n = m;
+  }
+  if (n) qsort(rows, n, sizeof(orow_t), row_cmp);
+  size_t w = n < cap ? n : cap;
+  if (out && w) memcpy(out, rows, w * sizeof(orow_t));
+  free(rows);
+  return n;
+}
+
+/* Stats summed over the streams of a trace (ALL32 = all traces). */
+void oracle_stats(oracle *o, uint32_t trace_filter, uint64_t *out) {
+  memset(out, 0, S_N * sizeof(uint64_t));
+  for (size_t i = 0; i < o->ns; i++) {
+    stream_t *s = &o->streams[i];
+    if (trace_filter != ALL32 && s->trace != trace_filter) continue;
+    for (int k = 0; k < S_N; k++) out[k] += s->st[k];
+  }
+  out[S_OPEN] = 0;
+  out[S_DEPTH] = 0;
+  for (size_t i = 0; i < o->nt; i++) {
+    thread_t *t = &o->threads[i];
+    stream_t *s = &o->streams[t->stream];
+    if (trace_filter != ALL32 && s->trace != trace_filter) continue;
+    out[S_OPEN] += t->h;
+    out[S_DEPTH] += t->overflowed ? 1 : 0;
+    out[S_THREADS] += 1;
+  }
+  /* processes: streams with a valid record; hosts: distinct (trace, host) among them */
+  map_t hosts; map_init(&hosts);
+  for (size_t i = 0; i < o->ns; i++) {
+    stream_t *s = &o->streams[i];
+    if (trace_filter != ALL32 && s->trace != trace_filter) continue;
+    if (!s->has_record) continue;
+    out[S_PROCS] += 1;
+    int ins;
+    map_get(&hosts, s->trace, s->host, 0, &ins);
+    if (ins) out[S_HOSTS] += 1;
+  }
+  map_free(&hosts);
+}
+
+uint64_t oracle_row_size(void) { return sizeof(orow_t); }

@@ -1,0 +1,199 @@
+/*
+ * thapi_tally.h -- C ABI of the MI355X trace-tally library.
+ *
+ * The library turns streams of API entry/exit records into exact per-API
+ * tallies on one AMD Instinct MI355X (gfx950).  The problem it solves is the
+ * one the paper's Tally view states (THAPI, section 3.4 "Babeltrace2 Analysis
+ * Tools", and the worked table of section 4.3): for every function, the
+ * number of calls and the summed, minimum and maximum inclusive duration
+ * (Time / Calls / Min / Max; Average and Time(%) derive from them), plus the
+ * number of hosts, processes and threads.  Intervals come from the start and
+ * end events of each call (section 3.3, interval plugins).  Threads are
+ * identified by host, process id and thread id (the event record of
+ * section 1.1).  This library additionally keeps self time (inclusive time
+ * minus the inclusive time of direct children), per-thread and per-process
+ * breakdowns and, for variable-length records, summed transfer sizes.
+ *
+ * All arithmetic is unsigned 64-bit integer nanoseconds; results are
+ * bit-exact and independent of how the input is chunked.
+ *
+ * Every function returns an int status: THAPI_OK (0) or a negative
+ * THAPI_E_* code.  No exception crosses the ABI.  A call that fails leaves
+ * the handle's state unchanged unless stated otherwise.
+ */
+#ifndef THAPI_TALLY_H
+#define THAPI_TALLY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define THAPI_TALLY_ABI_VERSION 1u
+
+/* ---- status codes ------------------------------------------------------ */
+#define THAPI_OK            0
+#define THAPI_E_INVAL      -1  /* null argument, bad ABI version, bad config, record bytes not a
+                                  multiple of the record size, payload size != sum of payload_len */
+#define THAPI_E_NOMEM      -2  /* device allocation failed, or a chunk larger than the whole budget */
+#define THAPI_E_AGAIN      -3  /* over the device budget with THAPI_NONBLOCKING: retry later */
+#define THAPI_E_DEPTH      -4  /* some thread's call stack exceeded max_depth; handle is failed */
+#define THAPI_E_MALFORMED  -5  /* THAPI_STRICT only: an anomaly counter is non-zero after a flush */
+#define THAPI_E_DEVICE     -6  /* a HIP call failed; sticky, only read(stats)/close stay valid */
+#define THAPI_E_BUFSZ      -7  /* read: capacity too small, *n_rows holds the required count */
+#define THAPI_E_CAPACITY   -8  /* more streams/threads than configured, or more than the per-range
+                                  thread limit (THAPI_MAX_RANGE_THREADS) in one range; handle is failed */
+#define THAPI_E_STATE      -9  /* call not valid now (submit after the final flush, use after failure) */
+
+/* ---- record formats (all little-endian) -------------------------------- *
+ * THAPI_FMT_FIXED24, 24 bytes per record:
+ *   API record    [0,8) ts u64 | [8,12) tid u32 | [12,14) fn u16 | [14] kind u8
+ *                 (0 = entry, 1 = exit) | [15] reserved | [16,24) ignored
+ *   kernel record [0,8) start u64 | [8,12) queue u32 | [12,14) kernel_id u16 |
+ *                 [14] kind = 2 | [15] reserved | [16,24) end u64
+ * THAPI_FMT_VAR16, 16-byte header + payload heap:
+ *   header        [0,8) ts u64 | [8,12) tid u32 | [12,14) fn u16 | [14] kind u8 |
+ *                 [15] payload_len u8 (0..255)
+ *   payloads are concatenated in record order in a separate buffer; record i's
+ *   payload starts at the sum of payload_len over records before it in the
+ *   same chunk.  An entry of a function with fn_has_size[fn] != 0 and
+ *   payload_len >= 8 carries its u64 transfer size at payload offset 0 (the
+ *   typed "size" argument of the section 1.1 record).  A kernel record carries
+ *   its u64 end time at payload offset 0 and needs payload_len >= 8.
+ * Host and process come from the stream key, not from the record. */
+#define THAPI_FMT_FIXED24 1u
+#define THAPI_FMT_VAR16   2u
+
+/* ---- open flags -------------------------------------------------------- */
+#define THAPI_DEVICE_INPUT 0x01u /* submit() takes device pointers (e.g. a torch tensor's data_ptr) */
+#define THAPI_NONBLOCKING  0x02u /* submit() over budget returns THAPI_E_AGAIN instead of waiting */
+#define THAPI_DROP_ON_FULL 0x04u /* submit() over budget drops the chunk and counts its records */
+#define THAPI_STRICT       0x08u /* flush() returns THAPI_E_MALFORMED when any anomaly was counted */
+#define THAPI_PROFILE      0x10u /* time every kernel with HIP events (see thapi_tally_timings) */
+
+/* ---- flush / read ------------------------------------------------------ */
+#define THAPI_TICKET_ALL  UINT64_MAX
+#define THAPI_FLUSH_FINAL 0x1u   /* close every stream: open calls become unclosed_final */
+
+#define THAPI_SCOPE_THREAD  1u   /* one row per (trace, host, pid, tid, fn) */
+#define THAPI_SCOPE_PROCESS 2u   /* one row per (trace, host, pid, fn); tid = THAPI_ALL */
+#define THAPI_SCOPE_FN      3u   /* one row per (trace, fn); host = pid = tid = THAPI_ALL */
+#define THAPI_SCOPE_KERNEL  4u   /* one row per (trace, host, pid, kernel_id); tid = THAPI_ALL */
+#define THAPI_ALL 0xFFFFFFFFu
+
+#define THAPI_ROW_API    1u
+#define THAPI_ROW_KERNEL 2u
+
+#define THAPI_MAX_DEPTH_LIMIT   64u  /* max_depth may not exceed this */
+#define THAPI_MAX_RANGE_THREADS 64u  /* distinct threads one stream may interleave within one range */
+
+typedef struct thapi_tally thapi_tally; /* opaque, owned by the library */
+
+typedef struct {
+  uint32_t abi_version;         /* must equal THAPI_TALLY_ABI_VERSION */
+  uint32_t format;              /* THAPI_FMT_FIXED24 or THAPI_FMT_VAR16 */
+  uint32_t n_fns;               /* API fn ids must be < n_fns (1..65536) */
+  uint32_t n_kernel_ids;        /* kernel ids must be < n_kernel_ids (0..65536) */
+  uint32_t max_depth;           /* per-thread call-stack limit, 1..64; 0 -> 16 */
+  uint32_t max_threads;         /* distinct (stream, tid) over the handle's life; 0 -> 65536 */
+  uint32_t max_streams;         /* distinct stream keys over the handle's life; 0 -> 4096 */
+  uint32_t flags;               /* THAPI_DEVICE_INPUT | THAPI_NONBLOCKING | ... */
+  const uint8_t *fn_has_size;   /* VAR16: n_fns flags, copied at open; may be NULL (no sizes) */
+  uint64_t device_budget_bytes; /* bytes of staged chunks admitted at once; 0 -> 16 GiB */
+  int32_t device;               /* HIP device ordinal */
+  uint32_t reserved;            /* must be 0 */
+  void *hip_stream;             /* hipStream_t to launch on (e.g. torch's current stream); NULL = own */
+  const char *autotune_cache;   /* path of the launch-shape cache file, or NULL */
+} thapi_tally_config;
+
+typedef struct {
+  uint32_t trace_id, host_id, pid, reserved; /* reserved must be 0 */
+} thapi_stream_key;
+
+typedef struct {                /* 88 bytes, naturally aligned */
+  uint32_t trace_id, host_id, pid, tid;
+  uint16_t id;                  /* fn id (API rows) or kernel id (kernel rows) */
+  uint8_t row_kind;             /* THAPI_ROW_API or THAPI_ROW_KERNEL */
+  uint8_t pad;
+  uint32_t pad2;
+  uint64_t count;
+  uint64_t incl_sum, incl_min, incl_max; /* kernel rows: device duration end - start */
+  uint64_t self_sum, self_min, self_max; /* kernel rows: 0 */
+  uint64_t bytes_sum;                    /* VAR16 transfer sizes of tallied calls */
+} thapi_tally_row;
+
+typedef struct {
+  uint64_t records;        /* records consumed */
+  uint64_t entries, exits; /* valid API entry / exit records */
+  uint64_t kernel_records; /* valid kernel records (tallied) */
+  uint64_t orphan_exits;   /* exit with an empty stack (skipped) */
+  uint64_t fn_mismatch;    /* exit whose fn differs from the popped entry's (not tallied) */
+  uint64_t neg_duration;   /* exit earlier than its entry (not tallied) */
+  uint64_t self_underflow; /* children longer than the call: self time clamped to 0 */
+  uint64_t ts_regress;     /* API record earlier than the thread's previous one */
+  uint64_t unclosed_final; /* entries still open at the final flush (not tallied) */
+  uint64_t open_now;       /* entries open right now */
+  uint64_t depth_overflow; /* threads whose stack ever exceeded max_depth */
+  uint64_t bad_records;    /* unknown kind, fn/kernel id out of range, kernel end < start */
+  uint64_t dropped_records;/* records of chunks dropped under THAPI_DROP_ON_FULL */
+  uint64_t distinct_hosts, distinct_processes, distinct_threads;
+} thapi_tally_stats;
+
+/* Opens a handle on cfg->device.  Allocates all device tables up front
+ * (tallies: max_threads * n_fns * 64 B; stacks: max_threads * max_depth * 32 B).
+ * *out is set only on success.  Errors: THAPI_E_INVAL (bad config),
+ * THAPI_E_NOMEM, THAPI_E_DEVICE. */
+int thapi_tally_open(const thapi_tally_config *cfg, thapi_tally **out);
+
+/* Queues one chunk of one stream.  Chunks of one key are applied in submit
+ * order; keys are independent.  Host input (default) is copied before the
+ * call returns, so the caller may reuse its buffers at once; with
+ * THAPI_DEVICE_INPUT the pointers are device memory that must stay valid and
+ * unmodified until a flush covering the returned ticket has returned.
+ * payload/payload_bytes are used by VAR16 only (must be NULL/0 for FIXED24).
+ * Thread-safe.  Errors: THAPI_E_INVAL, THAPI_E_NOMEM, THAPI_E_AGAIN,
+ * THAPI_E_CAPACITY (too many streams), THAPI_E_STATE. */
+int thapi_tally_submit(thapi_tally *t, const thapi_stream_key *key,
+                       const void *records, size_t record_bytes,
+                       const void *payload, size_t payload_bytes, uint64_t *ticket_out);
+
+/* Runs every queued chunk up to `ticket` (THAPI_TICKET_ALL: all) through the
+ * GPU pipeline and waits for it.  THAPI_FLUSH_FINAL also closes all streams:
+ * open entries become unclosed_final and no further submit is accepted.
+ * Errors: THAPI_E_DEPTH, THAPI_E_CAPACITY, THAPI_E_MALFORMED (STRICT),
+ * THAPI_E_DEVICE, THAPI_E_STATE. */
+int thapi_tally_flush(thapi_tally *t, uint64_t ticket, uint32_t flags);
+
+/* Reads the tally of everything flushed so far for one scope and trace
+ * (THAPI_ALL = all traces), in canonical order (trace, host, pid, tid,
+ * row_kind, id).  rows may be NULL when capacity is 0 (size query).
+ * *n_rows receives the number of rows of the scope; if it exceeds capacity,
+ * nothing is written to rows and THAPI_E_BUFSZ is returned.  stats (may be
+ * NULL) receives the counters summed over the selected traces. */
+int thapi_tally_read(thapi_tally *t, uint32_t scope, uint32_t trace_id,
+                     thapi_tally_row *rows, size_t capacity, size_t *n_rows,
+                     thapi_tally_stats *stats);
+
+/* Forgets every tally, stack, stream and counter (device memory is kept) so
+ * the handle can start a new trace set.  Not valid while submits are queued. */
+int thapi_tally_reset(thapi_tally *t);
+
+/* Frees everything.  Queued chunks that were never flushed are discarded. */
+int thapi_tally_close(thapi_tally *t);
+
+/* Static English text for a status code; never NULL. */
+const char *thapi_tally_strerror(int code);
+
+/* THAPI_PROFILE only: per-kernel durations (ms) of the last flush and read,
+ * measured with HIP events on the launch stream, in the order
+ * {prepass, main, combine, final, readout}; entries that did not run are 0.
+ * n: capacity of ms[]; returns the number of entries written. */
+int thapi_tally_timings(thapi_tally *t, double *ms, int n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* THAPI_TALLY_H */

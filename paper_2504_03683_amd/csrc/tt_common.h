@@ -1,0 +1,117 @@
+// tt_common.h -- device-side layouts shared by the library's kernels and host runtime.
+//
+// Everything is integer: timestamps are u64 ns, sums/min/max are u64.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tt {
+
+constexpr int WAVE = 64;
+constexpr int WG = 256;              // workgroup of the range kernel
+constexpr int NWAVES = WG / WAVE;
+constexpr int S_MAX = 64;            // distinct threads one range may interleave (== THAPI_MAX_RANGE_THREADS)
+constexpr int TIDMAP = 256;          // LDS buckets of the tid -> local slot map (power of two)
+constexpr uint32_t EMPTY32 = 0xFFFFFFFFu;
+constexpr uint64_t EMPTY64 = ~0ull;
+constexpr uint32_t GV_PENDING = 0xFFFFFFFFu;  // global thread map: slot id not published yet
+constexpr uint32_t GV_INVALID = 0xFFFFFFFEu;  // global thread map: capacity exceeded
+constexpr uint32_t KL_MAX = 256;     // kernel ids pre-aggregated in LDS; larger ids go to global atomics
+
+// Per-stream counters kept on the device (indices into a [stream][ST_N] u64 array).
+enum : int {
+  ST_RECORDS = 0, ST_ENTRIES, ST_EXITS, ST_KERNEL, ST_ORPHAN, ST_MISMATCH, ST_NEGDUR, ST_UNDER,
+  ST_TSREG, ST_UNCLOSED, ST_BAD, ST_N
+};
+
+// Error bits raised by kernels (sticky per flush).
+enum : uint32_t { ERR_CAPACITY = 1u, ERR_RANGE_THREADS = 2u, ERR_DEPTH = 4u };
+
+// One submitted chunk, as the kernels see it.
+struct Seg {
+  const uint8_t *rec;   // record bytes (8-byte aligned)
+  const uint8_t *pay;   // VAR16 payload heap (any alignment) or null
+  uint64_t n_rec;
+  uint64_t pay_bytes;
+  uint32_t stream;
+  uint32_t pad;
+};
+
+// A contiguous run of one segment's records processed by one workgroup.
+struct Range {
+  uint32_t seg;
+  uint32_t stream;
+  uint64_t begin;       // first record (index into the segment)
+  uint64_t n;           // records
+  uint64_t pay_begin;   // VAR16: payload offset of `begin` within the segment (filled on device)
+};
+
+// Summary a range leaves for one of its threads (the boundary of the range):
+// exits that closed calls opened before the range (U items, in order), the
+// children time those calls accumulated inside the range, the calls still
+// open at the range end (O items, bottom to top), and the depth excursion.
+struct RHdr {
+  uint32_t gslot;       // global thread slot
+  uint32_t nu_listed;   // U items stored (<= max_depth)
+  uint32_t nu_total;    // exits that found the range-local stack empty
+  uint32_t n_o;         // calls open at the range end (stored: min(n_o, max_depth))
+  uint64_t floor;       // children time owed to the call below the range's own entries
+  int32_t H, M;         // depth excursion: max over the range of h and of (h - u)
+  uint64_t first_ts, last_ts;  // first / last API timestamp of the thread in the range
+  uint32_t flags;       // RF_*
+  uint32_t pad;
+  uint64_t pad2;
+};
+enum : uint32_t { RF_HAS_TS = 1u, RF_OVERFLOW = 2u };
+
+struct UItem { uint64_t ts, child; uint32_t fn, pad; uint64_t pad2; };
+struct OItem { uint64_t ts, child, bytes; uint32_t fn, pad; };
+
+// Global tally of one (thread, fn): the fields of a result row.
+struct Tally { uint64_t count, incl_sum, incl_min, incl_max, self_sum, self_min, self_max, bytes_sum; };
+struct KTally { uint64_t count, sum, min, max; };
+
+// Per-thread state carried on the device across ranges and flushes.
+struct CState { uint32_t h; uint32_t flags; uint64_t last_ts; };
+enum : uint32_t { CS_HAS_TS = 1u, CS_OVERFLOW = 2u };
+struct Frame { uint64_t ts, child, bytes; uint32_t fn, pad; };
+
+// Device tables of one handle.
+struct Tables {
+  uint64_t *gkeys;      // thread map keys: (stream << 32) | tid, EMPTY64 = free
+  uint32_t *gvals;      // thread map values: global slot
+  uint32_t gmask;       // capacity - 1
+  uint32_t *n_gslots;
+  uint32_t max_threads;
+  uint32_t *th_stream, *th_tid;
+  Tally *tally;         // [max_threads][n_fns]
+  uint32_t n_fns;
+  KTally *ktally;       // [max_streams][n_kid]
+  uint32_t n_kid;
+  CState *cstate;       // [max_threads]
+  Frame *cstack;        // [max_threads][D]
+  uint32_t D;           // max_depth
+  unsigned long long *sstats;  // [max_streams][ST_N]
+  uint32_t *err;
+  const uint8_t *has_size;     // [n_fns] or null
+};
+
+// Launch shape of the range kernel (tile T records, tally hash E entries).
+struct Shape {
+  uint32_t T;           // records per tile (multiple of WG)
+  uint32_t E;           // LDS tally entries (power of two)
+  uint32_t KL;          // kernel ids pre-aggregated in LDS (<= KL_MAX)
+  uint32_t lds_bytes;
+};
+
+__host__ __device__ inline uint32_t hash32(uint32_t x) {
+  x ^= x >> 16; x *= 0x7feb352du; x ^= x >> 15; x *= 0x846ca68bu; x ^= x >> 16;
+  return x;
+}
+__host__ __device__ inline uint64_t hash64(uint64_t x) {
+  x ^= x >> 33; x *= 0xff51afd7ed558ccdull; x ^= x >> 33; x *= 0xc4ceb9fe1a85ec53ull; x ^= x >> 33;
+  return x;
+}
+
+}  // namespace tt

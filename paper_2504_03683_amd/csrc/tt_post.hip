@@ -1,0 +1,435 @@
+// tt_post.hip -- kernels after the range pass: the carry combine, the final
+// flush, per-stream thread statistics and the readout (canonical ordering,
+// compaction and rollups of the tally tables into result rows).
+#include "tt_common.h"
+
+namespace tt {
+
+__device__ inline void ga64(uint64_t *p, uint64_t v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void gmin64(uint64_t *p, uint64_t v) {
+  __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void gmax64(uint64_t *p, uint64_t v) {
+  __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------- combine
+// One workgroup per stream that had ranges in this flush.  Each distinct
+// thread of the stream is owned by one lane, which folds the thread's range
+// summaries in range order onto the thread's carried stack: every U item pops
+// the call it closes (orphan exit when the stack is empty), checks fn and
+// time order, tallies inclusive and self time and credits the parent; the
+// range's floor time goes to the call left on top; O items are pushed.
+constexpr int CB_SET = 2048;
+
+__global__ __launch_bounds__(256) void k_combine(const uint32_t *__restrict__ spans, const RHdr *__restrict__ rhdr,
+                                                 const UItem *__restrict__ ru, const OItem *__restrict__ ro,
+                                                 const uint32_t *__restrict__ rnslots, Tables tb) {
+  __shared__ uint32_t set_key[CB_SET];
+  __shared__ uint32_t list[CB_SET];
+  __shared__ uint32_t nlist;
+  __shared__ uint32_t lcnt[ST_N];
+  const uint32_t stream = spans[3 * blockIdx.x], rb = spans[3 * blockIdx.x + 1], re = spans[3 * blockIdx.x + 2];
+  const int tid = threadIdx.x;
+  const uint32_t D = tb.D;
+  for (int i = tid; i < CB_SET; i += 256) set_key[i] = EMPTY32;
+  if (tid < ST_N) lcnt[tid] = 0;
+  if (tid == 0) nlist = 0;
+  __syncthreads();
+  for (uint32_t r = rb; r < re; r++) {
+    const uint32_t ns = rnslots[r];
+    for (uint32_t s = tid; s < ns; s += 256) {
+      const uint32_t g = rhdr[(size_t)r * S_MAX + s].gslot;
+      if (g >= tb.max_threads) continue;
+      uint32_t h = hash32(g) & (CB_SET - 1);
+      for (int probe = 0; probe < CB_SET; probe++) {
+        const uint32_t old = atomicCAS(&set_key[h], EMPTY32, g);
+        if (old == EMPTY32) {
+          const uint32_t k = atomicAdd(&nlist, 1u);
+          if (k < CB_SET) list[k] = g;
+          break;
+        }
+        if (old == g) break;
+        h = (h + 1) & (CB_SET - 1);
+      }
+    }
+  }
+  __syncthreads();
+  const uint32_t n = nlist < CB_SET ? nlist : CB_SET;
+  if (tid == 0 && nlist >= (uint32_t)CB_SET) atomicOr(tb.err, ERR_CAPACITY);
+  uint32_t c_tsreg = 0, c_orphan = 0, c_mis = 0, c_neg = 0, c_under = 0;
+  for (uint32_t i = tid; i < n; i += 256) {
+    const uint32_t g = list[i];
+    CState cs = tb.cstate[g];
+    Frame *stk = tb.cstack + (size_t)g * D;
+    for (uint32_t r = rb; r < re; r++) {
+      const uint32_t ns = rnslots[r];
+      const RHdr *hp = rhdr + (size_t)r * S_MAX;
+      uint32_t s = 0;
+      while (s < ns && hp[s].gslot != g) s++;
+      if (s == ns) continue;
+      const RHdr hd = hp[s];
+      const size_t ib = ((size_t)r * S_MAX + s) * D;
+      if (hd.flags & RF_HAS_TS) {
+        if ((cs.flags & CS_HAS_TS) && hd.first_ts < cs.last_ts) c_tsreg++;
+        cs.last_ts = hd.last_ts;
+        cs.flags |= CS_HAS_TS;
+      }
+      const int32_t ds = (int32_t)cs.h;
+      if ((hd.flags & RF_OVERFLOW) || hd.H > (int32_t)D || ds + hd.M > (int32_t)D) cs.flags |= CS_OVERFLOW;
+      for (uint32_t k = 0; k < hd.nu_listed; k++) {
+        const UItem u = ru[ib + k];
+        if (cs.h == 0) { c_orphan++; continue; }
+        cs.h--;
+        const Frame e = stk[cs.h];
+        if (e.fn != u.fn) { c_mis++; continue; }
+        if (u.ts < e.ts) { c_neg++; continue; }
+        const uint64_t incl = u.ts - e.ts;
+        const uint64_t ch = e.child + u.child;
+        uint64_t self;
+        if (ch <= incl) self = incl - ch; else { self = 0; c_under++; }
+        Tally *t = &tb.tally[(size_t)g * tb.n_fns + u.fn];
+        ga64(&t->count, 1);
+        ga64(&t->incl_sum, incl); gmin64(&t->incl_min, incl); gmax64(&t->incl_max, incl);
+        ga64(&t->self_sum, self); gmin64(&t->self_min, self); gmax64(&t->self_max, self);
+        if (e.bytes) ga64(&t->bytes_sum, e.bytes);
+        if (cs.h > 0) stk[cs.h - 1].child += incl;
+      }
+      if (cs.h > 0) stk[cs.h - 1].child += hd.floor;
+      const uint32_t no = hd.n_o < D ? hd.n_o : D;
+      for (uint32_t k = 0; k < no; k++) {
+        if (cs.h < D) {
+          const OItem o = ro[ib + k];
+          Frame f;
+          f.ts = o.ts; f.child = o.child; f.bytes = o.bytes; f.fn = o.fn; f.pad = 0;
+          stk[cs.h] = f;
+          cs.h++;
+        } else {
+          cs.flags |= CS_OVERFLOW;
+        }
+      }
+    }
+    if (cs.flags & CS_OVERFLOW) atomicOr(tb.err, ERR_DEPTH);
+    tb.cstate[g] = cs;
+  }
+  if (c_tsreg) atomicAdd(&lcnt[ST_TSREG], c_tsreg);
+  if (c_orphan) atomicAdd(&lcnt[ST_ORPHAN], c_orphan);
+  if (c_mis) atomicAdd(&lcnt[ST_MISMATCH], c_mis);
+  if (c_neg) atomicAdd(&lcnt[ST_NEGDUR], c_neg);
+  if (c_under) atomicAdd(&lcnt[ST_UNDER], c_under);
+  __syncthreads();
+  if (tid < ST_N && lcnt[tid]) atomicAdd(&tb.sstats[(size_t)stream * ST_N + tid], (unsigned long long)lcnt[tid]);
+}
+
+// Final flush: every call still open is counted as unclosed and forgotten.
+__global__ void k_final(Tables tb) {
+  const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= *tb.n_gslots || g >= tb.max_threads) return;
+  const uint32_t h = tb.cstate[g].h;
+  if (h) {
+    atomicAdd(&tb.sstats[(size_t)tb.th_stream[g] * ST_N + ST_UNCLOSED], (unsigned long long)h);
+    tb.cstate[g].h = 0;
+  }
+}
+
+// Per-stream thread statistics: threads, open calls, overflowed threads.
+__global__ void k_thread_stats(Tables tb, unsigned long long *__restrict__ out /* [stream][3] */) {
+  const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= *tb.n_gslots || g >= tb.max_threads) return;
+  const uint32_t s = tb.th_stream[g];
+  atomicAdd(&out[3 * s + 0], 1ull);
+  const CState cs = tb.cstate[g];
+  if (cs.h) atomicAdd(&out[3 * s + 1], (unsigned long long)cs.h);
+  if (cs.flags & CS_OVERFLOW) atomicAdd(&out[3 * s + 2], 1ull);
+}
+
+// --------------------------------------------------------------- readout
+// Thread keys in canonical order: key = (canonical stream rank << 32) | tid;
+// streams outside the trace filter get rank 0xFFFFFFFF and sort last.
+__global__ void k_thread_keys(Tables tb, const uint32_t *__restrict__ stream_rank, uint64_t *__restrict__ keys,
+                              uint32_t *__restrict__ vals, uint32_t n) {
+  const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  keys[g] = ((uint64_t)stream_rank[tb.th_stream[g]] << 32) | tb.th_tid[g];
+  vals[g] = g;
+}
+
+// Stable LSD radix sort of (key, val) pairs by one workgroup of 1024 lanes,
+// 8-bit digits; bits [lo_bit, hi_bit) of the key are sorted.  Each pass:
+// digit histogram, exclusive scan, then a stable scatter in chunks of 1024
+// where a record's rank among equal digits in its wave comes from ballots.
+constexpr int RS_WG = 1024;
+__global__ __launch_bounds__(RS_WG) void k_radix_sort(uint64_t *keys, uint32_t *vals, uint64_t *keys2,
+                                                      uint32_t *vals2, uint32_t n, int lo_bit, int hi_bit) {
+  __shared__ uint32_t hist[256];
+  __shared__ uint32_t base[256];
+  __shared__ uint32_t wc[RS_WG / WAVE][256];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  uint64_t *ks = keys, *kd = keys2;
+  uint32_t *vs = vals, *vd = vals2;
+  for (int b = lo_bit; b < hi_bit; b += 8) {
+    for (int i = tid; i < 256; i += RS_WG) hist[i] = 0;
+    __syncthreads();
+    for (uint32_t i = tid; i < n; i += RS_WG) atomicAdd(&hist[(ks[i] >> b) & 0xFF], 1u);
+    __syncthreads();
+    if (tid == 0) {
+      uint32_t acc = 0;
+      for (int d = 0; d < 256; d++) { base[d] = acc; acc += hist[d]; }
+    }
+    __syncthreads();
+    for (uint32_t c0 = 0; c0 < n; c0 += RS_WG) {
+      for (int i = lane; i < 256; i += WAVE) wc[w][i] = 0;
+      const uint32_t i = c0 + tid;
+      const bool valid = i < n;
+      const uint64_t k = valid ? ks[i] : 0;
+      const uint32_t v = valid ? vs[i] : 0;
+      const uint32_t d = (uint32_t)(k >> b) & 0xFF;
+      uint64_t mask = __ballot(valid);
+      for (int bit = 0; bit < 8; bit++) {
+        const uint64_t bb = __ballot(valid && ((d >> bit) & 1u));
+        mask &= ((d >> bit) & 1u) ? bb : ~bb;
+      }
+      const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+      const uint32_t rk = (uint32_t)__popcll(mask & lt);
+      if (valid && rk == 0) wc[w][d] = (uint32_t)__popcll(mask);
+      __syncthreads();
+      if (valid) {
+        uint32_t pre = 0;
+        for (int ww = 0; ww < w; ww++) pre += wc[ww][d];
+        const uint32_t pos = base[d] + pre + rk;
+        kd[pos] = k;
+        vd[pos] = v;
+      }
+      __syncthreads();
+      if (tid < 256) {
+        uint32_t tot = 0;
+        for (int ww = 0; ww < RS_WG / WAVE; ww++) tot += wc[ww][tid];
+        base[tid] += tot;
+      }
+      __syncthreads();
+    }
+    uint64_t *tk = ks; ks = kd; kd = tk;
+    uint32_t *tv = vs; vs = vd; vd = tv;
+  }
+  // the result must end in keys/vals: copy back after an odd number of passes
+  if (ks != keys) {
+    for (uint32_t i = tid; i < n; i += RS_WG) { keys[i] = ks[i]; vals[i] = vs[i]; }
+  }
+}
+
+// Group bounds: for every canonical stream rank, the positions of its threads
+// in the sorted key array.
+__global__ void k_group_bounds(const uint64_t *__restrict__ keys, uint32_t n, uint32_t *__restrict__ gbeg,
+                               uint32_t *__restrict__ gend, uint32_t n_ranks) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t sr = (uint32_t)(keys[i] >> 32);
+  if (sr >= n_ranks) return;
+  if (i == 0 || (uint32_t)(keys[i - 1] >> 32) != sr) gbeg[sr] = i;
+  if (i == n - 1 || (uint32_t)(keys[i + 1] >> 32) != sr) gend[sr] = i + 1;
+}
+
+// Row groups: a group emits one row per id (fn or kernel id) with a non-empty
+// tally, ids ascending.  mode 1 THREAD: group = a thread (sorted position);
+// mode 2 PROCESS: group = a canonical stream, members = its threads; mode 3 FN:
+// group = a trace, members = the threads of its streams; mode 4 KERNEL: group
+// = a canonical stream, source = its kernel tallies.
+struct RowCtx {
+  int mode;
+  uint32_t n_ids;                 // n_fns or n_kid
+  const uint64_t *keys;           // sorted thread keys
+  const uint32_t *vals;           // sorted thread slots
+  const uint32_t *gbeg, *gend;    // per canonical stream rank
+  const uint32_t *rank_stream;    // canonical rank -> stream index
+  const uint32_t *rank_key;       // canonical rank -> (trace, host, pid) as 3 u32
+  const uint32_t *trace_span;     // FN mode: group -> [rank_begin, rank_end)
+};
+
+struct Acc { uint64_t v[8]; };
+
+__device__ inline void acc_init(Acc &a) {
+  a.v[0] = 0; a.v[1] = 0; a.v[2] = ~0ull; a.v[3] = 0; a.v[4] = 0; a.v[5] = ~0ull; a.v[6] = 0; a.v[7] = 0;
+}
+__device__ inline void acc_add(Acc &a, const Tally &t) {
+  a.v[0] += t.count;
+  a.v[1] += t.incl_sum; a.v[2] = t.incl_min < a.v[2] ? t.incl_min : a.v[2]; a.v[3] = t.incl_max > a.v[3] ? t.incl_max : a.v[3];
+  a.v[4] += t.self_sum; a.v[5] = t.self_min < a.v[5] ? t.self_min : a.v[5]; a.v[6] = t.self_max > a.v[6] ? t.self_max : a.v[6];
+  a.v[7] += t.bytes_sum;
+}
+
+__device__ inline void group_value(const RowCtx &c, const Tables &tb, uint32_t grp, uint32_t id, Acc &a) {
+  acc_init(a);
+  if (c.mode == 1) {
+    acc_add(a, tb.tally[(size_t)c.vals[grp] * tb.n_fns + id]);
+  } else if (c.mode == 2) {
+    for (uint32_t i = c.gbeg[grp]; i < c.gend[grp]; i++) acc_add(a, tb.tally[(size_t)c.vals[i] * tb.n_fns + id]);
+  } else if (c.mode == 3) {
+    for (uint32_t r = c.trace_span[2 * grp]; r < c.trace_span[2 * grp + 1]; r++)
+      for (uint32_t i = c.gbeg[r]; i < c.gend[r]; i++) acc_add(a, tb.tally[(size_t)c.vals[i] * tb.n_fns + id]);
+  } else {
+    const KTally k = tb.ktally[(size_t)c.rank_stream[grp] * tb.n_kid + id];
+    a.v[0] = k.count; a.v[1] = k.sum; a.v[2] = k.min; a.v[3] = k.max;
+    a.v[4] = 0; a.v[5] = 0; a.v[6] = 0; a.v[7] = 0;
+  }
+}
+
+// Pass 1 (out == null): count the non-empty ids of each group into cnt[grp].
+// Pass 2: write them at off[grp] + (rank among the group's non-empty ids).
+__global__ __launch_bounds__(256) void k_group_rows(RowCtx c, Tables tb, uint32_t *__restrict__ cnt,
+                                                    const uint64_t *__restrict__ off, uint8_t *__restrict__ out) {
+  __shared__ uint32_t wsum[4];
+  __shared__ uint32_t run;
+  const uint32_t grp = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (tid == 0) run = 0;
+  __syncthreads();
+  for (uint32_t id0 = 0; id0 < c.n_ids; id0 += 256) {
+    const uint32_t id = id0 + tid;
+    Acc a;
+    bool ne = false;
+    if (id < c.n_ids) { group_value(c, tb, grp, id, a); ne = a.v[0] != 0; }
+    const uint64_t m = __ballot(ne);
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    if (lane == 0) wsum[w] = (uint32_t)__popcll(m);
+    __syncthreads();
+    uint32_t pre = run;
+    for (int k = 0; k < w; k++) pre += wsum[k];
+    if (ne && out) {
+      const uint64_t pos = off[grp] + pre + (uint32_t)__popcll(m & lt);
+      uint32_t *row = (uint32_t *)(out + pos * 88);
+      uint32_t tr, ho, pi, ti;
+      if (c.mode == 1) {
+        const uint32_t rank = (uint32_t)(c.keys[grp] >> 32);
+        tr = c.rank_key[3 * rank]; ho = c.rank_key[3 * rank + 1]; pi = c.rank_key[3 * rank + 2];
+        ti = (uint32_t)c.keys[grp];
+      } else if (c.mode == 2 || c.mode == 4) {
+        tr = c.rank_key[3 * grp]; ho = c.rank_key[3 * grp + 1]; pi = c.rank_key[3 * grp + 2];
+        ti = EMPTY32;
+      } else {
+        tr = c.rank_key[3 * c.trace_span[2 * grp]]; ho = EMPTY32; pi = EMPTY32; ti = EMPTY32;
+      }
+      row[0] = tr; row[1] = ho; row[2] = pi; row[3] = ti;
+      row[4] = (id & 0xFFFFu) | ((c.mode == 4 ? 2u : 1u) << 16);
+      row[5] = 0;
+      uint64_t *f = (uint64_t *)(out + pos * 88 + 24);
+      for (int k = 0; k < 8; k++) f[k] = a.v[k];
+    }
+    __syncthreads();
+    if (tid == 0) { uint32_t t = 0; for (int k = 0; k < 4; k++) t += wsum[k]; run += t; }
+    __syncthreads();
+  }
+  if (!out && tid == 0) cnt[grp] = run;
+}
+
+// Exclusive scan of cnt[0..n) into off[0..n] by one workgroup (off[n] = total).
+__global__ __launch_bounds__(1024) void k_scan_counts(const uint32_t *__restrict__ cnt, uint64_t *__restrict__ off,
+                                                      uint32_t n) {
+  __shared__ uint64_t part[1024];
+  __shared__ uint64_t carry;
+  const int tid = threadIdx.x;
+  if (tid == 0) carry = 0;
+  __syncthreads();
+  for (uint32_t c0 = 0; c0 < n; c0 += 1024) {
+    const uint32_t i = c0 + tid;
+    const uint64_t v = i < n ? cnt[i] : 0;
+    part[tid] = v;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+      const uint64_t t = tid >= o ? part[tid - o] : 0;
+      __syncthreads();
+      part[tid] += t;
+      __syncthreads();
+    }
+    if (i < n) off[i] = carry + part[tid] - v;
+    __syncthreads();
+    if (tid == 0) carry += part[1023];
+    __syncthreads();
+  }
+  if (tid == 0) off[n] = carry;
+}
+
+// ---------------------------------------------------------- fills / init
+__global__ void k_init_tally(Tally *t, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    Tally v;
+    v.count = 0; v.incl_sum = 0; v.incl_min = ~0ull; v.incl_max = 0;
+    v.self_sum = 0; v.self_min = ~0ull; v.self_max = 0; v.bytes_sum = 0;
+    t[i] = v;
+  }
+}
+__global__ void k_init_ktally(KTally *t, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    KTally v;
+    v.count = 0; v.sum = 0; v.min = ~0ull; v.max = 0;
+    t[i] = v;
+  }
+}
+__global__ void k_fill64(uint64_t *p, size_t n, uint64_t v) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ void k_fill32(uint32_t *p, size_t n, uint32_t v) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+// --------------------------------------------------------------- launchers
+static dim3 fill_grid(size_t n) {
+  size_t b = (n + 255) / 256;
+  if (b > 8192) b = 8192;
+  if (b == 0) b = 1;
+  return dim3((unsigned)b);
+}
+hipError_t launch_fill64(uint64_t *p, size_t n, uint64_t v, hipStream_t st) {
+  if (n) hipLaunchKernelGGL(k_fill64, fill_grid(n), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+hipError_t launch_fill32(uint32_t *p, size_t n, uint32_t v, hipStream_t st) {
+  if (n) hipLaunchKernelGGL(k_fill32, fill_grid(n), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+hipError_t launch_init_tables(const Tables &tb, size_t n_tally, size_t n_ktally, hipStream_t st) {
+  if (n_tally) hipLaunchKernelGGL(k_init_tally, fill_grid(n_tally), dim3(256), 0, st, tb.tally, n_tally);
+  if (n_ktally) hipLaunchKernelGGL(k_init_ktally, fill_grid(n_ktally), dim3(256), 0, st, tb.ktally, n_ktally);
+  return hipGetLastError();
+}
+hipError_t launch_combine(const uint32_t *spans, uint32_t n_spans, const RHdr *rhdr, const UItem *ru,
+                          const OItem *ro, const uint32_t *rnslots, const Tables &tb, hipStream_t st) {
+  if (n_spans) hipLaunchKernelGGL(k_combine, dim3(n_spans), dim3(256), 0, st, spans, rhdr, ru, ro, rnslots, tb);
+  return hipGetLastError();
+}
+hipError_t launch_final(const Tables &tb, uint32_t max_threads, hipStream_t st) {
+  hipLaunchKernelGGL(k_final, dim3((max_threads + 255) / 256), dim3(256), 0, st, tb);
+  return hipGetLastError();
+}
+hipError_t launch_thread_stats(const Tables &tb, uint32_t max_threads, unsigned long long *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_thread_stats, dim3((max_threads + 255) / 256), dim3(256), 0, st, tb, out);
+  return hipGetLastError();
+}
+hipError_t launch_sort_threads(const Tables &tb, const uint32_t *stream_rank, uint64_t *keys, uint32_t *vals,
+                               uint64_t *keys2, uint32_t *vals2, uint32_t n, int rank_bits, hipStream_t st) {
+  if (!n) return hipSuccess;
+  hipLaunchKernelGGL(k_thread_keys, dim3((n + 255) / 256), dim3(256), 0, st, tb, stream_rank, keys, vals, n);
+  // tid: 32 bits; canonical stream rank (or the 0xFFFFFFFF filter mark): 32 bits
+  hipLaunchKernelGGL(k_radix_sort, dim3(1), dim3(RS_WG), 0, st, keys, vals, keys2, vals2, n, 0, 32 + rank_bits);
+  return hipGetLastError();
+}
+hipError_t launch_group_bounds(const uint64_t *keys, uint32_t n, uint32_t *gbeg, uint32_t *gend, uint32_t n_ranks,
+                               hipStream_t st) {
+  if (n) hipLaunchKernelGGL(k_group_bounds, dim3((n + 255) / 256), dim3(256), 0, st, keys, n, gbeg, gend, n_ranks);
+  return hipGetLastError();
+}
+hipError_t launch_group_rows(const RowCtx &c, const Tables &tb, uint32_t n_groups, uint32_t *cnt, uint64_t *off,
+                             uint8_t *out, hipStream_t st) {
+  if (!n_groups) return hipSuccess;
+  if (!out) {
+    hipLaunchKernelGGL(k_group_rows, dim3(n_groups), dim3(256), 0, st, c, tb, cnt, (const uint64_t *)nullptr,
+                       (uint8_t *)nullptr);
+    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, cnt, off, n_groups);
+  } else {
+    hipLaunchKernelGGL(k_group_rows, dim3(n_groups), dim3(256), 0, st, c, tb, cnt, (const uint64_t *)off, out);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace tt

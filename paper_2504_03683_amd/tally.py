@@ -1,0 +1,216 @@
+"""ctypes binding of libthapi_tally.so (the C ABI declared in include/thapi_tally.h).
+
+Argument marshalling only: every step of the tally runs in the library's HIP
+kernels.  Host inputs are numpy uint8 arrays; device inputs (THAPI_DEVICE_INPUT)
+are torch tensors on the GPU (torch is used for device memory and streams only).
+If the shared library has not been built this module fails loudly; there is
+no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libthapi_tally.so")
+
+ABI_VERSION = 1
+FMT_FIXED24, FMT_VAR16 = 1, 2
+DEVICE_INPUT, NONBLOCKING, DROP_ON_FULL, STRICT, PROFILE = 0x1, 0x2, 0x4, 0x8, 0x10
+TICKET_ALL = (1 << 64) - 1
+FLUSH_FINAL = 0x1
+SCOPE_THREAD, SCOPE_PROCESS, SCOPE_FN, SCOPE_KERNEL = 1, 2, 3, 4
+ALL = 0xFFFFFFFF
+ROW_API, ROW_KERNEL = 1, 2
+MAX_DEPTH_LIMIT = 64
+MAX_RANGE_THREADS = 64
+
+OK, E_INVAL, E_NOMEM, E_AGAIN, E_DEPTH, E_MALFORMED, E_DEVICE, E_BUFSZ, E_CAPACITY, E_STATE = \
+    0, -1, -2, -3, -4, -5, -6, -7, -8, -9
+
+ENTRY_POINTS = ["thapi_tally_open", "thapi_tally_submit", "thapi_tally_flush", "thapi_tally_read",
+                "thapi_tally_reset", "thapi_tally_close", "thapi_tally_strerror", "thapi_tally_timings"]
+
+ROW_DTYPE = np.dtype([
+    ("trace", "<u4"), ("host", "<u4"), ("pid", "<u4"), ("tid", "<u4"),
+    ("id", "<u2"), ("row_kind", "u1"), ("pad", "u1"), ("pad2", "<u4"),
+    ("count", "<u8"), ("incl_sum", "<u8"), ("incl_min", "<u8"), ("incl_max", "<u8"),
+    ("self_sum", "<u8"), ("self_min", "<u8"), ("self_max", "<u8"), ("bytes_sum", "<u8"),
+])
+STAT_NAMES = ["records", "entries", "exits", "kernel_records", "orphan_exits", "fn_mismatch",
+              "neg_duration", "self_underflow", "ts_regress", "unclosed_final", "open_now",
+              "depth_overflow", "bad_records", "dropped_records", "distinct_hosts",
+              "distinct_processes", "distinct_threads"]
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("abi_version", ctypes.c_uint32), ("format", ctypes.c_uint32), ("n_fns", ctypes.c_uint32),
+                ("n_kernel_ids", ctypes.c_uint32), ("max_depth", ctypes.c_uint32),
+                ("max_threads", ctypes.c_uint32), ("max_streams", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("fn_has_size", ctypes.c_void_p), ("device_budget_bytes", ctypes.c_uint64),
+                ("device", ctypes.c_int32), ("reserved", ctypes.c_uint32), ("hip_stream", ctypes.c_void_p),
+                ("autotune_cache", ctypes.c_char_p)]
+
+
+class StreamKey(ctypes.Structure):
+    _fields_ = [("trace_id", ctypes.c_uint32), ("host_id", ctypes.c_uint32), ("pid", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in STAT_NAMES]
+
+
+assert ctypes.sizeof(Stats) == 8 * 17 and ROW_DTYPE.itemsize == 88
+
+_lib = None
+
+
+def load():
+    """The built library; raises if it is missing (build it with build.build())."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libthapi_tally.so is not built (run __graft_entry__.build()); "
+                          "there is no CPU fallback")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    lib.thapi_tally_open.argtypes = [ctypes.POINTER(Config), ctypes.POINTER(P)]
+    lib.thapi_tally_submit.argtypes = [P, ctypes.POINTER(StreamKey), P, ctypes.c_size_t, P, ctypes.c_size_t,
+                                       ctypes.POINTER(ctypes.c_uint64)]
+    lib.thapi_tally_flush.argtypes = [P, ctypes.c_uint64, ctypes.c_uint32]
+    lib.thapi_tally_read.argtypes = [P, ctypes.c_uint32, ctypes.c_uint32, P, ctypes.c_size_t,
+                                     ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(Stats)]
+    lib.thapi_tally_reset.argtypes = [P]
+    lib.thapi_tally_close.argtypes = [P]
+    lib.thapi_tally_strerror.argtypes = [ctypes.c_int]
+    lib.thapi_tally_strerror.restype = ctypes.c_char_p
+    lib.thapi_tally_timings.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.c_int]
+    for n in ENTRY_POINTS:
+        if n != "thapi_tally_strerror":
+            getattr(lib, n).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+class TallyError(RuntimeError):
+    def __init__(self, code, where=""):
+        self.code = code
+        msg = load().thapi_tally_strerror(code).decode()
+        super().__init__("%s: %s (%d)" % (where, msg, code))
+
+
+def _check(rc, where):
+    if rc < 0:
+        raise TallyError(rc, where)
+    return rc
+
+
+def _ptr_and_bytes(a):
+    """(pointer, nbytes, keepalive) of a numpy array or a torch tensor."""
+    if a is None:
+        return None, 0, None
+    if hasattr(a, "data_ptr"):   # torch tensor (device input)
+        return (a.data_ptr() or None), a.numel() * a.element_size(), a
+    a = np.ascontiguousarray(a)
+    return (a.ctypes.data if a.size else None), a.nbytes, a
+
+
+class Tally:
+    """One library handle.  See include/thapi_tally.h for the semantics."""
+
+    def __init__(self, fmt=FMT_FIXED24, n_fns=1, n_kernel_ids=0, max_depth=0, max_threads=0, max_streams=0,
+                 flags=0, has_size=None, budget=0, device=0, stream=None):
+        self._lib = load()
+        c = Config()
+        c.abi_version = ABI_VERSION
+        c.format = fmt
+        c.n_fns = n_fns
+        c.n_kernel_ids = n_kernel_ids
+        c.max_depth = max_depth
+        c.max_threads = max_threads
+        c.max_streams = max_streams
+        c.flags = flags
+        hs = None
+        if has_size is not None:
+            hs = np.ascontiguousarray(has_size, dtype=np.uint8)
+            c.fn_has_size = hs.ctypes.data
+        c.device_budget_bytes = budget
+        c.device = device
+        c.reserved = 0
+        if stream is not None:
+            c.hip_stream = stream if isinstance(stream, int) else stream.cuda_stream
+        self.fmt = fmt
+        self.flags = flags
+        self._h = ctypes.c_void_p()
+        _check(self._lib.thapi_tally_open(ctypes.byref(c), ctypes.byref(self._h)), "open")
+        self._keep = []
+
+    def submit(self, key, records, payload=None):
+        k = StreamKey(key[0], key[1], key[2], 0)
+        rp, rb, rk = _ptr_and_bytes(records)
+        pp, pb, pk = _ptr_and_bytes(payload)
+        ticket = ctypes.c_uint64(0)
+        _check(self._lib.thapi_tally_submit(self._h, ctypes.byref(k), rp, rb, pp, pb, ctypes.byref(ticket)),
+               "submit")
+        if self.flags & DEVICE_INPUT:
+            self._keep.append((rk, pk))   # device buffers must outlive the flush
+        return ticket.value
+
+    def submit_rc(self, key, records, payload=None):
+        """submit() returning the raw status instead of raising."""
+        k = StreamKey(key[0], key[1], key[2], 0)
+        rp, rb, _ = _ptr_and_bytes(records)
+        pp, pb, _ = _ptr_and_bytes(payload)
+        ticket = ctypes.c_uint64(0)
+        return self._lib.thapi_tally_submit(self._h, ctypes.byref(k), rp, rb, pp, pb, ctypes.byref(ticket))
+
+    def flush(self, ticket=TICKET_ALL, final=False):
+        rc = self._lib.thapi_tally_flush(self._h, ticket, FLUSH_FINAL if final else 0)
+        _check(rc, "flush")
+        self._keep = []
+        return rc
+
+    def flush_rc(self, ticket=TICKET_ALL, final=False):
+        rc = self._lib.thapi_tally_flush(self._h, ticket, FLUSH_FINAL if final else 0)
+        self._keep = []
+        return rc
+
+    def read(self, scope=SCOPE_THREAD, trace=ALL):
+        n = ctypes.c_size_t(0)
+        st = Stats()
+        _check(self._lib.thapi_tally_read(self._h, scope, trace, None, 0, ctypes.byref(n), ctypes.byref(st)),
+               "read")
+        rows = np.zeros(n.value, dtype=ROW_DTYPE)
+        if n.value:
+            _check(self._lib.thapi_tally_read(self._h, scope, trace, rows.ctypes.data, n.value, ctypes.byref(n),
+                                              ctypes.byref(st)), "read")
+        return rows, {k: int(getattr(st, k)) for k in STAT_NAMES}
+
+    def reset(self):
+        _check(self._lib.thapi_tally_reset(self._h), "reset")
+
+    def timings(self):
+        arr = (ctypes.c_double * 5)()
+        n = self._lib.thapi_tally_timings(self._h, arr, 5)
+        return dict(zip(["prepass", "range", "combine", "final", "readout"], list(arr)[:n]))
+
+    def close(self):
+        if self._h:
+            self._lib.thapi_tally_close(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -258,3 +258,85 @@ def chunk_sizes(seed: int, total_bytes: int, lo: int = 64 << 10, hi: int = 8 << 
         out.append(b)
         left -= b
     return out
+
+
+def random_submissions(seed: int, fmt: int = FMT_FIXED24, n_streams: int = 2, n_threads: int = 3,
+                       n_per_stream: int = 200, n_fns: int = 6, n_kid: int = 4, p_bad: float = 0.05,
+                       max_chunks: int = 4, tid_base: int = 100, p_kernel: float = 0.05):
+    """Seeded small traces with every kind of malformed record mixed in
+    (orphan exits, mismatched fns, time regressions, unknown kinds, fn and
+    kernel ids out of range, kernel end < start, short VAR16 payloads), each
+    stream cut into up to `max_chunks` chunks; returned in a round-robin
+    submit order as a list of ((trace, host, pid), records, payload)."""
+    rng = np.random.default_rng(seed)
+    per = []
+    for s in range(n_streams):
+        key = (s % 2, s // 2, 1000 + s)
+        t = T0_NS + int(rng.integers(0, 1000))
+        hdr = []
+        pays = []
+        for _ in range(n_per_stream):
+            th = int(rng.integers(0, n_threads))
+            r = rng.random()
+            t += int(rng.integers(-3, 40)) if rng.random() < 0.1 else int(rng.integers(0, 40))
+            fn = int(rng.integers(0, n_fns + (1 if rng.random() < p_bad else 0)))
+            if r < p_kernel:
+                kid = int(rng.integers(0, n_kid + (1 if rng.random() < p_bad else 0)))
+                end = t + int(rng.integers(-5 if rng.random() < p_bad else 0, 500))
+                if fmt == FMT_FIXED24:
+                    hdr.append(np.array([t, th, kid, 2, end], dtype=object))
+                else:
+                    plen = int(rng.choice([8, 12, 20])) if rng.random() > p_bad else int(rng.integers(0, 8))
+                    p = (int(end) & ((1 << 64) - 1)).to_bytes(8, "little") + bytes(rng.integers(65, 90, 24, dtype=np.uint8))
+                    hdr.append(np.array([t, th, kid, 2, plen], dtype=object))
+                    pays.append(p[:plen])
+                continue
+            if r < p_kernel + p_bad:
+                kind = int(rng.integers(3, 256))
+            else:
+                kind = 0 if rng.random() < 0.52 else 1
+            if fmt == FMT_FIXED24:
+                hdr.append(np.array([t, tid_base + th, fn, kind, 0], dtype=object))
+            else:
+                plen = int(rng.choice([0, 4, 8, 9, 16, 40]))
+                size = int(rng.integers(1, 1 << 40))
+                p = size.to_bytes(8, "little") + bytes(rng.integers(65, 90, 40, dtype=np.uint8))
+                hdr.append(np.array([t, tid_base + th, fn, kind, plen], dtype=object))
+                pays.append(p[:plen])
+        # encode
+        if fmt == FMT_FIXED24:
+            buf = bytearray()
+            for h in hdr:
+                ts, tid, fn, kind, end = (int(x) for x in h)
+                tid_field = tid if kind != 2 else tid
+                buf += ts.to_bytes(8, "little") + tid_field.to_bytes(4, "little") + fn.to_bytes(2, "little")
+                buf += bytes([kind, 0]) + (end & ((1 << 64) - 1)).to_bytes(8, "little")
+            rec = np.frombuffer(bytes(buf), dtype=np.uint8).copy()
+            pay = None
+            rs = 24
+        else:
+            buf = bytearray()
+            for h in hdr:
+                ts, tid, fn, kind, plen = (int(x) for x in h)
+                buf += ts.to_bytes(8, "little") + tid.to_bytes(4, "little") + fn.to_bytes(2, "little")
+                buf += bytes([kind, plen])
+            rec = np.frombuffer(bytes(buf), dtype=np.uint8).copy()
+            pay = np.frombuffer(b"".join(pays), dtype=np.uint8).copy()
+            rs = 16
+        n = rec.size // rs
+        k = int(rng.integers(1, max_chunks + 1))
+        cuts = sorted(set(rng.integers(0, n + 1, size=k - 1).tolist()))
+        bounds = [0] + cuts + [n]
+        parts = []
+        if fmt == FMT_VAR16:
+            plen = rec.reshape(-1, 16)[:, 15].astype(np.int64)
+            poff = np.concatenate([[0], np.cumsum(plen)])
+        for a, b in zip(bounds[:-1], bounds[1:]):
+            parts.append((key, rec[a * rs:b * rs], None if pay is None else pay[poff[a]:poff[b]]))
+        per.append(parts)
+    subs = []
+    while any(per):
+        for p in per:
+            if p:
+                subs.append(p.pop(0))
+    return subs

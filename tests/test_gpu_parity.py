@@ -1,0 +1,191 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle,
+element by element on every row scope and every counter.  All fields are
+integers, so the bar is bit-exact equality."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.parity import Case, assert_same, case_from_workload, run_gpu, run_oracle, say
+from tests.records import ENTRY, EXIT, KERNEL, fixed24, u64, var16
+
+pytestmark = pytest.mark.gpu
+T0 = synth.T0_NS
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2504_03683_amd import tally
+    tally.load()
+
+
+def check(case, **kw):
+    o = run_oracle(case)
+    g = run_gpu(case, **kw)
+    assert_same(g, o)
+    return g, o
+
+
+def test_handbuilt_nested():
+    say("case: hand-built nested calls")
+    ev = [(T0 + 100, 7, 0, ENTRY), (T0 + 110, 7, 1, ENTRY), (T0 + 130, 7, 1, EXIT),
+          (T0 + 150, 7, 2, ENTRY), (T0 + 160, 7, 3, ENTRY), (T0 + 190, 7, 3, EXIT),
+          (T0 + 200, 7, 2, EXIT), (T0 + 250, 7, 0, EXIT)]
+    g, _ = check(Case(1, 4, 0, [((0, 0, 1000), fixed24(ev), None)]))
+    assert len(g[1]) == 4 and int(g[1]["self_sum"][0]) == 80
+
+
+def test_handbuilt_anomalies_and_kernels():
+    say("case: hand-built anomalies")
+    ev = [(T0 + 5, 1, 0, EXIT), (T0 + 10, 1, 0, ENTRY), (T0 + 12, 1, 1, ENTRY), (T0 + 20, 1, 2, EXIT),
+          (T0 + 30, 1, 0, EXIT), (T0 + 40, 1, 3, ENTRY), (T0 + 35, 1, 3, EXIT), (T0 + 50, 1, 9, ENTRY),
+          (T0 + 60, 1, 0, 5), (T0 + 70, 1, 1, ENTRY),
+          (T0 + 10, 0, 3, KERNEL, T0 + 60), (T0 + 20, 1, 3, KERNEL, T0 + 25), (T0 + 30, 0, 4, KERNEL, T0 + 29),
+          (T0 + 40, 2, 70, KERNEL, T0 + 41)]
+    check(Case(1, 4, 64, [((0, 0, 1000), fixed24(ev), None)]))
+
+
+def test_handbuilt_var16():
+    say("case: hand-built VAR16 payload sizes")
+    hs = np.array([1, 0, 1], dtype=np.uint8)
+    ev = [(T0 + 0, 4, 0, ENTRY, u64(4096) + b"name_x"), (T0 + 5, 4, 1, ENTRY, u64(777)),
+          (T0 + 9, 4, 1, EXIT, b"zz"), (T0 + 20, 4, 0, EXIT, b""), (T0 + 30, 4, 2, ENTRY, b"1234567"),
+          (T0 + 31, 4, 2, EXIT, b""), (T0 + 40, 4, 0, ENTRY, u64(1 << 30)), (T0 + 41, 4, 0, EXIT, b"abc"),
+          (T0 + 50, 0, 5, KERNEL, u64(T0 + 80)), (T0 + 60, 0, 5, KERNEL, b"1234")]
+    hdr, pay = var16(ev)
+    check(Case(2, 3, 8, [((0, 0, 1000), hdr, pay)], has_size=hs))
+
+
+@pytest.mark.parametrize("seed", list(range(12)))
+@pytest.mark.parametrize("fmt", [1, 2])
+def test_random_malformed(seed, fmt):
+    say("case: random malformed fmt=%d seed=%d" % (fmt, seed))
+    subs = synth.random_submissions(seed, fmt=fmt, n_streams=3, n_threads=4, n_per_stream=300)
+    hs = np.array([1, 0, 1, 0, 1, 1], np.uint8) if fmt == 2 else None
+    flush_after = [i for i in range(len(subs)) if (i + seed) % 3 == 0]
+    check(Case(fmt, 6, 4, subs, has_size=hs, flush_after=flush_after, final=seed % 2 == 0, max_depth=64))
+
+
+def test_open_calls_between_flushes():
+    say("case: calls open across flushes, non-final read")
+    w = synth.config(0, scale=0.02)
+    c = case_from_workload(w, split=7, seed=3)
+    c.flush_after = list(range(0, len(c.subs), 2))
+    c.final = False
+    check(c)
+
+
+def test_config0_full():
+    say("case: plain-tiny, 1M records")
+    w = synth.config(0)
+    check(case_from_workload(w))
+
+
+def test_config0_device_input_chunks():
+    say("case: plain-tiny, device input, 9 chunks")
+    w = synth.config(0, scale=0.3)
+    c = case_from_workload(w, split=9, seed=11)
+    c.flush_after = [2, 5]
+    check(c, device_input=True)
+
+
+def test_config1_reduced():
+    say("case: layered, 2% (2.2M records, 12 streams)")
+    w = synth.config(1, scale=0.02)
+    check(case_from_workload(w, split=3, seed=1))
+
+
+def test_config2_reduced():
+    say("case: layered VAR16, 4%")
+    w = synth.config(2, scale=0.04)
+    check(case_from_workload(w, split=2, seed=2))
+
+
+def test_config3_subset():
+    say("case: batched subset, 256 traces at 0.2%")
+    w = synth.config(3, scale=0.002)
+    check(case_from_workload(w), max_threads=65536, max_streams=4096)
+
+
+def test_config4_chunks_carry():
+    say("case: streaming shape, 64 processes x 64 threads, chunked")
+    w = synth.config(4, scale=0.02)
+    c = case_from_workload(w, split=5, seed=4)
+    c.flush_after = list(range(0, len(c.subs), 16))
+    check(c, max_threads=8192)
+
+
+def test_depth_overflow_is_an_error():
+    say("case: depth overflow")
+    from paper_2504_03683_amd import tally as T
+    ev = [(T0 + i, 1, 0, ENTRY) for i in range(6)] + [(T0 + 10 + i, 1, 0, EXIT) for i in range(6)]
+    rec = fixed24(ev)
+    o = oracle.Oracle(1, 1, 0, 4)
+    o.submit((0, 0, 1), rec)
+    o.finish()
+    assert o.stats()["depth_overflow"] == 1
+    with T.Tally(T.FMT_FIXED24, 1, 0, max_depth=4, max_threads=64, max_streams=8) as t:
+        t.submit((0, 0, 1), rec)
+        assert t.flush_rc(final=True) == T.E_DEPTH
+        _, st = t.read()
+        assert st["depth_overflow"] == 1
+
+
+def test_too_many_threads_in_one_range():
+    say("case: more than 64 threads interleaved in one range")
+    from paper_2504_03683_amd import tally as T
+    ev = []
+    for k in range(80):
+        ev.append((T0 + 2 * k, 1000 + k, 0, ENTRY))
+    for k in range(80):
+        ev.append((T0 + 500 + k, 1000 + k, 0, EXIT))
+    with T.Tally(T.FMT_FIXED24, 1, 0, max_threads=1024, max_streams=8) as t:
+        t.submit((0, 0, 1), fixed24(ev))
+        assert t.flush_rc(final=True) == T.E_CAPACITY
+
+
+def test_submit_validation():
+    say("case: submit validation")
+    from paper_2504_03683_amd import tally as T
+    with T.Tally(T.FMT_VAR16, 4, 0, max_threads=64, max_streams=4) as t:
+        hdr, pay = var16([(T0, 1, 0, ENTRY, b"12345678"), (T0 + 1, 1, 0, EXIT, b"")])
+        assert t.submit_rc((0, 0, 1), hdr, pay[:-1]) == T.E_INVAL   # payload size mismatch
+        assert t.submit_rc((0, 0, 1), hdr[:-3], pay) == T.E_INVAL   # partial record
+        assert t.submit_rc((0, 0, 1), hdr, pay) == T.OK
+        t.flush(final=True)
+        assert t.submit_rc((0, 0, 1), hdr, pay) == T.E_STATE       # after the final flush
+        rows, st = t.read()
+        assert st["records"] == 2 and len(rows) == 1
+    with T.Tally(T.FMT_FIXED24, 4, 0, max_threads=64, max_streams=2) as t:
+        rec = fixed24([(T0, 1, 0, ENTRY)])
+        assert t.submit_rc((0, 0, 1), rec) == T.OK
+        assert t.submit_rc((0, 0, 2), rec) == T.OK
+        assert t.submit_rc((0, 0, 3), rec) == T.E_CAPACITY         # max_streams
+
+
+def test_reset_and_repeat_determinism():
+    say("case: reset and repeat")
+    from paper_2504_03683_amd import tally as T
+    w = synth.config(0, scale=0.1)
+    outs = []
+    with T.Tally(T.FMT_FIXED24, w.n_fns, 0, max_depth=16, max_threads=256, max_streams=8) as t:
+        for _ in range(3):
+            t.reset()
+            for s in w.streams:
+                t.submit(s.key, s.records)
+            t.flush(final=True)
+            outs.append(t.read())
+    assert all(np.array_equal(outs[0][0], o[0]) and outs[0][1] == o[1] for o in outs[1:])
+
+
+@pytest.mark.slow
+def test_config1_full_size():
+    say("case: layered full size, 110M records (bench launch shape)")
+    w = synth.config(1)
+    c = case_from_workload(w)
+    o = run_oracle(c)
+    g = run_gpu(c, max_threads=1024, max_streams=64)
+    assert_same(g, o)

@@ -87,7 +87,8 @@ extern "C" {
 #define THAPI_ROW_KERNEL 2u
 
 #define THAPI_MAX_DEPTH_LIMIT   64u  /* max_depth may not exceed this */
-#define THAPI_MAX_RANGE_THREADS 64u  /* distinct threads one stream may interleave within one range */
+#define THAPI_MAX_RANGE_THREADS 64u  /* distinct threads one stream may interleave within one range
+                                        (1024 / max_depth when max_depth > 16) */
 
 typedef struct thapi_tally thapi_tally; /* opaque, owned by the library */
 

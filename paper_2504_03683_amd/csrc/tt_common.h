@@ -97,9 +97,10 @@ struct Tables {
   const uint8_t *has_size;     // [n_fns] or null
 };
 
-// Launch shape of the range kernel (tile T records, tally hash E entries).
+// Launch shape of the range kernel (tile of T records, runs of R, tally hash of E entries).
 struct Shape {
   uint32_t T;           // records per tile (multiple of WG)
+  uint32_t R;           // records per run (one lane walks one run)
   uint32_t E;           // LDS tally entries (power of two)
   uint32_t KL;          // kernel ids pre-aggregated in LDS (<= KL_MAX)
   uint32_t lds_bytes;

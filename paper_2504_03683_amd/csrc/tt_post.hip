@@ -84,7 +84,7 @@ __global__ __launch_bounds__(256) void k_combine(const uint32_t *__restrict__ sp
         if (cs.h == 0) { c_orphan++; continue; }
         cs.h--;
         const Frame e = stk[cs.h];
-        if (e.fn != u.fn) { c_mis++; continue; }
+        if (e.fn != u.fn || u.fn >= tb.n_fns) { c_mis++; continue; }
         if (u.ts < e.ts) { c_neg++; continue; }
         const uint64_t incl = u.ts - e.ts;
         const uint64_t ch = e.child + u.child;

@@ -62,7 +62,7 @@ struct RangeLds {
   uint32_t *run_uo;    // U items (16) | open entries at the end (16)
   uint32_t *run_hm;    // max local height (16) | max local level (16, signed)
   uint64_t *run_base;  // children time owed to the call below the run's entries at its end
-  int32_t *run_ds, *run_m, *run_F, *run_suf;
+  int32_t *run_ds, *run_m, *run_pm, *run_suf;  // start level, lowest level, prefix / suffix minimum
   uint16_t *oidx;      // [run][level - m - 1] -> open entry
   // thread slots
   uint32_t *s_gslot, *s_flags, *s_run0;
@@ -117,7 +117,7 @@ __host__ __device__ inline size_t range_lds_layout(uint8_t *base, RangeLds *L, u
   TAKE(run_base, uint64_t, NR);
   TAKE(run_ds, int32_t, NR);
   TAKE(run_m, int32_t, NR);
-  TAKE(run_F, int32_t, NR);
+  TAKE(run_pm, int32_t, NR);
   TAKE(run_suf, int32_t, NR);
   TAKE(oidx, uint16_t, (size_t)NR * R);
   TAKE(s_gslot, uint32_t, S_MAX);
@@ -205,9 +205,11 @@ __device__ inline void g_max64(uint64_t *p, uint64_t v) {
 // The u64 at byte offset `off` of a buffer of any alignment: two aligned
 // 8-byte loads and a funnel shift (the aligned words lie in the allocation's
 // granule, so they never cross it).
+typedef const __attribute__((address_space(1))) uint64_t gu64;  // global-memory view (no flat accesses)
+
 __device__ inline uint64_t load_u64_unaligned(const uint8_t *base, uint64_t off) {
   const uintptr_t a = (uintptr_t)(base + off);
-  const uint64_t *p = (const uint64_t *)(a & ~(uintptr_t)7);
+  gu64 *p = (gu64 *)(a & ~(uintptr_t)7);
   const uint32_t sh = (uint32_t)(a & 7) * 8;
   const uint64_t lo = __builtin_nontemporal_load(p);
   if (sh == 0) return lo;
@@ -257,23 +259,41 @@ __device__ uint32_t resolve_gslot(const Tables &tb, uint32_t stream, uint32_t ti
   return result;
 }
 
-// Adds one completed call to the (slot, fn) entry of the LDS tally hash.
-// Durations that do not fit 32 bits update the global min/max directly.
+// LDS tally layout: the first `direct_slots(n_fns, E) * n_fns` entries are
+// indexed directly by slot * n_fns + fn (no probing); the rest is an
+// open-addressing hash keyed (slot << 16 | fn) for slots beyond that.
+__host__ __device__ inline uint32_t direct_slots(uint32_t n_fns, uint32_t E) {
+  const uint32_t d = n_fns <= E ? E / n_fns : 0;
+  return d < (uint32_t)S_MAX ? d : (uint32_t)S_MAX;
+}
+
+// Adds one completed call to the (slot, fn) entry of the LDS tally.
+// Durations that do not fit 32 bits update the global min/max directly; a
+// key that finds no room goes to the global tally with atomics.
 template <int FMT>
 __device__ inline void tally_call(const RangeLds &L, uint32_t E, const Tables &tb, uint32_t slot, uint32_t gslot,
                                   uint32_t fn, uint64_t incl, uint64_t self, uint64_t bytes) {
   if (fn >= tb.n_fns || slot >= (uint32_t)S_MAX) return;
-  const uint32_t key = (slot << 16) | fn;
-  uint32_t h = hash32(key) & (E - 1);
+  const uint32_t nd = direct_slots(tb.n_fns, E);
+  const uint32_t d0 = nd * tb.n_fns;
+  uint32_t h = 0;
   bool found = false;
-  for (uint32_t probe = 0; probe < E; probe++) {
-    uint32_t k = L.t_key[h];
-    if (k == key) { found = true; break; }
-    if (k == EMPTY32) {
-      uint32_t old = atomicCAS(&L.t_key[h], EMPTY32, key);
-      if (old == EMPTY32 || old == key) { found = true; break; }
+  if (slot < nd) {
+    h = slot * tb.n_fns + fn;
+    found = true;
+  } else if (E > d0) {
+    const uint32_t key = (slot << 16) | fn;
+    const uint32_t span = E - d0;
+    h = d0 + hash32(key) % span;
+    for (uint32_t probe = 0; probe < span; probe++) {
+      const uint32_t k = L.t_key[h];
+      if (k == key) { found = true; break; }
+      if (k == EMPTY32) {
+        const uint32_t old = atomicCAS(&L.t_key[h], EMPTY32, key);
+        if (old == EMPTY32 || old == key) { found = true; break; }
+      }
+      h = h + 1 < E ? h + 1 : d0;
     }
-    h = (h + 1) & (E - 1);
   }
   Tally *g = gslot < tb.max_threads ? &tb.tally[(size_t)gslot * tb.n_fns + fn] : nullptr;
   if (found) {
@@ -334,79 +354,43 @@ __device__ inline int32_t seg_rscan_min(int32_t v, bool tail, bool &closed) {
   return v;
 }
 
-// ------------------------------------------------------------------ kernel
+// One tile of the range: decode `cur*`, prefetch the next tile into `nxt*`,
+// then slot map, sort, walk, fold, tally and carry.  Force-inlined twice by
+// the kernel so the two register buffers alternate without copies.
+struct Counters { uint32_t c[ST_N]; };
+
 template <int FMT, int ROWS, int R>
-__global__ __launch_bounds__(WG) void k_range(const Seg *__restrict__ segs, const Range *__restrict__ ranges,
-                                              Tables tb, Shape sh, RHdr *__restrict__ rhdr,
-                                              UItem *__restrict__ ru, OItem *__restrict__ ro,
-                                              uint32_t *__restrict__ rnslots) {
-  extern __shared__ __align__(16) uint8_t smem[];
+__device__ __forceinline__ void tile_pass(RangeLds &L, const Tables &tb, const uint32_t E, const uint32_t KL,
+                                          const uint32_t D, const Range &rg, const Seg &sg, gu64 *grec,
+                                          const uint64_t last_rec, const uint64_t t0, const uint64_t (&cur0)[ROWS],
+                                          const uint64_t (&cur1)[ROWS], const uint64_t (&cur2)[ROWS],
+                                          uint64_t (&nxt0)[ROWS], uint64_t (&nxt1)[ROWS], uint64_t (&nxt2)[ROWS],
+                                          uint64_t &pay_run, const size_t sbase, UItem *__restrict__ ru,
+                                          Counters &C) {
   constexpr uint32_t T = ROWS * WG;
   constexpr uint32_t RS = FMT == 2 ? 16 : 24;
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid >> 6;
-  const uint32_t D = tb.D, E = sh.E, KL = sh.KL;
-  const Range rg = ranges[blockIdx.x];
-  const Seg sg = segs[rg.seg];
-  RangeLds L;
-  range_lds_layout<true>(smem, &L, T, R, E, KL, D, FMT);
-
-  for (uint32_t i = tid; i < E; i += WG) {
-    L.t_key[i] = EMPTY32; L.t_cnt[i] = 0; L.t_imin[i] = EMPTY32; L.t_imax[i] = 0;
-    L.t_smin[i] = EMPTY32; L.t_smax[i] = 0; L.t_isum[i] = 0; L.t_ssum[i] = 0;
-    if (FMT == 2) L.t_bsum[i] = 0;
-  }
-  for (uint32_t i = tid; i < KL; i += WG) { L.q_cnt[i] = 0; L.q_min[i] = EMPTY32; L.q_max[i] = 0; L.q_sum[i] = 0; }
-  for (uint32_t i = tid; i < TIDMAP; i += WG) L.tidmap[i] = 0;
-  for (uint32_t i = tid; i < S_MAX; i += WG) {
-    L.s_gslot[i] = GV_INVALID; L.s_flags[i] = 0; L.s_u[i] = 0; L.s_o[i] = 0; L.s_H[i] = 0; L.s_M[i] = 0;
-    L.s_facc[i] = 0; L.s_first[i] = 0; L.s_last[i] = 0; L.s_lastnew[i] = 0;
-  }
-  for (uint32_t i = tid; i < ST_N; i += WG) L.cnt[i] = 0;
-  if (tid < 8) L.misc[tid] = 0;
-  __syncthreads();
-
-  const size_t sbase = (size_t)blockIdx.x * S_MAX;
-  uint64_t pay_run = rg.pay_begin;  // payload offset of the current tile's first record
-
-  // raw words of the tile being decoded; the next tile's loads are issued
-  // right after the current one is decoded
-  uint64_t raw0[ROWS], raw1[ROWS], raw2[ROWS];
-#pragma unroll
-  for (int r = 0; r < ROWS; r++) {
-    const uint32_t li = (uint32_t)w * (T / NWAVES) + (uint32_t)r * WAVE + lane;
-    raw0[r] = 0; raw1[r] = 0; raw2[r] = 0;
-    if (li < rg.n) {
-      const uint64_t *p = (const uint64_t *)(sg.rec + (rg.begin + li) * RS);
-      raw0[r] = __builtin_nontemporal_load(p);
-      raw1[r] = __builtin_nontemporal_load(p + 1);
-      if (FMT == 1) raw2[r] = __builtin_nontemporal_load(p + 2);
-    }
-  }
-
-  for (uint64_t t0 = 0; t0 < rg.n; t0 += T) {
-    const uint32_t n = (uint32_t)((rg.n - t0) < T ? (rg.n - t0) : T);
+  const uint32_t n = (uint32_t)((rg.n - t0) < T ? (rg.n - t0) : T);
     uint64_t r_ts[ROWS], r_x[ROWS], r_by[ROWS];
     uint32_t r_tid[ROWS], r_fk[ROWS], r_slot[ROWS], r_rank[ROWS];
     // ---- P1. decode, then prefetch the next tile
 #pragma unroll
     for (int r = 0; r < ROWS; r++) {
-      r_ts[r] = raw0[r];
-      r_tid[r] = (uint32_t)raw1[r];
-      r_fk[r] = (uint32_t)(raw1[r] >> 32);  // fn | kind << 16 | payload_len << 24
-      r_x[r] = raw2[r];
+      r_ts[r] = cur0[r];
+      r_tid[r] = (uint32_t)cur1[r];
+      r_fk[r] = (uint32_t)(cur1[r] >> 32);  // fn | kind << 16 | payload_len << 24
+      r_x[r] = cur2[r];
       r_by[r] = 0;
     }
-    if (t0 + T < rg.n) {
 #pragma unroll
-      for (int r = 0; r < ROWS; r++) {
-        const uint32_t li = (uint32_t)w * (T / NWAVES) + (uint32_t)r * WAVE + lane;
-        if (t0 + T + li < rg.n) {
-          const uint64_t *p = (const uint64_t *)(sg.rec + (rg.begin + t0 + T + li) * RS);
-          raw0[r] = __builtin_nontemporal_load(p);
-          raw1[r] = __builtin_nontemporal_load(p + 1);
-          if (FMT == 1) raw2[r] = __builtin_nontemporal_load(p + 2);
-        }
-      }
+    for (int r = 0; r < ROWS; r++) {
+      const uint32_t li = (uint32_t)w * (T / NWAVES) + (uint32_t)r * WAVE + lane;
+      uint64_t idx = rg.begin + t0 + T + li;
+      idx = idx < last_rec ? idx : last_rec;
+      gu64 *p = grec + idx * (RS / 8);
+      nxt0[r] = __builtin_nontemporal_load(p);
+      nxt1[r] = __builtin_nontemporal_load(p + 1);
+      nxt2[r] = FMT == 1 ? __builtin_nontemporal_load(p + 2) : 0;
     }
     // VAR16: payload offsets by an exclusive scan of payload_len in record order
     if (FMT == 2) {
@@ -475,11 +459,11 @@ __global__ __launch_bounds__(WG) void k_range(const Seg *__restrict__ segs, cons
         n_bad++;
       }
     }
-    if (n_ent) lds_add32(&L.cnt[ST_ENTRIES], n_ent);
-    if (n_exi) lds_add32(&L.cnt[ST_EXITS], n_exi);
-    if (n_kern) lds_add32(&L.cnt[ST_KERNEL], n_kern);
-    if (n_bad) lds_add32(&L.cnt[ST_BAD], n_bad);
-    if (tid == 0) lds_add32(&L.cnt[ST_RECORDS], n);
+    C.c[ST_ENTRIES] += n_ent;
+    C.c[ST_EXITS] += n_exi;
+    C.c[ST_KERNEL] += n_kern;
+    C.c[ST_BAD] += n_bad;
+    if (tid == 0) C.c[ST_RECORDS] += n;
     // ---- P3. thread id -> local slot
     // bucket word: bit 63 occupied, bit 62 pending, [32,40) slot, [0,32) tid
     bool any_miss = false;
@@ -611,7 +595,7 @@ __global__ __launch_bounds__(WG) void k_range(const Seg *__restrict__ segs, cons
         }
         if (p + 1 == L.soff[s + 1]) L.s_lastnew[s] = ts;
       }
-      if (c_tsreg) lds_add32(&L.cnt[ST_TSREG], c_tsreg);
+      C.c[ST_TSREG] += c_tsreg;
     }
     if (w == 0) {
       const uint32_t c = (uint32_t)lane < nslots ? L.soff[lane + 1] - L.soff[lane] : 0;
@@ -718,7 +702,7 @@ __global__ __launch_bounds__(WG) void k_range(const Seg *__restrict__ segs, cons
         if (valid) {
           L.run_ds[r] = ds;
           L.run_m[r] = m;
-          L.run_F[r] = F;
+          L.run_pm[r] = exmin;
           const uint32_t hm = L.run_hm[r];
           const int32_t Hr = (int32_t)(hm & 0xFFFFu), Mr = (int32_t)(hm >> 16);
           const int32_t hh = ds - F + Mr > Hr ? ds - F + Mr : Hr;
@@ -752,10 +736,11 @@ __global__ __launch_bounds__(WG) void k_range(const Seg *__restrict__ segs, cons
     // ---- P8. fold: match exits that left their run, credit children time to parents
     // psv(r, lev): the open entry at level `lev` as seen from run r
     auto psv = [&](uint32_t r, int32_t lev, uint32_t s) -> uint32_t {
-      int32_t j = (int32_t)r - 1;
-      const int32_t j0 = (int32_t)L.s_run0[s];
-      while (j >= j0 && L.run_m[j] >= lev) j--;
-      if (j >= j0) return L.oidx[(uint32_t)j * R + (uint32_t)(lev - L.run_m[j] - 1)];
+      if (L.run_pm[r] < lev) {  // some earlier run of this tile went below lev: the nearest one opened it
+        int32_t j = (int32_t)r - 1;
+        while (L.run_m[j] >= lev) j--;
+        return L.oidx[(uint32_t)j * R + (uint32_t)(lev - L.run_m[j] - 1)];
+      }
       const int32_t fl = -L.s_u[s];
       if (lev > fl) {
         const uint32_t pos = (uint32_t)(lev - fl - 1);
@@ -848,10 +833,10 @@ __global__ __launch_bounds__(WG) void k_range(const Seg *__restrict__ segs, cons
         if (ch <= incl) self = incl - ch; else { self = 0; c_under++; }
         tally_call<FMT>(L, E, tb, s, L.s_gslot[s], fn, incl, self, by);
       }
-      if (c_mis) lds_add32(&L.cnt[ST_MISMATCH], c_mis);
-      if (c_neg) lds_add32(&L.cnt[ST_NEGDUR], c_neg);
-      if (c_under) lds_add32(&L.cnt[ST_UNDER], c_under);
-      if (c_orph) lds_add32(&L.cnt[ST_ORPHAN], c_orph);
+      C.c[ST_MISMATCH] += c_mis;
+      C.c[ST_NEGDUR] += c_neg;
+      C.c[ST_UNDER] += c_under;
+      C.c[ST_ORPHAN] += c_orph;
     }
     __syncthreads();
     // ---- P10. carried stacks and thread state for the next tile
@@ -861,7 +846,8 @@ __global__ __launch_bounds__(WG) void k_range(const Seg *__restrict__ segs, cons
       const uint32_t s = L.run_info[t] >> 24;
       const int32_t m = L.run_m[t], suf = L.run_suf[t];
       const uint32_t last = L.s_run0[s + 1] - 1;
-      const int32_t fl = L.run_F[last] < L.run_m[last] ? L.run_F[last] : L.run_m[last];
+      int32_t fl = L.run_pm[last] < L.run_m[last] ? L.run_pm[last] : L.run_m[last];
+      fl = fl < -L.s_u[s] ? fl : -L.s_u[s];
       for (uint32_t k = 0; k < no; k++) {
         const int32_t lev = m + 1 + (int32_t)k;
         if (lev > suf) break;  // closed by a later run of this tile
@@ -883,7 +869,8 @@ __global__ __launch_bounds__(WG) void k_range(const Seg *__restrict__ segs, cons
       if (r1 > r0) {
         const uint32_t last = r1 - 1;
         const int32_t fl_old = -L.s_u[s];
-        const int32_t fl = L.run_F[last] < L.run_m[last] ? L.run_F[last] : L.run_m[last];
+        int32_t fl = L.run_pm[last] < L.run_m[last] ? L.run_pm[last] : L.run_m[last];
+        fl = fl < fl_old ? fl : fl_old;
         const uint32_t uo = L.run_uo[last];
         const int32_t depth = L.run_ds[last] - (int32_t)(uo & 0xFFFFu) + (int32_t)(uo >> 16);
         if (fl < fl_old) {
@@ -897,7 +884,72 @@ __global__ __launch_bounds__(WG) void k_range(const Seg *__restrict__ segs, cons
       }
     }
     __syncthreads();
+}
+
+// ------------------------------------------------------------------ kernel
+template <int FMT, int ROWS, int R>
+__global__ __launch_bounds__(WG) void k_range(const Seg *__restrict__ segs, const Range *__restrict__ ranges,
+                                              Tables tb, Shape sh, RHdr *__restrict__ rhdr,
+                                              UItem *__restrict__ ru, OItem *__restrict__ ro,
+                                              uint32_t *__restrict__ rnslots) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  constexpr uint32_t T = ROWS * WG;
+  constexpr uint32_t RS = FMT == 2 ? 16 : 24;
+  const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid >> 6;
+  const uint32_t D = tb.D, E = sh.E, KL = sh.KL;
+  const Range rg = ranges[blockIdx.x];
+  const Seg sg = segs[rg.seg];
+  RangeLds L;
+  range_lds_layout<true>(smem, &L, T, R, E, KL, D, FMT);
+
+  for (uint32_t i = tid; i < E; i += WG) {
+    L.t_key[i] = EMPTY32; L.t_cnt[i] = 0; L.t_imin[i] = EMPTY32; L.t_imax[i] = 0;
+    L.t_smin[i] = EMPTY32; L.t_smax[i] = 0; L.t_isum[i] = 0; L.t_ssum[i] = 0;
+    if (FMT == 2) L.t_bsum[i] = 0;
   }
+  for (uint32_t i = tid; i < KL; i += WG) { L.q_cnt[i] = 0; L.q_min[i] = EMPTY32; L.q_max[i] = 0; L.q_sum[i] = 0; }
+  for (uint32_t i = tid; i < TIDMAP; i += WG) L.tidmap[i] = 0;
+  for (uint32_t i = tid; i < S_MAX; i += WG) {
+    L.s_gslot[i] = GV_INVALID; L.s_flags[i] = 0; L.s_u[i] = 0; L.s_o[i] = 0; L.s_H[i] = 0; L.s_M[i] = 0;
+    L.s_facc[i] = 0; L.s_first[i] = 0; L.s_last[i] = 0; L.s_lastnew[i] = 0;
+  }
+  for (uint32_t i = tid; i < ST_N; i += WG) L.cnt[i] = 0;
+  if (tid < 8) L.misc[tid] = 0;
+  __syncthreads();
+
+  const size_t sbase = (size_t)blockIdx.x * S_MAX;
+  uint64_t pay_run = rg.pay_begin;  // payload offset of the current tile's first record
+
+  // raw words of the tile being decoded; the next tile's loads are issued
+  // right after the current one is decoded.  Loads are unconditional (index
+  // clamped to the range) so that nothing waits for them before the next tile.
+  gu64 *grec = (gu64 *)sg.rec;
+  const uint64_t last_rec = rg.begin + rg.n - 1;
+  uint64_t a0[ROWS], a1[ROWS], a2[ROWS], b0[ROWS], b1[ROWS], b2[ROWS];
+#pragma unroll
+  for (int r = 0; r < ROWS; r++) {
+    const uint32_t li = (uint32_t)w * (T / NWAVES) + (uint32_t)r * WAVE + lane;
+    uint64_t idx = rg.begin + li;
+    idx = idx < last_rec ? idx : last_rec;
+    gu64 *p = grec + idx * (RS / 8);
+    a0[r] = __builtin_nontemporal_load(p);
+    a1[r] = __builtin_nontemporal_load(p + 1);
+    a2[r] = FMT == 1 ? __builtin_nontemporal_load(p + 2) : 0;
+  }
+  Counters C;
+#pragma unroll
+  for (int k = 0; k < ST_N; k++) C.c[k] = 0;
+  for (uint64_t t0 = 0; t0 < rg.n; t0 += 2 * T) {
+    tile_pass<FMT, ROWS, R>(L, tb, E, KL, D, rg, sg, grec, last_rec, t0, a0, a1, a2, b0, b1, b2, pay_run, sbase, ru, C);
+    if (t0 + T < rg.n)
+      tile_pass<FMT, ROWS, R>(L, tb, E, KL, D, rg, sg, grec, last_rec, t0 + T, b0, b1, b2, a0, a1, a2, pay_run, sbase,
+                              ru, C);
+  }
+#pragma unroll
+  for (int k = 0; k < ST_N; k++)
+    if (C.c[k]) lds_add32(&L.cnt[k], C.c[k]);
+  __syncthreads();
+
 
   // ---- range end: summaries, tally and counter flush
   const uint32_t nslots = L.misc[0];
@@ -925,10 +977,19 @@ __global__ __launch_bounds__(WG) void k_range(const Seg *__restrict__ segs, cons
       o->pad = 0;
     }
   }
+  const uint32_t nd = direct_slots(tb.n_fns, E), d0 = nd * tb.n_fns;
   for (uint32_t i = tid; i < E; i += WG) {
-    const uint32_t key = L.t_key[i];
-    if (key == EMPTY32) continue;
-    const uint32_t s = key >> 16, fn = key & 0xFFFFu;
+    uint32_t s, fn;
+    if (i < d0) {
+      if (!L.t_cnt[i]) continue;
+      s = i / tb.n_fns;
+      fn = i - s * tb.n_fns;
+    } else {
+      const uint32_t key = L.t_key[i];
+      if (key == EMPTY32) continue;
+      s = key >> 16;
+      fn = key & 0xFFFFu;
+    }
     const uint32_t gs = L.s_gslot[s];
     if (gs >= tb.max_threads) continue;
     Tally *g = &tb.tally[(size_t)gs * tb.n_fns + fn];
@@ -963,7 +1024,7 @@ __global__ __launch_bounds__(WG) void k_range_paylen(const Seg *__restrict__ seg
   const Seg sg = segs[rg.seg];
   uint64_t s = 0;
   for (uint64_t i = threadIdx.x; i < rg.n; i += WG) {
-    const uint64_t w1 = __builtin_nontemporal_load((const uint64_t *)(sg.rec + (rg.begin + i) * 16) + 1);
+    const uint64_t w1 = __builtin_nontemporal_load((gu64 *)(sg.rec + (rg.begin + i) * 16) + 1);
     s += w1 >> 56;
   }
   atomicAdd(&acc, (unsigned long long)s);

@@ -9,8 +9,7 @@
 namespace tt {
 
 constexpr int WAVE = 64;
-constexpr int WG = 256;              // workgroup of the range kernel
-constexpr int NWAVES = WG / WAVE;
+constexpr int WG = 256;              // workgroup of the helper kernels
 constexpr int S_MAX = 64;            // distinct threads one range may interleave (== THAPI_MAX_RANGE_THREADS)
 constexpr int TIDMAP = 256;          // LDS buckets of the tid -> local slot map (power of two)
 constexpr uint32_t EMPTY32 = 0xFFFFFFFFu;
@@ -97,10 +96,9 @@ struct Tables {
   const uint8_t *has_size;     // [n_fns] or null
 };
 
-// Launch shape of the range kernel (tile of T records, runs of R, tally hash of E entries).
+// Launch shape of the range kernel (tile of T records, LDS tally of E entries).
 struct Shape {
-  uint32_t T;           // records per tile (multiple of WG)
-  uint32_t R;           // records per run (one lane walks one run)
+  uint32_t T;           // records per tile (a multiple of the range kernel's 1024 lanes)
   uint32_t E;           // LDS tally entries (power of two)
   uint32_t KL;          // kernel ids pre-aggregated in LDS (<= KL_MAX)
   uint32_t lds_bytes;

@@ -23,8 +23,8 @@
 #include "tt_common.h"
 
 namespace tt {
-size_t range_lds_bytes(uint32_t T, uint32_t R, uint32_t E, uint32_t KL, uint32_t D, int fmt);
-hipError_t launch_range(int fmt, uint32_t T, uint32_t R, const Seg *segs, const Range *ranges, uint32_t n_ranges,
+size_t range_lds_bytes(uint32_t T, uint32_t E, uint32_t KL, uint32_t D, int fmt);
+hipError_t launch_range(int fmt, uint32_t T, const Seg *segs, const Range *ranges, uint32_t n_ranges,
                         const Tables &tb, const Shape &sh, RHdr *rhdr, UItem *ru, OItem *ro, uint32_t *rnslots,
                         hipStream_t st);
 hipError_t launch_paylen(const Seg *segs, Range *ranges, uint32_t n_ranges, const uint32_t *seg_first_range,
@@ -170,31 +170,31 @@ void free_all(thapi_tally *t) {
   if (t->own_stream && t->st) hipStreamDestroy(t->st);
 }
 
-// Picks the range kernel's tile, run length and LDS tally size for the
-// format and depth: the largest tile and tally that fit the LDS, preferring a
-// full tally (2048 entries) over a larger tile.  THAPI_TALLY_SHAPE="T,R,E"
-// overrides the choice (used to tune the launch shape).
+// Picks the range kernel's tile and LDS tally size for the format and depth:
+// the largest tile and tally that fit the LDS, preferring a full tally (2048
+// entries) over a larger tile.  THAPI_TALLY_SHAPE="T,E" overrides the choice
+// (used to tune the launch shape).
 Shape pick_shape(const thapi_tally *t) {
   Shape s{};
   const uint32_t D = t->cfg.max_depth;
   const int fmt = (int)t->cfg.format;
   s.KL = std::min<uint32_t>(t->cfg.n_kernel_ids, KL_MAX);
-  auto fits = [&](uint32_t T, uint32_t R, uint32_t E) {
-    size_t b = range_lds_bytes(T, R, E, s.KL, D, fmt);
+  auto fits = [&](uint32_t T, uint32_t E) {
+    size_t b = range_lds_bytes(T, E, s.KL, D, fmt);
     if (b > t->lds_limit) return false;
-    s.T = T; s.R = R; s.E = E; s.lds_bytes = (uint32_t)b;
+    s.T = T; s.E = E; s.lds_bytes = (uint32_t)b;
     return true;
   };
   if (const char *env = getenv("THAPI_TALLY_SHAPE")) {
-    unsigned T = 0, R = 0, E = 0;
-    if (sscanf(env, "%u,%u,%u", &T, &R, &E) == 3 && (T == 1024 || T == 2048) && (R == 8 || R == 16) &&
-        E >= 64 && (E & (E - 1)) == 0 && fits(T, R, E))
+    unsigned T = 0, E = 0;
+    if (sscanf(env, "%u,%u", &T, &E) == 2 && (T == 1024 || T == 2048) && E >= 64 &&
+        (E & (E - 1)) == 0 && fits(T, E))
       return s;
   }
-  const uint32_t cand[][3] = {{2048, 8, 2048}, {1024, 8, 2048}, {2048, 8, 1024}, {1024, 8, 1024},
-                              {1024, 8, 512}, {1024, 8, 256}, {1024, 8, 128}, {1024, 8, 64}};
+  const uint32_t cand[][2] = {{2048, 2048}, {1024, 2048}, {2048, 1024}, {1024, 1024},
+                              {1024, 512}, {1024, 256}, {1024, 128}, {1024, 64}};
   for (auto &c : cand)
-    if (fits(c[0], c[1], c[2])) return s;
+    if (fits(c[0], c[1])) return s;
   s.T = 0;
   return s;
 }
@@ -456,9 +456,14 @@ int thapi_tally_flush(thapi_tally *t, uint64_t ticket, uint32_t flags) {
   uint64_t total = 0;
   for (auto &c : work) total += c.n_rec;
   const uint32_t T = t->shape.T;
-  // One range per CU (the range kernel holds one workgroup per CU): the
-  // records are cut into about n_cu equal ranges, never shorter than 16 tiles.
-  uint64_t target = std::max<uint64_t>(1, (uint64_t)t->n_cu);
+  // At most one range per CU (the range kernel holds one workgroup per CU):
+  // with n_seg chunks, ranges of ceil(total / (n_cu - n_seg)) records give at
+  // most n_cu ranges in all (each chunk adds at most one partial range).
+  // Ranges are never shorter than 16 tiles.
+  uint64_t n_seg = 0;
+  for (auto &c : work) n_seg += c.n_rec ? 1 : 0;
+  const uint64_t ncu = std::max<uint64_t>(1, (uint64_t)t->n_cu);
+  const uint64_t target = ncu > 2 * n_seg ? ncu - n_seg : std::max<uint64_t>(1, ncu / 2);
   uint64_t rlen = (total + target - 1) / target;
   rlen = std::max<uint64_t>(rlen, 16ull * T);
   rlen = std::min<uint64_t>(rlen, 1ull << 30);
@@ -508,7 +513,7 @@ int thapi_tally_flush(thapi_tally *t, uint64_t ticket, uint32_t flags) {
       HIPCHK(timed_end(t, TM_PREPASS));
     }
     HIPCHK(timed_begin(t, TM_RANGE));
-    HIPCHK(launch_range((int)t->cfg.format, T, t->shape.R, t->segs.as<Seg>(), t->ranges.as<Range>(), nR, t->tb, t->shape,
+    HIPCHK(launch_range((int)t->cfg.format, T, t->segs.as<Seg>(), t->ranges.as<Range>(), nR, t->tb, t->shape,
                         t->rhdr.as<RHdr>(), t->ru.as<UItem>(), t->ro.as<OItem>(), t->rnslots.as<uint32_t>(), t->st));
     HIPCHK(timed_end(t, TM_RANGE));
     HIPCHK(timed_begin(t, TM_COMBINE));

@@ -1,12 +1,12 @@
 // tt_range.hip -- the fused per-range kernel of the tally pipeline.
 //
-// One workgroup owns one contiguous range of one stream's records and walks
-// it tile by tile.  Per tile of T records it
+// One workgroup of 1024 lanes owns one contiguous range of one stream's
+// records and walks it tile by tile.  Per tile of T records it
 //   1. decodes the records with coalesced 8-byte loads (FIXED24: 3 words per
 //      record; VAR16: 2 header words plus, for entries of sized functions and
 //      kernel records, the u64 at payload offset 0, located by an exclusive
 //      prefix scan of payload_len across the tile); the next tile's loads are
-//      issued as soon as the current tile is decoded;
+//      in flight while the current tile is processed;
 //   2. tallies device-kernel records (kind 2) straight into an LDS table;
 //   3. maps each API record's thread id to a range-local slot through an LDS
 //      hash (new threads are resolved to a global thread slot once per range);
@@ -14,18 +14,19 @@
 //      (the rank of a record among equal slots is a popcount of the ballot
 //      match mask), so each thread's records become contiguous and stay in
 //      record order;
-//   5. cuts every thread's records into runs of at most R and lets each lane
-//      walk one run with a run-local call stack (entry: push; exit: pop and
-//      match), the stack operations that define a call's interval (paper
-//      section 3.3) and its tally (section 3.4, the table of section 4.3);
-//   6. folds the runs in parallel: a segmented scan gives every run its start
-//      depth, so an exit that found its run's stack empty knows the level it
-//      closes; the run that opened that level is the nearest earlier run of
-//      the thread whose lowest level lies below it (a previous-smaller-value
-//      search), or the thread's stack carried from earlier tiles; children
-//      time is credited to parents with LDS atomics, then self time and the
-//      tally are computed for every call in one parallel pass;
-//   7. updates each thread's carried stack with the calls still open.
+//   5. hands each thread's records to one wavefront, 64 records per step
+//      (a window).  Within a window everything is lane-parallel: the depth
+//      after each record is the carried depth plus a popcount of entries
+//      minus exits before it; an exit's entry is the last earlier lane whose
+//      entry opened the same level (highest set bit of that level's entry
+//      ballot below the lane), and its parent the last earlier entry one
+//      level down; entries opened before the window are on the thread's
+//      stack carried in LDS, indexed by level.  These are the stack
+//      operations that define a call's interval (paper section 3.3) and its
+//      tally (section 3.4, the table of section 4.3), done for 64 records at
+//      once.  Children time reaches parents through one LDS atomic per call,
+//      then self time and the tally follow, and the calls still open at the
+//      window end become the carried stack.
 // An exit that closes a call opened before the range is written to the range
 // summary (U item) with the children time that call collected inside the
 // range; the calls still open at the range end are written as O items.  The
@@ -35,43 +36,25 @@
 
 namespace tt {
 
-constexpr uint32_t NIL16 = 0xFFFFu;
-// tile_fk bits: [0,16) fn | 16 kind (0 entry, 1 exit) | flags | [24,32) rank of a U item in its run
-constexpr uint32_t FK_EXIT = 1u << 16;
-constexpr uint32_t FK_U = 1u << 17;      // exit that found its run's stack empty
-constexpr uint32_t FK_LOCAL = 1u << 18;  // exit matched inside its run
-constexpr uint32_t FK_MIS = 1u << 19;    // popped entry has another fn: not tallied
-constexpr uint32_t FK_NEG = 1u << 20;    // exit earlier than its entry: not tallied
-constexpr uint32_t FK_REAL = 1u << 21;   // U item matched to a real entry (tile or carried stack)
-// partner references of U items (tile_lnk after the fold)
-constexpr uint32_t REF_CARRIED = 0x8000u;  // | position in the carried stack
-constexpr uint32_t REF_VIRTUAL = 0xC000u;  // | levels below the thread's floor (opened before the range)
-constexpr uint32_t REF_LOST = 0xBFFFu;     // beyond the stack capacity (depth overflow)
+constexpr int RWG = 1024;           // lanes of the range kernel's workgroup
+constexpr int RNW = RWG / WAVE;     // its wavefronts
+constexpr uint32_t FK_EXIT = 1u << 16;  // tile_fk: [0,16) fn | 16 kind (0 entry, 1 exit)
 constexpr int32_t BIG = 0x3FFFFFFF;
 
 struct RangeLds {
-  // tile, sorted by slot
-  uint64_t *tile_ts;   // timestamp (a real U item's slot is reused for its inclusive time)
-  uint64_t *tile_ch;   // entry: children time; local exit: inclusive time; U item: children time in run
+  uint64_t *tile_ts;   // tile sorted by slot: timestamp
   uint64_t *tile_by;   // VAR16 transfer size of entries
-  uint32_t *tile_fk;
-  uint16_t *tile_lnk;  // entry: entry below it on its run stack; local exit: its entry; U item: run, then partner
-  uint8_t *tile_slot;
-  // runs
-  uint32_t *run_info;  // start (16) | length (8) | slot (8)
-  uint32_t *run_uo;    // U items (16) | open entries at the end (16)
-  uint32_t *run_hm;    // max local height (16) | max local level (16, signed)
-  uint64_t *run_base;  // children time owed to the call below the run's entries at its end
-  int32_t *run_ds, *run_m, *run_pm, *run_suf;  // start level, lowest level, prefix / suffix minimum
-  uint16_t *oidx;      // [run][level - m - 1] -> open entry
+  uint32_t *tile_fk;   // fn | kind << 16
   // thread slots
-  uint32_t *s_gslot, *s_flags, *s_run0;
-  int32_t *s_u, *s_o, *s_H, *s_M;
-  uint64_t *s_facc, *s_first, *s_last, *s_lastnew;
-  // carried stacks [slot][D] and children time of virtual levels [slot][D]
-  uint64_t *c_ts, *c_ch, *c_by, *vacc;
+  uint32_t *s_gslot, *s_flags;
+  int32_t *s_d, *s_u, *s_H, *s_M;   // depth relative to the range start, virtual closes, excursion
+  uint64_t *s_facc, *s_first, *s_last;
+  // carried stacks [slot][D] by level above the floor
+  uint64_t *c_ts, *c_ch, *c_by;
   uint16_t *c_fn;
-  // tally hash
+  // per-wave scratch: children time of the window's lanes, of virtual levels
+  uint64_t *w_ch, *w_vt;
+  // tally
   uint32_t *t_key, *t_cnt, *t_imin, *t_imax, *t_smin, *t_smax;
   uint64_t *t_isum, *t_ssum, *t_bsum;
   // kernel tally
@@ -81,20 +64,19 @@ struct RangeLds {
   uint64_t *tidmap;
   uint32_t *wcnt, *wbase, *soff;
   uint32_t *newtid, *newbucket;
-  uint32_t *misc;   // [0] nslots, [1] new ids, [2] runs in tile, [3] API records in tile
+  uint32_t *misc;   // [0] nslots, [1] new ids
   uint32_t *cnt;    // [ST_N] range-local counters
-  uint32_t *wsum;   // [NWAVES] per-wave payload sums
+  uint32_t *wsum;   // [RNW] per-wave payload sums
 };
 
 __host__ __device__ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
-__host__ __device__ inline uint32_t nruns_max(uint32_t T, uint32_t R) { return T / R + S_MAX; }
 // Distinct threads one range can hold: their carried stacks live in LDS.
 __host__ __device__ inline uint32_t slot_cap(uint32_t D) { return D <= 16 ? (uint32_t)S_MAX : 1024u / D; }
 
 // Byte layout of the dynamic LDS; the same function sizes it on the host.
 template <bool CARVE>
-__host__ __device__ inline size_t range_lds_layout(uint8_t *base, RangeLds *L, uint32_t T, uint32_t R, uint32_t E,
-                                                   uint32_t KL, uint32_t D, int fmt) {
+__host__ __device__ inline size_t range_lds_layout(uint8_t *base, RangeLds *L, uint32_t T, uint32_t E, uint32_t KL,
+                                                   uint32_t D, int fmt) {
   size_t o = 0;
   auto take = [&](size_t bytes) -> uint8_t * {
     o = align_up(o, 16);
@@ -102,40 +84,27 @@ __host__ __device__ inline size_t range_lds_layout(uint8_t *base, RangeLds *L, u
     o += bytes;
     return p;
   };
-  const uint32_t NR = nruns_max(T, R);
+  const size_t SC = slot_cap(D);
   uint8_t *p;
 #define TAKE(field, type, count) p = take(sizeof(type) * (size_t)(count)); if (CARVE) L->field = (type *)p
   TAKE(tile_ts, uint64_t, T);
-  TAKE(tile_ch, uint64_t, T);
   TAKE(tile_by, uint64_t, fmt == 2 ? T : 0);
   TAKE(tile_fk, uint32_t, T);
-  TAKE(tile_lnk, uint16_t, T);
-  TAKE(tile_slot, uint8_t, T);
-  TAKE(run_info, uint32_t, NR);
-  TAKE(run_uo, uint32_t, NR);
-  TAKE(run_hm, uint32_t, NR);
-  TAKE(run_base, uint64_t, NR);
-  TAKE(run_ds, int32_t, NR);
-  TAKE(run_m, int32_t, NR);
-  TAKE(run_pm, int32_t, NR);
-  TAKE(run_suf, int32_t, NR);
-  TAKE(oidx, uint16_t, (size_t)NR * R);
   TAKE(s_gslot, uint32_t, S_MAX);
   TAKE(s_flags, uint32_t, S_MAX);
-  TAKE(s_run0, uint32_t, S_MAX + 1);
+  TAKE(s_d, int32_t, S_MAX);
   TAKE(s_u, int32_t, S_MAX);
-  TAKE(s_o, int32_t, S_MAX);
   TAKE(s_H, int32_t, S_MAX);
   TAKE(s_M, int32_t, S_MAX);
   TAKE(s_facc, uint64_t, S_MAX);
   TAKE(s_first, uint64_t, S_MAX);
   TAKE(s_last, uint64_t, S_MAX);
-  TAKE(s_lastnew, uint64_t, S_MAX);
-  TAKE(c_ts, uint64_t, (size_t)slot_cap(D) * D);
-  TAKE(c_ch, uint64_t, (size_t)slot_cap(D) * D);
-  TAKE(c_by, uint64_t, fmt == 2 ? (size_t)slot_cap(D) * D : 0);
-  TAKE(vacc, uint64_t, (size_t)slot_cap(D) * D);
-  TAKE(c_fn, uint16_t, (size_t)slot_cap(D) * D);
+  TAKE(c_ts, uint64_t, SC * D);
+  TAKE(c_ch, uint64_t, SC * D);
+  TAKE(c_by, uint64_t, fmt == 2 ? SC * D : 0);
+  TAKE(c_fn, uint16_t, SC * D);
+  TAKE(w_ch, uint64_t, (size_t)RNW * WAVE);
+  TAKE(w_vt, uint64_t, (size_t)RNW * D);
   TAKE(t_key, uint32_t, E);
   TAKE(t_cnt, uint32_t, E);
   TAKE(t_imin, uint32_t, E);
@@ -150,20 +119,20 @@ __host__ __device__ inline size_t range_lds_layout(uint8_t *base, RangeLds *L, u
   TAKE(q_max, uint32_t, KL);
   TAKE(q_sum, uint64_t, KL);
   TAKE(tidmap, uint64_t, TIDMAP);
-  TAKE(wcnt, uint32_t, NWAVES * S_MAX);
-  TAKE(wbase, uint32_t, NWAVES * S_MAX);
+  TAKE(wcnt, uint32_t, RNW * S_MAX);
+  TAKE(wbase, uint32_t, RNW * S_MAX);
   TAKE(soff, uint32_t, S_MAX + 1);
   TAKE(newtid, uint32_t, TIDMAP);
   TAKE(newbucket, uint32_t, TIDMAP);
   TAKE(misc, uint32_t, 8);
   TAKE(cnt, uint32_t, ST_N);
-  TAKE(wsum, uint32_t, NWAVES * 2);
+  TAKE(wsum, uint32_t, RNW);
 #undef TAKE
   return align_up(o, 16);
 }
 
-size_t range_lds_bytes(uint32_t T, uint32_t R, uint32_t E, uint32_t KL, uint32_t D, int fmt) {
-  return range_lds_layout<false>(nullptr, nullptr, T, R, E, KL, D, fmt);
+size_t range_lds_bytes(uint32_t T, uint32_t E, uint32_t KL, uint32_t D, int fmt) {
+  return range_lds_layout<false>(nullptr, nullptr, T, E, KL, D, fmt);
 }
 
 // ---------------------------------------------------------------- helpers
@@ -313,53 +282,200 @@ __device__ inline void tally_call(const RangeLds &L, uint32_t E, const Tables &t
   }
 }
 
-// ------------------------------------------------------------------ scans
-// Wave-level segmented inclusive scans over int32; `head` marks the first
-// element of a segment (forward) or `tail` its last element (backward).
-// `closed` returns whether the lane's segment boundary lies inside the wave.
-__device__ inline int32_t seg_scan_add(int32_t v, bool head, bool &closed) {
-  const int lane = __lane_id();
-  int f = head;
+__device__ inline uint64_t lanemask_le() {
+  const uint32_t lane = __lane_id();
+  return lane == 63 ? ~0ull : ((2ull << lane) - 1);
+}
+__device__ inline uint64_t shfl64(uint64_t v, int src) {
+  const uint32_t lo = __shfl((uint32_t)v, src, WAVE), hi = __shfl((uint32_t)(v >> 32), src, WAVE);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ inline uint64_t shfl64_up1(uint64_t v) {
+  const uint32_t lo = __shfl_up((uint32_t)v, 1, WAVE), hi = __shfl_up((uint32_t)(v >> 32), 1, WAVE);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ inline int32_t wave_min_i32(int32_t v) {
 #pragma unroll
-  for (int o = 1; o < WAVE; o <<= 1) {
-    const int32_t t = __shfl_up(v, o, WAVE);
-    const int tf = __shfl_up(f, o, WAVE);
-    if (lane >= o) { if (!f) v += t; f |= tf; }
-  }
-  closed = f;
+  for (int o = 1; o < WAVE; o <<= 1) { const int32_t t = __shfl_xor(v, o, WAVE); v = t < v ? t : v; }
   return v;
 }
-__device__ inline int32_t seg_scan_min(int32_t v, bool head, bool &closed) {
-  const int lane = __lane_id();
-  int f = head;
+__device__ inline int32_t wave_max_i32(int32_t v) {
 #pragma unroll
-  for (int o = 1; o < WAVE; o <<= 1) {
-    const int32_t t = __shfl_up(v, o, WAVE);
-    const int tf = __shfl_up(f, o, WAVE);
-    if (lane >= o) { if (!f) v = t < v ? t : v; f |= tf; }
-  }
-  closed = f;
+  for (int o = 1; o < WAVE; o <<= 1) { const int32_t t = __shfl_xor(v, o, WAVE); v = t > v ? t : v; }
   return v;
 }
-__device__ inline int32_t seg_rscan_min(int32_t v, bool tail, bool &closed) {
+__device__ inline int32_t wave_prefix_min_i32(int32_t v) {
   const int lane = __lane_id();
-  int f = tail;
 #pragma unroll
-  for (int o = 1; o < WAVE; o <<= 1) {
-    const int32_t t = __shfl_down(v, o, WAVE);
-    const int tf = __shfl_down(f, o, WAVE);
-    if (lane + o < WAVE) { if (!f) v = t < v ? t : v; f |= tf; }
-  }
-  closed = f;
+  for (int o = 1; o < WAVE; o <<= 1) { const int32_t t = __shfl_up(v, o, WAVE); if (lane >= o) v = t < v ? t : v; }
   return v;
+}
+// Orders this wavefront's LDS accesses around it (all lanes take part).
+__device__ inline void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
 }
 
-// One tile of the range: decode `cur*`, prefetch the next tile into `nxt*`,
-// then slot map, sort, walk, fold, tally and carry.  Force-inlined twice by
-// the kernel so the two register buffers alternate without copies.
+// ------------------------------------------------------------------ window
 struct Counters { uint32_t c[ST_N]; };
 
-template <int FMT, int ROWS, int R>
+// One window: up to 64 consecutive records [a, a + nw) of slot s, one per
+// lane of the calling wavefront (all 64 lanes must call).
+template <int FMT>
+__device__ __forceinline__ void slot_window(RangeLds &L, const Tables &tb, const uint32_t E, const uint32_t D,
+                                            const uint32_t s, const uint32_t a, const uint32_t nw,
+                                            const size_t sbase, UItem *__restrict__ ru, Counters &C,
+                                            uint64_t *__restrict__ wch, uint64_t *__restrict__ wvt) {
+  const uint32_t lane = __lane_id();
+  const bool valid = lane < nw;
+  const uint32_t p = a + (valid ? lane : 0);
+  const uint64_t ts = valid ? L.tile_ts[p] : 0;
+  const uint32_t fk = valid ? L.tile_fk[p] : 0;
+  const uint32_t fn = fk & 0xFFFFu;
+  const bool ex = valid && (fk & FK_EXIT);
+  const bool en = valid && !(fk & FK_EXIT);
+  const uint64_t by = (FMT == 2 && valid) ? L.tile_by[p] : 0;
+  const int32_t d0 = L.s_d[s], u0 = L.s_u[s], fl0 = -u0;
+  const uint32_t flags0 = L.s_flags[s];
+  const uint64_t last0 = L.s_last[s];
+  // timestamp order within the thread
+  const uint64_t prev = shfl64_up1(ts);
+  if (valid) {
+    if (lane > 0) C.c[ST_TSREG] += ts < prev ? 1u : 0u;
+    else if (flags0 & RF_HAS_TS) C.c[ST_TSREG] += ts < last0 ? 1u : 0u;
+    else L.s_first[s] = ts;
+  }
+  // depth after each record (relative to the range start) and the level each record opens or closes
+  const uint64_t Em = __ballot(en), Xm = __ballot(ex);
+  const uint64_t le = lanemask_le(), lt = lanemask_lt();
+  const int32_t da = d0 + (int32_t)__popcll(Em & le) - (int32_t)__popcll(Xm & le);
+  const int32_t lev = en ? da : da + 1;
+  const int32_t d_end = d0 + (int32_t)__popcll(Em) - (int32_t)__popcll(Xm);
+  const int32_t levmin = wave_min_i32(valid ? lev : BIG);
+  const int32_t levmax = wave_max_i32(valid ? lev : -BIG);
+  const int32_t pmin = wave_prefix_min_i32(valid ? da : BIG);
+  const int32_t dlow = __shfl(pmin, WAVE - 1, WAVE);
+  const int32_t damin = dlow < d0 ? dlow : d0;      // lowest depth reached in the window
+  const int32_t fl1 = damin < fl0 ? damin : fl0;    // floor after the window
+  {
+    const int32_t fat = pmin < fl0 ? pmin : fl0;    // floor when this record happens
+    const int32_t hh = wave_max_i32(en ? lev - fat : -BIG);
+    const int32_t mm = wave_max_i32(en ? lev : -BIG);
+    if (lane == 0) {
+      if (hh > L.s_H[s]) L.s_H[s] = hh;
+      if (mm > L.s_M[s]) L.s_M[s] = mm;
+    }
+  }
+  wch[lane] = 0;
+  if (lane < D) wvt[lane] = 0;
+  wave_lds_fence();
+  // partner (entry of an exit) and parent (entry one level down) by level ballots
+  int32_t partner = -1, parent = -1;
+  bool open_at_end = false;
+  uint64_t prevE = 0;
+  for (int32_t v = levmin; v <= levmax; v++) {
+    const uint64_t Ev = __ballot(en && lev == v);
+    if (ex && lev == v) {
+      const uint64_t m1 = Ev & lt, m2 = prevE & lt;
+      partner = m1 ? 63 - (int32_t)__clzll(m1) : -1;
+      parent = m2 ? 63 - (int32_t)__clzll(m2) : -1;
+    }
+    if (Ev && v > damin && v <= d_end && lane == (uint32_t)(63 - __clzll(Ev))) open_at_end = true;
+    prevE = Ev;
+  }
+  // the entry each exit closes: in the window, on the carried stack, or opened before the range
+  uint64_t pts = shfl64(ts, partner >= 0 ? partner : (int32_t)lane);
+  uint32_t pfn = __shfl(fn, partner >= 0 ? partner : (int32_t)lane, WAVE);
+  uint64_t pby = FMT == 2 ? shfl64(by, partner >= 0 ? partner : (int32_t)lane) : 0;
+  int kind = 0;  // 1 window, 2 carried, 3 opened before the range, 4 beyond the stack capacity
+  uint32_t cpos = 0;
+  if (ex) {
+    if (partner >= 0) kind = 1;
+    else if (lev > fl0) {
+      cpos = (uint32_t)(lev - fl0 - 1);
+      if (cpos < D) {
+        kind = 2;
+        const uint32_t i = s * D + cpos;
+        pts = L.c_ts[i]; pfn = L.c_fn[i];
+        if (FMT == 2) pby = L.c_by[i];
+      } else {
+        kind = 4;
+      }
+    } else {
+      kind = 3;
+    }
+  }
+  bool ok = false;
+  uint64_t incl = 0;
+  if (kind == 1 || kind == 2) {
+    if (pfn != fn) C.c[ST_MISMATCH]++;
+    else if (ts < pts) C.c[ST_NEGDUR]++;
+    else { ok = true; incl = ts - pts; }
+  }
+  // children time to the parent
+  if (ok) {
+    if (parent >= 0) {
+      lds_add64(&wch[parent], incl);
+    } else {
+      const int32_t pl = lev - 1;
+      if (pl > fl0) {
+        const uint32_t pp = (uint32_t)(pl - fl0 - 1);
+        if (pp < D) lds_add64(&L.c_ch[s * D + pp], incl);
+      } else {
+        const uint32_t vk = (uint32_t)(fl0 - pl);
+        if (vk == 0) lds_add64(&L.s_facc[s], incl);
+        else if (vk - 1 < D && (uint32_t)u0 + vk < D) lds_add64(&wvt[vk - 1], incl);
+      }
+    }
+  }
+  wave_lds_fence();
+  // self time and tally of every call closed here; exits that close calls opened before the range
+  if (ok) {
+    const uint64_t ch = kind == 1 ? wch[partner] : L.c_ch[s * D + cpos];
+    uint64_t self;
+    if (ch <= incl) self = incl - ch;
+    else { self = 0; C.c[ST_UNDER]++; }
+    tally_call<FMT>(L, E, tb, s, L.s_gslot[s], fn, incl, self, pby);
+  } else if (kind == 3) {
+    const uint32_t vk = (uint32_t)(fl0 - lev);
+    const uint32_t gi = (uint32_t)u0 + vk;
+    if (gi < D) {
+      const uint64_t acc = vk == 0 ? L.s_facc[s] : (vk - 1 < D ? wvt[vk - 1] : 0);
+      UItem *u = &ru[(sbase + s) * D + gi];
+      u->ts = ts; u->child = acc; u->fn = fn; u->pad = 0; u->pad2 = 0;
+    } else {
+      C.c[ST_ORPHAN]++;  // deeper than any stack can be: certainly an orphan exit
+    }
+  }
+  wave_lds_fence();
+  // calls still open at the window end become the carried stack
+  if (open_at_end) {
+    const uint32_t pos = (uint32_t)(lev - fl1 - 1);
+    if (pos < D) {
+      const uint32_t i = s * D + pos;
+      L.c_ts[i] = ts; L.c_ch[i] = wch[lane]; L.c_fn[i] = (uint16_t)fn;
+      if (FMT == 2) L.c_by[i] = by;
+    } else {
+      atomicOr(&L.s_flags[s], RF_OVERFLOW);
+    }
+  }
+  if (lane == 0) {
+    L.s_d[s] = d_end;
+    L.s_u[s] = -fl1;
+    if (fl1 < fl0) {
+      const uint32_t vk = (uint32_t)(fl0 - fl1);
+      L.s_facc[s] = (vk - 1 < D && (uint32_t)u0 + vk < D) ? wvt[vk - 1] : 0;
+    }
+    atomicOr(&L.s_flags[s], RF_HAS_TS);
+  }
+  if (lane + 1 == nw) L.s_last[s] = ts;
+  wave_lds_fence();
+}
+
+// ------------------------------------------------------------------ tile
+// One tile of the range: decode `cur*`, prefetch the next tile into `nxt*`,
+// slot map and sort, then every wavefront walks the windows of its slots.
+template <int FMT, int ROWS>
 __device__ __forceinline__ void tile_pass(RangeLds &L, const Tables &tb, const uint32_t E, const uint32_t KL,
                                           const uint32_t D, const Range &rg, const Seg &sg, gu64 *grec,
                                           const uint64_t last_rec, const uint64_t t0, const uint64_t (&cur0)[ROWS],
@@ -367,7 +483,7 @@ __device__ __forceinline__ void tile_pass(RangeLds &L, const Tables &tb, const u
                                           uint64_t (&nxt0)[ROWS], uint64_t (&nxt1)[ROWS], uint64_t (&nxt2)[ROWS],
                                           uint64_t &pay_run, const size_t sbase, UItem *__restrict__ ru,
                                           Counters &C) {
-  constexpr uint32_t T = ROWS * WG;
+  constexpr uint32_t T = ROWS * RWG;
   constexpr uint32_t RS = FMT == 2 ? 16 : 24;
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid >> 6;
   const uint32_t n = (uint32_t)((rg.n - t0) < T ? (rg.n - t0) : T);
@@ -384,7 +500,7 @@ __device__ __forceinline__ void tile_pass(RangeLds &L, const Tables &tb, const u
     }
 #pragma unroll
     for (int r = 0; r < ROWS; r++) {
-      const uint32_t li = (uint32_t)w * (T / NWAVES) + (uint32_t)r * WAVE + lane;
+      const uint32_t li = (uint32_t)w * (T / RNW) + (uint32_t)r * WAVE + lane;
       uint64_t idx = rg.begin + t0 + T + li;
       idx = idx < last_rec ? idx : last_rec;
       gu64 *p = grec + idx * (RS / 8);
@@ -398,7 +514,7 @@ __device__ __forceinline__ void tile_pass(RangeLds &L, const Tables &tb, const u
       uint32_t excl[ROWS];
 #pragma unroll
       for (int r = 0; r < ROWS; r++) {
-        const uint32_t li = (uint32_t)w * (T / NWAVES) + (uint32_t)r * WAVE + lane;
+        const uint32_t li = (uint32_t)w * (T / RNW) + (uint32_t)r * WAVE + lane;
         const uint32_t v = li < n ? (r_fk[r] >> 24) : 0;
         const uint32_t inc = wave_incl_scan(v);
         excl[r] = run + inc - v;
@@ -407,10 +523,10 @@ __device__ __forceinline__ void tile_pass(RangeLds &L, const Tables &tb, const u
       if (lane == 0) L.wsum[w] = run;
       __syncthreads();
       uint32_t wpre = 0, tot = 0;
-      for (int k = 0; k < NWAVES; k++) { const uint32_t s = L.wsum[k]; if (k < w) wpre += s; tot += s; }
+      for (int k = 0; k < RNW; k++) { const uint32_t s = L.wsum[k]; if (k < w) wpre += s; tot += s; }
 #pragma unroll
       for (int r = 0; r < ROWS; r++) {
-        const uint32_t li = (uint32_t)w * (T / NWAVES) + (uint32_t)r * WAVE + lane;
+        const uint32_t li = (uint32_t)w * (T / RNW) + (uint32_t)r * WAVE + lane;
         const uint32_t fn = r_fk[r] & 0xFFFFu, kind = (r_fk[r] >> 16) & 0xFFu, plen = r_fk[r] >> 24;
         const uint64_t off = pay_run + wpre + excl[r];
         const bool sized = li < n && kind == 0 && fn < tb.n_fns && plen >= 8 && tb.has_size && tb.has_size[fn];
@@ -427,7 +543,7 @@ __device__ __forceinline__ void tile_pass(RangeLds &L, const Tables &tb, const u
     uint32_t n_ent = 0, n_exi = 0, n_kern = 0, n_bad = 0;
 #pragma unroll
     for (int r = 0; r < ROWS; r++) {
-      const uint32_t li = (uint32_t)w * (T / NWAVES) + (uint32_t)r * WAVE + lane;
+      const uint32_t li = (uint32_t)w * (T / RNW) + (uint32_t)r * WAVE + lane;
       const uint32_t fn = r_fk[r] & 0xFFFFu, kind = (r_fk[r] >> 16) & 0xFFu, plen = r_fk[r] >> 24;
       r_slot[r] = EMPTY32;
       if (li >= n) continue;
@@ -559,12 +675,12 @@ __device__ __forceinline__ void tile_pass(RangeLds &L, const Tables &tb, const u
     if (w == 0) {
       uint32_t tot = 0;
       if ((uint32_t)lane < nslots)
-        for (int k = 0; k < NWAVES; k++) tot += L.wcnt[k * S_MAX + lane];
+        for (int k = 0; k < RNW; k++) tot += L.wcnt[k * S_MAX + lane];
       const uint32_t inc = wave_incl_scan(tot);
       if ((uint32_t)lane < nslots) {
         uint32_t acc = inc - tot;
         L.soff[lane] = acc;
-        for (int k = 0; k < NWAVES; k++) { L.wbase[k * S_MAX + lane] = acc; acc += L.wcnt[k * S_MAX + lane]; }
+        for (int k = 0; k < RNW; k++) { L.wbase[k * S_MAX + lane] = acc; acc += L.wcnt[k * S_MAX + lane]; }
       }
       if (lane == WAVE - 1) L.soff[nslots] = inc;
     }
@@ -575,360 +691,60 @@ __device__ __forceinline__ void tile_pass(RangeLds &L, const Tables &tb, const u
       const uint32_t pos = L.wbase[w * S_MAX + r_slot[r]] + r_rank[r];
       L.tile_ts[pos] = r_ts[r];
       L.tile_fk[pos] = (r_fk[r] & 0xFFFFu) | (((r_fk[r] >> 16) & 1u) << 16);
-      L.tile_slot[pos] = (uint8_t)r_slot[r];
       if (FMT == 2) L.tile_by[pos] = r_by[r];
     }
     __syncthreads();
-    const uint32_t napi = L.soff[nslots];
-    // ---- P5. timestamp order per thread; runs of at most R records per thread
-    {
-      uint32_t c_tsreg = 0;
-      for (uint32_t p = tid; p < napi; p += WG) {
-        const uint32_t s = L.tile_slot[p];
-        const uint64_t ts = L.tile_ts[p];
-        if (p > L.soff[s]) {
-          if (ts < L.tile_ts[p - 1]) c_tsreg++;
-        } else if (L.s_flags[s] & RF_HAS_TS) {
-          if (ts < L.s_last[s]) c_tsreg++;
-        } else {
-          L.s_first[s] = ts;
-        }
-        if (p + 1 == L.soff[s + 1]) L.s_lastnew[s] = ts;
-      }
-      C.c[ST_TSREG] += c_tsreg;
-    }
-    if (w == 0) {
-      const uint32_t c = (uint32_t)lane < nslots ? L.soff[lane + 1] - L.soff[lane] : 0;
-      const uint32_t nr = (c + R - 1) / R;
-      const uint32_t inc = wave_incl_scan(nr);
-      if ((uint32_t)lane < nslots) L.s_run0[lane] = inc - nr;
-      if (lane == WAVE - 1) { L.s_run0[nslots] = inc; L.misc[2] = inc; }
-    }
-    for (uint32_t i = tid; i < nslots * D; i += WG) L.vacc[i] = 0;
-    __syncthreads();
-    const uint32_t NR = L.misc[2];
-    for (uint32_t t = tid; t < NR; t += WG) {
-      uint32_t lo = 0, hi = nslots - 1;
-      while (lo < hi) {
-        const uint32_t mid = (lo + hi + 1) >> 1;
-        if (L.s_run0[mid] <= t) lo = mid; else hi = mid - 1;
-      }
-      const uint32_t s = lo;
-      const uint32_t a = L.soff[s] + (t - L.s_run0[s]) * R;
-      const uint32_t len = (L.soff[s + 1] - a) < R ? (L.soff[s + 1] - a) : R;
-      L.run_info[t] = a | (len << 16) | (s << 24);
-    }
-    __syncthreads();
-    // ---- P6. walk: one lane per run, run-local stack linked through the tile
-    for (uint32_t t = tid; t < NR; t += WG) {
-      const uint32_t info = L.run_info[t];
-      const uint32_t a = info & 0xFFFFu, len = (info >> 16) & 0xFFu;
-      uint32_t top = NIL16;
-      uint64_t topc = 0, pend = 0;
-      int32_t h = 0, nu = 0, Hr = 0, Mr = 0;
-#pragma unroll
-      for (int i = 0; i < R; i++) {
-        if ((uint32_t)i >= len) break;
-        const uint32_t p = a + i;
-        const uint64_t ts = L.tile_ts[p];
-        const uint32_t fk = L.tile_fk[p];
-        if (!(fk & FK_EXIT)) {
-          if (top != NIL16) L.tile_ch[top] = topc;
-          L.tile_lnk[p] = (uint16_t)top;
-          top = p;
-          topc = 0;
-          h++;
-          Hr = h > Hr ? h : Hr;
-          Mr = h - nu > Mr ? h - nu : Mr;
-        } else if (top != NIL16) {
-          const uint32_t e = top;
-          const uint64_t ets = L.tile_ts[e];
-          const uint32_t efn = L.tile_fk[e] & 0xFFFFu;
-          const uint32_t nt = L.tile_lnk[e];
-          L.tile_ch[e] = topc;
-          uint32_t fl = FK_LOCAL;
-          uint64_t incl = 0;
-          if (efn != (fk & 0xFFFFu)) fl |= FK_MIS;
-          else if (ts < ets) fl |= FK_NEG;
-          else incl = ts - ets;
-          L.tile_fk[p] = fk | fl;
-          L.tile_ch[p] = incl;
-          L.tile_lnk[p] = (uint16_t)e;
-          const uint64_t add = (fl & (FK_MIS | FK_NEG)) ? 0 : incl;
-          h--;
-          top = nt;
-          if (nt != NIL16) topc = L.tile_ch[nt] + add;
-          else { pend += add; topc = 0; }
-        } else {
-          L.tile_fk[p] = fk | FK_U | ((uint32_t)nu << 24);
-          L.tile_ch[p] = pend;
-          L.tile_lnk[p] = (uint16_t)t;
-          pend = 0;
-          nu++;
-        }
-      }
-      if (top != NIL16) L.tile_ch[top] = topc;
-      uint32_t q = top;
-      for (int32_t k = h - 1; k >= 0; k--) { L.oidx[t * R + k] = (uint16_t)q; q = L.tile_lnk[q]; }
-      L.run_uo[t] = (uint32_t)nu | ((uint32_t)h << 16);
-      L.run_base[t] = pend;
-      L.run_hm[t] = ((uint32_t)Hr & 0xFFFFu) | ((uint32_t)Mr << 16);
-    }
-    __syncthreads();
-    // ---- P7. per-thread scans over runs: start level, lowest level, floor, suffix minimum
-    if (w == 0) {
-      int32_t csum = 0, cmin = BIG, cslot = -1;
-      for (uint32_t c0 = 0; c0 < NR; c0 += WAVE) {
-        const uint32_t r = c0 + lane;
-        const bool valid = r < NR;
-        const int32_t s = valid ? (int32_t)(L.run_info[r] >> 24) : -1;
-        const bool head = !valid || r == L.s_run0[s];
-        const uint32_t uo = valid ? L.run_uo[r] : 0;
-        const int32_t nu = (int32_t)(uo & 0xFFFFu), no = (int32_t)(uo >> 16);
-        const int32_t v = no - nu;
-        bool cl;
-        int32_t inc = seg_scan_add(v, head, cl);
-        if (!cl && s == cslot) inc += csum;
-        const int32_t su = valid ? L.s_u[s] : 0;
-        const int32_t ds = valid ? (L.s_o[s] - su) + inc - v : 0;
-        const int32_t m = ds - nu;
-        bool cl2;
-        int32_t imin = seg_scan_min(valid ? m : BIG, head, cl2);
-        if (!cl2 && s == cslot) imin = imin < cmin ? imin : cmin;
-        const int32_t prev = __shfl_up(imin, 1, WAVE);
-        int32_t exmin = BIG;
-        if (!head) exmin = lane == 0 ? cmin : prev;
-        const int32_t F = exmin < -su ? exmin : -su;
-        if (valid) {
-          L.run_ds[r] = ds;
-          L.run_m[r] = m;
-          L.run_pm[r] = exmin;
-          const uint32_t hm = L.run_hm[r];
-          const int32_t Hr = (int32_t)(hm & 0xFFFFu), Mr = (int32_t)(hm >> 16);
-          const int32_t hh = ds - F + Mr > Hr ? ds - F + Mr : Hr;
-          atomicMax(&L.s_H[s], hh);
-          atomicMax(&L.s_M[s], ds + Mr);
-        }
-        csum = __shfl(inc, WAVE - 1, WAVE);
-        cmin = __shfl(imin, WAVE - 1, WAVE);
-        cslot = __shfl(s, WAVE - 1, WAVE);
-      }
-      int32_t rmin = BIG, rslot = -1;
-      const int32_t nch = (int32_t)((NR + WAVE - 1) / WAVE);
-      for (int32_t c = nch - 1; c >= 0; c--) {
-        const uint32_t r = (uint32_t)c * WAVE + lane;
-        const bool valid = r < NR;
-        const int32_t s = valid ? (int32_t)(L.run_info[r] >> 24) : -1;
-        const bool tail = !valid || r + 1 == L.s_run0[s + 1];
-        const int32_t m = valid ? L.run_m[r] : BIG;
-        bool cl;
-        int32_t inc = seg_rscan_min(m, tail, cl);
-        if (!cl && s == rslot) inc = inc < rmin ? inc : rmin;
-        const int32_t nxt = __shfl_down(inc, 1, WAVE);
-        int32_t suf = BIG;
-        if (!tail) suf = lane == WAVE - 1 ? rmin : nxt;
-        if (valid) L.run_suf[r] = suf;
-        rmin = __shfl(inc, 0, WAVE);
-        rslot = __shfl(s, 0, WAVE);
-      }
-    }
-    __syncthreads();
-    // ---- P8. fold: match exits that left their run, credit children time to parents
-    // psv(r, lev): the open entry at level `lev` as seen from run r
-    auto psv = [&](uint32_t r, int32_t lev, uint32_t s) -> uint32_t {
-      if (L.run_pm[r] < lev) {  // some earlier run of this tile went below lev: the nearest one opened it
-        int32_t j = (int32_t)r - 1;
-        while (L.run_m[j] >= lev) j--;
-        return L.oidx[(uint32_t)j * R + (uint32_t)(lev - L.run_m[j] - 1)];
-      }
-      const int32_t fl = -L.s_u[s];
-      if (lev > fl) {
-        const uint32_t pos = (uint32_t)(lev - fl - 1);
-        return pos < D ? (REF_CARRIED | pos) : REF_LOST;
-      }
-      const uint32_t vk = (uint32_t)(fl - lev);
-      return REF_VIRTUAL | (vk < 0x3FFFu ? vk : 0x3FFFu);
-    };
-    auto add_child = [&](uint32_t ref, uint32_t s, uint64_t v) {
-      if (!v) return;
-      if (ref < REF_CARRIED) lds_add64(&L.tile_ch[ref], v);
-      else if (ref == REF_LOST) return;
-      else if (ref < REF_VIRTUAL) lds_add64(&L.c_ch[s * D + (ref & 0x3FFFu)], v);
-      else {
-        const uint32_t vk = ref & 0x3FFFu;
-        if (vk == 0) lds_add64(&L.s_facc[s], v);
-        else if (vk - 1 < D && (uint32_t)L.s_u[s] + vk < D) lds_add64(&L.vacc[s * D + vk - 1], v);
-      }
-    };
-    for (uint32_t p = tid; p < napi; p += WG) {
-      const uint32_t fk = L.tile_fk[p];
-      if (!(fk & FK_U)) continue;
-      const uint32_t s = L.tile_slot[p];
-      const uint32_t r = L.tile_lnk[p];
-      const int32_t lev = L.run_ds[r] - (int32_t)(fk >> 24);
-      const uint32_t ref = psv(r, lev, s);
-      L.tile_lnk[p] = (uint16_t)ref;
-      if (ref >= REF_VIRTUAL || ref == REF_LOST) continue;
-      uint64_t ets;
-      uint32_t efn;
-      if (ref < REF_CARRIED) { ets = L.tile_ts[ref]; efn = L.tile_fk[ref] & 0xFFFFu; }
-      else { const uint32_t i = s * D + (ref & 0x3FFFu); ets = L.c_ts[i]; efn = L.c_fn[i]; }
-      const uint64_t ts = L.tile_ts[p];
-      if (efn != (fk & 0xFFFFu)) { L.tile_fk[p] = fk | FK_MIS; continue; }
-      if (ts < ets) { L.tile_fk[p] = fk | FK_NEG; continue; }
-      const uint64_t incl = ts - ets;
-      L.tile_ts[p] = incl;
-      L.tile_fk[p] = fk | FK_REAL;
-      add_child(psv(r, lev - 1, s), s, incl);
-    }
-    for (uint32_t t = tid; t < NR; t += WG) {
-      const uint64_t b = L.run_base[t];
-      if (!b) continue;
-      const uint32_t s = L.run_info[t] >> 24;
-      add_child(psv(t, L.run_m[t], s), s, b);
-    }
-    __syncthreads();
-    // ---- P9. self time and tally of every call closed in this tile
-    {
-      uint32_t c_mis = 0, c_neg = 0, c_under = 0, c_orph = 0;
-      for (uint32_t p = tid; p < napi; p += WG) {
-        const uint32_t fk = L.tile_fk[p];
-        if (!(fk & FK_EXIT)) continue;
-        if (fk & FK_MIS) { c_mis++; continue; }
-        if (fk & FK_NEG) { c_neg++; continue; }
-        const uint32_t s = L.tile_slot[p];
-        const uint32_t fn = fk & 0xFFFFu;
-        uint64_t incl, ch, by = 0;
-        if (fk & FK_LOCAL) {
-          incl = L.tile_ch[p];
-          const uint32_t e = L.tile_lnk[p];
-          ch = L.tile_ch[e];
-          if (FMT == 2) by = L.tile_by[e];
-        } else if (fk & FK_REAL) {
-          incl = L.tile_ts[p];
-          const uint32_t ref = L.tile_lnk[p];
-          if (ref < REF_CARRIED) {
-            ch = L.tile_ch[ref] + L.tile_ch[p];
-            if (FMT == 2) by = L.tile_by[ref];
-          } else {
-            const uint32_t i = s * D + (ref & 0x3FFFu);
-            ch = L.c_ch[i] + L.tile_ch[p];
-            if (FMT == 2) by = L.c_by[i];
-          }
-        } else {
-          const uint32_t ref = L.tile_lnk[p];
-          if (ref < REF_VIRTUAL) continue;  // beyond the stack capacity: the flush fails anyway
-          const uint32_t vk = ref & 0x3FFFu;
-          const uint32_t gi = (uint32_t)L.s_u[s] + vk;
-          if (gi < D) {
-            const uint64_t acc = vk == 0 ? L.s_facc[s] : (vk - 1 < D ? L.vacc[s * D + vk - 1] : 0);
-            UItem *u = &ru[(sbase + s) * D + gi];
-            u->ts = L.tile_ts[p]; u->child = acc + L.tile_ch[p]; u->fn = fn; u->pad = 0; u->pad2 = 0;
-          } else {
-            c_orph++;  // deeper than any stack can be: certainly an orphan exit
-          }
-          continue;
-        }
-        uint64_t self;
-        if (ch <= incl) self = incl - ch; else { self = 0; c_under++; }
-        tally_call<FMT>(L, E, tb, s, L.s_gslot[s], fn, incl, self, by);
-      }
-      C.c[ST_MISMATCH] += c_mis;
-      C.c[ST_NEGDUR] += c_neg;
-      C.c[ST_UNDER] += c_under;
-      C.c[ST_ORPHAN] += c_orph;
-    }
-    __syncthreads();
-    // ---- P10. carried stacks and thread state for the next tile
-    for (uint32_t t = tid; t < NR; t += WG) {
-      const uint32_t no = L.run_uo[t] >> 16;
-      if (!no) continue;
-      const uint32_t s = L.run_info[t] >> 24;
-      const int32_t m = L.run_m[t], suf = L.run_suf[t];
-      const uint32_t last = L.s_run0[s + 1] - 1;
-      int32_t fl = L.run_pm[last] < L.run_m[last] ? L.run_pm[last] : L.run_m[last];
-      fl = fl < -L.s_u[s] ? fl : -L.s_u[s];
-      for (uint32_t k = 0; k < no; k++) {
-        const int32_t lev = m + 1 + (int32_t)k;
-        if (lev > suf) break;  // closed by a later run of this tile
-        const uint32_t e = L.oidx[t * R + k];
-        const uint32_t pos = (uint32_t)(lev - fl - 1);
-        if (pos < D) {
-          const uint32_t i = s * D + pos;
-          L.c_ts[i] = L.tile_ts[e];
-          L.c_ch[i] = L.tile_ch[e];
-          L.c_fn[i] = (uint16_t)(L.tile_fk[e] & 0xFFFFu);
-          if (FMT == 2) L.c_by[i] = L.tile_by[e];
-        } else {
-          atomicOr(&L.s_flags[s], RF_OVERFLOW);
-        }
-      }
-    }
-    if ((uint32_t)tid < nslots) {
-      const uint32_t s = tid, r0 = L.s_run0[s], r1 = L.s_run0[s + 1];
-      if (r1 > r0) {
-        const uint32_t last = r1 - 1;
-        const int32_t fl_old = -L.s_u[s];
-        int32_t fl = L.run_pm[last] < L.run_m[last] ? L.run_pm[last] : L.run_m[last];
-        fl = fl < fl_old ? fl : fl_old;
-        const uint32_t uo = L.run_uo[last];
-        const int32_t depth = L.run_ds[last] - (int32_t)(uo & 0xFFFFu) + (int32_t)(uo >> 16);
-        if (fl < fl_old) {
-          const uint32_t vk = (uint32_t)(fl_old - fl);
-          L.s_facc[s] = (vk - 1 < D && (uint32_t)L.s_u[s] + vk < D) ? L.vacc[s * D + vk - 1] : 0;
-        }
-        L.s_u[s] = -fl;
-        L.s_o[s] = depth - fl;
-        atomicOr(&L.s_flags[s], RF_HAS_TS);
-        L.s_last[s] = L.s_lastnew[s];
-      }
+    // ---- P5. windows: wavefront w walks slots w, w + RNW, ... in order
+    for (uint32_t s = (uint32_t)w; s < nslots; s += RNW) {
+      const uint32_t e = L.soff[s + 1];
+      for (uint32_t a = L.soff[s]; a < e; a += WAVE)
+        slot_window<FMT>(L, tb, E, D, s, a, (e - a) < WAVE ? (e - a) : WAVE, sbase, ru, C, L.w_ch + w * WAVE,
+                         L.w_vt + w * D);
     }
     __syncthreads();
 }
 
 // ------------------------------------------------------------------ kernel
-template <int FMT, int ROWS, int R>
-__global__ __launch_bounds__(WG) void k_range(const Seg *__restrict__ segs, const Range *__restrict__ ranges,
-                                              Tables tb, Shape sh, RHdr *__restrict__ rhdr,
-                                              UItem *__restrict__ ru, OItem *__restrict__ ro,
-                                              uint32_t *__restrict__ rnslots) {
+template <int FMT, int ROWS>
+__global__ __launch_bounds__(RWG) void k_range(const Seg *__restrict__ segs, const Range *__restrict__ ranges,
+                                               Tables tb, Shape sh, RHdr *__restrict__ rhdr,
+                                               UItem *__restrict__ ru, OItem *__restrict__ ro,
+                                               uint32_t *__restrict__ rnslots) {
   extern __shared__ __align__(16) uint8_t smem[];
-  constexpr uint32_t T = ROWS * WG;
+  constexpr uint32_t T = ROWS * RWG;
   constexpr uint32_t RS = FMT == 2 ? 16 : 24;
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid >> 6;
   const uint32_t D = tb.D, E = sh.E, KL = sh.KL;
   const Range rg = ranges[blockIdx.x];
   const Seg sg = segs[rg.seg];
   RangeLds L;
-  range_lds_layout<true>(smem, &L, T, R, E, KL, D, FMT);
-
-  for (uint32_t i = tid; i < E; i += WG) {
+  range_lds_layout<true>(smem, &L, T, E, KL, D, FMT);
+  for (uint32_t i = tid; i < E; i += RWG) {
     L.t_key[i] = EMPTY32; L.t_cnt[i] = 0; L.t_imin[i] = EMPTY32; L.t_imax[i] = 0;
     L.t_smin[i] = EMPTY32; L.t_smax[i] = 0; L.t_isum[i] = 0; L.t_ssum[i] = 0;
     if (FMT == 2) L.t_bsum[i] = 0;
   }
-  for (uint32_t i = tid; i < KL; i += WG) { L.q_cnt[i] = 0; L.q_min[i] = EMPTY32; L.q_max[i] = 0; L.q_sum[i] = 0; }
-  for (uint32_t i = tid; i < TIDMAP; i += WG) L.tidmap[i] = 0;
-  for (uint32_t i = tid; i < S_MAX; i += WG) {
-    L.s_gslot[i] = GV_INVALID; L.s_flags[i] = 0; L.s_u[i] = 0; L.s_o[i] = 0; L.s_H[i] = 0; L.s_M[i] = 0;
-    L.s_facc[i] = 0; L.s_first[i] = 0; L.s_last[i] = 0; L.s_lastnew[i] = 0;
+  for (uint32_t i = tid; i < KL; i += RWG) { L.q_cnt[i] = 0; L.q_min[i] = EMPTY32; L.q_max[i] = 0; L.q_sum[i] = 0; }
+  for (uint32_t i = tid; i < TIDMAP; i += RWG) L.tidmap[i] = 0;
+  for (uint32_t i = tid; i < S_MAX; i += RWG) {
+    L.s_gslot[i] = GV_INVALID; L.s_flags[i] = 0; L.s_d[i] = 0; L.s_u[i] = 0; L.s_H[i] = 0; L.s_M[i] = 0;
+    L.s_facc[i] = 0; L.s_first[i] = 0; L.s_last[i] = 0;
   }
-  for (uint32_t i = tid; i < ST_N; i += WG) L.cnt[i] = 0;
+  for (uint32_t i = tid; i < ST_N; i += RWG) L.cnt[i] = 0;
   if (tid < 8) L.misc[tid] = 0;
   __syncthreads();
 
   const size_t sbase = (size_t)blockIdx.x * S_MAX;
   uint64_t pay_run = rg.pay_begin;  // payload offset of the current tile's first record
-
-  // raw words of the tile being decoded; the next tile's loads are issued
-  // right after the current one is decoded.  Loads are unconditional (index
-  // clamped to the range) so that nothing waits for them before the next tile.
+  // Two register buffers of raw record words alternate between tiles; the
+  // loads are unconditional (index clamped to the range) so that nothing
+  // waits for them before the tile that uses them.
   gu64 *grec = (gu64 *)sg.rec;
   const uint64_t last_rec = rg.begin + rg.n - 1;
   uint64_t a0[ROWS], a1[ROWS], a2[ROWS], b0[ROWS], b1[ROWS], b2[ROWS];
 #pragma unroll
   for (int r = 0; r < ROWS; r++) {
-    const uint32_t li = (uint32_t)w * (T / NWAVES) + (uint32_t)r * WAVE + lane;
+    const uint32_t li = (uint32_t)w * (T / RNW) + (uint32_t)r * WAVE + lane;
     uint64_t idx = rg.begin + li;
     idx = idx < last_rec ? idx : last_rec;
     gu64 *p = grec + idx * (RS / 8);
@@ -939,17 +755,15 @@ __global__ __launch_bounds__(WG) void k_range(const Seg *__restrict__ segs, cons
   Counters C;
 #pragma unroll
   for (int k = 0; k < ST_N; k++) C.c[k] = 0;
-  for (uint64_t t0 = 0; t0 < rg.n; t0 += 2 * T) {
-    tile_pass<FMT, ROWS, R>(L, tb, E, KL, D, rg, sg, grec, last_rec, t0, a0, a1, a2, b0, b1, b2, pay_run, sbase, ru, C);
-    if (t0 + T < rg.n)
-      tile_pass<FMT, ROWS, R>(L, tb, E, KL, D, rg, sg, grec, last_rec, t0 + T, b0, b1, b2, a0, a1, a2, pay_run, sbase,
-                              ru, C);
+  for (uint64_t t0 = 0; t0 < rg.n; t0 += T) {
+    tile_pass<FMT, ROWS>(L, tb, E, KL, D, rg, sg, grec, last_rec, t0, a0, a1, a2, b0, b1, b2, pay_run, sbase, ru, C);
+#pragma unroll
+    for (int r = 0; r < ROWS; r++) { a0[r] = b0[r]; a1[r] = b1[r]; a2[r] = b2[r]; }
   }
 #pragma unroll
   for (int k = 0; k < ST_N; k++)
     if (C.c[k]) lds_add32(&L.cnt[k], C.c[k]);
   __syncthreads();
-
 
   // ---- range end: summaries, tally and counter flush
   const uint32_t nslots = L.misc[0];
@@ -960,7 +774,7 @@ __global__ __launch_bounds__(WG) void k_range(const Seg *__restrict__ segs, cons
     hd.gslot = L.s_gslot[s];
     hd.nu_total = (uint32_t)L.s_u[s];
     hd.nu_listed = hd.nu_total < D ? hd.nu_total : D;
-    hd.n_o = (uint32_t)L.s_o[s];
+    hd.n_o = (uint32_t)(L.s_d[s] + L.s_u[s]);
     hd.floor = L.s_facc[s];
     hd.H = L.s_H[s]; hd.M = L.s_M[s];
     hd.first_ts = L.s_first[s]; hd.last_ts = L.s_last[s];
@@ -978,7 +792,7 @@ __global__ __launch_bounds__(WG) void k_range(const Seg *__restrict__ segs, cons
     }
   }
   const uint32_t nd = direct_slots(tb.n_fns, E), d0 = nd * tb.n_fns;
-  for (uint32_t i = tid; i < E; i += WG) {
+  for (uint32_t i = tid; i < E; i += RWG) {
     uint32_t s, fn;
     if (i < d0) {
       if (!L.t_cnt[i]) continue;
@@ -1002,7 +816,7 @@ __global__ __launch_bounds__(WG) void k_range(const Seg *__restrict__ segs, cons
     if (L.t_smin[i] != EMPTY32) g_min64(&g->self_min, L.t_smin[i]);
     if (L.t_smax[i]) g_max64(&g->self_max, L.t_smax[i]);
   }
-  for (uint32_t i = tid; i < KL; i += WG) {
+  for (uint32_t i = tid; i < KL; i += RWG) {
     if (!L.q_cnt[i]) continue;
     KTally *kt = &tb.ktally[(size_t)sg.stream * tb.n_kid + i];
     g_add64(&kt->count, L.q_cnt[i]);
@@ -1010,7 +824,7 @@ __global__ __launch_bounds__(WG) void k_range(const Seg *__restrict__ segs, cons
     if (L.q_min[i] != EMPTY32) g_min64(&kt->min, L.q_min[i]);
     if (L.q_max[i]) g_max64(&kt->max, L.q_max[i]);
   }
-  for (uint32_t i = tid; i < ST_N; i += WG)
+  for (uint32_t i = tid; i < ST_N; i += RWG)
     if (L.cnt[i]) atomicAdd(&tb.sstats[(size_t)sg.stream * ST_N + i], (unsigned long long)L.cnt[i]);
 }
 
@@ -1045,27 +859,27 @@ __global__ void k_range_payoff(const Seg *__restrict__ segs, uint32_t n_segs, co
 }
 
 // --------------------------------------------------------------- launchers
-hipError_t launch_range(int fmt, uint32_t T, uint32_t R, const Seg *segs, const Range *ranges, uint32_t n_ranges,
+hipError_t launch_range(int fmt, uint32_t T, const Seg *segs, const Range *ranges, uint32_t n_ranges,
                         const Tables &tb, const Shape &sh, RHdr *rhdr, UItem *ru, OItem *ro,
                         uint32_t *rnslots, hipStream_t st) {
   if (!n_ranges) return hipSuccess;
-  dim3 grid(n_ranges), block(WG);
-#define TT_LAUNCH(F, ROWS_, R_)                                                                                 \
+  dim3 grid(n_ranges), block(RWG);
+#define TT_LAUNCH(F, ROWS_)                                                                                     \
   do {                                                                                                          \
-    hipError_t e = hipFuncSetAttribute((const void *)k_range<F, ROWS_, R_>,                                    \
+    hipError_t e = hipFuncSetAttribute((const void *)k_range<F, ROWS_>,                                        \
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds_bytes);          \
     if (e != hipSuccess) return e;                                                                              \
-    hipLaunchKernelGGL((k_range<F, ROWS_, R_>), grid, block, sh.lds_bytes, st, segs, ranges, tb, sh, rhdr, ru,  \
-                       ro, rnslots);                                                                            \
+    hipLaunchKernelGGL((k_range<F, ROWS_>), grid, block, sh.lds_bytes, st, segs, ranges, tb, sh, rhdr, ru, ro, \
+                       rnslots);                                                                                \
     return hipGetLastError();                                                                                   \
   } while (0)
-#define TT_SHAPES(F)                                  \
-  if (T == 1024 && R == 8) TT_LAUNCH(F, 4, 8);        \
-  if (T == 1024 && R == 16) TT_LAUNCH(F, 4, 16);      \
-  if (T == 2048 && R == 8) TT_LAUNCH(F, 8, 8);        \
-  if (T == 2048 && R == 16) TT_LAUNCH(F, 8, 16);
-  if (fmt == 1) { TT_SHAPES(1) } else { TT_SHAPES(2) }
-#undef TT_SHAPES
+  if (fmt == 1) {
+    if (T == 1024) TT_LAUNCH(1, 1);
+    if (T == 2048) TT_LAUNCH(1, 2);
+  } else {
+    if (T == 1024) TT_LAUNCH(2, 1);
+    if (T == 2048) TT_LAUNCH(2, 2);
+  }
 #undef TT_LAUNCH
   return hipErrorInvalidValue;
 }

@@ -104,7 +104,7 @@ __host__ __device__ inline size_t range_lds_layout(uint8_t *base, RangeLds *L, u
   TAKE(c_by, uint64_t, fmt == 2 ? SC * D : 0);
   TAKE(c_fn, uint16_t, SC * D);
   TAKE(w_ch, uint64_t, (size_t)RNW * WAVE);
-  TAKE(w_vt, uint64_t, (size_t)RNW * D);
+  TAKE(w_vt, uint64_t, (size_t)RNW * (D + 1));
   TAKE(t_key, uint32_t, E);
   TAKE(t_cnt, uint32_t, E);
   TAKE(t_imin, uint32_t, E);
@@ -282,34 +282,6 @@ __device__ inline void tally_call(const RangeLds &L, uint32_t E, const Tables &t
   }
 }
 
-__device__ inline uint64_t lanemask_le() {
-  const uint32_t lane = __lane_id();
-  return lane == 63 ? ~0ull : ((2ull << lane) - 1);
-}
-__device__ inline uint64_t shfl64(uint64_t v, int src) {
-  const uint32_t lo = __shfl((uint32_t)v, src, WAVE), hi = __shfl((uint32_t)(v >> 32), src, WAVE);
-  return ((uint64_t)hi << 32) | lo;
-}
-__device__ inline uint64_t shfl64_up1(uint64_t v) {
-  const uint32_t lo = __shfl_up((uint32_t)v, 1, WAVE), hi = __shfl_up((uint32_t)(v >> 32), 1, WAVE);
-  return ((uint64_t)hi << 32) | lo;
-}
-__device__ inline int32_t wave_min_i32(int32_t v) {
-#pragma unroll
-  for (int o = 1; o < WAVE; o <<= 1) { const int32_t t = __shfl_xor(v, o, WAVE); v = t < v ? t : v; }
-  return v;
-}
-__device__ inline int32_t wave_max_i32(int32_t v) {
-#pragma unroll
-  for (int o = 1; o < WAVE; o <<= 1) { const int32_t t = __shfl_xor(v, o, WAVE); v = t > v ? t : v; }
-  return v;
-}
-__device__ inline int32_t wave_prefix_min_i32(int32_t v) {
-  const int lane = __lane_id();
-#pragma unroll
-  for (int o = 1; o < WAVE; o <<= 1) { const int32_t t = __shfl_up(v, o, WAVE); if (lane >= o) v = t < v ? t : v; }
-  return v;
-}
 // Orders this wavefront's LDS accesses around it (all lanes take part).
 __device__ inline void wave_lds_fence() {
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -319,79 +291,137 @@ __device__ inline void wave_lds_fence() {
 // ------------------------------------------------------------------ window
 struct Counters { uint32_t c[ST_N]; };
 
-// One window: up to 64 consecutive records [a, a + nw) of slot s, one per
-// lane of the calling wavefront (all 64 lanes must call).
+// DPP lane moves (gfx9 encodings): row_shr:k = 0x110 + k, wave_shr:1 = 0x138,
+// row_bcast:15 = 0x142, row_bcast:31 = 0x143.  Lanes whose source is out of
+// range, or whose row is masked off, keep `old`.
+template <int CTRL, int ROWM = 0xF>
+__device__ __forceinline__ int32_t dpp(int32_t old, int32_t v) {
+  return __builtin_amdgcn_update_dpp(old, v, CTRL, ROWM, 0xF, false);
+}
+__device__ __forceinline__ int32_t imin(int32_t a, int32_t b) { return a < b ? a : b; }
+__device__ __forceinline__ int32_t imax(int32_t a, int32_t b) { return a > b ? a : b; }
+// Inclusive prefix minimum / maximum over the 64 lanes (row scans, then the
+// row ends broadcast to the rows above).
+__device__ __forceinline__ int32_t wave_scan_min(int32_t v) {
+  v = imin(v, dpp<0x111>(BIG, v));
+  v = imin(v, dpp<0x112>(BIG, v));
+  v = imin(v, dpp<0x114>(BIG, v));
+  v = imin(v, dpp<0x118>(BIG, v));
+  v = imin(v, dpp<0x142, 0xA>(BIG, v));
+  v = imin(v, dpp<0x143, 0xC>(BIG, v));
+  return v;
+}
+__device__ __forceinline__ int32_t wave_scan_max(int32_t v) {
+  v = imax(v, dpp<0x111>(-BIG, v));
+  v = imax(v, dpp<0x112>(-BIG, v));
+  v = imax(v, dpp<0x114>(-BIG, v));
+  v = imax(v, dpp<0x118>(-BIG, v));
+  v = imax(v, dpp<0x142, 0xA>(-BIG, v));
+  v = imax(v, dpp<0x143, 0xC>(-BIG, v));
+  return v;
+}
+__device__ __forceinline__ int32_t lane63(int32_t v) { return __builtin_amdgcn_readlane(v, 63); }
+__device__ __forceinline__ uint64_t bperm64(uint32_t lo, uint32_t hi, int32_t src) {
+  const uint32_t l = (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int32_t)lo);
+  const uint32_t h = (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int32_t)hi);
+  return ((uint64_t)h << 32) | l;
+}
+__device__ __forceinline__ int32_t msb64(uint64_t m) { return m ? 63 - (int32_t)__clzll(m) : -1; }
+__device__ __forceinline__ uint64_t uread64(uint64_t v, uint32_t lane) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int32_t)(uint32_t)v, (int32_t)lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int32_t)(uint32_t)(v >> 32), (int32_t)lane);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// State of one thread slot while a wavefront walks its records; lives in
+// registers across the windows of one tile and in LDS between tiles.
+struct SlotState {
+  int32_t d;        // depth relative to the range start
+  int32_t fl;       // floor: lowest depth reached (<= 0); -fl calls opened before the range were closed
+  int32_t H, M;     // excursion: a value above max_depth iff the height above the floor ever was; max level
+  uint32_t flags;   // RF_*
+  uint64_t facc;    // children time of the call at the floor (opened before the range)
+  uint64_t first, last;
+};
+
+// One window: records [a, a + nw) of slot s (nw <= 64), one per lane of the
+// calling wavefront (all 64 lanes call).  Every exit finds its entry as the
+// last earlier entry that opened the same level in the window, else on the
+// carried stack (level above the floor), else it closes a call opened before
+// the range (level at or below the floor); its parent is found the same way
+// one level down.
 template <int FMT>
 __device__ __forceinline__ void slot_window(RangeLds &L, const Tables &tb, const uint32_t E, const uint32_t D,
-                                            const uint32_t s, const uint32_t a, const uint32_t nw,
-                                            const size_t sbase, UItem *__restrict__ ru, Counters &C,
-                                            uint64_t *__restrict__ wch, uint64_t *__restrict__ wvt) {
+                                            const uint32_t s, const uint32_t gslot, const uint32_t a,
+                                            const uint32_t nw, SlotState &S, UItem *__restrict__ us,
+                                            Counters &C, uint64_t *__restrict__ wch, uint64_t *__restrict__ wvt) {
   const uint32_t lane = __lane_id();
   const bool valid = lane < nw;
   const uint32_t p = a + (valid ? lane : 0);
-  const uint64_t ts = valid ? L.tile_ts[p] : 0;
-  const uint32_t fk = valid ? L.tile_fk[p] : 0;
+  const uint64_t ts = L.tile_ts[p];
+  const uint32_t fk = L.tile_fk[p];
+  const uint64_t by = FMT == 2 ? L.tile_by[p] : 0;
   const uint32_t fn = fk & 0xFFFFu;
   const bool ex = valid && (fk & FK_EXIT);
   const bool en = valid && !(fk & FK_EXIT);
-  const uint64_t by = (FMT == 2 && valid) ? L.tile_by[p] : 0;
-  const int32_t d0 = L.s_d[s], u0 = L.s_u[s], fl0 = -u0;
-  const uint32_t flags0 = L.s_flags[s];
-  const uint64_t last0 = L.s_last[s];
-  // timestamp order within the thread
-  const uint64_t prev = shfl64_up1(ts);
-  if (valid) {
-    if (lane > 0) C.c[ST_TSREG] += ts < prev ? 1u : 0u;
-    else if (flags0 & RF_HAS_TS) C.c[ST_TSREG] += ts < last0 ? 1u : 0u;
-    else L.s_first[s] = ts;
+  const int32_t d0 = S.d, fl0 = S.fl, u0 = -fl0;
+  // timestamp order within the thread (lane 0 compares with the previous window)
+  {
+    const uint32_t plo = (uint32_t)dpp<0x138>((int32_t)(uint32_t)S.last, (int32_t)(uint32_t)ts);
+    const uint32_t phi = (uint32_t)dpp<0x138>((int32_t)(uint32_t)(S.last >> 32), (int32_t)(uint32_t)(ts >> 32));
+    const uint64_t prev = ((uint64_t)phi << 32) | plo;
+    if (valid && (lane > 0 || (S.flags & RF_HAS_TS)) && ts < prev) C.c[ST_TSREG]++;
+    if (!(S.flags & RF_HAS_TS)) S.first = uread64(ts, 0);
+    S.last = uread64(ts, nw - 1);
+    S.flags |= RF_HAS_TS;
   }
-  // depth after each record (relative to the range start) and the level each record opens or closes
+  // depth after each record and the level each record opens (entry) or closes (exit)
   const uint64_t Em = __ballot(en), Xm = __ballot(ex);
-  const uint64_t le = lanemask_le(), lt = lanemask_lt();
-  const int32_t da = d0 + (int32_t)__popcll(Em & le) - (int32_t)__popcll(Xm & le);
+  const uint64_t lt = lanemask_lt();
+  const int32_t da = d0 + (int32_t)__popcll(Em & lt) - (int32_t)__popcll(Xm & lt) + (en ? 1 : 0) - (ex ? 1 : 0);
   const int32_t lev = en ? da : da + 1;
   const int32_t d_end = d0 + (int32_t)__popcll(Em) - (int32_t)__popcll(Xm);
-  const int32_t levmin = wave_min_i32(valid ? lev : BIG);
-  const int32_t levmax = wave_max_i32(valid ? lev : -BIG);
-  const int32_t pmin = wave_prefix_min_i32(valid ? da : BIG);
-  const int32_t dlow = __shfl(pmin, WAVE - 1, WAVE);
-  const int32_t damin = dlow < d0 ? dlow : d0;      // lowest depth reached in the window
-  const int32_t fl1 = damin < fl0 ? damin : fl0;    // floor after the window
+  const int32_t pmin = wave_scan_min(valid ? da : BIG);
+  const int32_t damin = imin(lane63(pmin), d0);     // lowest depth in the window
+  const int32_t dmax = imax(lane63(wave_scan_max(valid ? da : -BIG)), d0);
+  const int32_t fl1 = imin(damin, fl0);             // floor after the window
   {
-    const int32_t fat = pmin < fl0 ? pmin : fl0;    // floor when this record happens
-    const int32_t hh = wave_max_i32(en ? lev - fat : -BIG);
-    const int32_t mm = wave_max_i32(en ? lev : -BIG);
-    if (lane == 0) {
-      if (hh > L.s_H[s]) L.s_H[s] = hh;
-      if (mm > L.s_M[s]) L.s_M[s] = mm;
+    const int32_t hub = dmax - fl1;                 // bounds the height above the floor in the window
+    if (hub <= (int32_t)D) {
+      S.H = imax(S.H, hub);
+    } else {
+      const int32_t h = lane63(wave_scan_max(en ? lev - imin(fl0, pmin) : -BIG));
+      S.H = imax(S.H, h);
     }
+    S.M = imax(S.M, dmax);
   }
-  wch[lane] = 0;
-  if (lane < D) wvt[lane] = 0;
-  wave_lds_fence();
-  // partner (entry of an exit) and parent (entry one level down) by level ballots
-  int32_t partner = -1, parent = -1;
-  bool open_at_end = false;
-  uint64_t prevE = 0;
-  for (int32_t v = levmin; v <= levmax; v++) {
+  // entries by level: lane k of (tlo, thi) holds the ballot of entries opening level damin + 1 + k
+  uint32_t tlo = 0, thi = 0;
+  const int32_t vend = imin(dmax, damin + WAVE);    // (the levels of 64 records span at most 64)
+  for (int32_t v = damin + 1; v <= vend; v++) {
     const uint64_t Ev = __ballot(en && lev == v);
-    if (ex && lev == v) {
-      const uint64_t m1 = Ev & lt, m2 = prevE & lt;
-      partner = m1 ? 63 - (int32_t)__clzll(m1) : -1;
-      parent = m2 ? 63 - (int32_t)__clzll(m2) : -1;
-    }
-    if (Ev && v > damin && v <= d_end && lane == (uint32_t)(63 - __clzll(Ev))) open_at_end = true;
-    prevE = Ev;
+    if ((int32_t)lane == v - damin - 1) { tlo = (uint32_t)Ev; thi = (uint32_t)(Ev >> 32); }
   }
+  const int32_t k = valid ? lev - damin - 1 : 0;
+  const uint64_t Elev = bperm64(tlo, thi, k);
+  const uint64_t Epar = bperm64(tlo, thi, k > 0 ? k - 1 : 0);
+  const int32_t partner = ex ? msb64(Elev & lt) : -1;
+  const int32_t parent = (ex && k > 0) ? msb64(Epar & lt) : -1;
+  const bool open_at_end = en && lev <= d_end && msb64(Elev) == (int32_t)lane;
+  wch[lane] = 0;
+  if (lane <= D) wvt[lane] = lane == 0 ? S.facc : 0;
   // the entry each exit closes: in the window, on the carried stack, or opened before the range
-  uint64_t pts = shfl64(ts, partner >= 0 ? partner : (int32_t)lane);
-  uint32_t pfn = __shfl(fn, partner >= 0 ? partner : (int32_t)lane, WAVE);
-  uint64_t pby = FMT == 2 ? shfl64(by, partner >= 0 ? partner : (int32_t)lane) : 0;
   int kind = 0;  // 1 window, 2 carried, 3 opened before the range, 4 beyond the stack capacity
   uint32_t cpos = 0;
+  uint64_t pts = 0, pby = 0;
+  uint32_t pfn = 0;
   if (ex) {
-    if (partner >= 0) kind = 1;
-    else if (lev > fl0) {
+    if (partner >= 0) {
+      kind = 1;
+      pts = L.tile_ts[a + partner];
+      pfn = L.tile_fk[a + partner] & 0xFFFFu;
+      if (FMT == 2) pby = L.tile_by[a + partner];
+    } else if (lev > fl0) {
       cpos = (uint32_t)(lev - fl0 - 1);
       if (cpos < D) {
         kind = 2;
@@ -412,6 +442,7 @@ __device__ __forceinline__ void slot_window(RangeLds &L, const Tables &tb, const
     else if (ts < pts) C.c[ST_NEGDUR]++;
     else { ok = true; incl = ts - pts; }
   }
+  wave_lds_fence();
   // children time to the parent
   if (ok) {
     if (parent >= 0) {
@@ -423,8 +454,7 @@ __device__ __forceinline__ void slot_window(RangeLds &L, const Tables &tb, const
         if (pp < D) lds_add64(&L.c_ch[s * D + pp], incl);
       } else {
         const uint32_t vk = (uint32_t)(fl0 - pl);
-        if (vk == 0) lds_add64(&L.s_facc[s], incl);
-        else if (vk - 1 < D && (uint32_t)u0 + vk < D) lds_add64(&wvt[vk - 1], incl);
+        if (vk == 0 || (vk <= D && (uint32_t)u0 + vk < D)) lds_add64(&wvt[vk], incl);
       }
     }
   }
@@ -435,14 +465,13 @@ __device__ __forceinline__ void slot_window(RangeLds &L, const Tables &tb, const
     uint64_t self;
     if (ch <= incl) self = incl - ch;
     else { self = 0; C.c[ST_UNDER]++; }
-    tally_call<FMT>(L, E, tb, s, L.s_gslot[s], fn, incl, self, pby);
+    tally_call<FMT>(L, E, tb, s, gslot, fn, incl, self, pby);
   } else if (kind == 3) {
     const uint32_t vk = (uint32_t)(fl0 - lev);
     const uint32_t gi = (uint32_t)u0 + vk;
     if (gi < D) {
-      const uint64_t acc = vk == 0 ? L.s_facc[s] : (vk - 1 < D ? wvt[vk - 1] : 0);
-      UItem *u = &ru[(sbase + s) * D + gi];
-      u->ts = ts; u->child = acc; u->fn = fn; u->pad = 0; u->pad2 = 0;
+      UItem *u = &us[gi];
+      u->ts = ts; u->child = wvt[vk]; u->fn = fn; u->pad = 0; u->pad2 = 0;
     } else {
       C.c[ST_ORPHAN]++;  // deeper than any stack can be: certainly an orphan exit
     }
@@ -455,21 +484,43 @@ __device__ __forceinline__ void slot_window(RangeLds &L, const Tables &tb, const
       const uint32_t i = s * D + pos;
       L.c_ts[i] = ts; L.c_ch[i] = wch[lane]; L.c_fn[i] = (uint16_t)fn;
       if (FMT == 2) L.c_by[i] = by;
-    } else {
-      atomicOr(&L.s_flags[s], RF_OVERFLOW);
     }
   }
-  if (lane == 0) {
-    L.s_d[s] = d_end;
-    L.s_u[s] = -fl1;
-    if (fl1 < fl0) {
-      const uint32_t vk = (uint32_t)(fl0 - fl1);
-      L.s_facc[s] = (vk - 1 < D && (uint32_t)u0 + vk < D) ? wvt[vk - 1] : 0;
-    }
-    atomicOr(&L.s_flags[s], RF_HAS_TS);
+  if (__ballot(open_at_end && (uint32_t)(lev - fl1 - 1) >= D)) S.flags |= RF_OVERFLOW;
+  {
+    const uint32_t dv = (uint32_t)(fl0 - fl1);
+    uint64_t nf = 0;
+    if (dv == 0 || (dv <= D && (uint32_t)u0 + dv < D)) nf = wvt[dv];
+    S.facc = uread64(nf, 0);
   }
-  if (lane + 1 == nw) L.s_last[s] = ts;
+  S.d = d_end;
+  S.fl = fl1;
   wave_lds_fence();
+}
+
+// All windows of slot s in this tile, records [b, e) of the sorted tile.
+template <int FMT>
+__device__ __forceinline__ void slot_walk(RangeLds &L, const Tables &tb, const uint32_t E, const uint32_t D,
+                                          const uint32_t s, const uint32_t b, const uint32_t e, const size_t sbase,
+                                          UItem *__restrict__ ru, Counters &C, uint64_t *__restrict__ wch,
+                                          uint64_t *__restrict__ wvt) {
+  SlotState S;
+  S.d = __builtin_amdgcn_readfirstlane(L.s_d[s]);
+  S.fl = -__builtin_amdgcn_readfirstlane(L.s_u[s]);
+  S.H = __builtin_amdgcn_readfirstlane(L.s_H[s]);
+  S.M = __builtin_amdgcn_readfirstlane(L.s_M[s]);
+  S.flags = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)L.s_flags[s]);
+  S.facc = uread64(L.s_facc[s], 0);
+  S.first = uread64(L.s_first[s], 0);
+  S.last = uread64(L.s_last[s], 0);
+  const uint32_t gslot = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)L.s_gslot[s]);
+  UItem *us = ru + (sbase + s) * D;
+  for (uint32_t a = b; a < e; a += WAVE)
+    slot_window<FMT>(L, tb, E, D, s, gslot, a, (e - a) < WAVE ? (e - a) : WAVE, S, us, C, wch, wvt);
+  if (__lane_id() == 0) {
+    L.s_d[s] = S.d; L.s_u[s] = -S.fl; L.s_H[s] = S.H; L.s_M[s] = S.M; L.s_flags[s] = S.flags;
+    L.s_facc[s] = S.facc; L.s_first[s] = S.first; L.s_last[s] = S.last;
+  }
 }
 
 // ------------------------------------------------------------------ tile
@@ -696,10 +747,8 @@ __device__ __forceinline__ void tile_pass(RangeLds &L, const Tables &tb, const u
     __syncthreads();
     // ---- P5. windows: wavefront w walks slots w, w + RNW, ... in order
     for (uint32_t s = (uint32_t)w; s < nslots; s += RNW) {
-      const uint32_t e = L.soff[s + 1];
-      for (uint32_t a = L.soff[s]; a < e; a += WAVE)
-        slot_window<FMT>(L, tb, E, D, s, a, (e - a) < WAVE ? (e - a) : WAVE, sbase, ru, C, L.w_ch + w * WAVE,
-                         L.w_vt + w * D);
+      const uint32_t b = L.soff[s], e = L.soff[s + 1];
+      if (b < e) slot_walk<FMT>(L, tb, E, D, s, b, e, sbase, ru, C, L.w_ch + w * WAVE, L.w_vt + w * (D + 1));
     }
     __syncthreads();
 }

@@ -13,6 +13,16 @@ Prints ONE JSON line.  `value` is events/s (every record consumed counts).
 bytes (24 B per record read + 64 B per tally row written) over its average
 duration, measured with HIP events on the launch stream.  `cpu_baseline`
 times the CPU oracle (single thread) on the same workload.
+
+Other forms (each prints its own single JSON line):
+  --form batched    256 traces of uneven size (10 k - 20 M records) in one
+                    flush = one persistent work-list launch, after the
+                    autotuner has picked the launch shape, against the plain
+                    per-trace form (256 sequential reset/submit/flush/read).
+  --form streaming  the continuous-batching service fed by open-loop Poisson
+                    arrivals of 64 KiB - 8 MiB chunks of 64 processes x 64
+                    threads, host input, at a sweep of offered rates; p50/p99
+                    chunk latency (completion - scheduled arrival).
 """
 from __future__ import annotations
 
@@ -33,6 +43,17 @@ WORKLOADS = {
     2: "layered stack VAR16: 12 processes x 8 threads, 200 fns, 50M records of 16 B header + 0-64 B payload",
 }
 HBM_PEAK_GBS = 8000.0
+METRIC = "trace events/sec tallied (bit-exact) + HBM GB/s fraction; p99 chunk latency"
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def base_line(steps, warmup, ms_per_step, value, config):
+    return {"metric": METRIC, "value": value, "unit": "events/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
+            "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "u64", "data": "synthetic", "config": config}
 
 
 def main():
@@ -44,20 +65,25 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--form", default="plain", choices=["plain", "batched", "streaming"])
+    ap.add_argument("--rates", default="2,5,10,20", help="streaming: offered GB/s per point")
+    ap.add_argument("--seconds", type=float, default=3.0, help="streaming: measured seconds per point")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(the tally shards by stream; see DESIGN.md for how it would scale)", file=sys.stderr)
         sys.exit(2)
 
+    if args.form == "batched":
+        return bench_batched(args)
+    if args.form == "streaming":
+        return bench_streaming(args)
+
     import numpy as np
     import torch
 
     import synth
     from paper_2504_03683_amd import tally as T
-
-    def log(msg):
-        print("[bench] " + msg, file=sys.stderr, flush=True)
 
     t0 = time.time()
     w = synth.config(args.config, scale=args.scale)
@@ -132,7 +158,7 @@ def main():
         o.close()
 
     out = {
-        "metric": "trace events/sec tallied (bit-exact) + HBM GB/s fraction; p99 chunk latency",
+        "metric": METRIC,
         "value": n_rec / (ms_per_step * 1e-3),
         "unit": "events/s",
         "n_gpus": 1,
@@ -154,6 +180,213 @@ def main():
         "parity": parity,
     }
     tl.close()
+    print(json.dumps(out), flush=True)
+
+
+def bench_batched(args):
+    """One flush over 256 traces vs 256 per-trace flushes, same GPU, same resident input."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2504_03683_amd import tally as T
+
+    t0 = time.time()
+    w = synth.config(3, scale=args.scale)
+    n_rec = w.n_records
+    log("generated batched: %d traces, %d records, %.2f GB in %.1fs" % (len(w.streams), n_rec,
+                                                                      w.record_bytes / 1e9, time.time() - t0))
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    recs = [torch.from_numpy(s.records).to(dev) for s in w.streams]
+    torch.cuda.synchronize()
+    max_threads = sum(len(s.tids) for s in w.streams) + 64
+    cache = os.path.join(os.environ.get("TMPDIR", "/tmp"), "thapi_tally_autotune.txt")
+    if os.path.exists(cache):
+        os.remove(cache)
+    kw = dict(max_depth=8, max_threads=max_threads, max_streams=512, has_size=None, stream=stream)
+    tb = T.Tally(w.fmt, w.n_fns, 0, flags=T.DEVICE_INPUT | T.PROFILE | T.GRAPH, autotune_cache=cache, **kw)
+
+    def submit_all(h):
+        for s, r in zip(w.streams, recs):
+            h.submit(s.key, r)
+
+    submit_all(tb)
+    tz = time.perf_counter()
+    chosen = tb.autotune(reps=2)
+    log("autotune: T=%d E=%d ranges/CU=%d (%.1fs)" % (chosen + (time.perf_counter() - tz,)))
+    tb.flush(final=True)
+    tb.reset()
+
+    def step_batched():
+        tb.reset()
+        submit_all(tb)
+        tb.flush(final=True)
+        return tb.read(T.SCOPE_THREAD)
+
+    def timed(fn, steps):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        out = None
+        for _ in range(steps):
+            out = fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps, out
+
+    for _ in range(args.warmup):
+        step_batched()
+    ms_b, (rows_b, stats_b) = timed(step_batched, args.steps)
+    log("batched: %.3f ms/step" % ms_b)
+
+    tp = T.Tally(w.fmt, w.n_fns, 0, flags=T.DEVICE_INPUT, **kw)
+
+    def step_per_trace():
+        out = []
+        for s, r in zip(w.streams, recs):
+            tp.reset()
+            tp.submit(s.key, r)
+            tp.flush(final=True)
+            out.append(tp.read(T.SCOPE_THREAD)[0])
+        return out
+
+    step_per_trace()
+    seq_steps = max(1, min(args.steps, 3))
+    ms_p, rows_p = timed(step_per_trace, seq_steps)
+    log("per-trace: %.3f ms/step" % ms_p)
+    same = np.array_equal(np.concatenate(rows_p), rows_b)
+    parity = "batched == per-trace: %s" % ("bit-exact" if same else "MISMATCH")
+    cpu = None
+    if not args.no_parity or not args.no_cpu_baseline:
+        import oracle
+        tc = time.perf_counter()
+        o = oracle.run_workload(w, max_depth=8)
+        cpu_s = time.perf_counter() - tc
+        want = o.rows(oracle.SCOPE_THREAD)
+        ok = same and rows_b.shape == want.shape and np.array_equal(rows_b, want)
+        ws = o.stats()
+        ok = ok and all(stats_b[k] == ws[k] for k in T.STAT_NAMES if k != "dropped_records")
+        parity = "bit-exact (batched, per-trace and oracle)" if ok else "MISMATCH: " + parity
+        log("oracle: %.2fs; parity %s" % (cpu_s, parity))
+        cpu = {"value": n_rec / cpu_s, "unit": "events/s", "cores": 1, "kind": "oracle",
+               "sample": "the whole batch (%d records, 256 traces), one pass, single thread" % n_rec}
+        o.close()
+    out = base_line(args.steps, args.warmup, ms_b, n_rec / (ms_b * 1e-3), {
+        "workload": "batched: 256 traces, 10k-20M FIXED24 records each (log-uniform), 1-64 threads, 32-200 fns"
+                    + ("" if args.scale == 1.0 else " (scale %g)" % args.scale),
+        "records": n_rec, "input_bytes": w.record_bytes, "format": "FIXED24", "traces": len(w.streams)})
+    out["batched_vs_per_trace"] = {"batched_ms": ms_b, "per_trace_ms": ms_p, "speedup": ms_p / ms_b,
+                                   "per_trace_events_per_s": n_rec / (ms_p * 1e-3),
+                                   "autotuned": {"T": chosen[0], "E": chosen[1], "ranges_per_cu": chosen[2]},
+                                   "graph": True}
+    out["cpu_baseline"] = cpu
+    out["parity"] = parity
+    tb.close()
+    tp.close()
+    print(json.dumps(out), flush=True)
+
+
+def bench_streaming(args):
+    """Open-loop Poisson arrivals into the service; latency = completion - scheduled arrival."""
+    import threading
+
+    import numpy as np
+
+    import synth
+    from paper_2504_03683_amd import tally as T
+
+    t0 = time.time()
+    w = synth.config(4, scale=args.scale)
+    log("generated streaming pool: %d processes, %.2f GB in %.1fs" % (len(w.streams), w.record_bytes / 1e9,
+                                                                     time.time() - t0))
+    rates = [float(x) for x in args.rates.split(",") if x]
+    n_prod = 4
+    points = []
+    total_wall = 0.0
+    for ri, rate in enumerate(rates):
+        rng = np.random.default_rng(1000 + ri)
+        dur = args.seconds + 0.5
+        # chunk plan per producer: (arrival time, process, byte offset, size)
+        sizes_rng = np.random.default_rng(2000 + ri)
+        offered = rate * 1e9 * dur
+        plans = [[] for _ in range(n_prod)]
+        cursor = [0] * len(w.streams)
+        cycle = [0] * len(w.streams)
+        tarr = [0.0] * n_prod
+        planned = 0
+        while planned < offered:
+            p = int(rng.integers(0, len(w.streams)))
+            q = p % n_prod
+            sz = int(np.exp(sizes_rng.uniform(np.log(64 << 10), np.log(8 << 20)))) // 24 * 24
+            n_b = w.streams[p].records.size
+            if cursor[p] >= n_b:
+                cursor[p] = 0
+                cycle[p] += 1
+            sz = min(sz, n_b - cursor[p])
+            # producer q offers rate / n_prod bytes per second: Poisson arrivals whose
+            # mean gap is the chunk's share of that rate
+            tarr[q] += float(rng.exponential(sz / (rate * 1e9 / n_prod)))
+            plans[q].append((tarr[q], p, cycle[p], cursor[p], sz))
+            cursor[p] += sz
+            planned += sz
+        n_streams = len(w.streams) * (max(cycle) + 1)
+        tl = T.Tally(w.fmt, w.n_fns, 0, max_depth=8, max_threads=64 * n_streams + 64,
+                     max_streams=n_streams + 8, flags=T.SERVICE, budget=16 << 30)
+        lat, lock = [], threading.Lock()
+        t_start = time.monotonic_ns() + int(50e6)
+
+        def produce(q):
+            mine = []
+            for (ta, p, cyc, off, sz) in plans[q]:
+                sched = t_start + int(ta * 1e9)
+                now = time.monotonic_ns()
+                if sched > now:
+                    time.sleep((sched - now) / 1e9)
+                s = w.streams[p]
+                tk = tl.submit((1 + cyc, s.key[1], s.key[2]), s.records[off:off + sz])
+                mine.append((tk, sched, ta, sz))
+            with lock:
+                lat.extend(mine)
+
+        th = [threading.Thread(target=produce, args=(q,)) for q in range(n_prod)]
+        wall0 = time.perf_counter()
+        for x in th:
+            x.start()
+        for x in th:
+            x.join()
+        tl.flush(final=True)
+        wall = time.perf_counter() - wall0
+        total_wall += wall
+        _, st = tl.read(T.SCOPE_FN)
+        info = tl.service_info()
+        lats, nbytes = [], 0
+        for tk, sched, ta, sz in lat:
+            if ta < 0.5:        # warm-up arrivals are not measured
+                continue
+            d = tl.ticket_done(tk)
+            lats.append((d - sched) / 1e6)
+            nbytes += sz
+        tl.close()
+        lats = np.array(lats)
+        span = max(1e-9, dur - 0.5)
+        pt = {"offered_GBps": rate, "admitted_GBps": nbytes / span / 1e9, "events_per_s": nbytes / 24 / span,
+              "chunks": int(len(lats)), "p50_ms": float(np.percentile(lats, 50)),
+              "p99_ms": float(np.percentile(lats, 99)), "max_ms": float(lats.max()),
+              "batches": info["batches"], "mean_batch_chunks": info["batch_chunks"] / max(1, info["batches"]),
+              "max_batch_chunks": info["max_batch_chunks"], "records": st["records"]}
+        log("rate %.1f GB/s: %s" % (rate, json.dumps(pt)))
+        points.append(pt)
+    best = max(points, key=lambda p: p["events_per_s"])
+    out = base_line(len(points), 0, 1e3 * total_wall / len(points), best["events_per_s"], {
+        "workload": "streaming: 64 processes x 64 threads, FIXED24 chunks 64KiB-8MiB (log-uniform), "
+                    "open-loop Poisson arrivals, host input, 16 GiB admission budget"
+                    + ("" if args.scale == 1.0 else " (pool scale %g)" % args.scale),
+        "rates_GBps": rates, "seconds_per_point": args.seconds, "producers": n_prod})
+    out["streaming"] = points
+    out["p99_chunk_latency_ms"] = best["p99_ms"]
+    out["cpu_baseline"] = None
+    out["parity"] = "not checked here (tests/test_gpu_streaming.py checks the service bit-exactly)"
     print(json.dumps(out), flush=True)
 
 

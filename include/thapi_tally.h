@@ -72,6 +72,10 @@ extern "C" {
 #define THAPI_DROP_ON_FULL 0x04u /* submit() over budget drops the chunk and counts its records */
 #define THAPI_STRICT       0x08u /* flush() returns THAPI_E_MALFORMED when any anomaly was counted */
 #define THAPI_PROFILE      0x10u /* time every kernel with HIP events (see thapi_tally_timings) */
+#define THAPI_GRAPH        0x20u /* flush() captures its kernels in a HIP graph once per launch
+                                    signature (work-list size, shape, buffers) and replays it */
+#define THAPI_SERVICE      0x40u /* streaming form: a library thread tallies chunks as they arrive
+                                    (continuous batching, see thapi_tally_ticket_done) */
 
 /* ---- flush / read ------------------------------------------------------ */
 #define THAPI_TICKET_ALL  UINT64_MAX
@@ -181,6 +185,48 @@ int thapi_tally_read(thapi_tally *t, uint32_t scope, uint32_t trace_id,
  * the handle can start a new trace set.  Not valid while submits are queued. */
 int thapi_tally_reset(thapi_tally *t);
 
+/* Batched form: times the pipeline on the chunks queued right now under each
+ * candidate launch shape -- records per tile (1024, 2048), LDS tally entries
+ * (2048, 1024) and work-list ranges per CU (1, 2, 4) -- and keeps the fastest
+ * for this workload class (device, format, max_depth, and the log2 buckets of
+ * n_fns, chunk count and record count).  The choice is used by every later
+ * flush of that class and, when cfg.autotune_cache names a file, written
+ * there as text lines "key T E rpc" and read back by later opens.  Each
+ * candidate runs reps + 1 times (the first one warms up; the minimum of the
+ * rest counts).  The queued chunks stay queued and the tables are re-initialised
+ * afterwards, so the handle must not have flushed since open/reset:
+ * THAPI_E_STATE otherwise, or when nothing is queued.  chosen (may be NULL)
+ * receives {T, E, rpc}.  Errors: THAPI_E_STATE, THAPI_E_CAPACITY (no candidate
+ * could take the work), THAPI_E_DEVICE. */
+int thapi_tally_autotune(thapi_tally *t, uint32_t reps, uint32_t *chosen);
+
+/* Streaming form (THAPI_SERVICE).  Aggregation on the node while the trace
+ * is still being produced (section 3, On-node Processing, builds aggregates
+ * from temporarily stored traces; section 6 names tracing and analysis run
+ * concurrently as work in progress), as a continuous-batching service: open()
+ * starts a worker thread and, for host input, reserves device_budget_bytes of
+ * device memory as the admission arena.  submit() waits for arena room (or
+ * returns THAPI_E_AGAIN / drops, per the flags), queues the chunk in ticket
+ * order and copies it on a copy stream; the worker repeatedly takes every
+ * chunk whose copy has landed, tallies them all in one pipeline launch while
+ * later chunks keep copying, stamps their completion and frees their arena
+ * space.  Open calls stay on the device stacks between batches, so results
+ * equal those of one flush over the same submissions.  flush(ticket) waits
+ * until the worker has covered `ticket`; flush(..., THAPI_FLUSH_FINAL) waits
+ * for everything submitted, then closes all streams.  A failure inside the
+ * worker (THAPI_E_DEPTH, THAPI_E_CAPACITY, THAPI_E_DEVICE) makes the handle
+ * failed and is returned by the next flush.
+ *
+ * thapi_tally_ticket_done: THAPI_OK and *done_ns (may be NULL) = the
+ * CLOCK_MONOTONIC time in ns at which the batch holding `ticket` completed,
+ * THAPI_E_AGAIN if it has not yet, THAPI_E_INVAL for a ticket never issued.
+ *
+ * thapi_tally_service_info: writes min(n, 6) counters {batches, chunks in
+ * batches, largest batch (chunks), bytes admitted, chunks queued now, arena
+ * bytes in use}; returns the number written. */
+int thapi_tally_ticket_done(thapi_tally *t, uint64_t ticket, uint64_t *done_ns);
+int thapi_tally_service_info(thapi_tally *t, uint64_t *info, int n);
+
 /* Frees everything.  Queued chunks that were never flushed are discarded. */
 int thapi_tally_close(thapi_tally *t);
 
@@ -190,6 +236,7 @@ const char *thapi_tally_strerror(int code);
 /* THAPI_PROFILE only: per-kernel durations (ms) of the last flush and read,
  * measured with HIP events on the launch stream, in the order
  * {prepass, main, combine, final, readout}; entries that did not run are 0.
+ * Under THAPI_GRAPH, "main" is the whole replayed graph.
  * n: capacity of ms[]; returns the number of entries written. */
 int thapi_tally_timings(thapi_tally *t, double *ms, int n);
 

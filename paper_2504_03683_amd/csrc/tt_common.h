@@ -102,6 +102,7 @@ struct Shape {
   uint32_t E;           // LDS tally entries (power of two)
   uint32_t KL;          // kernel ids pre-aggregated in LDS (<= KL_MAX)
   uint32_t lds_bytes;
+  uint32_t rpc;         // ranges per CU the records are cut into (work-list length / CUs)
 };
 
 __host__ __device__ inline uint32_t hash32(uint32_t x) {

@@ -17,6 +17,9 @@
 #include <map>
 #include <mutex>
 #include <new>
+#include <chrono>
+#include <string>
+#include <thread>
 #include <vector>
 
 #include "thapi_tally.h"
@@ -24,9 +27,10 @@
 
 namespace tt {
 size_t range_lds_bytes(uint32_t T, uint32_t E, uint32_t KL, uint32_t D, int fmt);
-hipError_t launch_range(int fmt, uint32_t T, const Seg *segs, const Range *ranges, uint32_t n_ranges,
-                        const Tables &tb, const Shape &sh, RHdr *rhdr, UItem *ru, OItem *ro, uint32_t *rnslots,
-                        hipStream_t st);
+hipError_t launch_range(int fmt, uint32_t T, const Seg *segs, const Range *ranges, const uint32_t *order,
+                        uint32_t n_ranges, uint32_t *qhead, uint32_t n_wg, const Tables &tb, const Shape &sh,
+                        RHdr *rhdr, UItem *ru, OItem *ro, uint32_t *rnslots, hipStream_t st);
+hipError_t prepare_range_kernels(uint32_t max_lds_bytes);
 hipError_t launch_paylen(const Seg *segs, Range *ranges, uint32_t n_ranges, const uint32_t *seg_first_range,
                          uint32_t n_segs, uint64_t *paylen, hipStream_t st);
 hipError_t launch_fill64(uint64_t *p, size_t n, uint64_t v, hipStream_t st);
@@ -83,6 +87,8 @@ struct Chunk {
   uint64_t ticket;
   void *owned;       // staged device copy (host input), freed after its flush
   uint64_t owned_bytes;
+  bool in_arena;     // service mode: the staged copy lives in the device arena
+  bool ready;        // service mode: the staged copy is complete
 };
 
 using SKey = std::array<uint32_t, 3>;
@@ -119,13 +125,34 @@ struct thapi_tally {
        *d_err = nullptr, *d_hs = nullptr;
   Shape shape{};
 
-  DevBuf segs, ranges, rhdr, ru, ro, rnslots, spans, paylen, segfirst;
+  DevBuf segs, ranges, order, qhead, rhdr, ru, ro, rnslots, spans, paylen, segfirst;
   DevBuf keys, vals, keys2, vals2, gbeg, gend, cnt, off, rank_stream, rank_key, trace_span, stream_rank, rows, tstats;
   void *h_pinned = nullptr;  // small pinned staging for results of device->host copies
   size_t h_pinned_cap = 0;
 
   double timings[TM_N] = {0};
   hipEvent_t ev[2 * TM_N] = {};
+
+  std::string arch;                                   // gcnArchName of the device
+  std::map<std::string, std::array<uint32_t, 3>> tuned;  // autotuned {T, E, rpc} per workload class
+  bool flushed_any = false;
+  hipGraphExec_t gexec = nullptr;                     // THAPI_GRAPH: the captured pipeline
+  std::array<uint64_t, 16> gsig{};
+  uint64_t graph_builds = 0, graph_launches = 0;
+  std::string cache_path;
+
+  // THAPI_SERVICE: the continuous-batching worker and the device arena that
+  // admits staged chunks (capacity = device_budget_bytes, FIFO reuse)
+  std::thread worker;
+  bool stop = false;
+  std::condition_variable work_cv;                    // worker: chunks ready or stop
+  hipStream_t cst = nullptr;                          // host -> device copies
+  uint8_t *arena = nullptr;
+  uint64_t a_head = 0, a_tail = 0;
+  std::deque<std::pair<uint64_t, uint64_t>> a_live;   // [offset, end) of live allocations, in order
+  uint64_t done_upto = 0;                             // every ticket <= this one is tallied
+  std::vector<uint64_t> done_ns;                      // [ticket] CLOCK_MONOTONIC ns of its batch's completion
+  uint64_t n_batches = 0, n_batch_chunks = 0, max_batch_chunks = 0, bytes_admitted = 0;
 };
 
 namespace {
@@ -159,7 +186,7 @@ void free_all(thapi_tally *t) {
   void *ps[] = {t->d_gkeys, t->d_gvals, t->d_ngs, t->d_ths, t->d_tht, t->d_tally, t->d_ktally,
                 t->d_cstate, t->d_cstack, t->d_sstats, t->d_err, t->d_hs};
   for (void *p : ps) if (p) hipFree(p);
-  DevBuf *bs[] = {&t->segs, &t->ranges, &t->rhdr, &t->ru, &t->ro, &t->rnslots, &t->spans, &t->paylen, &t->segfirst,
+  DevBuf *bs[] = {&t->segs, &t->ranges, &t->order, &t->qhead, &t->rhdr, &t->ru, &t->ro, &t->rnslots, &t->spans, &t->paylen, &t->segfirst,
                   &t->keys, &t->vals, &t->keys2, &t->vals2, &t->gbeg, &t->gend, &t->cnt, &t->off,
                   &t->rank_stream, &t->rank_key, &t->trace_span, &t->stream_rank, &t->rows, &t->tstats};
   for (DevBuf *b : bs) b->release();
@@ -167,29 +194,36 @@ void free_all(thapi_tally *t) {
   t->queue.clear();
   if (t->h_pinned) hipHostFree(t->h_pinned);
   for (auto &e : t->ev) if (e) hipEventDestroy(e);
+  if (t->gexec) { hipGraphExecDestroy(t->gexec); t->gexec = nullptr; }
+  if (t->arena) { hipFree(t->arena); t->arena = nullptr; }
+  if (t->cst) { hipStreamDestroy(t->cst); t->cst = nullptr; }
   if (t->own_stream && t->st) hipStreamDestroy(t->st);
 }
 
 // Picks the range kernel's tile and LDS tally size for the format and depth:
 // the largest tile and tally that fit the LDS, preferring a full tally (2048
-// entries) over a larger tile.  THAPI_TALLY_SHAPE="T,E" overrides the choice
-// (used to tune the launch shape).
+// entries) over a larger tile.  THAPI_TALLY_SHAPE="T,E[,rpc]" overrides the
+// choice (used to tune the launch shape).
 Shape pick_shape(const thapi_tally *t) {
   Shape s{};
   const uint32_t D = t->cfg.max_depth;
   const int fmt = (int)t->cfg.format;
   s.KL = std::min<uint32_t>(t->cfg.n_kernel_ids, KL_MAX);
+  s.rpc = 1;
   auto fits = [&](uint32_t T, uint32_t E) {
     size_t b = range_lds_bytes(T, E, s.KL, D, fmt);
-    if (b > t->lds_limit) return false;
+    if (b + 256 > t->lds_limit) return false;  // (plus the kernel's static LDS)
     s.T = T; s.E = E; s.lds_bytes = (uint32_t)b;
     return true;
   };
   if (const char *env = getenv("THAPI_TALLY_SHAPE")) {
-    unsigned T = 0, E = 0;
-    if (sscanf(env, "%u,%u", &T, &E) == 2 && (T == 1024 || T == 2048) && E >= 64 &&
-        (E & (E - 1)) == 0 && fits(T, E))
+    unsigned T = 0, E = 0, rpc = 1;
+    const int n = sscanf(env, "%u,%u,%u", &T, &E, &rpc);
+    if (n >= 2 && (T == 1024 || T == 2048) && E >= 64 && (E & (E - 1)) == 0 && rpc >= 1 && rpc <= 64 &&
+        fits(T, E)) {
+      s.rpc = rpc;
       return s;
+    }
   }
   const uint32_t cand[][2] = {{2048, 2048}, {1024, 2048}, {2048, 1024}, {1024, 1024},
                               {1024, 512}, {1024, 256}, {1024, 128}, {1024, 64}};
@@ -254,6 +288,11 @@ const char *thapi_tally_strerror(int code) {
   }
 }
 
+namespace {
+void load_tune_cache(thapi_tally *t);
+void service_loop(thapi_tally *t);
+}  // namespace
+
 int thapi_tally_open(const thapi_tally_config *cfg, thapi_tally **out) {
   if (!cfg || !out) return THAPI_E_INVAL;
   if (cfg->abi_version != THAPI_TALLY_ABI_VERSION) return THAPI_E_INVAL;
@@ -269,6 +308,7 @@ int thapi_tally_open(const thapi_tally_config *cfg, thapi_tally **out) {
   if (!t->cfg.max_streams) t->cfg.max_streams = 4096;
   if (!t->cfg.device_budget_bytes) t->cfg.device_budget_bytes = 16ull << 30;
   t->cfg.fn_has_size = nullptr;
+  if (cfg->autotune_cache) t->cache_path = cfg->autotune_cache;
   t->cfg.autotune_cache = nullptr;
   if (cfg->format == THAPI_FMT_VAR16 && cfg->fn_has_size)
     t->has_size.assign(cfg->fn_has_size, cfg->fn_has_size + cfg->n_fns);
@@ -328,10 +368,64 @@ int thapi_tally_open(const thapi_tally_config *cfg, thapi_tally **out) {
   }
   t->shape = pick_shape(t);
   if (!t->shape.T) return bail(THAPI_E_INVAL);
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, c.device) == hipSuccess) t->arch = prop.gcnArchName;
+    const std::string::size_type colon = t->arch.find(':');
+    if (colon != std::string::npos) t->arch.resize(colon);
+    if (t->arch.empty()) t->arch = "gpu";
+  }
+  load_tune_cache(t);
+  if (prepare_range_kernels((uint32_t)(t->lds_limit - 256)) != hipSuccess) return bail(THAPI_E_DEVICE);
+  if (c.flags & THAPI_SERVICE) {
+    if (hipStreamCreateWithFlags(&t->cst, hipStreamNonBlocking) != hipSuccess) return bail(THAPI_E_DEVICE);
+    if (!(c.flags & THAPI_DEVICE_INPUT) && hipMalloc((void **)&t->arena, c.device_budget_bytes) != hipSuccess) {
+      hipGetLastError();
+      return bail(THAPI_E_NOMEM);
+    }
+    t->worker = std::thread(service_loop, t);
+  }
   if (init_tables(t) != hipSuccess) return bail(THAPI_E_DEVICE);
   *out = t;
   return THAPI_OK;
 }
+
+namespace {
+
+// Service-mode arena: allocations are released in the order they were made
+// (the worker tallies queued chunks in ticket order), so free space is the
+// one or two gaps around the live span [a_tail, a_head).  Caller holds t->mu.
+bool arena_alloc(thapi_tally *t, uint64_t n, uint64_t *off) {
+  const uint64_t cap = t->cfg.device_budget_bytes;
+  if (t->a_live.empty()) t->a_head = t->a_tail = 0;
+  uint64_t at;
+  if (t->a_live.empty() || t->a_head > t->a_tail) {
+    if (cap - t->a_head >= n) at = t->a_head;
+    else if (!t->a_live.empty() && t->a_tail > n) at = 0;  // wrap; the end of the buffer stays unused
+    else return false;
+  } else {
+    if (t->a_tail - t->a_head > n) at = t->a_head;
+    else return false;
+  }
+  t->a_head = at + n;
+  t->a_live.push_back({at, at + n});
+  *off = at;
+  return true;
+}
+
+void arena_release_front(thapi_tally *t) {
+  if (t->a_live.empty()) return;
+  t->a_live.pop_front();
+  if (t->a_live.empty()) t->a_head = t->a_tail = 0;
+  else t->a_tail = t->a_live.front().first;
+}
+
+uint64_t now_ns() {
+  return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+             std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
 
 int thapi_tally_submit(thapi_tally *t, const thapi_stream_key *key, const void *records, size_t record_bytes,
                        const void *payload, size_t payload_bytes, uint64_t *ticket_out) {
@@ -391,9 +485,55 @@ int thapi_tally_submit(thapi_tally *t, const thapi_stream_key *key, const void *
   c.stream = sidx;
   c.n_rec = n_rec;
   c.pay_bytes = payload_bytes;
+  c.ready = true;
+  const bool service = (t->cfg.flags & THAPI_SERVICE) != 0;
   if (dev_in) {
     c.rec = (const uint8_t *)records;
     c.pay = (const uint8_t *)payload;
+  } else if (n_rec && service) {
+    // admission: wait for room in the device arena (FIFO reuse), queue the
+    // chunk in ticket order at once, copy outside the lock, then mark it ready
+    const uint64_t rec_al = (record_bytes + 255) / 256 * 256;
+    const uint64_t bytes = rec_al + (payload_bytes + 255) / 256 * 256;
+    if (bytes > t->cfg.device_budget_bytes) return THAPI_E_NOMEM;
+    uint64_t off = 0;
+    while (!arena_alloc(t, bytes, &off)) {
+      if (t->cfg.flags & THAPI_DROP_ON_FULL) {
+        t->dropped[sidx] += n_rec;
+        if (ticket_out) *ticket_out = 0;
+        return THAPI_OK;
+      }
+      if (t->cfg.flags & THAPI_NONBLOCKING) return THAPI_E_AGAIN;
+      t->cv.wait(lk);
+      if (t->failed || t->stop) return THAPI_E_STATE;
+    }
+    t->budget_used += bytes;
+    t->bytes_admitted += record_bytes + payload_bytes;
+    c.in_arena = true;
+    c.owned_bytes = bytes;
+    c.rec = t->arena + off;
+    c.pay = payload_bytes ? t->arena + off + rec_al : nullptr;
+    c.ready = false;
+    c.ticket = t->next_ticket++;
+    const uint64_t ticket = c.ticket;
+    t->queue.push_back(c);
+    lk.unlock();
+    hipError_t e = hipMemcpyAsync(t->arena + off, records, record_bytes, hipMemcpyHostToDevice, t->cst);
+    if (e == hipSuccess && payload_bytes)
+      e = hipMemcpyAsync(t->arena + off + rec_al, payload, payload_bytes, hipMemcpyHostToDevice, t->cst);
+    if (e == hipSuccess) e = hipStreamSynchronize(t->cst);
+    lk.lock();
+    for (auto it = t->queue.rbegin(); it != t->queue.rend(); ++it)
+      if (it->ticket == ticket) { it->ready = true; break; }
+    if (e != hipSuccess) {
+      t->failed = THAPI_E_DEVICE;
+      t->cv.notify_all();
+      t->work_cv.notify_all();
+      return THAPI_E_DEVICE;
+    }
+    if (ticket_out) *ticket_out = ticket;
+    t->work_cv.notify_all();
+    return THAPI_OK;
   } else if (n_rec) {
     const uint64_t bytes = record_bytes + payload_bytes + 64;
     if (bytes > t->cfg.device_budget_bytes) return THAPI_E_NOMEM;
@@ -429,123 +569,252 @@ int thapi_tally_submit(thapi_tally *t, const thapi_stream_key *key, const void *
   c.ticket = t->next_ticket++;
   if (ticket_out) *ticket_out = c.ticket;
   t->queue.push_back(c);
+  if (service) t->work_cv.notify_all();
   return THAPI_OK;
 }
 
-int thapi_tally_flush(thapi_tally *t, uint64_t ticket, uint32_t flags) {
-  if (!t) return THAPI_E_INVAL;
-  std::lock_guard<std::mutex> run(t->run_mu);
-  std::vector<Chunk> work;
-  {
-    std::lock_guard<std::mutex> g(t->mu);
-    if (t->failed) return t->failed == THAPI_E_DEVICE ? THAPI_E_DEVICE : THAPI_E_STATE;
-    if (t->finalized) return THAPI_E_STATE;
-    while (!t->queue.empty() && t->queue.front().ticket <= ticket) {
-      work.push_back(t->queue.front());
-      t->queue.pop_front();
-    }
-  }
-  if (hipSetDevice(t->dev) != hipSuccess) return THAPI_E_DEVICE;
-  for (int k = 0; k < TM_N; k++) t->timings[k] = 0;
-  // chunks grouped by stream, each stream's chunks in ticket order
-  std::stable_sort(work.begin(), work.end(), [](const Chunk &a, const Chunk &b) { return a.stream < b.stream; });
+namespace {
+
+// The device work of one flush: segments (one per chunk), ranges (a stream's
+// records cut into pieces of about equal length), per-stream spans of
+// consecutive ranges, and the work-list order (longest range first).
+struct Plan {
   std::vector<Seg> segs;
   std::vector<Range> ranges;
-  std::vector<uint32_t> segfirst;
-  std::vector<uint32_t> spans;
+  std::vector<uint32_t> segfirst, spans, order;
   uint64_t total = 0;
-  for (auto &c : work) total += c.n_rec;
-  const uint32_t T = t->shape.T;
-  // At most one range per CU (the range kernel holds one workgroup per CU):
-  // with n_seg chunks, ranges of ceil(total / (n_cu - n_seg)) records give at
-  // most n_cu ranges in all (each chunk adds at most one partial range).
-  // Ranges are never shorter than 16 tiles.
+};
+
+void plan_work(const thapi_tally *t, const std::vector<Chunk> &work, const Shape &sh, Plan &pl) {
+  pl = Plan();
+  for (auto &c : work) pl.total += c.n_rec;
+  // The work list holds about rpc * n_cu ranges: with n_seg chunks, ranges of
+  // ceil(total / (rpc * n_cu - n_seg)) records give at most rpc * n_cu of
+  // them (each chunk adds at most one partial range).  Ranges are never
+  // shorter than 16 tiles.
   uint64_t n_seg = 0;
   for (auto &c : work) n_seg += c.n_rec ? 1 : 0;
-  const uint64_t ncu = std::max<uint64_t>(1, (uint64_t)t->n_cu);
+  const uint64_t ncu = std::max<uint64_t>(1, (uint64_t)t->n_cu) * std::max<uint32_t>(1, sh.rpc);
   const uint64_t target = ncu > 2 * n_seg ? ncu - n_seg : std::max<uint64_t>(1, ncu / 2);
-  uint64_t rlen = (total + target - 1) / target;
-  rlen = std::max<uint64_t>(rlen, 16ull * T);
+  uint64_t rlen = (pl.total + target - 1) / target;
+  rlen = std::max<uint64_t>(rlen, 16ull * sh.T);
   rlen = std::min<uint64_t>(rlen, 1ull << 30);
   for (size_t i = 0; i < work.size(); i++) {
     const Chunk &c = work[i];
     if (!c.n_rec) continue;
-    Seg s{};
-    s.rec = c.rec; s.pay = c.pay; s.n_rec = c.n_rec; s.pay_bytes = c.pay_bytes; s.stream = c.stream;
-    segfirst.push_back((uint32_t)ranges.size());
-    const uint32_t si = (uint32_t)segs.size();
-    segs.push_back(s);
+    Seg sg{};
+    sg.rec = c.rec; sg.pay = c.pay; sg.n_rec = c.n_rec; sg.pay_bytes = c.pay_bytes; sg.stream = c.stream;
+    pl.segfirst.push_back((uint32_t)pl.ranges.size());
+    const uint32_t si = (uint32_t)pl.segs.size();
+    pl.segs.push_back(sg);
     const uint64_t nr = (c.n_rec + rlen - 1) / rlen;
     const uint64_t step = (c.n_rec + nr - 1) / nr;
     for (uint64_t b = 0; b < c.n_rec; b += step) {
       Range r{};
       r.seg = si; r.stream = c.stream; r.begin = b; r.n = std::min<uint64_t>(step, c.n_rec - b); r.pay_begin = 0;
-      if (spans.empty() || spans[spans.size() - 3] != c.stream) {
-        spans.push_back(c.stream); spans.push_back((uint32_t)ranges.size()); spans.push_back((uint32_t)ranges.size());
+      if (pl.spans.empty() || pl.spans[pl.spans.size() - 3] != c.stream) {
+        pl.spans.push_back(c.stream); pl.spans.push_back((uint32_t)pl.ranges.size());
+        pl.spans.push_back((uint32_t)pl.ranges.size());
       }
-      ranges.push_back(r);
-      spans[spans.size() - 1] = (uint32_t)ranges.size();
+      pl.ranges.push_back(r);
+      pl.spans[pl.spans.size() - 1] = (uint32_t)pl.ranges.size();
     }
   }
-  segfirst.push_back((uint32_t)ranges.size());
-  const uint32_t nR = (uint32_t)ranges.size(), nS = (uint32_t)segs.size(), nSp = (uint32_t)(spans.size() / 3);
+  pl.segfirst.push_back((uint32_t)pl.ranges.size());
+  // longest first: the persistent workgroups take them in this order, so the
+  // short ranges fill in at the end (LPT scheduling)
+  pl.order.resize(pl.ranges.size());
+  for (uint32_t k = 0; k < pl.order.size(); k++) pl.order[k] = k;
+  std::stable_sort(pl.order.begin(), pl.order.end(),
+                   [&](uint32_t a, uint32_t b) { return pl.ranges[a].n > pl.ranges[b].n; });
+}
+
+hipError_t upload_plan(thapi_tally *t, const Plan &pl) {
+  const uint32_t nR = (uint32_t)pl.ranges.size(), nS = (uint32_t)pl.segs.size();
   const uint32_t D = t->cfg.max_depth;
-  int rc = THAPI_OK;
+  hipError_t e;
+#define UPCHK(x) do { if ((e = (x)) != hipSuccess) return e; } while (0)
+  UPCHK(t->segs.ensure(sizeof(Seg) * nS));
+  UPCHK(t->ranges.ensure(sizeof(Range) * nR));
+  UPCHK(t->order.ensure(4ull * nR));
+  UPCHK(t->qhead.ensure(256));
+  UPCHK(t->segfirst.ensure(4ull * (nS + 1)));
+  UPCHK(t->spans.ensure(4ull * pl.spans.size()));
+  UPCHK(t->rhdr.ensure(sizeof(RHdr) * (size_t)nR * S_MAX));
+  UPCHK(t->ru.ensure(sizeof(UItem) * (size_t)nR * S_MAX * D));
+  UPCHK(t->ro.ensure(sizeof(OItem) * (size_t)nR * S_MAX * D));
+  UPCHK(t->rnslots.ensure(4ull * nR));
+  UPCHK(t->paylen.ensure(8ull * nR));
+  UPCHK(hipMemcpyAsync(t->segs.p, pl.segs.data(), sizeof(Seg) * nS, hipMemcpyHostToDevice, t->st));
+  UPCHK(hipMemcpyAsync(t->ranges.p, pl.ranges.data(), sizeof(Range) * nR, hipMemcpyHostToDevice, t->st));
+  UPCHK(hipMemcpyAsync(t->order.p, pl.order.data(), 4ull * nR, hipMemcpyHostToDevice, t->st));
+  UPCHK(hipMemcpyAsync(t->segfirst.p, pl.segfirst.data(), 4ull * (nS + 1), hipMemcpyHostToDevice, t->st));
+  UPCHK(hipMemcpyAsync(t->spans.p, pl.spans.data(), 4ull * pl.spans.size(), hipMemcpyHostToDevice, t->st));
+#undef UPCHK
+  return hipSuccess;
+}
+
+// The kernels of one flush, in stream order.  `timed` records the per-kernel
+// events (not used under graph capture).
+hipError_t launch_pipeline(thapi_tally *t, const Plan &pl, const Shape &sh, bool final, bool timed) {
+  const uint32_t nR = (uint32_t)pl.ranges.size(), nS = (uint32_t)pl.segs.size();
+  const uint32_t nSp = (uint32_t)(pl.spans.size() / 3);
+  hipError_t e;
+#define LPCHK(x) do { if ((e = (x)) != hipSuccess) return e; } while (0)
+#define TB(k) do { if (timed) LPCHK(timed_begin(t, k)); } while (0)
+#define TE(k) do { if (timed) LPCHK(timed_end(t, k)); } while (0)
+  LPCHK(launch_fill32(t->tb.err, 1, 0, t->st));
   if (nR) {
-    HIPCHK(t->segs.ensure(sizeof(Seg) * nS));
-    HIPCHK(t->ranges.ensure(sizeof(Range) * nR));
-    HIPCHK(t->segfirst.ensure(4ull * (nS + 1)));
-    HIPCHK(t->spans.ensure(4ull * spans.size()));
-    HIPCHK(t->rhdr.ensure(sizeof(RHdr) * (size_t)nR * S_MAX));
-    HIPCHK(t->ru.ensure(sizeof(UItem) * (size_t)nR * S_MAX * D));
-    HIPCHK(t->ro.ensure(sizeof(OItem) * (size_t)nR * S_MAX * D));
-    HIPCHK(t->rnslots.ensure(4ull * nR));
-    HIPCHK(t->paylen.ensure(8ull * nR));
-    HIPCHK(hipMemcpyAsync(t->segs.p, segs.data(), sizeof(Seg) * nS, hipMemcpyHostToDevice, t->st));
-    HIPCHK(hipMemcpyAsync(t->ranges.p, ranges.data(), sizeof(Range) * nR, hipMemcpyHostToDevice, t->st));
-    HIPCHK(hipMemcpyAsync(t->segfirst.p, segfirst.data(), 4ull * (nS + 1), hipMemcpyHostToDevice, t->st));
-    HIPCHK(hipMemcpyAsync(t->spans.p, spans.data(), 4ull * spans.size(), hipMemcpyHostToDevice, t->st));
-    HIPCHK(launch_fill32(t->tb.err, 1, 0, t->st));
     if (t->cfg.format == THAPI_FMT_VAR16) {
-      HIPCHK(timed_begin(t, TM_PREPASS));
-      HIPCHK(launch_paylen(t->segs.as<Seg>(), t->ranges.as<Range>(), nR, t->segfirst.as<uint32_t>(), nS,
-                           t->paylen.as<uint64_t>(), t->st));
-      HIPCHK(timed_end(t, TM_PREPASS));
+      TB(TM_PREPASS);
+      LPCHK(launch_paylen(t->segs.as<Seg>(), t->ranges.as<Range>(), nR, t->segfirst.as<uint32_t>(), nS,
+                          t->paylen.as<uint64_t>(), t->st));
+      TE(TM_PREPASS);
     }
-    HIPCHK(timed_begin(t, TM_RANGE));
-    HIPCHK(launch_range((int)t->cfg.format, T, t->segs.as<Seg>(), t->ranges.as<Range>(), nR, t->tb, t->shape,
-                        t->rhdr.as<RHdr>(), t->ru.as<UItem>(), t->ro.as<OItem>(), t->rnslots.as<uint32_t>(), t->st));
-    HIPCHK(timed_end(t, TM_RANGE));
-    HIPCHK(timed_begin(t, TM_COMBINE));
-    HIPCHK(launch_combine(t->spans.as<uint32_t>(), nSp, t->rhdr.as<RHdr>(), t->ru.as<UItem>(), t->ro.as<OItem>(),
-                          t->rnslots.as<uint32_t>(), t->tb, t->st));
-    HIPCHK(timed_end(t, TM_COMBINE));
+    LPCHK(launch_fill32(t->qhead.as<uint32_t>(), 1, 0, t->st));
+    TB(TM_RANGE);
+    LPCHK(launch_range((int)t->cfg.format, sh.T, t->segs.as<Seg>(), t->ranges.as<Range>(), t->order.as<uint32_t>(),
+                       nR, t->qhead.as<uint32_t>(), (uint32_t)t->n_cu, t->tb, sh, t->rhdr.as<RHdr>(),
+                       t->ru.as<UItem>(), t->ro.as<OItem>(), t->rnslots.as<uint32_t>(), t->st));
+    TE(TM_RANGE);
+    TB(TM_COMBINE);
+    LPCHK(launch_combine(t->spans.as<uint32_t>(), nSp, t->rhdr.as<RHdr>(), t->ru.as<UItem>(), t->ro.as<OItem>(),
+                         t->rnslots.as<uint32_t>(), t->tb, t->st));
+    TE(TM_COMBINE);
   }
-  if (flags & THAPI_FLUSH_FINAL) {
-    HIPCHK(timed_begin(t, TM_FINAL));
-    HIPCHK(launch_final(t->tb, t->cfg.max_threads, t->st));
-    HIPCHK(timed_end(t, TM_FINAL));
+  if (final) {
+    TB(TM_FINAL);
+    LPCHK(launch_final(t->tb, t->cfg.max_threads, t->st));
+    TE(TM_FINAL);
   }
+#undef TB
+#undef TE
+#undef LPCHK
+  return hipSuccess;
+}
+
+// THAPI_GRAPH: the pipeline is captured once per launch signature (sizes,
+// shape, buffers) and replayed while the signature repeats.
+hipError_t run_pipeline(thapi_tally *t, const Plan &pl, const Shape &sh, bool final) {
+  const bool prof = (t->cfg.flags & THAPI_PROFILE) != 0;
+  if (!(t->cfg.flags & THAPI_GRAPH)) return launch_pipeline(t, pl, sh, final, prof);
+  const std::array<uint64_t, 16> sig = {pl.ranges.size(), pl.segs.size(), pl.spans.size(), sh.T, sh.E, sh.rpc,
+                                        final ? 1u : 0u, (uint64_t)(uintptr_t)t->segs.p,
+                                        (uint64_t)(uintptr_t)t->ranges.p, (uint64_t)(uintptr_t)t->order.p,
+                                        (uint64_t)(uintptr_t)t->rhdr.p, (uint64_t)(uintptr_t)t->ru.p,
+                                        (uint64_t)(uintptr_t)t->ro.p, (uint64_t)(uintptr_t)t->rnslots.p,
+                                        (uint64_t)(uintptr_t)t->spans.p, (uint64_t)(uintptr_t)t->paylen.p};
+  hipError_t e;
+  if (!t->gexec || sig != t->gsig) {
+    if (t->gexec) { hipGraphExecDestroy(t->gexec); t->gexec = nullptr; }
+  if (t->arena) { hipFree(t->arena); t->arena = nullptr; }
+  if (t->cst) { hipStreamDestroy(t->cst); t->cst = nullptr; }
+    hipGraph_t g = nullptr;
+    if ((e = hipStreamBeginCapture(t->st, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
+    const hipError_t le = launch_pipeline(t, pl, sh, final, false);
+    e = hipStreamEndCapture(t->st, &g);
+    if (le != hipSuccess) { if (g) hipGraphDestroy(g); return le; }
+    if (e != hipSuccess) return e;
+    e = hipGraphInstantiate(&t->gexec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) { t->gexec = nullptr; return e; }
+    t->gsig = sig;
+    t->graph_builds++;
+  }
+  if (prof && (e = timed_begin(t, TM_RANGE)) != hipSuccess) return e;
+  if ((e = hipGraphLaunch(t->gexec, t->st)) != hipSuccess) return e;
+  if (prof && (e = timed_end(t, TM_RANGE)) != hipSuccess) return e;
+  t->graph_launches++;
+  return hipSuccess;
+}
+
+// ---- autotune cache: one line per workload class, "key T E rpc"
+std::string tune_key(const thapi_tally *t, const std::vector<Chunk> &work) {
+  uint64_t total = 0, nseg = 0;
+  for (auto &c : work) { total += c.n_rec; nseg += c.n_rec ? 1 : 0; }
+  auto lg = [](uint64_t x) { int b = 0; while (x > 1) { x >>= 1; b++; } return b; };
+  char k[160];
+  snprintf(k, sizeof k, "%s/cu%d/fmt%u/D%u/fns%d/segs%d/recs%d", t->arch.c_str(), t->n_cu, t->cfg.format,
+           t->cfg.max_depth, lg(t->cfg.n_fns), lg(nseg), lg(total));
+  return k;
+}
+
+void load_tune_cache(thapi_tally *t) {
+  if (t->cache_path.empty()) return;
+  FILE *f = fopen(t->cache_path.c_str(), "r");
+  if (!f) return;
+  char key[256];
+  unsigned T, E, rpc;
+  while (fscanf(f, "%255s %u %u %u", key, &T, &E, &rpc) == 4) t->tuned[key] = {T, E, rpc};
+  fclose(f);
+}
+
+void save_tune_cache(thapi_tally *t) {
+  if (t->cache_path.empty()) return;
+  FILE *f = fopen(t->cache_path.c_str(), "w");
+  if (!f) return;
+  for (auto &kv : t->tuned) fprintf(f, "%s %u %u %u\n", kv.first.c_str(), kv.second[0], kv.second[1], kv.second[2]);
+  fclose(f);
+}
+
+// The shape for this work: a tuned entry when one matches, else the default.
+Shape shape_for(thapi_tally *t, const std::vector<Chunk> &work) {
+  if (t->tuned.empty()) return t->shape;
+  auto it = t->tuned.find(tune_key(t, work));
+  if (it == t->tuned.end()) return t->shape;
+  Shape s = t->shape;
+  const size_t b = range_lds_bytes(it->second[0], it->second[1], s.KL, t->cfg.max_depth, (int)t->cfg.format);
+  if ((it->second[0] == 1024 || it->second[0] == 2048) && it->second[1] >= 64 && b + 256 <= t->lds_limit) {
+    s.T = it->second[0]; s.E = it->second[1]; s.lds_bytes = (uint32_t)b;
+    s.rpc = std::max<uint32_t>(1, std::min<uint32_t>(it->second[2], 64));
+  }
+  return s;
+}
+
+}  // namespace
+
+namespace {
+
+// Tallies one batch of chunks (taken off the queue by the caller) and, with
+// `final`, closes every stream.  Caller holds run_mu.
+int process_batch(thapi_tally *t, std::vector<Chunk> &work, bool final) {
+  if (hipSetDevice(t->dev) != hipSuccess) return THAPI_E_DEVICE;
+  for (int k = 0; k < TM_N; k++) t->timings[k] = 0;
+  // chunks grouped by stream, each stream's chunks in ticket order
+  std::stable_sort(work.begin(), work.end(), [](const Chunk &a, const Chunk &b) { return a.stream < b.stream; });
+  const Shape sh = shape_for(t, work);
+  Plan pl;
+  plan_work(t, work, sh, pl);
+  const uint32_t nR = (uint32_t)pl.ranges.size();
+  int rc = THAPI_OK;
+  if (nR) HIPCHK(upload_plan(t, pl));
+  HIPCHK(run_pipeline(t, pl, sh, final));
   HIPCHK(ensure_pinned(t, 64));
   uint32_t *herr = (uint32_t *)t->h_pinned;
   HIPCHK(hipMemcpyAsync(herr, t->tb.err, 4, hipMemcpyDeviceToHost, t->st));
   HIPCHK(hipStreamSynchronize(t->st));
   const uint32_t err = *herr;
-  if (nR) {
-    if (t->cfg.format == THAPI_FMT_VAR16) collect_timing(t, TM_PREPASS);
-    collect_timing(t, TM_RANGE);
-    collect_timing(t, TM_COMBINE);
+  if (t->cfg.flags & THAPI_GRAPH) {
+    collect_timing(t, TM_RANGE);  // whole graph
+  } else {
+    if (nR) {
+      if (t->cfg.format == THAPI_FMT_VAR16) collect_timing(t, TM_PREPASS);
+      collect_timing(t, TM_RANGE);
+      collect_timing(t, TM_COMBINE);
+    }
+    if (final) collect_timing(t, TM_FINAL);
   }
-  if (flags & THAPI_FLUSH_FINAL) collect_timing(t, TM_FINAL);
   {
     std::lock_guard<std::mutex> g(t->mu);
     for (auto &c : work) {
-      if (c.owned) { hipFree(c.owned); t->budget_used -= c.owned_bytes; }
+      if (c.in_arena) { arena_release_front(t); t->budget_used -= c.owned_bytes; }
+      else if (c.owned) { hipFree(c.owned); t->budget_used -= c.owned_bytes; }
     }
     t->cv.notify_all();
     if (err & (ERR_CAPACITY | ERR_RANGE_THREADS)) { t->failed = THAPI_E_CAPACITY; rc = THAPI_E_CAPACITY; }
     else if (err & ERR_DEPTH) { t->failed = THAPI_E_DEPTH; rc = THAPI_E_DEPTH; }
-    if (flags & THAPI_FLUSH_FINAL) t->finalized = true;
+    if (final) t->finalized = true;
+    t->flushed_any = true;
   }
   if (rc == THAPI_OK && (t->cfg.flags & THAPI_STRICT)) {
     // strict mode: any anomaly counted so far fails the flush
@@ -561,6 +830,166 @@ int thapi_tally_flush(thapi_tally *t, uint64_t ticket, uint32_t flags) {
     }
   }
   return rc;
+}
+
+// THAPI_SERVICE worker: the continuous-batching loop.  Each iteration takes
+// every chunk whose copy has landed (the ready prefix of the queue, in ticket
+// order), tallies them in one pipeline launch, stamps their completion time
+// and frees their arena space, which admits waiting submitters.  Chunks that
+// arrive meanwhile are copied on their own stream while the kernels run and
+// join the next iteration.
+void service_loop(thapi_tally *t) {
+  hipSetDevice(t->dev);
+  for (;;) {
+    std::vector<Chunk> work;
+    {
+      std::unique_lock<std::mutex> lk(t->mu);
+      t->work_cv.wait(lk, [&] {
+        return t->stop || t->failed || (!t->queue.empty() && t->queue.front().ready);
+      });
+      if (t->failed) { t->cv.notify_all(); return; }
+      if (t->queue.empty() || !t->queue.front().ready) {
+        if (t->stop) return;
+        continue;
+      }
+      while (!t->queue.empty() && t->queue.front().ready) {
+        work.push_back(t->queue.front());
+        t->queue.pop_front();
+      }
+    }
+    uint64_t last = 0;
+    for (auto &c : work) last = std::max(last, c.ticket);
+    const size_t nchunks = work.size();
+    int rc;
+    {
+      std::lock_guard<std::mutex> run(t->run_mu);
+      rc = process_batch(t, work, false);
+    }
+    const uint64_t tdone = now_ns();
+    std::lock_guard<std::mutex> g(t->mu);
+    if (rc != THAPI_OK && rc != THAPI_E_MALFORMED && !t->failed) t->failed = rc;
+    if (t->done_ns.size() <= last) t->done_ns.resize(last + 1, 0);
+    for (auto &c : work) t->done_ns[c.ticket] = tdone;
+    t->done_upto = std::max(t->done_upto, last);
+    t->n_batches++;
+    t->n_batch_chunks += nchunks;
+    t->max_batch_chunks = std::max<uint64_t>(t->max_batch_chunks, nchunks);
+    t->cv.notify_all();
+  }
+}
+
+}  // namespace
+
+int thapi_tally_flush(thapi_tally *t, uint64_t ticket, uint32_t flags) {
+  if (!t) return THAPI_E_INVAL;
+  const bool final = (flags & THAPI_FLUSH_FINAL) != 0;
+  if (t->cfg.flags & THAPI_SERVICE) {
+    // the worker tallies; wait until it has covered `ticket`
+    std::unique_lock<std::mutex> lk(t->mu);
+    if (t->finalized) return THAPI_E_STATE;
+    const uint64_t want = std::min<uint64_t>(ticket, t->next_ticket - 1);
+    t->cv.wait(lk, [&] { return t->failed || t->done_upto >= want || (want == 0); });
+    if (t->failed) return t->failed == THAPI_E_DEVICE ? THAPI_E_DEVICE : t->failed;
+    if (!final) return THAPI_OK;
+    if (!t->queue.empty()) return THAPI_E_STATE;  // submits still arriving: finish them first
+    lk.unlock();
+    std::lock_guard<std::mutex> run(t->run_mu);
+    std::vector<Chunk> none;
+    return process_batch(t, none, true);
+  }
+  std::lock_guard<std::mutex> run(t->run_mu);
+  std::vector<Chunk> work;
+  {
+    std::lock_guard<std::mutex> g(t->mu);
+    if (t->failed) return t->failed == THAPI_E_DEVICE ? THAPI_E_DEVICE : THAPI_E_STATE;
+    if (t->finalized) return THAPI_E_STATE;
+    while (!t->queue.empty() && t->queue.front().ticket <= ticket) {
+      work.push_back(t->queue.front());
+      t->queue.pop_front();
+    }
+  }
+  return process_batch(t, work, final);
+}
+
+int thapi_tally_ticket_done(thapi_tally *t, uint64_t ticket, uint64_t *done_ns) {
+  if (!t || !ticket) return THAPI_E_INVAL;
+  std::lock_guard<std::mutex> g(t->mu);
+  if (ticket >= t->next_ticket) return THAPI_E_INVAL;
+  if (ticket > t->done_upto || ticket >= t->done_ns.size()) return THAPI_E_AGAIN;
+  if (done_ns) *done_ns = t->done_ns[ticket];
+  return THAPI_OK;
+}
+
+int thapi_tally_service_info(thapi_tally *t, uint64_t *info, int n) {
+  if (!t || (n && !info)) return THAPI_E_INVAL;
+  std::lock_guard<std::mutex> g(t->mu);
+  const uint64_t v[6] = {t->n_batches, t->n_batch_chunks, t->max_batch_chunks, t->bytes_admitted,
+                         (uint64_t)t->queue.size(), t->budget_used};
+  const int m = std::min(n, 6);
+  for (int k = 0; k < m; k++) info[k] = v[k];
+  return m;
+}
+
+int thapi_tally_autotune(thapi_tally *t, uint32_t reps, uint32_t *chosen) {
+  if (!t) return THAPI_E_INVAL;
+  std::lock_guard<std::mutex> run(t->run_mu);
+  std::vector<Chunk> work;
+  {
+    std::lock_guard<std::mutex> g(t->mu);
+    if (t->failed) return t->failed == THAPI_E_DEVICE ? THAPI_E_DEVICE : THAPI_E_STATE;
+    if (t->finalized || t->flushed_any || t->queue.empty() || (t->cfg.flags & THAPI_SERVICE)) return THAPI_E_STATE;
+    work.assign(t->queue.begin(), t->queue.end());
+  }
+  if (hipSetDevice(t->dev) != hipSuccess) return THAPI_E_DEVICE;
+  std::stable_sort(work.begin(), work.end(), [](const Chunk &a, const Chunk &b) { return a.stream < b.stream; });
+  reps = std::max<uint32_t>(1, std::min<uint32_t>(reps, 16));
+  const uint32_t D = t->cfg.max_depth;
+  const int fmt = (int)t->cfg.format;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  float best_ms = -1;
+  Shape best = t->shape;
+  const uint32_t Ts[] = {2048, 1024}, Es[] = {2048, 1024}, rpcs[] = {1, 2, 4};
+  int rc = THAPI_OK;
+  for (uint32_t T : Ts)
+    for (uint32_t E : Es)
+      for (uint32_t rpc : rpcs) {
+        Shape sh = t->shape;
+        const size_t b = range_lds_bytes(T, E, sh.KL, D, fmt);
+        if (b + 256 > t->lds_limit) continue;
+        sh.T = T; sh.E = E; sh.rpc = rpc; sh.lds_bytes = (uint32_t)b;
+        Plan pl;
+        plan_work(t, work, sh, pl);
+        float ms_min = -1;
+        bool ok = true;
+        for (uint32_t r = 0; r < reps + 1 && ok; r++) {
+          hipError_t e = init_tables(t);
+          if (e == hipSuccess) e = upload_plan(t, pl);
+          if (e == hipSuccess) e = hipEventRecord(e0, t->st);
+          if (e == hipSuccess) e = launch_pipeline(t, pl, sh, false, false);
+          if (e == hipSuccess) e = hipEventRecord(e1, t->st);
+          uint32_t herr = 0;
+          if (e == hipSuccess) e = hipMemcpyAsync(&herr, t->tb.err, 4, hipMemcpyDeviceToHost, t->st);
+          if (e == hipSuccess) e = hipStreamSynchronize(t->st);
+          if (e != hipSuccess) { rc = hip_fail(t, e); ok = false; break; }
+          if (herr) { ok = false; break; }  // this shape cannot take the work (e.g. threads per range)
+          float ms = 0;
+          hipEventElapsedTime(&ms, e0, e1);
+          if (r > 0 && (ms_min < 0 || ms < ms_min)) ms_min = ms;  // first run warms up
+        }
+        if (rc != THAPI_OK) break;
+        if (ok && ms_min >= 0 && (best_ms < 0 || ms_min < best_ms)) { best_ms = ms_min; best = sh; }
+      }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc != THAPI_OK) return rc;
+  if (init_tables(t) != hipSuccess) return hip_fail(t, hipErrorUnknown);
+  if (best_ms < 0) return THAPI_E_CAPACITY;
+  t->tuned[tune_key(t, work)] = {best.T, best.E, best.rpc};
+  save_tune_cache(t);
+  if (chosen) { chosen[0] = best.T; chosen[1] = best.E; chosen[2] = best.rpc; }
+  return THAPI_OK;
 }
 
 int thapi_tally_read(thapi_tally *t, uint32_t scope, uint32_t trace_id, thapi_tally_row *rows, size_t capacity,
@@ -722,11 +1151,21 @@ int thapi_tally_reset(thapi_tally *t) {
   t->dropped.clear();
   t->failed = 0;
   t->finalized = false;
+  t->flushed_any = false;
   return THAPI_OK;
 }
 
 int thapi_tally_close(thapi_tally *t) {
   if (!t) return THAPI_E_INVAL;
+  if (t->worker.joinable()) {
+    {
+      std::lock_guard<std::mutex> g(t->mu);
+      t->stop = true;
+      t->cv.notify_all();
+      t->work_cv.notify_all();
+    }
+    t->worker.join();
+  }
   {
     std::lock_guard<std::mutex> run(t->run_mu);
     hipSetDevice(t->dev);

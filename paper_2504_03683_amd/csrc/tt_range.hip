@@ -140,13 +140,16 @@ __device__ inline uint64_t lanemask_lt() {
   const uint32_t lane = __lane_id();
   return lane ? (~0ull >> (64 - lane)) : 0ull;
 }
+// Inclusive prefix sum over the 64 lanes with DPP row shifts and row
+// broadcasts (gfx9 encodings: row_shr:k = 0x110 + k, row_bcast:15 = 0x142,
+// row_bcast:31 = 0x143; lanes without a source add 0).
 __device__ inline uint32_t wave_incl_scan(uint32_t v) {
-  const int lane = __lane_id();
-#pragma unroll
-  for (int o = 1; o < WAVE; o <<= 1) {
-    uint32_t t = __shfl_up(v, o, WAVE);
-    if (lane >= o) v += t;
-  }
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int32_t)v, 0x111, 0xF, 0xF, false);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int32_t)v, 0x112, 0xF, 0xF, false);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int32_t)v, 0x114, 0xF, 0xF, false);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int32_t)v, 0x118, 0xF, 0xF, false);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int32_t)v, 0x142, 0xA, 0xF, false);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int32_t)v, 0x143, 0xC, 0xF, false);
   return v;
 }
 __device__ inline void lds_add32(uint32_t *p, uint32_t v) {
@@ -632,45 +635,40 @@ __device__ __forceinline__ void tile_pass(RangeLds &L, const Tables &tb, const u
     C.c[ST_BAD] += n_bad;
     if (tid == 0) C.c[ST_RECORDS] += n;
     // ---- P3. thread id -> local slot
-    // bucket word: bit 63 occupied, bit 62 pending, [32,40) slot, [0,32) tid
-    bool any_miss = false;
+    // bucket word: bit 63 occupied, bit 62 pending, [32,40) slot, [0,32) tid.
+    // A lane that finds no bucket for its tid claims one as pending and lists
+    // the tid; after one barrier, no listed tid means nobody missed.
 #pragma unroll
     for (int r = 0; r < ROWS; r++) {
       if (r_slot[r] == EMPTY32) continue;
       const uint32_t t = r_tid[r];
       uint32_t h = hash32(t) & (TIDMAP - 1);
       for (uint32_t probe = 0; probe < TIDMAP; probe++) {
-        const uint64_t e = L.tidmap[h];
-        if (e == 0) { any_miss = true; r_slot[r] = EMPTY32 - 1; break; }
+        uint64_t e = L.tidmap[h];
+        if (e == 0) {
+          const uint64_t want = (1ull << 63) | (1ull << 62) | t;
+          e = atomicCAS((unsigned long long *)&L.tidmap[h], 0ull, (unsigned long long)want);
+          if (e == 0) {
+            const uint32_t k = atomicAdd(&L.misc[1], 1u);
+            L.newtid[k] = t;
+            L.newbucket[k] = h;
+            r_slot[r] = EMPTY32 - 1;
+            break;
+          }
+        }
         if ((uint32_t)e == t) {
-          if (e & (1ull << 62)) { any_miss = true; r_slot[r] = EMPTY32 - 1; }
-          else r_slot[r] = (uint32_t)(e >> 32) & 0xFFu;
+          const uint32_t sl = (uint32_t)(e >> 32) & 0xFFu;
+          if (e & (1ull << 62)) r_slot[r] = EMPTY32 - 1;
+          else r_slot[r] = sl < slot_cap(D) ? sl : EMPTY32;  // over the per-range limit: the flush fails
           break;
         }
         h = (h + 1) & (TIDMAP - 1);
       }
     }
-    if (__syncthreads_or(any_miss)) {
-#pragma unroll
-      for (int r = 0; r < ROWS; r++) {
-        if (r_slot[r] != EMPTY32 - 1) continue;
-        const uint32_t t = r_tid[r];
-        uint32_t h = hash32(t) & (TIDMAP - 1);
-        for (uint32_t probe = 0; probe < TIDMAP; probe++) {
-          const uint64_t want = (1ull << 63) | (1ull << 62) | t;
-          const uint64_t old = atomicCAS((unsigned long long *)&L.tidmap[h], 0ull, (unsigned long long)want);
-          if (old == 0) {
-            const uint32_t k = atomicAdd(&L.misc[1], 1u);
-            L.newtid[k] = t;
-            L.newbucket[k] = h;
-            break;
-          }
-          if ((uint32_t)old == t) break;
-          h = (h + 1) & (TIDMAP - 1);
-        }
-      }
-      __syncthreads();
-      const uint32_t n_new = L.misc[1], base = L.misc[0];
+    __syncthreads();
+    const uint32_t n_new = L.misc[1];
+    if (n_new) {
+      const uint32_t base = L.misc[0];
       const uint32_t scap = slot_cap(D);
       if ((uint32_t)tid < n_new) {
         const uint32_t s = base + tid;
@@ -754,20 +752,19 @@ __device__ __forceinline__ void tile_pass(RangeLds &L, const Tables &tb, const u
 }
 
 // ------------------------------------------------------------------ kernel
+// One whole range: LDS set-up, every tile, then the range summaries and the
+// flush of the LDS tallies and counters to the global tables.
 template <int FMT, int ROWS>
-__global__ __launch_bounds__(RWG) void k_range(const Seg *__restrict__ segs, const Range *__restrict__ ranges,
-                                               Tables tb, Shape sh, RHdr *__restrict__ rhdr,
-                                               UItem *__restrict__ ru, OItem *__restrict__ ro,
-                                               uint32_t *__restrict__ rnslots) {
-  extern __shared__ __align__(16) uint8_t smem[];
+__device__ __forceinline__ void range_body(RangeLds &L, const Seg *__restrict__ segs,
+                                           const Range *__restrict__ ranges, const uint32_t rid, const Tables &tb,
+                                           const Shape &sh, RHdr *__restrict__ rhdr, UItem *__restrict__ ru,
+                                           OItem *__restrict__ ro, uint32_t *__restrict__ rnslots) {
   constexpr uint32_t T = ROWS * RWG;
   constexpr uint32_t RS = FMT == 2 ? 16 : 24;
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid >> 6;
   const uint32_t D = tb.D, E = sh.E, KL = sh.KL;
-  const Range rg = ranges[blockIdx.x];
+  const Range rg = ranges[rid];
   const Seg sg = segs[rg.seg];
-  RangeLds L;
-  range_lds_layout<true>(smem, &L, T, E, KL, D, FMT);
   for (uint32_t i = tid; i < E; i += RWG) {
     L.t_key[i] = EMPTY32; L.t_cnt[i] = 0; L.t_imin[i] = EMPTY32; L.t_imax[i] = 0;
     L.t_smin[i] = EMPTY32; L.t_smax[i] = 0; L.t_isum[i] = 0; L.t_ssum[i] = 0;
@@ -783,7 +780,7 @@ __global__ __launch_bounds__(RWG) void k_range(const Seg *__restrict__ segs, con
   if (tid < 8) L.misc[tid] = 0;
   __syncthreads();
 
-  const size_t sbase = (size_t)blockIdx.x * S_MAX;
+  const size_t sbase = (size_t)rid * S_MAX;
   uint64_t pay_run = rg.pay_begin;  // payload offset of the current tile's first record
   // Two register buffers of raw record words alternate between tiles; the
   // loads are unconditional (index clamped to the range) so that nothing
@@ -816,7 +813,7 @@ __global__ __launch_bounds__(RWG) void k_range(const Seg *__restrict__ segs, con
 
   // ---- range end: summaries, tally and counter flush
   const uint32_t nslots = L.misc[0];
-  if (tid == 0) rnslots[blockIdx.x] = nslots;
+  if (tid == 0) rnslots[rid] = nslots;
   if ((uint32_t)tid < nslots) {
     const uint32_t s = tid;
     RHdr hd;
@@ -877,6 +874,29 @@ __global__ __launch_bounds__(RWG) void k_range(const Seg *__restrict__ segs, con
     if (L.cnt[i]) atomicAdd(&tb.sstats[(size_t)sg.stream * ST_N + i], (unsigned long long)L.cnt[i]);
 }
 
+// Persistent work-list launch: each workgroup (one per CU) takes the next
+// entry of `order` (range ids, longest first) until the list is exhausted.
+// `qhead` must be 0 at launch.
+template <int FMT, int ROWS>
+__global__ __launch_bounds__(RWG) void k_range(const Seg *__restrict__ segs, const Range *__restrict__ ranges,
+                                               const uint32_t *__restrict__ order, const uint32_t n_ranges,
+                                               uint32_t *__restrict__ qhead, Tables tb, Shape sh,
+                                               RHdr *__restrict__ rhdr, UItem *__restrict__ ru,
+                                               OItem *__restrict__ ro, uint32_t *__restrict__ rnslots) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  __shared__ uint32_t next;
+  RangeLds L;
+  range_lds_layout<true>(smem, &L, ROWS * RWG, sh.E, sh.KL, tb.D, FMT);
+  for (;;) {
+    if (threadIdx.x == 0) next = atomicAdd(qhead, 1u);
+    __syncthreads();
+    const uint32_t q = next;
+    __syncthreads();
+    if (q >= n_ranges) break;
+    range_body<FMT, ROWS>(L, segs, ranges, order[q], tb, sh, rhdr, ru, ro, rnslots);
+  }
+}
+
 // VAR16 pre-pass: payload bytes of each range (sum of payload_len).
 __global__ __launch_bounds__(WG) void k_range_paylen(const Seg *__restrict__ segs, Range *__restrict__ ranges,
                                                      uint64_t *__restrict__ out) {
@@ -908,18 +928,30 @@ __global__ void k_range_payoff(const Seg *__restrict__ segs, uint32_t n_segs, co
 }
 
 // --------------------------------------------------------------- launchers
-hipError_t launch_range(int fmt, uint32_t T, const Seg *segs, const Range *ranges, uint32_t n_ranges,
-                        const Tables &tb, const Shape &sh, RHdr *rhdr, UItem *ru, OItem *ro,
-                        uint32_t *rnslots, hipStream_t st) {
+// Allows every range-kernel variant up to max_lds_bytes of dynamic LDS (set
+// once, outside any stream capture).
+hipError_t prepare_range_kernels(uint32_t max_lds_bytes) {
+  const void *ks[] = {(const void *)k_range<1, 1>, (const void *)k_range<1, 2>, (const void *)k_range<2, 1>,
+                      (const void *)k_range<2, 2>};
+  for (const void *k : ks) {
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds_bytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// n_wg: workgroups of the persistent launch (at most one per CU is resident);
+// *qhead must be 0 (the caller clears it with a kernel, so the launch can be
+// captured in a graph).
+hipError_t launch_range(int fmt, uint32_t T, const Seg *segs, const Range *ranges, const uint32_t *order,
+                        uint32_t n_ranges, uint32_t *qhead, uint32_t n_wg, const Tables &tb, const Shape &sh,
+                        RHdr *rhdr, UItem *ru, OItem *ro, uint32_t *rnslots, hipStream_t st) {
   if (!n_ranges) return hipSuccess;
-  dim3 grid(n_ranges), block(RWG);
+  dim3 grid(n_wg < n_ranges ? n_wg : n_ranges), block(RWG);
 #define TT_LAUNCH(F, ROWS_)                                                                                     \
   do {                                                                                                          \
-    hipError_t e = hipFuncSetAttribute((const void *)k_range<F, ROWS_>,                                        \
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds_bytes);          \
-    if (e != hipSuccess) return e;                                                                              \
-    hipLaunchKernelGGL((k_range<F, ROWS_>), grid, block, sh.lds_bytes, st, segs, ranges, tb, sh, rhdr, ru, ro, \
-                       rnslots);                                                                                \
+    hipLaunchKernelGGL((k_range<F, ROWS_>), grid, block, sh.lds_bytes, st, segs, ranges, order, n_ranges,     \
+                       qhead, tb, sh, rhdr, ru, ro, rnslots);                                                   \
     return hipGetLastError();                                                                                   \
   } while (0)
   if (fmt == 1) {

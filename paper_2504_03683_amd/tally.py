@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libthapi_tally.so")
 
 ABI_VERSION = 1
 FMT_FIXED24, FMT_VAR16 = 1, 2
-DEVICE_INPUT, NONBLOCKING, DROP_ON_FULL, STRICT, PROFILE = 0x1, 0x2, 0x4, 0x8, 0x10
+DEVICE_INPUT, NONBLOCKING, DROP_ON_FULL, STRICT, PROFILE, GRAPH, SERVICE = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20, 0x40
 TICKET_ALL = (1 << 64) - 1
 FLUSH_FINAL = 0x1
 SCOPE_THREAD, SCOPE_PROCESS, SCOPE_FN, SCOPE_KERNEL = 1, 2, 3, 4
@@ -31,7 +31,8 @@ OK, E_INVAL, E_NOMEM, E_AGAIN, E_DEPTH, E_MALFORMED, E_DEVICE, E_BUFSZ, E_CAPACI
     0, -1, -2, -3, -4, -5, -6, -7, -8, -9
 
 ENTRY_POINTS = ["thapi_tally_open", "thapi_tally_submit", "thapi_tally_flush", "thapi_tally_read",
-                "thapi_tally_reset", "thapi_tally_close", "thapi_tally_strerror", "thapi_tally_timings"]
+                "thapi_tally_reset", "thapi_tally_close", "thapi_tally_strerror", "thapi_tally_timings",
+                "thapi_tally_autotune", "thapi_tally_ticket_done", "thapi_tally_service_info"]
 
 ROW_DTYPE = np.dtype([
     ("trace", "<u4"), ("host", "<u4"), ("pid", "<u4"), ("tid", "<u4"),
@@ -89,6 +90,9 @@ def load():
     lib.thapi_tally_strerror.argtypes = [ctypes.c_int]
     lib.thapi_tally_strerror.restype = ctypes.c_char_p
     lib.thapi_tally_timings.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.c_int]
+    lib.thapi_tally_autotune.argtypes = [P, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32)]
+    lib.thapi_tally_ticket_done.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]
+    lib.thapi_tally_service_info.argtypes = [P, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int]
     for n in ENTRY_POINTS:
         if n != "thapi_tally_strerror":
             getattr(lib, n).restype = ctypes.c_int
@@ -123,7 +127,7 @@ class Tally:
     """One library handle.  See include/thapi_tally.h for the semantics."""
 
     def __init__(self, fmt=FMT_FIXED24, n_fns=1, n_kernel_ids=0, max_depth=0, max_threads=0, max_streams=0,
-                 flags=0, has_size=None, budget=0, device=0, stream=None):
+                 flags=0, has_size=None, budget=0, device=0, stream=None, autotune_cache=None):
         self._lib = load()
         c = Config()
         c.abi_version = ABI_VERSION
@@ -143,6 +147,10 @@ class Tally:
         c.reserved = 0
         if stream is not None:
             c.hip_stream = stream if isinstance(stream, int) else stream.cuda_stream
+        self._cache_path = None
+        if autotune_cache is not None:
+            self._cache_path = os.fsencode(autotune_cache)   # kept alive with the handle
+            c.autotune_cache = self._cache_path
         self.fmt = fmt
         self.flags = flags
         self._h = ctypes.c_void_p()
@@ -192,6 +200,27 @@ class Tally:
 
     def reset(self):
         _check(self._lib.thapi_tally_reset(self._h), "reset")
+
+    def ticket_done(self, ticket):
+        """CLOCK_MONOTONIC ns at which the chunk's batch completed (service mode), or None if not yet."""
+        v = ctypes.c_uint64(0)
+        rc = self._lib.thapi_tally_ticket_done(self._h, ticket, ctypes.byref(v))
+        if rc == E_AGAIN:
+            return None
+        _check(rc, "ticket_done")
+        return v.value
+
+    def service_info(self):
+        arr = (ctypes.c_uint64 * 6)()
+        n = self._lib.thapi_tally_service_info(self._h, arr, 6)
+        return dict(zip(["batches", "batch_chunks", "max_batch_chunks", "bytes_admitted", "queued",
+                         "arena_used"], list(arr)[:n]))
+
+    def autotune(self, reps=2):
+        """Times the queued chunks under each candidate launch shape; returns the chosen (T, E, rpc)."""
+        out = (ctypes.c_uint32 * 3)()
+        _check(self._lib.thapi_tally_autotune(self._h, reps, out), "autotune")
+        return tuple(out)
 
     def timings(self):
         arr = (ctypes.c_double * 5)()

@@ -208,6 +208,17 @@ def has_size_flags(seed: int, n_fns: int, p: float) -> np.ndarray:
 P_LAUNCH_LAYERED = 1.35
 
 
+def _par(jobs):
+    """Runs independent stream generations on a thread pool (each stream is
+    seeded on its own, so the result does not depend on the pool)."""
+    from concurrent.futures import ThreadPoolExecutor
+    n = max(1, min(16, os.cpu_count() or 1, len(jobs)))
+    if n == 1:
+        return [j() for j in jobs]
+    with ThreadPoolExecutor(n) as ex:
+        return list(ex.map(lambda j: j(), jobs))
+
+
 def config(k: int, scale: float = 1.0, want_calls: bool = False) -> Workload:
     """Workload k (0..4) at `scale` x its full size (record quotas scale linearly)."""
     seed = SEED_BASE + k
@@ -223,24 +234,28 @@ def config(k: int, scale: float = 1.0, want_calls: bool = False) -> Workload:
         hs = has_size_flags(seed, 200, 0.25) if k == 2 else None
         total_api = 100_000_000 if k == 1 else int(50_000_000 / 1.1)
         quota = max(1, int(total_api * scale / 12))
-        streams = [gen_stream(cfg, seed, i, 0, 0, 1000 + i, 8, quota, want_calls, hs) for i in range(12)]
+        streams = _par([lambda i=i: gen_stream(cfg, seed, i, 0, 0, 1000 + i, 8, quota, want_calls, hs)
+                        for i in range(12)])
         return Workload("layered" if k == 1 else "layered-var16", fmt, 200, 64, 8, streams, hs)
     if k == 3:
         import random
         rnd = random.Random(seed)
-        streams = []
+        jobs = []
         for i in range(256):
             size = math.exp(rnd.uniform(math.log(1e4), math.log(2e7)))
             nthr = rnd.randint(1, 64)
             nfn = rnd.randint(32, 200)
             cfg = base_cfg(n_fns=nfn, max_depth=8)
             quota = max(1, int(size * scale))
-            streams.append(gen_stream(cfg, seed, i, i, 0, 1000, nthr, quota, want_calls))
+            jobs.append(lambda i=i, cfg=cfg, nthr=nthr, quota=quota:
+                        gen_stream(cfg, seed, i, i, 0, 1000, nthr, quota, want_calls))
+        streams = _par(jobs)
         return Workload("batched", FMT_FIXED24, 200, 0, 8, streams)
     if k == 4:
         cfg = base_cfg(n_fns=32, max_depth=4)
         quota = max(1, int(2_000_000 * scale))  # per process pool; chunks are cut by the server harness
-        streams = [gen_stream(cfg, seed, i, 0, 0, 2000 + i, 64, quota, want_calls) for i in range(64)]
+        streams = _par([lambda i=i: gen_stream(cfg, seed, i, 0, 0, 2000 + i, 64, quota, want_calls)
+                        for i in range(64)])
         return Workload("streaming", FMT_FIXED24, 32, 0, 4, streams)
     raise ValueError("workload index must be 0..4")
 

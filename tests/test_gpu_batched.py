@@ -1,0 +1,126 @@
+"""GPU parity of the batched form: many traces in one persistent work-list
+launch, every launch shape the autotuner may pick, the autotuner itself and
+its cache, and HIP-graph replay of the flush pipeline.  All compared
+bit-exactly with the CPU oracle or with the plain per-trace form."""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from tests.parity import SCOPES, assert_same, case_from_workload, run_gpu, run_oracle, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2504_03683_amd import tally
+    tally.load()
+
+
+@pytest.fixture(scope="module")
+def c3():
+    w = synth.config(3, scale=0.002)
+    c = case_from_workload(w)
+    return c, run_oracle(c)
+
+
+@pytest.fixture(scope="module")
+def c1():
+    w = synth.config(1, scale=0.01)
+    c = case_from_workload(w, split=3, seed=11)
+    return c, run_oracle(c)
+
+
+@pytest.mark.parametrize("shape", ["1024,1024,4", "2048,2048,2", "1024,2048,1", "2048,1024,3"])
+def test_launch_shapes(shape, c3, c1, monkeypatch):
+    monkeypatch.setenv("THAPI_TALLY_SHAPE", shape)
+    for name, (c, o) in (("batched 256 traces", c3), ("layered, 3 chunks per stream", c1)):
+        say("case: %s, shape %s" % (name, shape))
+        assert_same(run_gpu(c, max_threads=65536, max_streams=4096), o)
+
+
+def test_batched_equals_per_trace(c3):
+    """One flush over all traces gives, per trace, the rows of that trace tallied alone."""
+    from paper_2504_03683_amd import tally as T
+    c, o = c3
+    say("case: batched vs per-trace")
+    g = run_gpu(c, max_threads=65536, max_streams=4096)
+    assert_same(g, o)
+    traces = sorted({k[0] for k, _, _ in c.subs})
+    with T.Tally(c.fmt, c.n_fns, c.n_kid, max_depth=c.max_depth, max_threads=65536, max_streams=4096) as t, \
+            T.Tally(c.fmt, c.n_fns, c.n_kid, max_depth=c.max_depth, max_threads=65536, max_streams=4096) as b:
+        for key, rec, pay in c.subs:
+            b.submit(key, rec, pay)
+        b.flush(final=True)
+        for tr in traces[::17]:
+            t.reset()
+            for key, rec, pay in c.subs:
+                if key[0] == tr:
+                    t.submit(key, rec, pay)
+            t.flush(final=True)
+            for s in SCOPES:
+                alone, _ = t.read(s, tr)
+                mixed, _ = b.read(s, tr)
+                assert np.array_equal(alone, mixed), "trace %d scope %d" % (tr, s)
+
+
+def test_graph_replay(c1):
+    """Captured once, replayed with eager GPU work and synchronisations in between; every replay exact."""
+    import torch
+
+    from paper_2504_03683_amd import tally as T
+    c, o = c1
+    recs = [(key, torch.from_numpy(np.ascontiguousarray(rec)).cuda(), None) for key, rec, _ in c.subs]
+    with T.Tally(c.fmt, c.n_fns, c.n_kid, max_depth=c.max_depth, max_threads=4096, max_streams=1024,
+                 flags=T.DEVICE_INPUT | T.GRAPH) as t:
+        for it in range(4):
+            say("case: graph replay %d" % it)
+            t.reset()
+            for key, r, _ in recs:
+                t.submit(key, r)
+            t.flush(final=True)
+            g = {s: t.read(s)[0] for s in SCOPES}
+            g["stats"] = t.read(1)[1]
+            assert_same(g, o)
+            x = torch.randn(512, 512, device="cuda")
+            (x @ x).sum().item()
+            torch.cuda.synchronize()
+
+
+def test_autotune_and_cache(c3, tmp_path):
+    from paper_2504_03683_amd import tally as T
+    c, o = c3
+    cache = str(tmp_path / "tune.txt")
+    say("case: autotune on the batched subset")
+    with T.Tally(c.fmt, c.n_fns, c.n_kid, max_depth=c.max_depth, max_threads=65536, max_streams=4096,
+                 autotune_cache=cache) as t:
+        for key, rec, pay in c.subs:
+            t.submit(key, rec, pay)
+        chosen = t.autotune(reps=1)
+        assert chosen[0] in (1024, 2048) and chosen[1] in (1024, 2048) and chosen[2] in (1, 2, 4)
+        t.flush(final=True)
+        g = {s: t.read(s)[0] for s in SCOPES}
+        g["stats"] = t.read(1)[1]
+        assert_same(g, o)
+        assert t._lib.thapi_tally_autotune(t._h, 1, None) == T.E_STATE   # after a flush: refused
+    lines = open(cache).read().split("\n")
+    assert len([x for x in lines if x.strip()]) == 1
+    key, tt, ee, rr = lines[0].split()
+    assert (int(tt), int(ee), int(rr)) == tuple(chosen)
+    say("case: cached shape reused by a new handle")
+    g = run_gpu(c, max_threads=65536, max_streams=4096)
+    assert_same(g, o)
+    with T.Tally(c.fmt, c.n_fns, c.n_kid, max_depth=c.max_depth, max_threads=65536, max_streams=4096,
+                 autotune_cache=cache) as t:
+        for key, rec, pay in c.subs:
+            t.submit(key, rec, pay)
+        t.flush(final=True)
+        g = {s: t.read(s)[0] for s in SCOPES}
+        g["stats"] = t.read(1)[1]
+        assert_same(g, o)
+    assert os.path.exists(cache)

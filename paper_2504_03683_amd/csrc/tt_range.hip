@@ -66,6 +66,7 @@ struct RangeLds {
   uint32_t *newtid, *newbucket;
   uint32_t *misc;   // [0] nslots, [1] new ids
   uint32_t *cnt;    // [ST_N] range-local counters
+  uint32_t nd;      // slots of the direct-mapped tally region (direct_slots), set once per launch
   uint32_t *wsum;   // [RNW] per-wave payload sums
 };
 
@@ -240,48 +241,54 @@ __host__ __device__ inline uint32_t direct_slots(uint32_t n_fns, uint32_t E) {
 }
 
 // Adds one completed call to the (slot, fn) entry of the LDS tally.
-// Durations that do not fit 32 bits update the global min/max directly; a
-// key that finds no room goes to the global tally with atomics.
+// Durations that do not
+// fit 32 bits update the global min/max directly; a key that finds no room
+// goes to the global tally with atomics.
 template <int FMT>
 __device__ inline void tally_call(const RangeLds &L, uint32_t E, const Tables &tb, uint32_t slot, uint32_t gslot,
                                   uint32_t fn, uint64_t incl, uint64_t self, uint64_t bytes) {
   if (fn >= tb.n_fns || slot >= (uint32_t)S_MAX) return;
-  const uint32_t nd = direct_slots(tb.n_fns, E);
-  const uint32_t d0 = nd * tb.n_fns;
+  const uint32_t nd = L.nd;
   uint32_t h = 0;
   bool found = false;
   if (slot < nd) {
     h = slot * tb.n_fns + fn;
     found = true;
-  } else if (E > d0) {
-    const uint32_t key = (slot << 16) | fn;
-    const uint32_t span = E - d0;
-    h = d0 + hash32(key) % span;
-    for (uint32_t probe = 0; probe < span; probe++) {
-      const uint32_t k = L.t_key[h];
-      if (k == key) { found = true; break; }
-      if (k == EMPTY32) {
-        const uint32_t old = atomicCAS(&L.t_key[h], EMPTY32, key);
-        if (old == EMPTY32 || old == key) { found = true; break; }
+  } else {
+    const uint32_t d0 = nd * tb.n_fns;
+    if (E > d0) {
+      const uint32_t key = (slot << 16) | fn;
+      const uint32_t span = E - d0;
+      h = d0 + hash32(key) % span;
+      for (uint32_t probe = 0; probe < span; probe++) {
+        const uint32_t k = L.t_key[h];
+        if (k == key) { found = true; break; }
+        if (k == EMPTY32) {
+          const uint32_t old = atomicCAS(&L.t_key[h], EMPTY32, key);
+          if (old == EMPTY32 || old == key) { found = true; break; }
+        }
+        h = h + 1 < E ? h + 1 : d0;
       }
-      h = h + 1 < E ? h + 1 : d0;
     }
   }
-  Tally *g = gslot < tb.max_threads ? &tb.tally[(size_t)gslot * tb.n_fns + fn] : nullptr;
   if (found) {
     lds_add32(&L.t_cnt[h], 1u);
     lds_add64(&L.t_isum[h], incl);
     lds_add64(&L.t_ssum[h], self);
     if (FMT == 2 && bytes) lds_add64(&L.t_bsum[h], bytes);
     if (incl < EMPTY32) { lds_min32(&L.t_imin[h], (uint32_t)incl); lds_max32(&L.t_imax[h], (uint32_t)incl); }
-    else if (g) { g_min64(&g->incl_min, incl); g_max64(&g->incl_max, incl); }
     if (self < EMPTY32) { lds_min32(&L.t_smin[h], (uint32_t)self); lds_max32(&L.t_smax[h], (uint32_t)self); }
-    else if (g) { g_min64(&g->self_min, self); g_max64(&g->self_max, self); }
-  } else if (g) {
-    g_add64(&g->count, 1);
-    g_add64(&g->incl_sum, incl); g_min64(&g->incl_min, incl); g_max64(&g->incl_max, incl);
-    g_add64(&g->self_sum, self); g_min64(&g->self_min, self); g_max64(&g->self_max, self);
-    if (bytes) g_add64(&g->bytes_sum, bytes);
+  }
+  if ((!found || incl >= EMPTY32 || self >= EMPTY32) && gslot < tb.max_threads) {
+    Tally *g = &tb.tally[(size_t)gslot * tb.n_fns + fn];
+    if (!found) {
+      g_add64(&g->count, 1);
+      g_add64(&g->incl_sum, incl);
+      g_add64(&g->self_sum, self);
+      if (bytes) g_add64(&g->bytes_sum, bytes);
+    }
+    if (!found || incl >= EMPTY32) { g_min64(&g->incl_min, incl); g_max64(&g->incl_max, incl); }
+    if (!found || self >= EMPTY32) { g_min64(&g->self_min, self); g_max64(&g->self_max, self); }
   }
 }
 
@@ -292,7 +299,6 @@ __device__ inline void wave_lds_fence() {
 }
 
 // ------------------------------------------------------------------ window
-struct Counters { uint32_t c[ST_N]; };
 
 // DPP lane moves (gfx9 encodings): row_shr:k = 0x110 + k, wave_shr:1 = 0x138,
 // row_bcast:15 = 0x142, row_bcast:31 = 0x143.  Lanes whose source is out of
@@ -357,7 +363,7 @@ template <int FMT>
 __device__ __forceinline__ void slot_window(RangeLds &L, const Tables &tb, const uint32_t E, const uint32_t D,
                                             const uint32_t s, const uint32_t gslot, const uint32_t a,
                                             const uint32_t nw, SlotState &S, UItem *__restrict__ us,
-                                            Counters &C, uint64_t *__restrict__ wch, uint64_t *__restrict__ wvt) {
+                                            uint64_t *__restrict__ wch, uint64_t *__restrict__ wvt) {
   const uint32_t lane = __lane_id();
   const bool valid = lane < nw;
   const uint32_t p = a + (valid ? lane : 0);
@@ -373,7 +379,7 @@ __device__ __forceinline__ void slot_window(RangeLds &L, const Tables &tb, const
     const uint32_t plo = (uint32_t)dpp<0x138>((int32_t)(uint32_t)S.last, (int32_t)(uint32_t)ts);
     const uint32_t phi = (uint32_t)dpp<0x138>((int32_t)(uint32_t)(S.last >> 32), (int32_t)(uint32_t)(ts >> 32));
     const uint64_t prev = ((uint64_t)phi << 32) | plo;
-    if (valid && (lane > 0 || (S.flags & RF_HAS_TS)) && ts < prev) C.c[ST_TSREG]++;
+    if (valid && (lane > 0 || (S.flags & RF_HAS_TS)) && ts < prev) lds_add32(&L.cnt[ST_TSREG], 1u);
     if (!(S.flags & RF_HAS_TS)) S.first = uread64(ts, 0);
     S.last = uread64(ts, nw - 1);
     S.flags |= RF_HAS_TS;
@@ -441,8 +447,8 @@ __device__ __forceinline__ void slot_window(RangeLds &L, const Tables &tb, const
   bool ok = false;
   uint64_t incl = 0;
   if (kind == 1 || kind == 2) {
-    if (pfn != fn) C.c[ST_MISMATCH]++;
-    else if (ts < pts) C.c[ST_NEGDUR]++;
+    if (pfn != fn) lds_add32(&L.cnt[ST_MISMATCH], 1u);
+    else if (ts < pts) lds_add32(&L.cnt[ST_NEGDUR], 1u);
     else { ok = true; incl = ts - pts; }
   }
   wave_lds_fence();
@@ -467,7 +473,7 @@ __device__ __forceinline__ void slot_window(RangeLds &L, const Tables &tb, const
     const uint64_t ch = kind == 1 ? wch[partner] : L.c_ch[s * D + cpos];
     uint64_t self;
     if (ch <= incl) self = incl - ch;
-    else { self = 0; C.c[ST_UNDER]++; }
+    else { self = 0; lds_add32(&L.cnt[ST_UNDER], 1u); }
     tally_call<FMT>(L, E, tb, s, gslot, fn, incl, self, pby);
   } else if (kind == 3) {
     const uint32_t vk = (uint32_t)(fl0 - lev);
@@ -476,7 +482,7 @@ __device__ __forceinline__ void slot_window(RangeLds &L, const Tables &tb, const
       UItem *u = &us[gi];
       u->ts = ts; u->child = wvt[vk]; u->fn = fn; u->pad = 0; u->pad2 = 0;
     } else {
-      C.c[ST_ORPHAN]++;  // deeper than any stack can be: certainly an orphan exit
+      lds_add32(&L.cnt[ST_ORPHAN], 1u);  // deeper than any stack can be: certainly an orphan exit
     }
   }
   wave_lds_fence();
@@ -505,7 +511,7 @@ __device__ __forceinline__ void slot_window(RangeLds &L, const Tables &tb, const
 template <int FMT>
 __device__ __forceinline__ void slot_walk(RangeLds &L, const Tables &tb, const uint32_t E, const uint32_t D,
                                           const uint32_t s, const uint32_t b, const uint32_t e, const size_t sbase,
-                                          UItem *__restrict__ ru, Counters &C, uint64_t *__restrict__ wch,
+                                          UItem *__restrict__ ru, uint64_t *__restrict__ wch,
                                           uint64_t *__restrict__ wvt) {
   SlotState S;
   S.d = __builtin_amdgcn_readfirstlane(L.s_d[s]);
@@ -519,7 +525,7 @@ __device__ __forceinline__ void slot_walk(RangeLds &L, const Tables &tb, const u
   const uint32_t gslot = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)L.s_gslot[s]);
   UItem *us = ru + (sbase + s) * D;
   for (uint32_t a = b; a < e; a += WAVE)
-    slot_window<FMT>(L, tb, E, D, s, gslot, a, (e - a) < WAVE ? (e - a) : WAVE, S, us, C, wch, wvt);
+    slot_window<FMT>(L, tb, E, D, s, gslot, a, (e - a) < WAVE ? (e - a) : WAVE, S, us, wch, wvt);
   if (__lane_id() == 0) {
     L.s_d[s] = S.d; L.s_u[s] = -S.fl; L.s_H[s] = S.H; L.s_M[s] = S.M; L.s_flags[s] = S.flags;
     L.s_facc[s] = S.facc; L.s_first[s] = S.first; L.s_last[s] = S.last;
@@ -535,8 +541,7 @@ __device__ __forceinline__ void tile_pass(RangeLds &L, const Tables &tb, const u
                                           const uint64_t last_rec, const uint64_t t0, const uint64_t (&cur0)[ROWS],
                                           const uint64_t (&cur1)[ROWS], const uint64_t (&cur2)[ROWS],
                                           uint64_t (&nxt0)[ROWS], uint64_t (&nxt1)[ROWS], uint64_t (&nxt2)[ROWS],
-                                          uint64_t &pay_run, const size_t sbase, UItem *__restrict__ ru,
-                                          Counters &C) {
+                                          uint64_t &pay_run, const size_t sbase, UItem *__restrict__ ru) {
   constexpr uint32_t T = ROWS * RWG;
   constexpr uint32_t RS = FMT == 2 ? 16 : 24;
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid >> 6;
@@ -629,11 +634,18 @@ __device__ __forceinline__ void tile_pass(RangeLds &L, const Tables &tb, const u
         n_bad++;
       }
     }
-    C.c[ST_ENTRIES] += n_ent;
-    C.c[ST_EXITS] += n_exi;
-    C.c[ST_KERNEL] += n_kern;
-    C.c[ST_BAD] += n_bad;
-    if (tid == 0) C.c[ST_RECORDS] += n;
+    // per-wave totals of the tile's counts, one LDS add each
+    {
+      const uint32_t e1 = wave_incl_scan(n_ent), e2 = wave_incl_scan(n_exi);
+      const uint32_t e3 = wave_incl_scan(n_kern), e4 = wave_incl_scan(n_bad);
+      if (lane == WAVE - 1) {
+        if (e1) lds_add32(&L.cnt[ST_ENTRIES], e1);
+        if (e2) lds_add32(&L.cnt[ST_EXITS], e2);
+        if (e3) lds_add32(&L.cnt[ST_KERNEL], e3);
+        if (e4) lds_add32(&L.cnt[ST_BAD], e4);
+      }
+      if (tid == 0) lds_add32(&L.cnt[ST_RECORDS], n);
+    }
     // ---- P3. thread id -> local slot
     // bucket word: bit 63 occupied, bit 62 pending, [32,40) slot, [0,32) tid.
     // A lane that finds no bucket for its tid claims one as pending and lists
@@ -746,7 +758,7 @@ __device__ __forceinline__ void tile_pass(RangeLds &L, const Tables &tb, const u
     // ---- P5. windows: wavefront w walks slots w, w + RNW, ... in order
     for (uint32_t s = (uint32_t)w; s < nslots; s += RNW) {
       const uint32_t b = L.soff[s], e = L.soff[s + 1];
-      if (b < e) slot_walk<FMT>(L, tb, E, D, s, b, e, sbase, ru, C, L.w_ch + w * WAVE, L.w_vt + w * (D + 1));
+      if (b < e) slot_walk<FMT>(L, tb, E, D, s, b, e, sbase, ru, L.w_ch + w * WAVE, L.w_vt + w * (D + 1));
     }
     __syncthreads();
 }
@@ -798,17 +810,13 @@ __device__ __forceinline__ void range_body(RangeLds &L, const Seg *__restrict__ 
     a1[r] = __builtin_nontemporal_load(p + 1);
     a2[r] = FMT == 1 ? __builtin_nontemporal_load(p + 2) : 0;
   }
-  Counters C;
 #pragma unroll
-  for (int k = 0; k < ST_N; k++) C.c[k] = 0;
+
   for (uint64_t t0 = 0; t0 < rg.n; t0 += T) {
-    tile_pass<FMT, ROWS>(L, tb, E, KL, D, rg, sg, grec, last_rec, t0, a0, a1, a2, b0, b1, b2, pay_run, sbase, ru, C);
+    tile_pass<FMT, ROWS>(L, tb, E, KL, D, rg, sg, grec, last_rec, t0, a0, a1, a2, b0, b1, b2, pay_run, sbase, ru);
 #pragma unroll
     for (int r = 0; r < ROWS; r++) { a0[r] = b0[r]; a1[r] = b1[r]; a2[r] = b2[r]; }
   }
-#pragma unroll
-  for (int k = 0; k < ST_N; k++)
-    if (C.c[k]) lds_add32(&L.cnt[k], C.c[k]);
   __syncthreads();
 
   // ---- range end: summaries, tally and counter flush
@@ -837,7 +845,7 @@ __device__ __forceinline__ void range_body(RangeLds &L, const Seg *__restrict__ 
       o->pad = 0;
     }
   }
-  const uint32_t nd = direct_slots(tb.n_fns, E), d0 = nd * tb.n_fns;
+  const uint32_t nd = L.nd, d0 = nd * tb.n_fns;
   for (uint32_t i = tid; i < E; i += RWG) {
     uint32_t s, fn;
     if (i < d0) {
@@ -887,6 +895,7 @@ __global__ __launch_bounds__(RWG) void k_range(const Seg *__restrict__ segs, con
   __shared__ uint32_t next;
   RangeLds L;
   range_lds_layout<true>(smem, &L, ROWS * RWG, sh.E, sh.KL, tb.D, FMT);
+  L.nd = direct_slots(tb.n_fns, sh.E);
   for (;;) {
     if (threadIdx.x == 0) next = atomicAdd(qhead, 1u);
     __syncthreads();

@@ -79,7 +79,6 @@ def run_gpu(c: Case, device_input=False, max_threads=4096, max_streams=1024, ext
 
     from paper_2504_03683_amd import tally as T
     flags = extra_flags | (T.DEVICE_INPUT if device_input else 0)
-    out = {}
     with T.Tally(c.fmt, c.n_fns, c.n_kid, max_depth=c.max_depth, max_threads=max_threads,
                  max_streams=max_streams, flags=flags, has_size=c.has_size) as t:
         keep = []
@@ -94,15 +93,22 @@ def run_gpu(c: Case, device_input=False, max_threads=4096, max_streams=1024, ext
             if i in c.flush_after:
                 t.flush()
         t.flush(final=c.final)
-        for s in SCOPES:
-            out[s], st = t.read(s)
-        out["stats"] = st
-        traces = sorted({k[0] for k, _, _ in c.subs})
-        if len(traces) > 1:
-            t0 = traces[len(traces) // 2]
-            r1, s1 = t.read(1, t0)
-            out["trace_rows"] = (t0, r1, s1)
+        out = read_out(t, c)
         out["timings"] = t.timings()
+    return out
+
+
+def read_out(t, c: Case):
+    """Every scope of a flushed handle, plus one trace's rows and stats when the case has several traces."""
+    out = {}
+    for s in SCOPES:
+        out[s], st = t.read(s)
+    out["stats"] = st
+    traces = sorted({k[0] for k, _, _ in c.subs})
+    if len(traces) > 1:
+        t0 = traces[len(traces) // 2]
+        r1, s1 = t.read(1, t0)
+        out["trace_rows"] = (t0, r1, s1)
     return out
 
 

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import synth
-from tests.parity import SCOPES, assert_same, case_from_workload, run_gpu, run_oracle, say
+from tests.parity import SCOPES, assert_same, case_from_workload, read_out, run_gpu, run_oracle, say
 
 pytestmark = pytest.mark.gpu
 
@@ -84,9 +84,7 @@ def test_graph_replay(c1):
             for key, r, _ in recs:
                 t.submit(key, r)
             t.flush(final=True)
-            g = {s: t.read(s)[0] for s in SCOPES}
-            g["stats"] = t.read(1)[1]
-            assert_same(g, o)
+            assert_same(read_out(t, c), o)
             x = torch.randn(512, 512, device="cuda")
             (x @ x).sum().item()
             torch.cuda.synchronize()
@@ -104,9 +102,7 @@ def test_autotune_and_cache(c3, tmp_path):
         chosen = t.autotune(reps=1)
         assert chosen[0] in (1024, 2048) and chosen[1] in (1024, 2048) and chosen[2] in (1, 2, 4)
         t.flush(final=True)
-        g = {s: t.read(s)[0] for s in SCOPES}
-        g["stats"] = t.read(1)[1]
-        assert_same(g, o)
+        assert_same(read_out(t, c), o)
         assert t._lib.thapi_tally_autotune(t._h, 1, None) == T.E_STATE   # after a flush: refused
     lines = open(cache).read().split("\n")
     assert len([x for x in lines if x.strip()]) == 1
@@ -120,7 +116,5 @@ def test_autotune_and_cache(c3, tmp_path):
         for key, rec, pay in c.subs:
             t.submit(key, rec, pay)
         t.flush(final=True)
-        g = {s: t.read(s)[0] for s in SCOPES}
-        g["stats"] = t.read(1)[1]
-        assert_same(g, o)
+        assert_same(read_out(t, c), o)
     assert os.path.exists(cache)

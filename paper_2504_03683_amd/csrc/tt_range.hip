@@ -66,7 +66,7 @@ struct RangeLds {
   uint32_t *newtid, *newbucket;
   uint32_t *misc;   // [0] nslots, [1] new ids
   uint32_t *cnt;    // [ST_N] range-local counters
-  uint32_t nd;      // slots of the direct-mapped tally region (direct_slots), set once per launch
+  uint32_t nd;      // slots of the direct-mapped tally region, chosen per range at its first tile
   uint32_t *wsum;   // [RNW] per-wave payload sums
 };
 
@@ -232,13 +232,17 @@ __device__ uint32_t resolve_gslot(const Tables &tb, uint32_t stream, uint32_t ti
   return result;
 }
 
-// LDS tally layout: the first `direct_slots(n_fns, E) * n_fns` entries are
-// indexed directly by slot * n_fns + fn (no probing); the rest is an
-// open-addressing hash keyed (slot << 16 | fn) for slots beyond that.
+// LDS tally layout: the first nd * n_fns entries are indexed directly by
+// slot * n_fns + fn (no probing); the rest is an open-addressing hash keyed
+// (slot << 16 | fn) for slots beyond that.  nd is direct_slots(n_fns, E), or
+// 0 for a range whose first tile already has more threads than that.
 __host__ __device__ inline uint32_t direct_slots(uint32_t n_fns, uint32_t E) {
   const uint32_t d = n_fns <= E ? E / n_fns : 0;
   return d < (uint32_t)S_MAX ? d : (uint32_t)S_MAX;
 }
+
+// Probes of the LDS tally hash before a key falls back to the global tally.
+constexpr uint32_t TALLY_PROBES = 16;
 
 // Adds one completed call to the (slot, fn) entry of the LDS tally.
 // Durations that do not
@@ -259,8 +263,9 @@ __device__ inline void tally_call(const RangeLds &L, uint32_t E, const Tables &t
     if (E > d0) {
       const uint32_t key = (slot << 16) | fn;
       const uint32_t span = E - d0;
-      h = d0 + hash32(key) % span;
-      for (uint32_t probe = 0; probe < span; probe++) {
+      h = d0 + (d0 ? hash32(key) % span : hash32(key) & (E - 1));   // (E is a power of two)
+      const uint32_t probes = span < TALLY_PROBES ? span : TALLY_PROBES;
+      for (uint32_t probe = 0; probe < probes; probe++) {
         const uint32_t k = L.t_key[h];
         if (k == key) { found = true; break; }
         if (k == EMPTY32) {
@@ -712,6 +717,13 @@ __device__ __forceinline__ void tile_pass(RangeLds &L, const Tables &tb, const u
       __syncthreads();
     }
     const uint32_t nslots = L.misc[0];
+    // the tally layout of this range, fixed before its first call is tallied:
+    // direct-mapped rows for every thread when the first tile's threads all
+    // fit, otherwise one open-addressing table over all entries
+    if (t0 == 0) {
+      const uint32_t dcap = direct_slots(tb.n_fns, E);
+      L.nd = nslots <= dcap ? dcap : 0;
+    }
     // ---- P4. stable sort of the API records by slot
     uint32_t nbits = 0;
     while ((1u << nbits) < nslots) nbits++;
@@ -895,7 +907,6 @@ __global__ __launch_bounds__(RWG) void k_range(const Seg *__restrict__ segs, con
   __shared__ uint32_t next;
   RangeLds L;
   range_lds_layout<true>(smem, &L, ROWS * RWG, sh.E, sh.KL, tb.D, FMT);
-  L.nd = direct_slots(tb.n_fns, sh.E);
   for (;;) {
     if (threadIdx.x == 0) next = atomicAdd(qhead, 1u);
     __syncthreads();

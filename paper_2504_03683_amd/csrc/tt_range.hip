@@ -62,7 +62,7 @@ struct RangeLds {
   uint64_t *q_sum;
   // thread map and sort
   uint64_t *tidmap;
-  uint32_t *wcnt, *wbase, *soff;
+  uint32_t *wcnt, *soff;
   uint32_t *newtid, *newbucket;
   uint32_t *misc;   // [0] nslots, [1] new ids
   uint32_t *cnt;    // [ST_N] range-local counters
@@ -121,7 +121,6 @@ __host__ __device__ inline size_t range_lds_layout(uint8_t *base, RangeLds *L, u
   TAKE(q_sum, uint64_t, KL);
   TAKE(tidmap, uint64_t, TIDMAP);
   TAKE(wcnt, uint32_t, RNW * S_MAX);
-  TAKE(wbase, uint32_t, RNW * S_MAX);
   TAKE(soff, uint32_t, S_MAX + 1);
   TAKE(newtid, uint32_t, TIDMAP);
   TAKE(newbucket, uint32_t, TIDMAP);
@@ -364,17 +363,16 @@ struct SlotState {
 // carried stack (level above the floor), else it closes a call opened before
 // the range (level at or below the floor); its parent is found the same way
 // one level down.
+// The lane's record (ts, fk, by) was loaded by the caller ahead of time.
+// wvt[0] holds the children time of the call at the floor across windows.
 template <int FMT>
 __device__ __forceinline__ void slot_window(RangeLds &L, const Tables &tb, const uint32_t E, const uint32_t D,
                                             const uint32_t s, const uint32_t gslot, const uint32_t a,
-                                            const uint32_t nw, SlotState &S, UItem *__restrict__ us,
+                                            const uint32_t nw, const uint64_t ts, const uint32_t fk,
+                                            const uint64_t by, SlotState &S, UItem *__restrict__ us,
                                             uint64_t *__restrict__ wch, uint64_t *__restrict__ wvt) {
   const uint32_t lane = __lane_id();
   const bool valid = lane < nw;
-  const uint32_t p = a + (valid ? lane : 0);
-  const uint64_t ts = L.tile_ts[p];
-  const uint32_t fk = L.tile_fk[p];
-  const uint64_t by = FMT == 2 ? L.tile_by[p] : 0;
   const uint32_t fn = fk & 0xFFFFu;
   const bool ex = valid && (fk & FK_EXIT);
   const bool en = valid && !(fk & FK_EXIT);
@@ -423,7 +421,7 @@ __device__ __forceinline__ void slot_window(RangeLds &L, const Tables &tb, const
   const int32_t parent = (ex && k > 0) ? msb64(Epar & lt) : -1;
   const bool open_at_end = en && lev <= d_end && msb64(Elev) == (int32_t)lane;
   wch[lane] = 0;
-  if (lane <= D) wvt[lane] = lane == 0 ? S.facc : 0;
+  if (lane >= 1 && lane <= D) wvt[lane] = 0;
   // the entry each exit closes: in the window, on the carried stack, or opened before the range
   int kind = 0;  // 1 window, 2 carried, 3 opened before the range, 4 beyond the stack capacity
   uint32_t cpos = 0;
@@ -501,11 +499,10 @@ __device__ __forceinline__ void slot_window(RangeLds &L, const Tables &tb, const
     }
   }
   if (__ballot(open_at_end && (uint32_t)(lev - fl1 - 1) >= D)) S.flags |= RF_OVERFLOW;
-  {
+  if (fl1 < fl0 && lane == 0) {
+    // the floor moved down: its call's children time is that of the level reached
     const uint32_t dv = (uint32_t)(fl0 - fl1);
-    uint64_t nf = 0;
-    if (dv == 0 || (dv <= D && (uint32_t)u0 + dv < D)) nf = wvt[dv];
-    S.facc = uread64(nf, 0);
+    wvt[0] = (dv <= D && (uint32_t)u0 + dv < D) ? wvt[dv] : 0;
   }
   S.d = d_end;
   S.fl = fl1;
@@ -529,11 +526,24 @@ __device__ __forceinline__ void slot_walk(RangeLds &L, const Tables &tb, const u
   S.last = uread64(L.s_last[s], 0);
   const uint32_t gslot = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)L.s_gslot[s]);
   UItem *us = ru + (sbase + s) * D;
-  for (uint32_t a = b; a < e; a += WAVE)
-    slot_window<FMT>(L, tb, E, D, s, gslot, a, (e - a) < WAVE ? (e - a) : WAVE, S, us, wch, wvt);
-  if (__lane_id() == 0) {
+  const uint32_t lane = __lane_id();
+  if (lane == 0) wvt[0] = S.facc;
+  // each window's records are loaded one window ahead (the sorted tile does
+  // not change during the walk)
+  uint32_t p = b + (lane < e - b ? lane : 0);
+  uint64_t ts = L.tile_ts[p], by = FMT == 2 ? L.tile_by[p] : 0;
+  uint32_t fk = L.tile_fk[p];
+  for (uint32_t a = b; a < e; a += WAVE) {
+    const uint32_t an = a + WAVE;
+    p = an < e ? an + (lane < e - an ? lane : 0) : b;
+    const uint64_t ts_n = L.tile_ts[p], by_n = FMT == 2 ? L.tile_by[p] : 0;
+    const uint32_t fk_n = L.tile_fk[p];
+    slot_window<FMT>(L, tb, E, D, s, gslot, a, (e - a) < WAVE ? (e - a) : WAVE, ts, fk, by, S, us, wch, wvt);
+    ts = ts_n; fk = fk_n; by = by_n;
+  }
+  if (lane == 0) {
     L.s_d[s] = S.d; L.s_u[s] = -S.fl; L.s_H[s] = S.H; L.s_M[s] = S.M; L.s_flags[s] = S.flags;
-    L.s_facc[s] = S.facc; L.s_first[s] = S.first; L.s_last[s] = S.last;
+    L.s_facc[s] = wvt[0]; L.s_first[s] = S.first; L.s_last[s] = S.last;
   }
 }
 
@@ -745,23 +755,29 @@ __device__ __forceinline__ void tile_pass(RangeLds &L, const Tables &tb, const u
       if (valid && rk == 0) L.wcnt[w * S_MAX + s] = base + c;
     }
     __syncthreads();
-    if (w == 0) {
-      uint32_t tot = 0;
+    // each wave: lane s counts slot s over all waves and over the waves before
+    // this one, so every wave knows where its records of each slot go
+    uint32_t wb;
+    {
+      uint32_t tot = 0, before = 0;
       if ((uint32_t)lane < nslots)
-        for (int k = 0; k < RNW; k++) tot += L.wcnt[k * S_MAX + lane];
+        for (int k = 0; k < RNW; k++) {
+          const uint32_t c = L.wcnt[k * S_MAX + lane];
+          tot += c;
+          before += k < w ? c : 0;
+        }
       const uint32_t inc = wave_incl_scan(tot);
-      if ((uint32_t)lane < nslots) {
-        uint32_t acc = inc - tot;
-        L.soff[lane] = acc;
-        for (int k = 0; k < RNW; k++) { L.wbase[k * S_MAX + lane] = acc; acc += L.wcnt[k * S_MAX + lane]; }
+      wb = inc - tot + before;
+      if (w == 0) {
+        if ((uint32_t)lane < nslots) L.soff[lane] = inc - tot;
+        if (lane == WAVE - 1) L.soff[nslots] = inc;
       }
-      if (lane == WAVE - 1) L.soff[nslots] = inc;
     }
-    __syncthreads();
 #pragma unroll
     for (int r = 0; r < ROWS; r++) {
+      const uint32_t sl = r_slot[r] == EMPTY32 ? 0u : r_slot[r];
+      const uint32_t pos = (uint32_t)__builtin_amdgcn_ds_bpermute((int32_t)(sl << 2), (int32_t)wb) + r_rank[r];
       if (r_slot[r] == EMPTY32) continue;
-      const uint32_t pos = L.wbase[w * S_MAX + r_slot[r]] + r_rank[r];
       L.tile_ts[pos] = r_ts[r];
       L.tile_fk[pos] = (r_fk[r] & 0xFFFFu) | (((r_fk[r] >> 16) & 1u) << 16);
       if (FMT == 2) L.tile_by[pos] = r_by[r];

@@ -261,7 +261,7 @@ def bench_batched(args):
     submit_all(tb)
     tz = time.perf_counter()
     chosen = tb.autotune(reps=2)
-    log("autotune: T=%d E=%d ranges/CU=%d (%.1fs)" % (chosen + (time.perf_counter() - tz,)))
+    log("autotune: T=%d E=%d ranges/CU=%d pipelined=%d (%.1fs)" % (chosen + (time.perf_counter() - tz,)))
     tb.flush(final=True)
     tb.reset()
 
@@ -327,7 +327,8 @@ def bench_batched(args):
         "records": n_rec, "input_bytes": w.record_bytes, "format": "FIXED24", "traces": len(w.streams)})
     out["batched_vs_per_trace"] = {"batched_ms": ms_b, "per_trace_ms": ms_p, "speedup": ms_p / ms_b,
                                    "per_trace_events_per_s": n_rec / (ms_p * 1e-3),
-                                   "autotuned": {"T": chosen[0], "E": chosen[1], "ranges_per_cu": chosen[2]},
+                                   "autotuned": {"T": chosen[0], "E": chosen[1], "ranges_per_cu": chosen[2],
+                                                 "pipelined": chosen[3]},
                                    "graph": True}
     out["cpu_baseline"] = cpu
     out["parity"] = parity

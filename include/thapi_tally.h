@@ -186,17 +186,19 @@ int thapi_tally_read(thapi_tally *t, uint32_t scope, uint32_t trace_id,
 int thapi_tally_reset(thapi_tally *t);
 
 /* Batched form: times the pipeline on the chunks queued right now under each
- * candidate launch shape -- records per tile (1024, 2048), LDS tally entries
- * (2048, 1024) and work-list ranges per CU (1, 2, 4) -- and keeps the fastest
+ * candidate launch shape -- records in the LDS tile region (1024, 2048), LDS
+ * tally entries (2048, 1024), work-list ranges per CU (1, 2, 4) and the wave
+ * schedule (0: all waves build a tile, then walk it; 1: half the waves build
+ * the next tile while the other half walks the previous one) -- and keeps the fastest
  * for this workload class (device, format, max_depth, and the log2 buckets of
  * n_fns, chunk count and record count).  The choice is used by every later
  * flush of that class and, when cfg.autotune_cache names a file, written
- * there as text lines "key T E rpc" and read back by later opens.  Each
+ * there as text lines "key T E rpc pipe" and read back by later opens.  Each
  * candidate runs reps + 1 times (the first one warms up; the minimum of the
  * rest counts).  The queued chunks stay queued and the tables are re-initialised
  * afterwards, so the handle must not have flushed since open/reset:
  * THAPI_E_STATE otherwise, or when nothing is queued.  chosen (may be NULL)
- * receives {T, E, rpc}.  Errors: THAPI_E_STATE, THAPI_E_CAPACITY (no candidate
+ * receives {T, E, rpc, pipe}.  Errors: THAPI_E_STATE, THAPI_E_CAPACITY (no candidate
  * could take the work), THAPI_E_DEVICE. */
 int thapi_tally_autotune(thapi_tally *t, uint32_t reps, uint32_t *chosen);
 

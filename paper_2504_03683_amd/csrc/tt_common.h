@@ -25,7 +25,7 @@ enum : int {
 };
 
 // Error bits raised by kernels (sticky per flush).
-enum : uint32_t { ERR_CAPACITY = 1u, ERR_RANGE_THREADS = 2u, ERR_DEPTH = 4u };
+enum : uint32_t { ERR_CAPACITY = 1u, ERR_RANGE_THREADS = 2u, ERR_DEPTH = 4u, ERR_PIPE = 8u };
 
 // One submitted chunk, as the kernels see it.
 struct Seg {
@@ -103,6 +103,7 @@ struct Shape {
   uint32_t KL;          // kernel ids pre-aggregated in LDS (<= KL_MAX)
   uint32_t lds_bytes;
   uint32_t rpc;         // ranges per CU the records are cut into (work-list length / CUs)
+  uint32_t pipe;        // 1: producer and walker waves overlap (tiles of T / 2 records)
 };
 
 __host__ __device__ inline uint32_t hash32(uint32_t x) {

@@ -134,7 +134,7 @@ struct thapi_tally {
   hipEvent_t ev[2 * TM_N] = {};
 
   std::string arch;                                   // gcnArchName of the device
-  std::map<std::string, std::array<uint32_t, 3>> tuned;  // autotuned {T, E, rpc} per workload class
+  std::map<std::string, std::array<uint32_t, 4>> tuned;  // autotuned {T, E, rpc, pipe} per workload class
   bool flushed_any = false;
   hipGraphExec_t gexec = nullptr;                     // THAPI_GRAPH: the captured pipeline
   std::array<uint64_t, 16> gsig{};
@@ -202,14 +202,15 @@ void free_all(thapi_tally *t) {
 
 // Picks the range kernel's tile and LDS tally size for the format and depth:
 // the largest tile and tally that fit the LDS, preferring a full tally (2048
-// entries) over a larger tile.  THAPI_TALLY_SHAPE="T,E[,rpc]" overrides the
-// choice (used to tune the launch shape).
+// entries) over a larger tile.  THAPI_TALLY_SHAPE="T,E[,rpc[,pipe]]"
+// overrides the choice (used to tune the launch shape).
 Shape pick_shape(const thapi_tally *t) {
   Shape s{};
   const uint32_t D = t->cfg.max_depth;
   const int fmt = (int)t->cfg.format;
   s.KL = std::min<uint32_t>(t->cfg.n_kernel_ids, KL_MAX);
   s.rpc = 1;
+  s.pipe = 1;   // producer and walker waves overlap (the faster schedule on the layered workload)
   auto fits = [&](uint32_t T, uint32_t E) {
     size_t b = range_lds_bytes(T, E, s.KL, D, fmt);
     if (b + 256 > t->lds_limit) return false;  // (plus the kernel's static LDS)
@@ -217,11 +218,12 @@ Shape pick_shape(const thapi_tally *t) {
     return true;
   };
   if (const char *env = getenv("THAPI_TALLY_SHAPE")) {
-    unsigned T = 0, E = 0, rpc = 1;
-    const int n = sscanf(env, "%u,%u,%u", &T, &E, &rpc);
+    unsigned T = 0, E = 0, rpc = 1, pipe = 1;
+    const int n = sscanf(env, "%u,%u,%u,%u", &T, &E, &rpc, &pipe);
     if (n >= 2 && (T == 1024 || T == 2048) && E >= 64 && (E & (E - 1)) == 0 && rpc >= 1 && rpc <= 64 &&
-        fits(T, E)) {
+        pipe <= 1 && fits(T, E)) {
       s.rpc = rpc;
+      s.pipe = pipe;
       return s;
     }
   }
@@ -698,8 +700,8 @@ hipError_t launch_pipeline(thapi_tally *t, const Plan &pl, const Shape &sh, bool
 hipError_t run_pipeline(thapi_tally *t, const Plan &pl, const Shape &sh, bool final) {
   const bool prof = (t->cfg.flags & THAPI_PROFILE) != 0;
   if (!(t->cfg.flags & THAPI_GRAPH)) return launch_pipeline(t, pl, sh, final, prof);
-  const std::array<uint64_t, 16> sig = {pl.ranges.size(), pl.segs.size(), pl.spans.size(), sh.T, sh.E, sh.rpc,
-                                        final ? 1u : 0u, (uint64_t)(uintptr_t)t->segs.p,
+  const std::array<uint64_t, 16> sig = {pl.ranges.size(), pl.segs.size(), pl.spans.size(), sh.T, sh.E,
+                                        sh.rpc | ((uint64_t)sh.pipe << 32), final ? 1u : 0u, (uint64_t)(uintptr_t)t->segs.p,
                                         (uint64_t)(uintptr_t)t->ranges.p, (uint64_t)(uintptr_t)t->order.p,
                                         (uint64_t)(uintptr_t)t->rhdr.p, (uint64_t)(uintptr_t)t->ru.p,
                                         (uint64_t)(uintptr_t)t->ro.p, (uint64_t)(uintptr_t)t->rnslots.p,
@@ -744,8 +746,8 @@ void load_tune_cache(thapi_tally *t) {
   FILE *f = fopen(t->cache_path.c_str(), "r");
   if (!f) return;
   char key[256];
-  unsigned T, E, rpc;
-  while (fscanf(f, "%255s %u %u %u", key, &T, &E, &rpc) == 4) t->tuned[key] = {T, E, rpc};
+  unsigned T, E, rpc, pipe;
+  while (fscanf(f, "%255s %u %u %u %u", key, &T, &E, &rpc, &pipe) == 5) t->tuned[key] = {T, E, rpc, pipe};
   fclose(f);
 }
 
@@ -753,7 +755,8 @@ void save_tune_cache(thapi_tally *t) {
   if (t->cache_path.empty()) return;
   FILE *f = fopen(t->cache_path.c_str(), "w");
   if (!f) return;
-  for (auto &kv : t->tuned) fprintf(f, "%s %u %u %u\n", kv.first.c_str(), kv.second[0], kv.second[1], kv.second[2]);
+  for (auto &kv : t->tuned)
+    fprintf(f, "%s %u %u %u %u\n", kv.first.c_str(), kv.second[0], kv.second[1], kv.second[2], kv.second[3]);
   fclose(f);
 }
 
@@ -767,6 +770,7 @@ Shape shape_for(thapi_tally *t, const std::vector<Chunk> &work) {
   if ((it->second[0] == 1024 || it->second[0] == 2048) && it->second[1] >= 64 && b + 256 <= t->lds_limit) {
     s.T = it->second[0]; s.E = it->second[1]; s.lds_bytes = (uint32_t)b;
     s.rpc = std::max<uint32_t>(1, std::min<uint32_t>(it->second[2], 64));
+    s.pipe = it->second[3] ? 1u : 0u;
   }
   return s;
 }
@@ -811,7 +815,8 @@ int process_batch(thapi_tally *t, std::vector<Chunk> &work, bool final) {
       else if (c.owned) { hipFree(c.owned); t->budget_used -= c.owned_bytes; }
     }
     t->cv.notify_all();
-    if (err & (ERR_CAPACITY | ERR_RANGE_THREADS)) { t->failed = THAPI_E_CAPACITY; rc = THAPI_E_CAPACITY; }
+    if (err & ERR_PIPE) { t->failed = THAPI_E_DEVICE; rc = THAPI_E_DEVICE; }
+    else if (err & (ERR_CAPACITY | ERR_RANGE_THREADS)) { t->failed = THAPI_E_CAPACITY; rc = THAPI_E_CAPACITY; }
     else if (err & ERR_DEPTH) { t->failed = THAPI_E_DEPTH; rc = THAPI_E_DEPTH; }
     if (final) t->finalized = true;
     t->flushed_any = true;
@@ -950,15 +955,16 @@ int thapi_tally_autotune(thapi_tally *t, uint32_t reps, uint32_t *chosen) {
   HIPCHK(hipEventCreate(&e1));
   float best_ms = -1;
   Shape best = t->shape;
-  const uint32_t Ts[] = {2048, 1024}, Es[] = {2048, 1024}, rpcs[] = {1, 2, 4};
+  const uint32_t Ts[] = {2048, 1024}, Es[] = {2048, 1024}, rpcs[] = {1, 2, 4}, pipes[] = {0, 1};
   int rc = THAPI_OK;
   for (uint32_t T : Ts)
     for (uint32_t E : Es)
-      for (uint32_t rpc : rpcs) {
+      for (uint32_t rpc : rpcs)
+      for (uint32_t pipe : pipes) {
         Shape sh = t->shape;
         const size_t b = range_lds_bytes(T, E, sh.KL, D, fmt);
         if (b + 256 > t->lds_limit) continue;
-        sh.T = T; sh.E = E; sh.rpc = rpc; sh.lds_bytes = (uint32_t)b;
+        sh.T = T; sh.E = E; sh.rpc = rpc; sh.pipe = pipe; sh.lds_bytes = (uint32_t)b;
         Plan pl;
         plan_work(t, work, sh, pl);
         float ms_min = -1;
@@ -986,9 +992,9 @@ int thapi_tally_autotune(thapi_tally *t, uint32_t reps, uint32_t *chosen) {
   if (rc != THAPI_OK) return rc;
   if (init_tables(t) != hipSuccess) return hip_fail(t, hipErrorUnknown);
   if (best_ms < 0) return THAPI_E_CAPACITY;
-  t->tuned[tune_key(t, work)] = {best.T, best.E, best.rpc};
+  t->tuned[tune_key(t, work)] = {best.T, best.E, best.rpc, best.pipe};
   save_tune_cache(t);
-  if (chosen) { chosen[0] = best.T; chosen[1] = best.E; chosen[2] = best.rpc; }
+  if (chosen) { chosen[0] = best.T; chosen[1] = best.E; chosen[2] = best.rpc; chosen[3] = best.pipe; }
   return THAPI_OK;
 }
 

@@ -45,6 +45,10 @@ struct RangeLds {
   uint64_t *tile_ts;   // tile sorted by slot: timestamp
   uint64_t *tile_by;   // VAR16 transfer size of entries
   uint32_t *tile_fk;   // fn | kind << 16
+  // the sorted tile the walk reads (the tile region itself, or one half of it
+  // when producer and walker waves alternate between two halves)
+  const uint64_t *cts, *cby;
+  const uint32_t *cfk;
   // thread slots
   uint32_t *s_gslot, *s_flags;
   int32_t *s_d, *s_u, *s_H, *s_M;   // depth relative to the range start, virtual closes, excursion
@@ -64,7 +68,7 @@ struct RangeLds {
   uint64_t *tidmap;
   uint32_t *wcnt, *soff;
   uint32_t *newtid, *newbucket;
-  uint32_t *misc;   // [0] nslots, [1] new ids
+  uint32_t *misc;   // [0] nslots, [1] new ids, [2] nd, [3..6] producer/walker sync, [7..8] nslots per half
   uint32_t *cnt;    // [ST_N] range-local counters
   uint32_t nd;      // slots of the direct-mapped tally region, chosen per range at its first tile
   uint32_t *wsum;   // [RNW] per-wave payload sums
@@ -121,10 +125,10 @@ __host__ __device__ inline size_t range_lds_layout(uint8_t *base, RangeLds *L, u
   TAKE(q_sum, uint64_t, KL);
   TAKE(tidmap, uint64_t, TIDMAP);
   TAKE(wcnt, uint32_t, RNW * S_MAX);
-  TAKE(soff, uint32_t, S_MAX + 1);
+  TAKE(soff, uint32_t, 2 * (S_MAX + 1));
   TAKE(newtid, uint32_t, TIDMAP);
   TAKE(newbucket, uint32_t, TIDMAP);
-  TAKE(misc, uint32_t, 8);
+  TAKE(misc, uint32_t, 16);
   TAKE(cnt, uint32_t, ST_N);
   TAKE(wsum, uint32_t, RNW);
 #undef TAKE
@@ -430,9 +434,9 @@ __device__ __forceinline__ void slot_window(RangeLds &L, const Tables &tb, const
   if (ex) {
     if (partner >= 0) {
       kind = 1;
-      pts = L.tile_ts[a + partner];
-      pfn = L.tile_fk[a + partner] & 0xFFFFu;
-      if (FMT == 2) pby = L.tile_by[a + partner];
+      pts = L.cts[a + partner];
+      pfn = L.cfk[a + partner] & 0xFFFFu;
+      if (FMT == 2) pby = L.cby[a + partner];
     } else if (lev > fl0) {
       cpos = (uint32_t)(lev - fl0 - 1);
       if (cpos < D) {
@@ -531,13 +535,13 @@ __device__ __forceinline__ void slot_walk(RangeLds &L, const Tables &tb, const u
   // each window's records are loaded one window ahead (the sorted tile does
   // not change during the walk)
   uint32_t p = b + (lane < e - b ? lane : 0);
-  uint64_t ts = L.tile_ts[p], by = FMT == 2 ? L.tile_by[p] : 0;
-  uint32_t fk = L.tile_fk[p];
+  uint64_t ts = L.cts[p], by = FMT == 2 ? L.cby[p] : 0;
+  uint32_t fk = L.cfk[p];
   for (uint32_t a = b; a < e; a += WAVE) {
     const uint32_t an = a + WAVE;
     p = an < e ? an + (lane < e - an ? lane : 0) : b;
-    const uint64_t ts_n = L.tile_ts[p], by_n = FMT == 2 ? L.tile_by[p] : 0;
-    const uint32_t fk_n = L.tile_fk[p];
+    const uint64_t ts_n = L.cts[p], by_n = FMT == 2 ? L.cby[p] : 0;
+    const uint32_t fk_n = L.cfk[p];
     slot_window<FMT>(L, tb, E, D, s, gslot, a, (e - a) < WAVE ? (e - a) : WAVE, ts, fk, by, S, us, wch, wvt);
     ts = ts_n; fk = fk_n; by = by_n;
   }
@@ -547,20 +551,75 @@ __device__ __forceinline__ void slot_walk(RangeLds &L, const Tables &tb, const u
   }
 }
 
+// ------------------------------------------------------------------ sync
+// Bounded waits between the wave groups of one workgroup (all resident on one
+// CU).  A wait that runs out raises ERR_PIPE and returns, so every wave always
+// reaches the end of the kernel; the host then reports a device error.
+constexpr uint32_t SPIN_LIMIT = 1u << 22;
+
+__device__ inline void wait_at_least(uint32_t *ctr, uint32_t v, uint32_t *err) {
+  if (__lane_id() == 0) {
+    uint32_t i = 0;
+    while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < v) {
+      __builtin_amdgcn_s_sleep(2);
+      if (++i == SPIN_LIMIT) { atomicOr(err, ERR_PIPE); break; }
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Barrier of `nw` waves: the counter only grows, by nw per episode.
+__device__ inline void group_barrier(uint32_t *ctr, uint32_t nw, uint32_t *err) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  if (__lane_id() == 0) {
+    const uint32_t old = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+    const uint32_t target = (old / nw + 1) * nw;
+    uint32_t i = 0;
+    while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < target) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++i == SPIN_LIMIT) { atomicOr(err, ERR_PIPE); break; }
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Makes this group's LDS writes visible, then (one lane) sets *ctr = v.
+__device__ inline void publish(uint32_t *ctr, uint32_t v, bool me) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  if (me) __hip_atomic_store(ctr, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // ------------------------------------------------------------------ tile
-// One tile of the range: decode `cur*`, prefetch the next tile into `nxt*`,
-// slot map and sort, then every wavefront walks the windows of its slots.
-template <int FMT, int ROWS>
-__device__ __forceinline__ void tile_pass(RangeLds &L, const Tables &tb, const uint32_t E, const uint32_t KL,
-                                          const uint32_t D, const Range &rg, const Seg &sg, gu64 *grec,
-                                          const uint64_t last_rec, const uint64_t t0, const uint64_t (&cur0)[ROWS],
-                                          const uint64_t (&cur1)[ROWS], const uint64_t (&cur2)[ROWS],
-                                          uint64_t (&nxt0)[ROWS], uint64_t (&nxt1)[ROWS], uint64_t (&nxt2)[ROWS],
-                                          uint64_t &pay_run, const size_t sbase, UItem *__restrict__ ru) {
-  constexpr uint32_t T = ROWS * RWG;
+// Front half of one tile: decode `cur*`, prefetch the next tile into `nxt*`,
+// kernel records, slot map and stable sort into half `hb` of the tile region
+// (the whole region when PIPE is off).  With PIPE the producer group (the
+// upper RNW / 2 waves) runs it alone and synchronises through group barriers;
+// otherwise the whole workgroup runs it between workgroup barriers.
+template <int FMT, int ROWS, bool PIPE>
+__device__ __forceinline__ void front_tile(RangeLds &L, const Tables &tb, const uint32_t E, const uint32_t KL,
+                                           const uint32_t D, const Range &rg, const Seg &sg, gu64 *grec,
+                                           const uint64_t last_rec, const uint64_t t0, const uint32_t hb,
+                                           const uint64_t (&cur0)[ROWS], const uint64_t (&cur1)[ROWS],
+                                           const uint64_t (&cur2)[ROWS], uint64_t (&nxt0)[ROWS],
+                                           uint64_t (&nxt1)[ROWS], uint64_t (&nxt2)[ROWS], uint64_t &pay_run) {
+  constexpr uint32_t GW = PIPE ? RNW / 2 : RNW;     // waves of the group
+  constexpr uint32_t T = ROWS * GW * WAVE;          // records per tile
   constexpr uint32_t RS = FMT == 2 ? 16 : 24;
-  const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid >> 6;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int w = (int)(threadIdx.x >> 6) - (PIPE ? (int)(RNW / 2) : 0);   // wave within the group
+  const int tid = w * WAVE + lane;                                       // lane within the group
   const uint32_t n = (uint32_t)((rg.n - t0) < T ? (rg.n - t0) : T);
+  uint64_t *const tts = L.tile_ts + hb * T;
+  uint32_t *const tfk = L.tile_fk + hb * T;
+  uint64_t *const tby = L.tile_by + hb * T;
+  uint32_t *const soff = L.soff + hb * (S_MAX + 1);
+  auto gbar = [&]() {
+    if (PIPE) group_barrier(&L.misc[3], GW, tb.err);
+    else __syncthreads();
+  };
     uint64_t r_ts[ROWS], r_x[ROWS], r_by[ROWS];
     uint32_t r_tid[ROWS], r_fk[ROWS], r_slot[ROWS], r_rank[ROWS];
     // ---- P1. decode, then prefetch the next tile
@@ -574,7 +633,7 @@ __device__ __forceinline__ void tile_pass(RangeLds &L, const Tables &tb, const u
     }
 #pragma unroll
     for (int r = 0; r < ROWS; r++) {
-      const uint32_t li = (uint32_t)w * (T / RNW) + (uint32_t)r * WAVE + lane;
+      const uint32_t li = (uint32_t)w * (T / GW) + (uint32_t)r * WAVE + lane;
       uint64_t idx = rg.begin + t0 + T + li;
       idx = idx < last_rec ? idx : last_rec;
       gu64 *p = grec + idx * (RS / 8);
@@ -588,19 +647,19 @@ __device__ __forceinline__ void tile_pass(RangeLds &L, const Tables &tb, const u
       uint32_t excl[ROWS];
 #pragma unroll
       for (int r = 0; r < ROWS; r++) {
-        const uint32_t li = (uint32_t)w * (T / RNW) + (uint32_t)r * WAVE + lane;
+        const uint32_t li = (uint32_t)w * (T / GW) + (uint32_t)r * WAVE + lane;
         const uint32_t v = li < n ? (r_fk[r] >> 24) : 0;
         const uint32_t inc = wave_incl_scan(v);
         excl[r] = run + inc - v;
         run += __shfl(inc, WAVE - 1, WAVE);
       }
       if (lane == 0) L.wsum[w] = run;
-      __syncthreads();
+      gbar();
       uint32_t wpre = 0, tot = 0;
-      for (int k = 0; k < RNW; k++) { const uint32_t s = L.wsum[k]; if (k < w) wpre += s; tot += s; }
+      for (int k = 0; k < (int)GW; k++) { const uint32_t s = L.wsum[k]; if (k < w) wpre += s; tot += s; }
 #pragma unroll
       for (int r = 0; r < ROWS; r++) {
-        const uint32_t li = (uint32_t)w * (T / RNW) + (uint32_t)r * WAVE + lane;
+        const uint32_t li = (uint32_t)w * (T / GW) + (uint32_t)r * WAVE + lane;
         const uint32_t fn = r_fk[r] & 0xFFFFu, kind = (r_fk[r] >> 16) & 0xFFu, plen = r_fk[r] >> 24;
         const uint64_t off = pay_run + wpre + excl[r];
         const bool sized = li < n && kind == 0 && fn < tb.n_fns && plen >= 8 && tb.has_size && tb.has_size[fn];
@@ -611,13 +670,13 @@ __device__ __forceinline__ void tile_pass(RangeLds &L, const Tables &tb, const u
         }
       }
       pay_run += tot;
-      __syncthreads();
+      gbar();
     }
     // ---- P2. kernel records, validity, counters
     uint32_t n_ent = 0, n_exi = 0, n_kern = 0, n_bad = 0;
 #pragma unroll
     for (int r = 0; r < ROWS; r++) {
-      const uint32_t li = (uint32_t)w * (T / RNW) + (uint32_t)r * WAVE + lane;
+      const uint32_t li = (uint32_t)w * (T / GW) + (uint32_t)r * WAVE + lane;
       const uint32_t fn = r_fk[r] & 0xFFFFu, kind = (r_fk[r] >> 16) & 0xFFu, plen = r_fk[r] >> 24;
       r_slot[r] = EMPTY32;
       if (li >= n) continue;
@@ -692,7 +751,7 @@ __device__ __forceinline__ void tile_pass(RangeLds &L, const Tables &tb, const u
         h = (h + 1) & (TIDMAP - 1);
       }
     }
-    __syncthreads();
+    gbar();
     const uint32_t n_new = L.misc[1];
     if (n_new) {
       const uint32_t base = L.misc[0];
@@ -708,7 +767,7 @@ __device__ __forceinline__ void tile_pass(RangeLds &L, const Tables &tb, const u
           L.tidmap[L.newbucket[tid]] = (1ull << 63) | (0xFFull << 32) | t;
         }
       }
-      __syncthreads();
+      gbar();
       if (tid == 0) { L.misc[0] = base + n_new < scap ? base + n_new : scap; L.misc[1] = 0; }
 #pragma unroll
       for (int r = 0; r < ROWS; r++) {
@@ -724,15 +783,15 @@ __device__ __forceinline__ void tile_pass(RangeLds &L, const Tables &tb, const u
         }
         if (r_slot[r] >= scap) r_slot[r] = EMPTY32;  // over the per-range thread limit: the flush fails
       }
-      __syncthreads();
+      gbar();
     }
     const uint32_t nslots = L.misc[0];
     // the tally layout of this range, fixed before its first call is tallied:
     // direct-mapped rows for every thread when the first tile's threads all
     // fit, otherwise one open-addressing table over all entries
-    if (t0 == 0) {
+    if (t0 == 0 && tid == 0) {
       const uint32_t dcap = direct_slots(tb.n_fns, E);
-      L.nd = nslots <= dcap ? dcap : 0;
+      L.misc[2] = nslots <= dcap ? dcap : 0;
     }
     // ---- P4. stable sort of the API records by slot
     uint32_t nbits = 0;
@@ -754,14 +813,14 @@ __device__ __forceinline__ void tile_pass(RangeLds &L, const Tables &tb, const u
       r_rank[r] = base + rk;
       if (valid && rk == 0) L.wcnt[w * S_MAX + s] = base + c;
     }
-    __syncthreads();
+    gbar();
     // each wave: lane s counts slot s over all waves and over the waves before
     // this one, so every wave knows where its records of each slot go
     uint32_t wb;
     {
       uint32_t tot = 0, before = 0;
       if ((uint32_t)lane < nslots)
-        for (int k = 0; k < RNW; k++) {
+        for (int k = 0; k < (int)GW; k++) {
           const uint32_t c = L.wcnt[k * S_MAX + lane];
           tot += c;
           before += k < w ? c : 0;
@@ -769,8 +828,9 @@ __device__ __forceinline__ void tile_pass(RangeLds &L, const Tables &tb, const u
       const uint32_t inc = wave_incl_scan(tot);
       wb = inc - tot + before;
       if (w == 0) {
-        if ((uint32_t)lane < nslots) L.soff[lane] = inc - tot;
-        if (lane == WAVE - 1) L.soff[nslots] = inc;
+        if ((uint32_t)lane < nslots) soff[lane] = inc - tot;
+        if (lane == WAVE - 1) soff[nslots] = inc;
+        if (lane == 0) L.misc[7 + hb] = nslots;
       }
     }
 #pragma unroll
@@ -778,28 +838,48 @@ __device__ __forceinline__ void tile_pass(RangeLds &L, const Tables &tb, const u
       const uint32_t sl = r_slot[r] == EMPTY32 ? 0u : r_slot[r];
       const uint32_t pos = (uint32_t)__builtin_amdgcn_ds_bpermute((int32_t)(sl << 2), (int32_t)wb) + r_rank[r];
       if (r_slot[r] == EMPTY32) continue;
-      L.tile_ts[pos] = r_ts[r];
-      L.tile_fk[pos] = (r_fk[r] & 0xFFFFu) | (((r_fk[r] >> 16) & 1u) << 16);
-      if (FMT == 2) L.tile_by[pos] = r_by[r];
+      tts[pos] = r_ts[r];
+      tfk[pos] = (r_fk[r] & 0xFFFFu) | (((r_fk[r] >> 16) & 1u) << 16);
+      if (FMT == 2) tby[pos] = r_by[r];
     }
-    __syncthreads();
-    // ---- P5. windows: wavefront w walks slots w, w + RNW, ... in order
-    for (uint32_t s = (uint32_t)w; s < nslots; s += RNW) {
-      const uint32_t b = L.soff[s], e = L.soff[s + 1];
-      if (b < e) slot_walk<FMT>(L, tb, E, D, s, b, e, sbase, ru, L.w_ch + w * WAVE, L.w_vt + w * (D + 1));
-    }
-    __syncthreads();
+    gbar();
+}
+
+// The walk of one sorted tile: wavefront w walks the thread slots w, w + nww,
+// ... (nww walking waves), each slot's records in order.
+template <int FMT>
+__device__ __forceinline__ void walk_tile(RangeLds &L, const Tables &tb, const uint32_t E, const uint32_t D,
+                                          const uint32_t hb, const uint32_t half, const uint32_t nww,
+                                          const size_t sbase, UItem *__restrict__ ru) {
+  const uint32_t w = threadIdx.x >> 6;
+  const uint32_t *soff = L.soff + hb * (S_MAX + 1);
+  L.cts = L.tile_ts + hb * half;
+  L.cfk = L.tile_fk + hb * half;
+  L.cby = L.tile_by + hb * half;
+  L.nd = L.misc[2];
+  const uint32_t nslots = L.misc[7 + hb];
+  for (uint32_t s = w; s < nslots; s += nww) {
+    const uint32_t b = soff[s], e = soff[s + 1];
+    if (b < e) slot_walk<FMT>(L, tb, E, D, s, b, e, sbase, ru, L.w_ch + w * WAVE, L.w_vt + w * (D + 1));
+  }
 }
 
 // ------------------------------------------------------------------ kernel
 // One whole range: LDS set-up, every tile, then the range summaries and the
 // flush of the LDS tallies and counters to the global tables.
-template <int FMT, int ROWS>
+//
+// PIPE off: all 16 waves run the front half of a tile, then the walk, in
+// lockstep (workgroup barriers).  PIPE on: waves RNW/2 .. RNW-1 (producers)
+// build sorted tiles into the two halves of the tile region alternately while
+// waves 0 .. RNW/2-1 (walkers) walk the previous one; a tile is handed over
+// through two LDS counters (tiles built, tiles walked).
+template <int FMT, int ROWS, bool PIPE>
 __device__ __forceinline__ void range_body(RangeLds &L, const Seg *__restrict__ segs,
                                            const Range *__restrict__ ranges, const uint32_t rid, const Tables &tb,
                                            const Shape &sh, RHdr *__restrict__ rhdr, UItem *__restrict__ ru,
                                            OItem *__restrict__ ro, uint32_t *__restrict__ rnslots) {
-  constexpr uint32_t T = ROWS * RWG;
+  constexpr uint32_t GW = PIPE ? RNW / 2 : RNW;     // waves that build tiles
+  constexpr uint32_t T = ROWS * GW * WAVE;          // records per tile
   constexpr uint32_t RS = FMT == 2 ? 16 : 24;
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid >> 6;
   const uint32_t D = tb.D, E = sh.E, KL = sh.KL;
@@ -817,35 +897,53 @@ __device__ __forceinline__ void range_body(RangeLds &L, const Seg *__restrict__ 
     L.s_facc[i] = 0; L.s_first[i] = 0; L.s_last[i] = 0;
   }
   for (uint32_t i = tid; i < ST_N; i += RWG) L.cnt[i] = 0;
-  if (tid < 8) L.misc[tid] = 0;
+  if (tid < 16) L.misc[tid] = 0;
   __syncthreads();
 
   const size_t sbase = (size_t)rid * S_MAX;
-  uint64_t pay_run = rg.pay_begin;  // payload offset of the current tile's first record
-  // Two register buffers of raw record words alternate between tiles; the
-  // loads are unconditional (index clamped to the range) so that nothing
-  // waits for them before the tile that uses them.
-  gu64 *grec = (gu64 *)sg.rec;
-  const uint64_t last_rec = rg.begin + rg.n - 1;
-  uint64_t a0[ROWS], a1[ROWS], a2[ROWS], b0[ROWS], b1[ROWS], b2[ROWS];
+  const uint64_t ntiles = (rg.n + T - 1) / T;
+  if (!PIPE || w >= (int)GW) {
+    // tile builder: two register buffers of raw record words alternate
+    // between tiles; the loads are unconditional (index clamped to the range)
+    // so that nothing waits for them before the tile that uses them
+    const int gw = PIPE ? w - (int)GW : w;
+    uint64_t pay_run = rg.pay_begin;  // payload offset of the current tile's first record
+    gu64 *grec = (gu64 *)sg.rec;
+    const uint64_t last_rec = rg.begin + rg.n - 1;
+    uint64_t a0[ROWS], a1[ROWS], a2[ROWS], b0[ROWS], b1[ROWS], b2[ROWS];
 #pragma unroll
-  for (int r = 0; r < ROWS; r++) {
-    const uint32_t li = (uint32_t)w * (T / RNW) + (uint32_t)r * WAVE + lane;
-    uint64_t idx = rg.begin + li;
-    idx = idx < last_rec ? idx : last_rec;
-    gu64 *p = grec + idx * (RS / 8);
-    a0[r] = __builtin_nontemporal_load(p);
-    a1[r] = __builtin_nontemporal_load(p + 1);
-    a2[r] = FMT == 1 ? __builtin_nontemporal_load(p + 2) : 0;
-  }
+    for (int r = 0; r < ROWS; r++) {
+      const uint32_t li = (uint32_t)gw * (T / GW) + (uint32_t)r * WAVE + lane;
+      uint64_t idx = rg.begin + li;
+      idx = idx < last_rec ? idx : last_rec;
+      gu64 *p = grec + idx * (RS / 8);
+      a0[r] = __builtin_nontemporal_load(p);
+      a1[r] = __builtin_nontemporal_load(p + 1);
+      a2[r] = FMT == 1 ? __builtin_nontemporal_load(p + 2) : 0;
+    }
+    for (uint64_t t = 0; t < ntiles; t++) {
+      const uint32_t hb = PIPE ? (uint32_t)(t & 1) : 0u;
+      // PIPE: the half of tile t - 2 must have been walked
+      if (PIPE && t >= 2) wait_at_least(&L.misc[6], (uint32_t)(t - 1), tb.err);
+      front_tile<FMT, ROWS, PIPE>(L, tb, E, KL, D, rg, sg, grec, last_rec, t * T, hb, a0, a1, a2, b0, b1, b2,
+                                  pay_run);
+      if (PIPE) publish(&L.misc[5], (uint32_t)(t + 1), w == (int)GW && lane == 0);
+      else walk_tile<FMT>(L, tb, E, D, 0, T, RNW, sbase, ru);
+      if (!PIPE) __syncthreads();
 #pragma unroll
-
-  for (uint64_t t0 = 0; t0 < rg.n; t0 += T) {
-    tile_pass<FMT, ROWS>(L, tb, E, KL, D, rg, sg, grec, last_rec, t0, a0, a1, a2, b0, b1, b2, pay_run, sbase, ru);
-#pragma unroll
-    for (int r = 0; r < ROWS; r++) { a0[r] = b0[r]; a1[r] = b1[r]; a2[r] = b2[r]; }
+      for (int r = 0; r < ROWS; r++) { a0[r] = b0[r]; a1[r] = b1[r]; a2[r] = b2[r]; }
+    }
+  } else {
+    // walker
+    for (uint64_t t = 0; t < ntiles; t++) {
+      wait_at_least(&L.misc[5], (uint32_t)(t + 1), tb.err);
+      walk_tile<FMT>(L, tb, E, D, (uint32_t)(t & 1), T, GW, sbase, ru);
+      group_barrier(&L.misc[4], GW, tb.err);
+      publish(&L.misc[6], (uint32_t)(t + 1), w == 0 && lane == 0);
+    }
   }
   __syncthreads();
+  L.nd = L.misc[2];
 
   // ---- range end: summaries, tally and counter flush
   const uint32_t nslots = L.misc[0];
@@ -913,7 +1011,7 @@ __device__ __forceinline__ void range_body(RangeLds &L, const Seg *__restrict__ 
 // Persistent work-list launch: each workgroup (one per CU) takes the next
 // entry of `order` (range ids, longest first) until the list is exhausted.
 // `qhead` must be 0 at launch.
-template <int FMT, int ROWS>
+template <int FMT, int ROWS, bool PIPE>
 __global__ __launch_bounds__(RWG) void k_range(const Seg *__restrict__ segs, const Range *__restrict__ ranges,
                                                const uint32_t *__restrict__ order, const uint32_t n_ranges,
                                                uint32_t *__restrict__ qhead, Tables tb, Shape sh,
@@ -922,14 +1020,14 @@ __global__ __launch_bounds__(RWG) void k_range(const Seg *__restrict__ segs, con
   extern __shared__ __align__(16) uint8_t smem[];
   __shared__ uint32_t next;
   RangeLds L;
-  range_lds_layout<true>(smem, &L, ROWS * RWG, sh.E, sh.KL, tb.D, FMT);
+  range_lds_layout<true>(smem, &L, ROWS * RWG, sh.E, sh.KL, tb.D, FMT);   // (PIPE: two halves of ROWS * RWG / 2)
   for (;;) {
     if (threadIdx.x == 0) next = atomicAdd(qhead, 1u);
     __syncthreads();
     const uint32_t q = next;
     __syncthreads();
     if (q >= n_ranges) break;
-    range_body<FMT, ROWS>(L, segs, ranges, order[q], tb, sh, rhdr, ru, ro, rnslots);
+    range_body<FMT, ROWS, PIPE>(L, segs, ranges, order[q], tb, sh, rhdr, ru, ro, rnslots);
   }
 }
 
@@ -967,8 +1065,10 @@ __global__ void k_range_payoff(const Seg *__restrict__ segs, uint32_t n_segs, co
 // Allows every range-kernel variant up to max_lds_bytes of dynamic LDS (set
 // once, outside any stream capture).
 hipError_t prepare_range_kernels(uint32_t max_lds_bytes) {
-  const void *ks[] = {(const void *)k_range<1, 1>, (const void *)k_range<1, 2>, (const void *)k_range<2, 1>,
-                      (const void *)k_range<2, 2>};
+  const void *ks[] = {(const void *)k_range<1, 1, false>, (const void *)k_range<1, 2, false>,
+                      (const void *)k_range<2, 1, false>, (const void *)k_range<2, 2, false>,
+                      (const void *)k_range<1, 1, true>,  (const void *)k_range<1, 2, true>,
+                      (const void *)k_range<2, 1, true>,  (const void *)k_range<2, 2, true>};
   for (const void *k : ks) {
     hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds_bytes);
     if (e != hipSuccess) return e;
@@ -978,24 +1078,26 @@ hipError_t prepare_range_kernels(uint32_t max_lds_bytes) {
 
 // n_wg: workgroups of the persistent launch (at most one per CU is resident);
 // *qhead must be 0 (the caller clears it with a kernel, so the launch can be
-// captured in a graph).
+// captured in a graph).  T: records of the LDS tile region (1024 or 2048);
+// with sh.pipe the tiles are half of it.
 hipError_t launch_range(int fmt, uint32_t T, const Seg *segs, const Range *ranges, const uint32_t *order,
                         uint32_t n_ranges, uint32_t *qhead, uint32_t n_wg, const Tables &tb, const Shape &sh,
                         RHdr *rhdr, UItem *ru, OItem *ro, uint32_t *rnslots, hipStream_t st) {
   if (!n_ranges) return hipSuccess;
   dim3 grid(n_wg < n_ranges ? n_wg : n_ranges), block(RWG);
-#define TT_LAUNCH(F, ROWS_)                                                                                     \
+#define TT_LAUNCH(F, ROWS_, P_)                                                                                 \
   do {                                                                                                          \
-    hipLaunchKernelGGL((k_range<F, ROWS_>), grid, block, sh.lds_bytes, st, segs, ranges, order, n_ranges,     \
+    hipLaunchKernelGGL((k_range<F, ROWS_, P_>), grid, block, sh.lds_bytes, st, segs, ranges, order, n_ranges, \
                        qhead, tb, sh, rhdr, ru, ro, rnslots);                                                   \
     return hipGetLastError();                                                                                   \
   } while (0)
+  const bool p = sh.pipe != 0;
   if (fmt == 1) {
-    if (T == 1024) TT_LAUNCH(1, 1);
-    if (T == 2048) TT_LAUNCH(1, 2);
+    if (T == 1024) { if (p) TT_LAUNCH(1, 1, true); else TT_LAUNCH(1, 1, false); }
+    if (T == 2048) { if (p) TT_LAUNCH(1, 2, true); else TT_LAUNCH(1, 2, false); }
   } else {
-    if (T == 1024) TT_LAUNCH(2, 1);
-    if (T == 2048) TT_LAUNCH(2, 2);
+    if (T == 1024) { if (p) TT_LAUNCH(2, 1, true); else TT_LAUNCH(2, 1, false); }
+    if (T == 2048) { if (p) TT_LAUNCH(2, 2, true); else TT_LAUNCH(2, 2, false); }
   }
 #undef TT_LAUNCH
   return hipErrorInvalidValue;

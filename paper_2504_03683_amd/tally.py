@@ -217,8 +217,8 @@ class Tally:
                          "arena_used"], list(arr)[:n]))
 
     def autotune(self, reps=2):
-        """Times the queued chunks under each candidate launch shape; returns the chosen (T, E, rpc)."""
-        out = (ctypes.c_uint32 * 3)()
+        """Times the queued chunks under each candidate launch shape; returns the chosen (T, E, rpc, pipe)."""
+        out = (ctypes.c_uint32 * 4)()
         _check(self._lib.thapi_tally_autotune(self._h, reps, out), "autotune")
         return tuple(out)
 

@@ -36,7 +36,8 @@ def c1():
     return c, run_oracle(c)
 
 
-@pytest.mark.parametrize("shape", ["1024,1024,4", "2048,2048,2", "1024,2048,1", "2048,1024,3"])
+@pytest.mark.parametrize("shape", ["1024,1024,4,0", "2048,2048,2,0", "1024,2048,1,0", "2048,1024,3,0",
+                                   "2048,2048,1,1", "1024,1024,2,1", "2048,1024,4,1"])
 def test_launch_shapes(shape, c3, c1, monkeypatch):
     monkeypatch.setenv("THAPI_TALLY_SHAPE", shape)
     for name, (c, o) in (("batched 256 traces", c3), ("layered, 3 chunks per stream", c1)):
@@ -101,13 +102,14 @@ def test_autotune_and_cache(c3, tmp_path):
             t.submit(key, rec, pay)
         chosen = t.autotune(reps=1)
         assert chosen[0] in (1024, 2048) and chosen[1] in (1024, 2048) and chosen[2] in (1, 2, 4)
+        assert chosen[3] in (0, 1)
         t.flush(final=True)
         assert_same(read_out(t, c), o)
         assert t._lib.thapi_tally_autotune(t._h, 1, None) == T.E_STATE   # after a flush: refused
     lines = open(cache).read().split("\n")
     assert len([x for x in lines if x.strip()]) == 1
-    key, tt, ee, rr = lines[0].split()
-    assert (int(tt), int(ee), int(rr)) == tuple(chosen)
+    key, tt, ee, rr, pp = lines[0].split()
+    assert (int(tt), int(ee), int(rr), int(pp)) == tuple(chosen)
     say("case: cached shape reused by a new handle")
     g = run_gpu(c, max_threads=65536, max_streams=4096)
     assert_same(g, o)

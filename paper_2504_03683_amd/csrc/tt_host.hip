@@ -9,6 +9,7 @@
 // rows on the device, then copies the rows out.
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <condition_variable>
 #include <cstdio>
 #include <cstdlib>
@@ -153,6 +154,16 @@ struct thapi_tally {
   uint64_t done_upto = 0;                             // every ticket <= this one is tallied
   std::vector<uint64_t> done_ns;                      // [ticket] CLOCK_MONOTONIC ns of its batch's completion
   uint64_t n_batches = 0, n_batch_chunks = 0, max_batch_chunks = 0, bytes_admitted = 0;
+
+  // the rows of the last read that did not fit its buffer (the size query of
+  // a two-call read), kept until the tallies or streams change
+  std::atomic<uint64_t> gen{0};       // bumped by submit, flush and reset
+  bool rc_valid = false;
+  uint64_t rc_gen = 0;
+  uint32_t rc_scope = 0, rc_trace = 0;
+  std::vector<thapi_tally_row> rc_rows;
+  thapi_tally_stats rc_stats{};
+  DevBuf rstream;
 };
 
 namespace {
@@ -186,7 +197,7 @@ void free_all(thapi_tally *t) {
   void *ps[] = {t->d_gkeys, t->d_gvals, t->d_ngs, t->d_ths, t->d_tht, t->d_tally, t->d_ktally,
                 t->d_cstate, t->d_cstack, t->d_sstats, t->d_err, t->d_hs};
   for (void *p : ps) if (p) hipFree(p);
-  DevBuf *bs[] = {&t->segs, &t->ranges, &t->order, &t->qhead, &t->rhdr, &t->ru, &t->ro, &t->rnslots, &t->spans, &t->paylen, &t->segfirst,
+  DevBuf *bs[] = {&t->rstream, &t->segs, &t->ranges, &t->order, &t->qhead, &t->rhdr, &t->ru, &t->ro, &t->rnslots, &t->spans, &t->paylen, &t->segfirst,
                   &t->keys, &t->vals, &t->keys2, &t->vals2, &t->gbeg, &t->gend, &t->cnt, &t->off,
                   &t->rank_stream, &t->rank_key, &t->trace_span, &t->stream_rank, &t->rows, &t->tstats};
   for (DevBuf *b : bs) b->release();
@@ -471,6 +482,7 @@ int thapi_tally_submit(thapi_tally *t, const thapi_stream_key *key, const void *
     return THAPI_E_INVAL;
   }
   std::unique_lock<std::mutex> lk(t->mu);
+  t->gen++;
   SKey sk{key->trace_id, key->host_id, key->pid};
   auto it = t->stream_idx.find(sk);
   uint32_t sidx;
@@ -782,6 +794,7 @@ namespace {
 // Tallies one batch of chunks (taken off the queue by the caller) and, with
 // `final`, closes every stream.  Caller holds run_mu.
 int process_batch(thapi_tally *t, std::vector<Chunk> &work, bool final) {
+  t->gen++;
   if (hipSetDevice(t->dev) != hipSuccess) return THAPI_E_DEVICE;
   for (int k = 0; k < TM_N; k++) t->timings[k] = 0;
   // chunks grouped by stream, each stream's chunks in ticket order
@@ -1015,6 +1028,16 @@ int thapi_tally_read(thapi_tally *t, uint32_t scope, uint32_t trace_id, thapi_ta
     failed = t->failed;
   }
   if (failed == THAPI_E_DEVICE) return THAPI_E_DEVICE;
+  const uint64_t gen = t->gen.load();
+  if (t->rc_valid && t->rc_gen == gen && t->rc_scope == scope && t->rc_trace == trace_id) {
+    *n_rows = t->rc_rows.size();
+    if (stats) *stats = t->rc_stats;
+    if (t->rc_rows.size() > capacity) return capacity == 0 && !rows ? THAPI_OK : THAPI_E_BUFSZ;
+    if (!t->rc_rows.empty()) memcpy(rows, t->rc_rows.data(), sizeof(thapi_tally_row) * t->rc_rows.size());
+    t->rc_valid = false;
+    return THAPI_OK;
+  }
+  t->rc_valid = false;
   const uint32_t nstreams = (uint32_t)keys.size();
   // canonical order of the selected streams
   std::vector<uint32_t> sel;
@@ -1047,7 +1070,8 @@ int thapi_tally_read(thapi_tally *t, uint32_t scope, uint32_t trace_id, thapi_ta
   HIPCHK(hipMemcpyAsync(ts3.data(), t->tstats.p, 24ull * std::max<uint32_t>(nstreams, 1), hipMemcpyDeviceToHost, t->st));
   if (nstreams) HIPCHK(hipMemcpyAsync(sst.data(), t->tb.sstats, 8ull * nstreams * ST_N, hipMemcpyDeviceToHost, t->st));
   HIPCHK(hipStreamSynchronize(t->st));
-  if (stats) {
+  thapi_tally_stats stats_all{};
+  {
     thapi_tally_stats s{};
     std::vector<std::array<uint32_t, 2>> hosts;
     for (uint32_t i : sel) {
@@ -1065,7 +1089,8 @@ int thapi_tally_read(thapi_tally *t, uint32_t scope, uint32_t trace_id, thapi_ta
     }
     std::sort(hosts.begin(), hosts.end());
     s.distinct_hosts = (uint64_t)(std::unique(hosts.begin(), hosts.end()) - hosts.begin());
-    *stats = s;
+    stats_all = s;
+    if (stats) *stats = s;
   }
   // threads of the selected streams, sorted canonically
   uint32_t nsel_threads = 0;
@@ -1104,10 +1129,9 @@ int thapi_tally_read(thapi_tally *t, uint32_t scope, uint32_t trace_id, thapi_ta
   rc.rank_key = t->rank_key.as<uint32_t>(); rc.trace_span = t->trace_span.as<uint32_t>();
   std::vector<uint32_t> rank_stream(std::max<uint32_t>(nrank, 1), 0);
   for (uint32_t r = 0; r < nrank; r++) rank_stream[r] = sel[r];
-  DevBuf rstream;
-  HIPCHK(rstream.ensure(4ull * rank_stream.size()));
-  HIPCHK(hipMemcpyAsync(rstream.p, rank_stream.data(), 4ull * rank_stream.size(), hipMemcpyHostToDevice, t->st));
-  rc.rank_stream = rstream.as<uint32_t>();
+  HIPCHK(t->rstream.ensure(4ull * rank_stream.size()));
+  HIPCHK(hipMemcpyAsync(t->rstream.p, rank_stream.data(), 4ull * rank_stream.size(), hipMemcpyHostToDevice, t->st));
+  rc.rank_stream = t->rstream.as<uint32_t>();
   uint32_t ngroups = 0;
   if (scope == THAPI_SCOPE_THREAD) ngroups = ng ? nsel_threads : 0;
   else if (scope == THAPI_SCOPE_PROCESS) ngroups = ng ? nrank : 0;
@@ -1122,22 +1146,28 @@ int thapi_tally_read(thapi_tally *t, uint32_t scope, uint32_t trace_id, thapi_ta
     total = *htot;
   }
   *n_rows = (size_t)total;
-  if (total > capacity) {
-    hipStreamSynchronize(t->st);
-    rstream.release();
-    HIPCHK(timed_end(t, TM_READOUT));
-    return capacity == 0 && !rows ? THAPI_OK : THAPI_E_BUFSZ;
-  }
+  // rows that do not fit the caller's buffer are kept for the second call of
+  // a two-call read
+  const bool keep = total > capacity;
+  if (keep) t->rc_rows.resize(total);
+  thapi_tally_row *dst = keep ? t->rc_rows.data() : rows;
   if (total) {
     HIPCHK(t->rows.ensure(88ull * total));
     HIPCHK(launch_group_rows(rc, t->tb, ngroups, t->cnt.as<uint32_t>(), t->off.as<uint64_t>(), t->rows.as<uint8_t>(),
                              t->st));
-    HIPCHK(hipMemcpyAsync(rows, t->rows.p, 88ull * total, hipMemcpyDeviceToHost, t->st));
+    HIPCHK(hipMemcpyAsync(dst, t->rows.p, 88ull * total, hipMemcpyDeviceToHost, t->st));
   }
   HIPCHK(timed_end(t, TM_READOUT));
   HIPCHK(hipStreamSynchronize(t->st));
   collect_timing(t, TM_READOUT);
-  rstream.release();
+  if (keep) {
+    t->rc_valid = true;
+    t->rc_gen = gen;
+    t->rc_scope = scope;
+    t->rc_trace = trace_id;
+    t->rc_stats = stats_all;
+    return capacity == 0 && !rows ? THAPI_OK : THAPI_E_BUFSZ;
+  }
   return THAPI_OK;
 }
 
@@ -1150,6 +1180,7 @@ int thapi_tally_reset(thapi_tally *t) {
     if (t->failed == THAPI_E_DEVICE) return THAPI_E_DEVICE;
   }
   if (hipSetDevice(t->dev) != hipSuccess) return THAPI_E_DEVICE;
+  t->gen++;
   if (init_tables(t) != hipSuccess) return hip_fail(t, hipErrorUnknown);
   std::lock_guard<std::mutex> g(t->mu);
   t->stream_idx.clear();

@@ -23,12 +23,15 @@ __device__ inline void gmax64(uint64_t *p, uint64_t v) {
 // time order, tallies inclusive and self time and credits the parent; the
 // range's floor time goes to the call left on top; O items are pushed.
 constexpr int CB_SET = 2048;
+constexpr int CB_MAP = 16384;   // (range, thread) -> slot table, used when the span fits
 
 __global__ __launch_bounds__(256) void k_combine(const uint32_t *__restrict__ spans, const RHdr *__restrict__ rhdr,
                                                  const UItem *__restrict__ ru, const OItem *__restrict__ ro,
                                                  const uint32_t *__restrict__ rnslots, Tables tb) {
   __shared__ uint32_t set_key[CB_SET];
+  __shared__ uint32_t set_val[CB_SET];
   __shared__ uint32_t list[CB_SET];
+  __shared__ uint8_t smap[CB_MAP];
   __shared__ uint32_t nlist;
   __shared__ uint32_t lcnt[ST_N];
   const uint32_t stream = spans[3 * blockIdx.x], rb = spans[3 * blockIdx.x + 1], re = spans[3 * blockIdx.x + 2];
@@ -49,6 +52,7 @@ __global__ __launch_bounds__(256) void k_combine(const uint32_t *__restrict__ sp
         if (old == EMPTY32) {
           const uint32_t k = atomicAdd(&nlist, 1u);
           if (k < CB_SET) list[k] = g;
+          set_val[h] = k;
           break;
         }
         if (old == g) break;
@@ -59,6 +63,31 @@ __global__ __launch_bounds__(256) void k_combine(const uint32_t *__restrict__ sp
   __syncthreads();
   const uint32_t n = nlist < CB_SET ? nlist : CB_SET;
   if (tid == 0 && nlist >= (uint32_t)CB_SET) atomicOr(tb.err, ERR_CAPACITY);
+  // where each thread sits in each range's summaries (0xFF: not in that range)
+  const bool use_map = (uint64_t)(re - rb) * n <= (uint64_t)CB_MAP;
+  if (use_map) {
+    for (uint32_t i = tid; i < (re - rb) * n; i += 256) smap[i] = 0xFF;
+    __syncthreads();
+    for (uint32_t r = rb; r < re; r++) {
+      const uint32_t ns = rnslots[r];
+      for (uint32_t s = tid; s < ns; s += 256) {
+        const uint32_t g = rhdr[(size_t)r * S_MAX + s].gslot;
+        if (g >= tb.max_threads) continue;
+        uint32_t h = hash32(g) & (CB_SET - 1);
+        for (int probe = 0; probe < CB_SET; probe++) {
+          const uint32_t k = set_key[h];
+          if (k == g) {
+            const uint32_t i = set_val[h];
+            if (i < n) smap[(r - rb) * n + i] = (uint8_t)s;
+            break;
+          }
+          if (k == EMPTY32) break;
+          h = (h + 1) & (CB_SET - 1);
+        }
+      }
+    }
+    __syncthreads();
+  }
   uint32_t c_tsreg = 0, c_orphan = 0, c_mis = 0, c_neg = 0, c_under = 0;
   for (uint32_t i = tid; i < n; i += 256) {
     const uint32_t g = list[i];
@@ -68,8 +97,13 @@ __global__ __launch_bounds__(256) void k_combine(const uint32_t *__restrict__ sp
       const uint32_t ns = rnslots[r];
       const RHdr *hp = rhdr + (size_t)r * S_MAX;
       uint32_t s = 0;
-      while (s < ns && hp[s].gslot != g) s++;
-      if (s == ns) continue;
+      if (use_map) {
+        s = smap[(r - rb) * n + i];
+        if (s == 0xFF) continue;
+      } else {
+        while (s < ns && hp[s].gslot != g) s++;
+        if (s == ns) continue;
+      }
       const RHdr hd = hp[s];
       const size_t ib = ((size_t)r * S_MAX + s) * D;
       if (hd.flags & RF_HAS_TS) {

@@ -594,7 +594,9 @@ __device__ inline void publish(uint32_t *ctr, uint32_t v, bool me) {
 
 // ------------------------------------------------------------------ tile
 // Front half of one tile: decode `cur*`, prefetch the next tile into `nxt*`,
-// kernel records, slot map and stable sort into half `hb` of the tile region
+// kernel records (wave totals of entries, exits, kernel, bad and -- wave 0 --
+// all records accumulate in wc), slot map and stable sort into half `hb` of
+// the tile region
 // (the whole region when PIPE is off).  With PIPE the producer group (the
 // upper RNW / 2 waves) runs it alone and synchronises through group barriers;
 // otherwise the whole workgroup runs it between workgroup barriers.
@@ -604,7 +606,8 @@ __device__ __forceinline__ void front_tile(RangeLds &L, const Tables &tb, const 
                                            const uint64_t last_rec, const uint64_t t0, const uint32_t hb,
                                            const uint64_t (&cur0)[ROWS], const uint64_t (&cur1)[ROWS],
                                            const uint64_t (&cur2)[ROWS], uint64_t (&nxt0)[ROWS],
-                                           uint64_t (&nxt1)[ROWS], uint64_t (&nxt2)[ROWS], uint64_t &pay_run) {
+                                           uint64_t (&nxt1)[ROWS], uint64_t (&nxt2)[ROWS], uint64_t &pay_run,
+                                           uint32_t (&wc)[5]) {
   constexpr uint32_t GW = PIPE ? RNW / 2 : RNW;     // waves of the group
   constexpr uint32_t T = ROWS * GW * WAVE;          // records per tile
   constexpr uint32_t RS = FMT == 2 ? 16 : 24;
@@ -672,58 +675,50 @@ __device__ __forceinline__ void front_tile(RangeLds &L, const Tables &tb, const 
       pay_run += tot;
       gbar();
     }
-    // ---- P2. kernel records, validity, counters
-    uint32_t n_ent = 0, n_exi = 0, n_kern = 0, n_bad = 0;
+    // ---- P2. kernel records, validity, counters (wave totals by ballot)
 #pragma unroll
     for (int r = 0; r < ROWS; r++) {
       const uint32_t li = (uint32_t)w * (T / GW) + (uint32_t)r * WAVE + lane;
       const uint32_t fn = r_fk[r] & 0xFFFFu, kind = (r_fk[r] >> 16) & 0xFFu, plen = r_fk[r] >> 24;
       r_slot[r] = EMPTY32;
-      if (li >= n) continue;
-      if (kind == 2) {
-        const uint64_t end = r_x[r];
-        const bool ok = fn < tb.n_kid && (FMT == 1 || plen >= 8) && end >= r_ts[r];
-        if (ok) {
-          const uint64_t d = end - r_ts[r];
-          n_kern++;
-          if (fn < KL) {
-            lds_add32(&L.q_cnt[fn], 1u);
-            lds_add64(&L.q_sum[fn], d);
-            if (d < EMPTY32) { lds_min32(&L.q_min[fn], (uint32_t)d); lds_max32(&L.q_max[fn], (uint32_t)d); }
-            else {
+      bool kern_ok = false, bad = false;
+      if (li < n) {
+        if (kind == 2) {
+          const uint64_t end = r_x[r];
+          kern_ok = fn < tb.n_kid && (FMT == 1 || plen >= 8) && end >= r_ts[r];
+          bad = !kern_ok;
+          if (kern_ok) {
+            const uint64_t d = end - r_ts[r];
+            if (fn < KL) {
+              lds_add32(&L.q_cnt[fn], 1u);
+              lds_add64(&L.q_sum[fn], d);
+              if (d < EMPTY32) { lds_min32(&L.q_min[fn], (uint32_t)d); lds_max32(&L.q_max[fn], (uint32_t)d); }
+              else {
+                KTally *kt = &tb.ktally[(size_t)sg.stream * tb.n_kid + fn];
+                g_min64(&kt->min, d); g_max64(&kt->max, d);
+              }
+            } else {
               KTally *kt = &tb.ktally[(size_t)sg.stream * tb.n_kid + fn];
-              g_min64(&kt->min, d); g_max64(&kt->max, d);
+              g_add64(&kt->count, 1); g_add64(&kt->sum, d); g_min64(&kt->min, d); g_max64(&kt->max, d);
             }
-          } else {
-            KTally *kt = &tb.ktally[(size_t)sg.stream * tb.n_kid + fn];
-            g_add64(&kt->count, 1); g_add64(&kt->sum, d); g_min64(&kt->min, d); g_max64(&kt->max, d);
           }
+        } else if (kind <= 1 && fn < tb.n_fns) {
+          r_slot[r] = 0;
         } else {
-          n_bad++;
+          bad = true;
         }
-      } else if (kind <= 1 && fn < tb.n_fns) {
-        r_slot[r] = 0;
-        if (kind == 0) n_ent++; else n_exi++;
-      } else {
-        n_bad++;
       }
+      wc[0] += (uint32_t)__popcll(__ballot(r_slot[r] == 0 && kind == 0));
+      wc[1] += (uint32_t)__popcll(__ballot(r_slot[r] == 0 && kind == 1));
+      wc[2] += (uint32_t)__popcll(__ballot(kern_ok));
+      wc[3] += (uint32_t)__popcll(__ballot(bad));
     }
-    // per-wave totals of the tile's counts, one LDS add each
-    {
-      const uint32_t e1 = wave_incl_scan(n_ent), e2 = wave_incl_scan(n_exi);
-      const uint32_t e3 = wave_incl_scan(n_kern), e4 = wave_incl_scan(n_bad);
-      if (lane == WAVE - 1) {
-        if (e1) lds_add32(&L.cnt[ST_ENTRIES], e1);
-        if (e2) lds_add32(&L.cnt[ST_EXITS], e2);
-        if (e3) lds_add32(&L.cnt[ST_KERNEL], e3);
-        if (e4) lds_add32(&L.cnt[ST_BAD], e4);
-      }
-      if (tid == 0) lds_add32(&L.cnt[ST_RECORDS], n);
-    }
+    if (w == 0) wc[4] += n;
     // ---- P3. thread id -> local slot
     // bucket word: bit 63 occupied, bit 62 pending, [32,40) slot, [0,32) tid.
     // A lane that finds no bucket for its tid claims one as pending and lists
-    // the tid; after one barrier, no listed tid means nobody missed.
+    // the tid; its record is ranked after the listed tids get slots.
+    uint32_t r_late = 0;   // bit r: row r's thread has no slot yet
 #pragma unroll
     for (int r = 0; r < ROWS; r++) {
       if (r_slot[r] == EMPTY32) continue;
@@ -739,25 +734,56 @@ __device__ __forceinline__ void front_tile(RangeLds &L, const Tables &tb, const 
             L.newtid[k] = t;
             L.newbucket[k] = h;
             r_slot[r] = EMPTY32 - 1;
+            r_late |= 1u << r;
             break;
           }
         }
         if ((uint32_t)e == t) {
           const uint32_t sl = (uint32_t)(e >> 32) & 0xFFu;
-          if (e & (1ull << 62)) r_slot[r] = EMPTY32 - 1;
+          if (e & (1ull << 62)) { r_slot[r] = EMPTY32 - 1; r_late |= 1u << r; }
           else r_slot[r] = sl < slot_cap(D) ? sl : EMPTY32;  // over the per-range limit: the flush fails
           break;
         }
         h = (h + 1) & (TIDMAP - 1);
       }
     }
+    // ---- P4. stable sort of the API records by slot: rank each record among
+    // the wave's records of its slot (ballot match masks over the slot bits;
+    // per-wave counters carry the rank across rows).  Records of threads new
+    // in this tile are ranked after their slots exist; no other record of
+    // those slots is in the tile, so the order stays stable.
+    const uint32_t nslots0 = L.misc[0];
+    if (lane < S_MAX) L.wcnt[w * S_MAX + lane] = 0;
+    auto rank_rows = [&](const bool late, const uint32_t ns) {
+      uint32_t nbits = 0;
+      while ((1u << nbits) < ns) nbits++;
+#pragma unroll
+      for (int r = 0; r < ROWS; r++) {
+        const bool valid = late ? (r_late & (1u << r)) && r_slot[r] != EMPTY32
+                                : r_slot[r] != EMPTY32 && r_slot[r] != EMPTY32 - 1;
+        const uint32_t s = valid ? r_slot[r] : 0;
+        uint64_t mask = __ballot(valid);
+        for (uint32_t b = 0; b < nbits; b++) {
+          const uint64_t bb = __ballot(valid && ((s >> b) & 1u));
+          mask &= ((s >> b) & 1u) ? bb : ~bb;
+        }
+        const uint32_t rk = (uint32_t)__popcll(mask & lanemask_lt());
+        const uint32_t c = (uint32_t)__popcll(mask);
+        uint32_t base = 0;
+        if (valid) base = L.wcnt[w * S_MAX + s];
+        if (valid) r_rank[r] = base + rk;
+        if (valid && rk == 0) L.wcnt[w * S_MAX + s] = base + c;
+      }
+    };
+    rank_rows(false, nslots0);
     gbar();
     const uint32_t n_new = L.misc[1];
+    uint32_t nslots = nslots0;
     if (n_new) {
-      const uint32_t base = L.misc[0];
+      // threads seen for the first time in this range: global slot, local slot
       const uint32_t scap = slot_cap(D);
       if ((uint32_t)tid < n_new) {
-        const uint32_t s = base + tid;
+        const uint32_t s = nslots0 + tid;
         const uint32_t t = L.newtid[tid];
         if (s < scap) {
           L.s_gslot[s] = resolve_gslot(tb, sg.stream, t);
@@ -768,10 +794,11 @@ __device__ __forceinline__ void front_tile(RangeLds &L, const Tables &tb, const 
         }
       }
       gbar();
-      if (tid == 0) { L.misc[0] = base + n_new < scap ? base + n_new : scap; L.misc[1] = 0; }
+      nslots = nslots0 + n_new < scap ? nslots0 + n_new : scap;
+      if (tid == 0) { L.misc[0] = nslots; L.misc[1] = 0; }
 #pragma unroll
       for (int r = 0; r < ROWS; r++) {
-        if (r_slot[r] != EMPTY32 - 1) continue;
+        if (!(r_late & (1u << r))) continue;
         const uint32_t t = r_tid[r];
         uint32_t h = hash32(t) & (TIDMAP - 1);
         r_slot[r] = EMPTY32;
@@ -783,9 +810,9 @@ __device__ __forceinline__ void front_tile(RangeLds &L, const Tables &tb, const 
         }
         if (r_slot[r] >= scap) r_slot[r] = EMPTY32;  // over the per-range thread limit: the flush fails
       }
+      rank_rows(true, nslots);
       gbar();
     }
-    const uint32_t nslots = L.misc[0];
     // the tally layout of this range, fixed before its first call is tallied:
     // direct-mapped rows for every thread when the first tile's threads all
     // fit, otherwise one open-addressing table over all entries
@@ -793,27 +820,6 @@ __device__ __forceinline__ void front_tile(RangeLds &L, const Tables &tb, const 
       const uint32_t dcap = direct_slots(tb.n_fns, E);
       L.misc[2] = nslots <= dcap ? dcap : 0;
     }
-    // ---- P4. stable sort of the API records by slot
-    uint32_t nbits = 0;
-    while ((1u << nbits) < nslots) nbits++;
-    if (lane < S_MAX) L.wcnt[w * S_MAX + lane] = 0;
-#pragma unroll
-    for (int r = 0; r < ROWS; r++) {
-      const bool valid = r_slot[r] != EMPTY32;
-      const uint32_t s = valid ? r_slot[r] : 0;
-      uint64_t mask = __ballot(valid);
-      for (uint32_t b = 0; b < nbits; b++) {
-        const uint64_t bb = __ballot(valid && ((s >> b) & 1u));
-        mask &= ((s >> b) & 1u) ? bb : ~bb;
-      }
-      const uint32_t rk = (uint32_t)__popcll(mask & lanemask_lt());
-      const uint32_t c = (uint32_t)__popcll(mask);
-      uint32_t base = 0;
-      if (valid) base = L.wcnt[w * S_MAX + s];
-      r_rank[r] = base + rk;
-      if (valid && rk == 0) L.wcnt[w * S_MAX + s] = base + c;
-    }
-    gbar();
     // each wave: lane s counts slot s over all waves and over the waves before
     // this one, so every wave knows where its records of each slot go
     uint32_t wb;
@@ -911,6 +917,7 @@ __device__ __forceinline__ void range_body(RangeLds &L, const Seg *__restrict__ 
     gu64 *grec = (gu64 *)sg.rec;
     const uint64_t last_rec = rg.begin + rg.n - 1;
     uint64_t a0[ROWS], a1[ROWS], a2[ROWS], b0[ROWS], b1[ROWS], b2[ROWS];
+    uint32_t wc[5] = {0, 0, 0, 0, 0};   // this wave's record counts over the range
 #pragma unroll
     for (int r = 0; r < ROWS; r++) {
       const uint32_t li = (uint32_t)gw * (T / GW) + (uint32_t)r * WAVE + lane;
@@ -926,12 +933,18 @@ __device__ __forceinline__ void range_body(RangeLds &L, const Seg *__restrict__ 
       // PIPE: the half of tile t - 2 must have been walked
       if (PIPE && t >= 2) wait_at_least(&L.misc[6], (uint32_t)(t - 1), tb.err);
       front_tile<FMT, ROWS, PIPE>(L, tb, E, KL, D, rg, sg, grec, last_rec, t * T, hb, a0, a1, a2, b0, b1, b2,
-                                  pay_run);
+                                  pay_run, wc);
       if (PIPE) publish(&L.misc[5], (uint32_t)(t + 1), w == (int)GW && lane == 0);
       else walk_tile<FMT>(L, tb, E, D, 0, T, RNW, sbase, ru);
       if (!PIPE) __syncthreads();
 #pragma unroll
       for (int r = 0; r < ROWS; r++) { a0[r] = b0[r]; a1[r] = b1[r]; a2[r] = b2[r]; }
+    }
+    if (lane == 0) {
+      const int idx[5] = {ST_ENTRIES, ST_EXITS, ST_KERNEL, ST_BAD, ST_RECORDS};
+#pragma unroll
+      for (int k = 0; k < 5; k++)
+        if (wc[k]) lds_add32(&L.cnt[idx[k]], wc[k]);
     }
   } else {
     // walker

@@ -68,7 +68,8 @@ struct RangeLds {
   uint64_t *tidmap;
   uint32_t *wcnt, *soff;
   uint32_t *newtid, *newbucket;
-  uint32_t *misc;   // [0] nslots, [1] new ids, [2] nd, [3..6] producer/walker sync, [7..8] nslots per half
+  uint32_t *misc;   // [0] nslots, [1] new ids, [2] nd, [3] builder barrier, [5] tiles built,
+                    // [7..8] nslots per half, [16..] tiles walked per walking wave
   uint32_t *cnt;    // [ST_N] range-local counters
   uint32_t nd;      // slots of the direct-mapped tally region, chosen per range at its first tile
   uint32_t *wsum;   // [RNW] per-wave payload sums
@@ -128,7 +129,7 @@ __host__ __device__ inline size_t range_lds_layout(uint8_t *base, RangeLds *L, u
   TAKE(soff, uint32_t, 2 * (S_MAX + 1));
   TAKE(newtid, uint32_t, TIDMAP);
   TAKE(newbucket, uint32_t, TIDMAP);
-  TAKE(misc, uint32_t, 16);
+  TAKE(misc, uint32_t, 32);
   TAKE(cnt, uint32_t, ST_N);
   TAKE(wsum, uint32_t, RNW);
 #undef TAKE
@@ -513,25 +514,51 @@ __device__ __forceinline__ void slot_window(RangeLds &L, const Tables &tb, const
   wave_lds_fence();
 }
 
-// All windows of slot s in this tile, records [b, e) of the sorted tile.
+// A walking wave keeps the state of the slot it walks in registers (and its
+// floor accumulator in wvt[0]) from one tile to the next while it walks that
+// slot only; it goes back to LDS when the wave turns to another slot and at
+// the range end.
+struct WalkCache {
+  uint32_t slot;   // EMPTY32: nothing cached
+  uint32_t gslot;
+  SlotState S;
+};
+
+__device__ __forceinline__ void slot_load(const RangeLds &L, const uint32_t s, WalkCache &c, uint64_t *wvt) {
+  c.slot = s;
+  c.S.d = __builtin_amdgcn_readfirstlane(L.s_d[s]);
+  c.S.fl = -__builtin_amdgcn_readfirstlane(L.s_u[s]);
+  c.S.H = __builtin_amdgcn_readfirstlane(L.s_H[s]);
+  c.S.M = __builtin_amdgcn_readfirstlane(L.s_M[s]);
+  c.S.flags = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)L.s_flags[s]);
+  c.S.facc = 0;  // (lives in wvt[0])
+  c.S.first = uread64(L.s_first[s], 0);
+  c.S.last = uread64(L.s_last[s], 0);
+  c.gslot = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)L.s_gslot[s]);
+  if (__lane_id() == 0) wvt[0] = L.s_facc[s];
+  wave_lds_fence();
+}
+
+__device__ __forceinline__ void slot_store(RangeLds &L, WalkCache &c, const uint64_t *wvt) {
+  if (c.slot == EMPTY32) return;
+  const uint32_t s = c.slot;
+  if (__lane_id() == 0) {
+    L.s_d[s] = c.S.d; L.s_u[s] = -c.S.fl; L.s_H[s] = c.S.H; L.s_M[s] = c.S.M; L.s_flags[s] = c.S.flags;
+    L.s_facc[s] = wvt[0]; L.s_first[s] = c.S.first; L.s_last[s] = c.S.last;
+  }
+  c.slot = EMPTY32;
+  wave_lds_fence();
+}
+
+// All windows of the cached slot in this tile, records [b, e) of the sorted tile.
 template <int FMT>
 __device__ __forceinline__ void slot_walk(RangeLds &L, const Tables &tb, const uint32_t E, const uint32_t D,
-                                          const uint32_t s, const uint32_t b, const uint32_t e, const size_t sbase,
+                                          WalkCache &c, const uint32_t b, const uint32_t e, const size_t sbase,
                                           UItem *__restrict__ ru, uint64_t *__restrict__ wch,
                                           uint64_t *__restrict__ wvt) {
-  SlotState S;
-  S.d = __builtin_amdgcn_readfirstlane(L.s_d[s]);
-  S.fl = -__builtin_amdgcn_readfirstlane(L.s_u[s]);
-  S.H = __builtin_amdgcn_readfirstlane(L.s_H[s]);
-  S.M = __builtin_amdgcn_readfirstlane(L.s_M[s]);
-  S.flags = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)L.s_flags[s]);
-  S.facc = uread64(L.s_facc[s], 0);
-  S.first = uread64(L.s_first[s], 0);
-  S.last = uread64(L.s_last[s], 0);
-  const uint32_t gslot = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)L.s_gslot[s]);
+  const uint32_t s = c.slot;
   UItem *us = ru + (sbase + s) * D;
   const uint32_t lane = __lane_id();
-  if (lane == 0) wvt[0] = S.facc;
   // each window's records are loaded one window ahead (the sorted tile does
   // not change during the walk)
   uint32_t p = b + (lane < e - b ? lane : 0);
@@ -542,12 +569,33 @@ __device__ __forceinline__ void slot_walk(RangeLds &L, const Tables &tb, const u
     p = an < e ? an + (lane < e - an ? lane : 0) : b;
     const uint64_t ts_n = L.cts[p], by_n = FMT == 2 ? L.cby[p] : 0;
     const uint32_t fk_n = L.cfk[p];
-    slot_window<FMT>(L, tb, E, D, s, gslot, a, (e - a) < WAVE ? (e - a) : WAVE, ts, fk, by, S, us, wch, wvt);
+    slot_window<FMT>(L, tb, E, D, s, c.gslot, a, (e - a) < WAVE ? (e - a) : WAVE, ts, fk, by, c.S, us, wch, wvt);
     ts = ts_n; fk = fk_n; by = by_n;
   }
-  if (lane == 0) {
-    L.s_d[s] = S.d; L.s_u[s] = -S.fl; L.s_H[s] = S.H; L.s_M[s] = S.M; L.s_flags[s] = S.flags;
-    L.s_facc[s] = wvt[0]; L.s_first[s] = S.first; L.s_last[s] = S.last;
+}
+
+// The walk of one sorted tile: wavefront w walks the thread slots w, w + nww,
+// ... (nww walking waves), each slot's records in order.
+template <int FMT>
+__device__ __forceinline__ void walk_tile(RangeLds &L, const Tables &tb, const uint32_t E, const uint32_t D,
+                                          const uint32_t hb, const uint32_t half, const uint32_t nww,
+                                          const size_t sbase, UItem *__restrict__ ru, WalkCache &c) {
+  const uint32_t w = threadIdx.x >> 6;
+  const uint32_t *soff = L.soff + hb * (S_MAX + 1);
+  L.cts = L.tile_ts + hb * half;
+  L.cfk = L.tile_fk + hb * half;
+  L.cby = L.tile_by + hb * half;
+  L.nd = L.misc[2];
+  const uint32_t nslots = L.misc[7 + hb];
+  uint64_t *wch = L.w_ch + w * WAVE, *wvt = L.w_vt + w * (D + 1);
+  for (uint32_t s = w; s < nslots; s += nww) {
+    const uint32_t b = soff[s], e = soff[s + 1];
+    if (b == e) continue;
+    if (c.slot != s) {
+      slot_store(L, c, wvt);
+      slot_load(L, s, c, wvt);
+    }
+    slot_walk<FMT>(L, tb, E, D, c, b, e, sbase, ru, wch, wvt);
   }
 }
 
@@ -851,24 +899,6 @@ __device__ __forceinline__ void front_tile(RangeLds &L, const Tables &tb, const 
     gbar();
 }
 
-// The walk of one sorted tile: wavefront w walks the thread slots w, w + nww,
-// ... (nww walking waves), each slot's records in order.
-template <int FMT>
-__device__ __forceinline__ void walk_tile(RangeLds &L, const Tables &tb, const uint32_t E, const uint32_t D,
-                                          const uint32_t hb, const uint32_t half, const uint32_t nww,
-                                          const size_t sbase, UItem *__restrict__ ru) {
-  const uint32_t w = threadIdx.x >> 6;
-  const uint32_t *soff = L.soff + hb * (S_MAX + 1);
-  L.cts = L.tile_ts + hb * half;
-  L.cfk = L.tile_fk + hb * half;
-  L.cby = L.tile_by + hb * half;
-  L.nd = L.misc[2];
-  const uint32_t nslots = L.misc[7 + hb];
-  for (uint32_t s = w; s < nslots; s += nww) {
-    const uint32_t b = soff[s], e = soff[s + 1];
-    if (b < e) slot_walk<FMT>(L, tb, E, D, s, b, e, sbase, ru, L.w_ch + w * WAVE, L.w_vt + w * (D + 1));
-  }
-}
 
 // ------------------------------------------------------------------ kernel
 // One whole range: LDS set-up, every tile, then the range summaries and the
@@ -903,7 +933,7 @@ __device__ __forceinline__ void range_body(RangeLds &L, const Seg *__restrict__ 
     L.s_facc[i] = 0; L.s_first[i] = 0; L.s_last[i] = 0;
   }
   for (uint32_t i = tid; i < ST_N; i += RWG) L.cnt[i] = 0;
-  if (tid < 16) L.misc[tid] = 0;
+  if (tid < 32) L.misc[tid] = 0;
   __syncthreads();
 
   const size_t sbase = (size_t)rid * S_MAX;
@@ -918,6 +948,8 @@ __device__ __forceinline__ void range_body(RangeLds &L, const Seg *__restrict__ 
     const uint64_t last_rec = rg.begin + rg.n - 1;
     uint64_t a0[ROWS], a1[ROWS], a2[ROWS], b0[ROWS], b1[ROWS], b2[ROWS];
     uint32_t wc[5] = {0, 0, 0, 0, 0};   // this wave's record counts over the range
+    WalkCache wcache;
+    wcache.slot = EMPTY32;
 #pragma unroll
     for (int r = 0; r < ROWS; r++) {
       const uint32_t li = (uint32_t)gw * (T / GW) + (uint32_t)r * WAVE + lane;
@@ -931,15 +963,17 @@ __device__ __forceinline__ void range_body(RangeLds &L, const Seg *__restrict__ 
     for (uint64_t t = 0; t < ntiles; t++) {
       const uint32_t hb = PIPE ? (uint32_t)(t & 1) : 0u;
       // PIPE: the half of tile t - 2 must have been walked
-      if (PIPE && t >= 2) wait_at_least(&L.misc[6], (uint32_t)(t - 1), tb.err);
+      if (PIPE && t >= 2)
+        for (uint32_t v = 0; v < GW; v++) wait_at_least(&L.misc[16 + v], (uint32_t)(t - 1), tb.err);
       front_tile<FMT, ROWS, PIPE>(L, tb, E, KL, D, rg, sg, grec, last_rec, t * T, hb, a0, a1, a2, b0, b1, b2,
                                   pay_run, wc);
       if (PIPE) publish(&L.misc[5], (uint32_t)(t + 1), w == (int)GW && lane == 0);
-      else walk_tile<FMT>(L, tb, E, D, 0, T, RNW, sbase, ru);
+      else walk_tile<FMT>(L, tb, E, D, 0, T, RNW, sbase, ru, wcache);
       if (!PIPE) __syncthreads();
 #pragma unroll
       for (int r = 0; r < ROWS; r++) { a0[r] = b0[r]; a1[r] = b1[r]; a2[r] = b2[r]; }
     }
+    if (!PIPE) slot_store(L, wcache, L.w_vt + w * (D + 1));
     if (lane == 0) {
       const int idx[5] = {ST_ENTRIES, ST_EXITS, ST_KERNEL, ST_BAD, ST_RECORDS};
 #pragma unroll
@@ -947,13 +981,15 @@ __device__ __forceinline__ void range_body(RangeLds &L, const Seg *__restrict__ 
         if (wc[k]) lds_add32(&L.cnt[idx[k]], wc[k]);
     }
   } else {
-    // walker
+    // walker: its own progress counter tells the builders which half is free
+    WalkCache wcache;
+    wcache.slot = EMPTY32;
     for (uint64_t t = 0; t < ntiles; t++) {
       wait_at_least(&L.misc[5], (uint32_t)(t + 1), tb.err);
-      walk_tile<FMT>(L, tb, E, D, (uint32_t)(t & 1), T, GW, sbase, ru);
-      group_barrier(&L.misc[4], GW, tb.err);
-      publish(&L.misc[6], (uint32_t)(t + 1), w == 0 && lane == 0);
+      walk_tile<FMT>(L, tb, E, D, (uint32_t)(t & 1), T, GW, sbase, ru, wcache);
+      publish(&L.misc[16 + w], (uint32_t)(t + 1), lane == 0);
     }
+    slot_store(L, wcache, L.w_vt + w * (D + 1));
   }
   __syncthreads();
   L.nd = L.misc[2];

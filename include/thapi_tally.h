@@ -36,7 +36,8 @@ extern "C" {
 /* ---- status codes ------------------------------------------------------ */
 #define THAPI_OK            0
 #define THAPI_E_INVAL      -1  /* null argument, bad ABI version, bad config, record bytes not a
-                                  multiple of the record size, payload size != sum of payload_len */
+                                  multiple of the record size, payload size != sum of payload_len
+                                  (device input: reported by the flush; handle is failed) */
 #define THAPI_E_NOMEM      -2  /* device allocation failed, or a chunk larger than the whole budget */
 #define THAPI_E_AGAIN      -3  /* over the device budget with THAPI_NONBLOCKING: retry later */
 #define THAPI_E_DEPTH      -4  /* some thread's call stack exceeded max_depth; handle is failed */
@@ -158,6 +159,10 @@ int thapi_tally_open(const thapi_tally_config *cfg, thapi_tally **out);
  * THAPI_DEVICE_INPUT the pointers are device memory that must stay valid and
  * unmodified until a flush covering the returned ticket has returned.
  * payload/payload_bytes are used by VAR16 only (must be NULL/0 for FIXED24).
+ * VAR16 host input whose payload_len sum is not payload_bytes is refused
+ * here; device input is not read by submit (no synchronisation), and the
+ * flush that tallies such a chunk fails with THAPI_E_INVAL instead, having
+ * read no byte outside [payload, payload + payload_bytes).
  * Thread-safe.  Errors: THAPI_E_INVAL, THAPI_E_NOMEM, THAPI_E_AGAIN,
  * THAPI_E_CAPACITY (too many streams), THAPI_E_STATE. */
 int thapi_tally_submit(thapi_tally *t, const thapi_stream_key *key,
@@ -168,6 +173,7 @@ int thapi_tally_submit(thapi_tally *t, const thapi_stream_key *key,
  * GPU pipeline and waits for it.  THAPI_FLUSH_FINAL also closes all streams:
  * open entries become unclosed_final and no further submit is accepted.
  * Errors: THAPI_E_DEPTH, THAPI_E_CAPACITY, THAPI_E_MALFORMED (STRICT),
+ * THAPI_E_INVAL (VAR16 device input with a payload size mismatch),
  * THAPI_E_DEVICE, THAPI_E_STATE. */
 int thapi_tally_flush(thapi_tally *t, uint64_t ticket, uint32_t flags);
 

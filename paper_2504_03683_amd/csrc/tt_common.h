@@ -25,7 +25,7 @@ enum : int {
 };
 
 // Error bits raised by kernels (sticky per flush).
-enum : uint32_t { ERR_CAPACITY = 1u, ERR_RANGE_THREADS = 2u, ERR_DEPTH = 4u, ERR_PIPE = 8u };
+enum : uint32_t { ERR_CAPACITY = 1u, ERR_RANGE_THREADS = 2u, ERR_DEPTH = 4u, ERR_PIPE = 8u, ERR_PAYLOAD = 16u };
 
 // One submitted chunk, as the kernels see it.
 struct Seg {

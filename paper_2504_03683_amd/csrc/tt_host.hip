@@ -33,7 +33,7 @@ hipError_t launch_range(int fmt, uint32_t T, const Seg *segs, const Range *range
                         RHdr *rhdr, UItem *ru, OItem *ro, uint32_t *rnslots, hipStream_t st);
 hipError_t prepare_range_kernels(uint32_t max_lds_bytes);
 hipError_t launch_paylen(const Seg *segs, Range *ranges, uint32_t n_ranges, const uint32_t *seg_first_range,
-                         uint32_t n_segs, uint64_t *paylen, hipStream_t st);
+                         uint32_t n_segs, uint64_t *paylen, uint32_t *err, hipStream_t st);
 hipError_t launch_fill64(uint64_t *p, size_t n, uint64_t v, hipStream_t st);
 hipError_t launch_fill32(uint32_t *p, size_t n, uint32_t v, hipStream_t st);
 hipError_t launch_init_tables(const Tables &tb, size_t n_tally, size_t n_ktally, hipStream_t st);
@@ -273,13 +273,6 @@ hipError_t ensure_pinned(thapi_tally *t, size_t bytes) {
 
 // Sum of payload_len of a device VAR16 header buffer (used to validate a
 // device-input submit before it is accepted).
-__global__ void k_sum_plen(const uint8_t *rec, uint64_t n, unsigned long long *out) {
-  uint64_t s = 0;
-  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
-    s += rec[i * 16 + 15];
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
-  if ((threadIdx.x & 63) == 0 && s) atomicAdd(out, (unsigned long long)s);
-}
 
 }  // namespace
 
@@ -458,27 +451,15 @@ int thapi_tally_submit(thapi_tally *t, const thapi_stream_key *key, const void *
     if (t->finalized) return THAPI_E_STATE;
   }
   if (hipSetDevice(t->dev) != hipSuccess) return THAPI_E_DEVICE;
-  // VAR16: the payload heap must hold exactly the declared payload lengths
-  if (var && n_rec) {
+  // VAR16: the payload heap must hold exactly the declared payload lengths.
+  // Host input is checked here; device input is checked on the GPU by the
+  // flush that tallies the chunk (no synchronisation per submit).
+  if (var && n_rec && !dev_in) {
     uint64_t sum = 0;
-    if (!dev_in) {
-      const uint8_t *r = (const uint8_t *)records;
-      for (uint64_t i = 0; i < n_rec; i++) sum += r[i * 16 + 15];
-    } else {
-      unsigned long long *d = nullptr;
-      if (hipMalloc(&d, 8) != hipSuccess) return THAPI_E_NOMEM;
-      launch_fill64((uint64_t *)d, 1, 0, t->st);
-      hipLaunchKernelGGL(k_sum_plen, dim3(std::min<uint64_t>((n_rec + 255) / 256, 4096)), dim3(256), 0, t->st,
-                         (const uint8_t *)records, n_rec, d);
-      unsigned long long hs = 0;
-      hipError_t e = hipMemcpyAsync(&hs, d, 8, hipMemcpyDeviceToHost, t->st);
-      if (e == hipSuccess) e = hipStreamSynchronize(t->st);
-      hipFree(d);
-      if (e != hipSuccess) { std::lock_guard<std::mutex> g(t->mu); return hip_fail(t, e); }
-      sum = hs;
-    }
+    const uint8_t *r = (const uint8_t *)records;
+    for (uint64_t i = 0; i < n_rec; i++) sum += r[i * 16 + 15];
     if (sum != payload_bytes) return THAPI_E_INVAL;
-  } else if (var && payload_bytes) {
+  } else if (var && !n_rec && payload_bytes) {
     return THAPI_E_INVAL;
   }
   std::unique_lock<std::mutex> lk(t->mu);
@@ -682,7 +663,7 @@ hipError_t launch_pipeline(thapi_tally *t, const Plan &pl, const Shape &sh, bool
     if (t->cfg.format == THAPI_FMT_VAR16) {
       TB(TM_PREPASS);
       LPCHK(launch_paylen(t->segs.as<Seg>(), t->ranges.as<Range>(), nR, t->segfirst.as<uint32_t>(), nS,
-                          t->paylen.as<uint64_t>(), t->st));
+                          t->paylen.as<uint64_t>(), t->tb.err, t->st));
       TE(TM_PREPASS);
     }
     LPCHK(launch_fill32(t->qhead.as<uint32_t>(), 1, 0, t->st));
@@ -829,6 +810,7 @@ int process_batch(thapi_tally *t, std::vector<Chunk> &work, bool final) {
     }
     t->cv.notify_all();
     if (err & ERR_PIPE) { t->failed = THAPI_E_DEVICE; rc = THAPI_E_DEVICE; }
+    else if (err & ERR_PAYLOAD) { t->failed = THAPI_E_INVAL; rc = THAPI_E_INVAL; }
     else if (err & (ERR_CAPACITY | ERR_RANGE_THREADS)) { t->failed = THAPI_E_CAPACITY; rc = THAPI_E_CAPACITY; }
     else if (err & ERR_DEPTH) { t->failed = THAPI_E_DEPTH; rc = THAPI_E_DEPTH; }
     if (final) t->finalized = true;

@@ -713,8 +713,13 @@ __device__ __forceinline__ void front_tile(RangeLds &L, const Tables &tb, const 
         const uint32_t li = (uint32_t)w * (T / GW) + (uint32_t)r * WAVE + lane;
         const uint32_t fn = r_fk[r] & 0xFFFFu, kind = (r_fk[r] >> 16) & 0xFFu, plen = r_fk[r] >> 24;
         const uint64_t off = pay_run + wpre + excl[r];
-        const bool sized = li < n && kind == 0 && fn < tb.n_fns && plen >= 8 && tb.has_size && tb.has_size[fn];
-        const bool kend = li < n && kind == 2 && plen >= 8;
+        // off + 8 <= pay_bytes holds for every well-formed chunk; a chunk whose
+        // payload_len sum disagrees with its heap fails the flush (ERR_PAYLOAD)
+        // and reads nothing outside the heap
+        const bool in_heap = off + 8 <= sg.pay_bytes;
+        const bool sized = li < n && kind == 0 && fn < tb.n_fns && plen >= 8 && in_heap && tb.has_size &&
+                           tb.has_size[fn];
+        const bool kend = li < n && kind == 2 && plen >= 8 && in_heap;
         if (sized || kend) {
           const uint64_t v = load_u64_unaligned(sg.pay, off);
           if (sized) r_by[r] = v; else r_x[r] = v;
@@ -1089,18 +1094,25 @@ __global__ __launch_bounds__(WG) void k_range_paylen(const Seg *__restrict__ seg
   const Range rg = ranges[blockIdx.x];
   const Seg sg = segs[rg.seg];
   uint64_t s = 0;
-  for (uint64_t i = threadIdx.x; i < rg.n; i += WG) {
-    const uint64_t w1 = __builtin_nontemporal_load((gu64 *)(sg.rec + (rg.begin + i) * 16) + 1);
-    s += w1 >> 56;
+  gu64 *hdr = (gu64 *)(sg.rec + rg.begin * 16) + 1;   // word 1 of each header: payload_len in its top byte
+  uint64_t i = threadIdx.x;
+  for (; i + 7 * WG < rg.n; i += 8 * WG) {            // eight independent loads in flight per lane
+    uint64_t w[8];
+#pragma unroll
+    for (int k = 0; k < 8; k++) w[k] = __builtin_nontemporal_load(hdr + 2 * (i + (uint64_t)k * WG));
+#pragma unroll
+    for (int k = 0; k < 8; k++) s += w[k] >> 56;
   }
+  for (; i < rg.n; i += WG) s += __builtin_nontemporal_load(hdr + 2 * i) >> 56;
   atomicAdd(&acc, (unsigned long long)s);
   __syncthreads();
   if (threadIdx.x == 0) out[blockIdx.x] = acc;
 }
 
-// VAR16: exclusive prefix of the range payload sizes within each segment.
+// VAR16: exclusive prefix of the range payload sizes within each segment;
+// a segment whose payload_len sum is not its heap size raises ERR_PAYLOAD.
 __global__ void k_range_payoff(const Seg *__restrict__ segs, uint32_t n_segs, const uint32_t *__restrict__ seg_first_range,
-                               Range *__restrict__ ranges, const uint64_t *__restrict__ paylen) {
+                               Range *__restrict__ ranges, const uint64_t *__restrict__ paylen, uint32_t *err) {
   const uint32_t sgi = blockIdx.x * blockDim.x + threadIdx.x;
   if (sgi >= n_segs) return;
   uint64_t acc = 0;
@@ -1108,6 +1120,7 @@ __global__ void k_range_payoff(const Seg *__restrict__ segs, uint32_t n_segs, co
     ranges[r].pay_begin = acc;
     acc += paylen[r];
   }
+  if (acc != segs[sgi].pay_bytes) atomicOr(err, ERR_PAYLOAD);
 }
 
 // --------------------------------------------------------------- launchers
@@ -1153,11 +1166,11 @@ hipError_t launch_range(int fmt, uint32_t T, const Seg *segs, const Range *range
 }
 
 hipError_t launch_paylen(const Seg *segs, Range *ranges, uint32_t n_ranges, const uint32_t *seg_first_range,
-                         uint32_t n_segs, uint64_t *paylen, hipStream_t st) {
+                         uint32_t n_segs, uint64_t *paylen, uint32_t *err, hipStream_t st) {
   if (!n_ranges) return hipSuccess;
   hipLaunchKernelGGL(k_range_paylen, dim3(n_ranges), dim3(WG), 0, st, segs, ranges, paylen);
   hipLaunchKernelGGL(k_range_payoff, dim3((n_segs + 255) / 256), dim3(256), 0, st, segs, n_segs, seg_first_range,
-                     ranges, paylen);
+                     ranges, paylen, err);
   return hipGetLastError();
 }
 

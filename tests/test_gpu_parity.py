@@ -166,6 +166,28 @@ def test_submit_validation():
         assert t.submit_rc((0, 0, 3), rec) == T.E_CAPACITY         # max_streams
 
 
+def test_device_input_payload_mismatch():
+    """Device-input VAR16 is checked by the flush: a heap one byte short fails it
+    without reading outside the heap; after a reset the same handle is exact."""
+    import torch
+    say("case: device-input VAR16 payload size mismatch")
+    from paper_2504_03683_amd import tally as T
+    ev = [(T0, 1, 0, ENTRY, b"12345678"), (T0 + 5, 1, 1, ENTRY, b""), (T0 + 9, 1, 1, EXIT, b""),
+          (T0 + 20, 1, 0, EXIT, b"")]
+    hdr, pay = var16(ev)
+    dh = torch.from_numpy(np.frombuffer(hdr, np.uint8).copy()).cuda()
+    dp = torch.from_numpy(np.frombuffer(pay, np.uint8).copy()).cuda()
+    with T.Tally(T.FMT_VAR16, 4, 0, max_threads=64, max_streams=4, flags=T.DEVICE_INPUT) as t:
+        assert t.submit_rc((0, 0, 1), dh, dp[:-1]) == T.OK
+        assert t.flush_rc(final=True) == T.E_INVAL
+        assert t.submit_rc((0, 0, 1), dh, dp) == T.E_STATE
+        t.reset()
+        assert t.submit_rc((0, 0, 1), dh, dp) == T.OK
+        t.flush(final=True)
+        rows, st = t.read()
+        assert st["records"] == 4 and len(rows) == 2
+
+
 def test_reset_and_repeat_determinism():
     say("case: reset and repeat")
     from paper_2504_03683_amd import tally as T

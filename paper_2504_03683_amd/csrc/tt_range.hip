@@ -68,7 +68,7 @@ struct RangeLds {
   uint64_t *tidmap;
   uint32_t *wcnt, *soff;
   uint32_t *newtid, *newbucket;
-  uint32_t *misc;   // [0] nslots, [1] new ids, [2] nd, [3] builder barrier, [5] tiles built,
+  uint32_t *misc;   // [0] nslots, [1] new ids, [2] nd, [3] builder barrier, [5] tiles built x producer waves,
                     // [7..8] nslots per half, [16..] tiles walked per walking wave
   uint32_t *cnt;    // [ST_N] range-local counters
   uint32_t nd;      // slots of the direct-mapped tally region, chosen per range at its first tile
@@ -319,25 +319,38 @@ __device__ __forceinline__ int32_t dpp(int32_t old, int32_t v) {
 __device__ __forceinline__ int32_t imin(int32_t a, int32_t b) { return a < b ? a : b; }
 __device__ __forceinline__ int32_t imax(int32_t a, int32_t b) { return a > b ? a : b; }
 // Inclusive prefix minimum / maximum over the 64 lanes (row scans, then the
-// row ends broadcast to the rows above).
+// row ends broadcast to the rows above).  Lanes without a source see the
+// operation's identity, so each step can be a single DPP min / max.
+constexpr int32_t I32_MAX = 0x7FFFFFFF, I32_MIN = -0x7FFFFFFF - 1;
 __device__ __forceinline__ int32_t wave_scan_min(int32_t v) {
-  v = imin(v, dpp<0x111>(BIG, v));
-  v = imin(v, dpp<0x112>(BIG, v));
-  v = imin(v, dpp<0x114>(BIG, v));
-  v = imin(v, dpp<0x118>(BIG, v));
-  v = imin(v, dpp<0x142, 0xA>(BIG, v));
-  v = imin(v, dpp<0x143, 0xC>(BIG, v));
+  v = imin(v, dpp<0x111>(I32_MAX, v));
+  v = imin(v, dpp<0x112>(I32_MAX, v));
+  v = imin(v, dpp<0x114>(I32_MAX, v));
+  v = imin(v, dpp<0x118>(I32_MAX, v));
+  v = imin(v, dpp<0x142, 0xA>(I32_MAX, v));
+  v = imin(v, dpp<0x143, 0xC>(I32_MAX, v));
   return v;
 }
 __device__ __forceinline__ int32_t wave_scan_max(int32_t v) {
-  v = imax(v, dpp<0x111>(-BIG, v));
-  v = imax(v, dpp<0x112>(-BIG, v));
-  v = imax(v, dpp<0x114>(-BIG, v));
-  v = imax(v, dpp<0x118>(-BIG, v));
-  v = imax(v, dpp<0x142, 0xA>(-BIG, v));
-  v = imax(v, dpp<0x143, 0xC>(-BIG, v));
+  v = imax(v, dpp<0x111>(I32_MIN, v));
+  v = imax(v, dpp<0x112>(I32_MIN, v));
+  v = imax(v, dpp<0x114>(I32_MIN, v));
+  v = imax(v, dpp<0x118>(I32_MIN, v));
+  v = imax(v, dpp<0x142, 0xA>(I32_MIN, v));
+  v = imax(v, dpp<0x143, 0xC>(I32_MIN, v));
   return v;
 }
+// Both scans at once, step by step (two independent chains).
+__device__ __forceinline__ void wave_scan_minmax(int32_t &mn, int32_t &mx) {
+  mn = imin(mn, dpp<0x111>(I32_MAX, mn)); mx = imax(mx, dpp<0x111>(I32_MIN, mx));
+  mn = imin(mn, dpp<0x112>(I32_MAX, mn)); mx = imax(mx, dpp<0x112>(I32_MIN, mx));
+  mn = imin(mn, dpp<0x114>(I32_MAX, mn)); mx = imax(mx, dpp<0x114>(I32_MIN, mx));
+  mn = imin(mn, dpp<0x118>(I32_MAX, mn)); mx = imax(mx, dpp<0x118>(I32_MIN, mx));
+  mn = imin(mn, dpp<0x142, 0xA>(I32_MAX, mn)); mx = imax(mx, dpp<0x142, 0xA>(I32_MIN, mx));
+  mn = imin(mn, dpp<0x143, 0xC>(I32_MAX, mn)); mx = imax(mx, dpp<0x143, 0xC>(I32_MIN, mx));
+}
+// v_writelane: lane `lane` of the result is v (uniform), the others keep old.
+__device__ int32_t amd_writelane(int32_t v, int32_t lane, int32_t old) __asm("llvm.amdgcn.writelane.i32");
 __device__ __forceinline__ int32_t lane63(int32_t v) { return __builtin_amdgcn_readlane(v, 63); }
 __device__ __forceinline__ uint64_t bperm64(uint32_t lo, uint32_t hi, int32_t src) {
   const uint32_t l = (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int32_t)lo);
@@ -387,7 +400,8 @@ __device__ __forceinline__ void slot_window(RangeLds &L, const Tables &tb, const
     const uint32_t plo = (uint32_t)dpp<0x138>((int32_t)(uint32_t)S.last, (int32_t)(uint32_t)ts);
     const uint32_t phi = (uint32_t)dpp<0x138>((int32_t)(uint32_t)(S.last >> 32), (int32_t)(uint32_t)(ts >> 32));
     const uint64_t prev = ((uint64_t)phi << 32) | plo;
-    if (valid && (lane > 0 || (S.flags & RF_HAS_TS)) && ts < prev) lds_add32(&L.cnt[ST_TSREG], 1u);
+    const uint64_t bad = __ballot(valid && (lane > 0 || (S.flags & RF_HAS_TS)) && ts < prev);
+    if (bad && lane == 0) lds_add32(&L.cnt[ST_TSREG], (uint32_t)__popcll(bad));
     if (!(S.flags & RF_HAS_TS)) S.first = uread64(ts, 0);
     S.last = uread64(ts, nw - 1);
     S.flags |= RF_HAS_TS;
@@ -398,9 +412,10 @@ __device__ __forceinline__ void slot_window(RangeLds &L, const Tables &tb, const
   const int32_t da = d0 + (int32_t)__popcll(Em & lt) - (int32_t)__popcll(Xm & lt) + (en ? 1 : 0) - (ex ? 1 : 0);
   const int32_t lev = en ? da : da + 1;
   const int32_t d_end = d0 + (int32_t)__popcll(Em) - (int32_t)__popcll(Xm);
-  const int32_t pmin = wave_scan_min(valid ? da : BIG);
+  int32_t pmin = valid ? da : BIG, pmax = valid ? da : -BIG;
+  wave_scan_minmax(pmin, pmax);
   const int32_t damin = imin(lane63(pmin), d0);     // lowest depth in the window
-  const int32_t dmax = imax(lane63(wave_scan_max(valid ? da : -BIG)), d0);
+  const int32_t dmax = imax(lane63(pmax), d0);
   const int32_t fl1 = imin(damin, fl0);             // floor after the window
   {
     const int32_t hub = dmax - fl1;                 // bounds the height above the floor in the window
@@ -413,11 +428,15 @@ __device__ __forceinline__ void slot_window(RangeLds &L, const Tables &tb, const
     S.M = imax(S.M, dmax);
   }
   // entries by level: lane k of (tlo, thi) holds the ballot of entries opening level damin + 1 + k
-  uint32_t tlo = 0, thi = 0;
+  int32_t tlo = 0, thi = 0;
   const int32_t vend = imin(dmax, damin + WAVE);    // (the levels of 64 records span at most 64)
-  for (int32_t v = damin + 1; v <= vend; v++) {
-    const uint64_t Ev = __ballot(en && lev == v);
-    if ((int32_t)lane == v - damin - 1) { tlo = (uint32_t)Ev; thi = (uint32_t)(Ev >> 32); }
+  {
+    const int32_t levE = en ? lev : -BIG;           // entries only
+    for (int32_t v = damin + 1, j = 0; v <= vend; v++, j++) {
+      const uint64_t Ev = __ballot(levE == v);
+      tlo = amd_writelane((int32_t)(uint32_t)Ev, j, tlo);
+      thi = amd_writelane((int32_t)(uint32_t)(Ev >> 32), j, thi);
+    }
   }
   const int32_t k = valid ? lev - damin - 1 : 0;
   const uint64_t Elev = bperm64(tlo, thi, k);
@@ -427,70 +446,97 @@ __device__ __forceinline__ void slot_window(RangeLds &L, const Tables &tb, const
   const bool open_at_end = en && lev <= d_end && msb64(Elev) == (int32_t)lane;
   wch[lane] = 0;
   if (lane >= 1 && lane <= D) wvt[lane] = 0;
-  // the entry each exit closes: in the window, on the carried stack, or opened before the range
-  int kind = 0;  // 1 window, 2 carried, 3 opened before the range, 4 beyond the stack capacity
-  uint32_t cpos = 0;
-  uint64_t pts = 0, pby = 0;
-  uint32_t pfn = 0;
-  if (ex) {
-    if (partner >= 0) {
-      kind = 1;
-      pts = L.cts[a + partner];
-      pfn = L.cfk[a + partner] & 0xFFFFu;
-      if (FMT == 2) pby = L.cby[a + partner];
-    } else if (lev > fl0) {
-      cpos = (uint32_t)(lev - fl0 - 1);
-      if (cpos < D) {
-        kind = 2;
-        const uint32_t i = s * D + cpos;
-        pts = L.c_ts[i]; pfn = L.c_fn[i];
-        if (FMT == 2) pby = L.c_by[i];
-      } else {
-        kind = 4;
-      }
-    } else {
-      kind = 3;
-    }
-  }
-  bool ok = false;
-  uint64_t incl = 0;
-  if (kind == 1 || kind == 2) {
-    if (pfn != fn) lds_add32(&L.cnt[ST_MISMATCH], 1u);
-    else if (ts < pts) lds_add32(&L.cnt[ST_NEGDUR], 1u);
-    else { ok = true; incl = ts - pts; }
-  }
-  wave_lds_fence();
-  // children time to the parent
-  if (ok) {
-    if (parent >= 0) {
-      lds_add64(&wch[parent], incl);
-    } else {
-      const int32_t pl = lev - 1;
-      if (pl > fl0) {
-        const uint32_t pp = (uint32_t)(pl - fl0 - 1);
-        if (pp < D) lds_add64(&L.c_ch[s * D + pp], incl);
-      } else {
-        const uint32_t vk = (uint32_t)(fl0 - pl);
-        if (vk == 0 || (vk <= D && (uint32_t)u0 + vk < D)) lds_add64(&wvt[vk], incl);
+  // the entry each exit closes: in the window (inw), on the carried stack
+  // (car), or opened before the range (pre); an exit whose carried position
+  // lies beyond the stack capacity closes nothing here (the range is already
+  // flagged as overflowing).  Both candidate entries are read by every lane.
+  const bool inw = ex && partner >= 0;
+  const uint32_t cpos = (uint32_t)(lev - fl0 - 1);
+  const bool car = ex && partner < 0 && lev > fl0 && cpos < D;
+  const bool pre = ex && partner < 0 && lev <= fl0;
+  const uint32_t wi = a + (uint32_t)(partner >= 0 ? partner : 0);
+  const uint32_t ci = s * D + (car ? cpos : 0u);
+  const uint64_t wts = L.cts[wi], cts = L.c_ts[ci];
+  const uint32_t wfn = L.cfk[wi] & 0xFFFFu, cfn = L.c_fn[ci];
+  const uint64_t pts = inw ? wts : cts;
+  const uint32_t pfn = inw ? wfn : cfn;
+  uint64_t pby = 0;
+  if (FMT == 2) pby = inw ? L.cby[wi] : L.c_by[ci];
+  const bool matched = inw || car;
+  const bool mis = matched && pfn != fn;
+  const bool neg = matched && pfn == fn && ts < pts;
+  const bool ok = matched && pfn == fn && ts >= pts;
+  const uint64_t incl = ok ? ts - pts : 0;
+  {
+    const uint64_t mm = __ballot(mis), nm = __ballot(neg);
+    if (mm | nm) {
+      if (lane == 0) {
+        if (mm) lds_add32(&L.cnt[ST_MISMATCH], (uint32_t)__popcll(mm));
+        if (nm) lds_add32(&L.cnt[ST_NEGDUR], (uint32_t)__popcll(nm));
       }
     }
   }
   wave_lds_fence();
-  // self time and tally of every call closed here; exits that close calls opened before the range
-  if (ok) {
-    const uint64_t ch = kind == 1 ? wch[partner] : L.c_ch[s * D + cpos];
-    uint64_t self;
-    if (ch <= incl) self = incl - ch;
-    else { self = 0; lds_add32(&L.cnt[ST_UNDER], 1u); }
-    tally_call<FMT>(L, E, tb, s, gslot, fn, incl, self, pby);
-  } else if (kind == 3) {
-    const uint32_t vk = (uint32_t)(fl0 - lev);
-    const uint32_t gi = (uint32_t)u0 + vk;
-    if (gi < D) {
-      UItem *u = &us[gi];
-      u->ts = ts; u->child = wvt[vk]; u->fn = fn; u->pad = 0; u->pad2 = 0;
-    } else {
-      lds_add32(&L.cnt[ST_ORPHAN], 1u);  // deeper than any stack can be: certainly an orphan exit
+  // children time to the parent: in the window, on the carried stack, or the
+  // accumulator of a level below the floor
+  {
+    const int32_t pl = lev - 1;
+    const uint32_t pp = (uint32_t)(pl - fl0 - 1), vk = (uint32_t)(fl0 - pl);
+    const bool to_w = parent >= 0;
+    const bool to_c = !to_w && pl > fl0 && pp < D;
+    const bool to_v = !to_w && pl <= fl0 && (vk == 0 || (vk <= D && (uint32_t)u0 + vk < D));
+    uint64_t *dst = to_w ? &wch[parent >= 0 ? parent : 0] : to_c ? &L.c_ch[s * D + (to_c ? pp : 0u)]
+                                                                  : &wvt[to_v ? vk : 0u];
+    if (ok && (to_w || to_c || to_v)) lds_add64(dst, incl);
+  }
+  wave_lds_fence();
+  // self time and tally of every call closed here
+  {
+    const uint64_t wc = wch[partner >= 0 ? partner : 0], cc = L.c_ch[ci];
+    const uint64_t ch = inw ? wc : cc;
+    const bool under = ok && ch > incl;
+    const uint64_t self = (ok && !under) ? incl - ch : 0;
+    const uint64_t um = __ballot(under);
+    if (um && lane == 0) lds_add32(&L.cnt[ST_UNDER], (uint32_t)__popcll(um));
+    const bool tal = ok && fn < tb.n_fns;
+    if (s < L.nd) {
+      // direct-mapped rows of this slot; 32-bit min/max take no-op operands
+      // for durations of 2^32 ns or more, which go to the global row instead
+      const uint32_t h = s * tb.n_fns + (tal ? fn : 0u);
+      if (tal) {
+        lds_add32(&L.t_cnt[h], 1u);
+        lds_add64(&L.t_isum[h], incl);
+        lds_add64(&L.t_ssum[h], self);
+        if (FMT == 2) lds_add64(&L.t_bsum[h], pby);
+        const bool ib = incl >= EMPTY32, sb = self >= EMPTY32;
+        lds_min32(&L.t_imin[h], ib ? EMPTY32 : (uint32_t)incl);
+        lds_max32(&L.t_imax[h], ib ? 0u : (uint32_t)incl);
+        lds_min32(&L.t_smin[h], sb ? EMPTY32 : (uint32_t)self);
+        lds_max32(&L.t_smax[h], sb ? 0u : (uint32_t)self);
+      }
+      const bool big = tal && (incl >= EMPTY32 || self >= EMPTY32) && gslot < tb.max_threads;
+      if (__ballot(big)) {
+        if (big) {
+          Tally *g = &tb.tally[(size_t)gslot * tb.n_fns + fn];
+          if (incl >= EMPTY32) { g_min64(&g->incl_min, incl); g_max64(&g->incl_max, incl); }
+          if (self >= EMPTY32) { g_min64(&g->self_min, self); g_max64(&g->self_max, self); }
+        }
+      }
+    } else if (tal) {
+      tally_call<FMT>(L, E, tb, s, gslot, fn, incl, self, pby);
+    }
+  }
+  // exits that close calls opened before the range become U items
+  if (__ballot(pre)) {
+    if (pre) {
+      const uint32_t vk = (uint32_t)(fl0 - lev);
+      const uint32_t gi = (uint32_t)u0 + vk;
+      if (gi < D) {
+        UItem *u = &us[gi];
+        u->ts = ts; u->child = wvt[vk]; u->fn = fn; u->pad = 0; u->pad2 = 0;
+      } else {
+        lds_add32(&L.cnt[ST_ORPHAN], 1u);  // deeper than any stack can be: certainly an orphan exit
+      }
     }
   }
   wave_lds_fence();
@@ -580,7 +626,7 @@ template <int FMT>
 __device__ __forceinline__ void walk_tile(RangeLds &L, const Tables &tb, const uint32_t E, const uint32_t D,
                                           const uint32_t hb, const uint32_t half, const uint32_t nww,
                                           const size_t sbase, UItem *__restrict__ ru, WalkCache &c) {
-  const uint32_t w = threadIdx.x >> 6;
+  const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));   // (wave-uniform)
   const uint32_t *soff = L.soff + hb * (S_MAX + 1);
   L.cts = L.tile_ts + hb * half;
   L.cfk = L.tile_fk + hb * half;
@@ -614,6 +660,18 @@ __device__ inline void wait_at_least(uint32_t *ctr, uint32_t v, uint32_t *err) {
     }
   }
   __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Waits until ctr[k] >= v for every k < n (n <= 64): lane k polls ctr[k].
+__device__ inline void wait_all_at_least(uint32_t *ctr, uint32_t n, uint32_t v, uint32_t *err) {
+  const uint32_t lane = __lane_id();
+  uint32_t i = 0;
+  while (__ballot(lane < n && __hip_atomic_load(&ctr[lane < n ? lane : 0], __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_WORKGROUP) < v)) {
+    __builtin_amdgcn_s_sleep(1);
+    if (++i == SPIN_LIMIT) { if (lane == 0) atomicOr(err, ERR_PIPE); break; }
+  }
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
@@ -660,7 +718,7 @@ __device__ __forceinline__ void front_tile(RangeLds &L, const Tables &tb, const 
   constexpr uint32_t T = ROWS * GW * WAVE;          // records per tile
   constexpr uint32_t RS = FMT == 2 ? 16 : 24;
   const int lane = threadIdx.x & (WAVE - 1);
-  const int w = (int)(threadIdx.x >> 6) - (PIPE ? (int)(RNW / 2) : 0);   // wave within the group
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) - (PIPE ? (int)(RNW / 2) : 0);   // wave within the group
   const int tid = w * WAVE + lane;                                       // lane within the group
   const uint32_t n = (uint32_t)((rg.n - t0) < T ? (rg.n - t0) : T);
   uint64_t *const tts = L.tile_ts + hb * T;
@@ -806,7 +864,10 @@ __device__ __forceinline__ void front_tile(RangeLds &L, const Tables &tb, const 
     // in this tile are ranked after their slots exist; no other record of
     // those slots is in the tile, so the order stays stable.
     const uint32_t nslots0 = L.misc[0];
-    if (lane < S_MAX) L.wcnt[w * S_MAX + lane] = 0;
+    // per-wave counts of this half (PIPE: the two halves use separate rows,
+    // so a wave may start the next tile while others still read these)
+    uint32_t *const wcnt = L.wcnt + (PIPE ? hb * GW * S_MAX : 0u);
+    if (lane < S_MAX) wcnt[w * S_MAX + lane] = 0;
     auto rank_rows = [&](const bool late, const uint32_t ns) {
       uint32_t nbits = 0;
       while ((1u << nbits) < ns) nbits++;
@@ -823,9 +884,9 @@ __device__ __forceinline__ void front_tile(RangeLds &L, const Tables &tb, const 
         const uint32_t rk = (uint32_t)__popcll(mask & lanemask_lt());
         const uint32_t c = (uint32_t)__popcll(mask);
         uint32_t base = 0;
-        if (valid) base = L.wcnt[w * S_MAX + s];
+        if (valid) base = wcnt[w * S_MAX + s];
         if (valid) r_rank[r] = base + rk;
-        if (valid && rk == 0) L.wcnt[w * S_MAX + s] = base + c;
+        if (valid && rk == 0) wcnt[w * S_MAX + s] = base + c;
       }
     };
     rank_rows(false, nslots0);
@@ -880,7 +941,7 @@ __device__ __forceinline__ void front_tile(RangeLds &L, const Tables &tb, const 
       uint32_t tot = 0, before = 0;
       if ((uint32_t)lane < nslots)
         for (int k = 0; k < (int)GW; k++) {
-          const uint32_t c = L.wcnt[k * S_MAX + lane];
+          const uint32_t c = wcnt[k * S_MAX + lane];
           tot += c;
           before += k < w ? c : 0;
         }
@@ -901,7 +962,8 @@ __device__ __forceinline__ void front_tile(RangeLds &L, const Tables &tb, const 
       tfk[pos] = (r_fk[r] & 0xFFFFu) | (((r_fk[r] >> 16) & 1u) << 16);
       if (FMT == 2) tby[pos] = r_by[r];
     }
-    gbar();
+    // PIPE: each wave publishes its part of the tile itself (no barrier)
+    if (!PIPE) __syncthreads();
 }
 
 
@@ -913,7 +975,8 @@ __device__ __forceinline__ void front_tile(RangeLds &L, const Tables &tb, const 
 // lockstep (workgroup barriers).  PIPE on: waves RNW/2 .. RNW-1 (producers)
 // build sorted tiles into the two halves of the tile region alternately while
 // waves 0 .. RNW/2-1 (walkers) walk the previous one; a tile is handed over
-// through two LDS counters (tiles built, tiles walked).
+// through LDS counters: every producer wave counts each tile it finished,
+// every walker publishes the tiles it has walked.
 template <int FMT, int ROWS, bool PIPE>
 __device__ __forceinline__ void range_body(RangeLds &L, const Seg *__restrict__ segs,
                                            const Range *__restrict__ ranges, const uint32_t rid, const Tables &tb,
@@ -922,7 +985,7 @@ __device__ __forceinline__ void range_body(RangeLds &L, const Seg *__restrict__ 
   constexpr uint32_t GW = PIPE ? RNW / 2 : RNW;     // waves that build tiles
   constexpr uint32_t T = ROWS * GW * WAVE;          // records per tile
   constexpr uint32_t RS = FMT == 2 ? 16 : 24;
-  const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const uint32_t D = tb.D, E = sh.E, KL = sh.KL;
   const Range rg = ranges[rid];
   const Seg sg = segs[rg.seg];
@@ -968,11 +1031,14 @@ __device__ __forceinline__ void range_body(RangeLds &L, const Seg *__restrict__ 
     for (uint64_t t = 0; t < ntiles; t++) {
       const uint32_t hb = PIPE ? (uint32_t)(t & 1) : 0u;
       // PIPE: the half of tile t - 2 must have been walked
-      if (PIPE && t >= 2)
-        for (uint32_t v = 0; v < GW; v++) wait_at_least(&L.misc[16 + v], (uint32_t)(t - 1), tb.err);
+      if (PIPE && t >= 2) wait_all_at_least(&L.misc[16], GW, (uint32_t)(t - 1), tb.err);
       front_tile<FMT, ROWS, PIPE>(L, tb, E, KL, D, rg, sg, grec, last_rec, t * T, hb, a0, a1, a2, b0, b1, b2,
                                   pay_run, wc);
-      if (PIPE) publish(&L.misc[5], (uint32_t)(t + 1), w == (int)GW && lane == 0);
+      if (PIPE) {
+        // one count per builder wave and tile
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        if (lane == 0) __hip_atomic_fetch_add(&L.misc[5], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
       else walk_tile<FMT>(L, tb, E, D, 0, T, RNW, sbase, ru, wcache);
       if (!PIPE) __syncthreads();
 #pragma unroll
@@ -990,7 +1056,7 @@ __device__ __forceinline__ void range_body(RangeLds &L, const Seg *__restrict__ 
     WalkCache wcache;
     wcache.slot = EMPTY32;
     for (uint64_t t = 0; t < ntiles; t++) {
-      wait_at_least(&L.misc[5], (uint32_t)(t + 1), tb.err);
+      wait_at_least(&L.misc[5], (uint32_t)(t + 1) * GW, tb.err);
       walk_tile<FMT>(L, tb, E, D, (uint32_t)(t & 1), T, GW, sbase, ru, wcache);
       publish(&L.misc[16 + w], (uint32_t)(t + 1), lane == 0);
     }

@@ -45,10 +45,6 @@ struct RangeLds {
   uint64_t *tile_ts;   // tile sorted by slot: timestamp
   uint64_t *tile_by;   // VAR16 transfer size of entries
   uint32_t *tile_fk;   // fn | kind << 16
-  // the sorted tile the walk reads (the tile region itself, or one half of it
-  // when producer and walker waves alternate between two halves)
-  const uint64_t *cts, *cby;
-  const uint32_t *cfk;
   // thread slots
   uint32_t *s_gslot, *s_flags;
   int32_t *s_d, *s_u, *s_H, *s_M;   // depth relative to the range start, virtual closes, excursion
@@ -381,11 +377,12 @@ struct SlotState {
 // carried stack (level above the floor), else it closes a call opened before
 // the range (level at or below the floor); its parent is found the same way
 // one level down.
-// The lane's record (ts, fk, by) was loaded by the caller ahead of time.
+// The lane's record (ts, fk, by) was loaded by the caller ahead of time; the
+// records of one window may come from two consecutive tiles.
 // wvt[0] holds the children time of the call at the floor across windows.
 template <int FMT>
 __device__ __forceinline__ void slot_window(RangeLds &L, const Tables &tb, const uint32_t E, const uint32_t D,
-                                            const uint32_t s, const uint32_t gslot, const uint32_t a,
+                                            const uint32_t s, const uint32_t gslot,
                                             const uint32_t nw, const uint64_t ts, const uint32_t fk,
                                             const uint64_t by, SlotState &S, UItem *__restrict__ us,
                                             uint64_t *__restrict__ wch, uint64_t *__restrict__ wvt) {
@@ -454,14 +451,17 @@ __device__ __forceinline__ void slot_window(RangeLds &L, const Tables &tb, const
   const uint32_t cpos = (uint32_t)(lev - fl0 - 1);
   const bool car = ex && partner < 0 && lev > fl0 && cpos < D;
   const bool pre = ex && partner < 0 && lev <= fl0;
-  const uint32_t wi = a + (uint32_t)(partner >= 0 ? partner : 0);
+  // the partner lane holds the entry's record (every lane takes part in the
+  // permutes: a permute reads 0 from a lane that does not)
+  const int32_t psrc = partner >= 0 ? partner : 0;
   const uint32_t ci = s * D + (car ? cpos : 0u);
-  const uint64_t wts = L.cts[wi], cts = L.c_ts[ci];
-  const uint32_t wfn = L.cfk[wi] & 0xFFFFu, cfn = L.c_fn[ci];
+  const uint64_t wts = bperm64((uint32_t)ts, (uint32_t)(ts >> 32), psrc), cts = L.c_ts[ci];
+  const uint32_t wfn = (uint32_t)__builtin_amdgcn_ds_bpermute(psrc << 2, (int32_t)fk) & 0xFFFFu, cfn = L.c_fn[ci];
+  const uint64_t wby = FMT == 2 ? bperm64((uint32_t)by, (uint32_t)(by >> 32), psrc) : 0;
   const uint64_t pts = inw ? wts : cts;
   const uint32_t pfn = inw ? wfn : cfn;
   uint64_t pby = 0;
-  if (FMT == 2) pby = inw ? L.cby[wi] : L.c_by[ci];
+  if (FMT == 2) pby = inw ? wby : L.c_by[ci];
   const bool matched = inw || car;
   const bool mis = matched && pfn != fn;
   const bool neg = matched && pfn == fn && ts < pts;
@@ -560,91 +560,6 @@ __device__ __forceinline__ void slot_window(RangeLds &L, const Tables &tb, const
   wave_lds_fence();
 }
 
-// A walking wave keeps the state of the slot it walks in registers (and its
-// floor accumulator in wvt[0]) from one tile to the next while it walks that
-// slot only; it goes back to LDS when the wave turns to another slot and at
-// the range end.
-struct WalkCache {
-  uint32_t slot;   // EMPTY32: nothing cached
-  uint32_t gslot;
-  SlotState S;
-};
-
-__device__ __forceinline__ void slot_load(const RangeLds &L, const uint32_t s, WalkCache &c, uint64_t *wvt) {
-  c.slot = s;
-  c.S.d = __builtin_amdgcn_readfirstlane(L.s_d[s]);
-  c.S.fl = -__builtin_amdgcn_readfirstlane(L.s_u[s]);
-  c.S.H = __builtin_amdgcn_readfirstlane(L.s_H[s]);
-  c.S.M = __builtin_amdgcn_readfirstlane(L.s_M[s]);
-  c.S.flags = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)L.s_flags[s]);
-  c.S.facc = 0;  // (lives in wvt[0])
-  c.S.first = uread64(L.s_first[s], 0);
-  c.S.last = uread64(L.s_last[s], 0);
-  c.gslot = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)L.s_gslot[s]);
-  if (__lane_id() == 0) wvt[0] = L.s_facc[s];
-  wave_lds_fence();
-}
-
-__device__ __forceinline__ void slot_store(RangeLds &L, WalkCache &c, const uint64_t *wvt) {
-  if (c.slot == EMPTY32) return;
-  const uint32_t s = c.slot;
-  if (__lane_id() == 0) {
-    L.s_d[s] = c.S.d; L.s_u[s] = -c.S.fl; L.s_H[s] = c.S.H; L.s_M[s] = c.S.M; L.s_flags[s] = c.S.flags;
-    L.s_facc[s] = wvt[0]; L.s_first[s] = c.S.first; L.s_last[s] = c.S.last;
-  }
-  c.slot = EMPTY32;
-  wave_lds_fence();
-}
-
-// All windows of the cached slot in this tile, records [b, e) of the sorted tile.
-template <int FMT>
-__device__ __forceinline__ void slot_walk(RangeLds &L, const Tables &tb, const uint32_t E, const uint32_t D,
-                                          WalkCache &c, const uint32_t b, const uint32_t e, const size_t sbase,
-                                          UItem *__restrict__ ru, uint64_t *__restrict__ wch,
-                                          uint64_t *__restrict__ wvt) {
-  const uint32_t s = c.slot;
-  UItem *us = ru + (sbase + s) * D;
-  const uint32_t lane = __lane_id();
-  // each window's records are loaded one window ahead (the sorted tile does
-  // not change during the walk)
-  uint32_t p = b + (lane < e - b ? lane : 0);
-  uint64_t ts = L.cts[p], by = FMT == 2 ? L.cby[p] : 0;
-  uint32_t fk = L.cfk[p];
-  for (uint32_t a = b; a < e; a += WAVE) {
-    const uint32_t an = a + WAVE;
-    p = an < e ? an + (lane < e - an ? lane : 0) : b;
-    const uint64_t ts_n = L.cts[p], by_n = FMT == 2 ? L.cby[p] : 0;
-    const uint32_t fk_n = L.cfk[p];
-    slot_window<FMT>(L, tb, E, D, s, c.gslot, a, (e - a) < WAVE ? (e - a) : WAVE, ts, fk, by, c.S, us, wch, wvt);
-    ts = ts_n; fk = fk_n; by = by_n;
-  }
-}
-
-// The walk of one sorted tile: wavefront w walks the thread slots w, w + nww,
-// ... (nww walking waves), each slot's records in order.
-template <int FMT>
-__device__ __forceinline__ void walk_tile(RangeLds &L, const Tables &tb, const uint32_t E, const uint32_t D,
-                                          const uint32_t hb, const uint32_t half, const uint32_t nww,
-                                          const size_t sbase, UItem *__restrict__ ru, WalkCache &c) {
-  const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));   // (wave-uniform)
-  const uint32_t *soff = L.soff + hb * (S_MAX + 1);
-  L.cts = L.tile_ts + hb * half;
-  L.cfk = L.tile_fk + hb * half;
-  L.cby = L.tile_by + hb * half;
-  L.nd = L.misc[2];
-  const uint32_t nslots = L.misc[7 + hb];
-  uint64_t *wch = L.w_ch + w * WAVE, *wvt = L.w_vt + w * (D + 1);
-  for (uint32_t s = w; s < nslots; s += nww) {
-    const uint32_t b = soff[s], e = soff[s + 1];
-    if (b == e) continue;
-    if (c.slot != s) {
-      slot_store(L, c, wvt);
-      slot_load(L, s, c, wvt);
-    }
-    slot_walk<FMT>(L, tb, E, D, c, b, e, sbase, ru, wch, wvt);
-  }
-}
-
 // ------------------------------------------------------------------ sync
 // Bounded waits between the wave groups of one workgroup (all resident on one
 // CU).  A wait that runs out raises ERR_PIPE and returns, so every wave always
@@ -696,6 +611,136 @@ __device__ inline void group_barrier(uint32_t *ctr, uint32_t nw, uint32_t *err) 
 __device__ inline void publish(uint32_t *ctr, uint32_t v, bool me) {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   if (me) __hip_atomic_store(ctr, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// A walking wave keeps the state of the slot it walks in registers (and its
+// floor accumulator in wvt[0]) from one tile to the next while it walks that
+// slot only; it goes back to LDS when the wave turns to another slot and at
+// the range end.  With two alternating tile halves, the slot's last records of
+// a tile that do not fill a window wait for the next tile in registers (one
+// record per lane), so that windows run across tile boundaries instead of
+// ending ragged.
+struct WalkCache {
+  uint32_t slot;      // EMPTY32: nothing cached
+  uint32_t gslot;
+  SlotState S;
+  uint32_t pend;      // deferred records of the slot (< WAVE), lane i holds the i-th
+  uint64_t dts, dby;
+  uint32_t dfk;
+};
+
+__device__ __forceinline__ void slot_load(const RangeLds &L, const uint32_t s, WalkCache &c, uint64_t *wvt) {
+  c.slot = s;
+  c.pend = 0;
+  c.S.d = __builtin_amdgcn_readfirstlane(L.s_d[s]);
+  c.S.fl = -__builtin_amdgcn_readfirstlane(L.s_u[s]);
+  c.S.H = __builtin_amdgcn_readfirstlane(L.s_H[s]);
+  c.S.M = __builtin_amdgcn_readfirstlane(L.s_M[s]);
+  c.S.flags = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)L.s_flags[s]);
+  c.S.facc = 0;  // (lives in wvt[0])
+  c.S.first = uread64(L.s_first[s], 0);
+  c.S.last = uread64(L.s_last[s], 0);
+  c.gslot = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)L.s_gslot[s]);
+  if (__lane_id() == 0) wvt[0] = L.s_facc[s];
+  wave_lds_fence();
+}
+
+// (the deferred records must have been walked)
+__device__ __forceinline__ void slot_store(RangeLds &L, WalkCache &c, const uint64_t *wvt) {
+  if (c.slot == EMPTY32) return;
+  const uint32_t s = c.slot;
+  if (__lane_id() == 0) {
+    L.s_d[s] = c.S.d; L.s_u[s] = -c.S.fl; L.s_H[s] = c.S.H; L.s_M[s] = c.S.M; L.s_flags[s] = c.S.flags;
+    L.s_facc[s] = wvt[0]; L.s_first[s] = c.S.first; L.s_last[s] = c.S.last;
+  }
+  c.slot = EMPTY32;
+  wave_lds_fence();
+}
+
+// Walks the cached slot's deferred records followed by records [b, e) of the
+// tile region, in windows of WAVE records.  With `defer`, a last partial
+// window that lies within [b, e) is kept for the next tile instead.
+template <int FMT>
+__device__ __forceinline__ void slot_walk(RangeLds &L, const Tables &tb, const uint32_t E, const uint32_t D,
+                                          WalkCache &c, const uint32_t b, const uint32_t e, const bool defer,
+                                          const size_t sbase, UItem *__restrict__ ru, uint64_t *__restrict__ wch,
+                                          uint64_t *__restrict__ wvt) {
+  const uint32_t s = c.slot;
+  UItem *us = ru + (sbase + s) * D;
+  const uint32_t lane = __lane_id();
+  const uint32_t pend = c.pend;
+  const uint32_t ntot = pend + (e - b);
+  uint32_t nwalk = ntot;
+  if (defer) {
+    const uint32_t r = ntot & (WAVE - 1);
+    if (r && ntot - r >= pend) nwalk = ntot - r;
+  }
+  if (nwalk) {
+    // the v-th record of the sequence (v >= pend) sits at b + v - pend; each
+    // window's records are loaded one window ahead (the tile does not change
+    // during the walk)
+    const uint32_t last = e > b ? e - 1 : 0u;   // reads stay within [b, e) (index 0 when it is empty)
+    const uint32_t v = lane < nwalk ? lane : 0u;
+    uint32_t p = v < pend ? (b < last ? b : last) : b + (v - pend);
+    uint64_t ts = L.tile_ts[p], by = FMT == 2 ? L.tile_by[p] : 0;
+    uint32_t fk = L.tile_fk[p];
+    if (lane < pend) { ts = c.dts; fk = c.dfk; by = c.dby; }
+    for (uint32_t v0 = 0; v0 < nwalk; v0 += WAVE) {
+      const uint32_t vn = v0 + WAVE;
+      p = vn < nwalk ? b + (vn - pend) + (lane < nwalk - vn ? lane : 0u) : (b < last ? b : last);
+      const uint64_t ts_n = L.tile_ts[p], by_n = FMT == 2 ? L.tile_by[p] : 0;
+      const uint32_t fk_n = L.tile_fk[p];
+      slot_window<FMT>(L, tb, E, D, s, c.gslot, (nwalk - v0) < WAVE ? (nwalk - v0) : WAVE, ts, fk, by, c.S, us,
+                       wch, wvt);
+      ts = ts_n; fk = fk_n; by = by_n;
+    }
+  }
+  // records [b + nwalk - pend, e) wait for the next tile
+  c.pend = ntot - nwalk;
+  if (c.pend) {
+    const uint32_t p = b + (nwalk - pend) + (lane < c.pend ? lane : 0u);
+    c.dts = L.tile_ts[p];
+    c.dfk = L.tile_fk[p];
+    c.dby = FMT == 2 ? L.tile_by[p] : 0;
+  }
+}
+
+// The walk of one sorted tile (the tile region's half hb): wavefront w walks
+// the thread slots w, w + nww, ... (nww walking waves), each slot's records in
+// order.  With `defer`, the last slot's partial last window may wait for the
+// next tile (WalkCache); any other deferred records are walked here.
+template <int FMT>
+__device__ __forceinline__ void walk_tile(RangeLds &L, const Tables &tb, const uint32_t E, const uint32_t D,
+                                          const uint32_t hb, const uint32_t half, const uint32_t nww,
+                                          const bool defer, const size_t sbase, UItem *__restrict__ ru,
+                                          WalkCache &c) {
+  const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));   // (wave-uniform)
+  const uint32_t *soff = L.soff + hb * (S_MAX + 1);
+  const uint32_t base = hb * half;
+  L.nd = L.misc[2];
+  const uint32_t nslots = L.misc[7 + hb];
+  uint64_t *wch = L.w_ch + w * WAVE, *wvt = L.w_vt + w * (D + 1);
+  for (uint32_t s = w; s < nslots; s += nww) {
+    const uint32_t b = base + soff[s], e = base + soff[s + 1];
+    if (c.slot != s) {
+      if (b == e) continue;
+      if (c.pend) slot_walk<FMT>(L, tb, E, D, c, b, b, false, sbase, ru, wch, wvt);
+      slot_store(L, c, wvt);
+      slot_load(L, s, c, wvt);
+    }
+    if (b == e && !c.pend) continue;
+    slot_walk<FMT>(L, tb, E, D, c, b, e, defer && s + nww >= nslots, sbase, ru, wch, wvt);
+  }
+}
+
+// Walks what the cached slot still defers, then puts its state back to LDS.
+template <int FMT>
+__device__ __forceinline__ void walk_finish(RangeLds &L, const Tables &tb, const uint32_t E, const uint32_t D,
+                                            const size_t sbase, UItem *__restrict__ ru, WalkCache &c) {
+  const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
+  uint64_t *wch = L.w_ch + w * WAVE, *wvt = L.w_vt + w * (D + 1);
+  if (c.slot != EMPTY32 && c.pend) slot_walk<FMT>(L, tb, E, D, c, 0, 0, false, sbase, ru, wch, wvt);
+  slot_store(L, c, wvt);
 }
 
 // ------------------------------------------------------------------ tile
@@ -1018,6 +1063,7 @@ __device__ __forceinline__ void range_body(RangeLds &L, const Seg *__restrict__ 
     uint32_t wc[5] = {0, 0, 0, 0, 0};   // this wave's record counts over the range
     WalkCache wcache;
     wcache.slot = EMPTY32;
+    wcache.pend = 0;
 #pragma unroll
     for (int r = 0; r < ROWS; r++) {
       const uint32_t li = (uint32_t)gw * (T / GW) + (uint32_t)r * WAVE + lane;
@@ -1039,12 +1085,12 @@ __device__ __forceinline__ void range_body(RangeLds &L, const Seg *__restrict__ 
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         if (lane == 0) __hip_atomic_fetch_add(&L.misc[5], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
       }
-      else walk_tile<FMT>(L, tb, E, D, 0, T, RNW, sbase, ru, wcache);
+      else walk_tile<FMT>(L, tb, E, D, 0, T, RNW, false, sbase, ru, wcache);
       if (!PIPE) __syncthreads();
 #pragma unroll
       for (int r = 0; r < ROWS; r++) { a0[r] = b0[r]; a1[r] = b1[r]; a2[r] = b2[r]; }
     }
-    if (!PIPE) slot_store(L, wcache, L.w_vt + w * (D + 1));
+    if (!PIPE) slot_store(L, wcache, L.w_vt + w * (D + 1));   // (nothing is deferred without PIPE)
     if (lane == 0) {
       const int idx[5] = {ST_ENTRIES, ST_EXITS, ST_KERNEL, ST_BAD, ST_RECORDS};
 #pragma unroll
@@ -1055,12 +1101,13 @@ __device__ __forceinline__ void range_body(RangeLds &L, const Seg *__restrict__ 
     // walker: its own progress counter tells the builders which half is free
     WalkCache wcache;
     wcache.slot = EMPTY32;
+    wcache.pend = 0;
     for (uint64_t t = 0; t < ntiles; t++) {
       wait_at_least(&L.misc[5], (uint32_t)(t + 1) * GW, tb.err);
-      walk_tile<FMT>(L, tb, E, D, (uint32_t)(t & 1), T, GW, sbase, ru, wcache);
+      walk_tile<FMT>(L, tb, E, D, (uint32_t)(t & 1), T, GW, true, sbase, ru, wcache);
       publish(&L.misc[16 + w], (uint32_t)(t + 1), lane == 0);
     }
-    slot_store(L, wcache, L.w_vt + w * (D + 1));
+    walk_finish<FMT>(L, tb, E, D, sbase, ru, wcache);
   }
   __syncthreads();
   L.nd = L.misc[2];

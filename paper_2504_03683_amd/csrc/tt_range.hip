@@ -41,22 +41,36 @@ constexpr int RNW = RWG / WAVE;     // its wavefronts
 constexpr uint32_t FK_EXIT = 1u << 16;  // tile_fk: [0,16) fn | 16 kind (0 entry, 1 exit)
 constexpr int32_t BIG = 0x3FFFFFFF;
 
+// LDS records are arrays of structs, so that one base address serves every
+// field (the field offset goes into the instruction).
+// A thread slot: depth relative to the range start, virtual closes (calls
+// opened before the range that it closed), excursion, flags, global slot,
+// children time of the call at the floor, first and last timestamps.
+struct SRec {
+  int32_t d, u, H, M;
+  uint32_t flags, gslot;
+  uint64_t facc, first, last;
+};
+// A carried frame: an entry still open, by level above the floor.
+struct CFrame1 { uint64_t ts, ch; uint32_t fn, pad; };
+struct CFrame2 { uint64_t ts, ch, by; uint32_t fn, pad; };
+template <int FMT> struct CFrameOf { typedef CFrame1 T; };
+template <> struct CFrameOf<2> { typedef CFrame2 T; };
+// An LDS tally entry: key (hashed region), count, 32-bit min/max, u64 sums.
+struct TEnt1 { uint32_t key, cnt, imin, imax, smin, smax; uint64_t isum, ssum; };
+struct TEnt2 { uint32_t key, cnt, imin, imax, smin, smax; uint64_t isum, ssum, bsum; };
+template <int FMT> struct TEntOf { typedef TEnt1 T; };
+template <> struct TEntOf<2> { typedef TEnt2 T; };
+
 struct RangeLds {
   uint64_t *tile_ts;   // tile sorted by slot: timestamp
   uint64_t *tile_by;   // VAR16 transfer size of entries
   uint32_t *tile_fk;   // fn | kind << 16
-  // thread slots
-  uint32_t *s_gslot, *s_flags;
-  int32_t *s_d, *s_u, *s_H, *s_M;   // depth relative to the range start, virtual closes, excursion
-  uint64_t *s_facc, *s_first, *s_last;
-  // carried stacks [slot][D] by level above the floor
-  uint64_t *c_ts, *c_ch, *c_by;
-  uint16_t *c_fn;
+  SRec *srec;          // [S_MAX] thread slots
+  void *cfr;           // [slot][D] carried frames (CFrame1 / CFrame2)
   // per-wave scratch: children time of the window's lanes, of virtual levels
   uint64_t *w_ch, *w_vt;
-  // tally
-  uint32_t *t_key, *t_cnt, *t_imin, *t_imax, *t_smin, *t_smax;
-  uint64_t *t_isum, *t_ssum, *t_bsum;
+  void *tal;           // [E] tally entries (TEnt1 / TEnt2)
   // kernel tally
   uint32_t *q_cnt, *q_min, *q_max;
   uint64_t *q_sum;
@@ -92,30 +106,11 @@ __host__ __device__ inline size_t range_lds_layout(uint8_t *base, RangeLds *L, u
   TAKE(tile_ts, uint64_t, T);
   TAKE(tile_by, uint64_t, fmt == 2 ? T : 0);
   TAKE(tile_fk, uint32_t, T);
-  TAKE(s_gslot, uint32_t, S_MAX);
-  TAKE(s_flags, uint32_t, S_MAX);
-  TAKE(s_d, int32_t, S_MAX);
-  TAKE(s_u, int32_t, S_MAX);
-  TAKE(s_H, int32_t, S_MAX);
-  TAKE(s_M, int32_t, S_MAX);
-  TAKE(s_facc, uint64_t, S_MAX);
-  TAKE(s_first, uint64_t, S_MAX);
-  TAKE(s_last, uint64_t, S_MAX);
-  TAKE(c_ts, uint64_t, SC * D);
-  TAKE(c_ch, uint64_t, SC * D);
-  TAKE(c_by, uint64_t, fmt == 2 ? SC * D : 0);
-  TAKE(c_fn, uint16_t, SC * D);
+  TAKE(srec, SRec, S_MAX);
+  TAKE(cfr, uint8_t, SC * D * (fmt == 2 ? sizeof(CFrame2) : sizeof(CFrame1)));
   TAKE(w_ch, uint64_t, (size_t)RNW * WAVE);
   TAKE(w_vt, uint64_t, (size_t)RNW * (D + 1));
-  TAKE(t_key, uint32_t, E);
-  TAKE(t_cnt, uint32_t, E);
-  TAKE(t_imin, uint32_t, E);
-  TAKE(t_imax, uint32_t, E);
-  TAKE(t_smin, uint32_t, E);
-  TAKE(t_smax, uint32_t, E);
-  TAKE(t_isum, uint64_t, E);
-  TAKE(t_ssum, uint64_t, E);
-  TAKE(t_bsum, uint64_t, fmt == 2 ? E : 0);
+  TAKE(tal, uint8_t, E * (fmt == 2 ? sizeof(TEnt2) : sizeof(TEnt1)));
   TAKE(q_cnt, uint32_t, KL);
   TAKE(q_min, uint32_t, KL);
   TAKE(q_max, uint32_t, KL);
@@ -252,6 +247,8 @@ template <int FMT>
 __device__ inline void tally_call(const RangeLds &L, uint32_t E, const Tables &tb, uint32_t slot, uint32_t gslot,
                                   uint32_t fn, uint64_t incl, uint64_t self, uint64_t bytes) {
   if (fn >= tb.n_fns || slot >= (uint32_t)S_MAX) return;
+  typedef typename TEntOf<FMT>::T TE;
+  TE *const tal = (TE *)L.tal;
   const uint32_t nd = L.nd;
   uint32_t h = 0;
   bool found = false;
@@ -266,10 +263,10 @@ __device__ inline void tally_call(const RangeLds &L, uint32_t E, const Tables &t
       h = d0 + (d0 ? hash32(key) % span : hash32(key) & (E - 1));   // (E is a power of two)
       const uint32_t probes = span < TALLY_PROBES ? span : TALLY_PROBES;
       for (uint32_t probe = 0; probe < probes; probe++) {
-        const uint32_t k = L.t_key[h];
+        const uint32_t k = tal[h].key;
         if (k == key) { found = true; break; }
         if (k == EMPTY32) {
-          const uint32_t old = atomicCAS(&L.t_key[h], EMPTY32, key);
+          const uint32_t old = atomicCAS(&tal[h].key, EMPTY32, key);
           if (old == EMPTY32 || old == key) { found = true; break; }
         }
         h = h + 1 < E ? h + 1 : d0;
@@ -277,12 +274,12 @@ __device__ inline void tally_call(const RangeLds &L, uint32_t E, const Tables &t
     }
   }
   if (found) {
-    lds_add32(&L.t_cnt[h], 1u);
-    lds_add64(&L.t_isum[h], incl);
-    lds_add64(&L.t_ssum[h], self);
-    if (FMT == 2 && bytes) lds_add64(&L.t_bsum[h], bytes);
-    if (incl < EMPTY32) { lds_min32(&L.t_imin[h], (uint32_t)incl); lds_max32(&L.t_imax[h], (uint32_t)incl); }
-    if (self < EMPTY32) { lds_min32(&L.t_smin[h], (uint32_t)self); lds_max32(&L.t_smax[h], (uint32_t)self); }
+    lds_add32(&tal[h].cnt, 1u);
+    lds_add64(&tal[h].isum, incl);
+    lds_add64(&tal[h].ssum, self);
+    if constexpr (FMT == 2) { if (bytes) lds_add64(&tal[h].bsum, bytes); }
+    if (incl < EMPTY32) { lds_min32(&tal[h].imin, (uint32_t)incl); lds_max32(&tal[h].imax, (uint32_t)incl); }
+    if (self < EMPTY32) { lds_min32(&tal[h].smin, (uint32_t)self); lds_max32(&tal[h].smax, (uint32_t)self); }
   }
   if ((!found || incl >= EMPTY32 || self >= EMPTY32) && gslot < tb.max_threads) {
     Tally *g = &tb.tally[(size_t)gslot * tb.n_fns + fn];
@@ -455,13 +452,15 @@ __device__ __forceinline__ void slot_window(RangeLds &L, const Tables &tb, const
   // permutes: a permute reads 0 from a lane that does not)
   const int32_t psrc = partner >= 0 ? partner : 0;
   const uint32_t ci = s * D + (car ? cpos : 0u);
-  const uint64_t wts = bperm64((uint32_t)ts, (uint32_t)(ts >> 32), psrc), cts = L.c_ts[ci];
-  const uint32_t wfn = (uint32_t)__builtin_amdgcn_ds_bpermute(psrc << 2, (int32_t)fk) & 0xFFFFu, cfn = L.c_fn[ci];
+  typedef typename CFrameOf<FMT>::T CF;
+  CF *const cfr = (CF *)L.cfr;
+  const uint64_t wts = bperm64((uint32_t)ts, (uint32_t)(ts >> 32), psrc), cts = cfr[ci].ts;
+  const uint32_t wfn = (uint32_t)__builtin_amdgcn_ds_bpermute(psrc << 2, (int32_t)fk) & 0xFFFFu, cfn = cfr[ci].fn;
   const uint64_t wby = FMT == 2 ? bperm64((uint32_t)by, (uint32_t)(by >> 32), psrc) : 0;
   const uint64_t pts = inw ? wts : cts;
   const uint32_t pfn = inw ? wfn : cfn;
   uint64_t pby = 0;
-  if (FMT == 2) pby = inw ? wby : L.c_by[ci];
+  if constexpr (FMT == 2) pby = inw ? wby : cfr[ci].by;
   const bool matched = inw || car;
   const bool mis = matched && pfn != fn;
   const bool neg = matched && pfn == fn && ts < pts;
@@ -485,36 +484,37 @@ __device__ __forceinline__ void slot_window(RangeLds &L, const Tables &tb, const
     const bool to_w = parent >= 0;
     const bool to_c = !to_w && pl > fl0 && pp < D;
     const bool to_v = !to_w && pl <= fl0 && (vk == 0 || (vk <= D && (uint32_t)u0 + vk < D));
-    uint64_t *dst = to_w ? &wch[parent >= 0 ? parent : 0] : to_c ? &L.c_ch[s * D + (to_c ? pp : 0u)]
+    uint64_t *dst = to_w ? &wch[parent >= 0 ? parent : 0] : to_c ? &cfr[s * D + (to_c ? pp : 0u)].ch
                                                                   : &wvt[to_v ? vk : 0u];
     if (ok && (to_w || to_c || to_v)) lds_add64(dst, incl);
   }
   wave_lds_fence();
   // self time and tally of every call closed here
   {
-    const uint64_t wc = wch[partner >= 0 ? partner : 0], cc = L.c_ch[ci];
+    const uint64_t wc = wch[partner >= 0 ? partner : 0], cc = cfr[ci].ch;
     const uint64_t ch = inw ? wc : cc;
     const bool under = ok && ch > incl;
     const uint64_t self = (ok && !under) ? incl - ch : 0;
     const uint64_t um = __ballot(under);
     if (um && lane == 0) lds_add32(&L.cnt[ST_UNDER], (uint32_t)__popcll(um));
-    const bool tal = ok && fn < tb.n_fns;
+    const bool tally = ok && fn < tb.n_fns;
     if (s < L.nd) {
       // direct-mapped rows of this slot; 32-bit min/max take no-op operands
       // for durations of 2^32 ns or more, which go to the global row instead
-      const uint32_t h = s * tb.n_fns + (tal ? fn : 0u);
-      if (tal) {
-        lds_add32(&L.t_cnt[h], 1u);
-        lds_add64(&L.t_isum[h], incl);
-        lds_add64(&L.t_ssum[h], self);
-        if (FMT == 2) lds_add64(&L.t_bsum[h], pby);
+      typedef typename TEntOf<FMT>::T TE;
+      TE *const te = (TE *)L.tal + s * tb.n_fns + (tally ? fn : 0u);
+      if (tally) {
+        lds_add32(&te->cnt, 1u);
+        lds_add64(&te->isum, incl);
+        lds_add64(&te->ssum, self);
+        if constexpr (FMT == 2) lds_add64(&te->bsum, pby);
         const bool ib = incl >= EMPTY32, sb = self >= EMPTY32;
-        lds_min32(&L.t_imin[h], ib ? EMPTY32 : (uint32_t)incl);
-        lds_max32(&L.t_imax[h], ib ? 0u : (uint32_t)incl);
-        lds_min32(&L.t_smin[h], sb ? EMPTY32 : (uint32_t)self);
-        lds_max32(&L.t_smax[h], sb ? 0u : (uint32_t)self);
+        lds_min32(&te->imin, ib ? EMPTY32 : (uint32_t)incl);
+        lds_max32(&te->imax, ib ? 0u : (uint32_t)incl);
+        lds_min32(&te->smin, sb ? EMPTY32 : (uint32_t)self);
+        lds_max32(&te->smax, sb ? 0u : (uint32_t)self);
       }
-      const bool big = tal && (incl >= EMPTY32 || self >= EMPTY32) && gslot < tb.max_threads;
+      const bool big = tally && (incl >= EMPTY32 || self >= EMPTY32) && gslot < tb.max_threads;
       if (__ballot(big)) {
         if (big) {
           Tally *g = &tb.tally[(size_t)gslot * tb.n_fns + fn];
@@ -522,7 +522,7 @@ __device__ __forceinline__ void slot_window(RangeLds &L, const Tables &tb, const
           if (self >= EMPTY32) { g_min64(&g->self_min, self); g_max64(&g->self_max, self); }
         }
       }
-    } else if (tal) {
+    } else if (tally) {
       tally_call<FMT>(L, E, tb, s, gslot, fn, incl, self, pby);
     }
   }
@@ -545,8 +545,8 @@ __device__ __forceinline__ void slot_window(RangeLds &L, const Tables &tb, const
     const uint32_t pos = (uint32_t)(lev - fl1 - 1);
     if (pos < D) {
       const uint32_t i = s * D + pos;
-      L.c_ts[i] = ts; L.c_ch[i] = wch[lane]; L.c_fn[i] = (uint16_t)fn;
-      if (FMT == 2) L.c_by[i] = by;
+      cfr[i].ts = ts; cfr[i].ch = wch[lane]; cfr[i].fn = fn;
+      if constexpr (FMT == 2) cfr[i].by = by;
     }
   }
   if (__ballot(open_at_end && (uint32_t)(lev - fl1 - 1) >= D)) S.flags |= RF_OVERFLOW;
@@ -632,16 +632,17 @@ struct WalkCache {
 __device__ __forceinline__ void slot_load(const RangeLds &L, const uint32_t s, WalkCache &c, uint64_t *wvt) {
   c.slot = s;
   c.pend = 0;
-  c.S.d = __builtin_amdgcn_readfirstlane(L.s_d[s]);
-  c.S.fl = -__builtin_amdgcn_readfirstlane(L.s_u[s]);
-  c.S.H = __builtin_amdgcn_readfirstlane(L.s_H[s]);
-  c.S.M = __builtin_amdgcn_readfirstlane(L.s_M[s]);
-  c.S.flags = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)L.s_flags[s]);
+  const SRec &r = L.srec[s];
+  c.S.d = __builtin_amdgcn_readfirstlane(r.d);
+  c.S.fl = -__builtin_amdgcn_readfirstlane(r.u);
+  c.S.H = __builtin_amdgcn_readfirstlane(r.H);
+  c.S.M = __builtin_amdgcn_readfirstlane(r.M);
+  c.S.flags = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)r.flags);
   c.S.facc = 0;  // (lives in wvt[0])
-  c.S.first = uread64(L.s_first[s], 0);
-  c.S.last = uread64(L.s_last[s], 0);
-  c.gslot = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)L.s_gslot[s]);
-  if (__lane_id() == 0) wvt[0] = L.s_facc[s];
+  c.S.first = uread64(r.first, 0);
+  c.S.last = uread64(r.last, 0);
+  c.gslot = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)r.gslot);
+  if (__lane_id() == 0) wvt[0] = r.facc;
   wave_lds_fence();
 }
 
@@ -650,8 +651,9 @@ __device__ __forceinline__ void slot_store(RangeLds &L, WalkCache &c, const uint
   if (c.slot == EMPTY32) return;
   const uint32_t s = c.slot;
   if (__lane_id() == 0) {
-    L.s_d[s] = c.S.d; L.s_u[s] = -c.S.fl; L.s_H[s] = c.S.H; L.s_M[s] = c.S.M; L.s_flags[s] = c.S.flags;
-    L.s_facc[s] = wvt[0]; L.s_first[s] = c.S.first; L.s_last[s] = c.S.last;
+    SRec &r = L.srec[s];
+    r.d = c.S.d; r.u = -c.S.fl; r.H = c.S.H; r.M = c.S.M; r.flags = c.S.flags;
+    r.facc = wvt[0]; r.first = c.S.first; r.last = c.S.last;
   }
   c.slot = EMPTY32;
   wave_lds_fence();
@@ -945,7 +947,7 @@ __device__ __forceinline__ void front_tile(RangeLds &L, const Tables &tb, const 
         const uint32_t s = nslots0 + tid;
         const uint32_t t = L.newtid[tid];
         if (s < scap) {
-          L.s_gslot[s] = resolve_gslot(tb, sg.stream, t);
+          L.srec[s].gslot = resolve_gslot(tb, sg.stream, t);
           L.tidmap[L.newbucket[tid]] = (1ull << 63) | ((uint64_t)s << 32) | t;
         } else {
           atomicOr(tb.err, ERR_RANGE_THREADS);
@@ -1034,16 +1036,22 @@ __device__ __forceinline__ void range_body(RangeLds &L, const Seg *__restrict__ 
   const uint32_t D = tb.D, E = sh.E, KL = sh.KL;
   const Range rg = ranges[rid];
   const Seg sg = segs[rg.seg];
+  typedef typename TEntOf<FMT>::T TE;
+  typedef typename CFrameOf<FMT>::T CF;
+  TE *const tal = (TE *)L.tal;
+  const CF *const cfr = (const CF *)L.cfr;
   for (uint32_t i = tid; i < E; i += RWG) {
-    L.t_key[i] = EMPTY32; L.t_cnt[i] = 0; L.t_imin[i] = EMPTY32; L.t_imax[i] = 0;
-    L.t_smin[i] = EMPTY32; L.t_smax[i] = 0; L.t_isum[i] = 0; L.t_ssum[i] = 0;
-    if (FMT == 2) L.t_bsum[i] = 0;
+    TE &te = tal[i];
+    te.key = EMPTY32; te.cnt = 0; te.imin = EMPTY32; te.imax = 0;
+    te.smin = EMPTY32; te.smax = 0; te.isum = 0; te.ssum = 0;
+    if constexpr (FMT == 2) te.bsum = 0;
   }
   for (uint32_t i = tid; i < KL; i += RWG) { L.q_cnt[i] = 0; L.q_min[i] = EMPTY32; L.q_max[i] = 0; L.q_sum[i] = 0; }
   for (uint32_t i = tid; i < TIDMAP; i += RWG) L.tidmap[i] = 0;
   for (uint32_t i = tid; i < S_MAX; i += RWG) {
-    L.s_gslot[i] = GV_INVALID; L.s_flags[i] = 0; L.s_d[i] = 0; L.s_u[i] = 0; L.s_H[i] = 0; L.s_M[i] = 0;
-    L.s_facc[i] = 0; L.s_first[i] = 0; L.s_last[i] = 0;
+    SRec &r = L.srec[i];
+    r.gslot = GV_INVALID; r.flags = 0; r.d = 0; r.u = 0; r.H = 0; r.M = 0;
+    r.facc = 0; r.first = 0; r.last = 0;
   }
   for (uint32_t i = tid; i < ST_N; i += RWG) L.cnt[i] = 0;
   if (tid < 32) L.misc[tid] = 0;
@@ -1117,51 +1125,54 @@ __device__ __forceinline__ void range_body(RangeLds &L, const Seg *__restrict__ 
   if (tid == 0) rnslots[rid] = nslots;
   if ((uint32_t)tid < nslots) {
     const uint32_t s = tid;
+    const SRec &r = L.srec[s];
     RHdr hd;
-    hd.gslot = L.s_gslot[s];
-    hd.nu_total = (uint32_t)L.s_u[s];
+    hd.gslot = r.gslot;
+    hd.nu_total = (uint32_t)r.u;
     hd.nu_listed = hd.nu_total < D ? hd.nu_total : D;
-    hd.n_o = (uint32_t)(L.s_d[s] + L.s_u[s]);
-    hd.floor = L.s_facc[s];
-    hd.H = L.s_H[s]; hd.M = L.s_M[s];
-    hd.first_ts = L.s_first[s]; hd.last_ts = L.s_last[s];
-    hd.flags = L.s_flags[s];
+    hd.n_o = (uint32_t)(r.d + r.u);
+    hd.floor = r.facc;
+    hd.H = r.H; hd.M = r.M;
+    hd.first_ts = r.first; hd.last_ts = r.last;
+    hd.flags = r.flags;
     hd.pad = 0; hd.pad2 = 0;
     rhdr[sbase + s] = hd;
     const uint32_t no = hd.n_o < D ? hd.n_o : D;
     for (uint32_t k = 0; k < no; k++) {
       OItem *o = &ro[(sbase + s) * D + k];
-      o->ts = L.c_ts[(size_t)s * D + k];
-      o->child = L.c_ch[(size_t)s * D + k];
-      o->bytes = FMT == 2 ? L.c_by[(size_t)s * D + k] : 0;
-      o->fn = L.c_fn[(size_t)s * D + k];
+      const CF &cf = cfr[(size_t)s * D + k];
+      o->ts = cf.ts;
+      o->child = cf.ch;
+      if constexpr (FMT == 2) o->bytes = cf.by; else o->bytes = 0;
+      o->fn = (uint16_t)cf.fn;
       o->pad = 0;
     }
   }
   const uint32_t nd = L.nd, d0 = nd * tb.n_fns;
   for (uint32_t i = tid; i < E; i += RWG) {
     uint32_t s, fn;
+    const TE &te = tal[i];
     if (i < d0) {
-      if (!L.t_cnt[i]) continue;
+      if (!te.cnt) continue;
       s = i / tb.n_fns;
       fn = i - s * tb.n_fns;
     } else {
-      const uint32_t key = L.t_key[i];
+      const uint32_t key = te.key;
       if (key == EMPTY32) continue;
       s = key >> 16;
       fn = key & 0xFFFFu;
     }
-    const uint32_t gs = L.s_gslot[s];
+    const uint32_t gs = L.srec[s].gslot;
     if (gs >= tb.max_threads) continue;
     Tally *g = &tb.tally[(size_t)gs * tb.n_fns + fn];
-    g_add64(&g->count, L.t_cnt[i]);
-    g_add64(&g->incl_sum, L.t_isum[i]);
-    g_add64(&g->self_sum, L.t_ssum[i]);
-    if (FMT == 2 && L.t_bsum[i]) g_add64(&g->bytes_sum, L.t_bsum[i]);
-    if (L.t_imin[i] != EMPTY32) g_min64(&g->incl_min, L.t_imin[i]);
-    if (L.t_imax[i]) g_max64(&g->incl_max, L.t_imax[i]);
-    if (L.t_smin[i] != EMPTY32) g_min64(&g->self_min, L.t_smin[i]);
-    if (L.t_smax[i]) g_max64(&g->self_max, L.t_smax[i]);
+    g_add64(&g->count, te.cnt);
+    g_add64(&g->incl_sum, te.isum);
+    g_add64(&g->self_sum, te.ssum);
+    if constexpr (FMT == 2) { if (te.bsum) g_add64(&g->bytes_sum, te.bsum); }
+    if (te.imin != EMPTY32) g_min64(&g->incl_min, te.imin);
+    if (te.imax) g_max64(&g->incl_max, te.imax);
+    if (te.smin != EMPTY32) g_min64(&g->self_min, te.smin);
+    if (te.smax) g_max64(&g->self_max, te.smax);
   }
   for (uint32_t i = tid; i < KL; i += RWG) {
     if (!L.q_cnt[i]) continue;

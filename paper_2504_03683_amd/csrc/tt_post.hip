@@ -220,9 +220,9 @@ __global__ __launch_bounds__(RS_WG) void k_radix_sort(uint64_t *keys, uint32_t *
       const uint64_t k = valid ? ks[i] : 0;
       const uint32_t v = valid ? vs[i] : 0;
       const uint32_t d = (uint32_t)(k >> b) & 0xFF;
-      uint64_t mask = __ballot(valid);
+      uint64_t mask = __builtin_amdgcn_ballot_w64(valid);
       for (int bit = 0; bit < 8; bit++) {
-        const uint64_t bb = __ballot(valid && ((d >> bit) & 1u));
+        const uint64_t bb = __builtin_amdgcn_ballot_w64(valid && ((d >> bit) & 1u));
         mask &= ((d >> bit) & 1u) ? bb : ~bb;
       }
       const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
@@ -324,7 +324,7 @@ __global__ __launch_bounds__(256) void k_group_rows(RowCtx c, Tables tb, uint32_
     Acc a;
     bool ne = false;
     if (id < c.n_ids) { group_value(c, tb, grp, id, a); ne = a.v[0] != 0; }
-    const uint64_t m = __ballot(ne);
+    const uint64_t m = __builtin_amdgcn_ballot_w64(ne);
     const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
     if (lane == 0) wsum[w] = (uint32_t)__popcll(m);
     __syncthreads();

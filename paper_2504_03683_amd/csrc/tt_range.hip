@@ -132,6 +132,9 @@ size_t range_lds_bytes(uint32_t T, uint32_t E, uint32_t KL, uint32_t D, int fmt)
 }
 
 // ---------------------------------------------------------------- helpers
+// Lanes of the wavefront for which p holds (p stays a lane mask; HIP's
+// __ballot takes an int and round-trips the predicate through a register).
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 __device__ inline uint64_t lanemask_lt() {
   const uint32_t lane = __lane_id();
   return lane ? (~0ull >> (64 - lane)) : 0ull;
@@ -394,14 +397,14 @@ __device__ __forceinline__ void slot_window(RangeLds &L, const Tables &tb, const
     const uint32_t plo = (uint32_t)dpp<0x138>((int32_t)(uint32_t)S.last, (int32_t)(uint32_t)ts);
     const uint32_t phi = (uint32_t)dpp<0x138>((int32_t)(uint32_t)(S.last >> 32), (int32_t)(uint32_t)(ts >> 32));
     const uint64_t prev = ((uint64_t)phi << 32) | plo;
-    const uint64_t bad = __ballot(valid && (lane > 0 || (S.flags & RF_HAS_TS)) && ts < prev);
+    const uint64_t bad = ballot(valid && (lane > 0 || (S.flags & RF_HAS_TS)) && ts < prev);
     if (bad && lane == 0) lds_add32(&L.cnt[ST_TSREG], (uint32_t)__popcll(bad));
     if (!(S.flags & RF_HAS_TS)) S.first = uread64(ts, 0);
     S.last = uread64(ts, nw - 1);
     S.flags |= RF_HAS_TS;
   }
   // depth after each record and the level each record opens (entry) or closes (exit)
-  const uint64_t Em = __ballot(en), Xm = __ballot(ex);
+  const uint64_t Em = ballot(en), Xm = ballot(ex);
   const uint64_t lt = lanemask_lt();
   const int32_t da = d0 + (int32_t)__popcll(Em & lt) - (int32_t)__popcll(Xm & lt) + (en ? 1 : 0) - (ex ? 1 : 0);
   const int32_t lev = en ? da : da + 1;
@@ -427,7 +430,7 @@ __device__ __forceinline__ void slot_window(RangeLds &L, const Tables &tb, const
   {
     const int32_t levE = en ? lev : -BIG;           // entries only
     for (int32_t v = damin + 1, j = 0; v <= vend; v++, j++) {
-      const uint64_t Ev = __ballot(levE == v);
+      const uint64_t Ev = ballot(levE == v);
       tlo = amd_writelane((int32_t)(uint32_t)Ev, j, tlo);
       thi = amd_writelane((int32_t)(uint32_t)(Ev >> 32), j, thi);
     }
@@ -466,13 +469,11 @@ __device__ __forceinline__ void slot_window(RangeLds &L, const Tables &tb, const
   const bool neg = matched && pfn == fn && ts < pts;
   const bool ok = matched && pfn == fn && ts >= pts;
   const uint64_t incl = ok ? ts - pts : 0;
-  {
-    const uint64_t mm = __ballot(mis), nm = __ballot(neg);
-    if (mm | nm) {
-      if (lane == 0) {
-        if (mm) lds_add32(&L.cnt[ST_MISMATCH], (uint32_t)__popcll(mm));
-        if (nm) lds_add32(&L.cnt[ST_NEGDUR], (uint32_t)__popcll(nm));
-      }
+  if (ballot(mis || neg)) {
+    const uint64_t mm = ballot(mis), nm = ballot(neg);
+    if (lane == 0) {
+      if (mm) lds_add32(&L.cnt[ST_MISMATCH], (uint32_t)__popcll(mm));
+      if (nm) lds_add32(&L.cnt[ST_NEGDUR], (uint32_t)__popcll(nm));
     }
   }
   wave_lds_fence();
@@ -484,9 +485,13 @@ __device__ __forceinline__ void slot_window(RangeLds &L, const Tables &tb, const
     const bool to_w = parent >= 0;
     const bool to_c = !to_w && pl > fl0 && pp < D;
     const bool to_v = !to_w && pl <= fl0 && (vk == 0 || (vk <= D && (uint32_t)u0 + vk < D));
-    uint64_t *dst = to_w ? &wch[parent >= 0 ? parent : 0] : to_c ? &cfr[s * D + (to_c ? pp : 0u)].ch
-                                                                  : &wvt[to_v ? vk : 0u];
-    if (ok && (to_w || to_c || to_v)) lds_add64(dst, incl);
+    // (byte offsets from the window-lane array, chosen by selects)
+    const int32_t o_w = (parent >= 0 ? parent : 0) * 8;
+    const int32_t o_c = (int32_t)((uint8_t *)&cfr[s * D + (to_c ? pp : 0u)].ch - (uint8_t *)wch);
+    const int32_t o_v = (int32_t)((uint8_t *)&wvt[to_v ? vk : 0u] - (uint8_t *)wch);
+    int32_t off = to_c ? o_c : o_v;
+    off = to_w ? o_w : off;
+    if (ok && (to_w || to_c || to_v)) lds_add64((uint64_t *)((uint8_t *)wch + off), incl);
   }
   wave_lds_fence();
   // self time and tally of every call closed here
@@ -495,7 +500,7 @@ __device__ __forceinline__ void slot_window(RangeLds &L, const Tables &tb, const
     const uint64_t ch = inw ? wc : cc;
     const bool under = ok && ch > incl;
     const uint64_t self = (ok && !under) ? incl - ch : 0;
-    const uint64_t um = __ballot(under);
+    const uint64_t um = ballot(under);
     if (um && lane == 0) lds_add32(&L.cnt[ST_UNDER], (uint32_t)__popcll(um));
     const bool tally = ok && fn < tb.n_fns;
     if (s < L.nd) {
@@ -515,7 +520,7 @@ __device__ __forceinline__ void slot_window(RangeLds &L, const Tables &tb, const
         lds_max32(&te->smax, sb ? 0u : (uint32_t)self);
       }
       const bool big = tally && (incl >= EMPTY32 || self >= EMPTY32) && gslot < tb.max_threads;
-      if (__ballot(big)) {
+      if (ballot(big)) {
         if (big) {
           Tally *g = &tb.tally[(size_t)gslot * tb.n_fns + fn];
           if (incl >= EMPTY32) { g_min64(&g->incl_min, incl); g_max64(&g->incl_max, incl); }
@@ -527,7 +532,7 @@ __device__ __forceinline__ void slot_window(RangeLds &L, const Tables &tb, const
     }
   }
   // exits that close calls opened before the range become U items
-  if (__ballot(pre)) {
+  if (ballot(pre)) {
     if (pre) {
       const uint32_t vk = (uint32_t)(fl0 - lev);
       const uint32_t gi = (uint32_t)u0 + vk;
@@ -549,7 +554,7 @@ __device__ __forceinline__ void slot_window(RangeLds &L, const Tables &tb, const
       if constexpr (FMT == 2) cfr[i].by = by;
     }
   }
-  if (__ballot(open_at_end && (uint32_t)(lev - fl1 - 1) >= D)) S.flags |= RF_OVERFLOW;
+  if (ballot(open_at_end && (uint32_t)(lev - fl1 - 1) >= D)) S.flags |= RF_OVERFLOW;
   if (fl1 < fl0 && lane == 0) {
     // the floor moved down: its call's children time is that of the level reached
     const uint32_t dv = (uint32_t)(fl0 - fl1);
@@ -582,7 +587,7 @@ __device__ inline void wait_at_least(uint32_t *ctr, uint32_t v, uint32_t *err) {
 __device__ inline void wait_all_at_least(uint32_t *ctr, uint32_t n, uint32_t v, uint32_t *err) {
   const uint32_t lane = __lane_id();
   uint32_t i = 0;
-  while (__ballot(lane < n && __hip_atomic_load(&ctr[lane < n ? lane : 0], __ATOMIC_RELAXED,
+  while (ballot(lane < n && __hip_atomic_load(&ctr[lane < n ? lane : 0], __ATOMIC_RELAXED,
                                                 __HIP_MEMORY_SCOPE_WORKGROUP) < v)) {
     __builtin_amdgcn_s_sleep(1);
     if (++i == SPIN_LIMIT) { if (lane == 0) atomicOr(err, ERR_PIPE); break; }
@@ -866,10 +871,10 @@ __device__ __forceinline__ void front_tile(RangeLds &L, const Tables &tb, const 
           bad = true;
         }
       }
-      wc[0] += (uint32_t)__popcll(__ballot(r_slot[r] == 0 && kind == 0));
-      wc[1] += (uint32_t)__popcll(__ballot(r_slot[r] == 0 && kind == 1));
-      wc[2] += (uint32_t)__popcll(__ballot(kern_ok));
-      wc[3] += (uint32_t)__popcll(__ballot(bad));
+      wc[0] += (uint32_t)__popcll(ballot(r_slot[r] == 0 && kind == 0));
+      wc[1] += (uint32_t)__popcll(ballot(r_slot[r] == 0 && kind == 1));
+      wc[2] += (uint32_t)__popcll(ballot(kern_ok));
+      wc[3] += (uint32_t)__popcll(ballot(bad));
     }
     if (w == 0) wc[4] += n;
     // ---- P3. thread id -> local slot
@@ -923,9 +928,9 @@ __device__ __forceinline__ void front_tile(RangeLds &L, const Tables &tb, const 
         const bool valid = late ? (r_late & (1u << r)) && r_slot[r] != EMPTY32
                                 : r_slot[r] != EMPTY32 && r_slot[r] != EMPTY32 - 1;
         const uint32_t s = valid ? r_slot[r] : 0;
-        uint64_t mask = __ballot(valid);
+        uint64_t mask = ballot(valid);
         for (uint32_t b = 0; b < nbits; b++) {
-          const uint64_t bb = __ballot(valid && ((s >> b) & 1u));
+          const uint64_t bb = ballot(valid && ((s >> b) & 1u));
           mask &= ((s >> b) & 1u) ? bb : ~bb;
         }
         const uint32_t rk = (uint32_t)__popcll(mask & lanemask_lt());

@@ -782,7 +782,7 @@ __device__ __forceinline__ void front_tile(RangeLds &L, const Tables &tb, const 
     else __syncthreads();
   };
     uint64_t r_ts[ROWS], r_x[ROWS], r_by[ROWS];
-    uint32_t r_tid[ROWS], r_fk[ROWS], r_slot[ROWS], r_rank[ROWS];
+    uint32_t r_tid[ROWS], r_fk[ROWS], r_slot[ROWS], r_rank[ROWS] = {};
     // ---- P1. decode, then prefetch the next tile
 #pragma unroll
     for (int r = 0; r < ROWS; r++) {
@@ -843,36 +843,32 @@ __device__ __forceinline__ void front_tile(RangeLds &L, const Tables &tb, const 
     for (int r = 0; r < ROWS; r++) {
       const uint32_t li = (uint32_t)w * (T / GW) + (uint32_t)r * WAVE + lane;
       const uint32_t fn = r_fk[r] & 0xFFFFu, kind = (r_fk[r] >> 16) & 0xFFu, plen = r_fk[r] >> 24;
-      r_slot[r] = EMPTY32;
-      bool kern_ok = false, bad = false;
-      if (li < n) {
-        if (kind == 2) {
-          const uint64_t end = r_x[r];
-          kern_ok = fn < tb.n_kid && (FMT == 1 || plen >= 8) && end >= r_ts[r];
-          bad = !kern_ok;
-          if (kern_ok) {
-            const uint64_t d = end - r_ts[r];
-            if (fn < KL) {
-              lds_add32(&L.q_cnt[fn], 1u);
-              lds_add64(&L.q_sum[fn], d);
-              if (d < EMPTY32) { lds_min32(&L.q_min[fn], (uint32_t)d); lds_max32(&L.q_max[fn], (uint32_t)d); }
-              else {
-                KTally *kt = &tb.ktally[(size_t)sg.stream * tb.n_kid + fn];
-                g_min64(&kt->min, d); g_max64(&kt->max, d);
-              }
-            } else {
-              KTally *kt = &tb.ktally[(size_t)sg.stream * tb.n_kid + fn];
-              g_add64(&kt->count, 1); g_add64(&kt->sum, d); g_min64(&kt->min, d); g_max64(&kt->max, d);
-            }
-          }
-        } else if (kind <= 1 && fn < tb.n_fns) {
-          r_slot[r] = 0;
-        } else {
-          bad = true;
+      const bool in = li < n;
+      const bool api = in && kind <= 1 && fn < tb.n_fns;
+      const uint64_t end = r_x[r], d = end - r_ts[r];
+      const bool kern_ok = in && kind == 2 && fn < tb.n_kid && (FMT == 1 || plen >= 8) && end >= r_ts[r];
+      const bool bad = in && !api && !kern_ok;
+      r_slot[r] = api ? 0u : EMPTY32;
+      // kernel durations: LDS rows for ids below KL and durations below 2^32
+      // ns; the rest goes to the global rows
+      const bool kl = kern_ok && fn < KL && d < EMPTY32;
+      if (kl) {
+        lds_add32(&L.q_cnt[fn], 1u);
+        lds_add64(&L.q_sum[fn], d);
+        lds_min32(&L.q_min[fn], (uint32_t)d);
+        lds_max32(&L.q_max[fn], (uint32_t)d);
+      }
+      const bool kg = kern_ok && !kl;
+      if (ballot(kg)) {
+        if (kg) {
+          KTally *kt = &tb.ktally[(size_t)sg.stream * tb.n_kid + fn];
+          if (fn < KL) { lds_add32(&L.q_cnt[fn], 1u); lds_add64(&L.q_sum[fn], d); }
+          else { g_add64(&kt->count, 1); g_add64(&kt->sum, d); }
+          g_min64(&kt->min, d); g_max64(&kt->max, d);
         }
       }
-      wc[0] += (uint32_t)__popcll(ballot(r_slot[r] == 0 && kind == 0));
-      wc[1] += (uint32_t)__popcll(ballot(r_slot[r] == 0 && kind == 1));
+      wc[0] += (uint32_t)__popcll(ballot(api && kind == 0));
+      wc[1] += (uint32_t)__popcll(ballot(api && kind == 1));
       wc[2] += (uint32_t)__popcll(ballot(kern_ok));
       wc[3] += (uint32_t)__popcll(ballot(bad));
     }
@@ -882,9 +878,23 @@ __device__ __forceinline__ void front_tile(RangeLds &L, const Tables &tb, const 
     // A lane that finds no bucket for its tid claims one as pending and lists
     // the tid; its record is ranked after the listed tids get slots.
     uint32_t r_late = 0;   // bit r: row r's thread has no slot yet
+    // (the first bucket settles nearly every record; the probe loop runs for
+    // the other lanes only)
+    uint32_t r_open = 0;   // bit r: row r still probing
 #pragma unroll
     for (int r = 0; r < ROWS; r++) {
-      if (r_slot[r] == EMPTY32) continue;
+      const uint32_t t = r_tid[r];
+      const uint64_t e = L.tidmap[hash32(t) & (TIDMAP - 1)];
+      const bool done = (e >> 63) && !((e >> 62) & 1u) && (uint32_t)e == t;
+      const uint32_t sl = (uint32_t)(e >> 32) & 0xFFu;
+      const bool act = r_slot[r] != EMPTY32;
+      if (act && done) r_slot[r] = sl < slot_cap(D) ? sl : EMPTY32;  // over the per-range limit: the flush fails
+      if (act && !done) r_open |= 1u << r;
+    }
+    if (ballot(r_open != 0)) {
+#pragma unroll
+    for (int r = 0; r < ROWS; r++) {
+      if (!(r_open & (1u << r))) continue;
       const uint32_t t = r_tid[r];
       uint32_t h = hash32(t) & (TIDMAP - 1);
       for (uint32_t probe = 0; probe < TIDMAP; probe++) {
@@ -909,6 +919,7 @@ __device__ __forceinline__ void front_tile(RangeLds &L, const Tables &tb, const 
         }
         h = (h + 1) & (TIDMAP - 1);
       }
+    }
     }
     // ---- P4. stable sort of the API records by slot: rank each record among
     // the wave's records of its slot (ballot match masks over the slot bits;
@@ -935,9 +946,8 @@ __device__ __forceinline__ void front_tile(RangeLds &L, const Tables &tb, const 
         }
         const uint32_t rk = (uint32_t)__popcll(mask & lanemask_lt());
         const uint32_t c = (uint32_t)__popcll(mask);
-        uint32_t base = 0;
-        if (valid) base = wcnt[w * S_MAX + s];
-        if (valid) r_rank[r] = base + rk;
+        const uint32_t base = wcnt[w * S_MAX + s];
+        r_rank[r] = valid ? base + rk : r_rank[r];
         if (valid && rk == 0) wcnt[w * S_MAX + s] = base + c;
       }
     };

@@ -127,12 +127,14 @@ def main():
     tl = T.Tally(w.fmt, w.n_fns, w.n_kernel_ids, max_depth=max(w.max_depth, 8), max_threads=max_threads,
                  max_streams=64, flags=T.DEVICE_INPUT | T.PROFILE, has_size=w.has_size, stream=stream)
 
+    rowbuf = np.zeros(max_threads * w.n_fns, dtype=T.ROW_DTYPE)   # reused by every read (capacity: all rows)
+
     def step():
         tl.reset()
         for s, r, p in zip(w.streams, recs, pays):
             tl.submit(s.key, r, p)
         tl.flush(final=True)
-        return tl.read(T.SCOPE_THREAD)
+        return tl.read(T.SCOPE_THREAD, out=rowbuf)
 
     for _ in range(args.warmup):
         step()

@@ -71,6 +71,17 @@ struct OItem { uint64_t ts, child, bytes; uint32_t fn, pad; };
 struct Tally { uint64_t count, incl_sum, incl_min, incl_max, self_sum, self_min, self_max, bytes_sum; };
 struct KTally { uint64_t count, sum, min, max; };
 
+// The tables a handle resets, for the one-launch initialisation.
+struct InitSet {
+  uint64_t *gkeys; size_t n_gkeys;
+  uint32_t *gvals; size_t n_gvals;
+  uint32_t *ngs, *err;
+  Tally *tally; size_t n_tally;
+  KTally *ktally; size_t n_ktally;
+  uint32_t *cstate; size_t n_cstate;
+  uint64_t *sstats; size_t n_sstats;
+};
+
 // Per-thread state carried on the device across ranges and flushes.
 struct CState { uint32_t h; uint32_t flags; uint64_t last_ts; };
 enum : uint32_t { CS_HAS_TS = 1u, CS_OVERFLOW = 2u };

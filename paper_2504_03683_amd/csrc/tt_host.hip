@@ -36,7 +36,7 @@ hipError_t launch_paylen(const Seg *segs, Range *ranges, uint32_t n_ranges, cons
                          uint32_t n_segs, uint64_t *paylen, uint32_t *err, hipStream_t st);
 hipError_t launch_fill64(uint64_t *p, size_t n, uint64_t v, hipStream_t st);
 hipError_t launch_fill32(uint32_t *p, size_t n, uint32_t v, hipStream_t st);
-hipError_t launch_init_tables(const Tables &tb, size_t n_tally, size_t n_ktally, hipStream_t st);
+hipError_t launch_init_all(const InitSet &is, hipStream_t st);
 hipError_t launch_combine(const uint32_t *spans, uint32_t n_spans, const RHdr *rhdr, const UItem *ru,
                           const OItem *ro, const uint32_t *rnslots, const Tables &tb, hipStream_t st);
 hipError_t launch_final(const Tables &tb, uint32_t max_threads, hipStream_t st);
@@ -130,6 +130,8 @@ struct thapi_tally {
   DevBuf keys, vals, keys2, vals2, gbeg, gend, cnt, off, rank_stream, rank_key, trace_span, stream_rank, rows, tstats;
   void *h_pinned = nullptr;  // small pinned staging for results of device->host copies
   size_t h_pinned_cap = 0;
+  void *h_plan = nullptr;    // pinned staging of the work list (asynchronous uploads)
+  size_t h_plan_cap = 0;
 
   double timings[TM_N] = {0};
   hipEvent_t ev[2 * TM_N] = {};
@@ -180,16 +182,17 @@ uint32_t record_size(const thapi_tally *t) { return t->cfg.format == THAPI_FMT_V
 hipError_t init_tables(thapi_tally *t) {
   const thapi_tally_config &c = t->cfg;
   hipError_t e;
-  if ((e = launch_fill64((uint64_t *)t->d_gkeys, t->gcap, EMPTY64, t->st)) != hipSuccess) return e;
-  if ((e = launch_fill32((uint32_t *)t->d_gvals, t->gcap, GV_PENDING, t->st)) != hipSuccess) return e;
-  if ((e = launch_fill32((uint32_t *)t->d_ngs, 1, 0, t->st)) != hipSuccess) return e;
-  if ((e = launch_fill32((uint32_t *)t->d_err, 1, 0, t->st)) != hipSuccess) return e;
-  if ((e = launch_init_tables(t->tb, (size_t)c.max_threads * c.n_fns, (size_t)c.max_streams * c.n_kernel_ids,
-                              t->st)) != hipSuccess)
-    return e;
-  if ((e = launch_fill32((uint32_t *)t->d_cstate, (size_t)c.max_threads * sizeof(CState) / 4, 0, t->st)) != hipSuccess)
-    return e;
-  if ((e = launch_fill64((uint64_t *)t->d_sstats, (size_t)c.max_streams * ST_N, 0, t->st)) != hipSuccess) return e;
+  // every table in one launch
+  InitSet is{};
+  is.gkeys = (uint64_t *)t->d_gkeys; is.n_gkeys = t->gcap;
+  is.gvals = (uint32_t *)t->d_gvals; is.n_gvals = t->gcap;
+  is.ngs = (uint32_t *)t->d_ngs;
+  is.err = (uint32_t *)t->d_err;
+  is.tally = t->tb.tally; is.n_tally = (size_t)c.max_threads * c.n_fns;
+  is.ktally = t->tb.ktally; is.n_ktally = (size_t)c.max_streams * c.n_kernel_ids;
+  is.cstate = (uint32_t *)t->d_cstate; is.n_cstate = (size_t)c.max_threads * sizeof(CState) / 4;
+  is.sstats = (uint64_t *)t->d_sstats; is.n_sstats = (size_t)c.max_streams * ST_N;
+  if ((e = launch_init_all(is, t->st)) != hipSuccess) return e;
   return hipStreamSynchronize(t->st);
 }
 
@@ -204,6 +207,7 @@ void free_all(thapi_tally *t) {
   for (auto &c : t->queue) if (c.owned) hipFree(c.owned);
   t->queue.clear();
   if (t->h_pinned) hipHostFree(t->h_pinned);
+  if (t->h_plan) hipHostFree(t->h_plan);
   for (auto &e : t->ev) if (e) hipEventDestroy(e);
   if (t->gexec) { hipGraphExecDestroy(t->gexec); t->gexec = nullptr; }
   if (t->arena) { hipFree(t->arena); t->arena = nullptr; }
@@ -270,9 +274,6 @@ hipError_t ensure_pinned(thapi_tally *t, size_t bytes) {
   if (e == hipSuccess) t->h_pinned_cap = want;
   return e;
 }
-
-// Sum of payload_len of a device VAR16 header buffer (used to validate a
-// device-input submit before it is accepted).
 
 }  // namespace
 
@@ -640,11 +641,28 @@ hipError_t upload_plan(thapi_tally *t, const Plan &pl) {
   UPCHK(t->ro.ensure(sizeof(OItem) * (size_t)nR * S_MAX * D));
   UPCHK(t->rnslots.ensure(4ull * nR));
   UPCHK(t->paylen.ensure(8ull * nR));
-  UPCHK(hipMemcpyAsync(t->segs.p, pl.segs.data(), sizeof(Seg) * nS, hipMemcpyHostToDevice, t->st));
-  UPCHK(hipMemcpyAsync(t->ranges.p, pl.ranges.data(), sizeof(Range) * nR, hipMemcpyHostToDevice, t->st));
-  UPCHK(hipMemcpyAsync(t->order.p, pl.order.data(), 4ull * nR, hipMemcpyHostToDevice, t->st));
-  UPCHK(hipMemcpyAsync(t->segfirst.p, pl.segfirst.data(), 4ull * (nS + 1), hipMemcpyHostToDevice, t->st));
-  UPCHK(hipMemcpyAsync(t->spans.p, pl.spans.data(), 4ull * pl.spans.size(), hipMemcpyHostToDevice, t->st));
+  // staged in pinned memory so the copies are asynchronous (the staging is
+  // reused only by the next flush, after this one has completed)
+  const size_t part[5] = {sizeof(Seg) * nS, sizeof(Range) * nR, 4ull * nR, 4ull * (nS + 1), 4ull * pl.spans.size()};
+  const void *src[5] = {pl.segs.data(), pl.ranges.data(), pl.order.data(), pl.segfirst.data(), pl.spans.data()};
+  void *dst[5] = {t->segs.p, t->ranges.p, t->order.p, t->segfirst.p, t->spans.p};
+  size_t tot = 0;
+  for (int i = 0; i < 5; i++) tot += (part[i] + 255) & ~(size_t)255;
+  if (tot > t->h_plan_cap) {
+    if (t->h_plan) hipHostFree(t->h_plan);
+    t->h_plan = nullptr;
+    t->h_plan_cap = 0;
+    UPCHK(hipHostMalloc(&t->h_plan, std::max<size_t>(tot, 1 << 16), hipHostMallocDefault));
+    t->h_plan_cap = std::max<size_t>(tot, 1 << 16);
+  }
+  uint8_t *hp = (uint8_t *)t->h_plan;
+  for (int i = 0; i < 5; i++) {
+    if (part[i]) {
+      memcpy(hp, src[i], part[i]);
+      UPCHK(hipMemcpyAsync(dst[i], hp, part[i], hipMemcpyHostToDevice, t->st));
+    }
+    hp += (part[i] + 255) & ~(size_t)255;
+  }
 #undef UPCHK
   return hipSuccess;
 }

@@ -385,26 +385,33 @@ __global__ __launch_bounds__(1024) void k_scan_counts(const uint32_t *__restrict
 }
 
 // ---------------------------------------------------------- fills / init
-__global__ void k_init_tally(Tally *t, size_t n) {
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-    Tally v;
-    v.count = 0; v.incl_sum = 0; v.incl_min = ~0ull; v.incl_max = 0;
-    v.self_sum = 0; v.self_min = ~0ull; v.self_max = 0; v.bytes_sum = 0;
-    t[i] = v;
-  }
-}
-__global__ void k_init_ktally(KTally *t, size_t n) {
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-    KTally v;
-    v.count = 0; v.sum = 0; v.min = ~0ull; v.max = 0;
-    t[i] = v;
-  }
-}
 __global__ void k_fill64(uint64_t *p, size_t n, uint64_t v) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
 }
 __global__ void k_fill32(uint32_t *p, size_t n, uint32_t v) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+// Every table of a handle at its initial value, in one launch.
+__global__ void k_init_all(InitSet is) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  const size_t i0 = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  for (size_t i = i0; i < is.n_gkeys; i += stride) is.gkeys[i] = EMPTY64;
+  for (size_t i = i0; i < is.n_gvals; i += stride) is.gvals[i] = GV_PENDING;
+  for (size_t i = i0; i < is.n_tally; i += stride) {
+    Tally v;
+    v.count = 0; v.incl_sum = 0; v.incl_min = ~0ull; v.incl_max = 0;
+    v.self_sum = 0; v.self_min = ~0ull; v.self_max = 0; v.bytes_sum = 0;
+    is.tally[i] = v;
+  }
+  for (size_t i = i0; i < is.n_ktally; i += stride) {
+    KTally v;
+    v.count = 0; v.sum = 0; v.min = ~0ull; v.max = 0;
+    is.ktally[i] = v;
+  }
+  for (size_t i = i0; i < is.n_cstate; i += stride) is.cstate[i] = 0;
+  for (size_t i = i0; i < is.n_sstats; i += stride) is.sstats[i] = 0;
+  if (i0 == 0) { *is.ngs = 0; *is.err = 0; }
 }
 
 // --------------------------------------------------------------- launchers
@@ -422,9 +429,12 @@ hipError_t launch_fill32(uint32_t *p, size_t n, uint32_t v, hipStream_t st) {
   if (n) hipLaunchKernelGGL(k_fill32, fill_grid(n), dim3(256), 0, st, p, n, v);
   return hipGetLastError();
 }
-hipError_t launch_init_tables(const Tables &tb, size_t n_tally, size_t n_ktally, hipStream_t st) {
-  if (n_tally) hipLaunchKernelGGL(k_init_tally, fill_grid(n_tally), dim3(256), 0, st, tb.tally, n_tally);
-  if (n_ktally) hipLaunchKernelGGL(k_init_ktally, fill_grid(n_ktally), dim3(256), 0, st, tb.ktally, n_ktally);
+hipError_t launch_init_all(const InitSet &is, hipStream_t st) {
+  size_t n = is.n_gkeys > is.n_tally ? is.n_gkeys : is.n_tally;
+  if (is.n_ktally > n) n = is.n_ktally;
+  if (is.n_cstate > n) n = is.n_cstate;
+  if (is.n_sstats > n) n = is.n_sstats;
+  hipLaunchKernelGGL(k_init_all, fill_grid(n), dim3(256), 0, st, is);
   return hipGetLastError();
 }
 hipError_t launch_combine(const uint32_t *spans, uint32_t n_spans, const RHdr *rhdr, const UItem *ru,

@@ -187,11 +187,24 @@ class Tally:
         self._keep = []
         return rc
 
-    def read(self, scope=SCOPE_THREAD, trace=ALL):
+    def read(self, scope=SCOPE_THREAD, trace=ALL, out=None):
+        """Rows of one scope (and stats).  With `out` (a ROW_DTYPE array the
+        caller reuses) the rows land there in one call when they fit, and a
+        view of it is returned; otherwise a new array (size query first)."""
         n = ctypes.c_size_t(0)
         st = Stats()
-        _check(self._lib.thapi_tally_read(self._h, scope, trace, None, 0, ctypes.byref(n), ctypes.byref(st)),
-               "read")
+        if out is not None and len(out):
+            if out.dtype != ROW_DTYPE or not out.flags.c_contiguous:
+                raise ValueError("out must be a contiguous ROW_DTYPE array")
+            rc = self._lib.thapi_tally_read(self._h, scope, trace, out.ctypes.data, len(out), ctypes.byref(n),
+                                            ctypes.byref(st))
+            if rc == OK:
+                return out[:n.value], {k: int(getattr(st, k)) for k in STAT_NAMES}
+            if rc != E_BUFSZ:
+                _check(rc, "read")
+        else:
+            _check(self._lib.thapi_tally_read(self._h, scope, trace, None, 0, ctypes.byref(n), ctypes.byref(st)),
+                   "read")
         rows = np.zeros(n.value, dtype=ROW_DTYPE)
         if n.value:
             _check(self._lib.thapi_tally_read(self._h, scope, trace, rows.ctypes.data, n.value, ctypes.byref(n),

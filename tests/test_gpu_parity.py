@@ -188,6 +188,26 @@ def test_device_input_payload_mismatch():
         assert st["records"] == 4 and len(rows) == 2
 
 
+def test_read_into_reused_buffer():
+    """read(out=...) fills a caller buffer in one call, and falls back when it is too small."""
+    say("case: read into a reused buffer")
+    from paper_2504_03683_amd import tally as T
+    w = synth.config(0, scale=0.05)
+    with T.Tally(T.FMT_FIXED24, w.n_fns, 0, max_depth=16, max_threads=256, max_streams=8) as t:
+        for s in w.streams:
+            t.submit(s.key, s.records)
+        t.flush(final=True)
+        for scope in (T.SCOPE_THREAD, T.SCOPE_PROCESS, T.SCOPE_FN):
+            ref, st_ref = t.read(scope)
+            big = np.zeros(len(ref) + 5, dtype=T.ROW_DTYPE)
+            got, st = t.read(scope, out=big)
+            assert np.array_equal(got, ref) and st == st_ref
+            assert got.base is big or got.base is big.base
+            small = np.zeros(max(len(ref) - 1, 1), dtype=T.ROW_DTYPE)
+            got2, _ = t.read(scope, out=small)
+            assert np.array_equal(got2, ref)
+
+
 def test_reset_and_repeat_determinism():
     say("case: reset and repeat")
     from paper_2504_03683_amd import tally as T

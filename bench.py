@@ -127,7 +127,10 @@ def main():
     tl = T.Tally(w.fmt, w.n_fns, w.n_kernel_ids, max_depth=max(w.max_depth, 8), max_threads=max_threads,
                  max_streams=64, flags=T.DEVICE_INPUT | T.PROFILE, has_size=w.has_size, stream=stream)
 
-    rowbuf = np.zeros(max_threads * w.n_fns, dtype=T.ROW_DTYPE)   # reused by every read (capacity: all rows)
+    # reused by every read (capacity: all rows), in pinned host memory so the
+    # rows arrive by DMA
+    rowbuf = torch.zeros(max_threads * w.n_fns * T.ROW_DTYPE.itemsize, dtype=torch.uint8,
+                         pin_memory=True).numpy().view(T.ROW_DTYPE)
 
     def step():
         tl.reset()

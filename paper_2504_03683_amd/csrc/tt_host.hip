@@ -625,6 +625,34 @@ void plan_work(const thapi_tally *t, const std::vector<Chunk> &work, const Shape
                    [&](uint32_t a, uint32_t b) { return pl.ranges[a].n > pl.ranges[b].n; });
 }
 
+// Host -> device copies of n host arrays through the pinned staging buffer,
+// so that they are asynchronous.  The staging is reused by the next call only,
+// which comes after the work that these copies feed has completed (flushes
+// and reads each end with a synchronisation).
+hipError_t stage_h2d(thapi_tally *t, void *const *dst, const void *const *src, const size_t *bytes, int n) {
+  size_t tot = 0;
+  for (int i = 0; i < n; i++) tot += (bytes[i] + 255) & ~(size_t)255;
+  if (tot > t->h_plan_cap) {
+    if (t->h_plan) hipHostFree(t->h_plan);
+    t->h_plan = nullptr;
+    t->h_plan_cap = 0;
+    const size_t want = std::max<size_t>(tot, 1 << 16);
+    hipError_t e = hipHostMalloc(&t->h_plan, want, hipHostMallocDefault);
+    if (e != hipSuccess) return e;
+    t->h_plan_cap = want;
+  }
+  uint8_t *hp = (uint8_t *)t->h_plan;
+  for (int i = 0; i < n; i++) {
+    if (bytes[i]) {
+      memcpy(hp, src[i], bytes[i]);
+      hipError_t e = hipMemcpyAsync(dst[i], hp, bytes[i], hipMemcpyHostToDevice, t->st);
+      if (e != hipSuccess) return e;
+    }
+    hp += (bytes[i] + 255) & ~(size_t)255;
+  }
+  return hipSuccess;
+}
+
 hipError_t upload_plan(thapi_tally *t, const Plan &pl) {
   const uint32_t nR = (uint32_t)pl.ranges.size(), nS = (uint32_t)pl.segs.size();
   const uint32_t D = t->cfg.max_depth;
@@ -641,28 +669,10 @@ hipError_t upload_plan(thapi_tally *t, const Plan &pl) {
   UPCHK(t->ro.ensure(sizeof(OItem) * (size_t)nR * S_MAX * D));
   UPCHK(t->rnslots.ensure(4ull * nR));
   UPCHK(t->paylen.ensure(8ull * nR));
-  // staged in pinned memory so the copies are asynchronous (the staging is
-  // reused only by the next flush, after this one has completed)
   const size_t part[5] = {sizeof(Seg) * nS, sizeof(Range) * nR, 4ull * nR, 4ull * (nS + 1), 4ull * pl.spans.size()};
   const void *src[5] = {pl.segs.data(), pl.ranges.data(), pl.order.data(), pl.segfirst.data(), pl.spans.data()};
   void *dst[5] = {t->segs.p, t->ranges.p, t->order.p, t->segfirst.p, t->spans.p};
-  size_t tot = 0;
-  for (int i = 0; i < 5; i++) tot += (part[i] + 255) & ~(size_t)255;
-  if (tot > t->h_plan_cap) {
-    if (t->h_plan) hipHostFree(t->h_plan);
-    t->h_plan = nullptr;
-    t->h_plan_cap = 0;
-    UPCHK(hipHostMalloc(&t->h_plan, std::max<size_t>(tot, 1 << 16), hipHostMallocDefault));
-    t->h_plan_cap = std::max<size_t>(tot, 1 << 16);
-  }
-  uint8_t *hp = (uint8_t *)t->h_plan;
-  for (int i = 0; i < 5; i++) {
-    if (part[i]) {
-      memcpy(hp, src[i], part[i]);
-      UPCHK(hipMemcpyAsync(dst[i], hp, part[i], hipMemcpyHostToDevice, t->st));
-    }
-    hp += (part[i] + 255) & ~(size_t)255;
-  }
+  UPCHK(stage_h2d(t, dst, src, part, 5));
 #undef UPCHK
   return hipSuccess;
 }
@@ -1057,19 +1067,22 @@ int thapi_tally_read(thapi_tally *t, uint32_t scope, uint32_t trace_id, thapi_ta
   }
   const uint32_t ntrace = (uint32_t)(tspan.size() / 2);
   HIPCHK(timed_begin(t, TM_READOUT));
-  HIPCHK(ensure_pinned(t, 64));
+  // thread count, per-stream thread statistics and counters in one round
+  // trip, through pinned memory
+  const size_t ns1 = std::max<uint32_t>(nstreams, 1);
+  HIPCHK(ensure_pinned(t, 64 + 24 * ns1 + 8 * ns1 * ST_N));
   uint32_t *hng = (uint32_t *)t->h_pinned;
+  const uint64_t *ts3 = (const uint64_t *)((uint8_t *)t->h_pinned + 64);
+  const uint64_t *sst = ts3 + 3 * ns1;
+  HIPCHK(t->tstats.ensure(24ull * ns1));
+  HIPCHK(launch_fill64(t->tstats.as<uint64_t>(), 3ull * ns1, 0, t->st));
+  HIPCHK(launch_thread_stats(t->tb, t->cfg.max_threads, t->tstats.as<unsigned long long>(), t->st));
   HIPCHK(hipMemcpyAsync(hng, t->tb.n_gslots, 4, hipMemcpyDeviceToHost, t->st));
+  HIPCHK(hipMemcpyAsync((void *)ts3, t->tstats.p, 24ull * ns1, hipMemcpyDeviceToHost, t->st));
+  if (nstreams)
+    HIPCHK(hipMemcpyAsync((void *)sst, t->tb.sstats, 8ull * nstreams * ST_N, hipMemcpyDeviceToHost, t->st));
   HIPCHK(hipStreamSynchronize(t->st));
   const uint32_t ng = std::min<uint32_t>(*hng, t->cfg.max_threads);
-  // per-stream thread statistics
-  HIPCHK(t->tstats.ensure(24ull * std::max<uint32_t>(nstreams, 1)));
-  HIPCHK(launch_fill64(t->tstats.as<uint64_t>(), 3ull * std::max<uint32_t>(nstreams, 1), 0, t->st));
-  if (ng) HIPCHK(launch_thread_stats(t->tb, ng, t->tstats.as<unsigned long long>(), t->st));
-  std::vector<uint64_t> ts3(3ull * std::max<uint32_t>(nstreams, 1), 0), sst((size_t)std::max<uint32_t>(nstreams, 1) * ST_N, 0);
-  HIPCHK(hipMemcpyAsync(ts3.data(), t->tstats.p, 24ull * std::max<uint32_t>(nstreams, 1), hipMemcpyDeviceToHost, t->st));
-  if (nstreams) HIPCHK(hipMemcpyAsync(sst.data(), t->tb.sstats, 8ull * nstreams * ST_N, hipMemcpyDeviceToHost, t->st));
-  HIPCHK(hipStreamSynchronize(t->st));
   thapi_tally_stats stats_all{};
   {
     thapi_tally_stats s{};
@@ -1109,10 +1122,17 @@ int thapi_tally_read(thapi_tally *t, uint32_t scope, uint32_t trace_id, thapi_ta
   const uint32_t maxg = std::max<uint32_t>(std::max<uint32_t>(nsel_threads, nrank), 1);
   HIPCHK(t->cnt.ensure(4ull * maxg));
   HIPCHK(t->off.ensure(8ull * (maxg + 1)));
-  HIPCHK(hipMemcpyAsync(t->stream_rank.p, srank.data(), 4ull * srank.size(), hipMemcpyHostToDevice, t->st));
-  HIPCHK(hipMemcpyAsync(t->rank_key.p, rank_key.data(), 4ull * rank_key.size(), hipMemcpyHostToDevice, t->st));
-  if (!tspan.empty())
-    HIPCHK(hipMemcpyAsync(t->trace_span.p, tspan.data(), 4ull * tspan.size(), hipMemcpyHostToDevice, t->st));
+  std::vector<uint32_t> rank_stream(std::max<uint32_t>(nrank, 1), 0);
+  for (uint32_t r = 0; r < nrank; r++) rank_stream[r] = sel[r];
+  HIPCHK(t->rstream.ensure(4ull * rank_stream.size()));
+  {
+    // host tables of the readout, staged in pinned memory (the work-list
+    // staging is free between flushes)
+    const void *src[4] = {srank.data(), rank_key.data(), tspan.data(), rank_stream.data()};
+    void *dst[4] = {t->stream_rank.p, t->rank_key.p, t->trace_span.p, t->rstream.p};
+    const size_t part[4] = {4ull * srank.size(), 4ull * rank_key.size(), 4ull * tspan.size(), 4ull * rank_stream.size()};
+    HIPCHK(stage_h2d(t, dst, src, part, 4));
+  }
   HIPCHK(launch_fill32(t->gbeg.as<uint32_t>(), std::max<uint32_t>(nrank, 1), 0, t->st));
   HIPCHK(launch_fill32(t->gend.as<uint32_t>(), std::max<uint32_t>(nrank, 1), 0, t->st));
   if (ng) {
@@ -1127,10 +1147,6 @@ int thapi_tally_read(thapi_tally *t, uint32_t scope, uint32_t trace_id, thapi_ta
   rc.keys = t->keys.as<uint64_t>(); rc.vals = t->vals.as<uint32_t>();
   rc.gbeg = t->gbeg.as<uint32_t>(); rc.gend = t->gend.as<uint32_t>();
   rc.rank_key = t->rank_key.as<uint32_t>(); rc.trace_span = t->trace_span.as<uint32_t>();
-  std::vector<uint32_t> rank_stream(std::max<uint32_t>(nrank, 1), 0);
-  for (uint32_t r = 0; r < nrank; r++) rank_stream[r] = sel[r];
-  HIPCHK(t->rstream.ensure(4ull * rank_stream.size()));
-  HIPCHK(hipMemcpyAsync(t->rstream.p, rank_stream.data(), 4ull * rank_stream.size(), hipMemcpyHostToDevice, t->st));
   rc.rank_stream = t->rstream.as<uint32_t>();
   uint32_t ngroups = 0;
   if (scope == THAPI_SCOPE_THREAD) ngroups = ng ? nsel_threads : 0;

@@ -24,6 +24,7 @@ __device__ inline void gmax64(uint64_t *p, uint64_t v) {
 // range's floor time goes to the call left on top; O items are pushed.
 constexpr int CB_SET = 2048;
 constexpr int CB_MAP = 16384;   // (range, thread) -> slot table, used when the span fits
+constexpr int CB_STK = 512;     // frames of the carried stacks held in LDS during the fold, when they fit
 
 __global__ __launch_bounds__(256) void k_combine(const uint32_t *__restrict__ spans, const RHdr *__restrict__ rhdr,
                                                  const UItem *__restrict__ ru, const OItem *__restrict__ ro,
@@ -32,6 +33,7 @@ __global__ __launch_bounds__(256) void k_combine(const uint32_t *__restrict__ sp
   __shared__ uint32_t set_val[CB_SET];
   __shared__ uint32_t list[CB_SET];
   __shared__ uint8_t smap[CB_MAP];
+  __shared__ Frame lstk[CB_STK];
   __shared__ uint32_t nlist;
   __shared__ uint32_t lcnt[ST_N];
   const uint32_t stream = spans[3 * blockIdx.x], rb = spans[3 * blockIdx.x + 1], re = spans[3 * blockIdx.x + 2];
@@ -41,9 +43,12 @@ __global__ __launch_bounds__(256) void k_combine(const uint32_t *__restrict__ sp
   if (tid < ST_N) lcnt[tid] = 0;
   if (tid == 0) nlist = 0;
   __syncthreads();
-  for (uint32_t r = rb; r < re; r++) {
-    const uint32_t ns = rnslots[r];
-    for (uint32_t s = tid; s < ns; s += 256) {
+  // (range, slot) pairs are spread over all lanes, so the header loads of
+  // different ranges are in flight together
+  for (uint32_t x = tid; x < (re - rb) * (uint32_t)S_MAX; x += 256) {
+    const uint32_t r = rb + x / S_MAX, s = x % S_MAX;
+    if (s >= rnslots[r]) continue;
+    {
       const uint32_t g = rhdr[(size_t)r * S_MAX + s].gslot;
       if (g >= tb.max_threads) continue;
       uint32_t h = hash32(g) & (CB_SET - 1);
@@ -68,9 +73,10 @@ __global__ __launch_bounds__(256) void k_combine(const uint32_t *__restrict__ sp
   if (use_map) {
     for (uint32_t i = tid; i < (re - rb) * n; i += 256) smap[i] = 0xFF;
     __syncthreads();
-    for (uint32_t r = rb; r < re; r++) {
-      const uint32_t ns = rnslots[r];
-      for (uint32_t s = tid; s < ns; s += 256) {
+    for (uint32_t x = tid; x < (re - rb) * (uint32_t)S_MAX; x += 256) {
+      const uint32_t r = rb + x / S_MAX, s = x % S_MAX;
+      if (s >= rnslots[r]) continue;
+      {
         const uint32_t g = rhdr[(size_t)r * S_MAX + s].gslot;
         if (g >= tb.max_threads) continue;
         uint32_t h = hash32(g) & (CB_SET - 1);
@@ -88,24 +94,53 @@ __global__ __launch_bounds__(256) void k_combine(const uint32_t *__restrict__ sp
     }
     __syncthreads();
   }
+  // the carried stacks move to LDS for the fold when they fit (set_val, no
+  // longer needed, holds each listed thread's height)
+  const bool lds_stack = (uint64_t)n * D <= (uint64_t)CB_STK;
+  if (lds_stack) {
+    for (uint32_t i = tid; i < n; i += 256) set_val[i] = tb.cstate[list[i]].h;
+    __syncthreads();
+    for (uint32_t x = tid; x < n * D; x += 256) {
+      const uint32_t i = x / D, f = x - i * D;
+      if (f < set_val[i]) lstk[x] = tb.cstack[(size_t)list[i] * D + f];
+    }
+    __syncthreads();
+  }
   uint32_t c_tsreg = 0, c_orphan = 0, c_mis = 0, c_neg = 0, c_under = 0;
   for (uint32_t i = tid; i < n; i += 256) {
     const uint32_t g = list[i];
     CState cs = tb.cstate[g];
-    Frame *stk = tb.cstack + (size_t)g * D;
-    for (uint32_t r = rb; r < re; r++) {
+    Frame *stk = lds_stack ? lstk + (size_t)i * D : tb.cstack + (size_t)g * D;
+    // slot of this thread in range r's summaries, S_MAX when it has none
+    auto slot_in = [&](const uint32_t r) -> uint32_t {
+      if (use_map) {
+        const uint32_t s = smap[(r - rb) * n + i];
+        return s == 0xFF ? (uint32_t)S_MAX : s;
+      }
       const uint32_t ns = rnslots[r];
       const RHdr *hp = rhdr + (size_t)r * S_MAX;
       uint32_t s = 0;
-      if (use_map) {
-        s = smap[(r - rb) * n + i];
-        if (s == 0xFF) continue;
-      } else {
-        while (s < ns && hp[s].gslot != g) s++;
-        if (s == ns) continue;
+      while (s < ns && hp[s].gslot != g) s++;
+      return s < ns ? s : (uint32_t)S_MAX;
+    };
+    auto next_range = [&](uint32_t r, uint32_t &s) {
+      for (; r < re; r++) {
+        s = slot_in(r);
+        if (s < (uint32_t)S_MAX) break;
       }
-      const RHdr hd = hp[s];
+      return r;
+    };
+    // each range's header is loaded while the previous range is folded
+    uint32_t s = 0;
+    uint32_t r = next_range(rb, s);
+    RHdr hd_next;
+    if (r < re) hd_next = rhdr[(size_t)r * S_MAX + s];
+    while (r < re) {
+      const RHdr hd = hd_next;
       const size_t ib = ((size_t)r * S_MAX + s) * D;
+      uint32_t s2 = 0;
+      const uint32_t r2 = next_range(r + 1, s2);
+      if (r2 < re) hd_next = rhdr[(size_t)r2 * S_MAX + s2];
       if (hd.flags & RF_HAS_TS) {
         if ((cs.flags & CS_HAS_TS) && hd.first_ts < cs.last_ts) c_tsreg++;
         cs.last_ts = hd.last_ts;
@@ -113,40 +148,66 @@ __global__ __launch_bounds__(256) void k_combine(const uint32_t *__restrict__ sp
       }
       const int32_t ds = (int32_t)cs.h;
       if ((hd.flags & RF_OVERFLOW) || hd.H > (int32_t)D || ds + hd.M > (int32_t)D) cs.flags |= CS_OVERFLOW;
-      for (uint32_t k = 0; k < hd.nu_listed; k++) {
-        const UItem u = ru[ib + k];
-        if (cs.h == 0) { c_orphan++; continue; }
-        cs.h--;
-        const Frame e = stk[cs.h];
-        if (e.fn != u.fn || u.fn >= tb.n_fns) { c_mis++; continue; }
-        if (u.ts < e.ts) { c_neg++; continue; }
-        const uint64_t incl = u.ts - e.ts;
-        const uint64_t ch = e.child + u.child;
-        uint64_t self;
-        if (ch <= incl) self = incl - ch; else { self = 0; c_under++; }
-        Tally *t = &tb.tally[(size_t)g * tb.n_fns + u.fn];
-        ga64(&t->count, 1);
-        ga64(&t->incl_sum, incl); gmin64(&t->incl_min, incl); gmax64(&t->incl_max, incl);
-        ga64(&t->self_sum, self); gmin64(&t->self_min, self); gmax64(&t->self_max, self);
-        if (e.bytes) ga64(&t->bytes_sum, e.bytes);
-        if (cs.h > 0) stk[cs.h - 1].child += incl;
+      // U items, four loads in flight at a time
+      for (uint32_t k0 = 0; k0 < hd.nu_listed; k0 += 4) {
+        UItem uu[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++)
+          if (k0 + j < hd.nu_listed) uu[j] = ru[ib + k0 + j];
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+          if (k0 + j >= hd.nu_listed) break;
+          const UItem &u = uu[j];
+          if (cs.h == 0) { c_orphan++; continue; }
+          cs.h--;
+          const Frame e = stk[cs.h];
+          if (e.fn != u.fn || u.fn >= tb.n_fns) { c_mis++; continue; }
+          if (u.ts < e.ts) { c_neg++; continue; }
+          const uint64_t incl = u.ts - e.ts;
+          const uint64_t ch = e.child + u.child;
+          uint64_t self;
+          if (ch <= incl) self = incl - ch; else { self = 0; c_under++; }
+          Tally *t = &tb.tally[(size_t)g * tb.n_fns + u.fn];
+          ga64(&t->count, 1);
+          ga64(&t->incl_sum, incl); gmin64(&t->incl_min, incl); gmax64(&t->incl_max, incl);
+          ga64(&t->self_sum, self); gmin64(&t->self_min, self); gmax64(&t->self_max, self);
+          if (e.bytes) ga64(&t->bytes_sum, e.bytes);
+          if (cs.h > 0) stk[cs.h - 1].child += incl;
+        }
       }
       if (cs.h > 0) stk[cs.h - 1].child += hd.floor;
       const uint32_t no = hd.n_o < D ? hd.n_o : D;
-      for (uint32_t k = 0; k < no; k++) {
-        if (cs.h < D) {
-          const OItem o = ro[ib + k];
-          Frame f;
-          f.ts = o.ts; f.child = o.child; f.bytes = o.bytes; f.fn = o.fn; f.pad = 0;
-          stk[cs.h] = f;
-          cs.h++;
-        } else {
-          cs.flags |= CS_OVERFLOW;
+      for (uint32_t k0 = 0; k0 < no; k0 += 4) {
+        OItem oo[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++)
+          if (k0 + j < no) oo[j] = ro[ib + k0 + j];
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+          if (k0 + j >= no) break;
+          if (cs.h < D) {
+            Frame f;
+            f.ts = oo[j].ts; f.child = oo[j].child; f.bytes = oo[j].bytes; f.fn = oo[j].fn; f.pad = 0;
+            stk[cs.h] = f;
+            cs.h++;
+          } else {
+            cs.flags |= CS_OVERFLOW;
+          }
         }
       }
+      r = r2;
+      s = s2;
     }
     if (cs.flags & CS_OVERFLOW) atomicOr(tb.err, ERR_DEPTH);
     tb.cstate[g] = cs;
+    if (lds_stack) set_val[i] = cs.h;
+  }
+  if (lds_stack) {
+    __syncthreads();
+    for (uint32_t x = tid; x < n * D; x += 256) {
+      const uint32_t i = x / D, f = x - i * D;
+      if (f < set_val[i]) tb.cstack[(size_t)list[i] * D + f] = lstk[x];
+    }
   }
   if (c_tsreg) atomicAdd(&lcnt[ST_TSREG], c_tsreg);
   if (c_orphan) atomicAdd(&lcnt[ST_ORPHAN], c_orphan);

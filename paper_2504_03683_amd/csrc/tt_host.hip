@@ -587,13 +587,21 @@ void plan_work(const thapi_tally *t, const std::vector<Chunk> &work, const Shape
   // The work list holds about rpc * n_cu ranges: with n_seg chunks, ranges of
   // ceil(total / (rpc * n_cu - n_seg)) records give at most rpc * n_cu of
   // them (each chunk adds at most one partial range).  Ranges are never
-  // shorter than 16 tiles.
+  // shorter than 4 tiles, and a stream gets at most about RANGE_CHAIN of them
+  // (the combine folds one stream's ranges one after the other), so a small
+  // flush still spreads over several workgroups and a long single stream does
+  // not make a long fold.
+  constexpr uint64_t RANGE_CHAIN = 32;
   uint64_t n_seg = 0;
-  for (auto &c : work) n_seg += c.n_rec ? 1 : 0;
+  std::map<uint32_t, uint64_t> per_stream;
+  for (auto &c : work) {
+    n_seg += c.n_rec ? 1 : 0;
+    per_stream[c.stream] += c.n_rec;
+  }
   const uint64_t ncu = std::max<uint64_t>(1, (uint64_t)t->n_cu) * std::max<uint32_t>(1, sh.rpc);
   const uint64_t target = ncu > 2 * n_seg ? ncu - n_seg : std::max<uint64_t>(1, ncu / 2);
   uint64_t rlen = (pl.total + target - 1) / target;
-  rlen = std::max<uint64_t>(rlen, 16ull * sh.T);
+  rlen = std::max<uint64_t>(rlen, 4ull * sh.T);
   rlen = std::min<uint64_t>(rlen, 1ull << 30);
   for (size_t i = 0; i < work.size(); i++) {
     const Chunk &c = work[i];
@@ -603,7 +611,8 @@ void plan_work(const thapi_tally *t, const std::vector<Chunk> &work, const Shape
     pl.segfirst.push_back((uint32_t)pl.ranges.size());
     const uint32_t si = (uint32_t)pl.segs.size();
     pl.segs.push_back(sg);
-    const uint64_t nr = (c.n_rec + rlen - 1) / rlen;
+    const uint64_t rl = std::max<uint64_t>(rlen, (per_stream[c.stream] + RANGE_CHAIN - 1) / RANGE_CHAIN);
+    const uint64_t nr = (c.n_rec + rl - 1) / rl;
     const uint64_t step = (c.n_rec + nr - 1) / nr;
     for (uint64_t b = 0; b < c.n_rec; b += step) {
       Range r{};

@@ -11,6 +11,7 @@
 #include <array>
 #include <atomic>
 #include <condition_variable>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -587,11 +588,14 @@ void plan_work(const thapi_tally *t, const std::vector<Chunk> &work, const Shape
   // The work list holds about rpc * n_cu ranges: with n_seg chunks, ranges of
   // ceil(total / (rpc * n_cu - n_seg)) records give at most rpc * n_cu of
   // them (each chunk adds at most one partial range).  Ranges are never
-  // shorter than 4 tiles, and a stream gets at most about RANGE_CHAIN of them
-  // (the combine folds one stream's ranges one after the other), so a small
-  // flush still spreads over several workgroups and a long single stream does
-  // not make a long fold.
-  constexpr uint64_t RANGE_CHAIN = 32;
+  // shorter than 4 tiles.  The combine folds one stream's range summaries one
+  // after the other, so a stream of N records gets at most about
+  // sqrt(N / RANGE_FOLD) ranges: the count that balances the range kernel's
+  // time (N / R records per workgroup) against the fold's (R summaries), with
+  // RANGE_FOLD the records a workgroup tallies in the time one summary takes
+  // to fold (measured: about 4.7 ns per record; 3-6 us per summary, more for
+  // more threads per stream).
+  constexpr double RANGE_FOLD = 1000.0;
   uint64_t n_seg = 0;
   std::map<uint32_t, uint64_t> per_stream;
   for (auto &c : work) {
@@ -611,7 +615,9 @@ void plan_work(const thapi_tally *t, const std::vector<Chunk> &work, const Shape
     pl.segfirst.push_back((uint32_t)pl.ranges.size());
     const uint32_t si = (uint32_t)pl.segs.size();
     pl.segs.push_back(sg);
-    const uint64_t rl = std::max<uint64_t>(rlen, (per_stream[c.stream] + RANGE_CHAIN - 1) / RANGE_CHAIN);
+    const uint64_t ns = per_stream[c.stream];
+    const uint64_t rmax = std::max<uint64_t>(1, (uint64_t)std::sqrt((double)ns / RANGE_FOLD));
+    const uint64_t rl = std::max<uint64_t>(rlen, (ns + rmax - 1) / rmax);
     const uint64_t nr = (c.n_rec + rl - 1) / rl;
     const uint64_t step = (c.n_rec + nr - 1) / nr;
     for (uint64_t b = 0; b < c.n_rec; b += step) {

@@ -33,6 +33,7 @@ hipError_t launch_range(int fmt, uint32_t T, const Seg *segs, const Range *range
                         uint32_t n_ranges, uint32_t *qhead, uint32_t n_wg, const Tables &tb, const Shape &sh,
                         RHdr *rhdr, UItem *ru, OItem *ro, uint32_t *rnslots, hipStream_t st);
 hipError_t prepare_range_kernels(uint32_t max_lds_bytes);
+hipError_t prepare_combine_kernel();
 hipError_t launch_paylen(const Seg *segs, Range *ranges, uint32_t n_ranges, const uint32_t *seg_first_range,
                          uint32_t n_segs, uint64_t *paylen, uint32_t *err, hipStream_t st);
 hipError_t launch_fill64(uint64_t *p, size_t n, uint64_t v, hipStream_t st);
@@ -385,6 +386,7 @@ int thapi_tally_open(const thapi_tally_config *cfg, thapi_tally **out) {
   }
   load_tune_cache(t);
   if (prepare_range_kernels((uint32_t)(t->lds_limit - 256)) != hipSuccess) return bail(THAPI_E_DEVICE);
+  if (prepare_combine_kernel() != hipSuccess) return bail(THAPI_E_DEVICE);
   if (c.flags & THAPI_SERVICE) {
     if (hipStreamCreateWithFlags(&t->cst, hipStreamNonBlocking) != hipSuccess) return bail(THAPI_E_DEVICE);
     if (!(c.flags & THAPI_DEVICE_INPUT) && hipMalloc((void **)&t->arena, c.device_budget_bytes) != hipSuccess) {

@@ -25,6 +25,7 @@ __device__ inline void gmax64(uint64_t *p, uint64_t v) {
 constexpr int CB_SET = 2048;
 constexpr int CB_MAP = 16384;   // (range, thread) -> slot table, used when the span fits
 constexpr int CB_STK = 512;     // frames of the carried stacks held in LDS during the fold, when they fit
+constexpr int CB_DYN = 96 * 1024;  // dynamic LDS for the span's summaries, staged when they fit
 
 __global__ __launch_bounds__(256) void k_combine(const uint32_t *__restrict__ spans, const RHdr *__restrict__ rhdr,
                                                  const UItem *__restrict__ ru, const OItem *__restrict__ ro,
@@ -34,6 +35,7 @@ __global__ __launch_bounds__(256) void k_combine(const uint32_t *__restrict__ sp
   __shared__ uint32_t list[CB_SET];
   __shared__ uint8_t smap[CB_MAP];
   __shared__ Frame lstk[CB_STK];
+  extern __shared__ __align__(16) uint8_t cdyn[];   // CB_DYN bytes: the span's staged summaries
   __shared__ uint32_t nlist;
   __shared__ uint32_t lcnt[ST_N];
   const uint32_t stream = spans[3 * blockIdx.x], rb = spans[3 * blockIdx.x + 1], re = spans[3 * blockIdx.x + 2];
@@ -106,41 +108,69 @@ __global__ __launch_bounds__(256) void k_combine(const uint32_t *__restrict__ sp
     }
     __syncthreads();
   }
+  // The span's summaries staged in LDS when they fit: headers by (range,
+  // thread) pair, then each pair's U items followed by its O items, packed by
+  // an exclusive scan of the pairs' item counts (set_key, no longer needed,
+  // holds the per-lane partial sums).  The fold then reads LDS only.
+  bool staged = false;
+  RHdr *const hdrL = (RHdr *)cdyn;
+  uint32_t *offL = nullptr;
+  uint8_t *itL = nullptr;
+  if (use_map) {
+    const uint32_t np = (re - rb) * n;
+    const size_t hbytes = (size_t)np * sizeof(RHdr), obytes = ((size_t)np * 4 + 15) & ~(size_t)15;
+    if (hbytes + obytes <= (size_t)CB_DYN) {
+      offL = (uint32_t *)(cdyn + hbytes);
+      itL = cdyn + hbytes + obytes;
+      for (uint32_t x = tid; x < np; x += 256) {
+        const uint32_t sl = smap[x];
+        if (sl != 0xFF) hdrL[x] = rhdr[(size_t)(rb + x / n) * S_MAX + sl];
+      }
+      __syncthreads();
+      auto cnt = [&](const uint32_t x) -> uint32_t {
+        if (smap[x] == 0xFF) return 0;
+        return hdrL[x].nu_listed + (hdrL[x].n_o < D ? hdrL[x].n_o : D);
+      };
+      const uint32_t chunk = (np + 255) / 256, lo = tid * chunk, hi = lo + chunk < np ? lo + chunk : np;
+      uint32_t part = 0;
+      for (uint32_t x = lo; x < hi; x++) part += cnt(x);
+      set_key[tid] = part;
+      __syncthreads();
+      if (tid == 0) {
+        uint32_t acc = 0;
+        for (int k = 0; k < 256; k++) { const uint32_t v = set_key[k]; set_key[k] = acc; acc += v; }
+        set_key[256] = acc;
+      }
+      __syncthreads();
+      uint32_t run = set_key[tid];
+      for (uint32_t x = lo; x < hi; x++) { offL[x] = run; run += cnt(x); }
+      const uint32_t total = set_key[256];
+      __syncthreads();
+      if (hbytes + obytes + (size_t)total * 32 <= (size_t)CB_DYN) {
+        staged = true;
+        for (uint32_t x = tid; x < np; x += 256) {
+          const uint32_t sl = smap[x];
+          if (sl == 0xFF) continue;
+          const size_t ib = ((size_t)(rb + x / n) * S_MAX + sl) * D;
+          const RHdr &hd = hdrL[x];
+          UItem *du = (UItem *)(itL + (size_t)offL[x] * 32);
+          for (uint32_t k = 0; k < hd.nu_listed; k++) du[k] = ru[ib + k];
+          OItem *dq = (OItem *)(du + hd.nu_listed);
+          const uint32_t no = hd.n_o < D ? hd.n_o : D;
+          for (uint32_t k = 0; k < no; k++) dq[k] = ro[ib + k];
+        }
+        __syncthreads();
+      }
+    }
+  }
   uint32_t c_tsreg = 0, c_orphan = 0, c_mis = 0, c_neg = 0, c_under = 0;
   for (uint32_t i = tid; i < n; i += 256) {
     const uint32_t g = list[i];
     CState cs = tb.cstate[g];
     Frame *stk = lds_stack ? lstk + (size_t)i * D : tb.cstack + (size_t)g * D;
-    // slot of this thread in range r's summaries, S_MAX when it has none
-    auto slot_in = [&](const uint32_t r) -> uint32_t {
-      if (use_map) {
-        const uint32_t s = smap[(r - rb) * n + i];
-        return s == 0xFF ? (uint32_t)S_MAX : s;
-      }
-      const uint32_t ns = rnslots[r];
-      const RHdr *hp = rhdr + (size_t)r * S_MAX;
-      uint32_t s = 0;
-      while (s < ns && hp[s].gslot != g) s++;
-      return s < ns ? s : (uint32_t)S_MAX;
-    };
-    auto next_range = [&](uint32_t r, uint32_t &s) {
-      for (; r < re; r++) {
-        s = slot_in(r);
-        if (s < (uint32_t)S_MAX) break;
-      }
-      return r;
-    };
-    // each range's header is loaded while the previous range is folded
-    uint32_t s = 0;
-    uint32_t r = next_range(rb, s);
-    RHdr hd_next;
-    if (r < re) hd_next = rhdr[(size_t)r * S_MAX + s];
-    while (r < re) {
-      const RHdr hd = hd_next;
-      const size_t ib = ((size_t)r * S_MAX + s) * D;
-      uint32_t s2 = 0;
-      const uint32_t r2 = next_range(r + 1, s2);
-      if (r2 < re) hd_next = rhdr[(size_t)r2 * S_MAX + s2];
+    // one range summary onto the carried stack; uat(k) / oat(k) give its
+    // U / O items (read four at a time)
+    auto fold_one = [&](const RHdr &hd, auto &&uat, auto &&oat) {
       if (hd.flags & RF_HAS_TS) {
         if ((cs.flags & CS_HAS_TS) && hd.first_ts < cs.last_ts) c_tsreg++;
         cs.last_ts = hd.last_ts;
@@ -148,12 +178,11 @@ __global__ __launch_bounds__(256) void k_combine(const uint32_t *__restrict__ sp
       }
       const int32_t ds = (int32_t)cs.h;
       if ((hd.flags & RF_OVERFLOW) || hd.H > (int32_t)D || ds + hd.M > (int32_t)D) cs.flags |= CS_OVERFLOW;
-      // U items, four loads in flight at a time
       for (uint32_t k0 = 0; k0 < hd.nu_listed; k0 += 4) {
         UItem uu[4];
 #pragma unroll
         for (int j = 0; j < 4; j++)
-          if (k0 + j < hd.nu_listed) uu[j] = ru[ib + k0 + j];
+          if (k0 + j < hd.nu_listed) uu[j] = uat(k0 + j);
 #pragma unroll
         for (int j = 0; j < 4; j++) {
           if (k0 + j >= hd.nu_listed) break;
@@ -181,7 +210,7 @@ __global__ __launch_bounds__(256) void k_combine(const uint32_t *__restrict__ sp
         OItem oo[4];
 #pragma unroll
         for (int j = 0; j < 4; j++)
-          if (k0 + j < no) oo[j] = ro[ib + k0 + j];
+          if (k0 + j < no) oo[j] = oat(k0 + j);
 #pragma unroll
         for (int j = 0; j < 4; j++) {
           if (k0 + j >= no) break;
@@ -195,8 +224,51 @@ __global__ __launch_bounds__(256) void k_combine(const uint32_t *__restrict__ sp
           }
         }
       }
-      r = r2;
-      s = s2;
+    };
+    if (staged) {
+      for (uint32_t r = rb; r < re; r++) {
+        const uint32_t x = (r - rb) * n + i;
+        if (smap[x] == 0xFF) continue;
+        const RHdr hd = hdrL[x];
+        const UItem *lu = (const UItem *)(itL + (size_t)offL[x] * 32);
+        const OItem *lo = (const OItem *)(lu + hd.nu_listed);
+        fold_one(hd, [&](uint32_t k) { return lu[k]; }, [&](uint32_t k) { return lo[k]; });
+      }
+    } else {
+      // slot of this thread in range r's summaries, S_MAX when it has none
+      auto slot_in = [&](const uint32_t r) -> uint32_t {
+        if (use_map) {
+          const uint32_t sl = smap[(r - rb) * n + i];
+          return sl == 0xFF ? (uint32_t)S_MAX : sl;
+        }
+        const uint32_t ns = rnslots[r];
+        const RHdr *hp = rhdr + (size_t)r * S_MAX;
+        uint32_t sl = 0;
+        while (sl < ns && hp[sl].gslot != g) sl++;
+        return sl < ns ? sl : (uint32_t)S_MAX;
+      };
+      auto next_range = [&](uint32_t r, uint32_t &sl) {
+        for (; r < re; r++) {
+          sl = slot_in(r);
+          if (sl < (uint32_t)S_MAX) break;
+        }
+        return r;
+      };
+      // each range's header is loaded while the previous range is folded
+      uint32_t sl = 0;
+      uint32_t r = next_range(rb, sl);
+      RHdr hd_next;
+      if (r < re) hd_next = rhdr[(size_t)r * S_MAX + sl];
+      while (r < re) {
+        const RHdr hd = hd_next;
+        const size_t ib = ((size_t)r * S_MAX + sl) * D;
+        uint32_t sl2 = 0;
+        const uint32_t r2 = next_range(r + 1, sl2);
+        if (r2 < re) hd_next = rhdr[(size_t)r2 * S_MAX + sl2];
+        fold_one(hd, [&](uint32_t k) { return ru[ib + k]; }, [&](uint32_t k) { return ro[ib + k]; });
+        r = r2;
+        sl = sl2;
+      }
     }
     if (cs.flags & CS_OVERFLOW) atomicOr(tb.err, ERR_DEPTH);
     tb.cstate[g] = cs;
@@ -498,9 +570,13 @@ hipError_t launch_init_all(const InitSet &is, hipStream_t st) {
   hipLaunchKernelGGL(k_init_all, fill_grid(n), dim3(256), 0, st, is);
   return hipGetLastError();
 }
+// Allows the combine its dynamic LDS (set once, outside any stream capture).
+hipError_t prepare_combine_kernel() {
+  return hipFuncSetAttribute((const void *)k_combine, hipFuncAttributeMaxDynamicSharedMemorySize, CB_DYN);
+}
 hipError_t launch_combine(const uint32_t *spans, uint32_t n_spans, const RHdr *rhdr, const UItem *ru,
                           const OItem *ro, const uint32_t *rnslots, const Tables &tb, hipStream_t st) {
-  if (n_spans) hipLaunchKernelGGL(k_combine, dim3(n_spans), dim3(256), 0, st, spans, rhdr, ru, ro, rnslots, tb);
+  if (n_spans) hipLaunchKernelGGL(k_combine, dim3(n_spans), dim3(256), CB_DYN, st, spans, rhdr, ru, ro, rnslots, tb);
   return hipGetLastError();
 }
 hipError_t launch_final(const Tables &tb, uint32_t max_threads, hipStream_t st) {

@@ -188,6 +188,22 @@ def test_device_input_payload_mismatch():
         assert st["records"] == 4 and len(rows) == 2
 
 
+@pytest.mark.parametrize("n_rec,split", [(100_000, 1), (1_000_000, 1), (600_000, 3)])
+def test_many_threads_one_stream(n_rec, split):
+    """One stream of 64 threads at max_depth 16: the combine's carried stacks
+    (64 x 16 frames) do not fit its LDS, and at 1 M records neither do the
+    range summaries of the stream (31 ranges x 64 threads), so the fold runs
+    from global memory; at 100 k records the summaries are staged in LDS."""
+    say("case: one stream, 64 threads, %d records, %d chunks" % (n_rec, split))
+    cfg = synth.base_cfg(n_fns=48, max_depth=6)
+    st = synth.gen_stream(cfg, 2504, 0, 0, 0, 4242, 64, n_rec)
+    w = synth.Workload("many-threads", 1, 48, 0, 6, [st])
+    c = case_from_workload(w, max_depth=16, split=split, seed=5)
+    if split > 1:
+        c.flush_after = [0]
+    check(c)
+
+
 def test_read_into_reused_buffer():
     """read(out=...) fills a caller buffer in one call, and falls back when it is too small."""
     say("case: read into a reused buffer")

@@ -27,6 +27,10 @@
 //      once.  Children time reaches parents through one LDS atomic per call,
 //      then self time and the tally follow, and the calls still open at the
 //      window end become the carried stack.
+// In the default (pipelined) schedule half of the wavefronts build sorted
+// tiles (steps 1-4) into one half of the tile region while the other half
+// walk the previous tile (step 5); a thread's windows run across tile
+// boundaries.
 // An exit that closes a call opened before the range is written to the range
 // summary (U item) with the children time that call collected inside the
 // range; the calls still open at the range end are written as O items.  The

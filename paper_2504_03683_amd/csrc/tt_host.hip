@@ -768,7 +768,7 @@ hipError_t run_pipeline(thapi_tally *t, const Plan &pl, const Shape &sh, bool fi
   return hipSuccess;
 }
 
-// ---- autotune cache: one line per workload class, "key T E rpc"
+// ---- autotune cache: one line per workload class, "key T E rpc pipe"
 std::string tune_key(const thapi_tally *t, const std::vector<Chunk> &work) {
   uint64_t total = 0, nseg = 0;
   for (auto &c : work) { total += c.n_rec; nseg += c.n_rec ? 1 : 0; }

@@ -896,6 +896,22 @@ __device__ __forceinline__ void front_tile(RangeLds &L, const Tables &tb, const 
       if (act && !done) r_open |= 1u << r;
     }
     if (ballot(r_open != 0)) {
+    // the next bucket settles a tid whose first bucket was taken by another
+    // (in a stream with such a pair, nearly every wave holds records of the
+    // displaced thread, so this keeps those waves out of the probe loop)
+#pragma unroll
+    for (int r = 0; r < ROWS; r++) {
+      if (!(r_open & (1u << r))) continue;
+      const uint32_t t = r_tid[r];
+      const uint64_t e = L.tidmap[(hash32(t) + 1u) & (TIDMAP - 1)];
+      if ((e >> 63) && !((e >> 62) & 1u) && (uint32_t)e == t) {
+        const uint32_t sl = (uint32_t)(e >> 32) & 0xFFu;
+        r_slot[r] = sl < slot_cap(D) ? sl : EMPTY32;  // over the per-range limit: the flush fails
+        r_open &= ~(1u << r);
+      }
+    }
+    }
+    if (ballot(r_open != 0)) {
 #pragma unroll
     for (int r = 0; r < ROWS; r++) {
       if (!(r_open & (1u << r))) continue;

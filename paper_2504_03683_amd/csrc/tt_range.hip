@@ -136,6 +136,12 @@ size_t range_lds_bytes(uint32_t T, uint32_t E, uint32_t KL, uint32_t D, int fmt)
 }
 
 // ---------------------------------------------------------------- helpers
+// First bucket of a thread id in the range's tid map: multiplicative
+// (Fibonacci) hashing, the top bits of t * 2^32/phi; one multiply, and ids
+// that differ by a constant stride spread over the table.
+constexpr uint32_t TIDMAP_BITS = 8;
+static_assert(TIDMAP == 1 << TIDMAP_BITS, "tid map size");
+__device__ __forceinline__ uint32_t tid_bucket(uint32_t t) { return (t * 0x9E3779B1u) >> (32 - TIDMAP_BITS); }
 // Lanes of the wavefront for which p holds (p stays a lane mask; HIP's
 // __ballot takes an int and round-trips the predicate through a register).
 __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
@@ -888,7 +894,7 @@ __device__ __forceinline__ void front_tile(RangeLds &L, const Tables &tb, const 
 #pragma unroll
     for (int r = 0; r < ROWS; r++) {
       const uint32_t t = r_tid[r];
-      const uint64_t e = L.tidmap[hash32(t) & (TIDMAP - 1)];
+      const uint64_t e = L.tidmap[tid_bucket(t)];
       const bool done = (e >> 63) && !((e >> 62) & 1u) && (uint32_t)e == t;
       const uint32_t sl = (uint32_t)(e >> 32) & 0xFFu;
       const bool act = r_slot[r] != EMPTY32;
@@ -903,7 +909,7 @@ __device__ __forceinline__ void front_tile(RangeLds &L, const Tables &tb, const 
     for (int r = 0; r < ROWS; r++) {
       if (!(r_open & (1u << r))) continue;
       const uint32_t t = r_tid[r];
-      const uint64_t e = L.tidmap[(hash32(t) + 1u) & (TIDMAP - 1)];
+      const uint64_t e = L.tidmap[(tid_bucket(t) + 1u) & (TIDMAP - 1)];
       if ((e >> 63) && !((e >> 62) & 1u) && (uint32_t)e == t) {
         const uint32_t sl = (uint32_t)(e >> 32) & 0xFFu;
         r_slot[r] = sl < slot_cap(D) ? sl : EMPTY32;  // over the per-range limit: the flush fails
@@ -916,7 +922,7 @@ __device__ __forceinline__ void front_tile(RangeLds &L, const Tables &tb, const 
     for (int r = 0; r < ROWS; r++) {
       if (!(r_open & (1u << r))) continue;
       const uint32_t t = r_tid[r];
-      uint32_t h = hash32(t) & (TIDMAP - 1);
+      uint32_t h = tid_bucket(t);
       for (uint32_t probe = 0; probe < TIDMAP; probe++) {
         uint64_t e = L.tidmap[h];
         if (e == 0) {
@@ -996,7 +1002,7 @@ __device__ __forceinline__ void front_tile(RangeLds &L, const Tables &tb, const 
       for (int r = 0; r < ROWS; r++) {
         if (!(r_late & (1u << r))) continue;
         const uint32_t t = r_tid[r];
-        uint32_t h = hash32(t) & (TIDMAP - 1);
+        uint32_t h = tid_bucket(t);
         r_slot[r] = EMPTY32;
         for (uint32_t probe = 0; probe < TIDMAP; probe++) {
           const uint64_t e = L.tidmap[h];

@@ -47,6 +47,9 @@ hipError_t launch_sort_threads(const Tables &tb, const uint32_t *stream_rank, ui
                                uint64_t *keys2, uint32_t *vals2, uint32_t n, int rank_bits, hipStream_t st);
 hipError_t launch_group_bounds(const uint64_t *keys, uint32_t n, uint32_t *gbeg, uint32_t *gend, uint32_t n_ranks,
                                hipStream_t st);
+bool sort_small_fits(uint32_t n);
+hipError_t launch_sort_small(const Tables &tb, const uint32_t *stream_rank, uint64_t *keys, uint32_t *vals, uint32_t n,
+                             uint32_t *gbeg, uint32_t *gend, uint32_t n_ranks, hipStream_t st);
 struct RowCtx {
   int mode;
   uint32_t n_ids;
@@ -1150,9 +1153,13 @@ int thapi_tally_read(thapi_tally *t, uint32_t scope, uint32_t trace_id, thapi_ta
     const size_t part[4] = {4ull * srank.size(), 4ull * rank_key.size(), 4ull * tspan.size(), 4ull * rank_stream.size()};
     HIPCHK(stage_h2d(t, dst, src, part, 4));
   }
-  HIPCHK(launch_fill32(t->gbeg.as<uint32_t>(), std::max<uint32_t>(nrank, 1), 0, t->st));
-  HIPCHK(launch_fill32(t->gend.as<uint32_t>(), std::max<uint32_t>(nrank, 1), 0, t->st));
-  if (ng) {
+  if (sort_small_fits(ng)) {
+    // keys, sort and group bounds in one launch
+    HIPCHK(launch_sort_small(t->tb, t->stream_rank.as<uint32_t>(), t->keys.as<uint64_t>(), t->vals.as<uint32_t>(), ng,
+                             t->gbeg.as<uint32_t>(), t->gend.as<uint32_t>(), std::max<uint32_t>(nrank, 1), t->st));
+  } else {
+    HIPCHK(launch_fill32(t->gbeg.as<uint32_t>(), std::max<uint32_t>(nrank, 1), 0, t->st));
+    HIPCHK(launch_fill32(t->gend.as<uint32_t>(), std::max<uint32_t>(nrank, 1), 0, t->st));
     HIPCHK(launch_sort_threads(t->tb, t->stream_rank.as<uint32_t>(), t->keys.as<uint64_t>(), t->vals.as<uint32_t>(),
                                t->keys2.as<uint64_t>(), t->vals2.as<uint32_t>(), ng, rank_bits, t->st));
     HIPCHK(launch_group_bounds(t->keys.as<uint64_t>(), ng, t->gbeg.as<uint32_t>(), t->gend.as<uint32_t>(), nrank,

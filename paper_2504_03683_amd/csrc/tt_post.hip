@@ -393,6 +393,45 @@ __global__ __launch_bounds__(RS_WG) void k_radix_sort(uint64_t *keys, uint32_t *
   }
 }
 
+// Small thread sets (at most SORT_SMALL threads): the keys, a stable sort
+// and the group bounds in one workgroup.  Each lane ranks its key by counting
+// the keys that order before it, ties by position, over a copy in LDS (all
+// lanes read the same key at a time); gbeg/gend are cleared first.
+constexpr int SORT_SMALL = 256;
+__global__ __launch_bounds__(SORT_SMALL) void k_sort_small(Tables tb, const uint32_t *__restrict__ stream_rank,
+                                                           uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
+                                                           uint32_t n, uint32_t *__restrict__ gbeg,
+                                                           uint32_t *__restrict__ gend, uint32_t n_ranks) {
+  __shared__ uint64_t k_in[SORT_SMALL];
+  __shared__ uint64_t k_out[SORT_SMALL];
+  const uint32_t i = threadIdx.x;
+  uint64_t k = 0;
+  if (i < n) {
+    k = ((uint64_t)stream_rank[tb.th_stream[i]] << 32) | tb.th_tid[i];
+    k_in[i] = k;
+  }
+  for (uint32_t r = i; r < n_ranks; r += SORT_SMALL) { gbeg[r] = 0; gend[r] = 0; }
+  __syncthreads();
+  if (i < n) {
+    uint32_t rank = 0;
+    for (uint32_t j = 0; j < n; j++) {
+      const uint64_t kj = k_in[j];
+      rank += (kj < k || (kj == k && j < i)) ? 1u : 0u;
+    }
+    k_out[rank] = k;
+    keys[rank] = k;
+    vals[rank] = i;
+  }
+  __syncthreads();
+  if (i < n) {
+    const uint32_t sr = (uint32_t)(k_out[i] >> 32);
+    if (sr < n_ranks) {
+      if (i == 0 || (uint32_t)(k_out[i - 1] >> 32) != sr) gbeg[sr] = i;
+      if (i == n - 1 || (uint32_t)(k_out[i + 1] >> 32) != sr) gend[sr] = i + 1;
+    }
+  }
+}
+
 // Group bounds: for every canonical stream rank, the positions of its threads
 // in the sorted key array.
 __global__ void k_group_bounds(const uint64_t *__restrict__ keys, uint32_t n, uint32_t *__restrict__ gbeg,
@@ -600,6 +639,14 @@ hipError_t launch_sort_threads(const Tables &tb, const uint32_t *stream_rank, ui
   hipLaunchKernelGGL(k_thread_keys, dim3((n + 255) / 256), dim3(256), 0, st, tb, stream_rank, keys, vals, n);
   // tid: 32 bits; canonical stream rank (or the 0xFFFFFFFF filter mark): 32 bits
   hipLaunchKernelGGL(k_radix_sort, dim3(1), dim3(RS_WG), 0, st, keys, vals, keys2, vals2, n, 0, 32 + rank_bits);
+  return hipGetLastError();
+}
+bool sort_small_fits(uint32_t n) { return n <= (uint32_t)SORT_SMALL; }
+hipError_t launch_sort_small(const Tables &tb, const uint32_t *stream_rank, uint64_t *keys, uint32_t *vals, uint32_t n,
+                             uint32_t *gbeg, uint32_t *gend, uint32_t n_ranks, hipStream_t st) {
+  if (n > (uint32_t)SORT_SMALL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_sort_small, dim3(1), dim3(SORT_SMALL), 0, st, tb, stream_rank, keys, vals, n, gbeg, gend,
+                     n_ranks);
   return hipGetLastError();
 }
 hipError_t launch_group_bounds(const uint64_t *keys, uint32_t n, uint32_t *gbeg, uint32_t *gend, uint32_t n_ranks,

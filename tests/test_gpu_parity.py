@@ -204,6 +204,48 @@ def test_many_threads_one_stream(n_rec, split):
     check(c)
 
 
+@pytest.mark.parametrize("extra", [0, 1])
+def test_readout_sort_boundary(extra):
+    """256 threads (the readout sorts them in one workgroup) and 257 (the
+    radix-sort path), in four traces of one and two processes."""
+    say("case: readout of %d threads" % (256 + extra))
+    cfg = synth.base_cfg(n_fns=24, max_depth=5)
+    sts = [synth.gen_stream(cfg, 31, i, i // 2, 0, 3000 + 17 * i, 64, 20_000) for i in range(4)]
+    if extra:
+        sts.append(synth.gen_stream(cfg, 31, 9, 1, 0, 2999, 1, 3_000))
+    w = synth.Workload("readout-boundary", 1, 24, 0, 5, sts)
+    check(case_from_workload(w, split=2, seed=6), max_threads=1024)
+
+
+def test_tid_bucket_collisions():
+    """Thread ids chosen to share first buckets of the range kernel's tid map
+    (multiplicative hashing into 256 buckets): three ids on one bucket and two
+    on the bucket after it, and two on the last bucket with one more on bucket
+    0 (the displaced id wraps around), so lookups go through the next-bucket
+    check and the probe loop, in the order each range meets the threads."""
+    say("case: tid map bucket collisions")
+
+    def bucket(t):
+        return ((t * 0x9E3779B1) & 0xFFFFFFFF) >> 24
+
+    by = {}
+    for t in range(1, 100_000):
+        by.setdefault(bucket(t), []).append(t)
+    tids = np.array(by[17][:3] + by[18][:2] + by[255][:2] + by[0][:1], dtype=np.uint32)
+    cfg = synth.base_cfg(n_fns=48, max_depth=6)
+    st = synth.gen_stream(cfg, 77, 0, 0, 0, 5151, 8, 300_000)
+    r = st.records.reshape(-1, 24)
+    api = r[:, 14] < 2
+    old = r[api, 8:12].copy().view("<u4").ravel()
+    src = np.array(st.tid_of_thread, dtype=np.uint32)
+    order = np.argsort(src)
+    k = np.searchsorted(src[order], old)
+    assert np.array_equal(src[order][k], old)
+    r[api, 8:12] = tids[order][k].astype("<u4").view(np.uint8).reshape(-1, 4)
+    w = synth.Workload("tid-collisions", 1, 48, 0, 6, [st])
+    check(case_from_workload(w, max_depth=8, split=2, seed=3))
+
+
 def test_read_into_reused_buffer():
     """read(out=...) fills a caller buffer in one call, and falls back when it is too small."""
     say("case: read into a reused buffer")

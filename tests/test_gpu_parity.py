@@ -266,6 +266,40 @@ def test_read_into_reused_buffer():
             assert np.array_equal(got2, ref)
 
 
+def test_read_statistics_after_changes():
+    """Reads right after a flush, a second read, a read while a new stream's
+    chunk is queued, after the final flush and after a reset: each agrees
+    with a handle that did only the same flushes."""
+    say("case: read statistics after changes")
+    from paper_2504_03683_amd import tally as T
+    w = synth.config(0, scale=0.05)
+    s0 = w.streams[0]
+    other = synth.gen_stream(synth.base_cfg(n_fns=w.n_fns, max_depth=4), 9, 1, 0, 0, 1500, 3, 20_000)
+    kw = dict(max_depth=16, max_threads=256, max_streams=8)
+    with T.Tally(T.FMT_FIXED24, w.n_fns, 0, **kw) as t, T.Tally(T.FMT_FIXED24, w.n_fns, 0, **kw) as ref:
+        t.submit(s0.key, s0.records)
+        t.flush()
+        ref.submit(s0.key, s0.records)
+        ref.flush()
+        want = ref.read()
+        for got in (t.read(), t.read()):
+            assert np.array_equal(got[0], want[0]) and got[1] == want[1]
+        t.submit(other.key, other.records)   # queued, not flushed
+        got = t.read()
+        assert np.array_equal(got[0], want[0])
+        assert {k: v for k, v in got[1].items() if k != "dropped_records"} == \
+            {k: v for k, v in want[1].items() if k != "dropped_records"}
+        t.flush(final=True)
+        ref.submit(other.key, other.records)
+        ref.flush(final=True)
+        want = ref.read()
+        got = t.read()
+        assert np.array_equal(got[0], want[0]) and got[1] == want[1]
+        t.reset()
+        rows, st = t.read()
+        assert len(rows) == 0 and st["records"] == 0 and st["distinct_threads"] == 0
+
+
 def test_reset_and_repeat_determinism():
     say("case: reset and repeat")
     from paper_2504_03683_amd import tally as T

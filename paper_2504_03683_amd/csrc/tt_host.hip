@@ -83,6 +83,11 @@ struct DevBuf {
   void release() { if (p) hipFree(p); p = nullptr; cap = 0; }
   template <class T> T *as() const { return (T *)p; }
 };
+// An array inside a packed DevBuf (set by each upload).
+struct DevView {
+  void *p = nullptr;
+  template <class T> T *as() const { return (T *)p; }
+};
 
 struct Chunk {
   uint32_t stream;
@@ -131,8 +136,12 @@ struct thapi_tally {
        *d_err = nullptr, *d_hs = nullptr;
   Shape shape{};
 
-  DevBuf segs, ranges, order, qhead, rhdr, ru, ro, rnslots, spans, paylen, segfirst;
-  DevBuf keys, vals, keys2, vals2, gbeg, gend, cnt, off, rank_stream, rank_key, trace_span, stream_rank, rows, tstats;
+  DevBuf rhdr, ru, ro, rnslots, paylen;
+  DevBuf plan_pack;                                   // the work list, uploaded in one copy
+  DevView segs, ranges, order, qhead, segfirst, spans;
+  DevBuf keys, vals, keys2, vals2, gbeg, gend, cnt, off, rows, tstats;
+  DevBuf read_pack;                                   // the readout's host tables, uploaded in one copy
+  DevView rank_key, trace_span, stream_rank, rstream;
   void *h_pinned = nullptr;  // small pinned staging for results of device->host copies
   size_t h_pinned_cap = 0;
   void *h_plan = nullptr;    // pinned staging of the work list (asynchronous uploads)
@@ -170,7 +179,6 @@ struct thapi_tally {
   uint32_t rc_scope = 0, rc_trace = 0;
   std::vector<thapi_tally_row> rc_rows;
   thapi_tally_stats rc_stats{};
-  DevBuf rstream;
 };
 
 namespace {
@@ -205,9 +213,8 @@ void free_all(thapi_tally *t) {
   void *ps[] = {t->d_gkeys, t->d_gvals, t->d_ngs, t->d_ths, t->d_tht, t->d_tally, t->d_ktally,
                 t->d_cstate, t->d_cstack, t->d_sstats, t->d_err, t->d_hs};
   for (void *p : ps) if (p) hipFree(p);
-  DevBuf *bs[] = {&t->rstream, &t->segs, &t->ranges, &t->order, &t->qhead, &t->rhdr, &t->ru, &t->ro, &t->rnslots, &t->spans, &t->paylen, &t->segfirst,
-                  &t->keys, &t->vals, &t->keys2, &t->vals2, &t->gbeg, &t->gend, &t->cnt, &t->off,
-                  &t->rank_stream, &t->rank_key, &t->trace_span, &t->stream_rank, &t->rows, &t->tstats};
+  DevBuf *bs[] = {&t->plan_pack, &t->rhdr, &t->ru, &t->ro, &t->rnslots, &t->paylen, &t->keys, &t->vals, &t->keys2,
+                  &t->vals2, &t->gbeg, &t->gend, &t->cnt, &t->off, &t->read_pack, &t->rows, &t->tstats};
   for (DevBuf *b : bs) b->release();
   for (auto &c : t->queue) if (c.owned) hipFree(c.owned);
   t->queue.clear();
@@ -645,13 +652,18 @@ void plan_work(const thapi_tally *t, const std::vector<Chunk> &work, const Shape
                    [&](uint32_t a, uint32_t b) { return pl.ranges[a].n > pl.ranges[b].n; });
 }
 
-// Host -> device copies of n host arrays through the pinned staging buffer,
-// so that they are asynchronous.  The staging is reused by the next call only,
-// which comes after the work that these copies feed has completed (flushes
-// and reads each end with a synchronisation).
-hipError_t stage_h2d(thapi_tally *t, void *const *dst, const void *const *src, const size_t *bytes, int n) {
-  size_t tot = 0;
-  for (int i = 0; i < n; i++) tot += (bytes[i] + 255) & ~(size_t)255;
+// Host -> device upload of n host arrays in one asynchronous copy: they are
+// packed at 256-byte aligned offsets (at least 256 bytes each) in the pinned
+// staging buffer and land at the same offsets of `pack`; views[i] receives
+// the device address of array i.  The staging is reused by the next call
+// only, which comes after the work that the copy feeds has completed
+// (flushes and reads each end with a synchronisation).
+hipError_t stage_h2d(thapi_tally *t, DevBuf &pack, DevView *const *views, const void *const *src,
+                     const size_t *bytes, int n) {
+  size_t tot = 0, used = 0;
+  for (int i = 0; i < n; i++) tot += std::max<size_t>((bytes[i] + 255) & ~(size_t)255, 256);
+  hipError_t e = pack.ensure(tot);
+  if (e != hipSuccess) return e;
   if (tot > t->h_plan_cap) {
     if (t->h_plan) hipHostFree(t->h_plan);
     t->h_plan = nullptr;
@@ -661,16 +673,16 @@ hipError_t stage_h2d(thapi_tally *t, void *const *dst, const void *const *src, c
     if (e != hipSuccess) return e;
     t->h_plan_cap = want;
   }
-  uint8_t *hp = (uint8_t *)t->h_plan;
+  size_t o = 0;
   for (int i = 0; i < n; i++) {
     if (bytes[i]) {
-      memcpy(hp, src[i], bytes[i]);
-      hipError_t e = hipMemcpyAsync(dst[i], hp, bytes[i], hipMemcpyHostToDevice, t->st);
-      if (e != hipSuccess) return e;
+      memcpy((uint8_t *)t->h_plan + o, src[i], bytes[i]);
+      used = o + bytes[i];
     }
-    hp += (bytes[i] + 255) & ~(size_t)255;
+    views[i]->p = (uint8_t *)pack.p + o;
+    o += std::max<size_t>((bytes[i] + 255) & ~(size_t)255, 256);
   }
-  return hipSuccess;
+  return used ? hipMemcpyAsync(pack.p, t->h_plan, used, hipMemcpyHostToDevice, t->st) : hipSuccess;
 }
 
 hipError_t upload_plan(thapi_tally *t, const Plan &pl) {
@@ -678,21 +690,17 @@ hipError_t upload_plan(thapi_tally *t, const Plan &pl) {
   const uint32_t D = t->cfg.max_depth;
   hipError_t e;
 #define UPCHK(x) do { if ((e = (x)) != hipSuccess) return e; } while (0)
-  UPCHK(t->segs.ensure(sizeof(Seg) * nS));
-  UPCHK(t->ranges.ensure(sizeof(Range) * nR));
-  UPCHK(t->order.ensure(4ull * nR));
-  UPCHK(t->qhead.ensure(256));
-  UPCHK(t->segfirst.ensure(4ull * (nS + 1)));
-  UPCHK(t->spans.ensure(4ull * pl.spans.size()));
   UPCHK(t->rhdr.ensure(sizeof(RHdr) * (size_t)nR * S_MAX));
   UPCHK(t->ru.ensure(sizeof(UItem) * (size_t)nR * S_MAX * D));
   UPCHK(t->ro.ensure(sizeof(OItem) * (size_t)nR * S_MAX * D));
   UPCHK(t->rnslots.ensure(4ull * nR));
   UPCHK(t->paylen.ensure(8ull * nR));
-  const size_t part[5] = {sizeof(Seg) * nS, sizeof(Range) * nR, 4ull * nR, 4ull * (nS + 1), 4ull * pl.spans.size()};
-  const void *src[5] = {pl.segs.data(), pl.ranges.data(), pl.order.data(), pl.segfirst.data(), pl.spans.data()};
-  void *dst[5] = {t->segs.p, t->ranges.p, t->order.p, t->segfirst.p, t->spans.p};
-  UPCHK(stage_h2d(t, dst, src, part, 5));
+  // the work queue's head (zero) travels with the work list
+  static const uint32_t zero = 0;
+  const size_t part[6] = {sizeof(Seg) * nS, sizeof(Range) * nR, 4ull * nR, 4ull * (nS + 1), 4ull * pl.spans.size(), 4};
+  const void *src[6] = {pl.segs.data(), pl.ranges.data(), pl.order.data(), pl.segfirst.data(), pl.spans.data(), &zero};
+  DevView *dst[6] = {&t->segs, &t->ranges, &t->order, &t->segfirst, &t->spans, &t->qhead};
+  UPCHK(stage_h2d(t, t->plan_pack, dst, src, part, 6));
 #undef UPCHK
   return hipSuccess;
 }
@@ -714,7 +722,6 @@ hipError_t launch_pipeline(thapi_tally *t, const Plan &pl, const Shape &sh, bool
                           t->paylen.as<uint64_t>(), t->tb.err, t->st));
       TE(TM_PREPASS);
     }
-    LPCHK(launch_fill32(t->qhead.as<uint32_t>(), 1, 0, t->st));
     TB(TM_RANGE);
     LPCHK(launch_range((int)t->cfg.format, sh.T, t->segs.as<Seg>(), t->ranges.as<Range>(), t->order.as<uint32_t>(),
                        nR, t->qhead.as<uint32_t>(), (uint32_t)t->n_cu, t->tb, sh, t->rhdr.as<RHdr>(),
@@ -1130,9 +1137,6 @@ int thapi_tally_read(thapi_tally *t, uint32_t scope, uint32_t trace_id, thapi_ta
   for (uint32_t i : sel) nsel_threads += (uint32_t)ts3[3 * i];
   int rank_bits = 1;
   while ((1u << rank_bits) <= nrank + 1 && rank_bits < 32) rank_bits++;
-  HIPCHK(t->stream_rank.ensure(4ull * srank.size()));
-  HIPCHK(t->rank_key.ensure(4ull * rank_key.size()));
-  HIPCHK(t->trace_span.ensure(4ull * std::max<size_t>(tspan.size(), 2)));
   HIPCHK(t->keys.ensure(8ull * std::max<uint32_t>(ng, 1)));
   HIPCHK(t->vals.ensure(4ull * std::max<uint32_t>(ng, 1)));
   HIPCHK(t->keys2.ensure(8ull * std::max<uint32_t>(ng, 1)));
@@ -1144,14 +1148,13 @@ int thapi_tally_read(thapi_tally *t, uint32_t scope, uint32_t trace_id, thapi_ta
   HIPCHK(t->off.ensure(8ull * (maxg + 1)));
   std::vector<uint32_t> rank_stream(std::max<uint32_t>(nrank, 1), 0);
   for (uint32_t r = 0; r < nrank; r++) rank_stream[r] = sel[r];
-  HIPCHK(t->rstream.ensure(4ull * rank_stream.size()));
   {
     // host tables of the readout, staged in pinned memory (the work-list
     // staging is free between flushes)
     const void *src[4] = {srank.data(), rank_key.data(), tspan.data(), rank_stream.data()};
-    void *dst[4] = {t->stream_rank.p, t->rank_key.p, t->trace_span.p, t->rstream.p};
+    DevView *dst[4] = {&t->stream_rank, &t->rank_key, &t->trace_span, &t->rstream};
     const size_t part[4] = {4ull * srank.size(), 4ull * rank_key.size(), 4ull * tspan.size(), 4ull * rank_stream.size()};
-    HIPCHK(stage_h2d(t, dst, src, part, 4));
+    HIPCHK(stage_h2d(t, t->read_pack, dst, src, part, 4));
   }
   if (sort_small_fits(ng)) {
     // keys, sort and group bounds in one launch

@@ -42,7 +42,8 @@ hipError_t launch_init_all(const InitSet &is, hipStream_t st);
 hipError_t launch_combine(const uint32_t *spans, uint32_t n_spans, const RHdr *rhdr, const UItem *ru,
                           const OItem *ro, const uint32_t *rnslots, const Tables &tb, hipStream_t st);
 hipError_t launch_final(const Tables &tb, uint32_t max_threads, hipStream_t st);
-hipError_t launch_thread_stats(const Tables &tb, uint32_t max_threads, unsigned long long *out, hipStream_t st);
+hipError_t launch_thread_stats(const Tables &tb, uint32_t max_threads, unsigned long long *out, uint32_t ns,
+                               uint32_t ns1, hipStream_t st);
 hipError_t launch_sort_threads(const Tables &tb, const uint32_t *stream_rank, uint64_t *keys, uint32_t *vals,
                                uint64_t *keys2, uint32_t *vals2, uint32_t n, int rank_bits, hipStream_t st);
 hipError_t launch_group_bounds(const uint64_t *keys, uint32_t n, uint32_t *gbeg, uint32_t *gend, uint32_t n_ranks,
@@ -1094,20 +1095,20 @@ int thapi_tally_read(thapi_tally *t, uint32_t scope, uint32_t trace_id, thapi_ta
   }
   const uint32_t ntrace = (uint32_t)(tspan.size() / 2);
   HIPCHK(timed_begin(t, TM_READOUT));
-  // thread count, per-stream thread statistics and counters in one round
-  // trip, through pinned memory
+  // thread count, per-stream thread statistics and counters gathered in one
+  // device buffer, then one round trip through pinned memory
   const size_t ns1 = std::max<uint32_t>(nstreams, 1);
-  HIPCHK(ensure_pinned(t, 64 + 24 * ns1 + 8 * ns1 * ST_N));
-  uint32_t *hng = (uint32_t *)t->h_pinned;
+  const size_t sbytes = 64 + 24 * ns1 + 8 * ns1 * ST_N;
+  HIPCHK(ensure_pinned(t, sbytes));
+  const uint32_t *hng = (const uint32_t *)t->h_pinned;   // low word of a u64
   const uint64_t *ts3 = (const uint64_t *)((uint8_t *)t->h_pinned + 64);
   const uint64_t *sst = ts3 + 3 * ns1;
-  HIPCHK(t->tstats.ensure(24ull * ns1));
-  HIPCHK(launch_fill64(t->tstats.as<uint64_t>(), 3ull * ns1, 0, t->st));
-  HIPCHK(launch_thread_stats(t->tb, t->cfg.max_threads, t->tstats.as<unsigned long long>(), t->st));
-  HIPCHK(hipMemcpyAsync(hng, t->tb.n_gslots, 4, hipMemcpyDeviceToHost, t->st));
-  HIPCHK(hipMemcpyAsync((void *)ts3, t->tstats.p, 24ull * ns1, hipMemcpyDeviceToHost, t->st));
-  if (nstreams)
-    HIPCHK(hipMemcpyAsync((void *)sst, t->tb.sstats, 8ull * nstreams * ST_N, hipMemcpyDeviceToHost, t->st));
+  HIPCHK(t->tstats.ensure(sbytes));
+  HIPCHK(launch_fill64(t->tstats.as<uint64_t>() + 8, 3ull * ns1, 0, t->st));
+  HIPCHK(launch_thread_stats(t->tb, t->cfg.max_threads, t->tstats.as<unsigned long long>(), nstreams, (uint32_t)ns1,
+                             t->st));
+  HIPCHK(hipMemcpyAsync(t->h_pinned, t->tstats.p, 64 + 24 * ns1 + 8ull * nstreams * ST_N, hipMemcpyDeviceToHost,
+                        t->st));
   HIPCHK(hipStreamSynchronize(t->st));
   const uint32_t ng = std::min<uint32_t>(*hng, t->cfg.max_threads);
   thapi_tally_stats stats_all{};

@@ -308,15 +308,22 @@ __global__ void k_final(Tables tb) {
   }
 }
 
-// Per-stream thread statistics: threads, open calls, overflowed threads.
-__global__ void k_thread_stats(Tables tb, unsigned long long *__restrict__ out /* [stream][3] */) {
+// The readout's statistics in one buffer, for one copy to the host:
+// out[0] the thread count; from out[8], per stream, threads, open calls and
+// overflowed threads (3 x u64, zero on entry); from out[8 + 3 * ns1] the
+// per-stream counters of the ns streams (ST_N x u64 each).
+__global__ void k_thread_stats(Tables tb, unsigned long long *__restrict__ out, uint32_t ns, uint32_t ns1) {
   const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (blockIdx.x == 0) {
+    if (threadIdx.x == 0) out[0] = *tb.n_gslots;
+    for (uint32_t i = threadIdx.x; i < ns * ST_N; i += blockDim.x) out[8 + 3 * (size_t)ns1 + i] = tb.sstats[i];
+  }
   if (g >= *tb.n_gslots || g >= tb.max_threads) return;
-  const uint32_t s = tb.th_stream[g];
-  atomicAdd(&out[3 * s + 0], 1ull);
+  unsigned long long *ts = out + 8 + 3 * (size_t)tb.th_stream[g];
+  atomicAdd(&ts[0], 1ull);
   const CState cs = tb.cstate[g];
-  if (cs.h) atomicAdd(&out[3 * s + 1], (unsigned long long)cs.h);
-  if (cs.flags & CS_OVERFLOW) atomicAdd(&out[3 * s + 2], 1ull);
+  if (cs.h) atomicAdd(&ts[1], (unsigned long long)cs.h);
+  if (cs.flags & CS_OVERFLOW) atomicAdd(&ts[2], 1ull);
 }
 
 // --------------------------------------------------------------- readout
@@ -629,8 +636,9 @@ hipError_t launch_final(const Tables &tb, uint32_t max_threads, hipStream_t st) 
   hipLaunchKernelGGL(k_final, dim3((max_threads + 255) / 256), dim3(256), 0, st, tb);
   return hipGetLastError();
 }
-hipError_t launch_thread_stats(const Tables &tb, uint32_t max_threads, unsigned long long *out, hipStream_t st) {
-  hipLaunchKernelGGL(k_thread_stats, dim3((max_threads + 255) / 256), dim3(256), 0, st, tb, out);
+hipError_t launch_thread_stats(const Tables &tb, uint32_t max_threads, unsigned long long *out, uint32_t ns,
+                               uint32_t ns1, hipStream_t st) {
+  hipLaunchKernelGGL(k_thread_stats, dim3((max_threads + 255) / 256), dim3(256), 0, st, tb, out, ns, ns1);
   return hipGetLastError();
 }
 hipError_t launch_sort_threads(const Tables &tb, const uint32_t *stream_rank, uint64_t *keys, uint32_t *vals,

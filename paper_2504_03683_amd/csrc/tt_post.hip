@@ -184,10 +184,10 @@ __global__ __launch_bounds__(256) void k_combine(const uint32_t *__restrict__ sp
         if ((hd.flags & RF_OVERFLOW) || hd.H > (int32_t)D || ds + hd.M > (int32_t)D) cs.flags |= CS_OVERFLOW;
         for (uint32_t k0 = 0; k0 < hd.nu_listed; k0 += 4) {
           UItem uu[4];
-  #pragma unroll
+#pragma unroll
           for (int j = 0; j < 4; j++)
             if (k0 + j < hd.nu_listed) uu[j] = uat(k0 + j);
-  #pragma unroll
+#pragma unroll
           for (int j = 0; j < 4; j++) {
             if (k0 + j >= hd.nu_listed) break;
             const UItem &u = uu[j];
@@ -212,10 +212,10 @@ __global__ __launch_bounds__(256) void k_combine(const uint32_t *__restrict__ sp
         const uint32_t no = hd.n_o < D ? hd.n_o : D;
         for (uint32_t k0 = 0; k0 < no; k0 += 4) {
           OItem oo[4];
-  #pragma unroll
+#pragma unroll
           for (int j = 0; j < 4; j++)
             if (k0 + j < no) oo[j] = oat(k0 + j);
-  #pragma unroll
+#pragma unroll
           for (int j = 0; j < 4; j++) {
             if (k0 + j >= no) break;
             if (cs.h < D) {

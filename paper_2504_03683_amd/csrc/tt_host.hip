@@ -606,9 +606,9 @@ void plan_work(const thapi_tally *t, const std::vector<Chunk> &work, const Shape
   // sqrt(N / RANGE_FOLD) ranges: the count that balances the range kernel's
   // time (N / R records per workgroup) against the fold's (R summaries), with
   // RANGE_FOLD the records a workgroup tallies in the time one summary takes
-  // to fold (measured: about 4.7 ns per record; 3-6 us per summary, more for
-  // more threads per stream).
-  constexpr double RANGE_FOLD = 1000.0;
+  // to fold (measured: about 4.4 ns per record; about 1.1 us per summary
+  // with the U items folded in parallel).
+  constexpr double RANGE_FOLD = 250.0;
   uint64_t n_seg = 0;
   std::map<uint32_t, uint64_t> per_stream;
   for (auto &c : work) {

@@ -193,7 +193,10 @@ int hip_fail(thapi_tally *t, hipError_t e) {
 
 uint32_t record_size(const thapi_tally *t) { return t->cfg.format == THAPI_FMT_VAR16 ? 16u : 24u; }
 
-hipError_t init_tables(thapi_tally *t) {
+// Resets every table in one launch on the handle's stream; `wait` also
+// waits for it (a reset does not: whatever follows on the stream is ordered
+// after it).
+hipError_t init_tables(thapi_tally *t, bool wait = true) {
   const thapi_tally_config &c = t->cfg;
   hipError_t e;
   // every table in one launch
@@ -207,7 +210,7 @@ hipError_t init_tables(thapi_tally *t) {
   is.cstate = (uint32_t *)t->d_cstate; is.n_cstate = (size_t)c.max_threads * sizeof(CState) / 4;
   is.sstats = (uint64_t *)t->d_sstats; is.n_sstats = (size_t)c.max_streams * ST_N;
   if ((e = launch_init_all(is, t->st)) != hipSuccess) return e;
-  return hipStreamSynchronize(t->st);
+  return wait ? hipStreamSynchronize(t->st) : hipSuccess;
 }
 
 void free_all(thapi_tally *t) {
@@ -1225,7 +1228,7 @@ int thapi_tally_reset(thapi_tally *t) {
   }
   if (hipSetDevice(t->dev) != hipSuccess) return THAPI_E_DEVICE;
   t->gen++;
-  if (init_tables(t) != hipSuccess) return hip_fail(t, hipErrorUnknown);
+  if (init_tables(t, false) != hipSuccess) return hip_fail(t, hipErrorUnknown);
   std::lock_guard<std::mutex> g(t->mu);
   t->stream_idx.clear();
   t->stream_keys.clear();

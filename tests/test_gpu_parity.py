@@ -204,6 +204,37 @@ def test_many_threads_one_stream(n_rec, split):
     check(c)
 
 
+@pytest.mark.parametrize("flush_between", [False, True])
+def test_combine_long_unwind(flush_between):
+    """One chunk opens 13 nested calls on each of two threads (a closed child
+    at every level); the next closes them all and one more: more U items in
+    one range summary than a fold group takes at a time, with a mismatched
+    fn, an exit earlier than its entry, children closed between the exits,
+    and a final orphan exit.  Both chunks in one flush, or a flush between."""
+    say("case: long unwind across chunks (flush between: %s)" % flush_between)
+    ev1, ev2 = [], []
+    ts = T0
+    for d in range(13):
+        for th in (5, 9):
+            ev1.append((ts, th, d, ENTRY)); ts += 10
+            ev1.append((ts, th, 20 + d % 3, ENTRY)); ts += 3
+            ev1.append((ts, th, 20 + d % 3, EXIT)); ts += 2
+    for d in reversed(range(13)):
+        for th in (5, 9):
+            fn = 7 if (d == 6 and th == 5) else d
+            ev2.append((T0 + 1 if (d == 3 and th == 9) else ts, th, fn, EXIT)); ts += 7
+            if d % 2 == 0 and d > 0:
+                ev2.append((ts, th, 30, ENTRY)); ts += 4
+                ev2.append((ts, th, 30, EXIT)); ts += 1
+    ev2.append((ts, 5, 0, EXIT))
+    c = Case(1, 32, 0, [((0, 0, 1000), fixed24(ev1), None), ((0, 0, 1000), fixed24(ev2), None)])
+    if flush_between:
+        c.flush_after = [0]
+    g, o = check(c)
+    st = o["stats"]
+    assert st["orphan_exits"] >= 1 and st["fn_mismatch"] >= 1 and st["neg_duration"] >= 1
+
+
 @pytest.mark.parametrize("extra", [0, 1])
 def test_readout_sort_boundary(extra):
     """256 threads (the readout sorts them in one workgroup) and 257 (the

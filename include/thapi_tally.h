@@ -188,7 +188,9 @@ int thapi_tally_read(thapi_tally *t, uint32_t scope, uint32_t trace_id,
                      thapi_tally_stats *stats);
 
 /* Forgets every tally, stack, stream and counter (device memory is kept) so
- * the handle can start a new trace set.  Not valid while submits are queued. */
+ * the handle can start a new trace set.  Not valid while submits are queued.
+ * The device tables are cleared by work enqueued on the handle's stream,
+ * which later flushes and reads follow; the call does not wait for it. */
 int thapi_tally_reset(thapi_tally *t);
 
 /* Batched form: times the pipeline on the chunks queued right now under each

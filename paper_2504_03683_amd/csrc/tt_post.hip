@@ -17,7 +17,8 @@ __device__ inline void gmax64(uint64_t *p, uint64_t v) {
 
 // ---------------------------------------------------------------- combine
 // One workgroup per stream that had ranges in this flush.  Each distinct
-// thread of the stream is owned by one lane, which folds the thread's range
+// thread of the stream is owned by one lane (a group of 8 lanes when the
+// span's summaries and the stacks fit in LDS), which folds the thread's range
 // summaries in range order onto the thread's carried stack: every U item pops
 // the call it closes (orphan exit when the stack is empty), checks fn and
 // time order, tallies inclusive and self time and credits the parent; the

@@ -95,8 +95,9 @@ def main():
                          "counters (FETCH_SIZE / WRITE_SIZE) can be scaled to bytes")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the tally shards by stream; see DESIGN.md for how it would scale)", file=sys.stderr)
+        print("bench.py measures one GPU only: there is no multi-GPU path here "
+              "(the tally would shard by stream, with one reduction of the tables at the end)",
+              file=sys.stderr)
         sys.exit(2)
 
     if args.copy_calibration:

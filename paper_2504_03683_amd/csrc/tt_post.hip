@@ -165,7 +165,7 @@ __global__ __launch_bounds__(256) void k_combine(const uint32_t *__restrict__ sp
     }
   }
   uint32_t c_tsreg = 0, c_orphan = 0, c_mis = 0, c_neg = 0, c_under = 0;
-  if (staged && lds_stack) {
+  if (lds_stack && use_map) {
     // A group of CG lanes per listed thread takes a range summary's U items
     // CG at a time.  U item k pops the frame k below the top the range found
     // (k at or above that height: an orphan exit), so the items are
@@ -173,78 +173,99 @@ __global__ __launch_bounds__(256) void k_combine(const uint32_t *__restrict__ sp
     // frame it pops: that item's inclusive time when it was tallied (a
     // shuffle within the group).  Then one lane credits the new top (the
     // last item's time and the floor) and the group pushes the O items.
+    // hdr_of / u_of / o_of read the summaries from LDS when the span is
+    // staged, else from global memory (one instantiation each).
     constexpr uint32_t CG = 8;
     const uint32_t j = (uint32_t)tid % CG;
-    for (uint32_t i = (uint32_t)tid / CG; i < n; i += 256 / CG) {
-      const uint32_t g = list[i];
-      CState cs = tb.cstate[g];
-      Frame *stk = lstk + (size_t)i * D;
-      for (uint32_t r = rb; r < re; r++) {
-        const uint32_t x = (r - rb) * n + i;
-        if (smap[x] == 0xFF) continue;
-        const RHdr hd = hdrL[x];
-        const UItem *lu = (const UItem *)(itL + (size_t)offL[x] * 32);
-        const OItem *lo = (const OItem *)(lu + hd.nu_listed);
-        if (hd.flags & RF_HAS_TS) {
-          if ((cs.flags & CS_HAS_TS) && hd.first_ts < cs.last_ts && j == 0) c_tsreg++;
-          cs.last_ts = hd.last_ts;
-          cs.flags |= CS_HAS_TS;
-        }
-        const int32_t ds = (int32_t)cs.h;
-        if ((hd.flags & RF_OVERFLOW) || hd.H > (int32_t)D || ds + hd.M > (int32_t)D) cs.flags |= CS_OVERFLOW;
-        const uint32_t h0 = cs.h, nu = hd.nu_listed;
-        uint64_t carry = 0;      // the previous chunk's last item: its time when tallied
-        uint64_t last = 0;       // the range's last U item: its time when tallied
-        for (uint32_t k0 = 0; k0 < nu; k0 += CG) {
-          const uint32_t k = k0 + j;
-          bool ok = false;
-          uint64_t incl = 0, uchild = 0, echild = 0, bytes = 0;
-          uint32_t fn = 0;
-          if (k < nu) {
-            if (k >= h0) {
-              c_orphan++;
-            } else {
-              const UItem u = lu[k];
-              const Frame e = stk[h0 - 1 - k];
-              if (e.fn != u.fn || u.fn >= tb.n_fns) c_mis++;
-              else if (u.ts < e.ts) c_neg++;
-              else { ok = true; incl = u.ts - e.ts; uchild = u.child; echild = e.child; bytes = e.bytes; fn = u.fn; }
+    auto grouped = [&](auto &&hdr_of, auto &&u_of, auto &&o_of) {
+      for (uint32_t i = (uint32_t)tid / CG; i < n; i += 256 / CG) {
+        const uint32_t g = list[i];
+        CState cs = tb.cstate[g];
+        Frame *stk = lstk + (size_t)i * D;
+        for (uint32_t r = rb; r < re; r++) {
+          const uint32_t x = (r - rb) * n + i;
+          const uint32_t sl = smap[x];
+          if (sl == 0xFF) continue;
+          const RHdr hd = hdr_of(r, x, sl);
+          if (hd.flags & RF_HAS_TS) {
+            if ((cs.flags & CS_HAS_TS) && hd.first_ts < cs.last_ts && j == 0) c_tsreg++;
+            cs.last_ts = hd.last_ts;
+            cs.flags |= CS_HAS_TS;
+          }
+          const int32_t ds = (int32_t)cs.h;
+          if ((hd.flags & RF_OVERFLOW) || hd.H > (int32_t)D || ds + hd.M > (int32_t)D) cs.flags |= CS_OVERFLOW;
+          const uint32_t h0 = cs.h, nu = hd.nu_listed;
+          uint64_t carry = 0;      // the previous chunk's last item: its time when tallied
+          uint64_t last = 0;       // the range's last U item: its time when tallied
+          for (uint32_t k0 = 0; k0 < nu; k0 += CG) {
+            const uint32_t k = k0 + j;
+            bool ok = false;
+            uint64_t incl = 0, uchild = 0, echild = 0, bytes = 0;
+            uint32_t fn = 0;
+            if (k < nu) {
+              if (k >= h0) {
+                c_orphan++;
+              } else {
+                const UItem u = u_of(r, x, sl, hd, k);
+                const Frame e = stk[h0 - 1 - k];
+                if (e.fn != u.fn || u.fn >= tb.n_fns) c_mis++;
+                else if (u.ts < e.ts) c_neg++;
+                else { ok = true; incl = u.ts - e.ts; uchild = u.child; echild = e.child; bytes = e.bytes; fn = u.fn; }
+              }
+            }
+            const uint64_t mine = ok ? incl : 0;
+            const uint64_t before = __shfl_up(mine, 1, CG);
+            const uint64_t credit = j == 0 ? carry : before;
+            carry = __shfl(mine, CG - 1, CG);
+            if (k0 + CG >= nu) last = __shfl(mine, (nu - 1) % CG, CG);
+            if (ok) {
+              const uint64_t ch = echild + uchild + credit;
+              uint64_t self;
+              if (ch <= incl) self = incl - ch; else { self = 0; c_under++; }
+              Tally *t = &tb.tally[(size_t)g * tb.n_fns + fn];
+              ga64(&t->count, 1);
+              ga64(&t->incl_sum, incl); gmin64(&t->incl_min, incl); gmax64(&t->incl_max, incl);
+              ga64(&t->self_sum, self); gmin64(&t->self_min, self); gmax64(&t->self_max, self);
+              if (bytes) ga64(&t->bytes_sum, bytes);
             }
           }
-          const uint64_t mine = ok ? incl : 0;
-          const uint64_t before = __shfl_up(mine, 1, CG);
-          const uint64_t credit = j == 0 ? carry : before;
-          carry = __shfl(mine, CG - 1, CG);
-          if (k0 + CG >= nu) last = __shfl(mine, (nu - 1) % CG, CG);
-          if (ok) {
-            const uint64_t ch = echild + uchild + credit;
-            uint64_t self;
-            if (ch <= incl) self = incl - ch; else { self = 0; c_under++; }
-            Tally *t = &tb.tally[(size_t)g * tb.n_fns + fn];
-            ga64(&t->count, 1);
-            ga64(&t->incl_sum, incl); gmin64(&t->incl_min, incl); gmax64(&t->incl_max, incl);
-            ga64(&t->self_sum, self); gmin64(&t->self_min, self); gmax64(&t->self_max, self);
-            if (bytes) ga64(&t->bytes_sum, bytes);
+          uint32_t h = h0 > nu ? h0 - nu : 0;
+          if (h > 0 && j == 0) stk[h - 1].child += last + hd.floor;
+          const uint32_t no = hd.n_o < D ? hd.n_o : D;
+          for (uint32_t k = j; k < no; k += CG) {
+            if (h + k < D) {
+              const OItem o = o_of(r, x, sl, hd, k);
+              Frame f;
+              f.ts = o.ts; f.child = o.child; f.bytes = o.bytes; f.fn = o.fn; f.pad = 0;
+              stk[h + k] = f;
+            }
           }
+          if (h + no > D) cs.flags |= CS_OVERFLOW;
+          cs.h = h + no < D ? h + no : D;
         }
-        uint32_t h = h0 > nu ? h0 - nu : 0;
-        if (h > 0 && j == 0) stk[h - 1].child += last + hd.floor;
-        const uint32_t no = hd.n_o < D ? hd.n_o : D;
-        for (uint32_t k = j; k < no; k += CG) {
-          if (h + k < D) {
-            Frame f;
-            f.ts = lo[k].ts; f.child = lo[k].child; f.bytes = lo[k].bytes; f.fn = lo[k].fn; f.pad = 0;
-            stk[h + k] = f;
-          }
+        if (j == 0) {
+          if (cs.flags & CS_OVERFLOW) atomicOr(tb.err, ERR_DEPTH);
+          tb.cstate[g] = cs;
+          set_val[i] = cs.h;
         }
-        if (h + no > D) cs.flags |= CS_OVERFLOW;
-        cs.h = h + no < D ? h + no : D;
       }
-      if (j == 0) {
-        if (cs.flags & CS_OVERFLOW) atomicOr(tb.err, ERR_DEPTH);
-        tb.cstate[g] = cs;
-        set_val[i] = cs.h;
-      }
+    };
+    if (staged) {
+      grouped([&](uint32_t, uint32_t x, uint32_t) { return hdrL[x]; },
+              [&](uint32_t, uint32_t x, uint32_t, const RHdr &, uint32_t k) {
+                return ((const UItem *)(itL + (size_t)offL[x] * 32))[k];
+              },
+              [&](uint32_t, uint32_t x, uint32_t, const RHdr &hd, uint32_t k) {
+                return ((const OItem *)(itL + (size_t)(offL[x] + hd.nu_listed) * 32))[k];
+              });
+    } else {
+      grouped([&](uint32_t r, uint32_t, uint32_t sl) { return rhdr[(size_t)r * S_MAX + sl]; },
+              [&](uint32_t r, uint32_t, uint32_t sl, const RHdr &, uint32_t k) {
+                return ru[((size_t)r * S_MAX + sl) * D + k];
+              },
+              [&](uint32_t r, uint32_t, uint32_t sl, const RHdr &, uint32_t k) {
+                return ro[((size_t)r * S_MAX + sl) * D + k];
+              });
     }
   } else {
   for (uint32_t i = tid; i < n; i += 256) {

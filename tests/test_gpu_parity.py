@@ -235,6 +235,17 @@ def test_combine_long_unwind(flush_between):
     assert st["orphan_exits"] >= 1 and st["fn_mismatch"] >= 1 and st["neg_duration"] >= 1
 
 
+def test_combine_unstaged_span():
+    """One stream of 8 threads and 6 M records in two chunks: some 150
+    ranges, whose summaries do not fit the combine's LDS staging, so the
+    grouped fold reads them from global memory."""
+    say("case: one stream, 8 threads, 6M records (summaries folded from global memory)")
+    cfg = synth.base_cfg(n_fns=64, max_depth=6)
+    st = synth.gen_stream(cfg, 4242, 0, 0, 0, 777, 8, 6_000_000)
+    w = synth.Workload("unstaged-span", 1, 64, 0, 6, [st])
+    check(case_from_workload(w, max_depth=8, split=2, seed=8))
+
+
 @pytest.mark.parametrize("extra", [0, 1])
 def test_readout_sort_boundary(extra):
     """256 threads (the readout sorts them in one workgroup) and 257 (the

@@ -268,123 +268,123 @@ __global__ __launch_bounds__(256) void k_combine(const uint32_t *__restrict__ sp
               });
     }
   } else {
-  for (uint32_t i = tid; i < n; i += 256) {
-    const uint32_t g = list[i];
-    CState cs = tb.cstate[g];
-    // The fold is instantiated once for the stack in LDS and once for the
-    // stack in global memory, so that stack accesses are LDS or global
-    // instructions: through a generic pointer each of them would wait for
-    // the tally atomics issued before it.
-    auto fold_thread = [&](Frame *stk) {
-      // one range summary onto the carried stack; uat(k) / oat(k) give its
-      // U / O items (read four at a time)
-      auto fold_one = [&](const RHdr &hd, auto &&uat, auto &&oat) {
-        if (hd.flags & RF_HAS_TS) {
-          if ((cs.flags & CS_HAS_TS) && hd.first_ts < cs.last_ts) c_tsreg++;
-          cs.last_ts = hd.last_ts;
-          cs.flags |= CS_HAS_TS;
-        }
-        const int32_t ds = (int32_t)cs.h;
-        if ((hd.flags & RF_OVERFLOW) || hd.H > (int32_t)D || ds + hd.M > (int32_t)D) cs.flags |= CS_OVERFLOW;
-        for (uint32_t k0 = 0; k0 < hd.nu_listed; k0 += 4) {
-          UItem uu[4];
-#pragma unroll
-          for (int j = 0; j < 4; j++)
-            if (k0 + j < hd.nu_listed) uu[j] = uat(k0 + j);
-#pragma unroll
-          for (int j = 0; j < 4; j++) {
-            if (k0 + j >= hd.nu_listed) break;
-            const UItem &u = uu[j];
-            if (cs.h == 0) { c_orphan++; continue; }
-            cs.h--;
-            const Frame e = stk[cs.h];
-            if (e.fn != u.fn || u.fn >= tb.n_fns) { c_mis++; continue; }
-            if (u.ts < e.ts) { c_neg++; continue; }
-            const uint64_t incl = u.ts - e.ts;
-            const uint64_t ch = e.child + u.child;
-            uint64_t self;
-            if (ch <= incl) self = incl - ch; else { self = 0; c_under++; }
-            Tally *t = &tb.tally[(size_t)g * tb.n_fns + u.fn];
-            ga64(&t->count, 1);
-            ga64(&t->incl_sum, incl); gmin64(&t->incl_min, incl); gmax64(&t->incl_max, incl);
-            ga64(&t->self_sum, self); gmin64(&t->self_min, self); gmax64(&t->self_max, self);
-            if (e.bytes) ga64(&t->bytes_sum, e.bytes);
-            if (cs.h > 0) stk[cs.h - 1].child += incl;
+    for (uint32_t i = tid; i < n; i += 256) {
+      const uint32_t g = list[i];
+      CState cs = tb.cstate[g];
+      // The fold is instantiated once for the stack in LDS and once for the
+      // stack in global memory, so that stack accesses are LDS or global
+      // instructions: through a generic pointer each of them would wait for
+      // the tally atomics issued before it.
+      auto fold_thread = [&](Frame *stk) {
+        // one range summary onto the carried stack; uat(k) / oat(k) give its
+        // U / O items (read four at a time)
+        auto fold_one = [&](const RHdr &hd, auto &&uat, auto &&oat) {
+          if (hd.flags & RF_HAS_TS) {
+            if ((cs.flags & CS_HAS_TS) && hd.first_ts < cs.last_ts) c_tsreg++;
+            cs.last_ts = hd.last_ts;
+            cs.flags |= CS_HAS_TS;
           }
-        }
-        if (cs.h > 0) stk[cs.h - 1].child += hd.floor;
-        const uint32_t no = hd.n_o < D ? hd.n_o : D;
-        for (uint32_t k0 = 0; k0 < no; k0 += 4) {
-          OItem oo[4];
+          const int32_t ds = (int32_t)cs.h;
+          if ((hd.flags & RF_OVERFLOW) || hd.H > (int32_t)D || ds + hd.M > (int32_t)D) cs.flags |= CS_OVERFLOW;
+          for (uint32_t k0 = 0; k0 < hd.nu_listed; k0 += 4) {
+            UItem uu[4];
 #pragma unroll
-          for (int j = 0; j < 4; j++)
-            if (k0 + j < no) oo[j] = oat(k0 + j);
+            for (int j = 0; j < 4; j++)
+              if (k0 + j < hd.nu_listed) uu[j] = uat(k0 + j);
 #pragma unroll
-          for (int j = 0; j < 4; j++) {
-            if (k0 + j >= no) break;
-            if (cs.h < D) {
-              Frame f;
-              f.ts = oo[j].ts; f.child = oo[j].child; f.bytes = oo[j].bytes; f.fn = oo[j].fn; f.pad = 0;
-              stk[cs.h] = f;
-              cs.h++;
-            } else {
-              cs.flags |= CS_OVERFLOW;
+            for (int j = 0; j < 4; j++) {
+              if (k0 + j >= hd.nu_listed) break;
+              const UItem &u = uu[j];
+              if (cs.h == 0) { c_orphan++; continue; }
+              cs.h--;
+              const Frame e = stk[cs.h];
+              if (e.fn != u.fn || u.fn >= tb.n_fns) { c_mis++; continue; }
+              if (u.ts < e.ts) { c_neg++; continue; }
+              const uint64_t incl = u.ts - e.ts;
+              const uint64_t ch = e.child + u.child;
+              uint64_t self;
+              if (ch <= incl) self = incl - ch; else { self = 0; c_under++; }
+              Tally *t = &tb.tally[(size_t)g * tb.n_fns + u.fn];
+              ga64(&t->count, 1);
+              ga64(&t->incl_sum, incl); gmin64(&t->incl_min, incl); gmax64(&t->incl_max, incl);
+              ga64(&t->self_sum, self); gmin64(&t->self_min, self); gmax64(&t->self_max, self);
+              if (e.bytes) ga64(&t->bytes_sum, e.bytes);
+              if (cs.h > 0) stk[cs.h - 1].child += incl;
             }
+          }
+          if (cs.h > 0) stk[cs.h - 1].child += hd.floor;
+          const uint32_t no = hd.n_o < D ? hd.n_o : D;
+          for (uint32_t k0 = 0; k0 < no; k0 += 4) {
+            OItem oo[4];
+#pragma unroll
+            for (int j = 0; j < 4; j++)
+              if (k0 + j < no) oo[j] = oat(k0 + j);
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+              if (k0 + j >= no) break;
+              if (cs.h < D) {
+                Frame f;
+                f.ts = oo[j].ts; f.child = oo[j].child; f.bytes = oo[j].bytes; f.fn = oo[j].fn; f.pad = 0;
+                stk[cs.h] = f;
+                cs.h++;
+              } else {
+                cs.flags |= CS_OVERFLOW;
+              }
+            }
+          }
+        };
+        if (staged) {
+          for (uint32_t r = rb; r < re; r++) {
+            const uint32_t x = (r - rb) * n + i;
+            if (smap[x] == 0xFF) continue;
+            const RHdr hd = hdrL[x];
+            const UItem *lu = (const UItem *)(itL + (size_t)offL[x] * 32);
+            const OItem *lo = (const OItem *)(lu + hd.nu_listed);
+            fold_one(hd, [&](uint32_t k) { return lu[k]; }, [&](uint32_t k) { return lo[k]; });
+          }
+        } else {
+          // slot of this thread in range r's summaries, S_MAX when it has none
+          auto slot_in = [&](const uint32_t r) -> uint32_t {
+            if (use_map) {
+              const uint32_t sl = smap[(r - rb) * n + i];
+              return sl == 0xFF ? (uint32_t)S_MAX : sl;
+            }
+            const uint32_t ns = rnslots[r];
+            const RHdr *hp = rhdr + (size_t)r * S_MAX;
+            uint32_t sl = 0;
+            while (sl < ns && hp[sl].gslot != g) sl++;
+            return sl < ns ? sl : (uint32_t)S_MAX;
+          };
+          auto next_range = [&](uint32_t r, uint32_t &sl) {
+            for (; r < re; r++) {
+              sl = slot_in(r);
+              if (sl < (uint32_t)S_MAX) break;
+            }
+            return r;
+          };
+          // each range's header is loaded while the previous range is folded
+          uint32_t sl = 0;
+          uint32_t r = next_range(rb, sl);
+          RHdr hd_next;
+          if (r < re) hd_next = rhdr[(size_t)r * S_MAX + sl];
+          while (r < re) {
+            const RHdr hd = hd_next;
+            const size_t ib = ((size_t)r * S_MAX + sl) * D;
+            uint32_t sl2 = 0;
+            const uint32_t r2 = next_range(r + 1, sl2);
+            if (r2 < re) hd_next = rhdr[(size_t)r2 * S_MAX + sl2];
+            fold_one(hd, [&](uint32_t k) { return ru[ib + k]; }, [&](uint32_t k) { return ro[ib + k]; });
+            r = r2;
+            sl = sl2;
           }
         }
       };
-      if (staged) {
-        for (uint32_t r = rb; r < re; r++) {
-          const uint32_t x = (r - rb) * n + i;
-          if (smap[x] == 0xFF) continue;
-          const RHdr hd = hdrL[x];
-          const UItem *lu = (const UItem *)(itL + (size_t)offL[x] * 32);
-          const OItem *lo = (const OItem *)(lu + hd.nu_listed);
-          fold_one(hd, [&](uint32_t k) { return lu[k]; }, [&](uint32_t k) { return lo[k]; });
-        }
-      } else {
-        // slot of this thread in range r's summaries, S_MAX when it has none
-        auto slot_in = [&](const uint32_t r) -> uint32_t {
-          if (use_map) {
-            const uint32_t sl = smap[(r - rb) * n + i];
-            return sl == 0xFF ? (uint32_t)S_MAX : sl;
-          }
-          const uint32_t ns = rnslots[r];
-          const RHdr *hp = rhdr + (size_t)r * S_MAX;
-          uint32_t sl = 0;
-          while (sl < ns && hp[sl].gslot != g) sl++;
-          return sl < ns ? sl : (uint32_t)S_MAX;
-        };
-        auto next_range = [&](uint32_t r, uint32_t &sl) {
-          for (; r < re; r++) {
-            sl = slot_in(r);
-            if (sl < (uint32_t)S_MAX) break;
-          }
-          return r;
-        };
-        // each range's header is loaded while the previous range is folded
-        uint32_t sl = 0;
-        uint32_t r = next_range(rb, sl);
-        RHdr hd_next;
-        if (r < re) hd_next = rhdr[(size_t)r * S_MAX + sl];
-        while (r < re) {
-          const RHdr hd = hd_next;
-          const size_t ib = ((size_t)r * S_MAX + sl) * D;
-          uint32_t sl2 = 0;
-          const uint32_t r2 = next_range(r + 1, sl2);
-          if (r2 < re) hd_next = rhdr[(size_t)r2 * S_MAX + sl2];
-          fold_one(hd, [&](uint32_t k) { return ru[ib + k]; }, [&](uint32_t k) { return ro[ib + k]; });
-          r = r2;
-          sl = sl2;
-        }
-      }
-    };
-    if (lds_stack) fold_thread(lstk + (size_t)i * D);
-    else fold_thread(tb.cstack + (size_t)g * D);
-    if (cs.flags & CS_OVERFLOW) atomicOr(tb.err, ERR_DEPTH);
-    tb.cstate[g] = cs;
-    if (lds_stack) set_val[i] = cs.h;
-  }
+      if (lds_stack) fold_thread(lstk + (size_t)i * D);
+      else fold_thread(tb.cstack + (size_t)g * D);
+      if (cs.flags & CS_OVERFLOW) atomicOr(tb.err, ERR_DEPTH);
+      tb.cstate[g] = cs;
+      if (lds_stack) set_val[i] = cs.h;
+    }
   }
   if (lds_stack) {
     __syncthreads();

@@ -72,6 +72,72 @@ def profiled_traffic():
     return int(m2.group(1))
 
 
+def host_cpu():
+    """The host's CPU model and the cores this process may use."""
+    model = platform.processor() or platform.machine()
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, sorted(os.sched_getaffinity(0)), os.cpu_count()
+
+
+def inputs_sha256(w):
+    """SHA-256 over every stream's record bytes (and payload heap), in stream order."""
+    import hashlib
+    h = hashlib.sha256()
+    for s in w.streams:
+        h.update(memoryview(s.records))
+        if s.payload is not None:
+            h.update(memoryview(s.payload))
+    return h.hexdigest()
+
+
+def oracle_pinned(w, max_depth, reps=3):
+    """The oracle, single-threaded, pinned to one core of this process's set;
+    median of `reps` passes over the whole workload.  Returns (seconds, core)."""
+    import oracle
+    cores = sorted(os.sched_getaffinity(0))
+    core = cores[0]
+    os.sched_setaffinity(0, {core})
+    try:
+        runs = []
+        for _ in range(reps):
+            tc = time.perf_counter()
+            oracle.run_workload(w, max_depth=max_depth).close()
+            runs.append(time.perf_counter() - tc)
+    finally:
+        os.sched_setaffinity(0, set(cores))
+    return sorted(runs)[len(runs) // 2], core
+
+
+def oracle_parallel(w, max_depth):
+    """The per-stream parallel CPU baseline: independent streams on N =
+    min(#streams, cores) worker threads (the oracle's C code runs without the
+    interpreter lock), each with its own oracle over its share of the streams."""
+    import concurrent.futures as cf
+
+    import oracle
+    n = max(1, min(len(w.streams), len(os.sched_getaffinity(0))))
+    shares = [w.streams[i::n] for i in range(n)]
+
+    def work(share):
+        o = oracle.Oracle(w.fmt, w.n_fns, w.n_kernel_ids, max_depth, w.has_size)
+        for s in share:
+            assert o.submit(s.key, s.records, s.payload) == 0
+        o.finish()
+        o.close()
+
+    tc = time.perf_counter()
+    with cf.ThreadPoolExecutor(n) as ex:
+        list(ex.map(work, shares))
+    return time.perf_counter() - tc, n
+
+
 def base_line(steps, warmup, ms_per_step, value, config):
     return {"metric": METRIC, "value": value, "unit": "events/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
             "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -87,9 +153,12 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="plain form: leave out the batched-vs-per-trace comparison on the batched workload")
     ap.add_argument("--form", default="plain", choices=["plain", "batched", "streaming"])
     ap.add_argument("--rates", default="2,5,10,20", help="streaming: offered GB/s per point")
-    ap.add_argument("--seconds", type=float, default=3.0, help="streaming: measured seconds per point")
+    ap.add_argument("--seconds", type=float, default=10.0, help="streaming: measured seconds per point")
+    ap.add_argument("--no-plain", action="store_true", help="streaming: leave out the plain-form comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one elementwise pass of known size (1 GiB read + 1 GiB written) so that HBM "
                          "counters (FETCH_SIZE / WRITE_SIZE) can be scaled to bytes")
@@ -117,7 +186,9 @@ def main():
     w = synth.config(args.config, scale=args.scale)
     n_rec = w.n_records
     in_bytes = w.record_bytes + w.payload_bytes
-    log("generated %s: %d records, %.2f GB in %.1fs" % (w.name, n_rec, in_bytes / 1e9, time.time() - t0))
+    sha = inputs_sha256(w)
+    log("generated %s: %d records, %.2f GB in %.1fs (sha256 %s)" % (w.name, n_rec, in_bytes / 1e9, time.time() - t0,
+                                                                    sha[:16]))
 
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
@@ -165,36 +236,39 @@ def main():
     log("kernel ms (avg): " + ", ".join("%s %.4f" % (k, sum(v) / len(v)) for k, v in other_ms.items()))
 
     avg_range_ms = sum(range_ms) / len(range_ms)
+    avg = {k: sum(v) / len(v) for k, v in other_ms.items()}
+    pipeline_ms = avg.get("prepass", 0) + avg["range"] + avg.get("combine", 0) + avg.get("final", 0)
     rows_written = len(rows)
     alg_bytes = in_bytes + 64 * rows_written  # records read once + tally rows written
     achieved = alg_bytes / (avg_range_ms * 1e-3) / 1e9
+    read_bw = T.read_bandwidth(0, 4 << 30, 5)
+    log("measured streaming-read bandwidth: %.0f GB/s" % read_bw)
 
     parity = "not checked"
     cpu = None
-    if not args.no_cpu_baseline or not args.no_parity:
+    rows = rows.copy()
+    if not args.no_parity:
         import oracle
         tc = time.perf_counter()
         o = oracle.run_workload(w, max_depth=max(w.max_depth, 8))
-        cpu_s = time.perf_counter() - tc
-        log("oracle: %.2fs for %d records" % (cpu_s, n_rec))
-        runs = [cpu_s]
-        if not args.no_parity:
-            want = o.rows(oracle.SCOPE_THREAD)
-            ok = rows.shape == want.shape and np.array_equal(rows, want)
-            ws = o.stats()
-            ok = ok and all(stats[k] == ws[k] for k in T.STAT_NAMES if k != "dropped_records")
-            parity = "bit-exact" if ok else "MISMATCH"
-            log("parity vs oracle: " + parity)
+        log("oracle: %.2fs for %d records" % (time.perf_counter() - tc, n_rec))
+        want = o.rows(oracle.SCOPE_THREAD)
+        ok = rows.shape == want.shape and np.array_equal(rows, want)
+        ws = o.stats()
+        ok = ok and all(stats[k] == ws[k] for k in T.STAT_NAMES if k != "dropped_records")
+        parity = "bit-exact" if ok else "MISMATCH"
+        log("parity vs oracle: " + parity)
         o.close()
-        if not args.no_cpu_baseline:
-            for _ in range(2):      # median of three single-threaded passes
-                tc = time.perf_counter()
-                oracle.run_workload(w, max_depth=max(w.max_depth, 8)).close()
-                runs.append(time.perf_counter() - tc)
-            cpu_s = sorted(runs)[1]
-            cpu = {"value": n_rec / cpu_s, "unit": "events/s", "cores": 1, "kind": "oracle",
-                   "sample": "the whole workload (%d records), median of 3 single-threaded passes; host %s" % (
-                       n_rec, platform.processor() or platform.machine())}
+    if not args.no_cpu_baseline:
+        model, cores, ncpu = host_cpu()
+        cpu_s, core = oracle_pinned(w, max(w.max_depth, 8))
+        par_s, n_par = oracle_parallel(w, max(w.max_depth, 8))
+        log("oracle pinned to core %d: %.2fs; %d workers: %.2fs" % (core, cpu_s, n_par, par_s))
+        cpu = {"value": n_rec / cpu_s, "unit": "events/s", "cores": 1, "kind": "oracle",
+               "sample": "the whole workload (%d records), median of 3 passes, pinned to one core" % n_rec,
+               "cpu_model": model, "cores_available": len(cores), "nproc": ncpu,
+               "parallel": {"value": n_rec / par_s, "unit": "events/s", "workers": n_par,
+                            "kind": "oracle per stream, N = min(streams, cores available)"}}
 
     out = {
         "metric": METRIC,
@@ -211,15 +285,20 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.config] + ("" if args.scale == 1.0 else " (scale %g)" % args.scale),
                    "records": n_rec, "input_bytes": in_bytes, "format": "FIXED24" if w.fmt == 1 else "VAR16",
-                   "streams": len(w.streams)},
+                   "streams": len(w.streams), "seed": synth.SEED_BASE + args.config, "input_sha256": sha},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": profiled_traffic() if (args.config == 1 and args.scale == 1.0) else None,
-                     "kernel": "tt::k_range", "kernel_ms": avg_range_ms, "alg_bytes": alg_bytes},
+                     "kernel": "tt::k_range", "kernel_ms": avg_range_ms, "alg_bytes": alg_bytes,
+                     "pipeline_ms": pipeline_ms, "pipeline_frac": alg_bytes / (pipeline_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "measured_read_GBps": read_bw, "frac_of_measured_read": achieved / read_bw},
         "cpu_baseline": cpu,
         "parity": parity,
     }
     tl.close()
+    del recs, pays
+    if not args.no_batched:
+        out["batched_vs_per_trace"] = run_batched(args, stream, steps=min(args.steps, 10), warmup=2, autotune=False)
     print(json.dumps(out), flush=True)
 
 
@@ -236,8 +315,11 @@ def copy_calibration():
     print(json.dumps({"copy_calibration": {"read_bytes": n, "write_bytes": n, "dispatches": 2}}), flush=True)
 
 
-def bench_batched(args):
-    """One flush over 256 traces vs 256 per-trace flushes, same GPU, same resident input."""
+def run_batched(args, stream, steps, warmup, autotune=True):
+    """The batched workload (256 traces of uneven size, resident in HBM) as one
+    flush = one persistent work-list launch (graph-replayed), against the plain
+    per-trace form (256 sequential reset/submit/flush/read) on the same GPU and
+    input; both checked against each other and against the oracle."""
     import numpy as np
     import torch
 
@@ -250,26 +332,30 @@ def bench_batched(args):
     log("generated batched: %d traces, %d records, %.2f GB in %.1fs" % (len(w.streams), n_rec,
                                                                       w.record_bytes / 1e9, time.time() - t0))
     dev = torch.device("cuda:0")
-    stream = torch.cuda.current_stream(dev)
     recs = [torch.from_numpy(s.records).to(dev) for s in w.streams]
     torch.cuda.synchronize()
     max_threads = sum(len(s.tid_of_thread) for s in w.streams) + 64
-    cache = os.path.join(os.environ.get("TMPDIR", "/tmp"), "thapi_tally_autotune.txt")
-    if os.path.exists(cache):
-        os.remove(cache)
     kw = dict(max_depth=8, max_threads=max_threads, max_streams=512, has_size=None, stream=stream)
-    tb = T.Tally(w.fmt, w.n_fns, 0, flags=T.DEVICE_INPUT | T.PROFILE | T.GRAPH, autotune_cache=cache, **kw)
+    chosen = None
+    if autotune:
+        cache = os.path.join(os.environ.get("TMPDIR", "/tmp"), "thapi_tally_autotune.txt")
+        if os.path.exists(cache):
+            os.remove(cache)
+        tb = T.Tally(w.fmt, w.n_fns, 0, flags=T.DEVICE_INPUT | T.PROFILE | T.GRAPH, autotune_cache=cache, **kw)
+    else:
+        tb = T.Tally(w.fmt, w.n_fns, 0, flags=T.DEVICE_INPUT | T.PROFILE | T.GRAPH, **kw)
 
     def submit_all(h):
         for s, r in zip(w.streams, recs):
             h.submit(s.key, r)
 
-    submit_all(tb)
-    tz = time.perf_counter()
-    chosen = tb.autotune(reps=2)
-    log("autotune: T=%d E=%d ranges/CU=%d pipelined=%d (%.1fs)" % (chosen + (time.perf_counter() - tz,)))
-    tb.flush(final=True)
-    tb.reset()
+    if autotune:
+        submit_all(tb)
+        tz = time.perf_counter()
+        chosen = tb.autotune(reps=2)
+        log("autotune: T=%d E=%d ranges/CU=%d pipelined=%d (%.1fs)" % (chosen + (time.perf_counter() - tz,)))
+        tb.flush(final=True)
+        tb.reset()
 
     def step_batched():
         tb.reset()
@@ -277,20 +363,20 @@ def bench_batched(args):
         tb.flush(final=True)
         return tb.read(T.SCOPE_THREAD)
 
-    def timed(fn, steps):
+    def timed(fn, n):
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         out = None
-        for _ in range(steps):
+        for _ in range(n):
             out = fn()
         e1.record(stream)
         torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / steps, out
+        return e0.elapsed_time(e1) / n, out
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step_batched()
-    ms_b, (rows_b, stats_b) = timed(step_batched, args.steps)
+    ms_b, (rows_b, stats_b) = timed(step_batched, steps)
     log("batched: %.3f ms/step" % ms_b)
 
     # the plain per-trace form: a handle sized for one trace (at most 64 threads), reset between traces
@@ -307,13 +393,12 @@ def bench_batched(args):
         return out
 
     step_per_trace()
-    seq_steps = max(1, min(args.steps, 3))
-    ms_p, rows_p = timed(step_per_trace, seq_steps)
+    ms_p, rows_p = timed(step_per_trace, max(1, min(steps, 3)))
     log("per-trace: %.3f ms/step" % ms_p)
     same = np.array_equal(np.concatenate(rows_p), rows_b)
     parity = "batched == per-trace: %s" % ("bit-exact" if same else "MISMATCH")
-    cpu = None
-    if not args.no_parity or not args.no_cpu_baseline:
+    cpu_s = None
+    if not args.no_parity:
         import oracle
         tc = time.perf_counter()
         o = oracle.run_workload(w, max_depth=8)
@@ -324,27 +409,92 @@ def bench_batched(args):
         ok = ok and all(stats_b[k] == ws[k] for k in T.STAT_NAMES if k != "dropped_records")
         parity = "bit-exact (batched, per-trace and oracle)" if ok else "MISMATCH: " + parity
         log("oracle: %.2fs; parity %s" % (cpu_s, parity))
-        cpu = {"value": n_rec / cpu_s, "unit": "events/s", "cores": 1, "kind": "oracle",
-               "sample": "the whole batch (%d records, 256 traces), one pass, single thread" % n_rec}
         o.close()
-    out = base_line(args.steps, args.warmup, ms_b, n_rec / (ms_b * 1e-3), {
-        "workload": "batched: 256 traces, 10k-20M FIXED24 records each (log-uniform), 1-64 threads, 32-200 fns"
-                    + ("" if args.scale == 1.0 else " (scale %g)" % args.scale),
-        "records": n_rec, "input_bytes": w.record_bytes, "format": "FIXED24", "traces": len(w.streams)})
-    out["batched_vs_per_trace"] = {"batched_ms": ms_b, "per_trace_ms": ms_p, "speedup": ms_p / ms_b,
-                                   "per_trace_events_per_s": n_rec / (ms_p * 1e-3),
-                                   "autotuned": {"T": chosen[0], "E": chosen[1], "ranges_per_cu": chosen[2],
-                                                 "pipelined": chosen[3]},
-                                   "graph": True}
-    out["cpu_baseline"] = cpu
-    out["parity"] = parity
     tb.close()
     tp.close()
+    del recs
+    torch.cuda.empty_cache()
+    sub = {"workload": "batched: 256 traces, 10k-20M FIXED24 records each (log-uniform), 1-64 threads, "
+                       "32-200 fns" + ("" if args.scale == 1.0 else " (scale %g)" % args.scale),
+           "records": n_rec, "input_bytes": w.record_bytes, "seed": synth.SEED_BASE + 3,
+           "batched_ms": ms_b, "per_trace_ms": ms_p, "speedup": ms_p / ms_b,
+           "batched_events_per_s": n_rec / (ms_b * 1e-3), "per_trace_events_per_s": n_rec / (ms_p * 1e-3),
+           "batched_hbm_frac": w.record_bytes / (ms_b * 1e-3) / 1e9 / HBM_PEAK_GBS,
+           "graph": True, "parity": parity}
+    if chosen is not None:
+        sub["autotuned"] = {"T": chosen[0], "E": chosen[1], "ranges_per_cu": chosen[2], "pipelined": chosen[3]}
+    if cpu_s is not None:
+        sub["oracle_events_per_s"] = n_rec / cpu_s
+    return sub
+
+
+def bench_batched(args):
+    """One flush over 256 traces vs 256 per-trace flushes, same GPU, same resident input."""
+    import torch
+    stream = torch.cuda.current_stream(torch.device("cuda:0"))
+    sub = run_batched(args, stream, args.steps, args.warmup, autotune=True)
+    out = base_line(args.steps, args.warmup, sub["batched_ms"], sub["batched_events_per_s"], {
+        "workload": sub["workload"], "records": sub["records"], "input_bytes": sub["input_bytes"],
+        "format": "FIXED24", "traces": 256})
+    out["batched_vs_per_trace"] = sub
+    out["cpu_baseline"] = None if "oracle_events_per_s" not in sub else {
+        "value": sub["oracle_events_per_s"], "unit": "events/s", "cores": 1, "kind": "oracle",
+        "sample": "the whole batch (%d records, 256 traces), one pass, single thread" % sub["records"]}
+    out["parity"] = sub["parity"]
     print(json.dumps(out), flush=True)
 
 
+def _streaming_expected(w, plan_chunks, n_prod):
+    """Oracle rows (thread scope, canonical order) and counters of one
+    streaming run: a pool stream's chunks of one cycle form the stream
+    (1 + cycle, host, pid), and tallies do not depend on where chunks are cut,
+    so a full cycle is the oracle of the whole pool stream and a partial one
+    the oracle of its prefix."""
+    import concurrent.futures as cf
+
+    import numpy as np
+
+    import oracle
+    last = {}
+    for (ta, p, cyc, off, sz) in plan_chunks:
+        last[(p, cyc)] = max(last.get((p, cyc), 0), off + sz)
+    jobs = {}
+    for (p, cyc), end in last.items():
+        full = end >= w.streams[p].records.size
+        jobs.setdefault((p, end if not full else -1), []).append(cyc)
+
+    def run(item):
+        (p, end), cycs = item
+        s = w.streams[p]
+        rec = s.records if end < 0 else s.records[:end]
+        o = oracle.Oracle(w.fmt, w.n_fns, w.n_kernel_ids, 8)
+        assert o.submit(s.key, rec) == 0
+        o.finish()
+        r, st = o.rows(oracle.SCOPE_THREAD), o.stats()
+        o.close()
+        return r, st, cycs
+
+    n = max(1, min(16, len(os.sched_getaffinity(0))))
+    parts, stats = [], {}
+    with cf.ThreadPoolExecutor(n) as ex:
+        for r, st, cycs in ex.map(run, list(jobs.items())):
+            for c in cycs:
+                rr = r.copy()
+                rr["trace"] = 1 + c
+                parts.append(rr)
+                for k, v in st.items():
+                    stats[k] = stats.get(k, 0) + v
+    # hosts are (trace, host) pairs, shared by the streams of one trace
+    stats["distinct_hosts"] = len({(1 + c, w.streams[p].host) for (p, _), cycs in jobs.items() for c in cycs})
+    rows = np.concatenate(parts) if parts else np.zeros(0, dtype=oracle.ROW_DTYPE)
+    order = np.lexsort((rows["id"], rows["row_kind"], rows["tid"], rows["pid"], rows["host"], rows["trace"]))
+    return rows[order], stats
+
+
 def bench_streaming(args):
-    """Open-loop Poisson arrivals into the service; latency = completion - scheduled arrival."""
+    """Open-loop Poisson arrivals into the service; latency = completion - scheduled arrival.
+    The same chunk schedule is then fed to the plain form (one submit + flush per chunk,
+    one consumer), and every service run is checked against the oracle."""
     import threading
 
     import numpy as np
@@ -360,6 +510,7 @@ def bench_streaming(args):
     n_prod = 4
     points = []
     total_wall = 0.0
+    all_exact = True
     for ri, rate in enumerate(rates):
         rng = np.random.default_rng(1000 + ri)
         dur = args.seconds + 0.5
@@ -387,54 +538,84 @@ def bench_streaming(args):
             cursor[p] += sz
             planned += sz
         n_streams = len(w.streams) * (max(cycle) + 1)
-        tl = T.Tally(w.fmt, w.n_fns, 0, max_depth=8, max_threads=64 * n_streams + 64,
-                     max_streams=n_streams + 8, flags=T.SERVICE, budget=16 << 30)
-        lat, lock = [], threading.Lock()
-        t_start = time.monotonic_ns() + int(50e6)
+        kw = dict(max_depth=8, max_threads=64 * n_streams + 64, max_streams=n_streams + 8)
 
-        def produce(q):
-            mine = []
-            for (ta, p, cyc, off, sz) in plans[q]:
-                sched = t_start + int(ta * 1e9)
-                now = time.monotonic_ns()
-                if sched > now:
-                    time.sleep((sched - now) / 1e9)
-                s = w.streams[p]
-                tk = tl.submit((1 + cyc, s.key[1], s.key[2]), s.records[off:off + sz])
-                mine.append((tk, sched, ta, sz))
-            with lock:
-                lat.extend(mine)
+        def run_form(service):
+            tl = T.Tally(w.fmt, w.n_fns, 0, flags=T.SERVICE if service else 0, budget=16 << 30, **kw)
+            lat, lock = [], threading.Lock()
+            t_start = time.monotonic_ns() + int(50e6)
+            wall_cap = time.monotonic_ns() + int(2 * dur * 1e9) + int(50e6)
+            skipped = [0]
 
-        th = [threading.Thread(target=produce, args=(q,)) for q in range(n_prod)]
-        wall0 = time.perf_counter()
-        for x in th:
-            x.start()
-        for x in th:
-            x.join()
-        tl.flush(final=True)
-        wall = time.perf_counter() - wall0
+            def produce(chunks):
+                mine = []
+                for (ta, p, cyc, off, sz) in chunks:
+                    sched = t_start + int(ta * 1e9)
+                    now = time.monotonic_ns()
+                    if not service and now > wall_cap:
+                        skipped[0] += 1
+                        continue
+                    if sched > now:
+                        time.sleep((sched - now) / 1e9)
+                    s = w.streams[p]
+                    tk = tl.submit((1 + cyc, s.key[1], s.key[2]), s.records[off:off + sz])
+                    if not service:
+                        tl.flush(tk)
+                        mine.append((tk, sched, ta, sz, time.monotonic_ns()))
+                    else:
+                        mine.append((tk, sched, ta, sz, None))
+                with lock:
+                    lat.extend(mine)
+
+            wall0 = time.perf_counter()
+            if service:
+                th = [threading.Thread(target=produce, args=(plans[q],)) for q in range(n_prod)]
+                for x in th:
+                    x.start()
+                for x in th:
+                    x.join()
+            else:
+                produce(sorted((c for pl in plans for c in pl), key=lambda c: c[0]))
+            tl.flush(final=True)
+            wall = time.perf_counter() - wall0
+            rows, st = tl.read(T.SCOPE_THREAD)
+            info = tl.service_info() if service else {}
+            lats, nbytes, first, last = [], 0, None, None
+            for tk, sched, ta, sz, done in lat:
+                if ta < 0.5:        # warm-up arrivals are not measured
+                    continue
+                d = tl.ticket_done(tk) if service else done
+                lats.append((d - sched) / 1e6)
+                nbytes += sz
+                first = sched if first is None else min(first, sched)
+                last = d if last is None else max(last, d)
+            tl.close()
+            lats = np.array(lats)
+            span = max(1e-9, (last - first) / 1e9)
+            pt = {"achieved_GBps": nbytes / span / 1e9, "events_per_s": nbytes / 24 / span,
+                  "chunks": int(len(lats)), "p50_ms": float(np.percentile(lats, 50)),
+                  "p99_ms": float(np.percentile(lats, 99)), "max_ms": float(lats.max())}
+            if service:
+                pt.update({"batches": info["batches"], "mean_batch_chunks": info["batch_chunks"] / max(1, info["batches"]),
+                           "max_batch_chunks": info["max_batch_chunks"]})
+            else:
+                pt["chunks_not_started_within_2x_duration"] = skipped[0]
+            return pt, rows, st, wall
+
+        pt, rows, st, wall = run_form(True)
         total_wall += wall
-        _, st = tl.read(T.SCOPE_FN)
-        info = tl.service_info()
-        lats, nbytes, first, last = [], 0, None, None
-        for tk, sched, ta, sz in lat:
-            if ta < 0.5:        # warm-up arrivals are not measured
-                continue
-            d = tl.ticket_done(tk)
-            lats.append((d - sched) / 1e6)
-            nbytes += sz
-            first = sched if first is None else min(first, sched)
-            last = d if last is None else max(last, d)
-        tl.close()
-        lats = np.array(lats)
-        # achieved: measured chunks' bytes over first scheduled arrival .. last completion
-        span = max(1e-9, (last - first) / 1e9)
-        pt = {"offered_GBps": rate, "achieved_GBps": nbytes / span / 1e9, "events_per_s": nbytes / 24 / span,
-              "chunks": int(len(lats)), "p50_ms": float(np.percentile(lats, 50)),
-              "p99_ms": float(np.percentile(lats, 99)), "max_ms": float(lats.max()),
-              "batches": info["batches"], "mean_batch_chunks": info["batch_chunks"] / max(1, info["batches"]),
-              "max_batch_chunks": info["max_batch_chunks"], "records": st["records"]}
-        log("rate %.1f GB/s: %s" % (rate, json.dumps(pt)))
+        pt = dict({"offered_GBps": rate}, **pt)
+        if not args.no_parity:
+            want, wst = _streaming_expected(w, [c for pl in plans for c in pl], n_prod)
+            ok = rows.shape == want.shape and np.array_equal(rows, want)
+            ok = ok and all(st[k] == wst[k] for k in T.STAT_NAMES if k != "dropped_records")
+            pt["parity"] = "bit-exact" if ok else "MISMATCH"
+            all_exact = all_exact and ok
+        log("rate %.1f GB/s, service: %s" % (rate, json.dumps(pt)))
+        if not args.no_plain:
+            pp, _, _, _ = run_form(False)
+            log("rate %.1f GB/s, plain: %s" % (rate, json.dumps(pp)))
+            pt["plain_one_chunk_per_flush"] = pp
         points.append(pt)
     best = max(points, key=lambda p: p["events_per_s"])
     out = base_line(len(points), 0, 1e3 * total_wall / len(points), best["events_per_s"], {
@@ -445,7 +626,7 @@ def bench_streaming(args):
     out["streaming"] = points
     out["p99_chunk_latency_ms"] = best["p99_ms"]
     out["cpu_baseline"] = None
-    out["parity"] = "not checked here (tests/test_gpu_streaming.py checks the service bit-exactly)"
+    out["parity"] = ("bit-exact at every rate" if all_exact else "MISMATCH") if not args.no_parity else "not checked"
     print(json.dumps(out), flush=True)
 
 

@@ -76,7 +76,8 @@ extern "C" {
 #define THAPI_GRAPH        0x20u /* flush() captures its kernels in a HIP graph once per launch
                                     signature (work-list size, shape, buffers) and replays it */
 #define THAPI_SERVICE      0x40u /* streaming form: a library thread tallies chunks as they arrive
-                                    (continuous batching, see thapi_tally_ticket_done) */
+                                    (continuous batching, see thapi_tally_ticket_done); cannot be
+                                    combined with THAPI_GRAPH (open returns THAPI_E_INVAL) */
 
 /* ---- flush / read ------------------------------------------------------ */
 #define THAPI_TICKET_ALL  UINT64_MAX
@@ -188,9 +189,14 @@ int thapi_tally_read(thapi_tally *t, uint32_t scope, uint32_t trace_id,
                      thapi_tally_stats *stats);
 
 /* Forgets every tally, stack, stream and counter (device memory is kept) so
- * the handle can start a new trace set.  Not valid while submits are queued.
- * The device tables are cleared by work enqueued on the handle's stream,
- * which later flushes and reads follow; the call does not wait for it. */
+ * the handle can start a new trace set.  Not valid while submits are queued
+ * (THAPI_E_STATE), except on a THAPI_SERVICE handle that a failure other than
+ * THAPI_E_DEVICE stopped: there the chunks still queued are discarded (their
+ * tickets never complete) and the service thread is started again.  On a
+ * running service handle, reset first waits until every submitted chunk is
+ * tallied.  The device tables are cleared by work enqueued on the handle's
+ * stream, which later flushes and reads follow; the call does not wait for it.
+ * A handle failed with THAPI_E_DEVICE cannot be reset. */
 int thapi_tally_reset(thapi_tally *t);
 
 /* Batched form: times the pipeline on the chunks queued right now under each
@@ -217,10 +223,13 @@ int thapi_tally_autotune(thapi_tally *t, uint32_t reps, uint32_t *chosen);
  * starts a worker thread and, for host input, reserves device_budget_bytes of
  * device memory as the admission arena.  submit() waits for arena room (or
  * returns THAPI_E_AGAIN / drops, per the flags), queues the chunk in ticket
- * order and copies it on a copy stream; the worker repeatedly takes every
- * chunk whose copy has landed, tallies them all in one pipeline launch while
- * later chunks keep copying, stamps their completion and frees their arena
- * space.  Open calls stay on the device stacks between batches, so results
+ * order, copies the caller's bytes into a pinned staging ring (at most
+ * min(device_budget_bytes, 512 MiB), so the caller may reuse its buffer when
+ * submit returns) and enqueues the ring -> arena DMA on one of four copy
+ * streams, without waiting for it; the worker repeatedly takes every queued
+ * chunk, makes its launch wait on the device for those chunks' copies,
+ * tallies them all in one pipeline launch while later chunks keep copying,
+ * stamps their completion and frees their ring and arena space.  Open calls stay on the device stacks between batches, so results
  * equal those of one flush over the same submissions.  flush(ticket) waits
  * until the worker has covered `ticket`; flush(..., THAPI_FLUSH_FINAL) waits
  * for everything submitted, then closes all streams.  A failure inside the
@@ -237,8 +246,64 @@ int thapi_tally_autotune(thapi_tally *t, uint32_t reps, uint32_t *chosen);
 int thapi_tally_ticket_done(thapi_tally *t, uint64_t ticket, uint64_t *done_ns);
 int thapi_tally_service_info(thapi_tally *t, uint64_t *info, int n);
 
+/* Aggregate export and merge (section 3.7, On-node Processing: the aggregate
+ * of a trace, small enough to keep where the trace itself is not, can be
+ * replayed into a tally, and the aggregates of many nodes are combined at a
+ * global master).
+ *
+ * thapi_tally_export writes everything flushed so far as one self-describing
+ * little-endian byte blob: every stream's key, dropped records and counters;
+ * every thread's (stream, tid), open calls (its carried stack), flags and
+ * last timestamp; every non-empty (thread, fn) tally and (stream, kernel)
+ * tally.  Layout, in order:
+ *   header  16 x u32: magic "THTALLY1" (2 words), version 1, format, n_fns,
+ *           n_kernel_ids, max_depth, n_streams, n_threads, n_frames, n_rows,
+ *           n_krows, finalized (0/1), 3 x 0
+ *   streams n_streams x {u32 trace, host, pid, 0; u64 dropped; u64 counters[11]}
+ *           (counters: records, entries, exits, kernel records, orphan exits,
+ *           fn mismatch, negative durations, self underflow, ts regressions,
+ *           unclosed at the final flush, bad records)
+ *   threads n_threads x {u32 stream index, tid, open calls, flags (1: has a
+ *           timestamp, 2: stack overflowed); u64 last timestamp}
+ *   frames  n_frames x {u32 thread index, fn; u64 entry ts, children time,
+ *           bytes}, each thread's open calls bottom first, threads in order
+ *   rows    n_rows x {u32 thread index, fn; u64 count, incl sum/min/max,
+ *           self sum/min/max, bytes}
+ *   krows   n_krows x {u32 stream index, kernel id; u64 count, sum, min, max}
+ * Two-call pattern: *size receives the blob size; with capacity `cap` too
+ * small nothing is written and THAPI_E_BUFSZ is returned (THAPI_OK when buf
+ * is NULL and cap is 0).  Errors: THAPI_E_INVAL, THAPI_E_BUFSZ,
+ * THAPI_E_STATE (failed handle), THAPI_E_DEVICE.
+ *
+ * thapi_tally_merge combines a blob into the handle: streams match by key
+ * (new keys are registered), threads by (stream key, tid); counts, sums,
+ * counters and dropped records add, mins and maxes combine; a blob thread's
+ * open calls and last timestamp are installed on the handle's thread, which
+ * must have no open call (THAPI_E_STATE otherwise, and nothing changes).  So
+ * the merge of the exports of handles that saw disjoint sets of streams
+ * equals one handle that saw them all, and a fresh handle that merges an
+ * export taken between flushes continues the trace exactly where the
+ * exporting handle stopped (checkpoint / resume).  The blob's format, n_fns,
+ * n_kernel_ids and max_depth must equal the handle's (THAPI_E_INVAL).  Not
+ * valid on a THAPI_SERVICE handle, while chunks are queued or after the final
+ * flush (THAPI_E_STATE).  Errors: THAPI_E_INVAL (malformed blob),
+ * THAPI_E_CAPACITY (more streams than max_streams: nothing changes; more
+ * threads than max_threads: the handle is failed), THAPI_E_STATE,
+ * THAPI_E_DEVICE. */
+int thapi_tally_export(thapi_tally *t, void *buf, size_t cap, size_t *size);
+int thapi_tally_merge(thapi_tally *t, const void *buf, size_t size);
+
 /* Frees everything.  Queued chunks that were never flushed are discarded. */
 int thapi_tally_close(thapi_tally *t);
+
+/* Measurement helper, not part of the tally: the streaming-read bandwidth of
+ * `device` in GB/s (1e9 bytes/s), from a plain read kernel (16-byte
+ * non-temporal loads, grid-stride, about 16 workgroups per compute unit)
+ * over a freshly allocated buffer of `bytes` (rounded down to the kernel's
+ * quantum; at least 1 MiB), best of `reps` timed passes after one warm-up.
+ * The figure that an HBM-bound kernel's fraction of the published peak can
+ * be set against.  Errors: THAPI_E_INVAL, THAPI_E_NOMEM, THAPI_E_DEVICE. */
+int thapi_tally_read_bandwidth(int32_t device, uint64_t bytes, uint32_t reps, double *gbs);
 
 /* Static English text for a status code; never NULL. */
 const char *thapi_tally_strerror(int code);

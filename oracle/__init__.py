@@ -31,6 +31,11 @@ STAT_NAMES = ["records", "entries", "exits", "kernel_records", "orphan_exits", "
               "depth_overflow", "bad_records", "dropped_records", "distinct_hosts",
               "distinct_processes", "distinct_threads"]
 
+IVAL_DTYPE = np.dtype([
+    ("trace", "<u4"), ("host", "<u4"), ("pid", "<u4"), ("tid", "<u4"), ("fn", "<u4"), ("depth", "<u4"),
+    ("start", "<u8"), ("end", "<u8"), ("parent_start", "<u8"), ("parent_fn", "<u4"), ("pad", "<u4"),
+])
+
 _lib = None
 
 
@@ -61,6 +66,11 @@ def _load():
         lib.oracle_stats.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p]
         lib.oracle_row_size.restype = ctypes.c_uint64
         assert lib.oracle_row_size() == ROW_DTYPE.itemsize
+        lib.oracle_keep_intervals.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        lib.oracle_intervals.restype = ctypes.c_size_t
+        lib.oracle_intervals.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]
+        lib.oracle_interval_size.restype = ctypes.c_uint64
+        assert lib.oracle_interval_size() == IVAL_DTYPE.itemsize
         _lib = lib
     return _lib
 
@@ -108,6 +118,18 @@ class Oracle:
         out = np.zeros(n, dtype=ROW_DTYPE)
         if n:
             self._lib.oracle_rows(self._h, scope, trace, out.ctypes.data, n)
+        return out
+
+    def keep_intervals(self, on: bool = True):
+        """Keep every tallied call as an interval from now on (see oracle_intervals)."""
+        self._lib.oracle_keep_intervals(self._h, 1 if on else 0)
+
+    def intervals(self) -> np.ndarray:
+        """Kept intervals, IVAL_DTYPE, sorted by (trace, host, pid, tid, start, depth, end, fn, parent)."""
+        n = self._lib.oracle_intervals(self._h, None, 0)
+        out = np.zeros(n, dtype=IVAL_DTYPE)
+        if n:
+            self._lib.oracle_intervals(self._h, out.ctypes.data, n)
         return out
 
     def stats(self, trace: int = ALL) -> dict:

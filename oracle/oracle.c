@@ -33,6 +33,13 @@
  *   anything else: a bad record.
  * Final flush: every entry still open counts as unclosed and is not tallied.
  * All arithmetic is unsigned 64-bit integer (modulo 2^64).
+ *
+ * On request (oracle_keep_intervals) every tallied call is also kept as an
+ * interval (section 3.3: an interval plugin turns the entry and exit events
+ * of a call into one record spanning them; section 3.6 draws such records on
+ * a timeline): {stream, tid, fn, depth, entry ts, exit ts, and the entry ts
+ * and fn of the call that was the stack top when this one was entered (its
+ * parent; none at the top level)}, depth 1 being the top level.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -84,6 +91,7 @@ typedef struct {
 typedef struct { uint32_t trace, host, pid; uint64_t st[17]; int has_record; } stream_t;
 typedef struct { uint32_t stream, tid, fn; uint64_t v[8]; } tally_t;   /* count, incl sum/min/max, self sum/min/max, bytes */
 typedef struct { uint32_t stream, kid; uint64_t v[4]; } ktally_t;       /* count, dur sum/min/max */
+typedef struct { uint32_t stream, tid, fn, depth; uint64_t start, end, pstart; uint32_t pfn, pad; } ival_t;
 
 enum { S_RECORDS, S_ENTRIES, S_EXITS, S_KERNEL, S_ORPHAN, S_MISMATCH, S_NEGDUR, S_SELFUNDER,
        S_TSREG, S_UNCLOSED, S_OPEN, S_DEPTH, S_BAD, S_DROPPED, S_HOSTS, S_PROCS, S_THREADS, S_N };
@@ -96,6 +104,8 @@ typedef struct oracle {
   thread_t *threads; size_t nt, tcap;
   tally_t *tallies; size_t ntal, talcap;
   ktally_t *kt; size_t nkt, ktcap;
+  int keep_ivals;
+  ival_t *iv; size_t niv, ivcap;
 } oracle;
 
 #define GROW(arr, n, cap) do { if ((n) == (cap)) { (cap) = (cap) ? (cap) * 2 : 64; \
@@ -114,7 +124,7 @@ oracle *oracle_new(int format, uint32_t n_fns, uint32_t n_kernel_ids, uint32_t m
 void oracle_free(oracle *o) {
   if (!o) return;
   for (size_t i = 0; i < o->nt; i++) free(o->threads[i].stk);
-  free(o->threads); free(o->streams); free(o->tallies); free(o->kt); free(o->has_size);
+  free(o->threads); free(o->streams); free(o->tallies); free(o->kt); free(o->has_size); free(o->iv);
   map_free(&o->smap); map_free(&o->tmap); map_free(&o->tally_map); map_free(&o->kmap);
   free(o);
 }
@@ -250,6 +260,15 @@ int oracle_submit(oracle *o, uint32_t trace, uint32_t host, uint32_t pid,
       if (e.child <= incl) self = incl - e.child;
       else { self = 0; st->st[S_SELFUNDER]++; }
       tally_add(o, sid, tid, fn, incl, self, e.bytes);
+      if (o->keep_ivals) {
+        GROW(o->iv, o->niv, o->ivcap);
+        ival_t *v = &o->iv[o->niv++];
+        v->stream = sid; v->tid = tid; v->fn = fn; v->depth = (uint32_t)t->h + 1;
+        v->start = e.ts; v->end = ts;
+        v->pstart = t->h ? t->stk[t->h - 1].ts : 0;
+        v->pfn = t->h ? t->stk[t->h - 1].fn : 0xFFFFFFFFu;
+        v->pad = 0;
+      }
       if (t->h) t->stk[t->h - 1].child += incl;
     }
   }
@@ -376,3 +395,41 @@ void oracle_stats(oracle *o, uint32_t trace_filter, uint64_t *out) {
 }
 
 uint64_t oracle_row_size(void) { return sizeof(orow_t); }
+
+/* ----------------------------------------------------------- intervals */
+void oracle_keep_intervals(oracle *o, int on) { o->keep_ivals = on; }
+
+typedef struct {
+  uint32_t trace, host, pid, tid;
+  uint32_t fn, depth;
+  uint64_t start, end, parent_start;
+  uint32_t parent_fn, pad;
+} oival_t;
+
+static int ival_cmp(const void *x, const void *y) {
+  const oival_t *a = (const oival_t *)x, *b = (const oival_t *)y;
+#define C(f) if (a->f != b->f) return a->f < b->f ? -1 : 1;
+  C(trace) C(host) C(pid) C(tid) C(start) C(depth) C(end) C(fn) C(parent_start) C(parent_fn)
+#undef C
+  return 0;
+}
+
+/* Every kept interval, sorted by (trace, host, pid, tid, start, depth, end,
+ * fn, parent).  Returns the count; writes at most `cap`. */
+size_t oracle_intervals(oracle *o, oival_t *out, size_t cap) {
+  oival_t *v = (oival_t *)calloc(o->niv ? o->niv : 1, sizeof(oival_t));
+  for (size_t i = 0; i < o->niv; i++) {
+    const ival_t *a = &o->iv[i];
+    const stream_t *s = &o->streams[a->stream];
+    v[i].trace = s->trace; v[i].host = s->host; v[i].pid = s->pid; v[i].tid = a->tid;
+    v[i].fn = a->fn; v[i].depth = a->depth; v[i].start = a->start; v[i].end = a->end;
+    v[i].parent_start = a->pstart; v[i].parent_fn = a->pfn;
+  }
+  if (o->niv) qsort(v, o->niv, sizeof(oival_t), ival_cmp);
+  size_t w = o->niv < cap ? o->niv : cap;
+  if (out && w) memcpy(out, v, w * sizeof(oival_t));
+  free(v);
+  return o->niv;
+}
+
+uint64_t oracle_interval_size(void) { return sizeof(oival_t); }

@@ -87,6 +87,14 @@ struct CState { uint32_t h; uint32_t flags; uint64_t last_ts; };
 enum : uint32_t { CS_HAS_TS = 1u, CS_OVERFLOW = 2u };
 struct Frame { uint64_t ts, child, bytes; uint32_t fn, pad; };
 
+// Merge input (thapi_tally_merge): one thread of an exported aggregate with
+// its stream mapped to this handle's index, its open calls (frames
+// [frame0, frame0 + h) of the frame array), flags and last timestamp; one
+// tally row of a blob thread; one kernel row of a mapped stream.
+struct MThread { uint32_t stream, tid, h, flags; uint64_t last_ts; uint32_t frame0, pad; };
+struct MRow { uint32_t thread, fn; Tally v; };
+struct MKRow { uint32_t stream, kid; KTally v; };
+
 // Device tables of one handle.
 struct Tables {
   uint64_t *gkeys;      // thread map keys: (stream << 32) | tid, EMPTY64 = free
@@ -124,6 +132,65 @@ __host__ __device__ inline uint32_t hash32(uint32_t x) {
 __host__ __device__ inline uint64_t hash64(uint64_t x) {
   x ^= x >> 33; x *= 0xff51afd7ed558ccdull; x ^= x >> 33; x *= 0xc4ceb9fe1a85ec53ull; x ^= x >> 33;
   return x;
+}
+
+// Resolves (stream, tid) to its global thread slot, inserting it on first
+// sight.  Lock-free open addressing in two phases: every lane first inserts
+// or finds its key, and an inserting lane publishes the slot id before the
+// probe loop ends; only after the whole wave has left that loop does a lane
+// that found a key inserted elsewhere wait for its slot id.  (Waiting inside
+// the probe loop could deadlock: a lane of one wave spinning on a key whose
+// inserter is a masked-off lane of another spinning wave, and vice versa.)
+__device__ inline uint32_t resolve_gslot(const Tables &tb, uint32_t stream, uint32_t tid) {
+  const uint64_t key = ((uint64_t)stream << 32) | tid;
+  uint32_t h = (uint32_t)hash64(key) & tb.gmask;
+  uint32_t result = GV_INVALID;
+  bool wait = false;
+  for (uint32_t probe = 0; probe <= tb.gmask; probe++) {
+    const uint64_t old = atomicCAS((unsigned long long *)&tb.gkeys[h], (unsigned long long)EMPTY64,
+                                   (unsigned long long)key);
+    if (old == EMPTY64) {
+      uint32_t g = atomicAdd(tb.n_gslots, 1u);
+      if (g >= tb.max_threads) {
+        atomicOr(tb.err, ERR_CAPACITY);
+        g = GV_INVALID;
+      } else {
+        tb.th_stream[g] = stream;
+        tb.th_tid[g] = tid;
+      }
+      __hip_atomic_store(&tb.gvals[h], g, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      result = g;
+      break;
+    }
+    if (old == key) { wait = true; break; }
+    h = (h + 1) & tb.gmask;
+  }
+  if (wait) {
+    uint32_t v;
+    while ((v = __hip_atomic_load(&tb.gvals[h], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) == GV_PENDING)
+      __builtin_amdgcn_s_sleep(2);
+    result = v;
+  } else if (result == GV_INVALID) {
+    atomicOr(tb.err, ERR_CAPACITY);
+  }
+  return result;
+}
+
+// The global thread slot of (stream, tid) if the thread map holds it (and
+// its slot id is published), else GV_INVALID; inserts nothing.
+__device__ inline uint32_t lookup_gslot(const Tables &tb, uint32_t stream, uint32_t tid) {
+  const uint64_t key = ((uint64_t)stream << 32) | tid;
+  uint32_t h = (uint32_t)hash64(key) & tb.gmask;
+  for (uint32_t probe = 0; probe <= tb.gmask; probe++) {
+    const uint64_t k = __hip_atomic_load(&tb.gkeys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (k == EMPTY64) return GV_INVALID;
+    if (k == key) {
+      const uint32_t v = __hip_atomic_load(&tb.gvals[h], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+      return v == GV_PENDING ? GV_INVALID : v;
+    }
+    h = (h + 1) & tb.gmask;
+  }
+  return GV_INVALID;
 }
 
 }  // namespace tt

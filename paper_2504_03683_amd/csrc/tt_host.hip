@@ -19,6 +19,7 @@
 #include <map>
 #include <mutex>
 #include <new>
+#include <set>
 #include <chrono>
 #include <string>
 #include <thread>
@@ -69,6 +70,7 @@ using namespace tt;
 
 namespace {
 
+
 struct DevBuf {
   void *p = nullptr;
   size_t cap = 0;
@@ -100,10 +102,68 @@ struct Chunk {
   void *owned;       // staged device copy (host input), freed after its flush
   uint64_t owned_bytes;
   bool in_arena;     // service mode: the staged copy lives in the device arena
-  bool ready;        // service mode: the staged copy is complete
+  bool in_ring;      // service mode: the bytes went through the pinned staging ring
+  bool ready;        // service mode: the copy to the device is enqueued (or complete)
+  int ev;            // service mode: event recorded after the copy (index into the pool), or -1
 };
 
+// First-in first-out allocator over [0, cap): allocations are released in the
+// order they were made, so free space is the one or two gaps around the live
+// span [tail, head).  Used for the device arena and the pinned staging ring
+// of the streaming form (chunks are tallied, and so released, in ticket order).
+struct Fifo {
+  uint64_t cap = 0, head = 0, tail = 0;
+  std::deque<std::pair<uint64_t, uint64_t>> live;   // [offset, end) of live allocations, in order
+  bool fit(uint64_t n, uint64_t *at) const {
+    if (live.empty()) { if (n > cap) return false; *at = 0; return true; }
+    if (head > tail) {
+      if (cap - head >= n) { *at = head; return true; }
+      if (tail > n) { *at = 0; return true; }   // wrap; the end of the buffer stays unused
+      return false;
+    }
+    if (tail - head > n) { *at = head; return true; }
+    return false;
+  }
+  void take(uint64_t at, uint64_t n) {
+    if (live.empty()) tail = at;
+    head = at + n;
+    live.push_back({at, at + n});
+  }
+  void release_front() {
+    if (live.empty()) return;
+    live.pop_front();
+    if (live.empty()) head = tail = 0;
+    else tail = live.front().first;
+  }
+};
+constexpr int N_COPY_STREAMS = 4;
+constexpr uint64_t RING_MAX = 512ull << 20;   // pinned staging ring of the streaming form
+
 using SKey = std::array<uint32_t, 3>;
+
+// The device work of one flush: segments (one per chunk), ranges (a stream's
+// records cut into pieces of about equal length), per-stream spans of
+// consecutive ranges, and the work-list order (longest range first).
+struct Plan {
+  std::vector<Seg> segs;
+  std::vector<Range> ranges;
+  std::vector<uint32_t> segfirst, spans, order;
+  uint64_t total = 0;
+};
+
+// Device addresses of one flush's work list (packed in one upload) and of its
+// range summaries: in the handle's grow-only buffers, or in the static
+// scratch array given to process_batch.
+struct FlushBufs {
+  Seg *segs = nullptr;
+  Range *ranges = nullptr;
+  uint32_t *order = nullptr, *segfirst = nullptr, *spans = nullptr, *qhead = nullptr;
+  RHdr *rhdr = nullptr;
+  UItem *ru = nullptr;
+  OItem *ro = nullptr;
+  uint32_t *rnslots = nullptr;
+  uint64_t *paylen = nullptr;
+};
 
 enum { TM_PREPASS = 0, TM_RANGE, TM_COMBINE, TM_FINAL, TM_READOUT, TM_N };
 
@@ -139,7 +199,7 @@ struct thapi_tally {
 
   DevBuf rhdr, ru, ro, rnslots, paylen;
   DevBuf plan_pack;                                   // the work list, uploaded in one copy
-  DevView segs, ranges, order, qhead, segfirst, spans;
+  FlushBufs fb;                                       // the current flush's device addresses
   DevBuf keys, vals, keys2, vals2, gbeg, gend, cnt, off, rows, tstats;
   DevBuf read_pack;                                   // the readout's host tables, uploaded in one copy
   DevView rank_key, trace_span, stream_rank, rstream;
@@ -164,10 +224,14 @@ struct thapi_tally {
   std::thread worker;
   bool stop = false;
   std::condition_variable work_cv;                    // worker: chunks ready or stop
-  hipStream_t cst = nullptr;                          // host -> device copies
-  uint8_t *arena = nullptr;
-  uint64_t a_head = 0, a_tail = 0;
-  std::deque<std::pair<uint64_t, uint64_t>> a_live;   // [offset, end) of live allocations, in order
+  bool worker_running = false;
+  hipStream_t cst[N_COPY_STREAMS] = {};               // host -> device copies (chunk k on stream k % N)
+  uint8_t *arena = nullptr;                           // device arena, capacity device_budget_bytes
+  Fifo afifo;
+  uint8_t *ring = nullptr;                            // pinned staging ring, min(budget, RING_MAX) bytes
+  Fifo rfifo;
+  std::vector<hipEvent_t> ev_pool;                    // copy-completion events
+  std::vector<int> ev_free;
   uint64_t done_upto = 0;                             // every ticket <= this one is tallied
   std::vector<uint64_t> done_ns;                      // [ticket] CLOCK_MONOTONIC ns of its batch's completion
   uint64_t n_batches = 0, n_batch_chunks = 0, max_batch_chunks = 0, bytes_admitted = 0;
@@ -175,6 +239,11 @@ struct thapi_tally {
   // the rows of the last read that did not fit its buffer (the size query of
   // a two-call read), kept until the tallies or streams change
   std::atomic<uint64_t> gen{0};       // bumped by submit, flush and reset
+  // export: the blob of a size query, kept for the second call
+  std::vector<uint8_t> exp_blob;
+  bool exp_valid = false;
+  uint64_t exp_gen = 0;
+  DevBuf merge_buf;
   bool rc_valid = false;
   uint64_t rc_gen = 0;
   uint32_t rc_scope = 0, rc_trace = 0;
@@ -218,7 +287,8 @@ void free_all(thapi_tally *t) {
                 t->d_cstate, t->d_cstack, t->d_sstats, t->d_err, t->d_hs};
   for (void *p : ps) if (p) hipFree(p);
   DevBuf *bs[] = {&t->plan_pack, &t->rhdr, &t->ru, &t->ro, &t->rnslots, &t->paylen, &t->keys, &t->vals, &t->keys2,
-                  &t->vals2, &t->gbeg, &t->gend, &t->cnt, &t->off, &t->read_pack, &t->rows, &t->tstats};
+                  &t->vals2, &t->gbeg, &t->gend, &t->cnt, &t->off, &t->read_pack, &t->rows, &t->tstats,
+                  &t->merge_buf};
   for (DevBuf *b : bs) b->release();
   for (auto &c : t->queue) if (c.owned) hipFree(c.owned);
   t->queue.clear();
@@ -227,7 +297,10 @@ void free_all(thapi_tally *t) {
   for (auto &e : t->ev) if (e) hipEventDestroy(e);
   if (t->gexec) { hipGraphExecDestroy(t->gexec); t->gexec = nullptr; }
   if (t->arena) { hipFree(t->arena); t->arena = nullptr; }
-  if (t->cst) { hipStreamDestroy(t->cst); t->cst = nullptr; }
+  if (t->ring) { hipHostFree(t->ring); t->ring = nullptr; }
+  for (auto &s : t->cst) if (s) { hipStreamDestroy(s); s = nullptr; }
+  for (auto &e : t->ev_pool) if (e) hipEventDestroy(e);
+  t->ev_pool.clear();
   if (t->own_stream && t->st) hipStreamDestroy(t->st);
 }
 
@@ -314,6 +387,7 @@ const char *thapi_tally_strerror(int code) {
 namespace {
 void load_tune_cache(thapi_tally *t);
 void service_loop(thapi_tally *t);
+hipError_t grow_plan_staging(thapi_tally *t, size_t bytes);
 }  // namespace
 
 int thapi_tally_open(const thapi_tally_config *cfg, thapi_tally **out) {
@@ -323,6 +397,9 @@ int thapi_tally_open(const thapi_tally_config *cfg, thapi_tally **out) {
   if (cfg->n_fns < 1 || cfg->n_fns > 65536 || cfg->n_kernel_ids > 65536) return THAPI_E_INVAL;
   if (cfg->max_depth > THAPI_MAX_DEPTH_LIMIT || cfg->reserved) return THAPI_E_INVAL;
   if (cfg->max_threads > (1u << 30) || cfg->max_streams > (1u << 24)) return THAPI_E_INVAL;
+  // the streaming form's batches differ in size from one to the next, so a
+  // captured graph would be rebuilt for nearly every batch: not offered
+  if ((cfg->flags & THAPI_SERVICE) && (cfg->flags & THAPI_GRAPH)) return THAPI_E_INVAL;
   thapi_tally *t = new (std::nothrow) thapi_tally();
   if (!t) return THAPI_E_NOMEM;
   t->cfg = *cfg;
@@ -399,49 +476,63 @@ int thapi_tally_open(const thapi_tally_config *cfg, thapi_tally **out) {
     if (t->arch.empty()) t->arch = "gpu";
   }
   load_tune_cache(t);
+  // pinned staging for the work list and for counters read back, sized up
+  // front
+  if (grow_plan_staging(t, 1u << 20) != hipSuccess ||
+      ensure_pinned(t, 64 + (24 + 8ull * ST_N) * c.max_streams) != hipSuccess)
+    return bail(THAPI_E_NOMEM);
   if (prepare_range_kernels((uint32_t)(t->lds_limit - 256)) != hipSuccess) return bail(THAPI_E_DEVICE);
   if (prepare_combine_kernel() != hipSuccess) return bail(THAPI_E_DEVICE);
   if (c.flags & THAPI_SERVICE) {
-    if (hipStreamCreateWithFlags(&t->cst, hipStreamNonBlocking) != hipSuccess) return bail(THAPI_E_DEVICE);
-    if (!(c.flags & THAPI_DEVICE_INPUT) && hipMalloc((void **)&t->arena, c.device_budget_bytes) != hipSuccess) {
-      hipGetLastError();
-      return bail(THAPI_E_NOMEM);
+    for (auto &s : t->cst)
+      if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return bail(THAPI_E_DEVICE);
+    if (!(c.flags & THAPI_DEVICE_INPUT)) {
+      if (hipMalloc((void **)&t->arena, c.device_budget_bytes) != hipSuccess) {
+        hipGetLastError();
+        return bail(THAPI_E_NOMEM);
+      }
+      t->afifo.cap = c.device_budget_bytes;
+      const uint64_t rcap = std::min<uint64_t>(c.device_budget_bytes, RING_MAX);
+      if (hipHostMalloc((void **)&t->ring, rcap, hipHostMallocDefault) != hipSuccess) {
+        hipGetLastError();
+        return bail(THAPI_E_NOMEM);
+      }
+      t->rfifo.cap = rcap;
     }
-    t->worker = std::thread(service_loop, t);
   }
   if (init_tables(t) != hipSuccess) return bail(THAPI_E_DEVICE);
+  if (c.flags & THAPI_SERVICE) {
+    t->worker_running = true;
+    t->worker = std::thread(service_loop, t);
+  }
   *out = t;
   return THAPI_OK;
 }
 
 namespace {
 
-// Service-mode arena: allocations are released in the order they were made
-// (the worker tallies queued chunks in ticket order), so free space is the
-// one or two gaps around the live span [a_tail, a_head).  Caller holds t->mu.
-bool arena_alloc(thapi_tally *t, uint64_t n, uint64_t *off) {
-  const uint64_t cap = t->cfg.device_budget_bytes;
-  if (t->a_live.empty()) t->a_head = t->a_tail = 0;
-  uint64_t at;
-  if (t->a_live.empty() || t->a_head > t->a_tail) {
-    if (cap - t->a_head >= n) at = t->a_head;
-    else if (!t->a_live.empty() && t->a_tail > n) at = 0;  // wrap; the end of the buffer stays unused
-    else return false;
-  } else {
-    if (t->a_tail - t->a_head > n) at = t->a_head;
-    else return false;
-  }
-  t->a_head = at + n;
-  t->a_live.push_back({at, at + n});
-  *off = at;
-  return true;
+// A copy-completion event from the pool (caller holds t->mu); -1 if none
+// could be created.
+int event_get(thapi_tally *t) {
+  if (!t->ev_free.empty()) { const int k = t->ev_free.back(); t->ev_free.pop_back(); return k; }
+  hipEvent_t e = nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) { hipGetLastError(); return -1; }
+  t->ev_pool.push_back(e);
+  return (int)t->ev_pool.size() - 1;
 }
 
-void arena_release_front(thapi_tally *t) {
-  if (t->a_live.empty()) return;
-  t->a_live.pop_front();
-  if (t->a_live.empty()) t->a_head = t->a_tail = 0;
-  else t->a_tail = t->a_live.front().first;
+// Gives a staged chunk's arena, ring and event back (caller holds t->mu;
+// chunks are released in ticket order).
+void release_chunk(thapi_tally *t, const Chunk &c) {
+  if (c.in_arena) {
+    t->afifo.release_front();
+    if (c.in_ring) t->rfifo.release_front();
+    if (c.ev >= 0) t->ev_free.push_back(c.ev);
+    t->budget_used -= c.owned_bytes;
+  } else if (c.owned) {
+    hipFree(c.owned);
+    t->budget_used -= c.owned_bytes;
+  }
 }
 
 uint64_t now_ns() {
@@ -495,6 +586,7 @@ int thapi_tally_submit(thapi_tally *t, const thapi_stream_key *key, const void *
     sidx = it->second;
   }
   Chunk c{};
+  c.ev = -1;
   c.stream = sidx;
   c.n_rec = n_rec;
   c.pay_bytes = payload_bytes;
@@ -504,13 +596,20 @@ int thapi_tally_submit(thapi_tally *t, const thapi_stream_key *key, const void *
     c.rec = (const uint8_t *)records;
     c.pay = (const uint8_t *)payload;
   } else if (n_rec && service) {
-    // admission: wait for room in the device arena (FIFO reuse), queue the
-    // chunk in ticket order at once, copy outside the lock, then mark it ready
+    // admission: wait for room in the device arena and the pinned staging
+    // ring (both FIFO), queue the chunk in ticket order at once, then -- outside
+    // the lock -- copy the caller's bytes into the ring and enqueue the ring ->
+    // arena copy on one of the copy streams with an event after it.  The
+    // worker's launch waits for that event on the device, so a submit never
+    // waits for its own DMA; the caller's buffer is free when submit returns.
     const uint64_t rec_al = (record_bytes + 255) / 256 * 256;
     const uint64_t bytes = rec_al + (payload_bytes + 255) / 256 * 256;
     if (bytes > t->cfg.device_budget_bytes) return THAPI_E_NOMEM;
-    uint64_t off = 0;
-    while (!arena_alloc(t, bytes, &off)) {
+    const bool via_ring = bytes <= t->rfifo.cap;   // (larger chunks: one synchronous pageable copy)
+    uint64_t off = 0, roff = 0;
+    for (;;) {
+      if (t->failed || t->stop) return THAPI_E_STATE;
+      if (t->afifo.fit(bytes, &off) && (!via_ring || t->rfifo.fit(bytes, &roff))) break;
       if (t->cfg.flags & THAPI_DROP_ON_FULL) {
         t->dropped[sidx] += n_rec;
         if (ticket_out) *ticket_out = 0;
@@ -518,29 +617,44 @@ int thapi_tally_submit(thapi_tally *t, const thapi_stream_key *key, const void *
       }
       if (t->cfg.flags & THAPI_NONBLOCKING) return THAPI_E_AGAIN;
       t->cv.wait(lk);
-      if (t->failed || t->stop) return THAPI_E_STATE;
     }
+    const int ev = via_ring ? event_get(t) : -1;
+    if (via_ring && ev < 0) return THAPI_E_DEVICE;
+    t->afifo.take(off, bytes);
+    if (via_ring) t->rfifo.take(roff, bytes);
     t->budget_used += bytes;
     t->bytes_admitted += record_bytes + payload_bytes;
     c.in_arena = true;
+    c.in_ring = via_ring;
     c.owned_bytes = bytes;
     c.rec = t->arena + off;
     c.pay = payload_bytes ? t->arena + off + rec_al : nullptr;
     c.ready = false;
+    c.ev = ev;
     c.ticket = t->next_ticket++;
     const uint64_t ticket = c.ticket;
+    hipStream_t cs = t->cst[ticket % N_COPY_STREAMS];
     t->queue.push_back(c);
     lk.unlock();
-    hipError_t e = hipMemcpyAsync(t->arena + off, records, record_bytes, hipMemcpyHostToDevice, t->cst);
-    if (e == hipSuccess && payload_bytes)
-      e = hipMemcpyAsync(t->arena + off + rec_al, payload, payload_bytes, hipMemcpyHostToDevice, t->cst);
-    if (e == hipSuccess) e = hipStreamSynchronize(t->cst);
+    hipError_t e;
+    if (via_ring) {
+      uint8_t *h = t->ring + roff;
+      memcpy(h, records, record_bytes);
+      if (payload_bytes) memcpy(h + rec_al, payload, payload_bytes);
+      e = hipMemcpyAsync(t->arena + off, h, rec_al + payload_bytes, hipMemcpyHostToDevice, cs);
+      if (e == hipSuccess) e = hipEventRecord(t->ev_pool[ev], cs);
+    } else {
+      e = hipMemcpyAsync(t->arena + off, records, record_bytes, hipMemcpyHostToDevice, cs);
+      if (e == hipSuccess && payload_bytes)
+        e = hipMemcpyAsync(t->arena + off + rec_al, payload, payload_bytes, hipMemcpyHostToDevice, cs);
+      if (e == hipSuccess) e = hipStreamSynchronize(cs);
+    }
     lk.lock();
     for (auto it = t->queue.rbegin(); it != t->queue.rend(); ++it)
       if (it->ticket == ticket) { it->ready = true; break; }
+    t->cv.notify_all();
     if (e != hipSuccess) {
       t->failed = THAPI_E_DEVICE;
-      t->cv.notify_all();
       t->work_cv.notify_all();
       return THAPI_E_DEVICE;
     }
@@ -588,15 +702,6 @@ int thapi_tally_submit(thapi_tally *t, const thapi_stream_key *key, const void *
 
 namespace {
 
-// The device work of one flush: segments (one per chunk), ranges (a stream's
-// records cut into pieces of about equal length), per-stream spans of
-// consecutive ranges, and the work-list order (longest range first).
-struct Plan {
-  std::vector<Seg> segs;
-  std::vector<Range> ranges;
-  std::vector<uint32_t> segfirst, spans, order;
-  uint64_t total = 0;
-};
 
 void plan_work(const thapi_tally *t, const std::vector<Chunk> &work, const Shape &sh, Plan &pl) {
   pl = Plan();
@@ -656,55 +761,112 @@ void plan_work(const thapi_tally *t, const std::vector<Chunk> &work, const Shape
                    [&](uint32_t a, uint32_t b) { return pl.ranges[a].n > pl.ranges[b].n; });
 }
 
-// Host -> device upload of n host arrays in one asynchronous copy: they are
-// packed at 256-byte aligned offsets (at least 256 bytes each) in the pinned
-// staging buffer and land at the same offsets of `pack`; views[i] receives
-// the device address of array i.  The staging is reused by the next call
-// only, which comes after the work that the copy feeds has completed
-// (flushes and reads each end with a synchronisation).
-hipError_t stage_h2d(thapi_tally *t, DevBuf &pack, DevView *const *views, const void *const *src,
-                     const size_t *bytes, int n) {
-  size_t tot = 0, used = 0;
+// Bytes of a packed upload of n arrays: 256-byte aligned parts of at least
+// 256 bytes each.
+size_t pack_bytes(const size_t *bytes, int n) {
+  size_t tot = 0;
   for (int i = 0; i < n; i++) tot += std::max<size_t>((bytes[i] + 255) & ~(size_t)255, 256);
-  hipError_t e = pack.ensure(tot);
-  if (e != hipSuccess) return e;
-  if (tot > t->h_plan_cap) {
-    if (t->h_plan) hipHostFree(t->h_plan);
-    t->h_plan = nullptr;
-    t->h_plan_cap = 0;
-    const size_t want = std::max<size_t>(tot, 1 << 16);
-    hipError_t e = hipHostMalloc(&t->h_plan, want, hipHostMallocDefault);
-    if (e != hipSuccess) return e;
-    t->h_plan_cap = want;
-  }
-  size_t o = 0;
+  return tot;
+}
+
+// Grows the pinned staging of packed uploads to `bytes` at least.
+hipError_t grow_plan_staging(thapi_tally *t, size_t bytes) {
+  if (bytes <= t->h_plan_cap) return hipSuccess;
+  if (t->h_plan) hipHostFree(t->h_plan);
+  t->h_plan = nullptr;
+  t->h_plan_cap = 0;
+  const size_t want = std::max<size_t>(bytes, 1 << 16);
+  hipError_t e = hipHostMalloc(&t->h_plan, want, hipHostMallocDefault);
+  if (e == hipSuccess) t->h_plan_cap = want;
+  return e;
+}
+
+// Host -> device upload of n host arrays in one asynchronous copy: they are
+// packed at 256-byte aligned offsets in the pinned staging buffer (which must
+// hold pack_bytes() already) and land at the same offsets of `dev`; *views[i]
+// receives the device address of array i.  The staging is reused by the next
+// call only, which comes after the work that the copy feeds has completed
+// (flushes and reads each end with a synchronisation).
+hipError_t stage_h2d(thapi_tally *t, uint8_t *dev, void **const *views, const void *const *src,
+                     const size_t *bytes, int n) {
+  size_t o = 0, used = 0;
   for (int i = 0; i < n; i++) {
     if (bytes[i]) {
       memcpy((uint8_t *)t->h_plan + o, src[i], bytes[i]);
       used = o + bytes[i];
     }
-    views[i]->p = (uint8_t *)pack.p + o;
+    *views[i] = dev + o;
     o += std::max<size_t>((bytes[i] + 255) & ~(size_t)255, 256);
   }
-  return used ? hipMemcpyAsync(pack.p, t->h_plan, used, hipMemcpyHostToDevice, t->st) : hipSuccess;
+  return used ? hipMemcpyAsync(dev, t->h_plan, used, hipMemcpyHostToDevice, t->st) : hipSuccess;
 }
 
-hipError_t upload_plan(thapi_tally *t, const Plan &pl) {
-  const uint32_t nR = (uint32_t)pl.ranges.size(), nS = (uint32_t)pl.segs.size();
-  const uint32_t D = t->cfg.max_depth;
+// Sizes of one flush's device buffers: the packed work list and the range
+// summaries (RHdr per range and slot, U and O items per range, slot and level).
+struct PlanSizes {
+  size_t part[6];
+  size_t pack, rhdr, ru, ro, rnslots, paylen;
+  size_t total() const {
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    return al(pack) + al(rhdr) + al(ru) + al(ro) + al(rnslots) + al(paylen);
+  }
+};
+
+PlanSizes plan_sizes(const thapi_tally *t, const Plan &pl) {
+  const size_t nR = pl.ranges.size(), nS = pl.segs.size();
+  const size_t D = t->cfg.max_depth;
+  PlanSizes z{};
+  const size_t part[6] = {sizeof(Seg) * nS, sizeof(Range) * nR, 4 * nR, 4 * (nS + 1), 4 * pl.spans.size(), 4};
+  for (int i = 0; i < 6; i++) z.part[i] = part[i];
+  z.pack = pack_bytes(part, 6);
+  z.rhdr = sizeof(RHdr) * nR * S_MAX;
+  z.ru = sizeof(UItem) * nR * S_MAX * D;
+  z.ro = sizeof(OItem) * nR * S_MAX * D;
+  z.rnslots = 4 * std::max<size_t>(nR, 1);
+  z.paylen = 8 * std::max<size_t>(nR, 1);
+  return z;
+}
+
+// Uploads the work list and points t->fb at the flush's buffers: the
+// handle's grow-only buffers, or -- with `scratch` -- consecutive 256-byte
+// aligned parts of that device array, which the caller has checked is large
+// enough (as it has the pinned staging).
+hipError_t upload_plan(thapi_tally *t, const Plan &pl, uint8_t *scratch = nullptr) {
+  const PlanSizes z = plan_sizes(t, pl);
   hipError_t e;
 #define UPCHK(x) do { if ((e = (x)) != hipSuccess) return e; } while (0)
-  UPCHK(t->rhdr.ensure(sizeof(RHdr) * (size_t)nR * S_MAX));
-  UPCHK(t->ru.ensure(sizeof(UItem) * (size_t)nR * S_MAX * D));
-  UPCHK(t->ro.ensure(sizeof(OItem) * (size_t)nR * S_MAX * D));
-  UPCHK(t->rnslots.ensure(4ull * nR));
-  UPCHK(t->paylen.ensure(8ull * nR));
+  uint8_t *pack;
+  FlushBufs &fb = t->fb;
+  if (scratch) {
+    size_t o = 0;
+    auto carve = [&](size_t bytes) { uint8_t *p = scratch + o; o += (bytes + 255) & ~(size_t)255; return p; };
+    pack = carve(z.pack);
+    fb.rhdr = (RHdr *)carve(z.rhdr);
+    fb.ru = (UItem *)carve(z.ru);
+    fb.ro = (OItem *)carve(z.ro);
+    fb.rnslots = (uint32_t *)carve(z.rnslots);
+    fb.paylen = (uint64_t *)carve(z.paylen);
+  } else {
+    UPCHK(t->rhdr.ensure(z.rhdr));
+    UPCHK(t->ru.ensure(z.ru));
+    UPCHK(t->ro.ensure(z.ro));
+    UPCHK(t->rnslots.ensure(z.rnslots));
+    UPCHK(t->paylen.ensure(z.paylen));
+    UPCHK(t->plan_pack.ensure(z.pack));
+    UPCHK(grow_plan_staging(t, z.pack));
+    pack = t->plan_pack.as<uint8_t>();
+    fb.rhdr = t->rhdr.as<RHdr>();
+    fb.ru = t->ru.as<UItem>();
+    fb.ro = t->ro.as<OItem>();
+    fb.rnslots = t->rnslots.as<uint32_t>();
+    fb.paylen = t->paylen.as<uint64_t>();
+  }
   // the work queue's head (zero) travels with the work list
   static const uint32_t zero = 0;
-  const size_t part[6] = {sizeof(Seg) * nS, sizeof(Range) * nR, 4ull * nR, 4ull * (nS + 1), 4ull * pl.spans.size(), 4};
   const void *src[6] = {pl.segs.data(), pl.ranges.data(), pl.order.data(), pl.segfirst.data(), pl.spans.data(), &zero};
-  DevView *dst[6] = {&t->segs, &t->ranges, &t->order, &t->segfirst, &t->spans, &t->qhead};
-  UPCHK(stage_h2d(t, t->plan_pack, dst, src, part, 6));
+  void **dst[6] = {(void **)&fb.segs, (void **)&fb.ranges, (void **)&fb.order, (void **)&fb.segfirst,
+                   (void **)&fb.spans, (void **)&fb.qhead};
+  UPCHK(stage_h2d(t, pack, dst, src, z.part, 6));
 #undef UPCHK
   return hipSuccess;
 }
@@ -714,6 +876,7 @@ hipError_t upload_plan(thapi_tally *t, const Plan &pl) {
 hipError_t launch_pipeline(thapi_tally *t, const Plan &pl, const Shape &sh, bool final, bool timed) {
   const uint32_t nR = (uint32_t)pl.ranges.size(), nS = (uint32_t)pl.segs.size();
   const uint32_t nSp = (uint32_t)(pl.spans.size() / 3);
+  const FlushBufs &fb = t->fb;
   hipError_t e;
 #define LPCHK(x) do { if ((e = (x)) != hipSuccess) return e; } while (0)
 #define TB(k) do { if (timed) LPCHK(timed_begin(t, k)); } while (0)
@@ -722,18 +885,15 @@ hipError_t launch_pipeline(thapi_tally *t, const Plan &pl, const Shape &sh, bool
   if (nR) {
     if (t->cfg.format == THAPI_FMT_VAR16) {
       TB(TM_PREPASS);
-      LPCHK(launch_paylen(t->segs.as<Seg>(), t->ranges.as<Range>(), nR, t->segfirst.as<uint32_t>(), nS,
-                          t->paylen.as<uint64_t>(), t->tb.err, t->st));
+      LPCHK(launch_paylen(fb.segs, fb.ranges, nR, fb.segfirst, nS, fb.paylen, t->tb.err, t->st));
       TE(TM_PREPASS);
     }
     TB(TM_RANGE);
-    LPCHK(launch_range((int)t->cfg.format, sh.T, t->segs.as<Seg>(), t->ranges.as<Range>(), t->order.as<uint32_t>(),
-                       nR, t->qhead.as<uint32_t>(), (uint32_t)t->n_cu, t->tb, sh, t->rhdr.as<RHdr>(),
-                       t->ru.as<UItem>(), t->ro.as<OItem>(), t->rnslots.as<uint32_t>(), t->st));
+    LPCHK(launch_range((int)t->cfg.format, sh.T, fb.segs, fb.ranges, fb.order, nR, fb.qhead, (uint32_t)t->n_cu, t->tb,
+                       sh, fb.rhdr, fb.ru, fb.ro, fb.rnslots, t->st));
     TE(TM_RANGE);
     TB(TM_COMBINE);
-    LPCHK(launch_combine(t->spans.as<uint32_t>(), nSp, t->rhdr.as<RHdr>(), t->ru.as<UItem>(), t->ro.as<OItem>(),
-                         t->rnslots.as<uint32_t>(), t->tb, t->st));
+    LPCHK(launch_combine(fb.spans, nSp, fb.rhdr, fb.ru, fb.ro, fb.rnslots, t->tb, t->st));
     TE(TM_COMBINE);
   }
   if (final) {
@@ -753,16 +913,14 @@ hipError_t run_pipeline(thapi_tally *t, const Plan &pl, const Shape &sh, bool fi
   const bool prof = (t->cfg.flags & THAPI_PROFILE) != 0;
   if (!(t->cfg.flags & THAPI_GRAPH)) return launch_pipeline(t, pl, sh, final, prof);
   const std::array<uint64_t, 16> sig = {pl.ranges.size(), pl.segs.size(), pl.spans.size(), sh.T, sh.E,
-                                        sh.rpc | ((uint64_t)sh.pipe << 32), final ? 1u : 0u, (uint64_t)(uintptr_t)t->segs.p,
-                                        (uint64_t)(uintptr_t)t->ranges.p, (uint64_t)(uintptr_t)t->order.p,
-                                        (uint64_t)(uintptr_t)t->rhdr.p, (uint64_t)(uintptr_t)t->ru.p,
-                                        (uint64_t)(uintptr_t)t->ro.p, (uint64_t)(uintptr_t)t->rnslots.p,
-                                        (uint64_t)(uintptr_t)t->spans.p, (uint64_t)(uintptr_t)t->paylen.p};
+                                        sh.rpc | ((uint64_t)sh.pipe << 32), final ? 1u : 0u, (uint64_t)(uintptr_t)t->fb.segs,
+                                        (uint64_t)(uintptr_t)t->fb.ranges, (uint64_t)(uintptr_t)t->fb.order,
+                                        (uint64_t)(uintptr_t)t->fb.rhdr, (uint64_t)(uintptr_t)t->fb.ru,
+                                        (uint64_t)(uintptr_t)t->fb.ro, (uint64_t)(uintptr_t)t->fb.rnslots,
+                                        (uint64_t)(uintptr_t)t->fb.spans, (uint64_t)(uintptr_t)t->fb.paylen};
   hipError_t e;
   if (!t->gexec || sig != t->gsig) {
     if (t->gexec) { hipGraphExecDestroy(t->gexec); t->gexec = nullptr; }
-  if (t->arena) { hipFree(t->arena); t->arena = nullptr; }
-  if (t->cst) { hipStreamDestroy(t->cst); t->cst = nullptr; }
     hipGraph_t g = nullptr;
     if ((e = hipStreamBeginCapture(t->st, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
     const hipError_t le = launch_pipeline(t, pl, sh, final, false);
@@ -833,18 +991,31 @@ namespace {
 
 // Tallies one batch of chunks (taken off the queue by the caller) and, with
 // `final`, closes every stream.  Caller holds run_mu.
-int process_batch(thapi_tally *t, std::vector<Chunk> &work, bool final) {
+// Groups the chunks of one batch by stream (each stream's chunks stay in
+// ticket order), picks the launch shape and plans the work list.
+Shape prepare_batch(thapi_tally *t, std::vector<Chunk> &work, Plan &pl) {
+  std::stable_sort(work.begin(), work.end(), [](const Chunk &a, const Chunk &b) { return a.stream < b.stream; });
+  const Shape sh = shape_for(t, work);
+  plan_work(t, work, sh, pl);
+  return sh;
+}
+
+// Tallies one batch of chunks, planned by prepare_batch (`pl`, `sh`) and
+// taken off the queue by the caller, and with `final` closes every stream.
+// With `scratch` the work list and range summaries go to that device array
+// (already checked to be large enough) instead of the handle's buffers.
+// Caller holds run_mu.
+int process_batch(thapi_tally *t, std::vector<Chunk> &work, bool final, const Plan &pl, const Shape &sh,
+                  uint8_t *scratch = nullptr) {
   t->gen++;
   if (hipSetDevice(t->dev) != hipSuccess) return THAPI_E_DEVICE;
   for (int k = 0; k < TM_N; k++) t->timings[k] = 0;
-  // chunks grouped by stream, each stream's chunks in ticket order
-  std::stable_sort(work.begin(), work.end(), [](const Chunk &a, const Chunk &b) { return a.stream < b.stream; });
-  const Shape sh = shape_for(t, work);
-  Plan pl;
-  plan_work(t, work, sh, pl);
   const uint32_t nR = (uint32_t)pl.ranges.size();
   int rc = THAPI_OK;
-  if (nR) HIPCHK(upload_plan(t, pl));
+  if (nR) HIPCHK(upload_plan(t, pl, scratch));
+  // streaming form: the launch waits on the device for the chunks' copies
+  for (auto &c : work)
+    if (c.ev >= 0) HIPCHK(hipStreamWaitEvent(t->st, t->ev_pool[c.ev], 0));
   HIPCHK(run_pipeline(t, pl, sh, final));
   HIPCHK(ensure_pinned(t, 64));
   uint32_t *herr = (uint32_t *)t->h_pinned;
@@ -863,10 +1034,7 @@ int process_batch(thapi_tally *t, std::vector<Chunk> &work, bool final) {
   }
   {
     std::lock_guard<std::mutex> g(t->mu);
-    for (auto &c : work) {
-      if (c.in_arena) { arena_release_front(t); t->budget_used -= c.owned_bytes; }
-      else if (c.owned) { hipFree(c.owned); t->budget_used -= c.owned_bytes; }
-    }
+    for (auto &c : work) release_chunk(t, c);
     t->cv.notify_all();
     if (err & ERR_PIPE) { t->failed = THAPI_E_DEVICE; rc = THAPI_E_DEVICE; }
     else if (err & ERR_PAYLOAD) { t->failed = THAPI_E_INVAL; rc = THAPI_E_INVAL; }
@@ -877,10 +1045,13 @@ int process_batch(thapi_tally *t, std::vector<Chunk> &work, bool final) {
   }
   if (rc == THAPI_OK && (t->cfg.flags & THAPI_STRICT)) {
     // strict mode: any anomaly counted so far fails the flush
-    std::vector<uint64_t> h((size_t)t->stream_keys.size() * ST_N);
-    if (!h.empty()) {
-      HIPCHK(hipMemcpy(h.data(), t->tb.sstats, 8 * h.size(), hipMemcpyDeviceToHost));
-      for (size_t i = 0; i < t->stream_keys.size(); i++) {
+    const size_t nst = t->stream_keys.size();
+    if (nst) {
+      HIPCHK(ensure_pinned(t, 8 * nst * ST_N));
+      const uint64_t *h = (const uint64_t *)t->h_pinned;
+      HIPCHK(hipMemcpyAsync(t->h_pinned, t->tb.sstats, 8 * nst * ST_N, hipMemcpyDeviceToHost, t->st));
+      HIPCHK(hipStreamSynchronize(t->st));
+      for (size_t i = 0; i < nst; i++) {
         const uint64_t *c = &h[i * ST_N];
         if (c[ST_ORPHAN] || c[ST_MISMATCH] || c[ST_NEGDUR] || c[ST_UNDER] || c[ST_TSREG] || c[ST_UNCLOSED] ||
             c[ST_BAD])
@@ -906,9 +1077,9 @@ void service_loop(thapi_tally *t) {
       t->work_cv.wait(lk, [&] {
         return t->stop || t->failed || (!t->queue.empty() && t->queue.front().ready);
       });
-      if (t->failed) { t->cv.notify_all(); return; }
+      if (t->failed) { t->worker_running = false; t->cv.notify_all(); return; }
       if (t->queue.empty() || !t->queue.front().ready) {
-        if (t->stop) return;
+        if (t->stop) { t->worker_running = false; return; }
         continue;
       }
       while (!t->queue.empty() && t->queue.front().ready) {
@@ -922,7 +1093,9 @@ void service_loop(thapi_tally *t) {
     int rc;
     {
       std::lock_guard<std::mutex> run(t->run_mu);
-      rc = process_batch(t, work, false);
+      Plan pl;
+      const Shape sh = prepare_batch(t, work, pl);
+      rc = process_batch(t, work, false, pl, sh);
     }
     const uint64_t tdone = now_ns();
     std::lock_guard<std::mutex> g(t->mu);
@@ -954,7 +1127,9 @@ int thapi_tally_flush(thapi_tally *t, uint64_t ticket, uint32_t flags) {
     lk.unlock();
     std::lock_guard<std::mutex> run(t->run_mu);
     std::vector<Chunk> none;
-    return process_batch(t, none, true);
+    Plan pl;
+    const Shape sh = prepare_batch(t, none, pl);
+    return process_batch(t, none, true, pl, sh);
   }
   std::lock_guard<std::mutex> run(t->run_mu);
   std::vector<Chunk> work;
@@ -967,8 +1142,12 @@ int thapi_tally_flush(thapi_tally *t, uint64_t ticket, uint32_t flags) {
       t->queue.pop_front();
     }
   }
-  return process_batch(t, work, final);
+  Plan pl;
+  const Shape sh = prepare_batch(t, work, pl);
+  return process_batch(t, work, final, pl, sh);
 }
+
+
 
 int thapi_tally_ticket_done(thapi_tally *t, uint64_t ticket, uint64_t *done_ns) {
   if (!t || !ticket) return THAPI_E_INVAL;
@@ -1156,9 +1335,12 @@ int thapi_tally_read(thapi_tally *t, uint32_t scope, uint32_t trace_id, thapi_ta
     // host tables of the readout, staged in pinned memory (the work-list
     // staging is free between flushes)
     const void *src[4] = {srank.data(), rank_key.data(), tspan.data(), rank_stream.data()};
-    DevView *dst[4] = {&t->stream_rank, &t->rank_key, &t->trace_span, &t->rstream};
+    void **dst[4] = {&t->stream_rank.p, &t->rank_key.p, &t->trace_span.p, &t->rstream.p};
     const size_t part[4] = {4ull * srank.size(), 4ull * rank_key.size(), 4ull * tspan.size(), 4ull * rank_stream.size()};
-    HIPCHK(stage_h2d(t, t->read_pack, dst, src, part, 4));
+    const size_t tot = pack_bytes(part, 4);
+    HIPCHK(t->read_pack.ensure(tot));
+    HIPCHK(grow_plan_staging(t, tot));
+    HIPCHK(stage_h2d(t, t->read_pack.as<uint8_t>(), dst, src, part, 4));
   }
   if (sort_small_fits(ng)) {
     // keys, sort and group bounds in one launch
@@ -1220,6 +1402,33 @@ int thapi_tally_read(thapi_tally *t, uint32_t scope, uint32_t trace_id, thapi_ta
 
 int thapi_tally_reset(thapi_tally *t) {
   if (!t) return THAPI_E_INVAL;
+  const bool service = (t->cfg.flags & THAPI_SERVICE) != 0;
+  if (service) {
+    std::unique_lock<std::mutex> lk(t->mu);
+    if (t->failed == THAPI_E_DEVICE) return THAPI_E_DEVICE;
+    if (t->failed) {
+      // the worker stopped at the failure: wait until every queued chunk's
+      // copy is enqueued and has landed, then discard what it left queued
+      t->cv.wait(lk, [&] {
+        for (auto &c : t->queue)
+          if (!c.ready) return false;
+        return true;
+      });
+      lk.unlock();
+      for (auto &cs : t->cst)
+        if (cs && hipStreamSynchronize(cs) != hipSuccess) return hip_fail(t, hipErrorUnknown);
+      lk.lock();
+      for (auto &c : t->queue) release_chunk(t, c);
+      t->queue.clear();
+      t->cv.notify_all();
+    } else {
+      // every submitted chunk must have been tallied (the worker may hold a
+      // batch it took off the queue)
+      if (!t->queue.empty()) return THAPI_E_STATE;
+      t->cv.wait(lk, [&] { return t->failed || t->done_upto + 1 >= t->next_ticket; });
+      if (t->failed) return t->failed == THAPI_E_DEVICE ? THAPI_E_DEVICE : THAPI_E_STATE;
+    }
+  }
   std::lock_guard<std::mutex> run(t->run_mu);
   {
     std::lock_guard<std::mutex> g(t->mu);
@@ -1236,6 +1445,14 @@ int thapi_tally_reset(thapi_tally *t) {
   t->failed = 0;
   t->finalized = false;
   t->flushed_any = false;
+  if (service && !t->worker_running) {
+    // a failure stopped the worker (it has released the lock for good once
+    // worker_running is false): start a new one
+    if (t->worker.joinable()) t->worker.join();
+    t->stop = false;
+    t->worker_running = true;
+    t->worker = std::thread(service_loop, t);
+  }
   return THAPI_OK;
 }
 
@@ -1265,6 +1482,291 @@ int thapi_tally_timings(thapi_tally *t, double *ms, int n) {
   int k = std::min<int>(n, TM_N);
   for (int i = 0; i < k; i++) ms[i] = t->timings[i];
   return k;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Aggregate export and merge.  Blob layout (little-endian), in this order:
+//   header   16 x u32: magic "THTALLY1" (2 words), version 1, format, n_fns,
+//            n_kernel_ids, max_depth, n_streams, n_threads, n_frames, n_rows,
+//            n_krows, finalized, 3 x 0
+//   streams  n_streams x {u32 trace, host, pid, 0; u64 dropped; u64 counters[11]}
+//   threads  n_threads x {u32 stream index, tid, open calls h, flags; u64 last ts}
+//   frames   n_frames  x {u32 thread index, fn; u64 ts, children time, bytes}
+//            (each thread's h open calls, bottom first, threads in order)
+//   rows     n_rows    x {u32 thread index, fn; u64 count, incl sum/min/max,
+//                         self sum/min/max, bytes}
+//   krows    n_krows   x {u32 stream index, kernel id; u64 count, sum, min, max}
+// Counters in stream order: records, entries, exits, kernel records, orphan
+// exits, fn mismatch, negative durations, self underflow, ts regressions,
+// unclosed at the final flush, bad records.  Thread flags: 1 = has a
+// timestamp, 2 = its stack overflowed max_depth.
+namespace {
+
+constexpr uint32_t BLOB_MAGIC0 = 0x4C415448u, BLOB_MAGIC1 = 0x31594C4Cu;   // "THTALLY1"
+constexpr size_t BLOB_HDR = 64, BLOB_STREAM = 112, BLOB_THREAD = 24, BLOB_FRAME = 32, BLOB_ROW = 72,
+                 BLOB_KROW = 40;
+
+struct Writer {
+  uint8_t *p;
+  void u32(uint32_t v) { memcpy(p, &v, 4); p += 4; }
+  void u64(uint64_t v) { memcpy(p, &v, 8); p += 8; }
+};
+struct Reader {
+  const uint8_t *p;
+  uint32_t u32() { uint32_t v; memcpy(&v, p, 4); p += 4; return v; }
+  uint64_t u64() { uint64_t v; memcpy(&v, p, 8); p += 8; return v; }
+};
+
+// Builds the blob of everything flushed so far into t->exp_blob.  Caller
+// holds run_mu.
+int build_export(thapi_tally *t) {
+  const uint32_t D = t->cfg.max_depth, nf = t->cfg.n_fns, nk = t->cfg.n_kernel_ids;
+  std::vector<SKey> keys;
+  std::vector<uint64_t> dropped;
+  bool finalized;
+  {
+    std::lock_guard<std::mutex> g(t->mu);
+    keys = t->stream_keys;
+    dropped = t->dropped;
+    finalized = t->finalized;
+  }
+  const size_t ns = keys.size();
+  uint32_t ng = 0;
+  HIPCHK(hipStreamSynchronize(t->st));   // (a reset's table initialisation may still be queued)
+  HIPCHK(hipMemcpyAsync(t->h_pinned, t->tb.n_gslots, 4, hipMemcpyDeviceToHost, t->st));
+  HIPCHK(hipStreamSynchronize(t->st));
+  ng = std::min<uint32_t>(*(const uint32_t *)t->h_pinned, t->cfg.max_threads);
+  std::vector<uint32_t> ths(ng), tht(ng);
+  std::vector<CState> cs(ng);
+  std::vector<Frame> fr((size_t)ng * D);
+  std::vector<Tally> tal((size_t)ng * nf);
+  std::vector<KTally> kt(ns * nk);
+  std::vector<uint64_t> sst(ns * ST_N);
+  if (ng) {
+    HIPCHK(hipMemcpy(ths.data(), t->tb.th_stream, 4ull * ng, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(tht.data(), t->tb.th_tid, 4ull * ng, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(cs.data(), t->tb.cstate, sizeof(CState) * ng, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(fr.data(), t->tb.cstack, sizeof(Frame) * fr.size(), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(tal.data(), t->tb.tally, sizeof(Tally) * tal.size(), hipMemcpyDeviceToHost));
+  }
+  if (!kt.empty()) HIPCHK(hipMemcpy(kt.data(), t->tb.ktally, sizeof(KTally) * kt.size(), hipMemcpyDeviceToHost));
+  if (!sst.empty()) HIPCHK(hipMemcpy(sst.data(), t->tb.sstats, 8 * sst.size(), hipMemcpyDeviceToHost));
+  size_t n_frames = 0, n_rows = 0, n_krows = 0;
+  for (uint32_t g = 0; g < ng; g++) n_frames += std::min<uint32_t>(cs[g].h, D);
+  for (auto &v : tal) n_rows += v.count != 0;
+  for (auto &v : kt) n_krows += v.count != 0;
+  const size_t bytes = BLOB_HDR + BLOB_STREAM * ns + BLOB_THREAD * ng + BLOB_FRAME * n_frames + BLOB_ROW * n_rows +
+                       BLOB_KROW * n_krows;
+  t->exp_blob.assign(bytes, 0);
+  Writer w{t->exp_blob.data()};
+  const uint32_t hdr[16] = {BLOB_MAGIC0, BLOB_MAGIC1, 1u, t->cfg.format, nf, nk, D, (uint32_t)ns, ng,
+                            (uint32_t)n_frames, (uint32_t)n_rows, (uint32_t)n_krows, finalized ? 1u : 0u, 0, 0, 0};
+  for (uint32_t v : hdr) w.u32(v);
+  for (size_t i = 0; i < ns; i++) {
+    w.u32(keys[i][0]); w.u32(keys[i][1]); w.u32(keys[i][2]); w.u32(0);
+    w.u64(dropped[i]);
+    for (int k = 0; k < ST_N; k++) w.u64(sst[i * ST_N + k]);
+  }
+  for (uint32_t g = 0; g < ng; g++) {
+    w.u32(ths[g]); w.u32(tht[g]); w.u32(std::min<uint32_t>(cs[g].h, D)); w.u32(cs[g].flags);
+    w.u64(cs[g].last_ts);
+  }
+  for (uint32_t g = 0; g < ng; g++)
+    for (uint32_t k = 0; k < std::min<uint32_t>(cs[g].h, D); k++) {
+      const Frame &f = fr[(size_t)g * D + k];
+      w.u32(g); w.u32(f.fn); w.u64(f.ts); w.u64(f.child); w.u64(f.bytes);
+    }
+  for (uint32_t g = 0; g < ng; g++)
+    for (uint32_t f = 0; f < nf; f++) {
+      const Tally &v = tal[(size_t)g * nf + f];
+      if (!v.count) continue;
+      w.u32(g); w.u32(f);
+      w.u64(v.count); w.u64(v.incl_sum); w.u64(v.incl_min); w.u64(v.incl_max);
+      w.u64(v.self_sum); w.u64(v.self_min); w.u64(v.self_max); w.u64(v.bytes_sum);
+    }
+  for (size_t s = 0; s < ns; s++)
+    for (uint32_t k = 0; k < nk; k++) {
+      const KTally &v = kt[s * nk + k];
+      if (!v.count) continue;
+      w.u32((uint32_t)s); w.u32(k);
+      w.u64(v.count); w.u64(v.sum); w.u64(v.min); w.u64(v.max);
+    }
+  t->exp_gen = t->gen.load();
+  t->exp_valid = true;
+  return THAPI_OK;
+}
+
+}  // namespace
+
+namespace tt {
+hipError_t launch_merge(const Tables &tb, const MThread *th, uint32_t n_th, const Frame *frames, uint32_t *gmap,
+                        const MRow *rows, uint32_t n_rows, const MKRow *krows, uint32_t n_krows, const uint64_t *scnt,
+                        const uint32_t *sidx, uint32_t n_streams, uint32_t *conflict, bool check_only,
+                        hipStream_t st);
+}  // namespace tt
+
+extern "C" {
+
+int thapi_tally_export(thapi_tally *t, void *buf, size_t cap, size_t *size) {
+  if (!t || !size || (cap && !buf)) return THAPI_E_INVAL;
+  std::lock_guard<std::mutex> run(t->run_mu);
+  {
+    std::lock_guard<std::mutex> g(t->mu);
+    if (t->failed) return t->failed == THAPI_E_DEVICE ? THAPI_E_DEVICE : THAPI_E_STATE;
+  }
+  if (hipSetDevice(t->dev) != hipSuccess) return THAPI_E_DEVICE;
+  // the blob of a size query is kept for the second call while nothing changed
+  if (!t->exp_valid || t->exp_gen != t->gen.load()) {
+    const int rc = build_export(t);
+    if (rc != THAPI_OK) return rc;
+  }
+  *size = t->exp_blob.size();
+  if (t->exp_blob.size() > cap) return !buf && !cap ? THAPI_OK : THAPI_E_BUFSZ;
+  memcpy(buf, t->exp_blob.data(), t->exp_blob.size());
+  t->exp_valid = false;
+  return THAPI_OK;
+}
+
+int thapi_tally_merge(thapi_tally *t, const void *buf, size_t size) {
+  if (!t || (!buf && size)) return THAPI_E_INVAL;
+  if (size < BLOB_HDR) return THAPI_E_INVAL;
+  const uint8_t *b = (const uint8_t *)buf;
+  Reader r{b};
+  uint32_t h[16];
+  for (auto &v : h) v = r.u32();
+  if (h[0] != BLOB_MAGIC0 || h[1] != BLOB_MAGIC1 || h[2] != 1u) return THAPI_E_INVAL;
+  if (h[3] != t->cfg.format || h[4] != t->cfg.n_fns || h[5] != t->cfg.n_kernel_ids || h[6] != t->cfg.max_depth)
+    return THAPI_E_INVAL;
+  const uint64_t ns = h[7], nth = h[8], nfr = h[9], nrow = h[10], nkr = h[11];
+  const uint64_t want = BLOB_HDR + BLOB_STREAM * ns + BLOB_THREAD * nth + BLOB_FRAME * nfr + BLOB_ROW * nrow +
+                        BLOB_KROW * nkr;
+  if (want != size) return THAPI_E_INVAL;
+  const uint32_t D = t->cfg.max_depth, nf = t->cfg.n_fns, nk = t->cfg.n_kernel_ids;
+  // parse and validate everything before any change
+  std::vector<SKey> skeys(ns);
+  std::vector<uint64_t> sdrop(ns), scnt(ns * ST_N);
+  std::map<SKey, uint32_t> seen;
+  for (uint64_t i = 0; i < ns; i++) {
+    skeys[i] = {r.u32(), r.u32(), r.u32()};
+    if (r.u32() != 0) return THAPI_E_INVAL;
+    sdrop[i] = r.u64();
+    for (int k = 0; k < ST_N; k++) scnt[i * ST_N + k] = r.u64();
+    if (!seen.emplace(skeys[i], (uint32_t)i).second) return THAPI_E_INVAL;
+  }
+  std::vector<MThread> th(nth);
+  std::set<std::pair<uint32_t, uint32_t>> tkeys;
+  uint64_t frames_needed = 0;
+  for (uint64_t i = 0; i < nth; i++) {
+    MThread &m = th[i];
+    m.stream = r.u32(); m.tid = r.u32(); m.h = r.u32(); m.flags = r.u32(); m.last_ts = r.u64();
+    m.frame0 = (uint32_t)frames_needed; m.pad = 0;
+    if (m.stream >= ns || m.h > D || (m.flags & ~(uint32_t)(CS_HAS_TS | CS_OVERFLOW))) return THAPI_E_INVAL;
+    if (!tkeys.insert({m.stream, m.tid}).second) return THAPI_E_INVAL;
+    frames_needed += m.h;
+  }
+  if (frames_needed != nfr) return THAPI_E_INVAL;
+  std::vector<Frame> frames(nfr);
+  {
+    uint64_t i = 0;
+    for (uint64_t k = 0; k < nth; k++)
+      for (uint32_t j = 0; j < th[k].h; j++, i++) {
+        if (r.u32() != k) return THAPI_E_INVAL;
+        Frame &f = frames[i];
+        f.fn = r.u32(); f.ts = r.u64(); f.child = r.u64(); f.bytes = r.u64(); f.pad = 0;
+        if (f.fn >= nf) return THAPI_E_INVAL;
+      }
+  }
+  std::vector<MRow> rows(nrow);
+  for (auto &m : rows) {
+    m.thread = r.u32(); m.fn = r.u32();
+    m.v.count = r.u64(); m.v.incl_sum = r.u64(); m.v.incl_min = r.u64(); m.v.incl_max = r.u64();
+    m.v.self_sum = r.u64(); m.v.self_min = r.u64(); m.v.self_max = r.u64(); m.v.bytes_sum = r.u64();
+    if (m.thread >= nth || m.fn >= nf) return THAPI_E_INVAL;
+  }
+  std::vector<MKRow> krows(nkr);
+  for (auto &m : krows) {
+    m.stream = r.u32(); m.kid = r.u32();
+    m.v.count = r.u64(); m.v.sum = r.u64(); m.v.min = r.u64(); m.v.max = r.u64();
+    if (m.stream >= ns || m.kid >= nk) return THAPI_E_INVAL;
+  }
+  std::lock_guard<std::mutex> run(t->run_mu);
+  std::vector<uint32_t> sidx(ns);
+  {
+    std::lock_guard<std::mutex> g(t->mu);
+    if (t->cfg.flags & THAPI_SERVICE) return THAPI_E_STATE;
+    if (t->failed) return t->failed == THAPI_E_DEVICE ? THAPI_E_DEVICE : THAPI_E_STATE;
+    if (t->finalized || !t->queue.empty()) return THAPI_E_STATE;
+    size_t fresh = 0;
+    for (auto &k : skeys) fresh += t->stream_idx.count(k) == 0;
+    if (t->stream_keys.size() + fresh > t->cfg.max_streams) return THAPI_E_CAPACITY;
+  }
+  if (hipSetDevice(t->dev) != hipSuccess) return THAPI_E_DEVICE;
+  HIPCHK(hipStreamSynchronize(t->st));
+  // map the blob's streams to this handle's indices (registering new keys
+  // only after the conflict check below has passed)
+  std::vector<uint32_t> map_now(ns, EMPTY32);
+  {
+    std::lock_guard<std::mutex> g(t->mu);
+    uint32_t next = (uint32_t)t->stream_keys.size();
+    for (uint64_t i = 0; i < ns; i++) {
+      auto it = t->stream_idx.find(skeys[i]);
+      sidx[i] = it != t->stream_idx.end() ? it->second : next++;
+    }
+  }
+  for (auto &m : th) m.stream = sidx[m.stream];
+  for (auto &m : krows) m.stream = sidx[m.stream];
+  // one device buffer: threads, frames, rows, krows, counters, stream map, thread map, conflict flag
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t o_th = 0, o_fr = o_th + al(sizeof(MThread) * nth), o_row = o_fr + al(sizeof(Frame) * nfr),
+               o_kr = o_row + al(sizeof(MRow) * nrow), o_sc = o_kr + al(sizeof(MKRow) * nkr),
+               o_si = o_sc + al(8 * ns * ST_N), o_gm = o_si + al(4 * ns), o_cf = o_gm + al(4 * nth),
+               tot = o_cf + 256;
+  HIPCHK(t->merge_buf.ensure(tot));
+  uint8_t *d = t->merge_buf.as<uint8_t>();
+  if (nth) HIPCHK(hipMemcpy(d + o_th, th.data(), sizeof(MThread) * nth, hipMemcpyHostToDevice));
+  if (nfr) HIPCHK(hipMemcpy(d + o_fr, frames.data(), sizeof(Frame) * nfr, hipMemcpyHostToDevice));
+  if (nrow) HIPCHK(hipMemcpy(d + o_row, rows.data(), sizeof(MRow) * nrow, hipMemcpyHostToDevice));
+  if (nkr) HIPCHK(hipMemcpy(d + o_kr, krows.data(), sizeof(MKRow) * nkr, hipMemcpyHostToDevice));
+  if (ns) HIPCHK(hipMemcpy(d + o_sc, scnt.data(), 8 * ns * ST_N, hipMemcpyHostToDevice));
+  if (ns) HIPCHK(hipMemcpy(d + o_si, sidx.data(), 4 * ns, hipMemcpyHostToDevice));
+  HIPCHK(launch_fill32((uint32_t *)(d + o_cf), 1, 0, t->st));
+  const Tables &tb = t->tb;
+  uint32_t *conflict = (uint32_t *)(d + o_cf);
+  HIPCHK(launch_merge(tb, (const MThread *)(d + o_th), (uint32_t)nth, (const Frame *)(d + o_fr),
+                      (uint32_t *)(d + o_gm), (const MRow *)(d + o_row), (uint32_t)nrow, (const MKRow *)(d + o_kr),
+                      (uint32_t)nkr, (const uint64_t *)(d + o_sc), (const uint32_t *)(d + o_si), (uint32_t)ns,
+                      conflict, true, t->st));
+  HIPCHK(hipMemcpyAsync(t->h_pinned, conflict, 4, hipMemcpyDeviceToHost, t->st));
+  HIPCHK(hipStreamSynchronize(t->st));
+  if (*(const uint32_t *)t->h_pinned) return THAPI_E_STATE;   // open calls on both sides of one thread
+  {
+    std::lock_guard<std::mutex> g(t->mu);
+    for (uint64_t i = 0; i < ns; i++) {
+      if (sidx[i] == t->stream_keys.size()) {
+        t->stream_idx[skeys[i]] = sidx[i];
+        t->stream_keys.push_back(skeys[i]);
+        t->dropped.push_back(0);
+      }
+      t->dropped[sidx[i]] += sdrop[i];
+    }
+    t->gen++;
+    t->flushed_any = true;
+  }
+  HIPCHK(launch_fill32(t->tb.err, 1, 0, t->st));
+  HIPCHK(launch_merge(tb, (const MThread *)(d + o_th), (uint32_t)nth, (const Frame *)(d + o_fr),
+                      (uint32_t *)(d + o_gm), (const MRow *)(d + o_row), (uint32_t)nrow, (const MKRow *)(d + o_kr),
+                      (uint32_t)nkr, (const uint64_t *)(d + o_sc), (const uint32_t *)(d + o_si), (uint32_t)ns,
+                      conflict, false, t->st));
+  HIPCHK(hipMemcpyAsync(t->h_pinned, t->tb.err, 4, hipMemcpyDeviceToHost, t->st));
+  HIPCHK(hipStreamSynchronize(t->st));
+  if (*(const uint32_t *)t->h_pinned & ERR_CAPACITY) {
+    std::lock_guard<std::mutex> g(t->mu);
+    t->failed = THAPI_E_CAPACITY;
+    return THAPI_E_CAPACITY;
+  }
+  return THAPI_OK;
 }
 
 }  // extern "C"

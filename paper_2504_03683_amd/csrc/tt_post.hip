@@ -705,6 +705,76 @@ __global__ void k_init_all(InitSet is) {
   if (i0 == 0) { *is.ngs = 0; *is.err = 0; }
 }
 
+// ----------------------------------------------------------------- merge
+// Merge of an exported aggregate into the tables (the host has validated it
+// and mapped its streams to this handle's stream indices).
+
+// Pass 1 (run alone first): a blob thread with open calls must find no open
+// call on the same (stream, tid) here; a conflict sets *conflict, and the
+// host then runs no later pass.
+__global__ void k_merge_check(Tables tb, const MThread *__restrict__ th, uint32_t n, uint32_t *conflict) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || !th[i].h) return;
+  const uint32_t g = lookup_gslot(tb, th[i].stream, th[i].tid);
+  if (g < tb.max_threads && tb.cstate[g].h) atomicOr(conflict, 1u);
+}
+
+// Pass 2: every blob thread gets its slot here (inserted on first sight),
+// its open calls and last timestamp are installed, its flags combined.
+__global__ void k_merge_threads(Tables tb, const MThread *__restrict__ th, uint32_t n,
+                                const Frame *__restrict__ frames, uint32_t *__restrict__ gmap) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const MThread m = th[i];
+  const uint32_t g = resolve_gslot(tb, m.stream, m.tid);
+  gmap[i] = g;
+  if (g >= tb.max_threads) return;
+  CState cs = tb.cstate[g];
+  if (m.h) {
+    for (uint32_t k = 0; k < m.h; k++) tb.cstack[(size_t)g * tb.D + k] = frames[m.frame0 + k];
+    cs.h = m.h;
+  }
+  if (m.flags & CS_HAS_TS)
+    cs.last_ts = (cs.flags & CS_HAS_TS) && cs.last_ts > m.last_ts ? cs.last_ts : m.last_ts;
+  cs.flags |= m.flags;
+  tb.cstate[g] = cs;
+}
+
+// Pass 3: tally rows, kernel rows and stream counters, combined with u64
+// add / min / max (order-independent).
+__global__ void k_merge_rows(Tables tb, const uint32_t *__restrict__ gmap, const MRow *__restrict__ rows,
+                             uint32_t n_rows, const MKRow *__restrict__ krows, uint32_t n_krows,
+                             const uint64_t *__restrict__ scnt, const uint32_t *__restrict__ sidx, uint32_t n_streams) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_rows) {
+    const MRow r = rows[i];
+    const uint32_t g = gmap[r.thread];
+    if (g < tb.max_threads) {
+      Tally *d = &tb.tally[(size_t)g * tb.n_fns + r.fn];
+      ga64(&d->count, r.v.count);
+      ga64(&d->incl_sum, r.v.incl_sum);
+      ga64(&d->self_sum, r.v.self_sum);
+      ga64(&d->bytes_sum, r.v.bytes_sum);
+      gmin64(&d->incl_min, r.v.incl_min);
+      gmax64(&d->incl_max, r.v.incl_max);
+      gmin64(&d->self_min, r.v.self_min);
+      gmax64(&d->self_max, r.v.self_max);
+    }
+  }
+  if (i < n_krows) {
+    const MKRow r = krows[i];
+    KTally *d = &tb.ktally[(size_t)r.stream * tb.n_kid + r.kid];
+    ga64(&d->count, r.v.count);
+    ga64(&d->sum, r.v.sum);
+    gmin64(&d->min, r.v.min);
+    gmax64(&d->max, r.v.max);
+  }
+  if (i < n_streams * (uint32_t)ST_N) {
+    const uint32_t s = i / ST_N, k = i - s * ST_N;
+    if (scnt[i]) ga64((uint64_t *)&tb.sstats[(size_t)sidx[s] * ST_N + k], scnt[i]);
+  }
+}
+
 // --------------------------------------------------------------- launchers
 static dim3 fill_grid(size_t n) {
   size_t b = (n + 255) / 256;
@@ -777,6 +847,22 @@ hipError_t launch_group_rows(const RowCtx &c, const Tables &tb, uint32_t n_group
   } else {
     hipLaunchKernelGGL(k_group_rows, dim3(n_groups), dim3(256), 0, st, c, tb, cnt, (const uint64_t *)off, out);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_merge(const Tables &tb, const MThread *th, uint32_t n_th, const Frame *frames, uint32_t *gmap,
+                        const MRow *rows, uint32_t n_rows, const MKRow *krows, uint32_t n_krows, const uint64_t *scnt,
+                        const uint32_t *sidx, uint32_t n_streams, uint32_t *conflict, bool check_only,
+                        hipStream_t st) {
+  if (check_only) {
+    if (n_th) hipLaunchKernelGGL(k_merge_check, dim3((n_th + 255) / 256), dim3(256), 0, st, tb, th, n_th, conflict);
+    return hipGetLastError();
+  }
+  if (n_th) hipLaunchKernelGGL(k_merge_threads, dim3((n_th + 255) / 256), dim3(256), 0, st, tb, th, n_th, frames, gmap);
+  uint32_t n = n_rows > n_krows ? n_rows : n_krows;
+  if (n < n_streams * (uint32_t)ST_N) n = n_streams * (uint32_t)ST_N;
+  if (n) hipLaunchKernelGGL(k_merge_rows, dim3((n + 255) / 256), dim3(256), 0, st, tb, gmap, rows, n_rows, krows,
+                            n_krows, scnt, sidx, n_streams);
   return hipGetLastError();
 }
 

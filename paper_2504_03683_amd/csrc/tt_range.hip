@@ -198,48 +198,6 @@ __device__ inline uint64_t load_u64_unaligned(const uint8_t *base, uint64_t off)
   return (lo >> sh) | (hi << (64 - sh));
 }
 
-// Resolves (stream, tid) to its global thread slot, inserting it on first
-// sight.  Lock-free open addressing in two phases: every lane first inserts
-// or finds its key, and an inserting lane publishes the slot id before the
-// probe loop ends; only after the whole wave has left that loop does a lane
-// that found a key inserted elsewhere wait for its slot id.  (Waiting inside
-// the probe loop could deadlock: a lane of one wave spinning on a key whose
-// inserter is a masked-off lane of another spinning wave, and vice versa.)
-__device__ uint32_t resolve_gslot(const Tables &tb, uint32_t stream, uint32_t tid) {
-  const uint64_t key = ((uint64_t)stream << 32) | tid;
-  uint32_t h = (uint32_t)hash64(key) & tb.gmask;
-  uint32_t result = GV_INVALID;
-  bool wait = false;
-  for (uint32_t probe = 0; probe <= tb.gmask; probe++) {
-    const uint64_t old = atomicCAS((unsigned long long *)&tb.gkeys[h], (unsigned long long)EMPTY64,
-                                   (unsigned long long)key);
-    if (old == EMPTY64) {
-      uint32_t g = atomicAdd(tb.n_gslots, 1u);
-      if (g >= tb.max_threads) {
-        atomicOr(tb.err, ERR_CAPACITY);
-        g = GV_INVALID;
-      } else {
-        tb.th_stream[g] = stream;
-        tb.th_tid[g] = tid;
-      }
-      __hip_atomic_store(&tb.gvals[h], g, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      result = g;
-      break;
-    }
-    if (old == key) { wait = true; break; }
-    h = (h + 1) & tb.gmask;
-  }
-  if (wait) {
-    uint32_t v;
-    while ((v = __hip_atomic_load(&tb.gvals[h], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) == GV_PENDING)
-      __builtin_amdgcn_s_sleep(2);
-    result = v;
-  } else if (result == GV_INVALID) {
-    atomicOr(tb.err, ERR_CAPACITY);
-  }
-  return result;
-}
-
 // LDS tally layout: the first nd * n_fns entries are indexed directly by
 // slot * n_fns + fn (no probing); the rest is an open-addressing hash keyed
 // (slot << 16 | fn) for slots beyond that.  nd is direct_slots(n_fns, E), or

@@ -32,7 +32,9 @@ OK, E_INVAL, E_NOMEM, E_AGAIN, E_DEPTH, E_MALFORMED, E_DEVICE, E_BUFSZ, E_CAPACI
 
 ENTRY_POINTS = ["thapi_tally_open", "thapi_tally_submit", "thapi_tally_flush", "thapi_tally_read",
                 "thapi_tally_reset", "thapi_tally_close", "thapi_tally_strerror", "thapi_tally_timings",
-                "thapi_tally_autotune", "thapi_tally_ticket_done", "thapi_tally_service_info"]
+                "thapi_tally_autotune", "thapi_tally_ticket_done", "thapi_tally_service_info",
+                "thapi_tally_export", "thapi_tally_merge",
+                "thapi_tally_read_bandwidth"]
 
 ROW_DTYPE = np.dtype([
     ("trace", "<u4"), ("host", "<u4"), ("pid", "<u4"), ("tid", "<u4"),
@@ -83,6 +85,10 @@ def load():
     lib.thapi_tally_submit.argtypes = [P, ctypes.POINTER(StreamKey), P, ctypes.c_size_t, P, ctypes.c_size_t,
                                        ctypes.POINTER(ctypes.c_uint64)]
     lib.thapi_tally_flush.argtypes = [P, ctypes.c_uint64, ctypes.c_uint32]
+    lib.thapi_tally_export.argtypes = [P, P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
+    lib.thapi_tally_merge.argtypes = [P, P, ctypes.c_size_t]
+    lib.thapi_tally_read_bandwidth.argtypes = [ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint32,
+                                               ctypes.POINTER(ctypes.c_double)]
     lib.thapi_tally_read.argtypes = [P, ctypes.c_uint32, ctypes.c_uint32, P, ctypes.c_size_t,
                                      ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(Stats)]
     lib.thapi_tally_reset.argtypes = [P]
@@ -98,6 +104,13 @@ def load():
             getattr(lib, n).restype = ctypes.c_int
     _lib = lib
     return lib
+
+
+def read_bandwidth(device=0, nbytes=4 << 30, reps=5):
+    """Streaming-read bandwidth of the device in GB/s (thapi_tally_read_bandwidth)."""
+    v = ctypes.c_double(0)
+    _check(load().thapi_tally_read_bandwidth(device, nbytes, reps, ctypes.byref(v)), "read_bandwidth")
+    return v.value
 
 
 class TallyError(RuntimeError):
@@ -210,6 +223,23 @@ class Tally:
             _check(self._lib.thapi_tally_read(self._h, scope, trace, rows.ctypes.data, n.value, ctypes.byref(n),
                                               ctypes.byref(st)), "read")
         return rows, {k: int(getattr(st, k)) for k in STAT_NAMES}
+
+    def export(self):
+        """The aggregate of everything flushed so far, as a uint8 array (see thapi_tally_export)."""
+        n = ctypes.c_size_t(0)
+        _check(self._lib.thapi_tally_export(self._h, None, 0, ctypes.byref(n)), "export")
+        buf = np.zeros(n.value, dtype=np.uint8)
+        _check(self._lib.thapi_tally_export(self._h, buf.ctypes.data if n.value else None, n.value, ctypes.byref(n)),
+               "export")
+        return buf[:n.value]
+
+    def merge_rc(self, blob):
+        """thapi_tally_merge of an exported blob; returns the raw status."""
+        b = np.ascontiguousarray(blob, dtype=np.uint8)
+        return self._lib.thapi_tally_merge(self._h, b.ctypes.data if b.size else None, b.nbytes)
+
+    def merge(self, blob):
+        _check(self.merge_rc(blob), "merge")
 
     def reset(self):
         _check(self._lib.thapi_tally_reset(self._h), "reset")

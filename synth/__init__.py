@@ -219,8 +219,10 @@ def _par(jobs):
         return list(ex.map(lambda j: j(), jobs))
 
 
-def config(k: int, scale: float = 1.0, want_calls: bool = False) -> Workload:
-    """Workload k (0..4) at `scale` x its full size (record quotas scale linearly)."""
+def config(k: int, scale: float = 1.0, want_calls: bool = False, only=None) -> Workload:
+    """Workload k (0..4) at `scale` x its full size (record quotas scale linearly).
+    For workload 3, `only` (a list of trace indices) keeps just those traces,
+    generated exactly as in the whole batch."""
     seed = SEED_BASE + k
     if k == 0:
         cfg = base_cfg(n_fns=32, max_depth=4)
@@ -247,6 +249,8 @@ def config(k: int, scale: float = 1.0, want_calls: bool = False) -> Workload:
             nfn = rnd.randint(32, 200)
             cfg = base_cfg(n_fns=nfn, max_depth=8)
             quota = max(1, int(size * scale))
+            if only is not None and i not in only:
+                continue
             jobs.append(lambda i=i, cfg=cfg, nthr=nthr, quota=quota:
                         gen_stream(cfg, seed, i, i, 0, 1000, nthr, quota, want_calls))
         streams = _par(jobs)

@@ -29,3 +29,70 @@ def var16(events):
 
 def u64(v):
     return struct.pack("<Q", v)
+
+
+def random_trees(seed, n_threads, calls_per_thread, n_fns, tid_base=500, p_child=0.45, max_depth=6,
+                 p_big_leaf=0.0, p_big_tail=0.0, big_lo=1 << 32, big_hi=1 << 35, t0=0):
+    """Well-formed nested call trees per thread, merged by timestamp: a list of
+    (ts, tid, fn, kind) events.  Leaf durations and a parent's tail after its
+    last child are small (1..2000 ns) except that, with probability p_big_leaf
+    / p_big_tail, they are drawn from [big_lo, big_hi) ns instead (so calls
+    and self times of 2^32 ns and more appear)."""
+    import random
+    rnd = random.Random(seed)
+    evs = []
+    for th in range(n_threads):
+        tid = tid_base + 7919 * th
+        ts = t0 + rnd.randrange(0, 1000)
+        done = 0
+
+        def call(depth):
+            nonlocal ts, done
+            fn = rnd.randrange(n_fns)
+            evs.append((ts, tid, fn, ENTRY, th))
+            done += 1
+            kids = 0
+            while depth < max_depth and rnd.random() < p_child and done < calls_per_thread:
+                ts += rnd.randrange(0, 500)
+                call(depth + 1)
+                kids += 1
+            big = p_big_tail if kids else p_big_leaf
+            ts += rnd.randrange(big_lo, big_hi) if rnd.random() < big else rnd.randrange(1, 2000)
+            evs.append((ts, tid, fn, EXIT, th))
+
+        while done < calls_per_thread:
+            ts += rnd.randrange(0, 1000)
+            call(1)
+    evs.sort(key=lambda e: (e[0], e[4]))
+    return [e[:4] for e in evs]
+
+
+FIXED24_DTYPE = np.dtype([("ts", "<u8"), ("tid", "<u4"), ("fn", "<u2"), ("kind", "u1"), ("rsv", "u1"),
+                          ("end", "<u8")])
+
+
+def corrupt_fixed24(rec, seed, n_fns, p=0.002, lost_exits=3):
+    """A copy of FIXED24 records with seeded damage of every kind the tally
+    counts: entries made unreadable (unknown kind, fn out of range), exits of
+    another fn, exits moved earlier in time, kernel records that end before
+    they start, and a few exits lost (calls left open).  Damage to entries
+    heals at the end of their call tree (the cascade of pops ends in an orphan
+    exit), so stacks stay shallow however long the stream is."""
+    r = np.frombuffer(np.ascontiguousarray(rec).tobytes(), dtype=FIXED24_DTYPE).copy()
+    rng = np.random.default_rng(seed)
+    ent = np.nonzero(r["kind"] == 0)[0]
+    ex = np.nonzero(r["kind"] == 1)[0]
+    ker = np.nonzero(r["kind"] == 2)[0]
+    pick = ent[rng.random(len(ent)) < p]
+    half = rng.random(len(pick)) < 0.5
+    r["kind"][pick[half]] = rng.integers(3, 256, size=int(half.sum()))
+    r["fn"][pick[~half]] = n_fns + rng.integers(0, 100, size=int((~half).sum()))
+    pick = ex[rng.random(len(ex)) < p]
+    r["fn"][pick] = (r["fn"][pick].astype(np.int64) + 1 + rng.integers(0, n_fns - 1, size=len(pick))) % n_fns
+    pick = ex[rng.random(len(ex)) < p]
+    r["ts"][pick] -= rng.integers(1, 5000, size=len(pick)).astype(np.uint64)
+    pick = ker[rng.random(len(ker)) < p]
+    r["end"][pick] = r["ts"][pick] - rng.integers(1, 1000, size=len(pick)).astype(np.uint64)
+    if lost_exits and len(ex):
+        r["kind"][rng.choice(ex, size=min(lost_exits, len(ex)), replace=False)] = 9
+    return np.frombuffer(r.tobytes(), dtype=np.uint8).copy()

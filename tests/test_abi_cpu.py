@@ -95,3 +95,17 @@ def test_package_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(tally, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(ImportError):
         tally.load()
+
+
+def test_service_with_graph_is_rejected_without_gpu(lib):
+    """The streaming form cannot be combined with graph capture: open refuses
+    it before touching the device."""
+    from paper_2504_03683_amd import tally
+    h = ctypes.c_void_p()
+    c = tally.Config()
+    c.abi_version = 1
+    c.format = 1
+    c.n_fns = 4
+    c.flags = tally.SERVICE | tally.GRAPH
+    assert lib.thapi_tally_open(ctypes.byref(c), ctypes.byref(h)) == tally.E_INVAL
+    assert not h.value

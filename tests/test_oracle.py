@@ -379,3 +379,68 @@ def test_chunk_split_invariance():
     b.finish()
     assert np.array_equal(a.rows(), b.rows())
     assert a.stats() == b.stats()
+
+
+# ---------------------------------------------------------------- intervals
+def test_intervals_closed_form():
+    """A{ B{} C{ D{} } } on one thread: each call's interval, depth and parent
+    (the call that was the stack top at its entry) by hand."""
+    ev = [(T + 100, 7, 0, ENTRY), (T + 110, 7, 1, ENTRY), (T + 130, 7, 1, EXIT),
+          (T + 150, 7, 2, ENTRY), (T + 160, 7, 3, ENTRY), (T + 190, 7, 3, EXIT),
+          (T + 200, 7, 2, EXIT), (T + 250, 7, 0, EXIT)]
+    o = oracle.Oracle(1, 4)
+    o.keep_intervals()
+    assert o.submit(KEY, fixed24(ev)) == 0
+    o.finish()
+    got = [(int(v["fn"]), int(v["depth"]), int(v["start"]) - T, int(v["end"]) - T,
+            int(v["parent_start"]) - T if v["depth"] > 1 else None, int(v["parent_fn"]))
+           for v in o.intervals()]
+    NONE = 0xFFFFFFFF
+    assert got == [(0, 1, 100, 250, None, NONE), (1, 2, 110, 130, 100, 0), (2, 2, 150, 200, 100, 0),
+                   (3, 3, 160, 190, 150, 2)]
+
+
+def test_intervals_skip_untallied_calls():
+    """Only tallied calls become intervals: a mismatched exit, a negative
+    duration and a call left open at the final flush give none."""
+    ev = [(T + 10, 1, 0, ENTRY), (T + 12, 1, 1, ENTRY), (T + 20, 1, 2, EXIT), (T + 30, 1, 0, EXIT),
+          (T + 40, 1, 3, ENTRY), (T + 35, 1, 3, EXIT), (T + 50, 1, 0, ENTRY), (T + 51, 1, 1, ENTRY),
+          (T + 52, 1, 1, EXIT)]
+    o = oracle.Oracle(1, 4)
+    o.keep_intervals()
+    assert o.submit(KEY, fixed24(ev)) == 0
+    o.finish()
+    iv = o.intervals()
+    assert [(int(v["fn"]), int(v["start"]) - T, int(v["end"]) - T, int(v["depth"])) for v in iv] == \
+        [(0, 10, 30, 1), (1, 51, 52, 2)]
+    assert int(iv[1]["parent_start"]) - T == 50 and int(iv[1]["parent_fn"]) == 0
+
+
+@pytest.mark.parametrize("k,scale", [(0, 0.02), (1, 0.001), (4, 0.005)])
+def test_intervals_match_generator_call_list(k, scale):
+    """Every interval of a closed, well-formed trace is one call the generator
+    planned, with its depth and its parent's entry time and fn."""
+    w = synth.config(k, scale=scale, want_calls=True)
+    o = oracle.Oracle(w.fmt, w.n_fns, w.n_kernel_ids, 64, w.has_size)
+    o.keep_intervals()
+    for s in w.streams:
+        assert o.submit(s.key, s.records, s.payload) == 0
+    o.finish()
+    got = o.intervals()
+    parts = []
+    for s in w.streams:
+        c = s.calls
+        v = np.zeros(len(c), dtype=oracle.IVAL_DTYPE)
+        v["trace"], v["host"], v["pid"] = s.key
+        v["tid"] = np.array(s.tid_of_thread, dtype=np.uint32)[c["thread"]]
+        v["fn"], v["depth"], v["start"], v["end"] = c["fn"], c["depth"], c["t_entry"], c["t_exit"]
+        has_p = c["parent"] >= 0
+        v["parent_start"][has_p] = c["t_entry"][c["parent"][has_p]]
+        v["parent_fn"] = 0xFFFFFFFF
+        v["parent_fn"][has_p] = c["fn"][c["parent"][has_p]]
+        parts.append(v)
+    want = np.concatenate(parts)
+    want = want[np.lexsort((want["parent_fn"], want["parent_start"], want["fn"], want["end"], want["depth"],
+                            want["start"], want["tid"], want["pid"], want["host"], want["trace"]))]
+    assert len(got) == len(want) > 1000
+    assert np.array_equal(got, want)

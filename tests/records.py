@@ -77,10 +77,15 @@ def corrupt_fixed24(rec, seed, n_fns, p=0.002, lost_exits=3):
     another fn, exits moved earlier in time, kernel records that end before
     they start, and a few exits lost (calls left open).  Damage to entries
     heals at the end of their call tree (the cascade of pops ends in an orphan
-    exit), so stacks stay shallow however long the stream is."""
+    exit), so stacks stay shallow however long the stream is.  Entries are
+    damaged only in the first 90 % of the records and the lost exits are
+    taken from the last 10 %: a damaged entry later in the same thread would
+    pop the call a lost exit left open (a fn mismatch) and so close it, but
+    none comes after them, and those calls are still open at the end."""
     r = np.frombuffer(np.ascontiguousarray(rec).tobytes(), dtype=FIXED24_DTYPE).copy()
     rng = np.random.default_rng(seed)
-    ent = np.nonzero(r["kind"] == 0)[0]
+    cut = (len(r) * 9) // 10
+    ent = np.nonzero(r["kind"][:cut] == 0)[0]
     ex = np.nonzero(r["kind"] == 1)[0]
     ker = np.nonzero(r["kind"] == 2)[0]
     pick = ent[rng.random(len(ent)) < p]
@@ -93,6 +98,7 @@ def corrupt_fixed24(rec, seed, n_fns, p=0.002, lost_exits=3):
     r["ts"][pick] -= rng.integers(1, 5000, size=len(pick)).astype(np.uint64)
     pick = ker[rng.random(len(ker)) < p]
     r["end"][pick] = r["ts"][pick] - rng.integers(1, 1000, size=len(pick)).astype(np.uint64)
-    if lost_exits and len(ex):
-        r["kind"][rng.choice(ex, size=min(lost_exits, len(ex)), replace=False)] = 9
+    late = ex[ex >= cut]
+    if lost_exits and len(late):
+        r["kind"][rng.choice(late, size=min(lost_exits, len(late)), replace=False)] = 9
     return np.frombuffer(r.tobytes(), dtype=np.uint8).copy()

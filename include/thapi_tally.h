@@ -293,6 +293,27 @@ int thapi_tally_service_info(thapi_tally *t, uint64_t *info, int n);
 int thapi_tally_export(thapi_tally *t, void *buf, size_t cap, size_t *size);
 int thapi_tally_merge(thapi_tally *t, const void *buf, size_t size);
 
+/* For callers that cannot allocate memory (code under stream capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the same work as
+ * thapi_tally_flush, with the same results and errors, but the flush's device
+ * buffers -- the work list and the range summaries -- live in a static device
+ * array of THAPI_NOALLOC_SCRATCH_BYTES that each GPU holds for the life of
+ * the process, and the call allocates no device or pinned host memory (no
+ * hipMalloc, hipFree, hipHostMalloc or graph instantiation).  The kernels
+ * are launched directly even on a THAPI_GRAPH handle.  Requires a handle
+ * opened with THAPI_DEVICE_INPUT and without THAPI_SERVICE (host input is
+ * staged in allocations that a flush frees; the service thread flushes by
+ * itself): THAPI_E_INVAL otherwise.  A flush whose summaries do not fit the
+ * array (about 68 KiB per range at max_depth 16, 260 KiB at 64; the work is
+ * cut into fewer, longer ranges first, and every chunk needs one) returns
+ * THAPI_E_NOMEM and leaves every chunk queued.  Every call on one GPU shares
+ * that GPU's array and leaves its contents behind (the work-queue head that
+ * must start at zero is re-written by each call); calls that overlapped on
+ * one GPU would race on it, so the library serialises them within the
+ * process (each process has its own copy of the array). */
+#define THAPI_NOALLOC_SCRATCH_BYTES (32u << 20)
+int thapi_tally_flush_noalloc(thapi_tally *t, uint64_t ticket, uint32_t flags);
+
 /* Frees everything.  Queued chunks that were never flushed are discarded. */
 int thapi_tally_close(thapi_tally *t);
 

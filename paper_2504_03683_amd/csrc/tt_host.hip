@@ -68,7 +68,37 @@ hipError_t launch_group_rows(const RowCtx &c, const Tables &tb, uint32_t n_group
 
 using namespace tt;
 
+// Device memory of thapi_tally_flush_noalloc: the work list and the range
+// summaries of one flush.  In host code this name is only a stand-in for the
+// symbol: host code uses the address hipGetSymbolAddress gives for each
+// device (scratch_on), never the name.
+static __device__ __align__(256) uint8_t scratch[THAPI_NOALLOC_SCRATCH_BYTES];
+
 namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+uint8_t *g_scratch[MAX_DEVICES] = {};        // the array's address on each device (null: not resolved)
+std::mutex g_noalloc_mu[MAX_DEVICES];        // one no-alloc flush at a time per device
+
+// Resolves the scratch array's address on `dev`, which must be the current
+// device; once per device (thapi_tally_open calls it).
+hipError_t scratch_setup(int dev) {
+  if (dev < 0 || dev >= MAX_DEVICES) return hipSuccess;   // (the no-alloc flush then refuses)
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (g_scratch[dev]) return hipSuccess;
+  void *p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch[dev] = (uint8_t *)p;
+  return hipSuccess;
+}
+
+uint8_t *scratch_on(int dev) {
+  if (dev < 0 || dev >= MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  return g_scratch[dev];
+}
 
 
 struct DevBuf {
@@ -482,6 +512,7 @@ int thapi_tally_open(const thapi_tally_config *cfg, thapi_tally **out) {
       ensure_pinned(t, 64 + (24 + 8ull * ST_N) * c.max_streams) != hipSuccess)
     return bail(THAPI_E_NOMEM);
   if (prepare_range_kernels((uint32_t)(t->lds_limit - 256)) != hipSuccess) return bail(THAPI_E_DEVICE);
+  if (scratch_setup(c.device) != hipSuccess) return bail(THAPI_E_DEVICE);
   if (prepare_combine_kernel() != hipSuccess) return bail(THAPI_E_DEVICE);
   if (c.flags & THAPI_SERVICE) {
     for (auto &s : t->cst)
@@ -703,7 +734,10 @@ int thapi_tally_submit(thapi_tally *t, const thapi_stream_key *key, const void *
 namespace {
 
 
-void plan_work(const thapi_tally *t, const std::vector<Chunk> &work, const Shape &sh, Plan &pl) {
+// With max_ranges, the work list holds at most that many ranges (every
+// chunk still gets at least one; the caller checks n_seg <= max_ranges).
+void plan_work(const thapi_tally *t, const std::vector<Chunk> &work, const Shape &sh, Plan &pl,
+               uint64_t max_ranges = 0) {
   pl = Plan();
   for (auto &c : work) pl.total += c.n_rec;
   // The work list holds about rpc * n_cu ranges: with n_seg chunks, ranges of
@@ -724,7 +758,9 @@ void plan_work(const thapi_tally *t, const std::vector<Chunk> &work, const Shape
     per_stream[c.stream] += c.n_rec;
   }
   const uint64_t ncu = std::max<uint64_t>(1, (uint64_t)t->n_cu) * std::max<uint32_t>(1, sh.rpc);
-  const uint64_t target = ncu > 2 * n_seg ? ncu - n_seg : std::max<uint64_t>(1, ncu / 2);
+  uint64_t target = ncu > 2 * n_seg ? ncu - n_seg : std::max<uint64_t>(1, ncu / 2);
+  // each chunk adds at most one partial range to the total / rlen full ones
+  if (max_ranges) target = std::min<uint64_t>(target, max_ranges > n_seg ? max_ranges - n_seg : 1);
   uint64_t rlen = (pl.total + target - 1) / target;
   rlen = std::max<uint64_t>(rlen, 4ull * sh.T);
   rlen = std::min<uint64_t>(rlen, 1ull << 30);
@@ -993,10 +1029,10 @@ namespace {
 // `final`, closes every stream.  Caller holds run_mu.
 // Groups the chunks of one batch by stream (each stream's chunks stay in
 // ticket order), picks the launch shape and plans the work list.
-Shape prepare_batch(thapi_tally *t, std::vector<Chunk> &work, Plan &pl) {
+Shape prepare_batch(thapi_tally *t, std::vector<Chunk> &work, Plan &pl, uint64_t max_ranges = 0) {
   std::stable_sort(work.begin(), work.end(), [](const Chunk &a, const Chunk &b) { return a.stream < b.stream; });
   const Shape sh = shape_for(t, work);
-  plan_work(t, work, sh, pl);
+  plan_work(t, work, sh, pl, max_ranges);
   return sh;
 }
 
@@ -1016,13 +1052,16 @@ int process_batch(thapi_tally *t, std::vector<Chunk> &work, bool final, const Pl
   // streaming form: the launch waits on the device for the chunks' copies
   for (auto &c : work)
     if (c.ev >= 0) HIPCHK(hipStreamWaitEvent(t->st, t->ev_pool[c.ev], 0));
-  HIPCHK(run_pipeline(t, pl, sh, final));
+  // (the scratch variant replays no graph: instantiating one allocates)
+  const bool graph = (t->cfg.flags & THAPI_GRAPH) && !scratch;
+  if (graph) HIPCHK(run_pipeline(t, pl, sh, final));
+  else HIPCHK(launch_pipeline(t, pl, sh, final, (t->cfg.flags & THAPI_PROFILE) != 0));
   HIPCHK(ensure_pinned(t, 64));
   uint32_t *herr = (uint32_t *)t->h_pinned;
   HIPCHK(hipMemcpyAsync(herr, t->tb.err, 4, hipMemcpyDeviceToHost, t->st));
   HIPCHK(hipStreamSynchronize(t->st));
   const uint32_t err = *herr;
-  if (t->cfg.flags & THAPI_GRAPH) {
+  if (graph) {
     collect_timing(t, TM_RANGE);  // whole graph
   } else {
     if (nR) {
@@ -1148,6 +1187,52 @@ int thapi_tally_flush(thapi_tally *t, uint64_t ticket, uint32_t flags) {
 }
 
 
+
+int thapi_tally_flush_noalloc(thapi_tally *t, uint64_t ticket, uint32_t flags) {
+  if (!t) return THAPI_E_INVAL;
+  if ((t->cfg.flags & THAPI_SERVICE) || !(t->cfg.flags & THAPI_DEVICE_INPUT)) return THAPI_E_INVAL;
+  if (t->dev < 0 || t->dev >= MAX_DEVICES) return THAPI_E_INVAL;
+  uint8_t *const scr = scratch_on(t->dev);
+  if (!scr) return THAPI_E_DEVICE;
+  const bool final = (flags & THAPI_FLUSH_FINAL) != 0;
+  std::lock_guard<std::mutex> run(t->run_mu);
+  // the chunks up to `ticket` are planned first and taken off the queue only
+  // when their work fits the array (only flushes, which hold run_mu, take
+  // chunks off the queue; submits append)
+  std::vector<Chunk> work;
+  {
+    std::lock_guard<std::mutex> g(t->mu);
+    if (t->failed) return t->failed == THAPI_E_DEVICE ? THAPI_E_DEVICE : THAPI_E_STATE;
+    if (t->finalized) return THAPI_E_STATE;
+    for (auto &c : t->queue) {
+      if (c.ticket > ticket) break;
+      work.push_back(c);
+    }
+  }
+  const size_t n_take = work.size();
+  uint64_t n_seg = 0;
+  for (auto &c : work) n_seg += c.n_rec ? 1 : 0;
+  // bytes per range of the summaries (header and U / O items per slot) and
+  // of its work-list entries; a fixed part covers the segments and the
+  // 256-byte alignment of the eleven parts
+  const uint64_t D = t->cfg.max_depth;
+  const uint64_t per_range = sizeof(RHdr) * S_MAX + (sizeof(UItem) + sizeof(OItem)) * S_MAX * D +
+                             sizeof(Range) + 4 * 5 + 8;
+  const uint64_t fixed = 11 * 256 + (sizeof(Seg) + 4) * (n_seg + 1) + 12 * (n_seg + 1);
+  if (fixed >= THAPI_NOALLOC_SCRATCH_BYTES) return THAPI_E_NOMEM;
+  const uint64_t max_ranges = (THAPI_NOALLOC_SCRATCH_BYTES - fixed) / per_range;
+  if (n_seg > max_ranges) return THAPI_E_NOMEM;
+  Plan pl;
+  const Shape sh = prepare_batch(t, work, pl, max_ranges ? max_ranges : 1);
+  const PlanSizes z = plan_sizes(t, pl);
+  if (z.total() > THAPI_NOALLOC_SCRATCH_BYTES || z.pack > t->h_plan_cap) return THAPI_E_NOMEM;
+  {
+    std::lock_guard<std::mutex> g(t->mu);
+    for (size_t k = 0; k < n_take; k++) t->queue.pop_front();
+  }
+  std::lock_guard<std::mutex> dev_lock(g_noalloc_mu[t->dev]);
+  return process_batch(t, work, final, pl, sh, scr);
+}
 
 int thapi_tally_ticket_done(thapi_tally *t, uint64_t ticket, uint64_t *done_ns) {
   if (!t || !ticket) return THAPI_E_INVAL;

@@ -33,8 +33,9 @@ OK, E_INVAL, E_NOMEM, E_AGAIN, E_DEPTH, E_MALFORMED, E_DEVICE, E_BUFSZ, E_CAPACI
 ENTRY_POINTS = ["thapi_tally_open", "thapi_tally_submit", "thapi_tally_flush", "thapi_tally_read",
                 "thapi_tally_reset", "thapi_tally_close", "thapi_tally_strerror", "thapi_tally_timings",
                 "thapi_tally_autotune", "thapi_tally_ticket_done", "thapi_tally_service_info",
-                "thapi_tally_export", "thapi_tally_merge",
+                "thapi_tally_export", "thapi_tally_merge", "thapi_tally_flush_noalloc",
                 "thapi_tally_read_bandwidth"]
+NOALLOC_SCRATCH_BYTES = 32 << 20
 
 ROW_DTYPE = np.dtype([
     ("trace", "<u4"), ("host", "<u4"), ("pid", "<u4"), ("tid", "<u4"),
@@ -85,6 +86,7 @@ def load():
     lib.thapi_tally_submit.argtypes = [P, ctypes.POINTER(StreamKey), P, ctypes.c_size_t, P, ctypes.c_size_t,
                                        ctypes.POINTER(ctypes.c_uint64)]
     lib.thapi_tally_flush.argtypes = [P, ctypes.c_uint64, ctypes.c_uint32]
+    lib.thapi_tally_flush_noalloc.argtypes = [P, ctypes.c_uint64, ctypes.c_uint32]
     lib.thapi_tally_export.argtypes = [P, P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
     lib.thapi_tally_merge.argtypes = [P, P, ctypes.c_size_t]
     lib.thapi_tally_read_bandwidth.argtypes = [ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint32,
@@ -199,6 +201,18 @@ class Tally:
         rc = self._lib.thapi_tally_flush(self._h, ticket, FLUSH_FINAL if final else 0)
         self._keep = []
         return rc
+
+    def flush_noalloc_rc(self, ticket=TICKET_ALL, final=False):
+        """thapi_tally_flush_noalloc (the flush whose buffers are the library's
+        static device array); returns the raw status.  Chunks stay queued, and
+        their device buffers referenced, when it fails."""
+        rc = self._lib.thapi_tally_flush_noalloc(self._h, ticket, FLUSH_FINAL if final else 0)
+        if rc == OK:
+            self._keep = []
+        return rc
+
+    def flush_noalloc(self, ticket=TICKET_ALL, final=False):
+        return _check(self.flush_noalloc_rc(ticket, final), "flush_noalloc")
 
     def read(self, scope=SCOPE_THREAD, trace=ALL, out=None):
         """Rows of one scope (and stats).  With `out` (a ROW_DTYPE array the

@@ -298,7 +298,7 @@ def main():
     tl.close()
     del recs, pays
     if not args.no_batched:
-        out["batched_vs_per_trace"] = run_batched(args, stream, steps=min(args.steps, 10), warmup=2, autotune=False)
+        out["batched_vs_per_trace"] = run_batched(args, stream, steps=min(args.steps, 10), warmup=2, autotune=True)
     print(json.dumps(out), flush=True)
 
 

@@ -78,6 +78,8 @@ extern "C" {
 #define THAPI_SERVICE      0x40u /* streaming form: a library thread tallies chunks as they arrive
                                     (continuous batching, see thapi_tally_ticket_done); cannot be
                                     combined with THAPI_GRAPH (open returns THAPI_E_INVAL) */
+#define THAPI_INTERVALS    0x80u /* every flush also keeps the interval of each call it tallies (see
+                                    thapi_tally_intervals); not with THAPI_SERVICE */
 
 /* ---- flush / read ------------------------------------------------------ */
 #define THAPI_TICKET_ALL  UINT64_MAX
@@ -314,6 +316,35 @@ int thapi_tally_merge(thapi_tally *t, const void *buf, size_t size);
 #define THAPI_NOALLOC_SCRATCH_BYTES (32u << 20)
 int thapi_tally_flush_noalloc(thapi_tally *t, uint64_t ticket, uint32_t flags);
 
+/* Intervals (section 3.3: an interval plugin turns the entry and exit events
+ * of a call into one record spanning them; section 3.6 draws them on a
+ * timeline), materialised instead of aggregated.  With THAPI_INTERVALS, every
+ * flush keeps one record per call it tallies -- the calls completed inside its
+ * chunks and those it closed that earlier chunks or flushes opened -- until
+ * the next flush or reset: the stream key, tid, fn, depth (1 = top level),
+ * entry and exit timestamps, and the entry timestamp and fn of the parent
+ * (the call on top of the thread's stack when this one was entered; 0 and
+ * THAPI_ALL at the top level).  Calls that are not tallied (anomalies, calls
+ * still open) have no interval.  The device holds up to 32 bytes per record
+ * of the flush for them.
+ * thapi_tally_intervals writes the last flush's intervals, in no particular
+ * order (sort by trace, host, pid, tid, start, depth, end, fn, parent for a
+ * canonical one), to `out`: host memory, or device memory with
+ * THAPI_OUT_DEVICE.  *n receives the count; with capacity `cap` too small
+ * nothing is written and THAPI_E_BUFSZ is returned (THAPI_OK when out is
+ * NULL and cap is 0).  Errors: THAPI_E_INVAL, THAPI_E_BUFSZ, THAPI_E_STATE
+ * (handle opened without THAPI_INTERVALS, or failed), THAPI_E_DEVICE. */
+typedef struct {                 /* 56 bytes */
+  uint32_t trace_id, host_id, pid, tid;
+  uint32_t fn, depth;
+  uint64_t start, end;
+  uint64_t parent_start;
+  uint32_t parent_fn;
+  uint32_t pad;
+} thapi_tally_interval;
+#define THAPI_OUT_DEVICE 0x1u
+int thapi_tally_intervals(thapi_tally *t, thapi_tally_interval *out, size_t cap, size_t *n, uint32_t flags);
+
 /* Frees everything.  Queued chunks that were never flushed are discarded. */
 int thapi_tally_close(thapi_tally *t);
 
@@ -331,7 +362,8 @@ const char *thapi_tally_strerror(int code);
 
 /* THAPI_PROFILE only: per-kernel durations (ms) of the last flush and read,
  * measured with HIP events on the launch stream, in the order
- * {prepass, main, combine, final, readout}; entries that did not run are 0.
+ * {prepass, main, combine, final, readout, intervals}; entries that did not
+ * run are 0.
  * Under THAPI_GRAPH, "main" is the whole replayed graph.
  * n: capacity of ms[]; returns the number of entries written. */
 int thapi_tally_timings(thapi_tally *t, double *ms, int n);

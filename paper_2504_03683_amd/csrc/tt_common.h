@@ -44,7 +44,31 @@ struct Range {
   uint64_t begin;       // first record (index into the segment)
   uint64_t n;           // records
   uint64_t pay_begin;   // VAR16: payload offset of `begin` within the segment (filled on device)
+  uint64_t iv_base;     // intervals: first IvRec of the range (the flush's records before it)
 };
+
+// Intervals (the span from a call's entry to its exit, with its depth and
+// the call that was the stack top when it was entered).
+// A call matched inside a range, as the range kernel writes it: the depth
+// and a parent opened before the range depend on the stack the thread
+// carried into the range, which the combine finds later.  With the floor f
+// (the lowest depth the range had reached, relative to its start, when the
+// call was entered; -f = fneg) and the carried height h0, the call's depth
+// is max(0, h0 - fneg) + dl, and without IV_PARENT_SET its parent is the
+// carried frame fneg below the top, if max(0, h0 - fneg) > 0 (else none).
+struct IvRec {
+  uint64_t start, end, pstart;
+  uint16_t fn, pfn;     // pfn / pstart: the parent, with IV_PARENT_SET
+  uint8_t slot;         // range-local thread slot
+  uint8_t dl;           // levels above the floor (>= 1; capped at 255)
+  uint8_t fneg;         // -floor (capped at 255)
+  uint8_t flags;
+};
+enum : uint8_t { IV_PARENT_SET = 1u };
+// A call the combine closed (opened before its range): complete.
+struct CIval { uint64_t start, end, pstart; uint32_t gslot, depth, fn, pfn; };
+// One frame of the stack a thread carried into a range, top first.
+struct IvFrame { uint64_t ts; uint32_t fn, pad; };
 
 // Summary a range leaves for one of its threads (the boundary of the range):
 // exits that closed calls opened before the range (U items, in order), the
@@ -113,6 +137,14 @@ struct Tables {
   unsigned long long *sstats;  // [max_streams][ST_N]
   uint32_t *err;
   const uint8_t *has_size;     // [n_fns] or null
+  // intervals of the current flush (all null when they are not kept)
+  IvRec *iv;                   // range r writes from its iv_base
+  uint32_t *iv_n;              // [ranges] IvRecs written
+  uint32_t *iv_h0;             // [ranges][S_MAX] carried height at the range start (combine)
+  IvFrame *iv_snap;            // [ranges][S_MAX][D] that stack, top first (combine)
+  CIval *civ;                  // calls closed by the combine
+  uint32_t *civ_n;             // their count (zero at launch)
+  uint32_t civ_cap;
 };
 
 // Launch shape of the range kernel (tile of T records, LDS tally of E entries).

@@ -43,6 +43,8 @@ hipError_t launch_init_all(const InitSet &is, hipStream_t st);
 hipError_t launch_combine(const uint32_t *spans, uint32_t n_spans, const RHdr *rhdr, const UItem *ru,
                           const OItem *ro, const uint32_t *rnslots, const Tables &tb, hipStream_t st);
 hipError_t launch_final(const Tables &tb, uint32_t max_threads, hipStream_t st);
+hipError_t launch_iv_out(const Tables &tb, const Range *ranges, const RHdr *rhdr, uint32_t n_ranges,
+                         const uint64_t *off, const uint32_t *skeys, void *out, hipStream_t st);
 hipError_t launch_thread_stats(const Tables &tb, uint32_t max_threads, unsigned long long *out, uint32_t ns,
                                uint32_t ns1, hipStream_t st);
 hipError_t launch_sort_threads(const Tables &tb, const uint32_t *stream_rank, uint64_t *keys, uint32_t *vals,
@@ -195,7 +197,7 @@ struct FlushBufs {
   uint64_t *paylen = nullptr;
 };
 
-enum { TM_PREPASS = 0, TM_RANGE, TM_COMBINE, TM_FINAL, TM_READOUT, TM_N };
+enum { TM_PREPASS = 0, TM_RANGE, TM_COMBINE, TM_FINAL, TM_READOUT, TM_IVOUT, TM_N };
 
 }  // namespace
 
@@ -228,6 +230,11 @@ struct thapi_tally {
   Shape shape{};
 
   DevBuf rhdr, ru, ro, rnslots, paylen;
+  // THAPI_INTERVALS: the current flush's interval buffers (see Tables), the
+  // public records of the last intervals() call and its offsets / keys
+  DevBuf iv, iv_n, iv_h0, iv_snap, civ, civ_n, ivout, ivaux;
+  uint32_t iv_nranges = 0;                            // ranges of the last flush
+  bool iv_valid = false;                              // the interval buffers hold the last flush's
   DevBuf plan_pack;                                   // the work list, uploaded in one copy
   FlushBufs fb;                                       // the current flush's device addresses
   DevBuf keys, vals, keys2, vals2, gbeg, gend, cnt, off, rows, tstats;
@@ -245,7 +252,7 @@ struct thapi_tally {
   std::map<std::string, std::array<uint32_t, 4>> tuned;  // autotuned {T, E, rpc, pipe} per workload class
   bool flushed_any = false;
   hipGraphExec_t gexec = nullptr;                     // THAPI_GRAPH: the captured pipeline
-  std::array<uint64_t, 16> gsig{};
+  std::array<uint64_t, 22> gsig{};
   uint64_t graph_builds = 0, graph_launches = 0;
   std::string cache_path;
 
@@ -318,7 +325,8 @@ void free_all(thapi_tally *t) {
   for (void *p : ps) if (p) hipFree(p);
   DevBuf *bs[] = {&t->plan_pack, &t->rhdr, &t->ru, &t->ro, &t->rnslots, &t->paylen, &t->keys, &t->vals, &t->keys2,
                   &t->vals2, &t->gbeg, &t->gend, &t->cnt, &t->off, &t->read_pack, &t->rows, &t->tstats,
-                  &t->merge_buf};
+                  &t->merge_buf, &t->iv, &t->iv_n, &t->iv_h0, &t->iv_snap, &t->civ, &t->civ_n, &t->ivout,
+                  &t->ivaux};
   for (DevBuf *b : bs) b->release();
   for (auto &c : t->queue) if (c.owned) hipFree(c.owned);
   t->queue.clear();
@@ -430,6 +438,8 @@ int thapi_tally_open(const thapi_tally_config *cfg, thapi_tally **out) {
   // the streaming form's batches differ in size from one to the next, so a
   // captured graph would be rebuilt for nearly every batch: not offered
   if ((cfg->flags & THAPI_SERVICE) && (cfg->flags & THAPI_GRAPH)) return THAPI_E_INVAL;
+  // intervals are kept per flush; the service flushes on its own schedule
+  if ((cfg->flags & THAPI_SERVICE) && (cfg->flags & THAPI_INTERVALS)) return THAPI_E_INVAL;
   thapi_tally *t = new (std::nothrow) thapi_tally();
   if (!t) return THAPI_E_NOMEM;
   t->cfg = *cfg;
@@ -789,6 +799,10 @@ void plan_work(const thapi_tally *t, const std::vector<Chunk> &work, const Shape
     }
   }
   pl.segfirst.push_back((uint32_t)pl.ranges.size());
+  {
+    uint64_t acc = 0;   // intervals: each range may write one per record, from here
+    for (auto &r : pl.ranges) { r.iv_base = acc; acc += r.n; }
+  }
   // longest first: the persistent workgroups take them in this order, so the
   // short ranges fill in at the end (LPT scheduling)
   pl.order.resize(pl.ranges.size());
@@ -907,6 +921,34 @@ hipError_t upload_plan(thapi_tally *t, const Plan &pl, uint8_t *scratch = nullpt
   return hipSuccess;
 }
 
+// THAPI_INTERVALS: sizes the interval buffers for the planned flush and
+// points the tables at them (each range may write one IvRec per record; the
+// combine at most one interval per U item it folds).
+hipError_t prepare_intervals(thapi_tally *t, const Plan &pl) {
+  Tables &tb = t->tb;
+  if (!(t->cfg.flags & THAPI_INTERVALS)) return hipSuccess;
+  const size_t nR = std::max<size_t>(pl.ranges.size(), 1), D = t->cfg.max_depth;
+  const size_t pairs = nR * S_MAX;
+  const size_t ccap = std::min<size_t>(pairs * D, 0xFFFFFFF0u);
+  hipError_t e;
+  if ((e = t->iv.ensure(sizeof(IvRec) * std::max<uint64_t>(pl.total, 1))) != hipSuccess) return e;
+  if ((e = t->iv_n.ensure(4 * nR)) != hipSuccess) return e;
+  if ((e = t->iv_h0.ensure(4 * pairs)) != hipSuccess) return e;
+  if ((e = t->iv_snap.ensure(sizeof(IvFrame) * pairs * D)) != hipSuccess) return e;
+  if ((e = t->civ.ensure(sizeof(CIval) * ccap)) != hipSuccess) return e;
+  if ((e = t->civ_n.ensure(4)) != hipSuccess) return e;
+  tb.iv = t->iv.as<IvRec>();
+  tb.iv_n = t->iv_n.as<uint32_t>();
+  tb.iv_h0 = t->iv_h0.as<uint32_t>();
+  tb.iv_snap = t->iv_snap.as<IvFrame>();
+  tb.civ = t->civ.as<CIval>();
+  tb.civ_n = t->civ_n.as<uint32_t>();
+  tb.civ_cap = (uint32_t)ccap;
+  t->iv_nranges = (uint32_t)pl.ranges.size();
+  t->iv_valid = true;
+  return hipSuccess;
+}
+
 // The kernels of one flush, in stream order.  `timed` records the per-kernel
 // events (not used under graph capture).
 hipError_t launch_pipeline(thapi_tally *t, const Plan &pl, const Shape &sh, bool final, bool timed) {
@@ -918,6 +960,7 @@ hipError_t launch_pipeline(thapi_tally *t, const Plan &pl, const Shape &sh, bool
 #define TB(k) do { if (timed) LPCHK(timed_begin(t, k)); } while (0)
 #define TE(k) do { if (timed) LPCHK(timed_end(t, k)); } while (0)
   LPCHK(launch_fill32(t->tb.err, 1, 0, t->st));
+  if (t->tb.civ_n) LPCHK(launch_fill32(t->tb.civ_n, 1, 0, t->st));
   if (nR) {
     if (t->cfg.format == THAPI_FMT_VAR16) {
       TB(TM_PREPASS);
@@ -948,8 +991,12 @@ hipError_t launch_pipeline(thapi_tally *t, const Plan &pl, const Shape &sh, bool
 hipError_t run_pipeline(thapi_tally *t, const Plan &pl, const Shape &sh, bool final) {
   const bool prof = (t->cfg.flags & THAPI_PROFILE) != 0;
   if (!(t->cfg.flags & THAPI_GRAPH)) return launch_pipeline(t, pl, sh, final, prof);
-  const std::array<uint64_t, 16> sig = {pl.ranges.size(), pl.segs.size(), pl.spans.size(), sh.T, sh.E,
-                                        sh.rpc | ((uint64_t)sh.pipe << 32), final ? 1u : 0u, (uint64_t)(uintptr_t)t->fb.segs,
+  const std::array<uint64_t, 22> sig = {pl.ranges.size(), pl.segs.size(), pl.spans.size(), sh.T, sh.E,
+                                        sh.rpc | ((uint64_t)sh.pipe << 32), final ? 1u : 0u,
+                                        (uint64_t)(uintptr_t)t->tb.iv, (uint64_t)(uintptr_t)t->tb.civ,
+                                        (uint64_t)(uintptr_t)t->tb.iv_n, (uint64_t)(uintptr_t)t->tb.iv_h0,
+                                        (uint64_t)(uintptr_t)t->tb.iv_snap, (uint64_t)(uintptr_t)t->tb.civ_n,
+                                        (uint64_t)(uintptr_t)t->fb.segs,
                                         (uint64_t)(uintptr_t)t->fb.ranges, (uint64_t)(uintptr_t)t->fb.order,
                                         (uint64_t)(uintptr_t)t->fb.rhdr, (uint64_t)(uintptr_t)t->fb.ru,
                                         (uint64_t)(uintptr_t)t->fb.ro, (uint64_t)(uintptr_t)t->fb.rnslots,
@@ -1049,6 +1096,7 @@ int process_batch(thapi_tally *t, std::vector<Chunk> &work, bool final, const Pl
   const uint32_t nR = (uint32_t)pl.ranges.size();
   int rc = THAPI_OK;
   if (nR) HIPCHK(upload_plan(t, pl, scratch));
+  HIPCHK(prepare_intervals(t, pl));
   // streaming form: the launch waits on the device for the chunks' copies
   for (auto &c : work)
     if (c.ev >= 0) HIPCHK(hipStreamWaitEvent(t->st, t->ev_pool[c.ev], 0));
@@ -1190,7 +1238,7 @@ int thapi_tally_flush(thapi_tally *t, uint64_t ticket, uint32_t flags) {
 
 int thapi_tally_flush_noalloc(thapi_tally *t, uint64_t ticket, uint32_t flags) {
   if (!t) return THAPI_E_INVAL;
-  if ((t->cfg.flags & THAPI_SERVICE) || !(t->cfg.flags & THAPI_DEVICE_INPUT)) return THAPI_E_INVAL;
+  if ((t->cfg.flags & (THAPI_SERVICE | THAPI_INTERVALS)) || !(t->cfg.flags & THAPI_DEVICE_INPUT)) return THAPI_E_INVAL;
   if (t->dev < 0 || t->dev >= MAX_DEVICES) return THAPI_E_INVAL;
   uint8_t *const scr = scratch_on(t->dev);
   if (!scr) return THAPI_E_DEVICE;
@@ -1290,6 +1338,7 @@ int thapi_tally_autotune(thapi_tally *t, uint32_t reps, uint32_t *chosen) {
         for (uint32_t r = 0; r < reps + 1 && ok; r++) {
           hipError_t e = init_tables(t);
           if (e == hipSuccess) e = upload_plan(t, pl);
+          if (e == hipSuccess) e = prepare_intervals(t, pl);
           if (e == hipSuccess) e = hipEventRecord(e0, t->st);
           if (e == hipSuccess) e = launch_pipeline(t, pl, sh, false, false);
           if (e == hipSuccess) e = hipEventRecord(e1, t->st);
@@ -1530,6 +1579,8 @@ int thapi_tally_reset(thapi_tally *t) {
   t->failed = 0;
   t->finalized = false;
   t->flushed_any = false;
+  t->iv_nranges = 0;
+  t->iv_valid = false;
   if (service && !t->worker_running) {
     // a failure stopped the worker (it has released the lock for good once
     // worker_running is false): start a new one
@@ -1559,6 +1610,61 @@ int thapi_tally_close(thapi_tally *t) {
     free_all(t);
   }
   delete t;
+  return THAPI_OK;
+}
+
+int thapi_tally_intervals(thapi_tally *t, thapi_tally_interval *out, size_t cap, size_t *n, uint32_t flags) {
+  if (!t || !n || (cap && !out) || (flags & ~THAPI_OUT_DEVICE)) return THAPI_E_INVAL;
+  if (!(t->cfg.flags & THAPI_INTERVALS)) return THAPI_E_STATE;
+  std::lock_guard<std::mutex> run(t->run_mu);
+  {
+    std::lock_guard<std::mutex> g(t->mu);
+    if (t->failed == THAPI_E_DEVICE) return THAPI_E_DEVICE;
+    if (t->failed) return THAPI_E_STATE;
+  }
+  *n = 0;
+  if (!t->iv_valid) return THAPI_OK;
+  if (hipSetDevice(t->dev) != hipSuccess) return THAPI_E_DEVICE;
+  const uint32_t nR = t->iv_nranges;
+  // interval counts: each range's, then the combine's
+  HIPCHK(ensure_pinned(t, 4ull * (nR + 1)));
+  uint32_t *hc = (uint32_t *)t->h_pinned;
+  if (nR) HIPCHK(hipMemcpyAsync(hc, t->tb.iv_n, 4ull * nR, hipMemcpyDeviceToHost, t->st));
+  HIPCHK(hipMemcpyAsync(hc + nR, t->tb.civ_n, 4, hipMemcpyDeviceToHost, t->st));
+  HIPCHK(hipStreamSynchronize(t->st));
+  std::vector<uint64_t> off(nR + 1);
+  uint64_t total = 0;
+  for (uint32_t r = 0; r < nR; r++) { off[r] = total; total += hc[r]; }
+  off[nR] = total;
+  total += std::min<uint32_t>(hc[nR], t->tb.civ_cap);
+  *n = total;
+  if (!out) return THAPI_OK;
+  if (cap < total) return THAPI_E_BUFSZ;
+  if (!total) return THAPI_OK;
+  // offsets and stream keys up in one copy, then one conversion launch
+  std::vector<uint32_t> keys(3 * std::max<size_t>(t->stream_keys.size(), 1));
+  for (size_t i = 0; i < t->stream_keys.size(); i++)
+    for (int k = 0; k < 3; k++) keys[3 * i + k] = t->stream_keys[i][k];
+  const size_t bytes[2] = {8 * off.size(), 4 * keys.size()};
+  HIPCHK(grow_plan_staging(t, pack_bytes(bytes, 2)));
+  HIPCHK(t->ivaux.ensure(pack_bytes(bytes, 2)));
+  void *d_off = nullptr, *d_keys = nullptr;
+  void **views[2] = {&d_off, &d_keys};
+  const void *src[2] = {off.data(), keys.data()};
+  HIPCHK(stage_h2d(t, t->ivaux.as<uint8_t>(), views, src, bytes, 2));
+  const bool on_dev = (flags & THAPI_OUT_DEVICE) != 0;
+  void *dst = out;
+  if (!on_dev) {
+    HIPCHK(t->ivout.ensure(sizeof(thapi_tally_interval) * total));
+    dst = t->ivout.p;
+  }
+  HIPCHK(timed_begin(t, TM_IVOUT));
+  HIPCHK(launch_iv_out(t->tb, t->fb.ranges, t->fb.rhdr, nR, (const uint64_t *)d_off, (const uint32_t *)d_keys, dst,
+                       t->st));
+  HIPCHK(timed_end(t, TM_IVOUT));
+  if (!on_dev) HIPCHK(hipMemcpyAsync(out, dst, sizeof(thapi_tally_interval) * total, hipMemcpyDeviceToHost, t->st));
+  HIPCHK(hipStreamSynchronize(t->st));
+  collect_timing(t, TM_IVOUT);
   return THAPI_OK;
 }
 
@@ -1838,6 +1944,7 @@ int thapi_tally_merge(thapi_tally *t, const void *buf, size_t size) {
     }
     t->gen++;
     t->flushed_any = true;
+    t->iv_valid = false;   // (a merge tallies no call of a flush)
   }
   HIPCHK(launch_fill32(t->tb.err, 1, 0, t->st));
   HIPCHK(launch_merge(tb, (const MThread *)(d + o_th), (uint32_t)nth, (const Frame *)(d + o_fr),

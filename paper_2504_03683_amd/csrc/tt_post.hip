@@ -15,6 +15,18 @@ __device__ inline void gmax64(uint64_t *p, uint64_t v) {
   __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Intervals: a call the combine closes (its frame at stack position pos, its
+// parent the frame below, if any).
+__device__ inline void emit_civ(const Tables &tb, const uint32_t g, const uint32_t pos, const uint64_t start,
+                                const uint64_t end, const uint32_t fn, const Frame *stk) {
+  CIval c;
+  c.start = start; c.end = end; c.gslot = g; c.depth = pos + 1; c.fn = fn;
+  if (pos > 0) { c.pstart = stk[pos - 1].ts; c.pfn = stk[pos - 1].fn; }
+  else { c.pstart = 0; c.pfn = EMPTY32; }
+  const uint32_t i = atomicAdd(tb.civ_n, 1u);
+  if (i < tb.civ_cap) tb.civ[i] = c;
+}
+
 // ---------------------------------------------------------------- combine
 // One workgroup per stream that had ranges in this flush.  Each distinct
 // thread of the stream is owned by one lane (a group of 8 lanes when the
@@ -195,6 +207,15 @@ __global__ __launch_bounds__(256) void k_combine(const uint32_t *__restrict__ sp
           const int32_t ds = (int32_t)cs.h;
           if ((hd.flags & RF_OVERFLOW) || hd.H > (int32_t)D || ds + hd.M > (int32_t)D) cs.flags |= CS_OVERFLOW;
           const uint32_t h0 = cs.h, nu = hd.nu_listed;
+          if (tb.iv_h0) {
+            // intervals: the stack this thread carried into the range, top first
+            const size_t rs = (size_t)r * S_MAX + sl;
+            if (j == 0) tb.iv_h0[rs] = h0;
+            for (uint32_t k = j; k < h0; k += CG) {
+              const Frame &f = stk[h0 - 1 - k];
+              tb.iv_snap[rs * D + k] = IvFrame{f.ts, f.fn, 0u};
+            }
+          }
           uint64_t carry = 0;      // the previous chunk's last item: its time when tallied
           uint64_t last = 0;       // the range's last U item: its time when tallied
           for (uint32_t k0 = 0; k0 < nu; k0 += CG) {
@@ -210,7 +231,10 @@ __global__ __launch_bounds__(256) void k_combine(const uint32_t *__restrict__ sp
                 const Frame e = stk[h0 - 1 - k];
                 if (e.fn != u.fn || u.fn >= tb.n_fns) c_mis++;
                 else if (u.ts < e.ts) c_neg++;
-                else { ok = true; incl = u.ts - e.ts; uchild = u.child; echild = e.child; bytes = e.bytes; fn = u.fn; }
+                else {
+                  ok = true; incl = u.ts - e.ts; uchild = u.child; echild = e.child; bytes = e.bytes; fn = u.fn;
+                  if (tb.civ) emit_civ(tb, g, h0 - 1 - k, e.ts, u.ts, u.fn, stk);
+                }
               }
             }
             const uint64_t mine = ok ? incl : 0;
@@ -278,7 +302,12 @@ __global__ __launch_bounds__(256) void k_combine(const uint32_t *__restrict__ sp
       auto fold_thread = [&](Frame *stk) {
         // one range summary onto the carried stack; uat(k) / oat(k) give its
         // U / O items (read four at a time)
-        auto fold_one = [&](const RHdr &hd, auto &&uat, auto &&oat) {
+        auto fold_one = [&](const RHdr &hd, const size_t rs, auto &&uat, auto &&oat) {
+          if (tb.iv_h0) {
+            // intervals: the stack this thread carried into the range, top first
+            tb.iv_h0[rs] = cs.h;
+            for (uint32_t k = 0; k < cs.h; k++) tb.iv_snap[rs * D + k] = IvFrame{stk[cs.h - 1 - k].ts, stk[cs.h - 1 - k].fn, 0u};
+          }
           if (hd.flags & RF_HAS_TS) {
             if ((cs.flags & CS_HAS_TS) && hd.first_ts < cs.last_ts) c_tsreg++;
             cs.last_ts = hd.last_ts;
@@ -309,6 +338,7 @@ __global__ __launch_bounds__(256) void k_combine(const uint32_t *__restrict__ sp
               ga64(&t->incl_sum, incl); gmin64(&t->incl_min, incl); gmax64(&t->incl_max, incl);
               ga64(&t->self_sum, self); gmin64(&t->self_min, self); gmax64(&t->self_max, self);
               if (e.bytes) ga64(&t->bytes_sum, e.bytes);
+              if (tb.civ) emit_civ(tb, g, cs.h, e.ts, u.ts, u.fn, stk);
               if (cs.h > 0) stk[cs.h - 1].child += incl;
             }
           }
@@ -340,7 +370,8 @@ __global__ __launch_bounds__(256) void k_combine(const uint32_t *__restrict__ sp
             const RHdr hd = hdrL[x];
             const UItem *lu = (const UItem *)(itL + (size_t)offL[x] * 32);
             const OItem *lo = (const OItem *)(lu + hd.nu_listed);
-            fold_one(hd, [&](uint32_t k) { return lu[k]; }, [&](uint32_t k) { return lo[k]; });
+            fold_one(hd, (size_t)r * S_MAX + smap[x], [&](uint32_t k) { return lu[k]; },
+                     [&](uint32_t k) { return lo[k]; });
           }
         } else {
           // slot of this thread in range r's summaries, S_MAX when it has none
@@ -373,7 +404,8 @@ __global__ __launch_bounds__(256) void k_combine(const uint32_t *__restrict__ sp
             uint32_t sl2 = 0;
             const uint32_t r2 = next_range(r + 1, sl2);
             if (r2 < re) hd_next = rhdr[(size_t)r2 * S_MAX + sl2];
-            fold_one(hd, [&](uint32_t k) { return ru[ib + k]; }, [&](uint32_t k) { return ro[ib + k]; });
+            fold_one(hd, (size_t)r * S_MAX + sl, [&](uint32_t k) { return ru[ib + k]; },
+                     [&](uint32_t k) { return ro[ib + k]; });
             r = r2;
             sl = sl2;
           }
@@ -400,6 +432,65 @@ __global__ __launch_bounds__(256) void k_combine(const uint32_t *__restrict__ sp
   if (c_under) atomicAdd(&lcnt[ST_UNDER], c_under);
   __syncthreads();
   if (tid < ST_N && lcnt[tid]) atomicAdd(&tb.sstats[(size_t)stream * ST_N + tid], (unsigned long long)lcnt[tid]);
+}
+
+// ------------------------------------------------------------- intervals
+// The public interval record (thapi_tally_interval).
+struct IvOut { uint32_t trace, host, pid, tid, fn, depth; uint64_t start, end, pstart; uint32_t pfn, pad; };
+
+// One flush's intervals in the public layout.  Blocks [0, n_ranges): range
+// r's IvRecs go to out + off[r], their depth and a parent opened before the
+// range resolved from the stack the combine recorded for the range's thread;
+// the other blocks: the combine's own intervals go to out + off[n_ranges].
+// skeys: (trace, host, pid) of each stream.
+__global__ __launch_bounds__(256) void k_iv_out(Tables tb, const Range *__restrict__ ranges,
+                                                const RHdr *__restrict__ rhdr, const uint32_t n_ranges,
+                                                const uint64_t *__restrict__ off, const uint32_t *__restrict__ skeys,
+                                                IvOut *__restrict__ out) {
+  const uint32_t D = tb.D;
+  auto key_of = [&](const uint32_t g, IvOut &o) {
+    if (g < tb.max_threads) {
+      const uint32_t st = tb.th_stream[g];
+      o.trace = skeys[3 * st]; o.host = skeys[3 * st + 1]; o.pid = skeys[3 * st + 2]; o.tid = tb.th_tid[g];
+    } else {
+      o.trace = o.host = o.pid = o.tid = EMPTY32;
+    }
+  };
+  if (blockIdx.x < n_ranges) {
+    const uint32_t r = blockIdx.x, n = tb.iv_n[r];
+    const IvRec *src = tb.iv + ranges[r].iv_base;
+    IvOut *dst = out + off[r];
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+      const IvRec v = src[i];
+      const size_t rs = (size_t)r * S_MAX + v.slot;
+      const uint32_t h0 = tb.iv_h0[rs];
+      const uint32_t base = h0 > v.fneg ? h0 - v.fneg : 0u;   // height below the floor, if any
+      IvOut o;
+      key_of(rhdr[rs].gslot, o);
+      o.fn = v.fn; o.depth = base + v.dl; o.start = v.start; o.end = v.end; o.pad = 0;
+      if (v.flags & IV_PARENT_SET) {
+        o.pstart = v.pstart; o.pfn = v.pfn;
+      } else if (base > 0) {
+        const IvFrame f = tb.iv_snap[rs * D + v.fneg];   // position base - 1, fneg below the top
+        o.pstart = f.ts; o.pfn = f.fn;
+      } else {
+        o.pstart = 0; o.pfn = EMPTY32;
+      }
+      dst[i] = o;
+    }
+  } else {
+    const uint32_t n = *tb.civ_n < tb.civ_cap ? *tb.civ_n : tb.civ_cap;
+    IvOut *dst = out + off[n_ranges];
+    const uint32_t nb = gridDim.x - n_ranges;
+    for (uint32_t i = (blockIdx.x - n_ranges) * blockDim.x + threadIdx.x; i < n; i += nb * blockDim.x) {
+      const CIval c = tb.civ[i];
+      IvOut o;
+      key_of(c.gslot, o);
+      o.fn = c.fn; o.depth = c.depth; o.start = c.start; o.end = c.end; o.pstart = c.pstart; o.pfn = c.pfn;
+      o.pad = 0;
+      dst[i] = o;
+    }
+  }
 }
 
 // Final flush: every call still open is counted as unclosed and forgotten.
@@ -807,6 +898,13 @@ hipError_t launch_combine(const uint32_t *spans, uint32_t n_spans, const RHdr *r
   if (n_spans) hipLaunchKernelGGL(k_combine, dim3(n_spans), dim3(256), CB_DYN, st, spans, rhdr, ru, ro, rnslots, tb);
   return hipGetLastError();
 }
+hipError_t launch_iv_out(const Tables &tb, const Range *ranges, const RHdr *rhdr, uint32_t n_ranges,
+                         const uint64_t *off, const uint32_t *skeys, void *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_iv_out, dim3(n_ranges + 64), dim3(256), 0, st, tb, ranges, rhdr, n_ranges, off, skeys,
+                     (IvOut *)out);
+  return hipGetLastError();
+}
+
 hipError_t launch_final(const Tables &tb, uint32_t max_threads, hipStream_t st) {
   hipLaunchKernelGGL(k_final, dim3((max_threads + 255) / 256), dim3(256), 0, st, tb);
   return hipGetLastError();

@@ -187,6 +187,8 @@ __device__ inline void g_max64(uint64_t *p, uint64_t v) {
 // 8-byte loads and a funnel shift (the aligned words lie in the allocation's
 // granule, so they never cross it).
 typedef const __attribute__((address_space(1))) uint64_t gu64;  // global-memory view (no flat accesses)
+typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) u64x2 gu64x2;
 
 __device__ inline uint64_t load_u64_unaligned(const uint8_t *base, uint64_t off) {
   const uintptr_t a = (uintptr_t)(base + off);
@@ -350,12 +352,13 @@ struct SlotState {
 // The lane's record (ts, fk, by) was loaded by the caller ahead of time; the
 // records of one window may come from two consecutive tiles.
 // wvt[0] holds the children time of the call at the floor across windows.
-template <int FMT>
+template <int FMT, bool IV>
 __device__ __forceinline__ void slot_window(RangeLds &L, const Tables &tb, const uint32_t E, const uint32_t D,
                                             const uint32_t s, const uint32_t gslot,
                                             const uint32_t nw, const uint64_t ts, const uint32_t fk,
                                             const uint64_t by, SlotState &S, UItem *__restrict__ us,
-                                            uint64_t *__restrict__ wch, uint64_t *__restrict__ wvt) {
+                                            uint64_t *__restrict__ wch, uint64_t *__restrict__ wvt,
+                                            IvRec *__restrict__ ivr) {
   const uint32_t lane = __lane_id();
   const bool valid = lane < nw;
   const uint32_t fn = fk & 0xFFFFu;
@@ -501,6 +504,44 @@ __device__ __forceinline__ void slot_window(RangeLds &L, const Tables &tb, const
       tally_call<FMT>(L, E, tb, s, gslot, fn, incl, self, pby);
     }
   }
+  // intervals: every call tallied here, with its parent when that is in the
+  // window or on the carried stack; depth and a parent opened before the
+  // range are left relative to the floor at the call's entry (the lowest
+  // depth before this exit: no depth below the call's level occurs while it
+  // is open, so the floor is the same at its entry)
+  if constexpr (IV) {
+    const bool emit = ok && fn < tb.n_fns;
+    const uint64_t em = ballot(emit);
+    const int32_t psrc2 = parent >= 0 ? parent : 0;
+    const uint64_t pts_w = bperm64((uint32_t)ts, (uint32_t)(ts >> 32), psrc2);
+    const uint32_t pfn_w = (uint32_t)__builtin_amdgcn_ds_bpermute(psrc2 << 2, (int32_t)fk) & 0xFFFFu;
+    const int32_t f = imin(fl0, dpp<0x138>(BIG, pmin));
+    if (em) {
+      const int32_t pl = lev - 1;
+      const uint32_t pp = (uint32_t)(pl - fl0 - 1);
+      const bool p_w = parent >= 0;
+      const bool p_c = !p_w && pl > fl0 && pp < D;
+      const uint32_t pci = s * D + (p_c ? pp : 0u);
+      const uint64_t pcts = cfr[pci].ts;
+      const uint32_t pcfn = cfr[pci].fn;
+      uint32_t base = 0;
+      if (lane == 0)
+        base = __hip_atomic_fetch_add(&L.misc[6], (uint32_t)__popcll(em), __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_WORKGROUP);
+      base = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)base);
+      if (emit) {
+        const uint32_t dl = (uint32_t)imin(lev - f, 255), fneg = (uint32_t)imin(-f, 255);
+        const uint64_t pst = p_w ? pts_w : (p_c ? pcts : 0ull);
+        const uint32_t pfn = p_w ? pfn_w : (p_c ? pcfn : 0u);
+        const uint64_t w3 = (uint64_t)fn | ((uint64_t)(pfn & 0xFFFFu) << 16) | ((uint64_t)s << 32) |
+                            ((uint64_t)dl << 40) | ((uint64_t)fneg << 48) |
+                            ((uint64_t)((p_w || p_c) ? IV_PARENT_SET : 0u) << 56);
+        gu64x2 *d = (gu64x2 *)(ivr + base + (uint32_t)__popcll(em & lt));
+        __builtin_nontemporal_store(u64x2{pts, ts}, d);
+        __builtin_nontemporal_store(u64x2{pst, w3}, d + 1);
+      }
+    }
+  }
   // exits that close calls opened before the range become U items
   if (ballot(pre)) {
     if (pre) {
@@ -637,11 +678,11 @@ __device__ __forceinline__ void slot_store(RangeLds &L, WalkCache &c, const uint
 // Walks the cached slot's deferred records followed by records [b, e) of the
 // tile region, in windows of WAVE records.  With `defer`, a last partial
 // window that lies within [b, e) is kept for the next tile instead.
-template <int FMT>
+template <int FMT, bool IV>
 __device__ __forceinline__ void slot_walk(RangeLds &L, const Tables &tb, const uint32_t E, const uint32_t D,
                                           WalkCache &c, const uint32_t b, const uint32_t e, const bool defer,
                                           const size_t sbase, UItem *__restrict__ ru, uint64_t *__restrict__ wch,
-                                          uint64_t *__restrict__ wvt) {
+                                          uint64_t *__restrict__ wvt, IvRec *__restrict__ ivr) {
   const uint32_t s = c.slot;
   UItem *us = ru + (sbase + s) * D;
   const uint32_t lane = __lane_id();
@@ -667,8 +708,8 @@ __device__ __forceinline__ void slot_walk(RangeLds &L, const Tables &tb, const u
       p = vn < nwalk ? b + (vn - pend) + (lane < nwalk - vn ? lane : 0u) : (b < last ? b : last);
       const uint64_t ts_n = L.tile_ts[p], by_n = FMT == 2 ? L.tile_by[p] : 0;
       const uint32_t fk_n = L.tile_fk[p];
-      slot_window<FMT>(L, tb, E, D, s, c.gslot, (nwalk - v0) < WAVE ? (nwalk - v0) : WAVE, ts, fk, by, c.S, us,
-                       wch, wvt);
+      slot_window<FMT, IV>(L, tb, E, D, s, c.gslot, (nwalk - v0) < WAVE ? (nwalk - v0) : WAVE, ts, fk, by, c.S,
+                           us, wch, wvt, ivr);
       ts = ts_n; fk = fk_n; by = by_n;
     }
   }
@@ -686,11 +727,11 @@ __device__ __forceinline__ void slot_walk(RangeLds &L, const Tables &tb, const u
 // the thread slots w, w + nww, ... (nww walking waves), each slot's records in
 // order.  With `defer`, the last slot's partial last window may wait for the
 // next tile (WalkCache); any other deferred records are walked here.
-template <int FMT>
+template <int FMT, bool IV>
 __device__ __forceinline__ void walk_tile(RangeLds &L, const Tables &tb, const uint32_t E, const uint32_t D,
                                           const uint32_t hb, const uint32_t half, const uint32_t nww,
                                           const bool defer, const size_t sbase, UItem *__restrict__ ru,
-                                          WalkCache &c) {
+                                          WalkCache &c, IvRec *__restrict__ ivr) {
   const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));   // (wave-uniform)
   const uint32_t *soff = L.soff + hb * (S_MAX + 1);
   const uint32_t base = hb * half;
@@ -701,22 +742,23 @@ __device__ __forceinline__ void walk_tile(RangeLds &L, const Tables &tb, const u
     const uint32_t b = base + soff[s], e = base + soff[s + 1];
     if (c.slot != s) {
       if (b == e) continue;
-      if (c.pend) slot_walk<FMT>(L, tb, E, D, c, b, b, false, sbase, ru, wch, wvt);
+      if (c.pend) slot_walk<FMT, IV>(L, tb, E, D, c, b, b, false, sbase, ru, wch, wvt, ivr);
       slot_store(L, c, wvt);
       slot_load(L, s, c, wvt);
     }
     if (b == e && !c.pend) continue;
-    slot_walk<FMT>(L, tb, E, D, c, b, e, defer && s + nww >= nslots, sbase, ru, wch, wvt);
+    slot_walk<FMT, IV>(L, tb, E, D, c, b, e, defer && s + nww >= nslots, sbase, ru, wch, wvt, ivr);
   }
 }
 
 // Walks what the cached slot still defers, then puts its state back to LDS.
-template <int FMT>
+template <int FMT, bool IV>
 __device__ __forceinline__ void walk_finish(RangeLds &L, const Tables &tb, const uint32_t E, const uint32_t D,
-                                            const size_t sbase, UItem *__restrict__ ru, WalkCache &c) {
+                                            const size_t sbase, UItem *__restrict__ ru, WalkCache &c,
+                                            IvRec *__restrict__ ivr) {
   const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
   uint64_t *wch = L.w_ch + w * WAVE, *wvt = L.w_vt + w * (D + 1);
-  if (c.slot != EMPTY32 && c.pend) slot_walk<FMT>(L, tb, E, D, c, 0, 0, false, sbase, ru, wch, wvt);
+  if (c.slot != EMPTY32 && c.pend) slot_walk<FMT, IV>(L, tb, E, D, c, 0, 0, false, sbase, ru, wch, wvt, ivr);
   slot_store(L, c, wvt);
 }
 
@@ -1025,7 +1067,7 @@ __device__ __forceinline__ void front_tile(RangeLds &L, const Tables &tb, const 
 // waves 0 .. RNW/2-1 (walkers) walk the previous one; a tile is handed over
 // through LDS counters: every producer wave counts each tile it finished,
 // every walker publishes the tiles it has walked.
-template <int FMT, int ROWS, bool PIPE>
+template <int FMT, int ROWS, bool PIPE, bool IV>
 __device__ __forceinline__ void range_body(RangeLds &L, const Seg *__restrict__ segs,
                                            const Range *__restrict__ ranges, const uint32_t rid, const Tables &tb,
                                            const Shape &sh, RHdr *__restrict__ rhdr, UItem *__restrict__ ru,
@@ -1060,6 +1102,7 @@ __device__ __forceinline__ void range_body(RangeLds &L, const Seg *__restrict__ 
 
   const size_t sbase = (size_t)rid * S_MAX;
   const uint64_t ntiles = (rg.n + T - 1) / T;
+  IvRec *const ivr = IV ? tb.iv + rg.iv_base : nullptr;
   if (!PIPE || w >= (int)GW) {
     // tile builder: two register buffers of raw record words alternate
     // between tiles; the loads are unconditional (index clamped to the range)
@@ -1094,7 +1137,7 @@ __device__ __forceinline__ void range_body(RangeLds &L, const Seg *__restrict__ 
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         if (lane == 0) __hip_atomic_fetch_add(&L.misc[5], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
       }
-      else walk_tile<FMT>(L, tb, E, D, 0, T, RNW, false, sbase, ru, wcache);
+      else walk_tile<FMT, IV>(L, tb, E, D, 0, T, RNW, false, sbase, ru, wcache, ivr);
       if (!PIPE) __syncthreads();
 #pragma unroll
       for (int r = 0; r < ROWS; r++) { a0[r] = b0[r]; a1[r] = b1[r]; a2[r] = b2[r]; }
@@ -1113,10 +1156,10 @@ __device__ __forceinline__ void range_body(RangeLds &L, const Seg *__restrict__ 
     wcache.pend = 0;
     for (uint64_t t = 0; t < ntiles; t++) {
       wait_at_least(&L.misc[5], (uint32_t)(t + 1) * GW, tb.err);
-      walk_tile<FMT>(L, tb, E, D, (uint32_t)(t & 1), T, GW, true, sbase, ru, wcache);
+      walk_tile<FMT, IV>(L, tb, E, D, (uint32_t)(t & 1), T, GW, true, sbase, ru, wcache, ivr);
       publish(&L.misc[16 + w], (uint32_t)(t + 1), lane == 0);
     }
-    walk_finish<FMT>(L, tb, E, D, sbase, ru, wcache);
+    walk_finish<FMT, IV>(L, tb, E, D, sbase, ru, wcache, ivr);
   }
   __syncthreads();
   L.nd = L.misc[2];
@@ -1124,6 +1167,7 @@ __device__ __forceinline__ void range_body(RangeLds &L, const Seg *__restrict__ 
   // ---- range end: summaries, tally and counter flush
   const uint32_t nslots = L.misc[0];
   if (tid == 0) rnslots[rid] = nslots;
+  if (IV && tid == 0) tb.iv_n[rid] = L.misc[6];
   if ((uint32_t)tid < nslots) {
     const uint32_t s = tid;
     const SRec &r = L.srec[s];
@@ -1190,7 +1234,7 @@ __device__ __forceinline__ void range_body(RangeLds &L, const Seg *__restrict__ 
 // Persistent work-list launch: each workgroup (one per CU) takes the next
 // entry of `order` (range ids, longest first) until the list is exhausted.
 // `qhead` must be 0 at launch.
-template <int FMT, int ROWS, bool PIPE>
+template <int FMT, int ROWS, bool PIPE, bool IV>
 __global__ __launch_bounds__(RWG) void k_range(const Seg *__restrict__ segs, const Range *__restrict__ ranges,
                                                const uint32_t *__restrict__ order, const uint32_t n_ranges,
                                                uint32_t *__restrict__ qhead, Tables tb, Shape sh,
@@ -1206,7 +1250,7 @@ __global__ __launch_bounds__(RWG) void k_range(const Seg *__restrict__ segs, con
     const uint32_t q = next;
     __syncthreads();
     if (q >= n_ranges) break;
-    range_body<FMT, ROWS, PIPE>(L, segs, ranges, order[q], tb, sh, rhdr, ru, ro, rnslots);
+    range_body<FMT, ROWS, PIPE, IV>(L, segs, ranges, order[q], tb, sh, rhdr, ru, ro, rnslots);
   }
 }
 
@@ -1252,10 +1296,14 @@ __global__ void k_range_payoff(const Seg *__restrict__ segs, uint32_t n_segs, co
 // Allows every range-kernel variant up to max_lds_bytes of dynamic LDS (set
 // once, outside any stream capture).
 hipError_t prepare_range_kernels(uint32_t max_lds_bytes) {
-  const void *ks[] = {(const void *)k_range<1, 1, false>, (const void *)k_range<1, 2, false>,
-                      (const void *)k_range<2, 1, false>, (const void *)k_range<2, 2, false>,
-                      (const void *)k_range<1, 1, true>,  (const void *)k_range<1, 2, true>,
-                      (const void *)k_range<2, 1, true>,  (const void *)k_range<2, 2, true>};
+  const void *ks[] = {(const void *)k_range<1, 1, false, false>, (const void *)k_range<1, 2, false, false>,
+                      (const void *)k_range<2, 1, false, false>, (const void *)k_range<2, 2, false, false>,
+                      (const void *)k_range<1, 1, true, false>,  (const void *)k_range<1, 2, true, false>,
+                      (const void *)k_range<2, 1, true, false>,  (const void *)k_range<2, 2, true, false>,
+                      (const void *)k_range<1, 1, false, true>,  (const void *)k_range<1, 2, false, true>,
+                      (const void *)k_range<2, 1, false, true>,  (const void *)k_range<2, 2, false, true>,
+                      (const void *)k_range<1, 1, true, true>,   (const void *)k_range<1, 2, true, true>,
+                      (const void *)k_range<2, 1, true, true>,   (const void *)k_range<2, 2, true, true>};
   for (const void *k : ks) {
     hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds_bytes);
     if (e != hipSuccess) return e;
@@ -1274,11 +1322,15 @@ hipError_t launch_range(int fmt, uint32_t T, const Seg *segs, const Range *range
   dim3 grid(n_wg < n_ranges ? n_wg : n_ranges), block(RWG);
 #define TT_LAUNCH(F, ROWS_, P_)                                                                                 \
   do {                                                                                                          \
-    hipLaunchKernelGGL((k_range<F, ROWS_, P_>), grid, block, sh.lds_bytes, st, segs, ranges, order, n_ranges, \
-                       qhead, tb, sh, rhdr, ru, ro, rnslots);                                                   \
+    if (iv)                                                                                                     \
+      hipLaunchKernelGGL((k_range<F, ROWS_, P_, true>), grid, block, sh.lds_bytes, st, segs, ranges, order,    \
+                         n_ranges, qhead, tb, sh, rhdr, ru, ro, rnslots);                                       \
+    else                                                                                                        \
+      hipLaunchKernelGGL((k_range<F, ROWS_, P_, false>), grid, block, sh.lds_bytes, st, segs, ranges, order,   \
+                         n_ranges, qhead, tb, sh, rhdr, ru, ro, rnslots);                                       \
     return hipGetLastError();                                                                                   \
   } while (0)
-  const bool p = sh.pipe != 0;
+  const bool p = sh.pipe != 0, iv = tb.iv != nullptr;
   if (fmt == 1) {
     if (T == 1024) { if (p) TT_LAUNCH(1, 1, true); else TT_LAUNCH(1, 1, false); }
     if (T == 2048) { if (p) TT_LAUNCH(1, 2, true); else TT_LAUNCH(1, 2, false); }

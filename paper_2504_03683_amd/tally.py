@@ -18,7 +18,9 @@ LIB_PATH = os.path.join(HERE, "libthapi_tally.so")
 
 ABI_VERSION = 1
 FMT_FIXED24, FMT_VAR16 = 1, 2
-DEVICE_INPUT, NONBLOCKING, DROP_ON_FULL, STRICT, PROFILE, GRAPH, SERVICE = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20, 0x40
+DEVICE_INPUT, NONBLOCKING, DROP_ON_FULL, STRICT, PROFILE, GRAPH, SERVICE, INTERVALS = \
+    0x1, 0x2, 0x4, 0x8, 0x10, 0x20, 0x40, 0x80
+OUT_DEVICE = 0x1
 TICKET_ALL = (1 << 64) - 1
 FLUSH_FINAL = 0x1
 SCOPE_THREAD, SCOPE_PROCESS, SCOPE_FN, SCOPE_KERNEL = 1, 2, 3, 4
@@ -33,7 +35,7 @@ OK, E_INVAL, E_NOMEM, E_AGAIN, E_DEPTH, E_MALFORMED, E_DEVICE, E_BUFSZ, E_CAPACI
 ENTRY_POINTS = ["thapi_tally_open", "thapi_tally_submit", "thapi_tally_flush", "thapi_tally_read",
                 "thapi_tally_reset", "thapi_tally_close", "thapi_tally_strerror", "thapi_tally_timings",
                 "thapi_tally_autotune", "thapi_tally_ticket_done", "thapi_tally_service_info",
-                "thapi_tally_export", "thapi_tally_merge", "thapi_tally_flush_noalloc",
+                "thapi_tally_export", "thapi_tally_merge", "thapi_tally_flush_noalloc", "thapi_tally_intervals",
                 "thapi_tally_read_bandwidth"]
 NOALLOC_SCRATCH_BYTES = 32 << 20
 
@@ -42,6 +44,10 @@ ROW_DTYPE = np.dtype([
     ("id", "<u2"), ("row_kind", "u1"), ("pad", "u1"), ("pad2", "<u4"),
     ("count", "<u8"), ("incl_sum", "<u8"), ("incl_min", "<u8"), ("incl_max", "<u8"),
     ("self_sum", "<u8"), ("self_min", "<u8"), ("self_max", "<u8"), ("bytes_sum", "<u8"),
+])
+IVAL_DTYPE = np.dtype([
+    ("trace", "<u4"), ("host", "<u4"), ("pid", "<u4"), ("tid", "<u4"), ("fn", "<u4"), ("depth", "<u4"),
+    ("start", "<u8"), ("end", "<u8"), ("parent_start", "<u8"), ("parent_fn", "<u4"), ("pad", "<u4"),
 ])
 STAT_NAMES = ["records", "entries", "exits", "kernel_records", "orphan_exits", "fn_mismatch",
               "neg_duration", "self_underflow", "ts_regress", "unclosed_final", "open_now",
@@ -87,6 +93,7 @@ def load():
                                        ctypes.POINTER(ctypes.c_uint64)]
     lib.thapi_tally_flush.argtypes = [P, ctypes.c_uint64, ctypes.c_uint32]
     lib.thapi_tally_flush_noalloc.argtypes = [P, ctypes.c_uint64, ctypes.c_uint32]
+    lib.thapi_tally_intervals.argtypes = [P, P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t), ctypes.c_uint32]
     lib.thapi_tally_export.argtypes = [P, P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
     lib.thapi_tally_merge.argtypes = [P, P, ctypes.c_size_t]
     lib.thapi_tally_read_bandwidth.argtypes = [ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint32,
@@ -238,6 +245,22 @@ class Tally:
                                               ctypes.byref(st)), "read")
         return rows, {k: int(getattr(st, k)) for k in STAT_NAMES}
 
+    def intervals(self, out=None):
+        """The last flush's intervals (IVAL_DTYPE, in no particular order).  With
+        `out` (a torch uint8 tensor on the GPU of at least 56 bytes per
+        interval) they are written there and the count is returned instead."""
+        n = ctypes.c_size_t(0)
+        _check(self._lib.thapi_tally_intervals(self._h, None, 0, ctypes.byref(n), 0), "intervals")
+        if out is not None:
+            cap = (out.numel() * out.element_size()) // IVAL_DTYPE.itemsize
+            _check(self._lib.thapi_tally_intervals(self._h, out.data_ptr() if cap else None, cap, ctypes.byref(n),
+                                                   OUT_DEVICE), "intervals")
+            return n.value
+        v = np.zeros(n.value, dtype=IVAL_DTYPE)
+        if n.value:
+            _check(self._lib.thapi_tally_intervals(self._h, v.ctypes.data, n.value, ctypes.byref(n), 0), "intervals")
+        return v
+
     def export(self):
         """The aggregate of everything flushed so far, as a uint8 array (see thapi_tally_export)."""
         n = ctypes.c_size_t(0)
@@ -280,9 +303,9 @@ class Tally:
         return tuple(out)
 
     def timings(self):
-        arr = (ctypes.c_double * 5)()
-        n = self._lib.thapi_tally_timings(self._h, arr, 5)
-        return dict(zip(["prepass", "range", "combine", "final", "readout"], list(arr)[:n]))
+        arr = (ctypes.c_double * 6)()
+        n = self._lib.thapi_tally_timings(self._h, arr, 6)
+        return dict(zip(["prepass", "range", "combine", "final", "readout", "intervals"], list(arr)[:n]))
 
     def close(self):
         if self._h:

@@ -19,6 +19,12 @@ Other forms (each prints its own single JSON line):
                     flush = one persistent work-list launch, after the
                     autotuner has picked the launch shape, against the plain
                     per-trace form (256 sequential reset/submit/flush/read).
+  --form intervals  the same workload with every tallied call also
+                    materialised as an interval record (stream key, tid, fn,
+                    depth, entry, exit, parent) in device memory: events/s,
+                    and the bytes read and written against HBM bandwidth;
+                    the intervals are checked against the oracle's by count
+                    and an order-independent fingerprint.
   --form streaming  the continuous-batching service fed by open-loop Poisson
                     arrivals of 64 KiB - 8 MiB chunks of 64 processes x 64
                     threads, host input, at a sweep of offered rates; p50/p99
@@ -155,7 +161,7 @@ def main():
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
                     help="plain form: leave out the batched-vs-per-trace comparison on the batched workload")
-    ap.add_argument("--form", default="plain", choices=["plain", "batched", "streaming"])
+    ap.add_argument("--form", default="plain", choices=["plain", "batched", "streaming", "intervals"])
     ap.add_argument("--rates", default="2,5,10,20", help="streaming: offered GB/s per point")
     ap.add_argument("--seconds", type=float, default=10.0, help="streaming: measured seconds per point")
     ap.add_argument("--no-plain", action="store_true", help="streaming: leave out the plain-form comparison")
@@ -175,6 +181,8 @@ def main():
         return bench_batched(args)
     if args.form == "streaming":
         return bench_streaming(args)
+    if args.form == "intervals":
+        return bench_intervals(args)
 
     import numpy as np
     import torch
@@ -442,6 +450,105 @@ def bench_batched(args):
         "sample": "the whole batch (%d records, 256 traces), one pass, single thread" % sub["records"]}
     out["parity"] = sub["parity"]
     print(json.dumps(out), flush=True)
+
+
+def interval_fingerprint(v):
+    """Order-independent fingerprint of interval records: (count, sum and xor
+    of a 64-bit mix of each record's seven words, mod 2^64).  Equal multisets
+    give equal fingerprints; different ones collide with probability ~2^-64."""
+    import numpy as np
+    w = np.ascontiguousarray(v).view(np.uint64).reshape(len(v), 7)
+    with np.errstate(over="ignore"):
+        h = np.full(len(v), 0x9E3779B97F4A7C15, dtype=np.uint64)
+        for k in range(7):
+            x = w[:, k] ^ h
+            x ^= x >> np.uint64(33)
+            x *= np.uint64(0xFF51AFD7ED558CCD)
+            x ^= x >> np.uint64(33)
+            x *= np.uint64(0xC4CEB9FE1A85EC53)
+            x ^= x >> np.uint64(33)
+            h = x + np.uint64(k + 1)
+        return int(len(v)), int(h.sum(dtype=np.uint64)), int(np.bitwise_xor.reduce(h)) if len(v) else 0
+
+
+def bench_intervals(args):
+    """Interval materialisation on the plain workload: reset, submit, final
+    flush with THAPI_INTERVALS, and the conversion of the intervals into a
+    device buffer; timed like the plain form."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2504_03683_amd import tally as T
+
+    w = synth.config(args.config, scale=args.scale)
+    n_rec = w.n_records
+    in_bytes = w.record_bytes + w.payload_bytes
+    log("generated %s: %d records, %.2f GB" % (w.name, n_rec, in_bytes / 1e9))
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    recs = [torch.from_numpy(s.records).to(dev) for s in w.streams]
+    pays = [None if s.payload is None else torch.from_numpy(s.payload).to(dev) for s in w.streams]
+    tl = T.Tally(w.fmt, w.n_fns, w.n_kernel_ids, max_depth=max(w.max_depth, 8), max_threads=1024, max_streams=64,
+                 flags=T.DEVICE_INPUT | T.PROFILE | T.INTERVALS, has_size=w.has_size, stream=stream)
+    out = torch.empty((n_rec // 2 + 1024) * T.IVAL_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+
+    def step():
+        tl.reset()
+        for s, r, p in zip(w.streams, recs, pays):
+            tl.submit(s.key, r, p)
+        tl.flush(final=True)
+        return tl.intervals(out=out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    tms = {}
+    e0.record(stream)
+    n_iv = 0
+    for _ in range(args.steps):
+        n_iv = step()
+        for k, v in tl.timings().items():
+            tms.setdefault(k, []).append(v)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    avg = {k: sum(v) / len(v) for k, v in tms.items()}
+    log("timed %d steps: %.3f ms/step; kernel ms (avg): %s" % (
+        args.steps, ms, ", ".join("%s %.4f" % kv for kv in avg.items())))
+    pipe_ms = avg.get("prepass", 0) + avg["range"] + avg["combine"] + avg["final"] + avg["intervals"]
+    alg = in_bytes + T.IVAL_DTYPE.itemsize * n_iv   # records read once, intervals written once
+    rng_bytes = in_bytes + 32 * n_iv                # the range kernel: records read, one 32-byte record per call
+    got = out[:n_iv * T.IVAL_DTYPE.itemsize].cpu().numpy().view(T.IVAL_DTYPE)
+    parity = "not checked"
+    if not args.no_parity:
+        import oracle
+        o = oracle.Oracle(w.fmt, w.n_fns, w.n_kernel_ids, max(w.max_depth, 8), w.has_size)
+        o.keep_intervals()
+        for s in w.streams:
+            assert o.submit(s.key, s.records, s.payload) == 0
+        o.finish()
+        want = o.intervals()
+        o.close()
+        fg, fw = interval_fingerprint(got), interval_fingerprint(want)
+        parity = "count and fingerprint equal to the oracle's" if fg == fw else "MISMATCH %s vs %s" % (fg, fw)
+        log("parity: " + parity)
+    line = base_line(args.steps, args.warmup, ms, n_rec / (ms * 1e-3), {
+        "workload": WORKLOADS[args.config] + ("" if args.scale == 1.0 else " (scale %g)" % args.scale) +
+        ", every tallied call materialised as an interval", "records": n_rec, "input_bytes": in_bytes,
+        "intervals": n_iv, "interval_bytes": T.IVAL_DTYPE.itemsize})
+    line["roofline"] = {"bound": "hbm", "achieved": rng_bytes / (avg["range"] * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": rng_bytes / (avg["range"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                        "traffic": None, "kernel": "tt::k_range (intervals)", "kernel_ms": avg["range"],
+                        "alg_bytes": rng_bytes, "convert_ms": avg["intervals"],
+                        "convert_GBps": 88 * n_iv / (avg["intervals"] * 1e-3) / 1e9 if avg["intervals"] else None,
+                        "pipeline_ms": pipe_ms, "pipeline_alg_bytes": alg,
+                        "pipeline_frac": alg / (pipe_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    line["cpu_baseline"] = None
+    line["parity"] = parity
+    tl.close()
+    print(json.dumps(line), flush=True)
 
 
 def _streaming_expected(w, plan_chunks, n_prod):

@@ -44,7 +44,8 @@ hipError_t launch_combine(const uint32_t *spans, uint32_t n_spans, const RHdr *r
                           const OItem *ro, const uint32_t *rnslots, const Tables &tb, hipStream_t st);
 hipError_t launch_final(const Tables &tb, uint32_t max_threads, hipStream_t st);
 hipError_t launch_iv_out(const Tables &tb, const Range *ranges, const RHdr *rhdr, uint32_t n_ranges,
-                         const uint64_t *off, const uint32_t *skeys, void *out, hipStream_t st);
+                         const uint32_t *rnslots, const uint64_t *off, const uint32_t *skeys, void *out,
+                         hipStream_t st);
 hipError_t launch_thread_stats(const Tables &tb, uint32_t max_threads, unsigned long long *out, uint32_t ns,
                                uint32_t ns1, hipStream_t st);
 hipError_t launch_sort_threads(const Tables &tb, const uint32_t *stream_rank, uint64_t *keys, uint32_t *vals,
@@ -1659,8 +1660,8 @@ int thapi_tally_intervals(thapi_tally *t, thapi_tally_interval *out, size_t cap,
     dst = t->ivout.p;
   }
   HIPCHK(timed_begin(t, TM_IVOUT));
-  HIPCHK(launch_iv_out(t->tb, t->fb.ranges, t->fb.rhdr, nR, (const uint64_t *)d_off, (const uint32_t *)d_keys, dst,
-                       t->st));
+  HIPCHK(launch_iv_out(t->tb, t->fb.ranges, t->fb.rhdr, nR, t->fb.rnslots, (const uint64_t *)d_off,
+                       (const uint32_t *)d_keys, dst, t->st));
   HIPCHK(timed_end(t, TM_IVOUT));
   if (!on_dev) HIPCHK(hipMemcpyAsync(out, dst, sizeof(thapi_tally_interval) * total, hipMemcpyDeviceToHost, t->st));
   HIPCHK(hipStreamSynchronize(t->st));

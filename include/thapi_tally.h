@@ -44,8 +44,8 @@ extern "C" {
 #define THAPI_E_MALFORMED  -5  /* THAPI_STRICT only: an anomaly counter is non-zero after a flush */
 #define THAPI_E_DEVICE     -6  /* a HIP call failed; sticky, only read(stats)/close stay valid */
 #define THAPI_E_BUFSZ      -7  /* read: capacity too small, *n_rows holds the required count */
-#define THAPI_E_CAPACITY   -8  /* more streams/threads than configured, or more than the per-range
-                                  thread limit (THAPI_MAX_RANGE_THREADS) in one range; handle is failed */
+#define THAPI_E_CAPACITY   -8  /* more streams or threads than configured (max_streams, max_threads);
+                                  handle is failed */
 #define THAPI_E_STATE      -9  /* call not valid now (submit after the final flush, use after failure) */
 
 /* ---- record formats (all little-endian) -------------------------------- *
@@ -95,8 +95,11 @@ extern "C" {
 #define THAPI_ROW_KERNEL 2u
 
 #define THAPI_MAX_DEPTH_LIMIT   64u  /* max_depth may not exceed this */
-#define THAPI_MAX_RANGE_THREADS 64u  /* distinct threads one stream may interleave within one range
-                                        (1024 / max_depth when max_depth > 16) */
+#define THAPI_MAX_RANGE_THREADS 64u  /* a performance figure, not a limit: the distinct threads of one
+                                        stream that one pass over a range holds on chip (1024 / max_depth
+                                        when max_depth > 16).  A range meeting more takes one extra pass
+                                        per further group of that many of the stream's threads (each
+                                        pass reads the range's records again); results are the same */
 
 typedef struct thapi_tally thapi_tally; /* opaque, owned by the library */
 
@@ -105,7 +108,8 @@ typedef struct {
   uint32_t format;              /* THAPI_FMT_FIXED24 or THAPI_FMT_VAR16 */
   uint32_t n_fns;               /* API fn ids must be < n_fns (1..65536) */
   uint32_t n_kernel_ids;        /* kernel ids must be < n_kernel_ids (0..65536) */
-  uint32_t max_depth;           /* per-thread call-stack limit, 1..64; 0 -> 16 */
+  uint32_t max_depth;           /* per-thread call-stack limit, 1..64; 0 -> 64 (a smaller limit lets one
+                                   pass hold more threads, see THAPI_MAX_RANGE_THREADS) */
   uint32_t max_threads;         /* distinct (stream, tid) over the handle's life; 0 -> 65536 */
   uint32_t max_streams;         /* distinct stream keys over the handle's life; 0 -> 4096 */
   uint32_t flags;               /* THAPI_DEVICE_INPUT | THAPI_NONBLOCKING | ... */
@@ -308,7 +312,10 @@ int thapi_tally_merge(thapi_tally *t, const void *buf, size_t size);
  * itself): THAPI_E_INVAL otherwise.  A flush whose summaries do not fit the
  * array (about 68 KiB per range at max_depth 16, 260 KiB at 64; the work is
  * cut into fewer, longer ranges first, and every chunk needs one) returns
- * THAPI_E_NOMEM and leaves every chunk queued.  Every call on one GPU shares
+ * THAPI_E_NOMEM and leaves every chunk queued.  A flush that meets more
+ * threads of one stream within one range than a pass holds
+ * (THAPI_MAX_RANGE_THREADS) needs memory for extra passes: it fails the
+ * handle with THAPI_E_NOMEM.  Every call on one GPU shares
  * that GPU's array and leaves its contents behind (the work-queue head that
  * must start at zero is re-written by each call); calls that overlapped on
  * one GPU would race on it, so the library serialises them within the
@@ -363,7 +370,8 @@ const char *thapi_tally_strerror(int code);
 /* THAPI_PROFILE only: per-kernel durations (ms) of the last flush and read,
  * measured with HIP events on the launch stream, in the order
  * {prepass, main, combine, final, readout, intervals}; entries that did not
- * run are 0.
+ * run are 0.  A flush that needed extra passes (THAPI_MAX_RANGE_THREADS)
+ * reports its first pass only.
  * Under THAPI_GRAPH, "main" is the whole replayed graph.
  * n: capacity of ms[]; returns the number of entries written. */
 int thapi_tally_timings(thapi_tally *t, double *ms, int n);

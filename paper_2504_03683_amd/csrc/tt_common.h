@@ -18,6 +18,10 @@ constexpr uint32_t GV_PENDING = 0xFFFFFFFFu;  // global thread map: slot id not 
 constexpr uint32_t GV_INVALID = 0xFFFFFFFEu;  // global thread map: capacity exceeded
 constexpr uint32_t KL_MAX = 256;     // kernel ids pre-aggregated in LDS; larger ids go to global atomics
 
+// Distinct threads of one stream one range holds in one pass: their carried
+// stacks live in LDS (S_MAX x 16 frames); more take extra passes.
+__host__ __device__ inline uint32_t slot_cap(uint32_t D) { return D <= 16 ? (uint32_t)S_MAX : 1024u / D; }
+
 // Per-stream counters kept on the device (indices into a [stream][ST_N] u64 array).
 enum : int {
   ST_RECORDS = 0, ST_ENTRIES, ST_EXITS, ST_KERNEL, ST_ORPHAN, ST_MISMATCH, ST_NEGDUR, ST_UNDER,
@@ -25,7 +29,10 @@ enum : int {
 };
 
 // Error bits raised by kernels (sticky per flush).
-enum : uint32_t { ERR_CAPACITY = 1u, ERR_RANGE_THREADS = 2u, ERR_DEPTH = 4u, ERR_PIPE = 8u, ERR_PAYLOAD = 16u };
+// ERR_WIDE is not a failure: some range met more threads than it holds in
+// LDS, and its other threads wait for extra passes (the combine and the final
+// flush leave the flush to the host, which launches those passes).
+enum : uint32_t { ERR_CAPACITY = 1u, ERR_WIDE = 2u, ERR_DEPTH = 4u, ERR_PIPE = 8u, ERR_PAYLOAD = 16u };
 
 // One submitted chunk, as the kernels see it.
 struct Seg {
@@ -45,6 +52,10 @@ struct Range {
   uint64_t n;           // records
   uint64_t pay_begin;   // VAR16: payload offset of `begin` within the segment (filled on device)
   uint64_t iv_base;     // intervals: first IvRec of the range (the flush's records before it)
+  uint32_t pass;        // 0: the range's first pass; k > 0: an extra pass over the records of range
+                        // `parent`, for the threads of the stream with ordinal in [(k-1) C, k C) that
+                        // its first pass did not take (C: the threads one range holds in LDS)
+  uint32_t parent;
 };
 
 // Intervals (the span from a call's entry to its exit, with its depth and
@@ -97,6 +108,7 @@ struct KTally { uint64_t count, sum, min, max; };
 
 // The tables a handle resets, for the one-launch initialisation.
 struct InitSet {
+  uint32_t *s_nth; size_t n_s_nth;
   uint64_t *gkeys; size_t n_gkeys;
   uint32_t *gvals; size_t n_gvals;
   uint32_t *ngs, *err;
@@ -127,6 +139,8 @@ struct Tables {
   uint32_t *n_gslots;
   uint32_t max_threads;
   uint32_t *th_stream, *th_tid;
+  uint32_t *th_ord;     // [max_threads] the thread's ordinal within its stream (order of registration)
+  uint32_t *s_nth;      // [max_streams] threads registered per stream
   Tally *tally;         // [max_threads][n_fns]
   uint32_t n_fns;
   KTally *ktally;       // [max_streams][n_kid]
@@ -189,6 +203,7 @@ __device__ inline uint32_t resolve_gslot(const Tables &tb, uint32_t stream, uint
       } else {
         tb.th_stream[g] = stream;
         tb.th_tid[g] = tid;
+        tb.th_ord[g] = atomicAdd(&tb.s_nth[stream], 1u);
       }
       __hip_atomic_store(&tb.gvals[h], g, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       result = g;

@@ -32,7 +32,8 @@ namespace tt {
 size_t range_lds_bytes(uint32_t T, uint32_t E, uint32_t KL, uint32_t D, int fmt);
 hipError_t launch_range(int fmt, uint32_t T, const Seg *segs, const Range *ranges, const uint32_t *order,
                         uint32_t n_ranges, uint32_t *qhead, uint32_t n_wg, const Tables &tb, const Shape &sh,
-                        RHdr *rhdr, UItem *ru, OItem *ro, uint32_t *rnslots, hipStream_t st);
+                        RHdr *rhdr, UItem *ru, OItem *ro, uint32_t *rnslots, uint32_t *rmore,
+                        const Range *pranges, uint32_t rid_base, hipStream_t st);
 hipError_t prepare_range_kernels(uint32_t max_lds_bytes);
 hipError_t prepare_combine_kernel();
 hipError_t launch_paylen(const Seg *segs, Range *ranges, uint32_t n_ranges, const uint32_t *seg_first_range,
@@ -41,9 +42,10 @@ hipError_t launch_fill64(uint64_t *p, size_t n, uint64_t v, hipStream_t st);
 hipError_t launch_fill32(uint32_t *p, size_t n, uint32_t v, hipStream_t st);
 hipError_t launch_init_all(const InitSet &is, hipStream_t st);
 hipError_t launch_combine(const uint32_t *spans, uint32_t n_spans, const RHdr *rhdr, const UItem *ru,
-                          const OItem *ro, const uint32_t *rnslots, const Tables &tb, hipStream_t st);
+                          const OItem *ro, const uint32_t *rnslots, const Tables &tb, const uint32_t *clist,
+                          hipStream_t st);
 hipError_t launch_final(const Tables &tb, uint32_t max_threads, hipStream_t st);
-hipError_t launch_iv_out(const Tables &tb, const Range *ranges, const RHdr *rhdr, uint32_t n_ranges,
+hipError_t launch_iv_out(const Tables &tb, const uint64_t *ivbase, const RHdr *rhdr, uint32_t n_ranges,
                          const uint32_t *rnslots, const uint64_t *off, const uint32_t *skeys, void *out,
                          hipStream_t st);
 hipError_t launch_thread_stats(const Tables &tb, uint32_t max_threads, unsigned long long *out, uint32_t ns,
@@ -117,6 +119,20 @@ struct DevBuf {
     return e;
   }
   void release() { if (p) hipFree(p); p = nullptr; cap = 0; }
+  // grows to `bytes` keeping the first `keep` bytes (copied on `st`, which is
+  // synchronised before the old buffer is freed)
+  hipError_t ensure_keep(size_t bytes, size_t keep, hipStream_t st) {
+    if (bytes <= cap) return hipSuccess;
+    DevBuf nb;
+    hipError_t e = nb.ensure(bytes);
+    if (e == hipSuccess && keep && p) e = hipMemcpyAsync(nb.p, p, std::min(keep, cap), hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) { nb.release(); return e; }
+    release();
+    p = nb.p;
+    cap = nb.cap;
+    return hipSuccess;
+  }
   template <class T> T *as() const { return (T *)p; }
 };
 // An array inside a packed DevBuf (set by each upload).
@@ -195,6 +211,7 @@ struct FlushBufs {
   UItem *ru = nullptr;
   OItem *ro = nullptr;
   uint32_t *rnslots = nullptr;
+  uint32_t *rmore = nullptr;   // per summary row: threads left to extra passes
   uint64_t *paylen = nullptr;
 };
 
@@ -227,14 +244,16 @@ struct thapi_tally {
   uint32_t gcap = 0;
   void *d_gkeys = nullptr, *d_gvals = nullptr, *d_ngs = nullptr, *d_ths = nullptr, *d_tht = nullptr,
        *d_tally = nullptr, *d_ktally = nullptr, *d_cstate = nullptr, *d_cstack = nullptr, *d_sstats = nullptr,
-       *d_err = nullptr, *d_hs = nullptr;
+       *d_err = nullptr, *d_hs = nullptr, *d_thord = nullptr, *d_snth = nullptr;
   Shape shape{};
 
-  DevBuf rhdr, ru, ro, rnslots, paylen;
+  DevBuf rhdr, ru, ro, rnslots, rmore, paylen;
+  DevBuf wide_pack;                                   // the extra passes' work list
   // THAPI_INTERVALS: the current flush's interval buffers (see Tables), the
   // public records of the last intervals() call and its offsets / keys
   DevBuf iv, iv_n, iv_h0, iv_snap, civ, civ_n, ivout, ivaux;
-  uint32_t iv_nranges = 0;                            // ranges of the last flush
+  uint32_t iv_nranges = 0;                            // summary rows of the last flush
+  std::vector<uint64_t> iv_bases;                     // their first IvRec
   bool iv_valid = false;                              // the interval buffers hold the last flush's
   DevBuf plan_pack;                                   // the work list, uploaded in one copy
   FlushBufs fb;                                       // the current flush's device addresses
@@ -316,15 +335,16 @@ hipError_t init_tables(thapi_tally *t, bool wait = true) {
   is.ktally = t->tb.ktally; is.n_ktally = (size_t)c.max_streams * c.n_kernel_ids;
   is.cstate = (uint32_t *)t->d_cstate; is.n_cstate = (size_t)c.max_threads * sizeof(CState) / 4;
   is.sstats = (uint64_t *)t->d_sstats; is.n_sstats = (size_t)c.max_streams * ST_N;
+  is.s_nth = (uint32_t *)t->d_snth; is.n_s_nth = c.max_streams;
   if ((e = launch_init_all(is, t->st)) != hipSuccess) return e;
   return wait ? hipStreamSynchronize(t->st) : hipSuccess;
 }
 
 void free_all(thapi_tally *t) {
   void *ps[] = {t->d_gkeys, t->d_gvals, t->d_ngs, t->d_ths, t->d_tht, t->d_tally, t->d_ktally,
-                t->d_cstate, t->d_cstack, t->d_sstats, t->d_err, t->d_hs};
+                t->d_cstate, t->d_cstack, t->d_sstats, t->d_err, t->d_hs, t->d_thord, t->d_snth};
   for (void *p : ps) if (p) hipFree(p);
-  DevBuf *bs[] = {&t->plan_pack, &t->rhdr, &t->ru, &t->ro, &t->rnslots, &t->paylen, &t->keys, &t->vals, &t->keys2,
+  DevBuf *bs[] = {&t->plan_pack, &t->rhdr, &t->ru, &t->ro, &t->rnslots, &t->rmore, &t->wide_pack, &t->paylen, &t->keys, &t->vals, &t->keys2,
                   &t->vals2, &t->gbeg, &t->gend, &t->cnt, &t->off, &t->read_pack, &t->rows, &t->tstats,
                   &t->merge_buf, &t->iv, &t->iv_n, &t->iv_h0, &t->iv_snap, &t->civ, &t->civ_n, &t->ivout,
                   &t->ivaux};
@@ -444,7 +464,7 @@ int thapi_tally_open(const thapi_tally_config *cfg, thapi_tally **out) {
   thapi_tally *t = new (std::nothrow) thapi_tally();
   if (!t) return THAPI_E_NOMEM;
   t->cfg = *cfg;
-  if (!t->cfg.max_depth) t->cfg.max_depth = 16;
+  if (!t->cfg.max_depth) t->cfg.max_depth = 64;
   if (!t->cfg.max_threads) t->cfg.max_threads = 65536;
   if (!t->cfg.max_streams) t->cfg.max_streams = 4096;
   if (!t->cfg.device_budget_bytes) t->cfg.device_budget_bytes = 16ull << 30;
@@ -488,6 +508,8 @@ int thapi_tally_open(const thapi_tally_config *cfg, thapi_tally **out) {
       {&t->d_sstats, 8ull * c.max_streams * ST_N},
       {&t->d_err, 256},
       {&t->d_hs, std::max<size_t>(c.n_fns, 1)},
+      {&t->d_thord, 4ull * c.max_threads},
+      {&t->d_snth, 4ull * c.max_streams},
   };
   for (auto &a : allocs) {
     hipError_t e = hipMalloc(a.p, a.bytes);
@@ -497,6 +519,7 @@ int thapi_tally_open(const thapi_tally_config *cfg, thapi_tally **out) {
   tb.gkeys = (uint64_t *)t->d_gkeys; tb.gvals = (uint32_t *)t->d_gvals; tb.gmask = t->gcap - 1;
   tb.n_gslots = (uint32_t *)t->d_ngs; tb.max_threads = c.max_threads;
   tb.th_stream = (uint32_t *)t->d_ths; tb.th_tid = (uint32_t *)t->d_tht;
+  tb.th_ord = (uint32_t *)t->d_thord; tb.s_nth = (uint32_t *)t->d_snth;
   tb.tally = (Tally *)t->d_tally; tb.n_fns = c.n_fns;
   tb.ktally = (KTally *)t->d_ktally; tb.n_kid = c.n_kernel_ids;
   tb.cstate = (CState *)t->d_cstate; tb.cstack = (Frame *)t->d_cstack; tb.D = D;
@@ -856,10 +879,10 @@ hipError_t stage_h2d(thapi_tally *t, uint8_t *dev, void **const *views, const vo
 // summaries (RHdr per range and slot, U and O items per range, slot and level).
 struct PlanSizes {
   size_t part[6];
-  size_t pack, rhdr, ru, ro, rnslots, paylen;
+  size_t pack, rhdr, ru, ro, rnslots, rmore, paylen;
   size_t total() const {
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    return al(pack) + al(rhdr) + al(ru) + al(ro) + al(rnslots) + al(paylen);
+    return al(pack) + al(rhdr) + al(ru) + al(ro) + al(rnslots) + al(rmore) + al(paylen);
   }
 };
 
@@ -874,6 +897,7 @@ PlanSizes plan_sizes(const thapi_tally *t, const Plan &pl) {
   z.ru = sizeof(UItem) * nR * S_MAX * D;
   z.ro = sizeof(OItem) * nR * S_MAX * D;
   z.rnslots = 4 * std::max<size_t>(nR, 1);
+  z.rmore = 4 * std::max<size_t>(nR, 1);
   z.paylen = 8 * std::max<size_t>(nR, 1);
   return z;
 }
@@ -896,12 +920,14 @@ hipError_t upload_plan(thapi_tally *t, const Plan &pl, uint8_t *scratch = nullpt
     fb.ru = (UItem *)carve(z.ru);
     fb.ro = (OItem *)carve(z.ro);
     fb.rnslots = (uint32_t *)carve(z.rnslots);
+    fb.rmore = (uint32_t *)carve(z.rmore);
     fb.paylen = (uint64_t *)carve(z.paylen);
   } else {
     UPCHK(t->rhdr.ensure(z.rhdr));
     UPCHK(t->ru.ensure(z.ru));
     UPCHK(t->ro.ensure(z.ro));
     UPCHK(t->rnslots.ensure(z.rnslots));
+    UPCHK(t->rmore.ensure(z.rmore));
     UPCHK(t->paylen.ensure(z.paylen));
     UPCHK(t->plan_pack.ensure(z.pack));
     UPCHK(grow_plan_staging(t, z.pack));
@@ -910,6 +936,7 @@ hipError_t upload_plan(thapi_tally *t, const Plan &pl, uint8_t *scratch = nullpt
     fb.ru = t->ru.as<UItem>();
     fb.ro = t->ro.as<OItem>();
     fb.rnslots = t->rnslots.as<uint32_t>();
+    fb.rmore = t->rmore.as<uint32_t>();
     fb.paylen = t->paylen.as<uint64_t>();
   }
   // the work queue's head (zero) travels with the work list
@@ -946,6 +973,8 @@ hipError_t prepare_intervals(thapi_tally *t, const Plan &pl) {
   tb.civ_n = t->civ_n.as<uint32_t>();
   tb.civ_cap = (uint32_t)ccap;
   t->iv_nranges = (uint32_t)pl.ranges.size();
+  t->iv_bases.resize(pl.ranges.size());
+  for (size_t i = 0; i < pl.ranges.size(); i++) t->iv_bases[i] = pl.ranges[i].iv_base;
   t->iv_valid = true;
   return hipSuccess;
 }
@@ -970,10 +999,10 @@ hipError_t launch_pipeline(thapi_tally *t, const Plan &pl, const Shape &sh, bool
     }
     TB(TM_RANGE);
     LPCHK(launch_range((int)t->cfg.format, sh.T, fb.segs, fb.ranges, fb.order, nR, fb.qhead, (uint32_t)t->n_cu, t->tb,
-                       sh, fb.rhdr, fb.ru, fb.ro, fb.rnslots, t->st));
+                       sh, fb.rhdr, fb.ru, fb.ro, fb.rnslots, fb.rmore, fb.ranges, 0, t->st));
     TE(TM_RANGE);
     TB(TM_COMBINE);
-    LPCHK(launch_combine(fb.spans, nSp, fb.rhdr, fb.ru, fb.ro, fb.rnslots, t->tb, t->st));
+    LPCHK(launch_combine(fb.spans, nSp, fb.rhdr, fb.ru, fb.ro, fb.rnslots, t->tb, nullptr, t->st));
     TE(TM_COMBINE);
   }
   if (final) {
@@ -1084,6 +1113,110 @@ Shape prepare_batch(thapi_tally *t, std::vector<Chunk> &work, Plan &pl, uint64_t
   return sh;
 }
 
+// After a first pass that left threads to extra passes (ERR_WIDE: some
+// range met more threads of its stream than slot_cap holds in LDS; the
+// combine and the final flush did nothing): one extra pass over such a
+// range per class of slot_cap stream-thread ordinals (the threads the first
+// pass took are skipped), each writing summary rows of its own after the
+// first pass's; then the combine, whose spans list each range followed by
+// its extra passes (threads are disjoint between them, and each thread's
+// summaries stay in record order), and the final flush.  *err receives the
+// error bits of this second launch.
+hipError_t run_extra_passes(thapi_tally *t, const Plan &pl, const Shape &sh, bool final, uint32_t *err) {
+  const uint32_t nR = (uint32_t)pl.ranges.size(), D = t->cfg.max_depth, SC = slot_cap(D);
+  const size_t nst = t->stream_keys.size();
+  hipError_t e;
+#define XCHK(x) do { if ((e = (x)) != hipSuccess) return e; } while (0)
+  XCHK(ensure_pinned(t, 4ull * (nR + nst) + 64));
+  uint32_t *h = (uint32_t *)t->h_pinned;
+  XCHK(hipMemcpyAsync(h, t->fb.rmore, 4ull * nR, hipMemcpyDeviceToHost, t->st));
+  XCHK(hipMemcpyAsync(h + nR, t->tb.s_nth, 4ull * nst, hipMemcpyDeviceToHost, t->st));
+  XCHK(hipStreamSynchronize(t->st));
+  std::vector<Range> ex;
+  std::vector<uint32_t> clist, spans2;
+  uint64_t ivtot = pl.total;
+  for (size_t k = 0; k + 2 < pl.spans.size(); k += 3) {
+    const uint32_t stream = pl.spans[k], rb = pl.spans[k + 1], re = pl.spans[k + 2];
+    spans2.push_back(stream);
+    spans2.push_back((uint32_t)clist.size());
+    for (uint32_t r = rb; r < re; r++) {
+      clist.push_back(r);
+      if (!h[r]) continue;
+      const uint32_t classes = (h[nR + stream] + SC - 1) / SC;
+      for (uint32_t c = 0; c < classes; c++) {
+        Range x = pl.ranges[r];
+        x.pass = c + 1;
+        x.parent = r;
+        x.iv_base = ivtot;
+        ivtot += x.n;
+        clist.push_back(nR + (uint32_t)ex.size());
+        ex.push_back(x);
+      }
+    }
+    spans2.push_back((uint32_t)clist.size());
+  }
+  const uint32_t nE = (uint32_t)ex.size(), nRows = nR + nE;
+  std::vector<uint32_t> order2(nE);
+  for (uint32_t k = 0; k < nE; k++) order2[k] = k;
+  std::stable_sort(order2.begin(), order2.end(), [&](uint32_t a, uint32_t b) { return ex[a].n > ex[b].n; });
+  // summary rows for the extra passes, after the first pass's (kept)
+  XCHK(t->rhdr.ensure_keep(sizeof(RHdr) * nRows * S_MAX, sizeof(RHdr) * nR * S_MAX, t->st));
+  XCHK(t->ru.ensure_keep(sizeof(UItem) * nRows * S_MAX * D, sizeof(UItem) * nR * S_MAX * D, t->st));
+  XCHK(t->ro.ensure_keep(sizeof(OItem) * nRows * S_MAX * D, sizeof(OItem) * nR * S_MAX * D, t->st));
+  XCHK(t->rnslots.ensure_keep(4ull * nRows, 4ull * nR, t->st));
+  XCHK(t->rmore.ensure_keep(4ull * nRows, 4ull * nR, t->st));
+  FlushBufs &fb = t->fb;
+  fb.rhdr = t->rhdr.as<RHdr>();
+  fb.ru = t->ru.as<UItem>();
+  fb.ro = t->ro.as<OItem>();
+  fb.rnslots = t->rnslots.as<uint32_t>();
+  fb.rmore = t->rmore.as<uint32_t>();
+  if (t->cfg.flags & THAPI_INTERVALS) {
+    // the extra passes' intervals follow the first pass's
+    Tables &tb = t->tb;
+    const size_t pairs = (size_t)nRows * S_MAX;
+    const size_t ccap = std::min<size_t>(pairs * D, 0xFFFFFFF0u);
+    XCHK(t->iv.ensure_keep(sizeof(IvRec) * std::max<uint64_t>(ivtot, 1), sizeof(IvRec) * pl.total, t->st));
+    XCHK(t->iv_n.ensure_keep(4ull * nRows, 4ull * nR, t->st));
+    XCHK(t->iv_h0.ensure(4 * pairs));
+    XCHK(t->iv_snap.ensure(sizeof(IvFrame) * pairs * D));
+    XCHK(t->civ.ensure(sizeof(CIval) * ccap));
+    tb.iv = t->iv.as<IvRec>();
+    tb.iv_n = t->iv_n.as<uint32_t>();
+    tb.iv_h0 = t->iv_h0.as<uint32_t>();
+    tb.iv_snap = t->iv_snap.as<IvFrame>();
+    tb.civ = t->civ.as<CIval>();
+    tb.civ_cap = (uint32_t)ccap;
+    t->iv_nranges = nRows;
+    for (auto &x : ex) t->iv_bases.push_back(x.iv_base);
+  }
+  // the extra work list, its order, the combine's positions and spans, and
+  // the work queue's head (zero), up in one copy
+  static const uint32_t zero = 0;
+  const size_t bytes[5] = {sizeof(Range) * nE, 4ull * nE, 4 * clist.size(), 4 * spans2.size(), 4};
+  XCHK(grow_plan_staging(t, pack_bytes(bytes, 5)));
+  XCHK(t->wide_pack.ensure(pack_bytes(bytes, 5)));
+  Range *d_ex = nullptr;
+  uint32_t *d_order = nullptr, *d_clist = nullptr, *d_spans = nullptr, *d_qhead = nullptr;
+  void **views[5] = {(void **)&d_ex, (void **)&d_order, (void **)&d_clist, (void **)&d_spans, (void **)&d_qhead};
+  const void *src[5] = {ex.data(), order2.data(), clist.data(), spans2.data(), &zero};
+  XCHK(stage_h2d(t, t->wide_pack.as<uint8_t>(), views, src, bytes, 5));
+  XCHK(launch_fill32(t->tb.err, 1, 0, t->st));
+  if (t->tb.civ_n) XCHK(launch_fill32(t->tb.civ_n, 1, 0, t->st));
+  Shape sx = sh;
+  sx.pipe = 0;   // (extra passes run one schedule: all waves build a tile, then walk it)
+  XCHK(launch_range((int)t->cfg.format, sh.T, fb.segs, d_ex, d_order, nE, d_qhead, (uint32_t)t->n_cu, t->tb, sx,
+                    fb.rhdr, fb.ru, fb.ro, fb.rnslots, fb.rmore, fb.ranges, nR, t->st));
+  XCHK(launch_combine(d_spans, (uint32_t)(spans2.size() / 3), fb.rhdr, fb.ru, fb.ro, fb.rnslots, t->tb, d_clist,
+                      t->st));
+  if (final) XCHK(launch_final(t->tb, t->cfg.max_threads, t->st));
+  XCHK(hipMemcpyAsync(h, t->tb.err, 4, hipMemcpyDeviceToHost, t->st));
+  XCHK(hipStreamSynchronize(t->st));
+  *err = h[0];
+#undef XCHK
+  return hipSuccess;
+}
+
 // Tallies one batch of chunks, planned by prepare_batch (`pl`, `sh`) and
 // taken off the queue by the caller, and with `final` closes every stream.
 // With `scratch` the work list and range summaries go to that device array
@@ -1109,7 +1242,14 @@ int process_batch(thapi_tally *t, std::vector<Chunk> &work, bool final, const Pl
   uint32_t *herr = (uint32_t *)t->h_pinned;
   HIPCHK(hipMemcpyAsync(herr, t->tb.err, 4, hipMemcpyDeviceToHost, t->st));
   HIPCHK(hipStreamSynchronize(t->st));
-  const uint32_t err = *herr;
+  uint32_t err = *herr;
+  bool nomem = false;
+  if (err == ERR_WIDE) {
+    // threads left to extra passes (their summary rows need memory that the
+    // no-alloc flush does not have)
+    if (scratch) nomem = true;
+    else HIPCHK(run_extra_passes(t, pl, sh, final, &err));
+  }
   if (graph) {
     collect_timing(t, TM_RANGE);  // whole graph
   } else {
@@ -1124,9 +1264,10 @@ int process_batch(thapi_tally *t, std::vector<Chunk> &work, bool final, const Pl
     std::lock_guard<std::mutex> g(t->mu);
     for (auto &c : work) release_chunk(t, c);
     t->cv.notify_all();
-    if (err & ERR_PIPE) { t->failed = THAPI_E_DEVICE; rc = THAPI_E_DEVICE; }
+    if (nomem) { t->failed = THAPI_E_NOMEM; rc = THAPI_E_NOMEM; }
+    else if (err & ERR_PIPE) { t->failed = THAPI_E_DEVICE; rc = THAPI_E_DEVICE; }
     else if (err & ERR_PAYLOAD) { t->failed = THAPI_E_INVAL; rc = THAPI_E_INVAL; }
-    else if (err & (ERR_CAPACITY | ERR_RANGE_THREADS)) { t->failed = THAPI_E_CAPACITY; rc = THAPI_E_CAPACITY; }
+    else if (err & (ERR_CAPACITY | ERR_WIDE)) { t->failed = THAPI_E_CAPACITY; rc = THAPI_E_CAPACITY; }
     else if (err & ERR_DEPTH) { t->failed = THAPI_E_DEPTH; rc = THAPI_E_DEPTH; }
     if (final) t->finalized = true;
     t->flushed_any = true;
@@ -1646,13 +1787,13 @@ int thapi_tally_intervals(thapi_tally *t, thapi_tally_interval *out, size_t cap,
   std::vector<uint32_t> keys(3 * std::max<size_t>(t->stream_keys.size(), 1));
   for (size_t i = 0; i < t->stream_keys.size(); i++)
     for (int k = 0; k < 3; k++) keys[3 * i + k] = t->stream_keys[i][k];
-  const size_t bytes[2] = {8 * off.size(), 4 * keys.size()};
-  HIPCHK(grow_plan_staging(t, pack_bytes(bytes, 2)));
-  HIPCHK(t->ivaux.ensure(pack_bytes(bytes, 2)));
-  void *d_off = nullptr, *d_keys = nullptr;
-  void **views[2] = {&d_off, &d_keys};
-  const void *src[2] = {off.data(), keys.data()};
-  HIPCHK(stage_h2d(t, t->ivaux.as<uint8_t>(), views, src, bytes, 2));
+  const size_t bytes[3] = {8 * off.size(), 4 * keys.size(), 8 * std::max<size_t>(t->iv_bases.size(), 1)};
+  HIPCHK(grow_plan_staging(t, pack_bytes(bytes, 3)));
+  HIPCHK(t->ivaux.ensure(pack_bytes(bytes, 3)));
+  void *d_off = nullptr, *d_keys = nullptr, *d_bases = nullptr;
+  void **views[3] = {&d_off, &d_keys, &d_bases};
+  const void *src[3] = {off.data(), keys.data(), t->iv_bases.data()};
+  HIPCHK(stage_h2d(t, t->ivaux.as<uint8_t>(), views, src, bytes, 3));
   const bool on_dev = (flags & THAPI_OUT_DEVICE) != 0;
   void *dst = out;
   if (!on_dev) {
@@ -1660,7 +1801,7 @@ int thapi_tally_intervals(thapi_tally *t, thapi_tally_interval *out, size_t cap,
     dst = t->ivout.p;
   }
   HIPCHK(timed_begin(t, TM_IVOUT));
-  HIPCHK(launch_iv_out(t->tb, t->fb.ranges, t->fb.rhdr, nR, t->fb.rnslots, (const uint64_t *)d_off,
+  HIPCHK(launch_iv_out(t->tb, (const uint64_t *)d_bases, t->fb.rhdr, nR, t->fb.rnslots, (const uint64_t *)d_off,
                        (const uint32_t *)d_keys, dst, t->st));
   HIPCHK(timed_end(t, TM_IVOUT));
   if (!on_dev) HIPCHK(hipMemcpyAsync(out, dst, sizeof(thapi_tally_interval) * total, hipMemcpyDeviceToHost, t->st));

@@ -40,9 +40,11 @@ constexpr int CB_MAP = 16384;   // (range, thread) -> slot table, used when the 
 constexpr int CB_STK = 512;     // frames of the carried stacks held in LDS during the fold, when they fit
 constexpr int CB_DYN = 96 * 1024;  // dynamic LDS for the span's summaries, staged when they fit
 
+template <bool LIST, bool IV>
 __global__ __launch_bounds__(256) void k_combine(const uint32_t *__restrict__ spans, const RHdr *__restrict__ rhdr,
                                                  const UItem *__restrict__ ru, const OItem *__restrict__ ro,
-                                                 const uint32_t *__restrict__ rnslots, Tables tb) {
+                                                 const uint32_t *__restrict__ rnslots, Tables tb,
+                                                 const uint32_t *__restrict__ clist) {
   __shared__ uint32_t set_key[CB_SET];
   __shared__ uint32_t set_val[CB_SET];
   __shared__ uint32_t list[CB_SET];
@@ -51,7 +53,13 @@ __global__ __launch_bounds__(256) void k_combine(const uint32_t *__restrict__ sp
   extern __shared__ __align__(16) uint8_t cdyn[];   // CB_DYN bytes: the span's staged summaries
   __shared__ uint32_t nlist;
   __shared__ uint32_t lcnt[ST_N];
+  // threads left to extra passes: the host folds after those passes (the
+  // flag is checked before the first global write, once it has arrived)
+  const uint32_t err0 = __hip_atomic_load(tb.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const uint32_t stream = spans[3 * blockIdx.x], rb = spans[3 * blockIdx.x + 1], re = spans[3 * blockIdx.x + 2];
+  // the span's positions [rb, re) name summary rows through clist (extra
+  // passes of a range follow it), or are the rows themselves
+  auto R = [&](const uint32_t p) -> size_t { return LIST ? clist[p] : p; };
   const int tid = threadIdx.x;
   const uint32_t D = tb.D;
   for (int i = tid; i < CB_SET; i += 256) set_key[i] = EMPTY32;
@@ -62,9 +70,9 @@ __global__ __launch_bounds__(256) void k_combine(const uint32_t *__restrict__ sp
   // different ranges are in flight together
   for (uint32_t x = tid; x < (re - rb) * (uint32_t)S_MAX; x += 256) {
     const uint32_t r = rb + x / S_MAX, s = x % S_MAX;
-    if (s >= rnslots[r]) continue;
+    if (s >= rnslots[R(r)]) continue;
     {
-      const uint32_t g = rhdr[(size_t)r * S_MAX + s].gslot;
+      const uint32_t g = rhdr[R(r) * S_MAX + s].gslot;
       if (g >= tb.max_threads) continue;
       uint32_t h = hash32(g) & (CB_SET - 1);
       for (int probe = 0; probe < CB_SET; probe++) {
@@ -81,6 +89,7 @@ __global__ __launch_bounds__(256) void k_combine(const uint32_t *__restrict__ sp
     }
   }
   __syncthreads();
+  if (err0 & ERR_WIDE) return;
   const uint32_t n = nlist < CB_SET ? nlist : CB_SET;
   if (tid == 0 && nlist >= (uint32_t)CB_SET) atomicOr(tb.err, ERR_CAPACITY);
   // where each thread sits in each range's summaries (0xFF: not in that range)
@@ -90,9 +99,9 @@ __global__ __launch_bounds__(256) void k_combine(const uint32_t *__restrict__ sp
     __syncthreads();
     for (uint32_t x = tid; x < (re - rb) * (uint32_t)S_MAX; x += 256) {
       const uint32_t r = rb + x / S_MAX, s = x % S_MAX;
-      if (s >= rnslots[r]) continue;
+      if (s >= rnslots[R(r)]) continue;
       {
-        const uint32_t g = rhdr[(size_t)r * S_MAX + s].gslot;
+        const uint32_t g = rhdr[R(r) * S_MAX + s].gslot;
         if (g >= tb.max_threads) continue;
         uint32_t h = hash32(g) & (CB_SET - 1);
         for (int probe = 0; probe < CB_SET; probe++) {
@@ -137,7 +146,7 @@ __global__ __launch_bounds__(256) void k_combine(const uint32_t *__restrict__ sp
       itL = cdyn + hbytes + obytes;
       for (uint32_t x = tid; x < np; x += 256) {
         const uint32_t sl = smap[x];
-        if (sl != 0xFF) hdrL[x] = rhdr[(size_t)(rb + x / n) * S_MAX + sl];
+        if (sl != 0xFF) hdrL[x] = rhdr[R(rb + x / n) * S_MAX + sl];
       }
       __syncthreads();
       auto cnt = [&](const uint32_t x) -> uint32_t {
@@ -164,7 +173,7 @@ __global__ __launch_bounds__(256) void k_combine(const uint32_t *__restrict__ sp
         for (uint32_t x = tid; x < np; x += 256) {
           const uint32_t sl = smap[x];
           if (sl == 0xFF) continue;
-          const size_t ib = ((size_t)(rb + x / n) * S_MAX + sl) * D;
+          const size_t ib = (R(rb + x / n) * S_MAX + sl) * D;
           const RHdr &hd = hdrL[x];
           UItem *du = (UItem *)(itL + (size_t)offL[x] * 32);
           for (uint32_t k = 0; k < hd.nu_listed; k++) du[k] = ru[ib + k];
@@ -207,9 +216,9 @@ __global__ __launch_bounds__(256) void k_combine(const uint32_t *__restrict__ sp
           const int32_t ds = (int32_t)cs.h;
           if ((hd.flags & RF_OVERFLOW) || hd.H > (int32_t)D || ds + hd.M > (int32_t)D) cs.flags |= CS_OVERFLOW;
           const uint32_t h0 = cs.h, nu = hd.nu_listed;
-          if (tb.iv_h0) {
+          if (IV) {
             // intervals: the stack this thread carried into the range, top first
-            const size_t rs = (size_t)r * S_MAX + sl;
+            const size_t rs = R(r) * S_MAX + sl;
             if (j == 0) tb.iv_h0[rs] = h0;
             for (uint32_t k = j; k < h0; k += CG) {
               const Frame &f = stk[h0 - 1 - k];
@@ -233,7 +242,7 @@ __global__ __launch_bounds__(256) void k_combine(const uint32_t *__restrict__ sp
                 else if (u.ts < e.ts) c_neg++;
                 else {
                   ok = true; incl = u.ts - e.ts; uchild = u.child; echild = e.child; bytes = e.bytes; fn = u.fn;
-                  if (tb.civ) emit_civ(tb, g, h0 - 1 - k, e.ts, u.ts, u.fn, stk);
+                  if (IV) emit_civ(tb, g, h0 - 1 - k, e.ts, u.ts, u.fn, stk);
                 }
               }
             }
@@ -283,12 +292,12 @@ __global__ __launch_bounds__(256) void k_combine(const uint32_t *__restrict__ sp
                 return ((const OItem *)(itL + (size_t)(offL[x] + hd.nu_listed) * 32))[k];
               });
     } else {
-      grouped([&](uint32_t r, uint32_t, uint32_t sl) { return rhdr[(size_t)r * S_MAX + sl]; },
+      grouped([&](uint32_t r, uint32_t, uint32_t sl) { return rhdr[R(r) * S_MAX + sl]; },
               [&](uint32_t r, uint32_t, uint32_t sl, const RHdr &, uint32_t k) {
-                return ru[((size_t)r * S_MAX + sl) * D + k];
+                return ru[(R(r) * S_MAX + sl) * D + k];
               },
               [&](uint32_t r, uint32_t, uint32_t sl, const RHdr &, uint32_t k) {
-                return ro[((size_t)r * S_MAX + sl) * D + k];
+                return ro[(R(r) * S_MAX + sl) * D + k];
               });
     }
   } else {
@@ -303,7 +312,7 @@ __global__ __launch_bounds__(256) void k_combine(const uint32_t *__restrict__ sp
         // one range summary onto the carried stack; uat(k) / oat(k) give its
         // U / O items (read four at a time)
         auto fold_one = [&](const RHdr &hd, const size_t rs, auto &&uat, auto &&oat) {
-          if (tb.iv_h0) {
+          if (IV) {
             // intervals: the stack this thread carried into the range, top first
             tb.iv_h0[rs] = cs.h;
             for (uint32_t k = 0; k < cs.h; k++) tb.iv_snap[rs * D + k] = IvFrame{stk[cs.h - 1 - k].ts, stk[cs.h - 1 - k].fn, 0u};
@@ -338,7 +347,7 @@ __global__ __launch_bounds__(256) void k_combine(const uint32_t *__restrict__ sp
               ga64(&t->incl_sum, incl); gmin64(&t->incl_min, incl); gmax64(&t->incl_max, incl);
               ga64(&t->self_sum, self); gmin64(&t->self_min, self); gmax64(&t->self_max, self);
               if (e.bytes) ga64(&t->bytes_sum, e.bytes);
-              if (tb.civ) emit_civ(tb, g, cs.h, e.ts, u.ts, u.fn, stk);
+              if (IV) emit_civ(tb, g, cs.h, e.ts, u.ts, u.fn, stk);
               if (cs.h > 0) stk[cs.h - 1].child += incl;
             }
           }
@@ -370,7 +379,7 @@ __global__ __launch_bounds__(256) void k_combine(const uint32_t *__restrict__ sp
             const RHdr hd = hdrL[x];
             const UItem *lu = (const UItem *)(itL + (size_t)offL[x] * 32);
             const OItem *lo = (const OItem *)(lu + hd.nu_listed);
-            fold_one(hd, (size_t)r * S_MAX + smap[x], [&](uint32_t k) { return lu[k]; },
+            fold_one(hd, R(r) * S_MAX + smap[x], [&](uint32_t k) { return lu[k]; },
                      [&](uint32_t k) { return lo[k]; });
           }
         } else {
@@ -380,8 +389,8 @@ __global__ __launch_bounds__(256) void k_combine(const uint32_t *__restrict__ sp
               const uint32_t sl = smap[(r - rb) * n + i];
               return sl == 0xFF ? (uint32_t)S_MAX : sl;
             }
-            const uint32_t ns = rnslots[r];
-            const RHdr *hp = rhdr + (size_t)r * S_MAX;
+            const uint32_t ns = rnslots[R(r)];
+            const RHdr *hp = rhdr + R(r) * S_MAX;
             uint32_t sl = 0;
             while (sl < ns && hp[sl].gslot != g) sl++;
             return sl < ns ? sl : (uint32_t)S_MAX;
@@ -397,14 +406,14 @@ __global__ __launch_bounds__(256) void k_combine(const uint32_t *__restrict__ sp
           uint32_t sl = 0;
           uint32_t r = next_range(rb, sl);
           RHdr hd_next;
-          if (r < re) hd_next = rhdr[(size_t)r * S_MAX + sl];
+          if (r < re) hd_next = rhdr[R(r) * S_MAX + sl];
           while (r < re) {
             const RHdr hd = hd_next;
-            const size_t ib = ((size_t)r * S_MAX + sl) * D;
+            const size_t ib = (R(r) * S_MAX + sl) * D;
             uint32_t sl2 = 0;
             const uint32_t r2 = next_range(r + 1, sl2);
-            if (r2 < re) hd_next = rhdr[(size_t)r2 * S_MAX + sl2];
-            fold_one(hd, (size_t)r * S_MAX + sl, [&](uint32_t k) { return ru[ib + k]; },
+            if (r2 < re) hd_next = rhdr[R(r2) * S_MAX + sl2];
+            fold_one(hd, R(r) * S_MAX + sl, [&](uint32_t k) { return ru[ib + k]; },
                      [&](uint32_t k) { return ro[ib + k]; });
             r = r2;
             sl = sl2;
@@ -439,14 +448,15 @@ __global__ __launch_bounds__(256) void k_combine(const uint32_t *__restrict__ sp
 struct IvOut { uint32_t trace, host, pid, tid, fn, depth; uint64_t start, end, pstart; uint32_t pfn, pad; };
 
 // One flush's intervals in the public layout.  Grid (n_ranges + 1, IV_SPLIT):
-// the blocks of column r < n_ranges convert range r's IvRecs, to out + off[r], with
+// the blocks of column r < n_ranges convert summary row r's IvRecs (from
+// ivbase[r]), to out + off[r], with
 // their depth and a parent opened before the range resolved from the stack
 // the combine recorded for the range's thread (each block first caches the
 // range's slots -- stream key, tid, carried height -- in LDS); the last column
 // copies the combine's own intervals to out + off[n_ranges].  skeys: (trace,
 // host, pid) of each stream.
 constexpr uint32_t IV_SPLIT = 32;
-__global__ __launch_bounds__(256) void k_iv_out(Tables tb, const Range *__restrict__ ranges,
+__global__ __launch_bounds__(256) void k_iv_out(Tables tb, const uint64_t *__restrict__ ivbase,
                                                 const RHdr *__restrict__ rhdr, const uint32_t n_ranges,
                                                 const uint32_t *__restrict__ rnslots,
                                                 const uint64_t *__restrict__ off, const uint32_t *__restrict__ skeys,
@@ -473,7 +483,7 @@ __global__ __launch_bounds__(256) void k_iv_out(Tables tb, const Range *__restri
     }
     __syncthreads();
     const uint32_t n = tb.iv_n[r];
-    const IvRec *src = tb.iv + ranges[r].iv_base;
+    const IvRec *src = tb.iv + ivbase[r];
     uint64_t *const dst = (uint64_t *)(out + off[r]);
     // each wave converts 64 consecutive records into its LDS block, then
     // writes the block's 8-byte words out in order (512 contiguous bytes per
@@ -528,6 +538,7 @@ __global__ __launch_bounds__(256) void k_iv_out(Tables tb, const Range *__restri
 
 // Final flush: every call still open is counted as unclosed and forgotten.
 __global__ void k_final(Tables tb) {
+  if (*tb.err & ERR_WIDE) return;   // (the host closes the streams after the extra passes)
   const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= *tb.n_gslots || g >= tb.max_threads) return;
   const uint32_t h = tb.cstate[g].h;
@@ -826,6 +837,7 @@ __global__ void k_init_all(InitSet is) {
   }
   for (size_t i = i0; i < is.n_cstate; i += stride) is.cstate[i] = 0;
   for (size_t i = i0; i < is.n_sstats; i += stride) is.sstats[i] = 0;
+  for (size_t i = i0; i < is.n_s_nth; i += stride) is.s_nth[i] = 0;
   if (i0 == 0) { *is.ngs = 0; *is.err = 0; }
 }
 
@@ -924,17 +936,30 @@ hipError_t launch_init_all(const InitSet &is, hipStream_t st) {
 }
 // Allows the combine its dynamic LDS (set once, outside any stream capture).
 hipError_t prepare_combine_kernel() {
-  return hipFuncSetAttribute((const void *)k_combine, hipFuncAttributeMaxDynamicSharedMemorySize, CB_DYN);
+  const void *ks[] = {(const void *)k_combine<false, false>, (const void *)k_combine<false, true>,
+                      (const void *)k_combine<true, false>, (const void *)k_combine<true, true>};
+  for (const void *k : ks) {
+    const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, CB_DYN);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 hipError_t launch_combine(const uint32_t *spans, uint32_t n_spans, const RHdr *rhdr, const UItem *ru,
-                          const OItem *ro, const uint32_t *rnslots, const Tables &tb, hipStream_t st) {
-  if (n_spans) hipLaunchKernelGGL(k_combine, dim3(n_spans), dim3(256), CB_DYN, st, spans, rhdr, ru, ro, rnslots, tb);
+                          const OItem *ro, const uint32_t *rnslots, const Tables &tb, const uint32_t *clist,
+                          hipStream_t st) {
+  if (!n_spans) return hipSuccess;
+#define TT_COMBINE(L_, I_) \
+  hipLaunchKernelGGL((k_combine<L_, I_>), dim3(n_spans), dim3(256), CB_DYN, st, spans, rhdr, ru, ro, rnslots, tb, clist)
+  const bool iv = tb.iv != nullptr;
+  if (clist) { if (iv) TT_COMBINE(true, true); else TT_COMBINE(true, false); }
+  else { if (iv) TT_COMBINE(false, true); else TT_COMBINE(false, false); }
+#undef TT_COMBINE
   return hipGetLastError();
 }
-hipError_t launch_iv_out(const Tables &tb, const Range *ranges, const RHdr *rhdr, uint32_t n_ranges,
+hipError_t launch_iv_out(const Tables &tb, const uint64_t *ivbase, const RHdr *rhdr, uint32_t n_ranges,
                          const uint32_t *rnslots, const uint64_t *off, const uint32_t *skeys, void *out,
                          hipStream_t st) {
-  hipLaunchKernelGGL(k_iv_out, dim3(n_ranges + 1, IV_SPLIT), dim3(256), 0, st, tb, ranges, rhdr, n_ranges, rnslots,
+  hipLaunchKernelGGL(k_iv_out, dim3(n_ranges + 1, IV_SPLIT), dim3(256), 0, st, tb, ivbase, rhdr, n_ranges, rnslots,
                      off, skeys, (IvOut *)out);
   return hipGetLastError();
 }

@@ -90,8 +90,6 @@ struct RangeLds {
 };
 
 __host__ __device__ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
-// Distinct threads one range can hold: their carried stacks live in LDS.
-__host__ __device__ inline uint32_t slot_cap(uint32_t D) { return D <= 16 ? (uint32_t)S_MAX : 1024u / D; }
 
 // Byte layout of the dynamic LDS; the same function sizes it on the host.
 template <bool CARVE>
@@ -142,6 +140,18 @@ size_t range_lds_bytes(uint32_t T, uint32_t E, uint32_t KL, uint32_t D, int fmt)
 constexpr uint32_t TIDMAP_BITS = 8;
 static_assert(TIDMAP == 1 << TIDMAP_BITS, "tid map size");
 __device__ __forceinline__ uint32_t tid_bucket(uint32_t t) { return (t * 0x9E3779B1u) >> (32 - TIDMAP_BITS); }
+// A set of at most S_MAX global thread slots in TIDMAP u32 words of LDS
+// (open addressing, EMPTY32 = free): the threads an extra pass skips.
+__device__ inline bool in_gset(const uint32_t *set, uint32_t g) {
+  uint32_t h = tid_bucket(g);
+  for (uint32_t probe = 0; probe < TIDMAP; probe++) {
+    const uint32_t v = set[h];
+    if (v == g) return true;
+    if (v == EMPTY32) return false;
+    h = (h + 1) & (TIDMAP - 1);
+  }
+  return false;
+}
 // Lanes of the wavefront for which p holds (p stays a lane mask; HIP's
 // __ballot takes an int and round-trips the predicate through a register).
 __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
@@ -770,7 +780,7 @@ __device__ __forceinline__ void walk_finish(RangeLds &L, const Tables &tb, const
 // (the whole region when PIPE is off).  With PIPE the producer group (the
 // upper RNW / 2 waves) runs it alone and synchronises through group barriers;
 // otherwise the whole workgroup runs it between workgroup barriers.
-template <int FMT, int ROWS, bool PIPE>
+template <int FMT, int ROWS, bool PIPE, bool XP>
 __device__ __forceinline__ void front_tile(RangeLds &L, const Tables &tb, const uint32_t E, const uint32_t KL,
                                            const uint32_t D, const Range &rg, const Seg &sg, gu64 *grec,
                                            const uint64_t last_rec, const uint64_t t0, const uint32_t hb,
@@ -850,17 +860,20 @@ __device__ __forceinline__ void front_tile(RangeLds &L, const Tables &tb, const 
       pay_run += tot;
       gbar();
     }
-    // ---- P2. kernel records, validity, counters (wave totals by ballot)
+    // ---- P2. kernel records, validity, counters (wave totals by ballot); an
+    // extra pass over the range only takes the API records of its threads
+    constexpr bool first_pass = !XP;
 #pragma unroll
     for (int r = 0; r < ROWS; r++) {
       const uint32_t li = (uint32_t)w * (T / GW) + (uint32_t)r * WAVE + lane;
       const uint32_t fn = r_fk[r] & 0xFFFFu, kind = (r_fk[r] >> 16) & 0xFFu, plen = r_fk[r] >> 24;
       const bool in = li < n;
       const bool api = in && kind <= 1 && fn < tb.n_fns;
+      r_slot[r] = api ? 0u : EMPTY32;
+      if constexpr (XP) continue;
       const uint64_t end = r_x[r], d = end - r_ts[r];
       const bool kern_ok = in && kind == 2 && fn < tb.n_kid && (FMT == 1 || plen >= 8) && end >= r_ts[r];
       const bool bad = in && !api && !kern_ok;
-      r_slot[r] = api ? 0u : EMPTY32;
       // kernel durations: LDS rows for ids below KL and durations below 2^32
       // ns; the rest goes to the global rows
       const bool kl = kern_ok && fn < KL && d < EMPTY32;
@@ -884,7 +897,7 @@ __device__ __forceinline__ void front_tile(RangeLds &L, const Tables &tb, const 
       wc[2] += (uint32_t)__popcll(ballot(kern_ok));
       wc[3] += (uint32_t)__popcll(ballot(bad));
     }
-    if (w == 0) wc[4] += n;
+    if (w == 0 && first_pass) wc[4] += n;
     // ---- P3. thread id -> local slot
     // bucket word: bit 63 occupied, bit 62 pending, [32,40) slot, [0,32) tid.
     // A lane that finds no bucket for its tid claims one as pending and lists
@@ -893,6 +906,27 @@ __device__ __forceinline__ void front_tile(RangeLds &L, const Tables &tb, const 
     // (the first bucket settles nearly every record; the probe loop runs for
     // the other lanes only)
     uint32_t r_open = 0;   // bit r: row r still probing
+    const uint32_t scap = slot_cap(D);
+    if constexpr (XP) {
+      // extra pass: the thread of each record through the global thread map;
+      // slot = ordinal - c0 for the threads of this pass's class that the
+      // range's first pass did not take (the set in L.newtid)
+      const uint32_t c0 = (rg.pass - 1) * scap;
+#pragma unroll
+      for (int r = 0; r < ROWS; r++) {
+        if (r_slot[r] == EMPTY32) continue;
+        const uint32_t g = lookup_gslot(tb, sg.stream, r_tid[r]);
+        uint32_t sl = EMPTY32;
+        if (g < tb.max_threads) {
+          const uint32_t o = tb.th_ord[g];
+          if (o - c0 < scap && !in_gset(L.newtid, g)) {
+            sl = o - c0;
+            L.srec[sl].gslot = g;   // (every such lane writes the same value)
+          }
+        }
+        r_slot[r] = sl;
+      }
+    } else {
 #pragma unroll
     for (int r = 0; r < ROWS; r++) {
       const uint32_t t = r_tid[r];
@@ -900,7 +934,7 @@ __device__ __forceinline__ void front_tile(RangeLds &L, const Tables &tb, const 
       const bool done = (e >> 63) && !((e >> 62) & 1u) && (uint32_t)e == t;
       const uint32_t sl = (uint32_t)(e >> 32) & 0xFFu;
       const bool act = r_slot[r] != EMPTY32;
-      if (act && done) r_slot[r] = sl < slot_cap(D) ? sl : EMPTY32;  // over the per-range limit: the flush fails
+      if (act && done) r_slot[r] = sl < scap ? sl : EMPTY32;  // beyond the range's slots: an extra pass takes it
       if (act && !done) r_open |= 1u << r;
     }
     if (ballot(r_open != 0)) {
@@ -914,7 +948,7 @@ __device__ __forceinline__ void front_tile(RangeLds &L, const Tables &tb, const 
       const uint64_t e = L.tidmap[(tid_bucket(t) + 1u) & (TIDMAP - 1)];
       if ((e >> 63) && !((e >> 62) & 1u) && (uint32_t)e == t) {
         const uint32_t sl = (uint32_t)(e >> 32) & 0xFFu;
-        r_slot[r] = sl < slot_cap(D) ? sl : EMPTY32;  // over the per-range limit: the flush fails
+        r_slot[r] = sl < scap ? sl : EMPTY32;  // beyond the range's slots: an extra pass takes it
         r_open &= ~(1u << r);
       }
     }
@@ -925,6 +959,7 @@ __device__ __forceinline__ void front_tile(RangeLds &L, const Tables &tb, const 
       if (!(r_open & (1u << r))) continue;
       const uint32_t t = r_tid[r];
       uint32_t h = tid_bucket(t);
+      bool placed = false;
       for (uint32_t probe = 0; probe < TIDMAP; probe++) {
         uint64_t e = L.tidmap[h];
         if (e == 0) {
@@ -936,17 +971,27 @@ __device__ __forceinline__ void front_tile(RangeLds &L, const Tables &tb, const 
             L.newbucket[k] = h;
             r_slot[r] = EMPTY32 - 1;
             r_late |= 1u << r;
+            placed = true;
             break;
           }
         }
         if ((uint32_t)e == t) {
           const uint32_t sl = (uint32_t)(e >> 32) & 0xFFu;
           if (e & (1ull << 62)) { r_slot[r] = EMPTY32 - 1; r_late |= 1u << r; }
-          else r_slot[r] = sl < slot_cap(D) ? sl : EMPTY32;  // over the per-range limit: the flush fails
+          else r_slot[r] = sl < scap ? sl : EMPTY32;  // beyond the range's slots: an extra pass takes it
+          placed = true;
           break;
         }
         h = (h + 1) & (TIDMAP - 1);
       }
+      if (!placed) {
+        // the map is full: the thread is registered (so it has an ordinal)
+        // and left to an extra pass
+        resolve_gslot(tb, sg.stream, t);
+        r_slot[r] = EMPTY32;
+        L.misc[9] = 1u;
+      }
+    }
     }
     }
     // ---- P4. stable sort of the API records by slot: rank each record among
@@ -985,17 +1030,15 @@ __device__ __forceinline__ void front_tile(RangeLds &L, const Tables &tb, const 
     uint32_t nslots = nslots0;
     if (n_new) {
       // threads seen for the first time in this range: global slot, local slot
-      const uint32_t scap = slot_cap(D);
       if ((uint32_t)tid < n_new) {
+        // (a thread beyond the range's slots is registered too, so that it
+        // has an ordinal, and left to an extra pass over the range)
         const uint32_t s = nslots0 + tid;
         const uint32_t t = L.newtid[tid];
-        if (s < scap) {
-          L.srec[s].gslot = resolve_gslot(tb, sg.stream, t);
-          L.tidmap[L.newbucket[tid]] = (1ull << 63) | ((uint64_t)s << 32) | t;
-        } else {
-          atomicOr(tb.err, ERR_RANGE_THREADS);
-          L.tidmap[L.newbucket[tid]] = (1ull << 63) | (0xFFull << 32) | t;
-        }
+        const uint32_t g = resolve_gslot(tb, sg.stream, t);
+        if (s < scap) L.srec[s].gslot = g;
+        else L.misc[9] = 1u;
+        L.tidmap[L.newbucket[tid]] = (1ull << 63) | ((uint64_t)(s < scap ? s : 0xFFu) << 32) | t;
       }
       gbar();
       nslots = nslots0 + n_new < scap ? nslots0 + n_new : scap;
@@ -1012,7 +1055,7 @@ __device__ __forceinline__ void front_tile(RangeLds &L, const Tables &tb, const 
           if ((uint32_t)e == t) { r_slot[r] = (uint32_t)(e >> 32) & 0xFFu; break; }
           h = (h + 1) & (TIDMAP - 1);
         }
-        if (r_slot[r] >= scap) r_slot[r] = EMPTY32;  // over the per-range thread limit: the flush fails
+        if (r_slot[r] >= scap) r_slot[r] = EMPTY32;  // beyond the range's slots: an extra pass takes it
       }
       rank_rows(true, nslots);
       gbar();
@@ -1067,17 +1110,20 @@ __device__ __forceinline__ void front_tile(RangeLds &L, const Tables &tb, const 
 // waves 0 .. RNW/2-1 (walkers) walk the previous one; a tile is handed over
 // through LDS counters: every producer wave counts each tile it finished,
 // every walker publishes the tiles it has walked.
-template <int FMT, int ROWS, bool PIPE, bool IV>
+template <int FMT, int ROWS, bool PIPE, bool IV, bool XP>
 __device__ __forceinline__ void range_body(RangeLds &L, const Seg *__restrict__ segs,
-                                           const Range *__restrict__ ranges, const uint32_t rid, const Tables &tb,
+                                           const Range *__restrict__ ranges, const uint32_t rid,
+                                           const uint32_t sid, const Range *__restrict__ pranges, const Tables &tb,
                                            const Shape &sh, RHdr *__restrict__ rhdr, UItem *__restrict__ ru,
-                                           OItem *__restrict__ ro, uint32_t *__restrict__ rnslots) {
+                                           OItem *__restrict__ ro, uint32_t *__restrict__ rnslots,
+                                           uint32_t *__restrict__ rmore) {
   constexpr uint32_t GW = PIPE ? RNW / 2 : RNW;     // waves that build tiles
   constexpr uint32_t T = ROWS * GW * WAVE;          // records per tile
   constexpr uint32_t RS = FMT == 2 ? 16 : 24;
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const uint32_t D = tb.D, E = sh.E, KL = sh.KL;
-  const Range rg = ranges[rid];
+  Range rg = ranges[rid];
+  if (XP) rg.pay_begin = pranges[rg.parent].pay_begin;   // (filled on the device for the first pass)
   const Seg sg = segs[rg.seg];
   typedef typename TEntOf<FMT>::T TE;
   typedef typename CFrameOf<FMT>::T CF;
@@ -1098,9 +1144,26 @@ __device__ __forceinline__ void range_body(RangeLds &L, const Seg *__restrict__ 
   }
   for (uint32_t i = tid; i < ST_N; i += RWG) L.cnt[i] = 0;
   if (tid < 32) L.misc[tid] = 0;
+  if (XP) for (uint32_t i = tid; i < TIDMAP; i += RWG) L.newtid[i] = EMPTY32;
   __syncthreads();
+  if (XP) {
+    // an extra pass: all of its class's slots exist from the start, and the
+    // threads the range's first pass took are skipped (a set in L.newtid)
+    const uint32_t nf = rnslots[rg.parent];
+    if ((uint32_t)tid < nf) {
+      const uint32_t g = rhdr[(size_t)rg.parent * S_MAX + tid].gslot;
+      uint32_t h = tid_bucket(g);
+      for (uint32_t probe = 0; probe < TIDMAP; probe++) {
+        const uint32_t old = atomicCAS(&L.newtid[h], EMPTY32, g);
+        if (old == EMPTY32 || old == g) break;
+        h = (h + 1) & (TIDMAP - 1);
+      }
+    }
+    if (tid == 0) L.misc[0] = slot_cap(D);
+    __syncthreads();
+  }
 
-  const size_t sbase = (size_t)rid * S_MAX;
+  const size_t sbase = (size_t)sid * S_MAX;
   const uint64_t ntiles = (rg.n + T - 1) / T;
   IvRec *const ivr = IV ? tb.iv + rg.iv_base : nullptr;
   if (!PIPE || w >= (int)GW) {
@@ -1130,8 +1193,8 @@ __device__ __forceinline__ void range_body(RangeLds &L, const Seg *__restrict__ 
       const uint32_t hb = PIPE ? (uint32_t)(t & 1) : 0u;
       // PIPE: the half of tile t - 2 must have been walked
       if (PIPE && t >= 2) wait_all_at_least(&L.misc[16], GW, (uint32_t)(t - 1), tb.err);
-      front_tile<FMT, ROWS, PIPE>(L, tb, E, KL, D, rg, sg, grec, last_rec, t * T, hb, a0, a1, a2, b0, b1, b2,
-                                  pay_run, wc);
+      front_tile<FMT, ROWS, PIPE, XP>(L, tb, E, KL, D, rg, sg, grec, last_rec, t * T, hb, a0, a1, a2, b0, b1, b2,
+                                      pay_run, wc);
       if (PIPE) {
         // one count per builder wave and tile
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -1166,8 +1229,12 @@ __device__ __forceinline__ void range_body(RangeLds &L, const Seg *__restrict__ 
 
   // ---- range end: summaries, tally and counter flush
   const uint32_t nslots = L.misc[0];
-  if (tid == 0) rnslots[rid] = nslots;
-  if (IV && tid == 0) tb.iv_n[rid] = L.misc[6];
+  if (tid == 0) {
+    rnslots[sid] = nslots;
+    rmore[sid] = L.misc[9];   // threads left to extra passes
+    if (L.misc[9]) atomicOr(tb.err, ERR_WIDE);
+  }
+  if (IV && tid == 0) tb.iv_n[sid] = L.misc[6];
   if ((uint32_t)tid < nslots) {
     const uint32_t s = tid;
     const SRec &r = L.srec[s];
@@ -1233,13 +1300,18 @@ __device__ __forceinline__ void range_body(RangeLds &L, const Seg *__restrict__ 
 
 // Persistent work-list launch: each workgroup (one per CU) takes the next
 // entry of `order` (range ids, longest first) until the list is exhausted.
-// `qhead` must be 0 at launch.
-template <int FMT, int ROWS, bool PIPE, bool IV>
+// `qhead` must be 0 at launch.  Range i writes its summaries as summary row
+// rid_base + i (rmore: whether threads were left to extra passes).  XP: a
+// launch of extra passes, whose entries name their first pass's range in
+// `pranges` (rid_base: the number of those ranges, > 0).
+template <int FMT, int ROWS, bool PIPE, bool IV, bool XP>
 __global__ __launch_bounds__(RWG) void k_range(const Seg *__restrict__ segs, const Range *__restrict__ ranges,
                                                const uint32_t *__restrict__ order, const uint32_t n_ranges,
                                                uint32_t *__restrict__ qhead, Tables tb, Shape sh,
                                                RHdr *__restrict__ rhdr, UItem *__restrict__ ru,
-                                               OItem *__restrict__ ro, uint32_t *__restrict__ rnslots) {
+                                               OItem *__restrict__ ro, uint32_t *__restrict__ rnslots,
+                                               uint32_t *__restrict__ rmore, const Range *__restrict__ pranges,
+                                               const uint32_t rid_base) {
   extern __shared__ __align__(16) uint8_t smem[];
   __shared__ uint32_t next;
   RangeLds L;
@@ -1250,7 +1322,9 @@ __global__ __launch_bounds__(RWG) void k_range(const Seg *__restrict__ segs, con
     const uint32_t q = next;
     __syncthreads();
     if (q >= n_ranges) break;
-    range_body<FMT, ROWS, PIPE, IV>(L, segs, ranges, order[q], tb, sh, rhdr, ru, ro, rnslots);
+    const uint32_t rid = order[q];
+    range_body<FMT, ROWS, PIPE, IV, XP>(L, segs, ranges, rid, XP ? rid_base + rid : rid, pranges, tb, sh, rhdr, ru,
+                                        ro, rnslots, rmore);
   }
 }
 
@@ -1296,14 +1370,18 @@ __global__ void k_range_payoff(const Seg *__restrict__ segs, uint32_t n_segs, co
 // Allows every range-kernel variant up to max_lds_bytes of dynamic LDS (set
 // once, outside any stream capture).
 hipError_t prepare_range_kernels(uint32_t max_lds_bytes) {
-  const void *ks[] = {(const void *)k_range<1, 1, false, false>, (const void *)k_range<1, 2, false, false>,
-                      (const void *)k_range<2, 1, false, false>, (const void *)k_range<2, 2, false, false>,
-                      (const void *)k_range<1, 1, true, false>,  (const void *)k_range<1, 2, true, false>,
-                      (const void *)k_range<2, 1, true, false>,  (const void *)k_range<2, 2, true, false>,
-                      (const void *)k_range<1, 1, false, true>,  (const void *)k_range<1, 2, false, true>,
-                      (const void *)k_range<2, 1, false, true>,  (const void *)k_range<2, 2, false, true>,
-                      (const void *)k_range<1, 1, true, true>,   (const void *)k_range<1, 2, true, true>,
-                      (const void *)k_range<2, 1, true, true>,   (const void *)k_range<2, 2, true, true>};
+  const void *ks[] = {
+#define TT_K(F, R, P, I, X) (const void *)k_range<F, R, P, I, X>
+      TT_K(1, 1, false, false, false), TT_K(1, 2, false, false, false), TT_K(2, 1, false, false, false),
+      TT_K(2, 2, false, false, false), TT_K(1, 1, true, false, false),  TT_K(1, 2, true, false, false),
+      TT_K(2, 1, true, false, false),  TT_K(2, 2, true, false, false),  TT_K(1, 1, false, true, false),
+      TT_K(1, 2, false, true, false),  TT_K(2, 1, false, true, false),  TT_K(2, 2, false, true, false),
+      TT_K(1, 1, true, true, false),   TT_K(1, 2, true, true, false),   TT_K(2, 1, true, true, false),
+      TT_K(2, 2, true, true, false),   TT_K(1, 1, false, false, true),  TT_K(1, 2, false, false, true),
+      TT_K(2, 1, false, false, true),  TT_K(2, 2, false, false, true),  TT_K(1, 1, false, true, true),
+      TT_K(1, 2, false, true, true),   TT_K(2, 1, false, true, true),   TT_K(2, 2, false, true, true),
+#undef TT_K
+  };
   for (const void *k : ks) {
     hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds_bytes);
     if (e != hipSuccess) return e;
@@ -1317,20 +1395,37 @@ hipError_t prepare_range_kernels(uint32_t max_lds_bytes) {
 // with sh.pipe the tiles are half of it.
 hipError_t launch_range(int fmt, uint32_t T, const Seg *segs, const Range *ranges, const uint32_t *order,
                         uint32_t n_ranges, uint32_t *qhead, uint32_t n_wg, const Tables &tb, const Shape &sh,
-                        RHdr *rhdr, UItem *ru, OItem *ro, uint32_t *rnslots, hipStream_t st) {
+                        RHdr *rhdr, UItem *ru, OItem *ro, uint32_t *rnslots, uint32_t *rmore,
+                        const Range *pranges, uint32_t rid_base, hipStream_t st) {
   if (!n_ranges) return hipSuccess;
   dim3 grid(n_wg < n_ranges ? n_wg : n_ranges), block(RWG);
 #define TT_LAUNCH(F, ROWS_, P_)                                                                                 \
   do {                                                                                                          \
     if (iv)                                                                                                     \
-      hipLaunchKernelGGL((k_range<F, ROWS_, P_, true>), grid, block, sh.lds_bytes, st, segs, ranges, order,    \
-                         n_ranges, qhead, tb, sh, rhdr, ru, ro, rnslots);                                       \
+      hipLaunchKernelGGL((k_range<F, ROWS_, P_, true, false>), grid, block, sh.lds_bytes, st, segs, ranges,    \
+                         order, n_ranges, qhead, tb, sh, rhdr, ru, ro, rnslots, rmore, pranges, rid_base);      \
     else                                                                                                        \
-      hipLaunchKernelGGL((k_range<F, ROWS_, P_, false>), grid, block, sh.lds_bytes, st, segs, ranges, order,   \
-                         n_ranges, qhead, tb, sh, rhdr, ru, ro, rnslots);                                       \
+      hipLaunchKernelGGL((k_range<F, ROWS_, P_, false, false>), grid, block, sh.lds_bytes, st, segs, ranges,   \
+                         order, n_ranges, qhead, tb, sh, rhdr, ru, ro, rnslots, rmore, pranges, rid_base);      \
     return hipGetLastError();                                                                                   \
   } while (0)
-  const bool p = sh.pipe != 0, iv = tb.iv != nullptr;
+  // extra passes: one schedule (all waves build a tile, then walk it)
+#define TT_LAUNCH_XP(F, ROWS_)                                                                                  \
+  do {                                                                                                          \
+    if (iv)                                                                                                     \
+      hipLaunchKernelGGL((k_range<F, ROWS_, false, true, true>), grid, block, sh.lds_bytes, st, segs, ranges,  \
+                         order, n_ranges, qhead, tb, sh, rhdr, ru, ro, rnslots, rmore, pranges, rid_base);      \
+    else                                                                                                        \
+      hipLaunchKernelGGL((k_range<F, ROWS_, false, false, true>), grid, block, sh.lds_bytes, st, segs, ranges, \
+                         order, n_ranges, qhead, tb, sh, rhdr, ru, ro, rnslots, rmore, pranges, rid_base);      \
+    return hipGetLastError();                                                                                   \
+  } while (0)
+  const bool p = sh.pipe != 0, iv = tb.iv != nullptr, xp = rid_base != 0;
+  if (xp) {
+    if (fmt == 1) { if (T == 1024) TT_LAUNCH_XP(1, 1); if (T == 2048) TT_LAUNCH_XP(1, 2); }
+    else { if (T == 1024) TT_LAUNCH_XP(2, 1); if (T == 2048) TT_LAUNCH_XP(2, 2); }
+    return hipErrorInvalidValue;
+  }
   if (fmt == 1) {
     if (T == 1024) { if (p) TT_LAUNCH(1, 1, true); else TT_LAUNCH(1, 1, false); }
     if (T == 2048) { if (p) TT_LAUNCH(1, 2, true); else TT_LAUNCH(1, 2, false); }
@@ -1338,6 +1433,7 @@ hipError_t launch_range(int fmt, uint32_t T, const Seg *segs, const Range *range
     if (T == 1024) { if (p) TT_LAUNCH(2, 1, true); else TT_LAUNCH(2, 1, false); }
     if (T == 2048) { if (p) TT_LAUNCH(2, 2, true); else TT_LAUNCH(2, 2, false); }
   }
+#undef TT_LAUNCH_XP
 #undef TT_LAUNCH
   return hipErrorInvalidValue;
 }

@@ -134,7 +134,10 @@ def test_depth_overflow_is_an_error():
         assert st["depth_overflow"] == 1
 
 
-def test_too_many_threads_in_one_range():
+def test_more_threads_in_one_range_than_a_pass_holds():
+    """80 threads with one call each, all open at once in one range: the
+    first pass takes 64, an extra pass the other 16; the tally equals the
+    oracle's (default max_depth 64: 16 threads per pass, so five passes)."""
     say("case: more than 64 threads interleaved in one range")
     from paper_2504_03683_amd import tally as T
     ev = []
@@ -142,9 +145,17 @@ def test_too_many_threads_in_one_range():
         ev.append((T0 + 2 * k, 1000 + k, 0, ENTRY))
     for k in range(80):
         ev.append((T0 + 500 + k, 1000 + k, 0, EXIT))
-    with T.Tally(T.FMT_FIXED24, 1, 0, max_threads=1024, max_streams=8) as t:
-        t.submit((0, 0, 1), fixed24(ev))
-        assert t.flush_rc(final=True) == T.E_CAPACITY
+    rec = fixed24(ev)
+    o = oracle.Oracle(1, 1, 0, 64)
+    o.submit((0, 0, 1), rec)
+    o.finish()
+    for depth in (16, 0):
+        with T.Tally(T.FMT_FIXED24, 1, 0, max_depth=depth, max_threads=1024, max_streams=8) as t:
+            t.submit((0, 0, 1), rec)
+            assert t.flush_rc(final=True) == T.OK
+            rows, st = t.read()
+        assert np.array_equal(rows, o.rows(1)) and st["distinct_threads"] == 80
+    o.close()
 
 
 def test_submit_validation():

@@ -98,3 +98,25 @@ def test_noalloc_refuses_host_input_and_service(T):
         assert t.flush_noalloc_rc() == T.E_INVAL
     with T.Tally(1, 8, 0, max_depth=16, max_threads=64, max_streams=8, flags=T.DEVICE_INPUT | T.SERVICE) as t:
         assert t.flush_noalloc_rc() == T.E_INVAL
+
+
+def test_noalloc_refuses_extra_passes(T):
+    """A flush that meets more threads of one stream within one range than a
+    pass holds needs summary rows for extra passes, which the static array
+    does not provide: THAPI_E_NOMEM, and the handle is failed; the same
+    chunks on an ordinary handle give the oracle's tally."""
+    say("case: no-alloc flush with more threads in one range than a pass holds")
+    from tests.records import ENTRY, EXIT, fixed24
+    ev = [(synth.T0_NS + 2 * k, 1000 + k, 0, ENTRY) for k in range(80)]
+    ev += [(synth.T0_NS + 500 + k, 1000 + k, 0, EXIT) for k in range(80)]
+    case = Case(1, 1, 0, [((0, 0, 1), fixed24(ev), None)], max_depth=16)
+    dev = _dev(case)
+    with T.Tally(1, 1, 0, max_depth=16, max_threads=256, max_streams=8, flags=T.DEVICE_INPUT) as t:
+        t.submit((0, 0, 1), dev[0][1])
+        assert t.flush_noalloc_rc(final=True) == T.E_NOMEM
+        assert t.flush_rc(final=True) == T.E_STATE
+    with T.Tally(1, 1, 0, max_depth=16, max_threads=256, max_streams=8, flags=T.DEVICE_INPUT) as t:
+        t.submit((0, 0, 1), dev[0][1])
+        assert t.flush_rc(final=True) == 0
+        got = read_out(t, case)
+    assert_same(got, run_oracle(case))

@@ -36,6 +36,16 @@ IVAL_DTYPE = np.dtype([
     ("start", "<u8"), ("end", "<u8"), ("parent_start", "<u8"), ("parent_fn", "<u4"), ("pad", "<u4"),
 ])
 
+COPY_DTYPE = np.dtype([
+    ("trace", "<u4"), ("host", "<u4"), ("pid", "<u4"), ("fn", "<u4"), ("dir", "<u4"), ("pad", "<u4"),
+    ("count", "<u8"), ("bytes", "<u8"),
+])
+HANDLE_DTYPE = np.dtype([
+    ("trace", "<u4"), ("host", "<u4"), ("pid", "<u4"), ("pad", "<u4"),
+    ("creates", "<u8"), ("releases", "<u8"), ("handles", "<u8"), ("unreleased", "<u8"), ("unmatched", "<u8"),
+])
+ROLE_COPY, ROLE_CREATE, ROLE_RELEASE = 1, 2, 3
+
 _lib = None
 
 
@@ -71,6 +81,16 @@ def _load():
         lib.oracle_intervals.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]
         lib.oracle_interval_size.restype = ctypes.c_uint64
         assert lib.oracle_interval_size() == IVAL_DTYPE.itemsize
+        lib.oracle_set_roles.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        lib.oracle_submit_packed.restype = ctypes.c_int
+        lib.oracle_submit_packed.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                             ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_size_t]
+        for f in ("oracle_copies", "oracle_handles"):
+            getattr(lib, f).restype = ctypes.c_size_t
+            getattr(lib, f).argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]
+        lib.oracle_copy_size.restype = ctypes.c_uint64
+        lib.oracle_handle_size.restype = ctypes.c_uint64
+        assert lib.oracle_copy_size() == COPY_DTYPE.itemsize and lib.oracle_handle_size() == HANDLE_DTYPE.itemsize
         _lib = lib
     return _lib
 
@@ -112,6 +132,33 @@ class Oracle:
 
     def finish(self):
         self._lib.oracle_finish(self._h)
+
+    def set_roles(self, roles):
+        """Per-fn payload roles (0, ROLE_COPY, ROLE_CREATE, ROLE_RELEASE), n_fns bytes."""
+        r = np.ascontiguousarray(roles, dtype=np.uint8)
+        self._roles = r
+        self._lib.oracle_set_roles(self._h, r.ctypes.data)
+
+    def submit_packed(self, key, buf, index) -> int:
+        """A packed chunk: packet bytes and the u64 offsets of its packets."""
+        trace, host, pid = key
+        b = np.ascontiguousarray(buf, dtype=np.uint8)
+        ix = np.ascontiguousarray(index, dtype=np.uint64)
+        return self._lib.oracle_submit_packed(self._h, trace, host, pid, _ptr(b), b.nbytes, _ptr(ix), ix.size)
+
+    def copies(self) -> np.ndarray:
+        n = self._lib.oracle_copies(self._h, None, 0)
+        out = np.zeros(n, dtype=COPY_DTYPE)
+        if n:
+            self._lib.oracle_copies(self._h, out.ctypes.data, n)
+        return out
+
+    def handles(self) -> np.ndarray:
+        n = self._lib.oracle_handles(self._h, None, 0)
+        out = np.zeros(n, dtype=HANDLE_DTYPE)
+        if n:
+            self._lib.oracle_handles(self._h, out.ctypes.data, n)
+        return out
 
     def rows(self, scope: int = SCOPE_THREAD, trace: int = ALL) -> np.ndarray:
         n = self._lib.oracle_rows(self._h, scope, trace, None, 0)

@@ -34,6 +34,26 @@
  * Final flush: every entry still open counts as unclosed and is not tallied.
  * All arithmetic is unsigned 64-bit integer (modulo 2^64).
  *
+ * Payload analytics (VAR16 only), per record in order and independent of
+ * call matching, for functions given a role (oracle_set_roles):
+ *   copy (role 1): an entry with payload_len >= 24 carries size (u64 at 0),
+ *     destination and source pointers (u64 at 8 and 16); a pointer whose top
+ *     byte is 0xff is device memory, any other host memory (section 1.1
+ *     reads a copy's direction from these prefixes); per (stream, fn,
+ *     direction = 2 * source-on-device + destination-on-device) the entries
+ *     are counted and their sizes summed.
+ *   create (role 2): an exit with payload_len >= 8 returns a handle (u64 at 0).
+ *   release (role 3): an entry with payload_len >= 8 takes a handle (u64 at 0).
+ *   Per stream, creates and releases are joined by handle value (section 4.2:
+ *   a validation pass reports unhandled releases): a value created C times
+ *   and released R times leaves max(0, C - R) handles unreleased and
+ *   max(0, R - C) releases that match no create; record order is not
+ *   considered.
+ * Packed chunks (oracle_submit_packed): CTF-like packets, each a 16-byte
+ * header {u32 magic "THPK", u32 packet bytes, u32 events, u32 0} followed by
+ * its events, each a VAR16 header and its payload inline, padded to a
+ * multiple of 8 bytes; the events are taken in order into the VAR16 path.
+ *
  * On request (oracle_keep_intervals) every tallied call is also kept as an
  * interval (section 3.3: an interval plugin turns the entry and exit events
  * of a call into one record spanning them; section 3.6 draws such records on
@@ -92,6 +112,8 @@ typedef struct { uint32_t trace, host, pid; uint64_t st[17]; int has_record; } s
 typedef struct { uint32_t stream, tid, fn; uint64_t v[8]; } tally_t;   /* count, incl sum/min/max, self sum/min/max, bytes */
 typedef struct { uint32_t stream, kid; uint64_t v[4]; } ktally_t;       /* count, dur sum/min/max */
 typedef struct { uint32_t stream, tid, fn, depth; uint64_t start, end, pstart; uint32_t pfn, pad; } ival_t;
+typedef struct { uint32_t stream, fn, dir; uint64_t count, bytes; } copy_t;
+typedef struct { uint32_t stream; uint64_t handle, creates, releases; } handle_t;
 
 enum { S_RECORDS, S_ENTRIES, S_EXITS, S_KERNEL, S_ORPHAN, S_MISMATCH, S_NEGDUR, S_SELFUNDER,
        S_TSREG, S_UNCLOSED, S_OPEN, S_DEPTH, S_BAD, S_DROPPED, S_HOSTS, S_PROCS, S_THREADS, S_N };
@@ -106,6 +128,9 @@ typedef struct oracle {
   ktally_t *kt; size_t nkt, ktcap;
   int keep_ivals;
   ival_t *iv; size_t niv, ivcap;
+  uint8_t *roles;                          /* per fn: 0, 1 copy, 2 create, 3 release */
+  map_t copy_map; copy_t *cp; size_t ncp, cpcap;
+  map_t hmap; handle_t *hd; size_t nhd, hdcap;
 } oracle;
 
 #define GROW(arr, n, cap) do { if ((n) == (cap)) { (cap) = (cap) ? (cap) * 2 : 64; \
@@ -118,6 +143,8 @@ oracle *oracle_new(int format, uint32_t n_fns, uint32_t n_kernel_ids, uint32_t m
   o->has_size = (uint8_t *)calloc(n_fns ? n_fns : 1, 1);
   if (has_size) memcpy(o->has_size, has_size, n_fns);
   map_init(&o->smap); map_init(&o->tmap); map_init(&o->tally_map); map_init(&o->kmap);
+  map_init(&o->copy_map); map_init(&o->hmap);
+  o->roles = (uint8_t *)calloc(n_fns ? n_fns : 1, 1);
   return o;
 }
 
@@ -125,7 +152,9 @@ void oracle_free(oracle *o) {
   if (!o) return;
   for (size_t i = 0; i < o->nt; i++) free(o->threads[i].stk);
   free(o->threads); free(o->streams); free(o->tallies); free(o->kt); free(o->has_size); free(o->iv);
+  free(o->roles); free(o->cp); free(o->hd);
   map_free(&o->smap); map_free(&o->tmap); map_free(&o->tally_map); map_free(&o->kmap);
+  map_free(&o->copy_map); map_free(&o->hmap);
   free(o);
 }
 
@@ -188,6 +217,37 @@ static void ktally_add(oracle *o, uint32_t stream, uint16_t kid, uint64_t dur) {
   if (dur > k->v[3]) k->v[3] = dur;
 }
 
+void oracle_set_roles(oracle *o, const uint8_t *roles) { memcpy(o->roles, roles, o->n_fns); }
+
+/* The payload analytics of one VAR16 record (see the header). */
+static void payload_roles(oracle *o, uint32_t sid, uint16_t fn, uint8_t kind, const uint8_t *p, uint32_t plen) {
+  if (kind > 1 || fn >= o->n_fns) return;
+  const uint8_t role = o->roles[fn];
+  int ins;
+  if (role == 1 && kind == 0 && plen >= 24) {
+    const uint64_t size = rd64(p), dst = rd64(p + 8), src = rd64(p + 16);
+    const uint32_t dir = ((src >> 56) == 0xFF ? 2u : 0u) + ((dst >> 56) == 0xFF ? 1u : 0u);
+    uint32_t id = map_get(&o->copy_map, ((uint64_t)sid << 32) | fn, dir, (uint32_t)o->ncp, &ins);
+    if (ins) {
+      GROW(o->cp, o->ncp, o->cpcap);
+      copy_t *c = &o->cp[o->ncp++];
+      c->stream = sid; c->fn = fn; c->dir = dir; c->count = 0; c->bytes = 0;
+    }
+    o->cp[id].count += 1;
+    o->cp[id].bytes += size;
+  } else if ((role == 2 && kind == 1 && plen >= 8) || (role == 3 && kind == 0 && plen >= 8)) {
+    const uint64_t h = rd64(p);
+    uint32_t id = map_get(&o->hmap, sid, h, (uint32_t)o->nhd, &ins);
+    if (ins) {
+      GROW(o->hd, o->nhd, o->hdcap);
+      handle_t *x = &o->hd[o->nhd++];
+      x->stream = sid; x->handle = h; x->creates = 0; x->releases = 0;
+    }
+    if (role == 2) o->hd[id].creates += 1;
+    else o->hd[id].releases += 1;
+  }
+}
+
 /* Validates a chunk like the library does; returns 0 or -1 (nothing changed). */
 static int check_chunk(const oracle *o, const uint8_t *rec, size_t rb, const uint8_t *pay, size_t pb) {
   size_t rs = o->format == 2 ? 16 : 24;
@@ -222,6 +282,7 @@ int oracle_submit(oracle *o, uint32_t trace, uint32_t host, uint32_t pid,
     const uint8_t *p = o->format == 2 ? pay + poff : NULL;
     poff += plen;
     st->st[S_RECORDS]++;
+    if (o->format == 2) payload_roles(o, sid, fn, kind, p, plen);
     if (kind == 2) {
       uint64_t end;
       int ok = fn < o->n_kernel_ids;
@@ -273,6 +334,56 @@ int oracle_submit(oracle *o, uint32_t trace, uint32_t host, uint32_t pid,
     }
   }
   return 0;
+}
+
+/* A packed chunk (see the header): its packets are taken in index order,
+ * each checked (magic, size, event count, events exactly filling it, packets
+ * contiguous and covering the chunk) and its events passed on as one VAR16
+ * chunk.  Returns 0, or -1 when the chunk is malformed (nothing changed). */
+int oracle_submit_packed(oracle *o, uint32_t trace, uint32_t host, uint32_t pid, const uint8_t *buf,
+                         size_t nbytes, const uint64_t *index, size_t n_packets) {
+  if (o->format != 2) return -1;
+  if ((nbytes && !buf) || (n_packets && !index) || (nbytes && !n_packets)) return -1;
+  size_t nev = 0, npay = 0;
+  for (int pass = 0; pass < 2; pass++) {
+    uint8_t *hdr = NULL, *pay = NULL;
+    if (pass == 1) {
+      hdr = (uint8_t *)malloc(nev ? nev * 16 : 1);
+      pay = (uint8_t *)malloc(npay ? npay : 1);
+    }
+    size_t ei = 0, pi = 0, expect = 0;
+    for (size_t k = 0; k < n_packets; k++) {
+      const uint64_t off = index[k];
+      if (off != expect || off % 8 || off + 16 > nbytes) { free(hdr); free(pay); return -1; }
+      const uint8_t *pk = buf + off;
+      const uint32_t magic = rd32(pk), pbytes = rd32(pk + 4), pev = rd32(pk + 8), z = rd32(pk + 12);
+      if (magic != 0x4B504854u || z || pbytes < 16 || pbytes % 8 || off + pbytes > nbytes) {
+        free(hdr); free(pay); return -1;
+      }
+      size_t o2 = 16;
+      for (uint32_t e = 0; e < pev; e++) {
+        if (o2 + 16 > pbytes) { free(hdr); free(pay); return -1; }
+        const uint32_t len = pk[o2 + 15];
+        const size_t esz = (16 + len + 7) / 8 * 8;
+        if (o2 + esz > pbytes) { free(hdr); free(pay); return -1; }
+        if (pass == 1) {
+          memcpy(hdr + ei * 16, pk + o2, 16);
+          memcpy(pay + pi, pk + o2 + 16, len);
+        }
+        ei++;
+        pi += len;
+        o2 += esz;
+      }
+      if (o2 != pbytes) { free(hdr); free(pay); return -1; }
+      expect = off + pbytes;
+    }
+    if (expect != nbytes) { free(hdr); free(pay); return -1; }
+    if (pass == 0) { nev = ei; npay = pi; continue; }
+    const int rc = oracle_submit(o, trace, host, pid, hdr, nev * 16, pay, npay);
+    free(hdr); free(pay);
+    return rc;
+  }
+  return -1;
 }
 
 /* Final flush: open entries are counted as unclosed and dropped. */
@@ -433,3 +544,76 @@ size_t oracle_intervals(oracle *o, oival_t *out, size_t cap) {
 }
 
 uint64_t oracle_interval_size(void) { return sizeof(oival_t); }
+
+/* ------------------------------------------------------ payload analytics */
+typedef struct {
+  uint32_t trace, host, pid, fn, dir, pad;
+  uint64_t count, bytes;
+} ocopy_t;
+typedef struct {
+  uint32_t trace, host, pid, pad;
+  uint64_t creates, releases, handles, unreleased, unmatched;
+} ohandle_t;
+
+static int copy_cmp(const void *x, const void *y) {
+  const ocopy_t *a = (const ocopy_t *)x, *b = (const ocopy_t *)y;
+#define C(f) if (a->f != b->f) return a->f < b->f ? -1 : 1;
+  C(trace) C(host) C(pid) C(fn) C(dir)
+#undef C
+  return 0;
+}
+static int handle_cmp(const void *x, const void *y) {
+  const ohandle_t *a = (const ohandle_t *)x, *b = (const ohandle_t *)y;
+#define C(f) if (a->f != b->f) return a->f < b->f ? -1 : 1;
+  C(trace) C(host) C(pid)
+#undef C
+  return 0;
+}
+
+/* Copy tallies, one row per (stream, fn, direction) with entries, in order
+ * (trace, host, pid, fn, dir). */
+size_t oracle_copies(oracle *o, ocopy_t *out, size_t cap) {
+  ocopy_t *v = (ocopy_t *)calloc(o->ncp ? o->ncp : 1, sizeof(ocopy_t));
+  for (size_t i = 0; i < o->ncp; i++) {
+    const copy_t *c = &o->cp[i];
+    const stream_t *s = &o->streams[c->stream];
+    v[i].trace = s->trace; v[i].host = s->host; v[i].pid = s->pid; v[i].fn = c->fn; v[i].dir = c->dir;
+    v[i].count = c->count; v[i].bytes = c->bytes;
+  }
+  if (o->ncp) qsort(v, o->ncp, sizeof(ocopy_t), copy_cmp);
+  if (out) memcpy(out, v, (o->ncp < cap ? o->ncp : cap) * sizeof(ocopy_t));
+  free(v);
+  return o->ncp;
+}
+
+/* The create / release join, one row per stream that had either, in order
+ * (trace, host, pid): creates, releases, distinct handle values, handles
+ * left unreleased and releases matching no create (summed over values). */
+size_t oracle_handles(oracle *o, ohandle_t *out, size_t cap) {
+  ohandle_t *v = (ohandle_t *)calloc(o->ns ? o->ns : 1, sizeof(ohandle_t));
+  uint8_t *used = (uint8_t *)calloc(o->ns ? o->ns : 1, 1);
+  for (size_t i = 0; i < o->nhd; i++) {
+    const handle_t *h = &o->hd[i];
+    ohandle_t *r = &v[h->stream];
+    used[h->stream] = 1;
+    r->creates += h->creates;
+    r->releases += h->releases;
+    r->handles += 1;
+    if (h->creates > h->releases) r->unreleased += h->creates - h->releases;
+    else r->unmatched += h->releases - h->creates;
+  }
+  size_t n = 0;
+  for (size_t i = 0; i < o->ns; i++) {
+    if (!used[i]) continue;
+    const stream_t *s = &o->streams[i];
+    v[i].trace = s->trace; v[i].host = s->host; v[i].pid = s->pid; v[i].pad = 0;
+    v[n++] = v[i];
+  }
+  if (n) qsort(v, n, sizeof(ohandle_t), handle_cmp);
+  if (out) memcpy(out, v, (n < cap ? n : cap) * sizeof(ohandle_t));
+  free(v); free(used);
+  return n;
+}
+
+uint64_t oracle_copy_size(void) { return sizeof(ocopy_t); }
+uint64_t oracle_handle_size(void) { return sizeof(ohandle_t); }

@@ -102,3 +102,38 @@ def corrupt_fixed24(rec, seed, n_fns, p=0.002, lost_exits=3):
     if lost_exits and len(late):
         r["kind"][rng.choice(late, size=min(lost_exits, len(late)), replace=False)] = 9
     return np.frombuffer(r.tobytes(), dtype=np.uint8).copy()
+
+
+PACKET_MAGIC = 0x4B504854   # "THPK"
+
+
+def packed(events, packet_bytes=4096):
+    """Packed (CTF-like) encoding of (ts, tid, fn, kind, payload_bytes)
+    events: packets of at most `packet_bytes` bytes, each a 16-byte header
+    {magic, packet bytes, events, 0} followed by its events, every event a
+    16-byte VAR16 header and its payload inline, padded to 8 bytes.  Returns
+    (bytes as uint8, u64 offsets of the packets)."""
+    out = bytearray()
+    index = []
+    cur = []
+
+    def close():
+        if not cur:
+            return
+        body = b"".join(cur)
+        index.append(len(out))
+        out.extend(struct.pack("<IIII", PACKET_MAGIC, 16 + len(body), len(cur), 0))
+        out.extend(body)
+        cur.clear()
+
+    used = 16
+    for ts, tid, fn, kind, p in events:
+        ev = struct.pack("<QIHBB", ts, tid, fn, kind, len(p)) + p
+        ev += b"\0" * ((-len(ev)) % 8)
+        if cur and used + len(ev) > packet_bytes:
+            close()
+            used = 16
+        cur.append(ev)
+        used += len(ev)
+    close()
+    return np.frombuffer(bytes(out), dtype=np.uint8).copy(), np.array(index, dtype=np.uint64)

@@ -444,3 +444,141 @@ def test_intervals_match_generator_call_list(k, scale):
                             want["start"], want["tid"], want["pid"], want["host"], want["trace"]))]
     assert len(got) == len(want) > 1000
     assert np.array_equal(got, want)
+
+
+# ------------------------------------------------------- payload analytics
+import struct  # noqa: E402
+
+from tests.records import packed, random_trees, var16  # noqa: E402
+
+HOSTP, DEVP = 0x00007F0000001000, 0xFF00000000002000
+
+
+def _copy_payload(size, dst, src, extra=b""):
+    return u64(size) + u64(dst) + u64(src) + extra
+
+
+def test_copy_directions_closed_form():
+    """Copy entries of each direction, by hand: the direction comes from the
+    top byte of the source and destination pointers (0xff: device), sizes
+    are summed per (fn, direction); exits, short payloads and other fns do
+    not count."""
+    ev = [(T + 1, 1, 0, ENTRY, _copy_payload(100, DEVP, HOSTP)),        # host -> device
+          (T + 2, 1, 0, EXIT, _copy_payload(999, DEVP, HOSTP)),         # an exit: not counted
+          (T + 3, 1, 0, ENTRY, _copy_payload(7, HOSTP, DEVP, b"xyz")),  # device -> host
+          (T + 4, 1, 0, EXIT, b""),
+          (T + 5, 1, 0, ENTRY, _copy_payload(5, DEVP, DEVP)),          # device -> device
+          (T + 6, 1, 0, EXIT, b""),
+          (T + 7, 1, 0, ENTRY, _copy_payload(11, 0xFE00000000000000, HOSTP)),  # 0xfe: host -> host
+          (T + 8, 1, 0, EXIT, b""),
+          (T + 9, 1, 0, ENTRY, _copy_payload(1000, DEVP, HOSTP)[:23]),  # 23 bytes: too short
+          (T + 10, 1, 0, EXIT, b""),
+          (T + 11, 1, 1, ENTRY, _copy_payload(64, DEVP, HOSTP)),        # fn 1 has no copy role
+          (T + 12, 1, 1, EXIT, b""),
+          (T + 13, 2, 0, ENTRY, _copy_payload(200, DEVP, HOSTP)),       # another thread, same stream
+          (T + 14, 2, 0, EXIT, b"")]
+    hdr, pay = var16(ev)
+    o = oracle.Oracle(2, 2, 0, 16)
+    o.set_roles([oracle.ROLE_COPY, 0])
+    assert o.submit(KEY, hdr, pay) == 0
+    got = [(int(r["fn"]), int(r["dir"]), int(r["count"]), int(r["bytes"])) for r in o.copies()]
+    # dir = 2 * (source on device) + (destination on device)
+    assert got == [(0, 0, 1, 11), (0, 1, 2, 300), (0, 2, 1, 7), (0, 3, 1, 5)]
+    assert o.handles().size == 0
+
+
+def test_handle_join_closed_form():
+    """Creates (handle in the exit payload) joined with releases (handle in
+    the entry payload) by value, per stream: a double release, a release of
+    a handle never created, two handles never released, and a release that
+    comes before its create (record order is not considered)."""
+    C, R = 0, 1   # fn 0 creates, fn 1 releases
+
+    def create(ts, h):
+        return [(ts, 1, C, ENTRY, b""), (ts + 1, 1, C, EXIT, u64(h))]
+
+    def release(ts, h):
+        return [(ts, 1, R, ENTRY, u64(h)), (ts + 1, 1, R, EXIT, b"")]
+    ev = (release(T + 0, 0x50) + create(T + 10, 0x10) + create(T + 20, 0x20) + create(T + 30, 0x30) +
+          release(T + 40, 0x10) + release(T + 50, 0x10) + release(T + 60, 0x40) + create(T + 70, 0x50) +
+          [(T + 80, 1, C, ENTRY, b""), (T + 81, 1, C, EXIT, b"1234567")])   # 7 bytes: no handle
+    hdr, pay = var16(ev)
+    o = oracle.Oracle(2, 2, 0, 16)
+    o.set_roles([oracle.ROLE_CREATE, oracle.ROLE_RELEASE])
+    assert o.submit(KEY, hdr, pay) == 0
+    h = o.handles()
+    assert len(h) == 1
+    r = h[0]
+    assert (int(r["creates"]), int(r["releases"]), int(r["handles"])) == (4, 4, 5)
+    # 0x20 and 0x30 never released; 0x10 released twice, 0x40 never created
+    assert (int(r["unreleased"]), int(r["unmatched"])) == (2, 2)
+    assert o.copies().size == 0
+
+
+def test_packed_chunks_equal_their_var16_events():
+    """The same events as packed packets (three packet sizes) and as VAR16:
+    identical tallies, counters and payload analytics."""
+    rnd = __import__("random").Random(7)
+    base = random_trees(5, 3, 400, 6, t0=T)
+    ev = []
+    for (ts, tid, fn, kind) in base:
+        ln = rnd.choice([0, 1, 8, 13, 24, 31, 64, 200])
+        p = bytes(rnd.randrange(256) for _ in range(ln))
+        if fn == 2 and kind == ENTRY and ln >= 24:
+            p = _copy_payload(rnd.randrange(1, 1 << 20), rnd.choice([HOSTP, DEVP]), rnd.choice([HOSTP, DEVP])) + p[24:]
+        if fn in (3, 4) and ln >= 8:
+            p = u64(0x1000 + rnd.randrange(40)) + p[8:]
+        ev.append((ts, tid, fn, kind, p))
+    roles = [0, 0, oracle.ROLE_COPY, oracle.ROLE_CREATE, oracle.ROLE_RELEASE, 0]
+    hs = np.array([0, 1, 1, 0, 0, 1], dtype=np.uint8)
+    hdr, pay = var16(ev)
+    ref = oracle.Oracle(2, 6, 0, 16, hs)
+    ref.set_roles(roles)
+    assert ref.submit(KEY, hdr, pay) == 0
+    ref.finish()
+    for pb in (256, 1024, 1 << 16):
+        buf, ix = packed(ev, pb)
+        assert len(ix) >= 1 and (pb > 60000 or len(ix) > 3)
+        o = oracle.Oracle(2, 6, 0, 16, hs)
+        o.set_roles(roles)
+        assert o.submit_packed(KEY, buf, ix) == 0
+        o.finish()
+        for s in (1, 2, 3):
+            assert np.array_equal(o.rows(s), ref.rows(s))
+        assert o.stats() == ref.stats()
+        assert np.array_equal(o.copies(), ref.copies()) and np.array_equal(o.handles(), ref.handles())
+        assert ref.copies().size > 2 and int(ref.handles()[0]["creates"]) > 10
+        o.close()
+
+
+def test_packed_layout_closed_form():
+    """Two events in one packet: header 16 B, event 1 (16 + 3 payload bytes,
+    padded to 24), event 2 (16 + 8 = 24): 64 bytes."""
+    ev = [(T + 1, 9, 0, ENTRY, b"abc"), (T + 5, 9, 0, EXIT, u64(7))]
+    buf, ix = packed(ev, 4096)
+    assert buf.size == 64 and list(ix) == [0]
+    assert struct.unpack("<IIII", buf[:16].tobytes()) == (0x4B504854, 64, 2, 0)
+    assert buf[16 + 15] == 3 and buf[40 + 15] == 8 and bytes(buf[32:35]) == b"abc" and not buf[35:40].any()
+
+
+def test_packed_malformed_chunks_change_nothing():
+    ev = [(T + 1, 9, 0, ENTRY, b"abc"), (T + 5, 9, 0, EXIT, b""), (T + 9, 9, 1, ENTRY, b"12345678"),
+          (T + 12, 9, 1, EXIT, b"")]
+    buf, ix = packed(ev, 48)
+    assert len(ix) == 4
+    o = oracle.Oracle(2, 2, 0, 16)
+
+    def bad(b, i):
+        assert o.submit_packed(KEY, b, i) == -1
+
+    b = buf.copy(); b[0] ^= 1; bad(b, ix)                                  # magic
+    b = buf.copy(); b[4:8] = np.frombuffer(struct.pack("<I", 48), np.uint8); bad(b, ix)   # packet size
+    b = buf.copy(); b[8:12] = np.frombuffer(struct.pack("<I", 2), np.uint8); bad(b, ix)   # event count
+    bad(buf, ix[:-1])                                                      # packets do not cover the chunk
+    bad(buf, np.array([0, int(ix[2]), int(ix[1]), int(ix[3])], dtype=np.uint64))   # index out of order
+    bad(buf[:-8], ix)                                                      # truncated
+    b = buf.copy(); b[16 + 15] = 40; bad(b, ix)                            # payload runs past its packet
+    o2 = oracle.Oracle(1, 2, 0, 16)
+    assert o2.submit_packed(KEY, buf, ix) == -1                            # not a VAR16 oracle
+    assert o.stats()["records"] == 0
+    assert o.submit_packed(KEY, buf, ix) == 0 and o.stats()["records"] == 4

@@ -63,9 +63,26 @@ extern "C" {
  *   payload_len >= 8 carries its u64 transfer size at payload offset 0 (the
  *   typed "size" argument of the section 1.1 record).  A kernel record carries
  *   its u64 end time at payload offset 0 and needs payload_len >= 8.
+ * THAPI_FMT_PACKED, interleaved variable-length records as a trace writer
+ *   lays them out (a CTF-like stream, section 3.1): packets one after the
+ *   other, each a 16-byte header [0,4) magic 0x4B504854 ("THPK") | [4,8)
+ *   packet bytes (header included, a multiple of 8) | [8,12) events |
+ *   [12,16) 0, followed by its events, every event a VAR16 header with its
+ *   payload inline and padded with zeros to a multiple of 8 bytes; the
+ *   events must fill the packet exactly.  submit() takes the packet bytes as
+ *   `records` (a multiple of 8 bytes) and, as `payload`, the packet index:
+ *   the u64 byte offset of every packet, ascending, the first 0 and each
+ *   next packet starting where the previous one ends (the index a trace
+ *   reader keeps, which lets packets be decoded in parallel).  A flush
+ *   decodes packed chunks on the GPU and tallies their events as VAR16
+ *   records (fn_has_size and kernel records as for VAR16); results equal
+ *   those of the same events submitted as VAR16.  Host input is checked by
+ *   submit (THAPI_E_INVAL); device input by the flush, which fails with
+ *   THAPI_E_INVAL and leaves the handle failed.
  * Host and process come from the stream key, not from the record. */
 #define THAPI_FMT_FIXED24 1u
 #define THAPI_FMT_VAR16   2u
+#define THAPI_FMT_PACKED  3u
 
 /* ---- open flags -------------------------------------------------------- */
 #define THAPI_DEVICE_INPUT 0x01u /* submit() takes device pointers (e.g. a torch tensor's data_ptr) */
@@ -105,7 +122,7 @@ typedef struct thapi_tally thapi_tally; /* opaque, owned by the library */
 
 typedef struct {
   uint32_t abi_version;         /* must equal THAPI_TALLY_ABI_VERSION */
-  uint32_t format;              /* THAPI_FMT_FIXED24 or THAPI_FMT_VAR16 */
+  uint32_t format;              /* THAPI_FMT_FIXED24, THAPI_FMT_VAR16 or THAPI_FMT_PACKED */
   uint32_t n_fns;               /* API fn ids must be < n_fns (1..65536) */
   uint32_t n_kernel_ids;        /* kernel ids must be < n_kernel_ids (0..65536) */
   uint32_t max_depth;           /* per-thread call-stack limit, 1..64; 0 -> 64 (a smaller limit lets one
@@ -351,6 +368,58 @@ typedef struct {                 /* 56 bytes */
 } thapi_tally_interval;
 #define THAPI_OUT_DEVICE 0x1u
 int thapi_tally_intervals(thapi_tally *t, thapi_tally_interval *out, size_t cap, size_t *n, uint32_t flags);
+
+/* Payload analytics (VAR16 and packed handles).  Functions can be given a
+ * role, and every record of such a function that carries the role's payload
+ * counts, whether or not its call is tallied (these are per-record counts,
+ * made while the records are decoded):
+ *   THAPI_ROLE_COPY: an entry with payload_len >= 24 carries a transfer
+ *     size (u64 at payload offset 0), its destination (8) and source (16)
+ *     pointers.  A pointer whose top byte is 0xff is device memory, any other
+ *     host memory (section 1.1 reads a copy's direction from these prefixes).
+ *     Per (stream, fn, direction) the entries are counted and the sizes
+ *     summed; direction = 2 * (source on device) + (destination on device):
+ *     THAPI_DIR_H2H 0, THAPI_DIR_H2D 1, THAPI_DIR_D2H 2, THAPI_DIR_D2D 3.
+ *   THAPI_ROLE_CREATE: an exit with payload_len >= 8 returns a handle (u64
+ *     at offset 0).  THAPI_ROLE_RELEASE: an entry with payload_len >= 8
+ *     takes one.  Creates and releases of a stream are joined by handle value
+ *     (the validation of section 4.2, which reports releases that were never
+ *     handled): a value created C times and released R times leaves
+ *     max(0, C - R) handles unreleased and max(0, R - C) releases that match
+ *     no create.  Record order is not considered, and handles persist across
+ *     flushes until a reset.
+ * thapi_tally_set_roles: roles[fn] in {0, THAPI_ROLE_*} for every fn
+ * (n_fns must equal the handle's), and room for max_handles distinct
+ * (stream, handle) values.  Valid once, before the first submit after open
+ * or reset (THAPI_E_STATE otherwise); a reset clears the tables and keeps
+ * the roles.  More distinct handles than that room fail the flush with
+ * THAPI_E_CAPACITY.  Errors: THAPI_E_INVAL (FIXED24 handle, bad role),
+ * THAPI_E_NOMEM, THAPI_E_STATE, THAPI_E_DEVICE.
+ * thapi_tally_copies / thapi_tally_handles: the rows of trace_id (THAPI_ALL:
+ * all) in order (trace, host, pid[, fn, dir]): one copy row per (stream, fn,
+ * direction) with entries, one handle row per stream with a create or a
+ * release.  Two-call pattern as for read (THAPI_E_BUFSZ).  THAPI_E_STATE when
+ * no roles were set. */
+#define THAPI_ROLE_COPY    1u
+#define THAPI_ROLE_CREATE  2u
+#define THAPI_ROLE_RELEASE 3u
+#define THAPI_DIR_H2H 0u
+#define THAPI_DIR_H2D 1u
+#define THAPI_DIR_D2H 2u
+#define THAPI_DIR_D2D 3u
+typedef struct {                 /* 40 bytes */
+  uint32_t trace_id, host_id, pid, fn, dir, pad;
+  uint64_t count, bytes;
+} thapi_copy_row;
+typedef struct {                 /* 56 bytes */
+  uint32_t trace_id, host_id, pid, pad;
+  uint64_t creates, releases, handles, unreleased, unmatched;
+} thapi_handle_row;
+int thapi_tally_set_roles(thapi_tally *t, const uint8_t *roles, uint32_t n_fns, uint32_t max_handles);
+int thapi_tally_copies(thapi_tally *t, uint32_t trace_id, thapi_copy_row *rows, size_t capacity,
+                       size_t *n_rows);
+int thapi_tally_handles(thapi_tally *t, uint32_t trace_id, thapi_handle_row *rows, size_t capacity,
+                        size_t *n_rows);
 
 /* Frees everything.  Queued chunks that were never flushed are discarded. */
 int thapi_tally_close(thapi_tally *t);

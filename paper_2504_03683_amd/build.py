@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libthapi_tally.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
-SOURCES = ["tt_range.hip", "tt_post.hip", "tt_host.hip", "tt_membw.hip"]
+SOURCES = ["tt_range.hip", "tt_post.hip", "tt_host.hip", "tt_membw.hip", "tt_payload.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

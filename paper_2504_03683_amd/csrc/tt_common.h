@@ -161,6 +161,19 @@ struct Tables {
   uint32_t civ_cap;
 };
 
+// Payload analytics tables (tt_payload.hip).  hs: 0 free, stream + 1 once
+// the slot's handle is written, with the top bit set while it is written.
+struct PayTables {
+  const uint8_t *roles;        // [n_fns] 0, copy 1, create 2, release 3
+  uint64_t *copies;            // [max_streams][n_fns][4] {count, bytes}
+  uint64_t *hk;                // [cap] handle values
+  uint32_t *hs;                // [cap] stream + 1
+  uint32_t *hc, *hr;           // [cap] creates, releases
+  uint32_t hmask;              // cap - 1
+  uint32_t n_fns;
+  uint32_t *err;
+};
+
 // Launch shape of the range kernel (tile of T records, LDS tally of E entries).
 struct Shape {
   uint32_t T;           // records per tile (a multiple of the range kernel's 1024 lanes)

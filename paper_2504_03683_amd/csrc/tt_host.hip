@@ -48,6 +48,15 @@ hipError_t launch_final(const Tables &tb, uint32_t max_threads, hipStream_t st);
 hipError_t launch_iv_out(const Tables &tb, const uint64_t *ivbase, const RHdr *rhdr, uint32_t n_ranges,
                          const uint32_t *rnslots, const uint64_t *off, const uint32_t *skeys, void *out,
                          hipStream_t st);
+hipError_t launch_pk_count(const uint8_t *buf, uint64_t nbytes, const uint64_t *index, uint32_t n_packets,
+                           uint32_t *ev, uint64_t *pay, uint32_t *err, hipStream_t st);
+hipError_t launch_pk_scan(uint32_t *ev, uint64_t *pay, uint32_t n, uint64_t *ev_off, uint64_t *tot, hipStream_t st);
+hipError_t launch_pk_write(const uint8_t *buf, uint64_t nbytes, const uint64_t *index, uint32_t n_packets,
+                           const uint64_t *ev_off, const uint64_t *pay_off, uint64_t *hdr, uint64_t *heap,
+                           uint32_t *err, hipStream_t st);
+hipError_t launch_payload(const Seg *segs, const Range *ranges, uint32_t n_ranges, const PayTables &pt,
+                          hipStream_t st);
+hipError_t launch_handle_stats(const PayTables &pt, unsigned long long *out, hipStream_t st);
 hipError_t launch_thread_stats(const Tables &tb, uint32_t max_threads, unsigned long long *out, uint32_t ns,
                                uint32_t ns1, hipStream_t st);
 hipError_t launch_sort_threads(const Tables &tb, const uint32_t *stream_rank, uint64_t *keys, uint32_t *vals,
@@ -154,6 +163,8 @@ struct Chunk {
   bool in_ring;      // service mode: the bytes went through the pinned staging ring
   bool ready;        // service mode: the copy to the device is enqueued (or complete)
   int ev;            // service mode: event recorded after the copy (index into the pool), or -1
+  uint64_t pk_bytes;    // packed chunk not yet decoded: its bytes (rec) and packets (index at pay)
+  uint64_t pk_packets;
 };
 
 // First-in first-out allocator over [0, cap): allocations are released in the
@@ -249,6 +260,15 @@ struct thapi_tally {
 
   DevBuf rhdr, ru, ro, rnslots, rmore, paylen;
   DevBuf wide_pack;                                   // the extra passes' work list
+  // packed chunks decoded into VAR16 for one flush: per-packet counts and
+  // offsets, then the headers and kept payload words
+  DevBuf pk_scr, pk_hdr, pk_heap;
+  // payload roles (thapi_tally_set_roles): the copy and handle tables
+  bool roles_on = false;
+  PayTables pt{};
+  uint32_t hcap = 0;
+  void *d_roles = nullptr, *d_copies = nullptr, *d_hk = nullptr, *d_hs2 = nullptr, *d_hc = nullptr, *d_hr = nullptr;
+  DevBuf hstat;
   // THAPI_INTERVALS: the current flush's interval buffers (see Tables), the
   // public records of the last intervals() call and its offsets / keys
   DevBuf iv, iv_n, iv_h0, iv_snap, civ, civ_n, ivout, ivaux;
@@ -317,7 +337,13 @@ int hip_fail(thapi_tally *t, hipError_t e) {
 }
 #define HIPCHK(x) do { hipError_t _e = (x); if (_e != hipSuccess) return hip_fail(t, _e); } while (0)
 
-uint32_t record_size(const thapi_tally *t) { return t->cfg.format == THAPI_FMT_VAR16 ? 16u : 24u; }
+// The record layout the kernels see: packed chunks are turned into VAR16
+// before a flush tallies them.
+int kfmt(const thapi_tally *t) { return t->cfg.format == THAPI_FMT_FIXED24 ? 1 : 2; }
+// Granularity of submitted record bytes (packed chunks: 8-byte words).
+uint32_t record_size(const thapi_tally *t) {
+  return t->cfg.format == THAPI_FMT_FIXED24 ? 24u : (t->cfg.format == THAPI_FMT_VAR16 ? 16u : 8u);
+}
 
 // Resets every table in one launch on the handle's stream; `wait` also
 // waits for it (a reset does not: whatever follows on the stream is ordered
@@ -342,12 +368,13 @@ hipError_t init_tables(thapi_tally *t, bool wait = true) {
 
 void free_all(thapi_tally *t) {
   void *ps[] = {t->d_gkeys, t->d_gvals, t->d_ngs, t->d_ths, t->d_tht, t->d_tally, t->d_ktally,
-                t->d_cstate, t->d_cstack, t->d_sstats, t->d_err, t->d_hs, t->d_thord, t->d_snth};
+                t->d_cstate, t->d_cstack, t->d_sstats, t->d_err, t->d_hs, t->d_thord, t->d_snth,
+                t->d_roles, t->d_copies, t->d_hk, t->d_hs2, t->d_hc, t->d_hr};
   for (void *p : ps) if (p) hipFree(p);
   DevBuf *bs[] = {&t->plan_pack, &t->rhdr, &t->ru, &t->ro, &t->rnslots, &t->rmore, &t->wide_pack, &t->paylen, &t->keys, &t->vals, &t->keys2,
                   &t->vals2, &t->gbeg, &t->gend, &t->cnt, &t->off, &t->read_pack, &t->rows, &t->tstats,
                   &t->merge_buf, &t->iv, &t->iv_n, &t->iv_h0, &t->iv_snap, &t->civ, &t->civ_n, &t->ivout,
-                  &t->ivaux};
+                  &t->ivaux, &t->pk_scr, &t->pk_hdr, &t->pk_heap, &t->hstat};
   for (DevBuf *b : bs) b->release();
   for (auto &c : t->queue) if (c.owned) hipFree(c.owned);
   t->queue.clear();
@@ -370,7 +397,7 @@ void free_all(thapi_tally *t) {
 Shape pick_shape(const thapi_tally *t) {
   Shape s{};
   const uint32_t D = t->cfg.max_depth;
-  const int fmt = (int)t->cfg.format;
+  const int fmt = kfmt(t);
   s.KL = std::min<uint32_t>(t->cfg.n_kernel_ids, KL_MAX);
   s.rpc = 1;
   s.pipe = 1;   // producer and walker waves overlap (the faster schedule on the layered workload)
@@ -447,12 +474,14 @@ namespace {
 void load_tune_cache(thapi_tally *t);
 void service_loop(thapi_tally *t);
 hipError_t grow_plan_staging(thapi_tally *t, size_t bytes);
+hipError_t clear_payload_tables(thapi_tally *t);
 }  // namespace
 
 int thapi_tally_open(const thapi_tally_config *cfg, thapi_tally **out) {
   if (!cfg || !out) return THAPI_E_INVAL;
   if (cfg->abi_version != THAPI_TALLY_ABI_VERSION) return THAPI_E_INVAL;
-  if (cfg->format != THAPI_FMT_FIXED24 && cfg->format != THAPI_FMT_VAR16) return THAPI_E_INVAL;
+  if (cfg->format != THAPI_FMT_FIXED24 && cfg->format != THAPI_FMT_VAR16 && cfg->format != THAPI_FMT_PACKED)
+    return THAPI_E_INVAL;
   if (cfg->n_fns < 1 || cfg->n_fns > 65536 || cfg->n_kernel_ids > 65536) return THAPI_E_INVAL;
   if (cfg->max_depth > THAPI_MAX_DEPTH_LIMIT || cfg->reserved) return THAPI_E_INVAL;
   if (cfg->max_threads > (1u << 30) || cfg->max_streams > (1u << 24)) return THAPI_E_INVAL;
@@ -471,7 +500,7 @@ int thapi_tally_open(const thapi_tally_config *cfg, thapi_tally **out) {
   t->cfg.fn_has_size = nullptr;
   if (cfg->autotune_cache) t->cache_path = cfg->autotune_cache;
   t->cfg.autotune_cache = nullptr;
-  if (cfg->format == THAPI_FMT_VAR16 && cfg->fn_has_size)
+  if (cfg->format != THAPI_FMT_FIXED24 && cfg->fn_has_size)
     t->has_size.assign(cfg->fn_has_size, cfg->fn_has_size + cfg->n_fns);
   const thapi_tally_config &c = t->cfg;
   auto bail = [&](int code) { free_all(t); delete t; return code; };
@@ -607,6 +636,34 @@ uint64_t now_ns() {
 
 }  // namespace
 
+namespace {
+// Events of a packed chunk held in host memory, checked the way the decode
+// kernels check them (magic, sizes, 8-byte alignment, events filling each
+// packet exactly, packets contiguous and covering the chunk); UINT64_MAX
+// when it is malformed.
+uint64_t packed_events(const uint8_t *buf, uint64_t nbytes, const uint64_t *index, uint64_t n_packets) {
+  uint64_t events = 0;
+  for (uint64_t k = 0; k < n_packets; k++) {
+    const uint64_t off = index[k];
+    if (off % 8 || off + 16 > nbytes || (k == 0 && off != 0)) return UINT64_MAX;
+    uint32_t h[4];
+    memcpy(h, buf + off, 16);
+    if (h[0] != 0x4B504854u || h[3] || h[1] < 16 || h[1] % 8 || off + h[1] > nbytes) return UINT64_MAX;
+    if ((k + 1 < n_packets ? index[k + 1] : nbytes) != off + h[1]) return UINT64_MAX;
+    uint64_t o = 16;
+    for (uint32_t e = 0; e < h[2]; e++) {
+      if (o + 16 > h[1]) return UINT64_MAX;
+      const uint64_t sz = (16 + (uint64_t)buf[off + o + 15] + 7) / 8 * 8;
+      if (o + sz > h[1]) return UINT64_MAX;
+      o += sz;
+    }
+    if (o != h[1]) return UINT64_MAX;
+    events += h[2];
+  }
+  return events;
+}
+}  // namespace
+
 int thapi_tally_submit(thapi_tally *t, const thapi_stream_key *key, const void *records, size_t record_bytes,
                        const void *payload, size_t payload_bytes, uint64_t *ticket_out) {
   if (!t || !key || key->reserved) return THAPI_E_INVAL;
@@ -614,8 +671,13 @@ int thapi_tally_submit(thapi_tally *t, const thapi_stream_key *key, const void *
   if (record_bytes % rs) return THAPI_E_INVAL;
   if (record_bytes && !records) return THAPI_E_INVAL;
   const bool var = t->cfg.format == THAPI_FMT_VAR16;
-  if (!var && (payload || payload_bytes)) return THAPI_E_INVAL;
+  const bool pk = t->cfg.format == THAPI_FMT_PACKED;
+  if (!var && !pk && (payload || payload_bytes)) return THAPI_E_INVAL;
   if (payload_bytes && !payload) return THAPI_E_INVAL;
+  // packed: the payload argument is the packet index (u64 offsets), one packet at least
+  if (pk && (payload_bytes % 8 || (record_bytes && !payload_bytes) || (!record_bytes && payload_bytes) ||
+             payload_bytes / 8 > UINT32_MAX))
+    return THAPI_E_INVAL;
   const bool dev_in = (t->cfg.flags & THAPI_DEVICE_INPUT) != 0;
   if (dev_in && ((uintptr_t)records & 7)) return THAPI_E_INVAL;
   const uint64_t n_rec = record_bytes / rs;
@@ -636,6 +698,13 @@ int thapi_tally_submit(thapi_tally *t, const thapi_stream_key *key, const void *
   } else if (var && !n_rec && payload_bytes) {
     return THAPI_E_INVAL;
   }
+  uint64_t pk_events = 0;
+  if (pk && n_rec && !dev_in) {
+    if (((uintptr_t)payload & 7) != 0) return THAPI_E_INVAL;
+    pk_events = packed_events((const uint8_t *)records, record_bytes, (const uint64_t *)payload, payload_bytes / 8);
+    if (pk_events == UINT64_MAX) return THAPI_E_INVAL;
+  }
+  if (pk && dev_in && ((uintptr_t)payload & 7)) return THAPI_E_INVAL;
   std::unique_lock<std::mutex> lk(t->mu);
   t->gen++;
   SKey sk{key->trace_id, key->host_id, key->pid};
@@ -653,7 +722,8 @@ int thapi_tally_submit(thapi_tally *t, const thapi_stream_key *key, const void *
   Chunk c{};
   c.ev = -1;
   c.stream = sidx;
-  c.n_rec = n_rec;
+  c.n_rec = pk ? 0 : n_rec;
+  if (pk) { c.pk_bytes = record_bytes; c.pk_packets = payload_bytes / 8; }
   c.pay_bytes = payload_bytes;
   c.ready = true;
   const bool service = (t->cfg.flags & THAPI_SERVICE) != 0;
@@ -676,7 +746,7 @@ int thapi_tally_submit(thapi_tally *t, const thapi_stream_key *key, const void *
       if (t->failed || t->stop) return THAPI_E_STATE;
       if (t->afifo.fit(bytes, &off) && (!via_ring || t->rfifo.fit(bytes, &roff))) break;
       if (t->cfg.flags & THAPI_DROP_ON_FULL) {
-        t->dropped[sidx] += n_rec;
+        t->dropped[sidx] += pk ? pk_events : n_rec;
         if (ticket_out) *ticket_out = 0;
         return THAPI_OK;
       }
@@ -731,7 +801,7 @@ int thapi_tally_submit(thapi_tally *t, const thapi_stream_key *key, const void *
     if (bytes > t->cfg.device_budget_bytes) return THAPI_E_NOMEM;
     while (t->budget_used + bytes > t->cfg.device_budget_bytes) {
       if (t->cfg.flags & THAPI_DROP_ON_FULL) {
-        t->dropped[sidx] += n_rec;
+        t->dropped[sidx] += pk ? pk_events : n_rec;
         if (ticket_out) *ticket_out = 0;
         return THAPI_OK;
       }
@@ -992,13 +1062,14 @@ hipError_t launch_pipeline(thapi_tally *t, const Plan &pl, const Shape &sh, bool
   LPCHK(launch_fill32(t->tb.err, 1, 0, t->st));
   if (t->tb.civ_n) LPCHK(launch_fill32(t->tb.civ_n, 1, 0, t->st));
   if (nR) {
-    if (t->cfg.format == THAPI_FMT_VAR16) {
+    if (kfmt(t) == 2) {
       TB(TM_PREPASS);
       LPCHK(launch_paylen(fb.segs, fb.ranges, nR, fb.segfirst, nS, fb.paylen, t->tb.err, t->st));
+      if (t->roles_on) LPCHK(launch_payload(fb.segs, fb.ranges, nR, t->pt, t->st));
       TE(TM_PREPASS);
     }
     TB(TM_RANGE);
-    LPCHK(launch_range((int)t->cfg.format, sh.T, fb.segs, fb.ranges, fb.order, nR, fb.qhead, (uint32_t)t->n_cu, t->tb,
+    LPCHK(launch_range(kfmt(t), sh.T, fb.segs, fb.ranges, fb.order, nR, fb.qhead, (uint32_t)t->n_cu, t->tb,
                        sh, fb.rhdr, fb.ru, fb.ro, fb.rnslots, fb.rmore, fb.ranges, 0, t->st));
     TE(TM_RANGE);
     TB(TM_COMBINE);
@@ -1089,7 +1160,7 @@ Shape shape_for(thapi_tally *t, const std::vector<Chunk> &work) {
   auto it = t->tuned.find(tune_key(t, work));
   if (it == t->tuned.end()) return t->shape;
   Shape s = t->shape;
-  const size_t b = range_lds_bytes(it->second[0], it->second[1], s.KL, t->cfg.max_depth, (int)t->cfg.format);
+  const size_t b = range_lds_bytes(it->second[0], it->second[1], s.KL, t->cfg.max_depth, kfmt(t));
   if ((it->second[0] == 1024 || it->second[0] == 2048) && it->second[1] >= 64 && b + 256 <= t->lds_limit) {
     s.T = it->second[0]; s.E = it->second[1]; s.lds_bytes = (uint32_t)b;
     s.rpc = std::max<uint32_t>(1, std::min<uint32_t>(it->second[2], 64));
@@ -1205,7 +1276,7 @@ hipError_t run_extra_passes(thapi_tally *t, const Plan &pl, const Shape &sh, boo
   if (t->tb.civ_n) XCHK(launch_fill32(t->tb.civ_n, 1, 0, t->st));
   Shape sx = sh;
   sx.pipe = 0;   // (extra passes run one schedule: all waves build a tile, then walk it)
-  XCHK(launch_range((int)t->cfg.format, sh.T, fb.segs, d_ex, d_order, nE, d_qhead, (uint32_t)t->n_cu, t->tb, sx,
+  XCHK(launch_range(kfmt(t), sh.T, fb.segs, d_ex, d_order, nE, d_qhead, (uint32_t)t->n_cu, t->tb, sx,
                     fb.rhdr, fb.ru, fb.ro, fb.rnslots, fb.rmore, fb.ranges, nR, t->st));
   XCHK(launch_combine(d_spans, (uint32_t)(spans2.size() / 3), fb.rhdr, fb.ru, fb.ro, fb.rnslots, t->tb, d_clist,
                       t->st));
@@ -1215,6 +1286,77 @@ hipError_t run_extra_passes(thapi_tally *t, const Plan &pl, const Shape &sh, boo
   *err = h[0];
 #undef XCHK
   return hipSuccess;
+}
+
+// Packed chunks of a batch (taken off the queue by the caller) become VAR16
+// chunks in the handle's decode buffers: per chunk, every packet's events
+// and kept payload bytes are counted (one lane per packet, the packet index
+// giving each lane its start), the counts are scanned and the totals
+// fetched, then the events are written out.  The staged copies stay owned by
+// the chunks.  A malformed chunk fails the handle with THAPI_E_INVAL (the
+// batch is released untallied).  Caller holds run_mu.
+int transcode_packed(thapi_tally *t, std::vector<Chunk> &work) {
+  if (t->cfg.format != THAPI_FMT_PACKED) return THAPI_OK;
+  std::vector<size_t> which;
+  uint64_t npk = 0;
+  for (size_t i = 0; i < work.size(); i++)
+    if (work[i].pk_packets) { which.push_back(i); npk += work[i].pk_packets; }
+  if (which.empty()) return THAPI_OK;
+  if (hipSetDevice(t->dev) != hipSuccess) return THAPI_E_DEVICE;
+  const size_t nc = which.size();
+  // scratch: per packet events (u32), kept bytes then their offsets (u64),
+  // event offsets (u64); per chunk the two totals
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t b_ev = al(4 * npk), b_pay = al(8 * npk), b_off = al(8 * npk), b_tot = al(16 * nc);
+  HIPCHK(t->pk_scr.ensure(b_ev + b_pay + b_off + b_tot));
+  uint8_t *sc = t->pk_scr.as<uint8_t>();
+  uint32_t *ev = (uint32_t *)sc;
+  uint64_t *pay = (uint64_t *)(sc + b_ev), *evoff = (uint64_t *)(sc + b_ev + b_pay);
+  uint64_t *tot = (uint64_t *)(sc + b_ev + b_pay + b_off);
+  HIPCHK(launch_fill32(t->tb.err, 1, 0, t->st));
+  // streaming form: the decode waits on the device for the chunks' copies
+  for (size_t j : which)
+    if (work[j].ev >= 0) HIPCHK(hipStreamWaitEvent(t->st, t->ev_pool[work[j].ev], 0));
+  uint64_t o = 0;
+  for (size_t j = 0; j < nc; j++) {
+    const Chunk &c = work[which[j]];
+    HIPCHK(launch_pk_count(c.rec, c.pk_bytes, (const uint64_t *)c.pay, (uint32_t)c.pk_packets, ev + o, pay + o,
+                           t->tb.err, t->st));
+    HIPCHK(launch_pk_scan(ev + o, pay + o, (uint32_t)c.pk_packets, evoff + o, tot + 2 * j, t->st));
+    o += c.pk_packets;
+  }
+  HIPCHK(ensure_pinned(t, 16 * nc + 16));
+  uint64_t *h = (uint64_t *)t->h_pinned;
+  HIPCHK(hipMemcpyAsync(h, tot, 16 * nc, hipMemcpyDeviceToHost, t->st));
+  HIPCHK(hipMemcpyAsync(h + 2 * nc, t->tb.err, 4, hipMemcpyDeviceToHost, t->st));
+  HIPCHK(hipStreamSynchronize(t->st));
+  if ((uint32_t)h[2 * nc] & ERR_PAYLOAD) {
+    std::lock_guard<std::mutex> g(t->mu);
+    for (auto &c : work) release_chunk(t, c);
+    work.clear();
+    t->failed = THAPI_E_INVAL;
+    t->cv.notify_all();
+    return THAPI_E_INVAL;
+  }
+  uint64_t ne = 0, nb = 0;
+  std::vector<uint64_t> ebase(nc), bbase(nc);
+  for (size_t j = 0; j < nc; j++) { ebase[j] = ne; bbase[j] = nb; ne += h[2 * j]; nb += h[2 * j + 1]; }
+  HIPCHK(t->pk_hdr.ensure(16 * std::max<uint64_t>(ne, 1)));
+  HIPCHK(t->pk_heap.ensure(std::max<uint64_t>(nb, 8)));
+  uint64_t *hdr = t->pk_hdr.as<uint64_t>(), *heap = t->pk_heap.as<uint64_t>();
+  o = 0;
+  for (size_t j = 0; j < nc; j++) {
+    Chunk &c = work[which[j]];
+    HIPCHK(launch_pk_write(c.rec, c.pk_bytes, (const uint64_t *)c.pay, (uint32_t)c.pk_packets, evoff + o, pay + o,
+                           hdr + 2 * ebase[j], heap + bbase[j] / 8, t->tb.err, t->st));
+    o += c.pk_packets;
+    c.rec = (const uint8_t *)(hdr + 2 * ebase[j]);
+    c.n_rec = h[2 * j];
+    c.pay = (const uint8_t *)(heap + bbase[j] / 8);
+    c.pay_bytes = h[2 * j + 1];
+    c.pk_packets = 0;
+  }
+  return THAPI_OK;
 }
 
 // Tallies one batch of chunks, planned by prepare_batch (`pl`, `sh`) and
@@ -1254,7 +1396,7 @@ int process_batch(thapi_tally *t, std::vector<Chunk> &work, bool final, const Pl
     collect_timing(t, TM_RANGE);  // whole graph
   } else {
     if (nR) {
-      if (t->cfg.format == THAPI_FMT_VAR16) collect_timing(t, TM_PREPASS);
+      if (kfmt(t) == 2) collect_timing(t, TM_PREPASS);
       collect_timing(t, TM_RANGE);
       collect_timing(t, TM_COMBINE);
     }
@@ -1322,9 +1464,12 @@ void service_loop(thapi_tally *t) {
     int rc;
     {
       std::lock_guard<std::mutex> run(t->run_mu);
-      Plan pl;
-      const Shape sh = prepare_batch(t, work, pl);
-      rc = process_batch(t, work, false, pl, sh);
+      rc = transcode_packed(t, work);
+      if (rc == THAPI_OK) {
+        Plan pl;
+        const Shape sh = prepare_batch(t, work, pl);
+        rc = process_batch(t, work, false, pl, sh);
+      }
     }
     const uint64_t tdone = now_ns();
     std::lock_guard<std::mutex> g(t->mu);
@@ -1371,16 +1516,18 @@ int thapi_tally_flush(thapi_tally *t, uint64_t ticket, uint32_t flags) {
       t->queue.pop_front();
     }
   }
+  const int trc = transcode_packed(t, work);
+  if (trc != THAPI_OK) return trc;
   Plan pl;
   const Shape sh = prepare_batch(t, work, pl);
   return process_batch(t, work, final, pl, sh);
 }
 
-
-
 int thapi_tally_flush_noalloc(thapi_tally *t, uint64_t ticket, uint32_t flags) {
   if (!t) return THAPI_E_INVAL;
-  if ((t->cfg.flags & (THAPI_SERVICE | THAPI_INTERVALS)) || !(t->cfg.flags & THAPI_DEVICE_INPUT)) return THAPI_E_INVAL;
+  if ((t->cfg.flags & (THAPI_SERVICE | THAPI_INTERVALS)) || !(t->cfg.flags & THAPI_DEVICE_INPUT) ||
+      t->cfg.format == THAPI_FMT_PACKED)
+    return THAPI_E_INVAL;
   if (t->dev < 0 || t->dev >= MAX_DEVICES) return THAPI_E_INVAL;
   uint8_t *const scr = scratch_on(t->dev);
   if (!scr) return THAPI_E_DEVICE;
@@ -1450,14 +1597,16 @@ int thapi_tally_autotune(thapi_tally *t, uint32_t reps, uint32_t *chosen) {
   {
     std::lock_guard<std::mutex> g(t->mu);
     if (t->failed) return t->failed == THAPI_E_DEVICE ? THAPI_E_DEVICE : THAPI_E_STATE;
-    if (t->finalized || t->flushed_any || t->queue.empty() || (t->cfg.flags & THAPI_SERVICE)) return THAPI_E_STATE;
+    if (t->finalized || t->flushed_any || t->queue.empty() || (t->cfg.flags & THAPI_SERVICE) ||
+        t->cfg.format == THAPI_FMT_PACKED)
+      return THAPI_E_STATE;
     work.assign(t->queue.begin(), t->queue.end());
   }
   if (hipSetDevice(t->dev) != hipSuccess) return THAPI_E_DEVICE;
   std::stable_sort(work.begin(), work.end(), [](const Chunk &a, const Chunk &b) { return a.stream < b.stream; });
   reps = std::max<uint32_t>(1, std::min<uint32_t>(reps, 16));
   const uint32_t D = t->cfg.max_depth;
-  const int fmt = (int)t->cfg.format;
+  const int fmt = kfmt(t);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
@@ -1714,6 +1863,7 @@ int thapi_tally_reset(thapi_tally *t) {
   if (hipSetDevice(t->dev) != hipSuccess) return THAPI_E_DEVICE;
   t->gen++;
   if (init_tables(t, false) != hipSuccess) return hip_fail(t, hipErrorUnknown);
+  if (clear_payload_tables(t) != hipSuccess) return hip_fail(t, hipErrorUnknown);
   std::lock_guard<std::mutex> g(t->mu);
   t->stream_idx.clear();
   t->stream_keys.clear();
@@ -1807,6 +1957,146 @@ int thapi_tally_intervals(thapi_tally *t, thapi_tally_interval *out, size_t cap,
   if (!on_dev) HIPCHK(hipMemcpyAsync(out, dst, sizeof(thapi_tally_interval) * total, hipMemcpyDeviceToHost, t->st));
   HIPCHK(hipStreamSynchronize(t->st));
   collect_timing(t, TM_IVOUT);
+  return THAPI_OK;
+}
+
+namespace {
+// Clears the copy and handle tables (on the handle's stream).
+hipError_t clear_payload_tables(thapi_tally *t) {
+  if (!t->roles_on) return hipSuccess;
+  hipError_t e;
+  const size_t nc = (size_t)t->cfg.max_streams * t->cfg.n_fns * 8;
+  if ((e = launch_fill64((uint64_t *)t->d_copies, nc, 0, t->st)) != hipSuccess) return e;
+  if ((e = launch_fill32((uint32_t *)t->d_hs2, t->hcap, 0, t->st)) != hipSuccess) return e;
+  if ((e = launch_fill32((uint32_t *)t->d_hc, t->hcap, 0, t->st)) != hipSuccess) return e;
+  return launch_fill32((uint32_t *)t->d_hr, t->hcap, 0, t->st);
+}
+
+// Stream indices of the registered streams in canonical (trace, host, pid)
+// order, keeping those of trace `trace` (or all).
+std::vector<uint32_t> canonical_streams(const thapi_tally *t, uint32_t trace) {
+  std::vector<uint32_t> v;
+  for (uint32_t i = 0; i < t->stream_keys.size(); i++)
+    if (trace == THAPI_ALL || t->stream_keys[i][0] == trace) v.push_back(i);
+  std::sort(v.begin(), v.end(), [&](uint32_t a, uint32_t b) { return t->stream_keys[a] < t->stream_keys[b]; });
+  return v;
+}
+}  // namespace
+
+int thapi_tally_set_roles(thapi_tally *t, const uint8_t *roles, uint32_t n_fns, uint32_t max_handles) {
+  if (!t || !roles || n_fns != t->cfg.n_fns || t->cfg.format == THAPI_FMT_FIXED24) return THAPI_E_INVAL;
+  for (uint32_t i = 0; i < n_fns; i++)
+    if (roles[i] > THAPI_ROLE_RELEASE) return THAPI_E_INVAL;
+  std::lock_guard<std::mutex> run(t->run_mu);
+  {
+    std::lock_guard<std::mutex> g(t->mu);
+    if (t->failed) return t->failed == THAPI_E_DEVICE ? THAPI_E_DEVICE : THAPI_E_STATE;
+    if (t->roles_on || t->flushed_any || !t->queue.empty()) return THAPI_E_STATE;
+  }
+  if (hipSetDevice(t->dev) != hipSuccess) return THAPI_E_DEVICE;
+  uint32_t cap = 64;
+  while (cap < 2ull * std::max<uint32_t>(max_handles, 1)) {
+    if (cap >= (1u << 30)) return THAPI_E_INVAL;
+    cap <<= 1;
+  }
+  struct A { void **p; size_t bytes; } allocs[] = {
+      {&t->d_roles, n_fns},
+      {&t->d_copies, 16ull * 4 * t->cfg.max_streams * n_fns},
+      {&t->d_hk, 8ull * cap},
+      {&t->d_hs2, 4ull * cap},
+      {&t->d_hc, 4ull * cap},
+      {&t->d_hr, 4ull * cap},
+  };
+  for (auto &a : allocs) {
+    if (hipMalloc(a.p, a.bytes) != hipSuccess) {
+      hipGetLastError();
+      for (auto &b : allocs) if (*b.p) { hipFree(*b.p); *b.p = nullptr; }
+      return THAPI_E_NOMEM;
+    }
+  }
+  HIPCHK(hipMemcpy(t->d_roles, roles, n_fns, hipMemcpyHostToDevice));
+  t->hcap = cap;
+  PayTables &pt = t->pt;
+  pt.roles = (const uint8_t *)t->d_roles;
+  pt.copies = (uint64_t *)t->d_copies;
+  pt.hk = (uint64_t *)t->d_hk;
+  pt.hs = (uint32_t *)t->d_hs2;
+  pt.hc = (uint32_t *)t->d_hc;
+  pt.hr = (uint32_t *)t->d_hr;
+  pt.hmask = cap - 1;
+  pt.n_fns = n_fns;
+  pt.err = t->tb.err;
+  t->roles_on = true;
+  HIPCHK(clear_payload_tables(t));
+  HIPCHK(hipStreamSynchronize(t->st));
+  return THAPI_OK;
+}
+
+int thapi_tally_copies(thapi_tally *t, uint32_t trace_id, thapi_copy_row *rows, size_t capacity, size_t *n_rows) {
+  if (!t || !n_rows || (capacity && !rows)) return THAPI_E_INVAL;
+  std::lock_guard<std::mutex> run(t->run_mu);
+  if (!t->roles_on) return THAPI_E_STATE;
+  {
+    std::lock_guard<std::mutex> g(t->mu);
+    if (t->failed == THAPI_E_DEVICE) return THAPI_E_DEVICE;
+  }
+  if (hipSetDevice(t->dev) != hipSuccess) return THAPI_E_DEVICE;
+  const size_t ns = t->stream_keys.size(), nf = t->cfg.n_fns;
+  std::vector<uint64_t> h(std::max<size_t>(ns * nf * 8, 1));
+  if (ns) {
+    HIPCHK(hipMemcpyAsync(h.data(), t->d_copies, 8 * ns * nf * 8, hipMemcpyDeviceToHost, t->st));
+    HIPCHK(hipStreamSynchronize(t->st));
+  }
+  std::vector<thapi_copy_row> out;
+  for (uint32_t s : canonical_streams(t, trace_id))
+    for (uint32_t f = 0; f < nf; f++)
+      for (uint32_t d = 0; d < 4; d++) {
+        const uint64_t *c = &h[((size_t)s * nf + f) * 8 + 2 * d];
+        if (!c[0]) continue;
+        thapi_copy_row r{};
+        r.trace_id = t->stream_keys[s][0]; r.host_id = t->stream_keys[s][1]; r.pid = t->stream_keys[s][2];
+        r.fn = f; r.dir = d; r.count = c[0]; r.bytes = c[1];
+        out.push_back(r);
+      }
+  *n_rows = out.size();
+  if (!rows && !capacity) return THAPI_OK;
+  if (capacity < out.size()) return THAPI_E_BUFSZ;
+  if (!out.empty()) memcpy(rows, out.data(), out.size() * sizeof(thapi_copy_row));
+  return THAPI_OK;
+}
+
+int thapi_tally_handles(thapi_tally *t, uint32_t trace_id, thapi_handle_row *rows, size_t capacity,
+                        size_t *n_rows) {
+  if (!t || !n_rows || (capacity && !rows)) return THAPI_E_INVAL;
+  std::lock_guard<std::mutex> run(t->run_mu);
+  if (!t->roles_on) return THAPI_E_STATE;
+  {
+    std::lock_guard<std::mutex> g(t->mu);
+    if (t->failed == THAPI_E_DEVICE) return THAPI_E_DEVICE;
+  }
+  if (hipSetDevice(t->dev) != hipSuccess) return THAPI_E_DEVICE;
+  const size_t ns = t->stream_keys.size();
+  std::vector<uint64_t> h(std::max<size_t>(5 * ns, 1));
+  if (ns) {
+    HIPCHK(t->hstat.ensure(40 * ns));
+    HIPCHK(launch_fill64(t->hstat.as<uint64_t>(), 5 * ns, 0, t->st));
+    HIPCHK(launch_handle_stats(t->pt, t->hstat.as<unsigned long long>(), t->st));
+    HIPCHK(hipMemcpyAsync(h.data(), t->hstat.p, 40 * ns, hipMemcpyDeviceToHost, t->st));
+    HIPCHK(hipStreamSynchronize(t->st));
+  }
+  std::vector<thapi_handle_row> out;
+  for (uint32_t s : canonical_streams(t, trace_id)) {
+    const uint64_t *c = &h[5 * (size_t)s];
+    if (!c[0] && !c[1]) continue;
+    thapi_handle_row r{};
+    r.trace_id = t->stream_keys[s][0]; r.host_id = t->stream_keys[s][1]; r.pid = t->stream_keys[s][2];
+    r.creates = c[0]; r.releases = c[1]; r.handles = c[2]; r.unreleased = c[3]; r.unmatched = c[4];
+    out.push_back(r);
+  }
+  *n_rows = out.size();
+  if (!rows && !capacity) return THAPI_OK;
+  if (capacity < out.size()) return THAPI_E_BUFSZ;
+  if (!out.empty()) memcpy(rows, out.data(), out.size() * sizeof(thapi_handle_row));
   return THAPI_OK;
 }
 

@@ -17,7 +17,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libthapi_tally.so")
 
 ABI_VERSION = 1
-FMT_FIXED24, FMT_VAR16 = 1, 2
+FMT_FIXED24, FMT_VAR16, FMT_PACKED = 1, 2, 3
+ROLE_COPY, ROLE_CREATE, ROLE_RELEASE = 1, 2, 3
+DIR_H2H, DIR_H2D, DIR_D2H, DIR_D2D = 0, 1, 2, 3
 DEVICE_INPUT, NONBLOCKING, DROP_ON_FULL, STRICT, PROFILE, GRAPH, SERVICE, INTERVALS = \
     0x1, 0x2, 0x4, 0x8, 0x10, 0x20, 0x40, 0x80
 OUT_DEVICE = 0x1
@@ -36,6 +38,7 @@ ENTRY_POINTS = ["thapi_tally_open", "thapi_tally_submit", "thapi_tally_flush", "
                 "thapi_tally_reset", "thapi_tally_close", "thapi_tally_strerror", "thapi_tally_timings",
                 "thapi_tally_autotune", "thapi_tally_ticket_done", "thapi_tally_service_info",
                 "thapi_tally_export", "thapi_tally_merge", "thapi_tally_flush_noalloc", "thapi_tally_intervals",
+                "thapi_tally_set_roles", "thapi_tally_copies", "thapi_tally_handles",
                 "thapi_tally_read_bandwidth"]
 NOALLOC_SCRATCH_BYTES = 32 << 20
 
@@ -48,6 +51,14 @@ ROW_DTYPE = np.dtype([
 IVAL_DTYPE = np.dtype([
     ("trace", "<u4"), ("host", "<u4"), ("pid", "<u4"), ("tid", "<u4"), ("fn", "<u4"), ("depth", "<u4"),
     ("start", "<u8"), ("end", "<u8"), ("parent_start", "<u8"), ("parent_fn", "<u4"), ("pad", "<u4"),
+])
+COPY_DTYPE = np.dtype([
+    ("trace", "<u4"), ("host", "<u4"), ("pid", "<u4"), ("fn", "<u4"), ("dir", "<u4"), ("pad", "<u4"),
+    ("count", "<u8"), ("bytes", "<u8"),
+])
+HANDLE_DTYPE = np.dtype([
+    ("trace", "<u4"), ("host", "<u4"), ("pid", "<u4"), ("pad", "<u4"),
+    ("creates", "<u8"), ("releases", "<u8"), ("handles", "<u8"), ("unreleased", "<u8"), ("unmatched", "<u8"),
 ])
 STAT_NAMES = ["records", "entries", "exits", "kernel_records", "orphan_exits", "fn_mismatch",
               "neg_duration", "self_underflow", "ts_regress", "unclosed_final", "open_now",
@@ -94,6 +105,9 @@ def load():
     lib.thapi_tally_flush.argtypes = [P, ctypes.c_uint64, ctypes.c_uint32]
     lib.thapi_tally_flush_noalloc.argtypes = [P, ctypes.c_uint64, ctypes.c_uint32]
     lib.thapi_tally_intervals.argtypes = [P, P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t), ctypes.c_uint32]
+    lib.thapi_tally_set_roles.argtypes = [P, P, ctypes.c_uint32, ctypes.c_uint32]
+    for f in ("thapi_tally_copies", "thapi_tally_handles"):
+        getattr(lib, f).argtypes = [P, ctypes.c_uint32, P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
     lib.thapi_tally_export.argtypes = [P, P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
     lib.thapi_tally_merge.argtypes = [P, P, ctypes.c_size_t]
     lib.thapi_tally_read_bandwidth.argtypes = [ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint32,
@@ -260,6 +274,29 @@ class Tally:
         if n.value:
             _check(self._lib.thapi_tally_intervals(self._h, v.ctypes.data, n.value, ctypes.byref(n), 0), "intervals")
         return v
+
+    def set_roles(self, roles, max_handles=1 << 20):
+        """Per-fn payload roles (0, ROLE_COPY, ROLE_CREATE, ROLE_RELEASE) and the
+        room for distinct handles (thapi_tally_set_roles)."""
+        r = np.ascontiguousarray(roles, dtype=np.uint8)
+        _check(self._lib.thapi_tally_set_roles(self._h, r.ctypes.data, r.size, max_handles), "set_roles")
+
+    def _rows2(self, fname, dtype, trace):
+        f = getattr(self._lib, fname)
+        n = ctypes.c_size_t(0)
+        _check(f(self._h, trace, None, 0, ctypes.byref(n)), fname)
+        out = np.zeros(n.value, dtype=dtype)
+        if n.value:
+            _check(f(self._h, trace, out.ctypes.data, n.value, ctypes.byref(n)), fname)
+        return out
+
+    def copies(self, trace=ALL):
+        """Copy rows: (trace, host, pid, fn, dir) -> entries and summed sizes."""
+        return self._rows2("thapi_tally_copies", COPY_DTYPE, trace)
+
+    def handles(self, trace=ALL):
+        """Per-stream create / release join rows."""
+        return self._rows2("thapi_tally_handles", HANDLE_DTYPE, trace)
 
     def export(self):
         """The aggregate of everything flushed so far, as a uint8 array (see thapi_tally_export)."""

@@ -92,6 +92,11 @@ def _load():
         lib.synth_cfg_size.restype = ctypes.c_uint64
         assert lib.synth_call_size() == CALL_DTYPE.itemsize
         assert lib.synth_cfg_size() == ctypes.sizeof(SynthCfg)
+        lib.synth_apply_handles.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double]
+        lib.synth_pack.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_uint32,
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64),
+                                   ctypes.POINTER(ctypes.c_uint64)]
         _lib = lib
     return _lib
 
@@ -359,3 +364,41 @@ def random_submissions(seed: int, fmt: int = FMT_FIXED24, n_streams: int = 2, n_
             if p:
                 subs.append(p.pop(0))
     return subs
+
+
+# ------------------------------------------------- payload roles, packing
+ROLE_COPY, ROLE_CREATE, ROLE_RELEASE = 1, 2, 3
+
+
+def layered_roles(has_size: np.ndarray) -> np.ndarray:
+    """Roles for the layered VAR16 workload: every function with a size is a
+    copy (its payload is size, then two pointers); the first two runtime-layer
+    functions (ids 40..119) without a size create and release handles."""
+    roles = np.where(has_size != 0, ROLE_COPY, 0).astype(np.uint8)
+    free = [f for f in range(40, 120) if not has_size[f]]
+    roles[free[0]] = ROLE_CREATE
+    roles[free[1]] = ROLE_RELEASE
+    return roles
+
+
+def apply_handles(s: "Stream", roles: np.ndarray, seed: int, p_bogus: float = 0.02) -> None:
+    """Writes create / release handles into a VAR16 stream's payloads, in place
+    (see synth_apply_handles)."""
+    lib = _load()
+    n = s.records.size // 16
+    lib.synth_apply_handles(s.records.ctypes.data, n, s.payload.ctypes.data if s.payload.size else None,
+                            np.ascontiguousarray(roles, dtype=np.uint8).ctypes.data, len(roles), seed, p_bogus)
+
+
+def pack(s: "Stream", per_packet: int = 64):
+    """Packed form of a VAR16 stream: (packet bytes as uint8, u64 packet offsets)."""
+    lib = _load()
+    n = s.records.size // 16
+    nb, npk = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    pay = s.payload.ctypes.data if s.payload.size else None
+    lib.synth_pack(s.records.ctypes.data, n, pay, per_packet, None, None, ctypes.byref(nb), ctypes.byref(npk))
+    buf = np.zeros(nb.value, dtype=np.uint8)
+    index = np.zeros(npk.value, dtype=np.uint64)
+    lib.synth_pack(s.records.ctypes.data, n, pay, per_packet, buf.ctypes.data, index.ctypes.data, ctypes.byref(nb),
+                   ctypes.byref(npk))
+    return buf, index

@@ -419,3 +419,70 @@ void synth_stream_free(synth_stream *s) {
 }
 uint64_t synth_call_size(void) { return sizeof(synth_call); }
 uint64_t synth_cfg_size(void) { return sizeof(synth_cfg); }
+
+/* ------------------------------------------------- payload roles, packing */
+/* Handles in the payloads of a VAR16 stream (in place), for functions given
+ * a role: the exit of a create function (role 2) with payload_len >= 8
+ * returns a fresh handle (host-like values, 16 apart); the entry of a release
+ * function (role 3) with payload_len >= 8 takes, with probability p_bogus, a
+ * value never created, else one of the handles created so far in this stream
+ * (uniformly, so some are released twice and some never). */
+void synth_apply_handles(uint8_t *hdr, uint64_t n, uint8_t *pay, const uint8_t *roles, uint32_t n_fns,
+                         uint64_t seed, double p_bogus) {
+  rng_t r;
+  rng_seed(&r, seed, 0x48414E44u, n);
+  uint64_t *pool = NULL, np = 0, cap = 0, off = 0;
+  for (uint64_t i = 0; i < n; i++) {
+    uint8_t *h = hdr + i * 16;
+    const uint32_t len = h[15];
+    const uint16_t fn = (uint16_t)(h[12] | (h[13] << 8));
+    const uint8_t kind = h[14];
+    const uint8_t role = fn < n_fns ? roles[fn] : 0;
+    if (len >= 8 && role == 2 && kind == 1) {
+      const uint64_t v = 0x0000000005000000ull + 16 * np;
+      put_u64(pay + off, v);
+      if (np == cap) { cap = cap ? cap * 2 : 1024; pool = (uint64_t *)realloc(pool, cap * 8); }
+      pool[np++] = v;
+    } else if (len >= 8 && role == 3 && kind == 0) {
+      uint64_t v;
+      if (!np || rng_unif(&r) < p_bogus) v = 0x0000000007000000ull + 16 * rng_range(&r, 0, 1u << 20);
+      else v = pool[rng_range(&r, 0, np - 1)];
+      put_u64(pay + off, v);
+    }
+    off += len;
+  }
+  free(pool);
+}
+
+/* Packed form of a VAR16 stream: packets of up to `per_packet` events, each a
+ * 16-byte header {magic "THPK", packet bytes, events, 0} and its events, every
+ * event its 16-byte header and payload, padded with zeros to 8 bytes.  With
+ * buf / index NULL only the sizes are returned (*nbytes, *npackets). */
+void synth_pack(const uint8_t *hdr, uint64_t n, const uint8_t *pay, uint32_t per_packet, uint8_t *buf,
+                uint64_t *index, uint64_t *nbytes, uint64_t *npackets) {
+  uint64_t o = 0, pk = 0, poff = 0;
+  for (uint64_t i = 0; i < n; i += per_packet) {
+    const uint64_t e1 = i + per_packet < n ? i + per_packet : n;
+    const uint64_t start = o;
+    o += 16;
+    for (uint64_t j = i; j < e1; j++) {
+      const uint32_t len = hdr[j * 16 + 15];
+      const uint64_t sz = (16 + len + 7) / 8 * 8;
+      if (buf) {
+        memcpy(buf + o, hdr + j * 16, 16);
+        memcpy(buf + o + 16, pay + poff, len);
+        memset(buf + o + 16 + len, 0, sz - 16 - len);
+      }
+      poff += len;
+      o += sz;
+    }
+    if (buf) {
+      const uint32_t h[4] = {0x4B504854u, (uint32_t)(o - start), (uint32_t)(e1 - i), 0};
+      memcpy(buf + start, h, 16);
+      index[pk] = start;
+    }
+    pk++;
+  }
+  *nbytes = o;
+  *npackets = pk;
+}

@@ -25,6 +25,12 @@ Other forms (each prints its own single JSON line):
                     and the bytes read and written against HBM bandwidth;
                     the intervals are checked against the oracle's by count
                     and an order-independent fingerprint.
+  --form packed     the variable-length workload as packed (CTF-like)
+                    chunks, 64 events per packet, with copy / create /
+                    release roles: decode on the GPU by packet index, tally,
+                    per-direction copy bytes and the handle join; every
+                    output checked against the oracle's (full size), and the
+                    same events as plain VAR16 records timed beside it.
   --form streaming  the continuous-batching service fed by open-loop Poisson
                     arrivals of 64 KiB - 8 MiB chunks of 64 processes x 64
                     threads, host input, at a sweep of offered rates; p50/p99
@@ -161,7 +167,7 @@ def main():
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
                     help="plain form: leave out the batched-vs-per-trace comparison on the batched workload")
-    ap.add_argument("--form", default="plain", choices=["plain", "batched", "streaming", "intervals"])
+    ap.add_argument("--form", default="plain", choices=["plain", "batched", "streaming", "intervals", "packed"])
     ap.add_argument("--rates", default="2,5,10,20", help="streaming: offered GB/s per point")
     ap.add_argument("--seconds", type=float, default=10.0, help="streaming: measured seconds per point")
     ap.add_argument("--no-plain", action="store_true", help="streaming: leave out the plain-form comparison")
@@ -183,6 +189,8 @@ def main():
         return bench_streaming(args)
     if args.form == "intervals":
         return bench_intervals(args)
+    if args.form == "packed":
+        return bench_packed(args)
 
     import numpy as np
     import torch
@@ -548,6 +556,157 @@ def bench_intervals(args):
     line["cpu_baseline"] = None
     line["parity"] = parity
     tl.close()
+    print(json.dumps(line), flush=True)
+
+
+def bench_packed(args):
+    """Packed chunks with payload roles on the variable-length workload: one
+    step = reset, submit every stream's packed chunk (device input), final
+    flush (decode, payload analytics, tally), and read the thread rows, the
+    copy rows and the handle rows."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2504_03683_amd import tally as T
+
+    t0 = time.time()
+    w = synth.config(2, scale=args.scale)
+    roles = synth.layered_roles(w.has_size)
+    for i, s in enumerate(w.streams):
+        synth.apply_handles(s, roles, 1000 + i)
+    packs = [synth.pack(s, 64) for s in w.streams]
+    n_rec = w.n_records
+    pk_bytes = sum(b.size for b, _ in packs)
+    ix_bytes = sum(8 * ix.size for _, ix in packs)
+    kinds = np.concatenate([s.records.reshape(-1, 16)[:, 14] for s in w.streams])
+    fns = np.concatenate([s.records.reshape(-1, 16)[:, 12:14].copy().view("<u2").ravel() for s in w.streams])
+    n_handle_recs = int(((roles[fns] == T.ROLE_CREATE) & (kinds == 1)).sum() +
+                        ((roles[fns] == T.ROLE_RELEASE) & (kinds == 0)).sum())
+    del kinds, fns
+    max_handles = max(1024, n_handle_recs)
+    log("generated %s with roles, packed: %d records, %.2f GB packed (%d packets) in %.1fs" % (
+        w.name, n_rec, pk_bytes / 1e9, ix_bytes // 8, time.time() - t0))
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    bufs = [(torch.from_numpy(b).to(dev), torch.from_numpy(ix.view(np.uint8)).to(dev)) for b, ix in packs]
+    depth = max(w.max_depth, 8)
+
+    def open_handle(fmt):
+        h = T.Tally(fmt, w.n_fns, w.n_kernel_ids, max_depth=depth, max_threads=1024, max_streams=64,
+                    flags=T.DEVICE_INPUT | T.PROFILE, has_size=w.has_size, stream=stream)
+        h.set_roles(roles, max_handles)
+        return h
+
+    rowbuf = torch.zeros(1024 * w.n_fns * T.ROW_DTYPE.itemsize, dtype=torch.uint8,
+                         pin_memory=True).numpy().view(T.ROW_DTYPE)
+
+    def timed(tl, inputs):
+        def step():
+            tl.reset()
+            for s, (r, p) in zip(w.streams, inputs):
+                tl.submit(s.key, r, p)
+            tl.flush(final=True)
+            rows, st = tl.read(T.SCOPE_THREAD, out=rowbuf)
+            return rows, st, tl.copies(), tl.handles()
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        tms = {}
+        e0.record(stream)
+        res = None
+        for _ in range(args.steps):
+            res = step()
+            for k, v in tl.timings().items():
+                tms.setdefault(k, []).append(v)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.steps, {k: sum(v) / len(v) for k, v in tms.items()}, res
+
+    tl = open_handle(T.FMT_PACKED)
+    ms, avg, (rows, stats, cop, hdl) = timed(tl, bufs)
+    rows = rows.copy()
+    log("packed: %.3f ms/step; kernel ms (avg): %s" % (ms, ", ".join("%s %.4f" % kv for kv in avg.items())))
+    tl.close()
+    del bufs
+    recs = [(torch.from_numpy(s.records).to(dev), torch.from_numpy(s.payload).to(dev)) for s in w.streams]
+    tv = open_handle(T.FMT_VAR16)
+    ms_v, avg_v, (rows_v, stats_v, cop_v, hdl_v) = timed(tv, recs)
+    log("VAR16, same events: %.3f ms/step; kernel ms (avg): %s" % (
+        ms_v, ", ".join("%s %.4f" % kv for kv in avg_v.items())))
+    same = (np.array_equal(rows, rows_v) and np.array_equal(cop.view(np.uint8), cop_v.view(np.uint8)) and
+            np.array_equal(hdl.view(np.uint8), hdl_v.view(np.uint8)))
+    tv.close()
+    del recs
+
+    # algorithmic bytes per kernel (see the design notes): the decode reads the
+    # packed bytes and the index once and writes 16 B per event plus the kept
+    # payload words; the payload analytics read every header and the payload
+    # words of records with a role; the range kernel reads the decoded input
+    kept = 0
+    pay_read = 0
+    for s in w.streams:
+        h = s.records.reshape(-1, 16)
+        ln = h[:, 15].astype(np.int64)
+        kept += int(np.where(ln >= 24, 24, np.where(ln >= 8, 8, 0)).sum())
+        fn = h[:, 12:14].copy().view("<u2").ravel()
+        r = roles[fn]
+        k = h[:, 14]
+        pay_read += int(24 * ((r == T.ROLE_COPY) & (k == 0) & (ln >= 24)).sum() +
+                        8 * ((((r == T.ROLE_CREATE) & (k == 1)) | ((r == T.ROLE_RELEASE) & (k == 0))) &
+                             (ln >= 8)).sum())
+    dec_bytes = pk_bytes + ix_bytes + 16 * n_rec + kept
+    payk_bytes = 16 * n_rec + pay_read
+    rng_bytes = 16 * n_rec + kept + 64 * len(rows)
+    kern = {"decode (tt::k_pk_count + k_pk_scan + k_pk_write)": (avg["decode"], dec_bytes),
+            "tt::k_payload": (avg["payload"], payk_bytes),
+            "tt::k_range": (avg["range"], rng_bytes)}
+    name, (kms, kbytes) = max(kern.items(), key=lambda kv: kv[1][0])
+    gbs = {k: b / (t * 1e-3) / 1e9 if t else None for k, (t, b) in kern.items()}
+    pipe_ms = avg["decode"] + avg["prepass"] + avg["payload"] + avg["range"] + avg["combine"] + avg["final"]
+
+    parity = "not checked"
+    cpu = None
+    if not args.no_parity:
+        import oracle
+        tc = time.perf_counter()
+        o = oracle.Oracle(2, w.n_fns, w.n_kernel_ids, depth, w.has_size)
+        o.set_roles(roles)
+        for s, (b, ix) in zip(w.streams, packs):
+            assert o.submit_packed(s.key, b, ix) == 0
+        o.finish()
+        cpu_s = time.perf_counter() - tc
+        ok = rows.shape == o.rows(oracle.SCOPE_THREAD).shape and np.array_equal(rows, o.rows(oracle.SCOPE_THREAD))
+        ws = o.stats()
+        ok = ok and all(stats[k] == ws[k] for k in T.STAT_NAMES if k != "dropped_records")
+        wc, wh = o.copies(), o.handles()
+        ok = ok and np.array_equal(cop.view(np.uint8), wc.view(np.uint8))
+        ok = ok and np.array_equal(hdl.view(np.uint8), wh.view(np.uint8))
+        o.close()
+        parity = ("bit-exact (thread rows, counters, %d copy rows, %d handle rows)" % (len(wc), len(wh))
+                  if ok else "MISMATCH")
+        log("oracle (packed decode, one thread): %.2fs; parity: %s" % (cpu_s, parity))
+        if not args.no_cpu_baseline:
+            model, cores, ncpu = host_cpu()
+            cpu = {"value": n_rec / cpu_s, "unit": "events/s", "cores": 1, "kind": "oracle",
+                   "sample": "the whole workload (%d records), one pass: packed decode, roles, tally" % n_rec,
+                   "cpu_model": model}
+    line = base_line(args.steps, args.warmup, ms, n_rec / (ms * 1e-3), {
+        "workload": WORKLOADS[2] + ("" if args.scale == 1.0 else " (scale %g)" % args.scale) +
+        "; packed (CTF-like) chunks, 64 events per packet, one chunk per stream; copy roles on the 48 sized fns, "
+        "one create and one release fn", "records": n_rec, "packed_bytes": pk_bytes, "packets": ix_bytes // 8,
+        "format": "PACKED", "streams": len(w.streams), "copy_rows": int(len(cop)), "handle_rows": int(len(hdl)),
+        "max_handles": max_handles})
+    line["roofline"] = {"bound": "hbm", "achieved": gbs[name], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": gbs[name] / HBM_PEAK_GBS, "traffic": None, "kernel": name, "kernel_ms": kms,
+                        "alg_bytes": kbytes,
+                        "kernels": {k: {"ms": t, "alg_bytes": b, "GBps": gbs[k]} for k, (t, b) in kern.items()},
+                        "pipeline_ms": pipe_ms}
+    line["cpu_baseline"] = cpu
+    line["parity"] = parity
+    line["var16_same_events"] = {"ms_per_step": ms_v, "value": n_rec / (ms_v * 1e-3), "unit": "events/s",
+                                 "kernel_ms": avg_v, "same_outputs_as_packed": bool(same)}
     print(json.dumps(line), flush=True)
 
 

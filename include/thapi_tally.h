@@ -438,8 +438,9 @@ const char *thapi_tally_strerror(int code);
 
 /* THAPI_PROFILE only: per-kernel durations (ms) of the last flush and read,
  * measured with HIP events on the launch stream, in the order
- * {prepass, main, combine, final, readout, intervals}; entries that did not
- * run are 0.  A flush that needed extra passes (THAPI_MAX_RANGE_THREADS)
+ * {prepass, main, combine, final, readout, intervals, decode, payload}
+ * (decode: the packed chunks' decode into records; payload: the copy and
+ * handle analytics of functions with roles); entries that did not run are 0.  A flush that needed extra passes (THAPI_MAX_RANGE_THREADS)
  * reports its first pass only.
  * Under THAPI_GRAPH, "main" is the whole replayed graph.
  * n: capacity of ms[]; returns the number of entries written. */

@@ -161,17 +161,44 @@ struct Tables {
   uint32_t civ_cap;
 };
 
-// Payload analytics tables (tt_payload.hip).  hs: 0 free, stream + 1 once
-// the slot's handle is written, with the top bit set while it is written.
+// Payload analytics tables (tt_payload.hip).  hs: 0 free, else stream + 1;
+// hk: the slot's handle, EMPTY64 until written.
 struct PayTables {
   const uint8_t *roles;        // [n_fns] 0, copy 1, create 2, release 3
   uint64_t *copies;            // [max_streams][n_fns][4] {count, bytes}
   uint64_t *hk;                // [cap] handle values
   uint32_t *hs;                // [cap] stream + 1
   uint32_t *hc, *hr;           // [cap] creates, releases
+  uint32_t *hx;                // [max_streams][2] creates, releases of the handle EMPTY64
+  uint64_t *hl_key;            // [hl_cap] handle records of the flush waiting to be joined
+  uint32_t *hl_meta;           // [hl_cap] stream << 1 | (release)
+  uint32_t *hl_n;              // their count (may exceed hl_cap: the rest were joined at once)
+  uint32_t hl_cap;
   uint32_t hmask;              // cap - 1
   uint32_t n_fns;
+  uint32_t n_streams;          // max_streams
   uint32_t *err;
+};
+
+// VAR16 payload offsets are found per slice of PAY_SLICE records of a range
+// (slice_first[r] = the first slice of range r, a prefix over ranges).
+constexpr uint32_t PAY_SLICE = 8192;
+__device__ __forceinline__ uint32_t range_of_slice(const uint32_t *slice_first, uint32_t n_ranges, uint32_t b) {
+  uint32_t lo = 0, hi = n_ranges - 1;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) / 2;
+    if (slice_first[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// One packed chunk of a flush (tt_payload.hip decodes them together).
+struct PkChunk {
+  const uint8_t *buf;        // packet bytes
+  uint64_t nbytes;
+  const uint64_t *index;     // packet offsets
+  uint64_t pad;
 };
 
 // Launch shape of the range kernel (tile of T records, LDS tally of E entries).

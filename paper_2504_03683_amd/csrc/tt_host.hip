@@ -37,7 +37,8 @@ hipError_t launch_range(int fmt, uint32_t T, const Seg *segs, const Range *range
 hipError_t prepare_range_kernels(uint32_t max_lds_bytes);
 hipError_t prepare_combine_kernel();
 hipError_t launch_paylen(const Seg *segs, Range *ranges, uint32_t n_ranges, const uint32_t *seg_first_range,
-                         uint32_t n_segs, uint64_t *paylen, uint32_t *err, hipStream_t st);
+                         uint32_t n_segs, const uint32_t *slice_first, uint32_t n_slices, uint64_t *paylen,
+                         uint32_t *err, hipStream_t st);
 hipError_t launch_fill64(uint64_t *p, size_t n, uint64_t v, hipStream_t st);
 hipError_t launch_fill32(uint32_t *p, size_t n, uint32_t v, hipStream_t st);
 hipError_t launch_init_all(const InitSet &is, hipStream_t st);
@@ -48,15 +49,14 @@ hipError_t launch_final(const Tables &tb, uint32_t max_threads, hipStream_t st);
 hipError_t launch_iv_out(const Tables &tb, const uint64_t *ivbase, const RHdr *rhdr, uint32_t n_ranges,
                          const uint32_t *rnslots, const uint64_t *off, const uint32_t *skeys, void *out,
                          hipStream_t st);
-hipError_t launch_pk_count(const uint8_t *buf, uint64_t nbytes, const uint64_t *index, uint32_t n_packets,
-                           uint32_t *ev, uint64_t *pay, uint32_t *err, hipStream_t st);
-hipError_t launch_pk_scan(uint32_t *ev, uint64_t *pay, uint32_t n, uint64_t *ev_off, uint64_t *tot, hipStream_t st);
-hipError_t launch_pk_write(const uint8_t *buf, uint64_t nbytes, const uint64_t *index, uint32_t n_packets,
-                           const uint64_t *ev_off, const uint64_t *pay_off, uint64_t *hdr, uint64_t *heap,
-                           uint32_t *err, hipStream_t st);
-hipError_t launch_payload(const Seg *segs, const Range *ranges, uint32_t n_ranges, const PayTables &pt,
-                          hipStream_t st);
-hipError_t launch_handle_stats(const PayTables &pt, unsigned long long *out, hipStream_t st);
+size_t pk_scratch_bytes(uint64_t np);
+hipError_t launch_pk_count(const PkChunk *chunks, const uint64_t *first, uint32_t nc, uint64_t np, uint8_t *scr,
+                           uint64_t *tot_out, uint32_t *err, hipStream_t st);
+hipError_t launch_pk_write(const PkChunk *chunks, const uint64_t *first, uint32_t nc, uint64_t np, uint8_t *scr,
+                           uint64_t *hdr, uint64_t *heap, uint32_t *err, hipStream_t st);
+hipError_t launch_payload(const Seg *segs, const Range *ranges, uint32_t n_ranges, const uint32_t *slice_first,
+                          uint32_t n_slices, const uint64_t *sliceoff, const PayTables &pt, hipStream_t st);
+hipError_t launch_handle_stats(const PayTables &pt, unsigned long long *out, uint32_t ns, hipStream_t st);
 hipError_t launch_thread_stats(const Tables &tb, uint32_t max_threads, unsigned long long *out, uint32_t ns,
                                uint32_t ns1, hipStream_t st);
 hipError_t launch_sort_threads(const Tables &tb, const uint32_t *stream_rank, uint64_t *keys, uint32_t *vals,
@@ -208,6 +208,7 @@ struct Plan {
   std::vector<Seg> segs;
   std::vector<Range> ranges;
   std::vector<uint32_t> segfirst, spans, order;
+  std::vector<uint32_t> slicefirst;   // VAR16: first payload slice of each range (and the total)
   uint64_t total = 0;
 };
 
@@ -217,16 +218,16 @@ struct Plan {
 struct FlushBufs {
   Seg *segs = nullptr;
   Range *ranges = nullptr;
-  uint32_t *order = nullptr, *segfirst = nullptr, *spans = nullptr, *qhead = nullptr;
+  uint32_t *order = nullptr, *segfirst = nullptr, *spans = nullptr, *qhead = nullptr, *slicefirst = nullptr;
   RHdr *rhdr = nullptr;
   UItem *ru = nullptr;
   OItem *ro = nullptr;
   uint32_t *rnslots = nullptr;
   uint32_t *rmore = nullptr;   // per summary row: threads left to extra passes
-  uint64_t *paylen = nullptr;
+  uint64_t *paylen = nullptr;   // VAR16: per payload slice, its bytes and then its offset
 };
 
-enum { TM_PREPASS = 0, TM_RANGE, TM_COMBINE, TM_FINAL, TM_READOUT, TM_IVOUT, TM_N };
+enum { TM_PREPASS = 0, TM_RANGE, TM_COMBINE, TM_FINAL, TM_READOUT, TM_IVOUT, TM_DECODE, TM_PAYLOAD, TM_N };
 
 }  // namespace
 
@@ -267,7 +268,8 @@ struct thapi_tally {
   bool roles_on = false;
   PayTables pt{};
   uint32_t hcap = 0;
-  void *d_roles = nullptr, *d_copies = nullptr, *d_hk = nullptr, *d_hs2 = nullptr, *d_hc = nullptr, *d_hr = nullptr;
+  void *d_roles = nullptr, *d_copies = nullptr, *d_hk = nullptr, *d_hs2 = nullptr, *d_hc = nullptr, *d_hr = nullptr,
+       *d_hx = nullptr, *d_hlk = nullptr, *d_hlm = nullptr, *d_hln = nullptr;
   DevBuf hstat;
   // THAPI_INTERVALS: the current flush's interval buffers (see Tables), the
   // public records of the last intervals() call and its offsets / keys
@@ -286,13 +288,15 @@ struct thapi_tally {
   size_t h_plan_cap = 0;
 
   double timings[TM_N] = {0};
+  double dec_ms1 = 0;                                 // packed decode: count and scan (the writes follow)
+  bool dec_pending = false;
   hipEvent_t ev[2 * TM_N] = {};
 
   std::string arch;                                   // gcnArchName of the device
   std::map<std::string, std::array<uint32_t, 4>> tuned;  // autotuned {T, E, rpc, pipe} per workload class
   bool flushed_any = false;
   hipGraphExec_t gexec = nullptr;                     // THAPI_GRAPH: the captured pipeline
-  std::array<uint64_t, 22> gsig{};
+  std::array<uint64_t, 24> gsig{};
   uint64_t graph_builds = 0, graph_launches = 0;
   std::string cache_path;
 
@@ -369,7 +373,8 @@ hipError_t init_tables(thapi_tally *t, bool wait = true) {
 void free_all(thapi_tally *t) {
   void *ps[] = {t->d_gkeys, t->d_gvals, t->d_ngs, t->d_ths, t->d_tht, t->d_tally, t->d_ktally,
                 t->d_cstate, t->d_cstack, t->d_sstats, t->d_err, t->d_hs, t->d_thord, t->d_snth,
-                t->d_roles, t->d_copies, t->d_hk, t->d_hs2, t->d_hc, t->d_hr};
+                t->d_roles, t->d_copies, t->d_hk, t->d_hs2, t->d_hc, t->d_hr, t->d_hx,
+                t->d_hlk, t->d_hlm, t->d_hln};
   for (void *p : ps) if (p) hipFree(p);
   DevBuf *bs[] = {&t->plan_pack, &t->rhdr, &t->ru, &t->ro, &t->rnslots, &t->rmore, &t->wide_pack, &t->paylen, &t->keys, &t->vals, &t->keys2,
                   &t->vals2, &t->gbeg, &t->gend, &t->cnt, &t->off, &t->read_pack, &t->rows, &t->tstats,
@@ -897,6 +902,11 @@ void plan_work(const thapi_tally *t, const std::vector<Chunk> &work, const Shape
     uint64_t acc = 0;   // intervals: each range may write one per record, from here
     for (auto &r : pl.ranges) { r.iv_base = acc; acc += r.n; }
   }
+  {
+    uint32_t acc = 0;   // payload slices of each range
+    for (auto &r : pl.ranges) { pl.slicefirst.push_back(acc); acc += (uint32_t)((r.n + PAY_SLICE - 1) / PAY_SLICE); }
+    pl.slicefirst.push_back(acc);
+  }
   // longest first: the persistent workgroups take them in this order, so the
   // short ranges fill in at the end (LPT scheduling)
   pl.order.resize(pl.ranges.size());
@@ -948,7 +958,7 @@ hipError_t stage_h2d(thapi_tally *t, uint8_t *dev, void **const *views, const vo
 // Sizes of one flush's device buffers: the packed work list and the range
 // summaries (RHdr per range and slot, U and O items per range, slot and level).
 struct PlanSizes {
-  size_t part[6];
+  size_t part[7];
   size_t pack, rhdr, ru, ro, rnslots, rmore, paylen;
   size_t total() const {
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
@@ -960,15 +970,16 @@ PlanSizes plan_sizes(const thapi_tally *t, const Plan &pl) {
   const size_t nR = pl.ranges.size(), nS = pl.segs.size();
   const size_t D = t->cfg.max_depth;
   PlanSizes z{};
-  const size_t part[6] = {sizeof(Seg) * nS, sizeof(Range) * nR, 4 * nR, 4 * (nS + 1), 4 * pl.spans.size(), 4};
-  for (int i = 0; i < 6; i++) z.part[i] = part[i];
-  z.pack = pack_bytes(part, 6);
+  const size_t part[7] = {sizeof(Seg) * nS, sizeof(Range) * nR, 4 * nR, 4 * (nS + 1), 4 * pl.spans.size(), 4,
+                          4 * pl.slicefirst.size()};
+  for (int i = 0; i < 7; i++) z.part[i] = part[i];
+  z.pack = pack_bytes(part, 7);
   z.rhdr = sizeof(RHdr) * nR * S_MAX;
   z.ru = sizeof(UItem) * nR * S_MAX * D;
   z.ro = sizeof(OItem) * nR * S_MAX * D;
   z.rnslots = 4 * std::max<size_t>(nR, 1);
   z.rmore = 4 * std::max<size_t>(nR, 1);
-  z.paylen = 8 * std::max<size_t>(nR, 1);
+  z.paylen = 8 * std::max<size_t>(pl.slicefirst.empty() ? 1 : pl.slicefirst.back(), 1);
   return z;
 }
 
@@ -1011,10 +1022,11 @@ hipError_t upload_plan(thapi_tally *t, const Plan &pl, uint8_t *scratch = nullpt
   }
   // the work queue's head (zero) travels with the work list
   static const uint32_t zero = 0;
-  const void *src[6] = {pl.segs.data(), pl.ranges.data(), pl.order.data(), pl.segfirst.data(), pl.spans.data(), &zero};
-  void **dst[6] = {(void **)&fb.segs, (void **)&fb.ranges, (void **)&fb.order, (void **)&fb.segfirst,
-                   (void **)&fb.spans, (void **)&fb.qhead};
-  UPCHK(stage_h2d(t, pack, dst, src, z.part, 6));
+  const void *src[7] = {pl.segs.data(), pl.ranges.data(), pl.order.data(), pl.segfirst.data(), pl.spans.data(), &zero,
+                        pl.slicefirst.data()};
+  void **dst[7] = {(void **)&fb.segs, (void **)&fb.ranges, (void **)&fb.order, (void **)&fb.segfirst,
+                   (void **)&fb.spans, (void **)&fb.qhead, (void **)&fb.slicefirst};
+  UPCHK(stage_h2d(t, pack, dst, src, z.part, 7));
 #undef UPCHK
   return hipSuccess;
 }
@@ -1064,9 +1076,14 @@ hipError_t launch_pipeline(thapi_tally *t, const Plan &pl, const Shape &sh, bool
   if (nR) {
     if (kfmt(t) == 2) {
       TB(TM_PREPASS);
-      LPCHK(launch_paylen(fb.segs, fb.ranges, nR, fb.segfirst, nS, fb.paylen, t->tb.err, t->st));
-      if (t->roles_on) LPCHK(launch_payload(fb.segs, fb.ranges, nR, t->pt, t->st));
+      const uint32_t nSl = pl.slicefirst.back();
+      LPCHK(launch_paylen(fb.segs, fb.ranges, nR, fb.segfirst, nS, fb.slicefirst, nSl, fb.paylen, t->tb.err, t->st));
       TE(TM_PREPASS);
+      if (t->roles_on) {
+        TB(TM_PAYLOAD);
+        LPCHK(launch_payload(fb.segs, fb.ranges, nR, fb.slicefirst, nSl, fb.paylen, t->pt, t->st));
+        TE(TM_PAYLOAD);
+      }
     }
     TB(TM_RANGE);
     LPCHK(launch_range(kfmt(t), sh.T, fb.segs, fb.ranges, fb.order, nR, fb.qhead, (uint32_t)t->n_cu, t->tb,
@@ -1092,7 +1109,9 @@ hipError_t launch_pipeline(thapi_tally *t, const Plan &pl, const Shape &sh, bool
 hipError_t run_pipeline(thapi_tally *t, const Plan &pl, const Shape &sh, bool final) {
   const bool prof = (t->cfg.flags & THAPI_PROFILE) != 0;
   if (!(t->cfg.flags & THAPI_GRAPH)) return launch_pipeline(t, pl, sh, final, prof);
-  const std::array<uint64_t, 22> sig = {pl.ranges.size(), pl.segs.size(), pl.spans.size(), sh.T, sh.E,
+  const std::array<uint64_t, 24> sig = {pl.slicefirst.empty() ? 0 : pl.slicefirst.back(),
+                                        (uint64_t)(uintptr_t)t->fb.slicefirst,
+                                        pl.ranges.size(), pl.segs.size(), pl.spans.size(), sh.T, sh.E,
                                         sh.rpc | ((uint64_t)sh.pipe << 32), final ? 1u : 0u,
                                         (uint64_t)(uintptr_t)t->tb.iv, (uint64_t)(uintptr_t)t->tb.civ,
                                         (uint64_t)(uintptr_t)t->tb.iv_n, (uint64_t)(uintptr_t)t->tb.iv_h0,
@@ -1289,48 +1308,57 @@ hipError_t run_extra_passes(thapi_tally *t, const Plan &pl, const Shape &sh, boo
 }
 
 // Packed chunks of a batch (taken off the queue by the caller) become VAR16
-// chunks in the handle's decode buffers: per chunk, every packet's events
-// and kept payload bytes are counted (one lane per packet, the packet index
-// giving each lane its start), the counts are scanned and the totals
-// fetched, then the events are written out.  The staged copies stay owned by
-// the chunks.  A malformed chunk fails the handle with THAPI_E_INVAL (the
-// batch is released untallied).  Caller holds run_mu.
+// chunks in the handle's decode buffers.  All packets of the batch are
+// decoded together: one count pass (one lane per packet, the packet index
+// giving each lane its start), a scan of the counts, the per-chunk totals
+// fetched, then one write pass.  The staged copies stay owned by the
+// chunks.  A malformed chunk fails the handle with THAPI_E_INVAL (the batch
+// is released untallied).  Caller holds run_mu.
 int transcode_packed(thapi_tally *t, std::vector<Chunk> &work) {
   if (t->cfg.format != THAPI_FMT_PACKED) return THAPI_OK;
   std::vector<size_t> which;
+  std::vector<PkChunk> desc;
+  std::vector<uint64_t> first;
   uint64_t npk = 0;
   for (size_t i = 0; i < work.size(); i++)
-    if (work[i].pk_packets) { which.push_back(i); npk += work[i].pk_packets; }
+    if (work[i].pk_packets) {
+      which.push_back(i);
+      desc.push_back(PkChunk{work[i].rec, work[i].pk_bytes, (const uint64_t *)work[i].pay, 0});
+      first.push_back(npk);
+      npk += work[i].pk_packets;
+    }
   if (which.empty()) return THAPI_OK;
+  first.push_back(npk);
   if (hipSetDevice(t->dev) != hipSuccess) return THAPI_E_DEVICE;
-  const size_t nc = which.size();
-  // scratch: per packet events (u32), kept bytes then their offsets (u64),
-  // event offsets (u64); per chunk the two totals
-  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-  const size_t b_ev = al(4 * npk), b_pay = al(8 * npk), b_off = al(8 * npk), b_tot = al(16 * nc);
-  HIPCHK(t->pk_scr.ensure(b_ev + b_pay + b_off + b_tot));
+  const uint32_t nc = (uint32_t)which.size();
+  // descriptors, packet prefix and the gathered totals after the scan scratch
+  const size_t b_scr = (pk_scratch_bytes(npk) + 255) & ~(size_t)255;
+  const size_t bytes[2] = {sizeof(PkChunk) * nc, 8ull * (nc + 1)};
+  const size_t b_tot = 16ull * (nc + 1);
+  HIPCHK(t->pk_scr.ensure(b_scr + pack_bytes(bytes, 2) + b_tot));
   uint8_t *sc = t->pk_scr.as<uint8_t>();
-  uint32_t *ev = (uint32_t *)sc;
-  uint64_t *pay = (uint64_t *)(sc + b_ev), *evoff = (uint64_t *)(sc + b_ev + b_pay);
-  uint64_t *tot = (uint64_t *)(sc + b_ev + b_pay + b_off);
+  HIPCHK(grow_plan_staging(t, pack_bytes(bytes, 2)));
+  void *d_desc = nullptr, *d_first = nullptr;
+  void **views[2] = {&d_desc, &d_first};
+  const void *src[2] = {desc.data(), first.data()};
+  HIPCHK(stage_h2d(t, sc + b_scr, views, src, bytes, 2));
+  uint64_t *d_tot = (uint64_t *)(sc + b_scr + pack_bytes(bytes, 2));
   HIPCHK(launch_fill32(t->tb.err, 1, 0, t->st));
   // streaming form: the decode waits on the device for the chunks' copies
   for (size_t j : which)
     if (work[j].ev >= 0) HIPCHK(hipStreamWaitEvent(t->st, t->ev_pool[work[j].ev], 0));
-  uint64_t o = 0;
-  for (size_t j = 0; j < nc; j++) {
-    const Chunk &c = work[which[j]];
-    HIPCHK(launch_pk_count(c.rec, c.pk_bytes, (const uint64_t *)c.pay, (uint32_t)c.pk_packets, ev + o, pay + o,
-                           t->tb.err, t->st));
-    HIPCHK(launch_pk_scan(ev + o, pay + o, (uint32_t)c.pk_packets, evoff + o, tot + 2 * j, t->st));
-    o += c.pk_packets;
-  }
-  HIPCHK(ensure_pinned(t, 16 * nc + 16));
+  HIPCHK(timed_begin(t, TM_DECODE));
+  HIPCHK(launch_pk_count((const PkChunk *)d_desc, (const uint64_t *)d_first, nc, npk, sc, d_tot, t->tb.err,
+                         t->st));
+  HIPCHK(timed_end(t, TM_DECODE));
+  HIPCHK(ensure_pinned(t, b_tot + 16));
   uint64_t *h = (uint64_t *)t->h_pinned;
-  HIPCHK(hipMemcpyAsync(h, tot, 16 * nc, hipMemcpyDeviceToHost, t->st));
-  HIPCHK(hipMemcpyAsync(h + 2 * nc, t->tb.err, 4, hipMemcpyDeviceToHost, t->st));
+  HIPCHK(hipMemcpyAsync(h, d_tot, b_tot, hipMemcpyDeviceToHost, t->st));
+  HIPCHK(hipMemcpyAsync(h + 2 * (nc + 1), t->tb.err, 4, hipMemcpyDeviceToHost, t->st));
   HIPCHK(hipStreamSynchronize(t->st));
-  if ((uint32_t)h[2 * nc] & ERR_PAYLOAD) {
+  collect_timing(t, TM_DECODE);
+  t->dec_ms1 = t->timings[TM_DECODE];
+  if ((uint32_t)h[2 * (nc + 1)] & ERR_PAYLOAD) {
     std::lock_guard<std::mutex> g(t->mu);
     for (auto &c : work) release_chunk(t, c);
     work.clear();
@@ -1338,24 +1366,23 @@ int transcode_packed(thapi_tally *t, std::vector<Chunk> &work) {
     t->cv.notify_all();
     return THAPI_E_INVAL;
   }
-  uint64_t ne = 0, nb = 0;
-  std::vector<uint64_t> ebase(nc), bbase(nc);
-  for (size_t j = 0; j < nc; j++) { ebase[j] = ne; bbase[j] = nb; ne += h[2 * j]; nb += h[2 * j + 1]; }
+  const uint64_t ne = h[2 * nc], nb = h[2 * nc + 1];
   HIPCHK(t->pk_hdr.ensure(16 * std::max<uint64_t>(ne, 1)));
   HIPCHK(t->pk_heap.ensure(std::max<uint64_t>(nb, 8)));
   uint64_t *hdr = t->pk_hdr.as<uint64_t>(), *heap = t->pk_heap.as<uint64_t>();
-  o = 0;
-  for (size_t j = 0; j < nc; j++) {
+  HIPCHK(timed_begin(t, TM_DECODE));
+  HIPCHK(launch_pk_write((const PkChunk *)d_desc, (const uint64_t *)d_first, nc, npk, sc, hdr, heap, t->tb.err,
+                         t->st));
+  HIPCHK(timed_end(t, TM_DECODE));
+  for (uint32_t j = 0; j < nc; j++) {
     Chunk &c = work[which[j]];
-    HIPCHK(launch_pk_write(c.rec, c.pk_bytes, (const uint64_t *)c.pay, (uint32_t)c.pk_packets, evoff + o, pay + o,
-                           hdr + 2 * ebase[j], heap + bbase[j] / 8, t->tb.err, t->st));
-    o += c.pk_packets;
-    c.rec = (const uint8_t *)(hdr + 2 * ebase[j]);
-    c.n_rec = h[2 * j];
-    c.pay = (const uint8_t *)(heap + bbase[j] / 8);
-    c.pay_bytes = h[2 * j + 1];
+    c.rec = (const uint8_t *)(hdr + 2 * h[2 * j]);
+    c.n_rec = h[2 * j + 2] - h[2 * j];
+    c.pay = (const uint8_t *)heap + h[2 * j + 1];
+    c.pay_bytes = h[2 * j + 3] - h[2 * j + 1];
     c.pk_packets = 0;
   }
+  t->dec_pending = (t->cfg.flags & THAPI_PROFILE) != 0;
   return THAPI_OK;
 }
 
@@ -1397,10 +1424,17 @@ int process_batch(thapi_tally *t, std::vector<Chunk> &work, bool final, const Pl
   } else {
     if (nR) {
       if (kfmt(t) == 2) collect_timing(t, TM_PREPASS);
+      if (kfmt(t) == 2 && t->roles_on) collect_timing(t, TM_PAYLOAD);
       collect_timing(t, TM_RANGE);
       collect_timing(t, TM_COMBINE);
     }
     if (final) collect_timing(t, TM_FINAL);
+  }
+  if (t->dec_pending) {
+    // the packed decode of this batch: its count and scan, then its writes
+    collect_timing(t, TM_DECODE);
+    t->timings[TM_DECODE] += t->dec_ms1;
+    t->dec_pending = false;
   }
   {
     std::lock_guard<std::mutex> g(t->mu);
@@ -1967,6 +2001,8 @@ hipError_t clear_payload_tables(thapi_tally *t) {
   hipError_t e;
   const size_t nc = (size_t)t->cfg.max_streams * t->cfg.n_fns * 8;
   if ((e = launch_fill64((uint64_t *)t->d_copies, nc, 0, t->st)) != hipSuccess) return e;
+  if ((e = launch_fill64((uint64_t *)t->d_hk, t->hcap, EMPTY64, t->st)) != hipSuccess) return e;
+  if ((e = launch_fill32((uint32_t *)t->d_hx, 2ull * t->cfg.max_streams, 0, t->st)) != hipSuccess) return e;
   if ((e = launch_fill32((uint32_t *)t->d_hs2, t->hcap, 0, t->st)) != hipSuccess) return e;
   if ((e = launch_fill32((uint32_t *)t->d_hc, t->hcap, 0, t->st)) != hipSuccess) return e;
   return launch_fill32((uint32_t *)t->d_hr, t->hcap, 0, t->st);
@@ -2006,6 +2042,10 @@ int thapi_tally_set_roles(thapi_tally *t, const uint8_t *roles, uint32_t n_fns, 
       {&t->d_hs2, 4ull * cap},
       {&t->d_hc, 4ull * cap},
       {&t->d_hr, 4ull * cap},
+      {&t->d_hx, 8ull * t->cfg.max_streams},
+      {&t->d_hlk, 8ull * cap},
+      {&t->d_hlm, 4ull * cap},
+      {&t->d_hln, 4},
   };
   for (auto &a : allocs) {
     if (hipMalloc(a.p, a.bytes) != hipSuccess) {
@@ -2023,6 +2063,12 @@ int thapi_tally_set_roles(thapi_tally *t, const uint8_t *roles, uint32_t n_fns, 
   pt.hs = (uint32_t *)t->d_hs2;
   pt.hc = (uint32_t *)t->d_hc;
   pt.hr = (uint32_t *)t->d_hr;
+  pt.hx = (uint32_t *)t->d_hx;
+  pt.hl_key = (uint64_t *)t->d_hlk;
+  pt.hl_meta = (uint32_t *)t->d_hlm;
+  pt.hl_n = (uint32_t *)t->d_hln;
+  pt.hl_cap = cap;
+  pt.n_streams = t->cfg.max_streams;
   pt.hmask = cap - 1;
   pt.n_fns = n_fns;
   pt.err = t->tb.err;
@@ -2080,7 +2126,7 @@ int thapi_tally_handles(thapi_tally *t, uint32_t trace_id, thapi_handle_row *row
   if (ns) {
     HIPCHK(t->hstat.ensure(40 * ns));
     HIPCHK(launch_fill64(t->hstat.as<uint64_t>(), 5 * ns, 0, t->st));
-    HIPCHK(launch_handle_stats(t->pt, t->hstat.as<unsigned long long>(), t->st));
+    HIPCHK(launch_handle_stats(t->pt, t->hstat.as<unsigned long long>(), (uint32_t)ns, t->st));
     HIPCHK(hipMemcpyAsync(h.data(), t->hstat.p, 40 * ns, hipMemcpyDeviceToHost, t->st));
     HIPCHK(hipStreamSynchronize(t->st));
   }

@@ -1328,40 +1328,52 @@ __global__ __launch_bounds__(RWG) void k_range(const Seg *__restrict__ segs, con
   }
 }
 
-// VAR16 pre-pass: payload bytes of each range (sum of payload_len).
-__global__ __launch_bounds__(WG) void k_range_paylen(const Seg *__restrict__ segs, Range *__restrict__ ranges,
+// VAR16 pre-pass: payload bytes of each slice of PAY_SLICE records (sum of
+// payload_len), one workgroup per slice.
+__global__ __launch_bounds__(WG) void k_slice_paylen(const Seg *__restrict__ segs, const Range *__restrict__ ranges,
+                                                     uint32_t n_ranges, const uint32_t *__restrict__ slice_first,
                                                      uint64_t *__restrict__ out) {
   __shared__ unsigned long long acc;
   if (threadIdx.x == 0) acc = 0;
   __syncthreads();
-  const Range rg = ranges[blockIdx.x];
+  const uint32_t r = range_of_slice(slice_first, n_ranges, blockIdx.x);
+  const Range rg = ranges[r];
   const Seg sg = segs[rg.seg];
+  const uint64_t lo = (uint64_t)(blockIdx.x - slice_first[r]) * PAY_SLICE;
+  const uint64_t n = rg.n - lo < PAY_SLICE ? rg.n - lo : PAY_SLICE;
   uint64_t s = 0;
-  gu64 *hdr = (gu64 *)(sg.rec + rg.begin * 16) + 1;   // word 1 of each header: payload_len in its top byte
+  gu64 *hdr = (gu64 *)(sg.rec + (rg.begin + lo) * 16) + 1;   // word 1 of each header: payload_len in its top byte
   uint64_t i = threadIdx.x;
-  for (; i + 7 * WG < rg.n; i += 8 * WG) {            // eight independent loads in flight per lane
+  for (; i + 7 * WG < n; i += 8 * WG) {               // eight independent loads in flight per lane
     uint64_t w[8];
 #pragma unroll
     for (int k = 0; k < 8; k++) w[k] = __builtin_nontemporal_load(hdr + 2 * (i + (uint64_t)k * WG));
 #pragma unroll
     for (int k = 0; k < 8; k++) s += w[k] >> 56;
   }
-  for (; i < rg.n; i += WG) s += __builtin_nontemporal_load(hdr + 2 * i) >> 56;
+  for (; i < n; i += WG) s += __builtin_nontemporal_load(hdr + 2 * i) >> 56;
   atomicAdd(&acc, (unsigned long long)s);
   __syncthreads();
   if (threadIdx.x == 0) out[blockIdx.x] = acc;
 }
 
-// VAR16: exclusive prefix of the range payload sizes within each segment;
-// a segment whose payload_len sum is not its heap size raises ERR_PAYLOAD.
+// VAR16: exclusive prefix of the slice payload sizes within each segment,
+// in place (paylen[b] becomes the payload offset of slice b), and each
+// range's pay_begin (that of its first slice); a segment whose payload_len
+// sum is not its heap size raises ERR_PAYLOAD.
 __global__ void k_range_payoff(const Seg *__restrict__ segs, uint32_t n_segs, const uint32_t *__restrict__ seg_first_range,
-                               Range *__restrict__ ranges, const uint64_t *__restrict__ paylen, uint32_t *err) {
+                               Range *__restrict__ ranges, const uint32_t *__restrict__ slice_first,
+                               uint64_t *__restrict__ paylen, uint32_t *err) {
   const uint32_t sgi = blockIdx.x * blockDim.x + threadIdx.x;
   if (sgi >= n_segs) return;
   uint64_t acc = 0;
   for (uint32_t r = seg_first_range[sgi]; r < seg_first_range[sgi + 1]; r++) {
     ranges[r].pay_begin = acc;
-    acc += paylen[r];
+    for (uint32_t b = slice_first[r]; b < slice_first[r + 1]; b++) {
+      const uint64_t v = paylen[b];
+      paylen[b] = acc;
+      acc += v;
+    }
   }
   if (acc != segs[sgi].pay_bytes) atomicOr(err, ERR_PAYLOAD);
 }
@@ -1439,11 +1451,12 @@ hipError_t launch_range(int fmt, uint32_t T, const Seg *segs, const Range *range
 }
 
 hipError_t launch_paylen(const Seg *segs, Range *ranges, uint32_t n_ranges, const uint32_t *seg_first_range,
-                         uint32_t n_segs, uint64_t *paylen, uint32_t *err, hipStream_t st) {
+                         uint32_t n_segs, const uint32_t *slice_first, uint32_t n_slices, uint64_t *paylen,
+                         uint32_t *err, hipStream_t st) {
   if (!n_ranges) return hipSuccess;
-  hipLaunchKernelGGL(k_range_paylen, dim3(n_ranges), dim3(WG), 0, st, segs, ranges, paylen);
+  hipLaunchKernelGGL(k_slice_paylen, dim3(n_slices), dim3(WG), 0, st, segs, ranges, n_ranges, slice_first, paylen);
   hipLaunchKernelGGL(k_range_payoff, dim3((n_segs + 255) / 256), dim3(256), 0, st, segs, n_segs, seg_first_range,
-                     ranges, paylen, err);
+                     ranges, slice_first, paylen, err);
   return hipGetLastError();
 }
 

@@ -340,9 +340,10 @@ class Tally:
         return tuple(out)
 
     def timings(self):
-        arr = (ctypes.c_double * 6)()
-        n = self._lib.thapi_tally_timings(self._h, arr, 6)
-        return dict(zip(["prepass", "range", "combine", "final", "readout", "intervals"], list(arr)[:n]))
+        arr = (ctypes.c_double * 8)()
+        n = self._lib.thapi_tally_timings(self._h, arr, 8)
+        return dict(zip(["prepass", "range", "combine", "final", "readout", "intervals", "decode", "payload"],
+                        list(arr)[:n]))
 
     def close(self):
         if self._h:

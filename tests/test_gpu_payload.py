@@ -66,6 +66,13 @@ def test_copies_and_handles_closed_form(T):
             ev += [(T0 + ts, 2, 1, ENTRY, b""), (T0 + ts + 1, 2, 1, EXIT, u64(h))]
         else:
             ev += [(T0 + ts, 2, 2, ENTRY, u64(h)), (T0 + ts + 1, 2, 2, EXIT, b"")]
+    # the handle values 2^64 - 1 (created twice, released once) and 0 (created once)
+    for ts, fn, h in [(100, 1, ~0 & (2**64 - 1)), (110, 2, ~0 & (2**64 - 1)), (120, 1, ~0 & (2**64 - 1)),
+                      (130, 1, 0)]:
+        if fn == 1:
+            ev += [(T0 + ts, 2, 1, ENTRY, b""), (T0 + ts + 1, 2, 1, EXIT, u64(h))]
+        else:
+            ev += [(T0 + ts, 2, 2, ENTRY, u64(h)), (T0 + ts + 1, 2, 2, EXIT, b"")]
     ev.sort(key=lambda e: e[0])
     hdr, pay = var16(ev)
     roles = np.array([T.ROLE_COPY, T.ROLE_CREATE, T.ROLE_RELEASE, 0], dtype=np.uint8)
@@ -79,8 +86,8 @@ def test_copies_and_handles_closed_form(T):
         t.flush(final=True)
         _compare(t, o)
         h = t.handles()
-        assert (int(h["creates"][0]), int(h["releases"][0]), int(h["unreleased"][0]), int(h["unmatched"][0])) == \
-            (4, 4, 2, 2)
+        assert (int(h["creates"][0]), int(h["releases"][0]), int(h["handles"][0]), int(h["unreleased"][0]),
+                int(h["unmatched"][0])) == (7, 5, 7, 4, 2)
         assert [(int(r["dir"]), int(r["count"]), int(r["bytes"])) for r in t.copies()] == \
             [(0, 1, 11), (1, 1, 100), (2, 1, 7), (3, 1, 5)]
     o.close()

@@ -659,7 +659,7 @@ def bench_packed(args):
     dec_bytes = pk_bytes + ix_bytes + 16 * n_rec + kept
     payk_bytes = 16 * n_rec + pay_read
     rng_bytes = 16 * n_rec + kept + 64 * len(rows)
-    kern = {"decode (tt::k_pk_count + k_pk_scan + k_pk_write)": (avg["decode"], dec_bytes),
+    kern = {"decode (tt::k_pk_count + scan + tt::k_pk_emit)": (avg["decode"], dec_bytes),
             "tt::k_payload": (avg["payload"], payk_bytes),
             "tt::k_range": (avg["range"], rng_bytes)}
     name, (kms, kbytes) = max(kern.items(), key=lambda kv: kv[1][0])

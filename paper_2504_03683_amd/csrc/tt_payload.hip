@@ -147,13 +147,15 @@ __global__ __launch_bounds__(PKE_WAVES * WAVE) void k_pk_emit(const PkChunk *__r
       const uint64_t pl = uni_lane64((uint64_t)(uintptr_t)p, l), ebl = uni_lane64(eb, l), hbl = uni_lane64(hb, l);
       gq64 *pp = (gq64 *)(uintptr_t)pl;
       uint32_t kl = 0;
-      uint64_t w0 = 0, w1 = 0;
-      uint32_t q = 0;
+      uint64_t w0 = 0, w1 = 0, x0 = 0, x1 = 0, x2 = 0;
       if (lane < ml) {
-        q = pos[wv][l][lane];
+        const uint32_t q = pos[wv][l][lane];
         w0 = pp[q];
         w1 = pp[q + 1];
         kl = kept_len((uint32_t)(w1 >> 56));
+        // (the kept words lie inside the event: its payload has kl bytes or more)
+        if (kl >= 8) x0 = pp[q + 2];
+        if (kl == 24) { x1 = pp[q + 3]; x2 = pp[q + 4]; }
       }
       uint32_t inc = kl;
       for (uint32_t d = 1; d < WAVE; d <<= 1) {
@@ -166,7 +168,8 @@ __global__ __launch_bounds__(PKE_WAVES * WAVE) void k_pk_emit(const PkChunk *__r
         hd[0] = w0;
         hd[1] = (w1 & 0x00FFFFFFFFFFFFFFull) | ((uint64_t)kl << 56);
         uint64_t *hp = heap + (hbl + inc - kl) / 8;
-        for (uint32_t x = 0; x < kl / 8; x++) hp[x] = pp[q + 2 + x];
+        if (kl >= 8) hp[0] = x0;
+        if (kl == 24) { hp[1] = x1; hp[2] = x2; }
       }
       if (lane == l) { eb += ml; hb += tot; }
     }

@@ -1360,22 +1360,37 @@ __global__ __launch_bounds__(WG) void k_slice_paylen(const Seg *__restrict__ seg
 // VAR16: exclusive prefix of the slice payload sizes within each segment,
 // in place (paylen[b] becomes the payload offset of slice b), and each
 // range's pay_begin (that of its first slice); a segment whose payload_len
-// sum is not its heap size raises ERR_PAYLOAD.
-__global__ void k_range_payoff(const Seg *__restrict__ segs, uint32_t n_segs, const uint32_t *__restrict__ seg_first_range,
-                               Range *__restrict__ ranges, const uint32_t *__restrict__ slice_first,
-                               uint64_t *__restrict__ paylen, uint32_t *err) {
-  const uint32_t sgi = blockIdx.x * blockDim.x + threadIdx.x;
-  if (sgi >= n_segs) return;
-  uint64_t acc = 0;
-  for (uint32_t r = seg_first_range[sgi]; r < seg_first_range[sgi + 1]; r++) {
-    ranges[r].pay_begin = acc;
-    for (uint32_t b = slice_first[r]; b < slice_first[r + 1]; b++) {
-      const uint64_t v = paylen[b];
-      paylen[b] = acc;
-      acc += v;
+// sum is not its heap size raises ERR_PAYLOAD.  One workgroup per segment
+// (its slices are consecutive), PO_WG slices at a time.
+constexpr uint32_t PO_WG = 256;
+__global__ __launch_bounds__(PO_WG) void k_range_payoff(const Seg *__restrict__ segs,
+                                                        const uint32_t *__restrict__ seg_first_range,
+                                                        Range *__restrict__ ranges,
+                                                        const uint32_t *__restrict__ slice_first,
+                                                        uint64_t *__restrict__ paylen, uint32_t *err) {
+  __shared__ uint64_t ws[PO_WG / WAVE];
+  const uint32_t sgi = blockIdx.x, lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  const uint32_t r0 = seg_first_range[sgi], r1 = seg_first_range[sgi + 1];
+  const uint32_t b0 = slice_first[r0], b1 = slice_first[r1];
+  uint64_t carry = 0;
+  for (uint32_t c = b0; c < b1; c += PO_WG) {
+    const uint32_t b = c + threadIdx.x;
+    const uint64_t v = b < b1 ? paylen[b] : 0;
+    uint64_t inc = v;
+    for (uint32_t d = 1; d < WAVE; d <<= 1) {
+      const uint64_t t = __shfl_up(inc, d, WAVE);
+      if (lane >= d) inc += t;
     }
+    if (lane == WAVE - 1) ws[w] = inc;
+    __syncthreads();
+    uint64_t before = 0, tot = 0;
+    for (uint32_t k = 0; k < PO_WG / WAVE; k++) { before += k < w ? ws[k] : 0; tot += ws[k]; }
+    if (b < b1) paylen[b] = carry + before + inc - v;
+    carry += tot;
+    __syncthreads();
   }
-  if (acc != segs[sgi].pay_bytes) atomicOr(err, ERR_PAYLOAD);
+  for (uint32_t r = r0 + threadIdx.x; r < r1; r += PO_WG) ranges[r].pay_begin = paylen[slice_first[r]];
+  if (threadIdx.x == 0 && carry != segs[sgi].pay_bytes) atomicOr(err, ERR_PAYLOAD);
 }
 
 // --------------------------------------------------------------- launchers
@@ -1455,8 +1470,8 @@ hipError_t launch_paylen(const Seg *segs, Range *ranges, uint32_t n_ranges, cons
                          uint32_t *err, hipStream_t st) {
   if (!n_ranges) return hipSuccess;
   hipLaunchKernelGGL(k_slice_paylen, dim3(n_slices), dim3(WG), 0, st, segs, ranges, n_ranges, slice_first, paylen);
-  hipLaunchKernelGGL(k_range_payoff, dim3((n_segs + 255) / 256), dim3(256), 0, st, segs, n_segs, seg_first_range,
-                     ranges, slice_first, paylen, err);
+  hipLaunchKernelGGL(k_range_payoff, dim3(n_segs), dim3(PO_WG), 0, st, segs, seg_first_range, ranges, slice_first,
+                     paylen, err);
   return hipGetLastError();
 }
 

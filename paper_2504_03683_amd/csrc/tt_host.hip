@@ -258,6 +258,8 @@ struct thapi_tally {
        *d_tally = nullptr, *d_ktally = nullptr, *d_cstate = nullptr, *d_cstack = nullptr, *d_sstats = nullptr,
        *d_err = nullptr, *d_hs = nullptr, *d_thord = nullptr, *d_snth = nullptr;
   Shape shape{};
+  bool shape_forced = false;                          // THAPI_TALLY_SHAPE gave the shape
+  uint64_t seen_threads = 0, seen_streams = 0;        // threads and streams at the end of the last flush
 
   DevBuf rhdr, ru, ro, rnslots, rmore, paylen;
   DevBuf wide_pack;                                   // the extra passes' work list
@@ -328,7 +330,8 @@ struct thapi_tally {
   bool rc_valid = false;
   uint64_t rc_gen = 0;
   uint32_t rc_scope = 0, rc_trace = 0;
-  std::vector<thapi_tally_row> rc_rows;
+  thapi_tally_row *rc_rows = nullptr;   // pinned, grow-only; rc_n rows valid
+  size_t rc_n = 0, rc_cap = 0;
   thapi_tally_stats rc_stats{};
 };
 
@@ -385,6 +388,7 @@ void free_all(thapi_tally *t) {
   t->queue.clear();
   if (t->h_pinned) hipHostFree(t->h_pinned);
   if (t->h_plan) hipHostFree(t->h_plan);
+  if (t->rc_rows) { hipHostFree(t->rc_rows); t->rc_rows = nullptr; }
   for (auto &e : t->ev) if (e) hipEventDestroy(e);
   if (t->gexec) { hipGraphExecDestroy(t->gexec); t->gexec = nullptr; }
   if (t->arena) { hipFree(t->arena); t->arena = nullptr; }
@@ -415,8 +419,8 @@ Shape pick_shape(const thapi_tally *t) {
   if (const char *env = getenv("THAPI_TALLY_SHAPE")) {
     unsigned T = 0, E = 0, rpc = 1, pipe = 1;
     const int n = sscanf(env, "%u,%u,%u,%u", &T, &E, &rpc, &pipe);
-    if (n >= 2 && (T == 1024 || T == 2048) && E >= 64 && (E & (E - 1)) == 0 && rpc >= 1 && rpc <= 64 &&
-        pipe <= 1 && fits(T, E)) {
+    const bool t_ok = T == 1024 || T == 2048 || (T == 4096 && fmt == 1);   // (4096: FIXED24 only)
+    if (n >= 2 && t_ok && E >= 64 && (E & (E - 1)) == 0 && rpc >= 1 && rpc <= 64 && pipe <= 1 && fits(T, E)) {
       s.rpc = rpc;
       s.pipe = pipe;
       return s;
@@ -566,6 +570,7 @@ int thapi_tally_open(const thapi_tally_config *cfg, thapi_tally **out) {
   }
   t->shape = pick_shape(t);
   if (!t->shape.T) return bail(THAPI_E_INVAL);
+  t->shape_forced = getenv("THAPI_TALLY_SHAPE") != nullptr;
   {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, c.device) == hipSuccess) t->arch = prop.gcnArchName;
@@ -1173,14 +1178,30 @@ void save_tune_cache(thapi_tally *t) {
   fclose(f);
 }
 
+// The default schedule for this handle: builders and walkers overlap
+// (pipelined) unless the streams it has tallied so far hold more than
+// WIDE_STREAM_THREADS threads each on average.  Each thread then brings only
+// a few records to a half tile, and its windows run nearly empty, so the
+// whole-tile schedule (every wave builds, then every wave walks, with every
+// slot's partial window waiting for its next records) is faster (measured:
+// pipelined 1.3x faster at 8 threads per stream, 1.3x slower at 12, 2.2x
+// slower at 64).
+constexpr uint64_t WIDE_STREAM_THREADS = 10;
+Shape default_shape(const thapi_tally *t) {
+  Shape s = t->shape;
+  if (!t->shape_forced && t->seen_streams && t->seen_threads > WIDE_STREAM_THREADS * t->seen_streams) s.pipe = 0;
+  return s;
+}
+
 // The shape for this work: a tuned entry when one matches, else the default.
 Shape shape_for(thapi_tally *t, const std::vector<Chunk> &work) {
-  if (t->tuned.empty()) return t->shape;
+  if (t->tuned.empty()) return default_shape(t);
   auto it = t->tuned.find(tune_key(t, work));
-  if (it == t->tuned.end()) return t->shape;
+  if (it == t->tuned.end()) return default_shape(t);
   Shape s = t->shape;
   const size_t b = range_lds_bytes(it->second[0], it->second[1], s.KL, t->cfg.max_depth, kfmt(t));
-  if ((it->second[0] == 1024 || it->second[0] == 2048) && it->second[1] >= 64 && b + 256 <= t->lds_limit) {
+  const bool t_ok = it->second[0] == 1024 || it->second[0] == 2048 || (it->second[0] == 4096 && kfmt(t) == 1);
+  if (t_ok && it->second[1] >= 64 && b + 256 <= t->lds_limit) {
     s.T = it->second[0]; s.E = it->second[1]; s.lds_bytes = (uint32_t)b;
     s.rpc = std::max<uint32_t>(1, std::min<uint32_t>(it->second[2], 64));
     s.pipe = it->second[3] ? 1u : 0u;
@@ -1410,8 +1431,14 @@ int process_batch(thapi_tally *t, std::vector<Chunk> &work, bool final, const Pl
   HIPCHK(ensure_pinned(t, 64));
   uint32_t *herr = (uint32_t *)t->h_pinned;
   HIPCHK(hipMemcpyAsync(herr, t->tb.err, 4, hipMemcpyDeviceToHost, t->st));
+  HIPCHK(hipMemcpyAsync(herr + 1, t->tb.n_gslots, 4, hipMemcpyDeviceToHost, t->st));   // (threads so far)
   HIPCHK(hipStreamSynchronize(t->st));
   uint32_t err = *herr;
+  t->seen_threads = herr[1];
+  {
+    std::lock_guard<std::mutex> g(t->mu);
+    t->seen_streams = t->stream_keys.size();
+  }
   bool nomem = false;
   if (err == ERR_WIDE) {
     // threads left to extra passes (their summary rows need memory that the
@@ -1646,12 +1673,13 @@ int thapi_tally_autotune(thapi_tally *t, uint32_t reps, uint32_t *chosen) {
   HIPCHK(hipEventCreate(&e1));
   float best_ms = -1;
   Shape best = t->shape;
-  const uint32_t Ts[] = {2048, 1024}, Es[] = {2048, 1024}, rpcs[] = {1, 2, 4}, pipes[] = {0, 1};
+  const uint32_t Ts[] = {4096, 2048, 1024}, Es[] = {2048, 1024}, rpcs[] = {1, 2, 4}, pipes[] = {0, 1};
   int rc = THAPI_OK;
   for (uint32_t T : Ts)
     for (uint32_t E : Es)
       for (uint32_t rpc : rpcs)
       for (uint32_t pipe : pipes) {
+        if (T == 4096 && fmt != 1) continue;   // (FIXED24 only)
         Shape sh = t->shape;
         const size_t b = range_lds_bytes(T, E, sh.KL, D, fmt);
         if (b + 256 > t->lds_limit) continue;
@@ -1709,10 +1737,10 @@ int thapi_tally_read(thapi_tally *t, uint32_t scope, uint32_t trace_id, thapi_ta
   if (failed == THAPI_E_DEVICE) return THAPI_E_DEVICE;
   const uint64_t gen = t->gen.load();
   if (t->rc_valid && t->rc_gen == gen && t->rc_scope == scope && t->rc_trace == trace_id) {
-    *n_rows = t->rc_rows.size();
+    *n_rows = t->rc_n;
     if (stats) *stats = t->rc_stats;
-    if (t->rc_rows.size() > capacity) return capacity == 0 && !rows ? THAPI_OK : THAPI_E_BUFSZ;
-    if (!t->rc_rows.empty()) memcpy(rows, t->rc_rows.data(), sizeof(thapi_tally_row) * t->rc_rows.size());
+    if (t->rc_n > capacity) return capacity == 0 && !rows ? THAPI_OK : THAPI_E_BUFSZ;
+    if (t->rc_n) memcpy(rows, t->rc_rows, sizeof(thapi_tally_row) * t->rc_n);
     t->rc_valid = false;
     return THAPI_OK;
   }
@@ -1837,8 +1865,16 @@ int thapi_tally_read(thapi_tally *t, uint32_t scope, uint32_t trace_id, thapi_ta
   // rows that do not fit the caller's buffer are kept for the second call of
   // a two-call read
   const bool keep = total > capacity;
-  if (keep) t->rc_rows.resize(total);
-  thapi_tally_row *dst = keep ? t->rc_rows.data() : rows;
+  if (keep && total > t->rc_cap) {
+    // (pinned, so that the rows arrive in one DMA; not zero-filled)
+    if (t->rc_rows) hipHostFree(t->rc_rows);
+    t->rc_rows = nullptr;
+    t->rc_cap = 0;
+    HIPCHK(hipHostMalloc((void **)&t->rc_rows, sizeof(thapi_tally_row) * total, hipHostMallocDefault));
+    t->rc_cap = total;
+  }
+  if (keep) t->rc_n = total;
+  thapi_tally_row *dst = keep ? t->rc_rows : rows;
   if (total) {
     HIPCHK(t->rows.ensure(88ull * total));
     HIPCHK(launch_group_rows(rc, t->tb, ngroups, t->cnt.as<uint32_t>(), t->off.as<uint64_t>(), t->rows.as<uint8_t>(),

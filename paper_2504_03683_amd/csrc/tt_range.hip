@@ -687,8 +687,10 @@ __device__ __forceinline__ void slot_store(RangeLds &L, WalkCache &c, const uint
 
 // Walks the cached slot's deferred records followed by records [b, e) of the
 // tile region, in windows of WAVE records.  With `defer`, a last partial
-// window that lies within [b, e) is kept for the next tile instead.
-template <int FMT, bool IV>
+// window that lies within [b, e) is kept for the next tile instead; with HOLD
+// as well, fewer than a window of records all wait (the new ones join the
+// waiting ones in registers).
+template <int FMT, bool IV, bool HOLD = false>
 __device__ __forceinline__ void slot_walk(RangeLds &L, const Tables &tb, const uint32_t E, const uint32_t D,
                                           WalkCache &c, const uint32_t b, const uint32_t e, const bool defer,
                                           const size_t sbase, UItem *__restrict__ ru, uint64_t *__restrict__ wch,
@@ -698,10 +700,21 @@ __device__ __forceinline__ void slot_walk(RangeLds &L, const Tables &tb, const u
   const uint32_t lane = __lane_id();
   const uint32_t pend = c.pend;
   const uint32_t ntot = pend + (e - b);
+  if (HOLD && defer && ntot < WAVE) {
+    // fewer than a window: the new records join the waiting ones in registers
+    if (lane >= pend && lane < ntot) {
+      const uint32_t p = b + (lane - pend);
+      c.dts = L.tile_ts[p];
+      c.dfk = L.tile_fk[p];
+      c.dby = FMT == 2 ? L.tile_by[p] : 0;
+    }
+    c.pend = ntot;
+    return;
+  }
   uint32_t nwalk = ntot;
   if (defer) {
     const uint32_t r = ntot & (WAVE - 1);
-    if (r && ntot - r >= pend) nwalk = ntot - r;
+    if (r && ntot - r >= pend) nwalk = ntot - r;   // (the tail must lie within [b, e))
   }
   if (nwalk) {
     // the v-th record of the sequence (v >= pend) sits at b + v - pend; each
@@ -733,21 +746,58 @@ __device__ __forceinline__ void slot_walk(RangeLds &L, const Tables &tb, const u
   }
 }
 
+// Waiting records of the slots a non-pipelined walker wave owns (slots w +
+// j * RNW, j < DEFER_SETS: every slot a range holds): the partial last window
+// of each, one record per lane, kept in registers until the slot's next
+// records arrive, so that windows run full across tiles for every slot.
+constexpr uint32_t DEFER_SETS = S_MAX / RNW;
+struct WalkDefer {
+  uint32_t n[DEFER_SETS];
+  uint64_t ts[DEFER_SETS], by[DEFER_SETS];
+  uint32_t fk[DEFER_SETS];
+};
+
 // The walk of one sorted tile (the tile region's half hb): wavefront w walks
 // the thread slots w, w + nww, ... (nww walking waves), each slot's records in
 // order.  With `defer`, the last slot's partial last window may wait for the
-// next tile (WalkCache); any other deferred records are walked here.
+// next tile (WalkCache); any other deferred records are walked here.  With
+// `dw` (non-pipelined, nww = RNW), every slot's may wait, in dw.
 template <int FMT, bool IV>
 __device__ __forceinline__ void walk_tile(RangeLds &L, const Tables &tb, const uint32_t E, const uint32_t D,
                                           const uint32_t hb, const uint32_t half, const uint32_t nww,
                                           const bool defer, const size_t sbase, UItem *__restrict__ ru,
-                                          WalkCache &c, IvRec *__restrict__ ivr) {
+                                          WalkCache &c, IvRec *__restrict__ ivr, WalkDefer *dw = nullptr) {
   const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));   // (wave-uniform)
   const uint32_t *soff = L.soff + hb * (S_MAX + 1);
   const uint32_t base = hb * half;
   L.nd = L.misc[2];
   const uint32_t nslots = L.misc[7 + hb];
   uint64_t *wch = L.w_ch + w * WAVE, *wvt = L.w_vt + w * (D + 1);
+  if (dw) {
+    // (the loop is unrolled over the sets, so that each set stays in registers)
+#pragma unroll
+    for (uint32_t j = 0; j < DEFER_SETS; j++) {
+      const uint32_t s = w + j * RNW;
+      if (s >= nslots) break;
+      const uint32_t b = base + soff[s], e = base + soff[s + 1];
+      if (b == e && !dw->n[j]) continue;
+      if (c.slot != s) {
+        slot_store(L, c, wvt);
+        slot_load(L, s, c, wvt);
+      }
+      c.pend = dw->n[j];
+      c.dts = dw->ts[j];
+      c.dfk = dw->fk[j];
+      c.dby = dw->by[j];
+      slot_walk<FMT, IV, true>(L, tb, E, D, c, b, e, defer, sbase, ru, wch, wvt, ivr);
+      dw->n[j] = c.pend;
+      dw->ts[j] = c.dts;
+      dw->fk[j] = c.dfk;
+      dw->by[j] = c.dby;
+      c.pend = 0;
+    }
+    return;
+  }
   for (uint32_t s = w; s < nslots; s += nww) {
     const uint32_t b = base + soff[s], e = base + soff[s + 1];
     if (c.slot != s) {
@@ -1179,6 +1229,9 @@ __device__ __forceinline__ void range_body(RangeLds &L, const Seg *__restrict__ 
     WalkCache wcache;
     wcache.slot = EMPTY32;
     wcache.pend = 0;
+    WalkDefer dw;
+#pragma unroll
+    for (uint32_t j = 0; j < DEFER_SETS; j++) { dw.n[j] = 0; dw.ts[j] = 0; dw.by[j] = 0; dw.fk[j] = 0; }
 #pragma unroll
     for (int r = 0; r < ROWS; r++) {
       const uint32_t li = (uint32_t)gw * (T / GW) + (uint32_t)r * WAVE + lane;
@@ -1200,12 +1253,15 @@ __device__ __forceinline__ void range_body(RangeLds &L, const Seg *__restrict__ 
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         if (lane == 0) __hip_atomic_fetch_add(&L.misc[5], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
       }
+      // (FIXED24: every slot's partial window waits for its next records;
+      // VAR16 keeps the registers for its payload words)
+      else if (FMT == 1) walk_tile<FMT, IV>(L, tb, E, D, 0, T, RNW, t + 1 < ntiles, sbase, ru, wcache, ivr, &dw);
       else walk_tile<FMT, IV>(L, tb, E, D, 0, T, RNW, false, sbase, ru, wcache, ivr);
       if (!PIPE) __syncthreads();
 #pragma unroll
       for (int r = 0; r < ROWS; r++) { a0[r] = b0[r]; a1[r] = b1[r]; a2[r] = b2[r]; }
     }
-    if (!PIPE) slot_store(L, wcache, L.w_vt + w * (D + 1));   // (nothing is deferred without PIPE)
+    if (!PIPE) slot_store(L, wcache, L.w_vt + w * (D + 1));   // (the last tile walks every waiting record)
     if (lane == 0) {
       const int idx[5] = {ST_ENTRIES, ST_EXITS, ST_KERNEL, ST_BAD, ST_RECORDS};
 #pragma unroll
@@ -1407,6 +1463,9 @@ hipError_t prepare_range_kernels(uint32_t max_lds_bytes) {
       TT_K(2, 2, true, true, false),   TT_K(1, 1, false, false, true),  TT_K(1, 2, false, false, true),
       TT_K(2, 1, false, false, true),  TT_K(2, 2, false, false, true),  TT_K(1, 1, false, true, true),
       TT_K(1, 2, false, true, true),   TT_K(2, 1, false, true, true),   TT_K(2, 2, false, true, true),
+      // (4096-record tiles: FIXED24 only; a VAR16 tile of 4096 records does not fit in LDS)
+      TT_K(1, 4, false, false, false), TT_K(1, 4, true, false, false),  TT_K(1, 4, false, true, false),
+      TT_K(1, 4, true, true, false),   TT_K(1, 4, false, false, true),  TT_K(1, 4, false, true, true),
 #undef TT_K
   };
   for (const void *k : ks) {
@@ -1418,7 +1477,8 @@ hipError_t prepare_range_kernels(uint32_t max_lds_bytes) {
 
 // n_wg: workgroups of the persistent launch (at most one per CU is resident);
 // *qhead must be 0 (the caller clears it with a kernel, so the launch can be
-// captured in a graph).  T: records of the LDS tile region (1024 or 2048);
+// captured in a graph).  T: records of the LDS tile region (1024, 2048, or
+// 4096 for FIXED24);
 // with sh.pipe the tiles are half of it.
 hipError_t launch_range(int fmt, uint32_t T, const Seg *segs, const Range *ranges, const uint32_t *order,
                         uint32_t n_ranges, uint32_t *qhead, uint32_t n_wg, const Tables &tb, const Shape &sh,
@@ -1449,13 +1509,20 @@ hipError_t launch_range(int fmt, uint32_t T, const Seg *segs, const Range *range
   } while (0)
   const bool p = sh.pipe != 0, iv = tb.iv != nullptr, xp = rid_base != 0;
   if (xp) {
-    if (fmt == 1) { if (T == 1024) TT_LAUNCH_XP(1, 1); if (T == 2048) TT_LAUNCH_XP(1, 2); }
-    else { if (T == 1024) TT_LAUNCH_XP(2, 1); if (T == 2048) TT_LAUNCH_XP(2, 2); }
+    if (fmt == 1) {
+      if (T == 1024) TT_LAUNCH_XP(1, 1);
+      if (T == 2048) TT_LAUNCH_XP(1, 2);
+      if (T == 4096) TT_LAUNCH_XP(1, 4);
+    } else {
+      if (T == 1024) TT_LAUNCH_XP(2, 1);
+      if (T == 2048) TT_LAUNCH_XP(2, 2);
+    }
     return hipErrorInvalidValue;
   }
   if (fmt == 1) {
     if (T == 1024) { if (p) TT_LAUNCH(1, 1, true); else TT_LAUNCH(1, 1, false); }
     if (T == 2048) { if (p) TT_LAUNCH(1, 2, true); else TT_LAUNCH(1, 2, false); }
+    if (T == 4096) { if (p) TT_LAUNCH(1, 4, true); else TT_LAUNCH(1, 4, false); }
   } else {
     if (T == 1024) { if (p) TT_LAUNCH(2, 1, true); else TT_LAUNCH(2, 1, false); }
     if (T == 2048) { if (p) TT_LAUNCH(2, 2, true); else TT_LAUNCH(2, 2, false); }

@@ -253,7 +253,7 @@ class Tally:
         else:
             _check(self._lib.thapi_tally_read(self._h, scope, trace, None, 0, ctypes.byref(n), ctypes.byref(st)),
                    "read")
-        rows = np.zeros(n.value, dtype=ROW_DTYPE)
+        rows = np.empty(n.value, dtype=ROW_DTYPE)   # (every row is written)
         if n.value:
             _check(self._lib.thapi_tally_read(self._h, scope, trace, rows.ctypes.data, n.value, ctypes.byref(n),
                                               ctypes.byref(st)), "read")

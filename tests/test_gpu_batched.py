@@ -36,13 +36,33 @@ def c1():
     return c, run_oracle(c)
 
 
-@pytest.mark.parametrize("shape", ["1024,1024,4,0", "2048,2048,2,0", "1024,2048,1,0", "2048,1024,3,0",
-                                   "2048,2048,1,1", "1024,1024,2,1", "2048,1024,4,1"])
+@pytest.fixture(scope="module")
+def c2():
+    w = synth.config(2, scale=0.01)
+    c = case_from_workload(w, split=2, seed=12)
+    return c, run_oracle(c)
+
+
+SHAPES = ["1024,1024,4,0", "2048,2048,2,0", "1024,2048,1,0", "2048,1024,3,0", "2048,2048,1,1", "1024,1024,2,1",
+          "2048,1024,4,1", "4096,1024,1,0", "4096,1024,4,0", "4096,1024,2,1", "4096,1024,1,1"]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
 def test_launch_shapes(shape, c3, c1, monkeypatch):
     monkeypatch.setenv("THAPI_TALLY_SHAPE", shape)
     for name, (c, o) in (("batched 256 traces", c3), ("layered, 3 chunks per stream", c1)):
         say("case: %s, shape %s" % (name, shape))
         assert_same(run_gpu(c, max_threads=65536, max_streams=4096), o)
+
+
+@pytest.mark.parametrize("shape", ["1024,2048,2,1", "2048,1024,1,0", "1024,1024,3,0", "2048,1024,2,1"])
+def test_launch_shapes_var16(shape, c2, monkeypatch):
+    """The layered VAR16 workload (payload offsets by slice, transfer bytes) in
+    each tile size and schedule."""
+    monkeypatch.setenv("THAPI_TALLY_SHAPE", shape)
+    c, o = c2
+    say("case: layered VAR16, 2 chunks per stream, shape %s" % shape)
+    assert_same(run_gpu(c, max_threads=4096, max_streams=256), o)
 
 
 def test_batched_equals_per_trace(c3):

@@ -118,7 +118,8 @@ def test_intervals_closed_form(T):
                    (3, 3, 160, 190, 150, 2)]
 
 
-@pytest.mark.parametrize("shape", ["2048,2048,1,1", "2048,2048,4,0", "1024,2048,2,1"])
+@pytest.mark.parametrize("shape", ["2048,2048,1,1", "2048,2048,4,0", "1024,2048,2,1", "4096,1024,2,0",
+                                   "4096,1024,1,1"])
 def test_intervals_deep_trees_across_ranges_and_flushes(T, shape):
     """Six threads of nested calls up to depth 24, cut into 7 chunks with
     flushes between: calls span windows, tiles, ranges and flushes, and

@@ -57,6 +57,15 @@ def test_more_threads_than_a_range_holds(n_threads):
     assert o["stats"]["distinct_threads"] == n_threads and o["stats"]["entries"] > 50000
 
 
+@pytest.mark.parametrize("shape", ["4096,1024,1,0", "4096,1024,2,1"])
+def test_extra_passes_with_large_tiles(shape, monkeypatch):
+    """130 interleaved threads with 4096-record tiles: the first pass and the
+    extra passes both run the large-tile kernels."""
+    monkeypatch.setenv("THAPI_TALLY_SHAPE", shape)
+    say("case: 130 interleaved threads, shape %s" % shape)
+    check(_wide_case(130, 700, seed=77), device_input=True, max_threads=1024)
+
+
 def test_three_hundred_threads():
     """300 interleaved threads: more than the range kernel's LDS thread map
     (256 buckets) holds, so the first pass also meets threads it cannot

@@ -31,6 +31,11 @@ Other forms (each prints its own single JSON line):
                     per-direction copy bytes and the handle join; every
                     output checked against the oracle's (full size), and the
                     same events as plain VAR16 records timed beside it.
+  --form threads    the range kernel alone on traces of 8 to 64 threads and
+                    32 or 200 fns (24 traces x 2 M records each), under the
+                    whole-tile and the pipelined schedule: how the threads a
+                    range interleaves and the (thread, fn) pairs its LDS
+                    tally holds set its rate.
   --form streaming  the continuous-batching service fed by open-loop Poisson
                     arrivals of 64 KiB - 8 MiB chunks of 64 processes x 64
                     threads, host input, at a sweep of offered rates; p50/p99
@@ -167,7 +172,7 @@ def main():
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
                     help="plain form: leave out the batched-vs-per-trace comparison on the batched workload")
-    ap.add_argument("--form", default="plain", choices=["plain", "batched", "streaming", "intervals", "packed"])
+    ap.add_argument("--form", default="plain", choices=["plain", "batched", "streaming", "intervals", "packed", "threads"])
     ap.add_argument("--rates", default="2,5,10,20", help="streaming: offered GB/s per point")
     ap.add_argument("--seconds", type=float, default=10.0, help="streaming: measured seconds per point")
     ap.add_argument("--no-plain", action="store_true", help="streaming: leave out the plain-form comparison")
@@ -193,6 +198,8 @@ def main():
         return bench_intervals(args)
     if args.form == "packed":
         return bench_packed(args)
+    if args.form == "threads":
+        return bench_threads(args)
 
     import numpy as np
     import torch
@@ -721,6 +728,46 @@ def bench_packed(args):
     line["var16_same_events"] = {"ms_per_step": ms_v, "value": n_rec / (ms_v * 1e-3), "unit": "events/s",
                                  "kernel_ms": avg_v, "same_outputs_as_packed": bool(same)}
     print(json.dumps(line), flush=True)
+
+
+def bench_threads(args):
+    """Range-kernel time (HIP events, best of the timed flushes) on 24 traces of
+    2 M records each with a given number of threads and fns, per schedule."""
+    import torch
+
+    import synth
+    from paper_2504_03683_amd import tally as T
+    dev = torch.device("cuda:0")
+    points = []
+    for nthr, nfn in [(8, 32), (12, 32), (16, 32), (24, 32), (64, 32), (8, 200), (32, 100), (64, 200)]:
+        cfg = synth.base_cfg(n_fns=nfn, max_depth=8)
+        streams = [synth.gen_stream(cfg, synth.SEED_BASE + 5, i, i, 0, 1000, nthr, int(2_000_000 * args.scale), False)
+                   for i in range(24)]
+        recs = [torch.from_numpy(st.records).to(dev) for st in streams]
+        n = sum(st.records.size // 24 for st in streams)
+        row = {"threads": nthr, "fns": nfn, "records": n}
+        for name, shape in (("whole_tile", "2048,2048,1,0"), ("pipelined", "2048,2048,1,1")):
+            os.environ["THAPI_TALLY_SHAPE"] = shape
+            t = T.Tally(T.FMT_FIXED24, 200, 0, max_depth=8, max_threads=24 * nthr + 64, max_streams=64,
+                        flags=T.DEVICE_INPUT | T.PROFILE)
+            del os.environ["THAPI_TALLY_SHAPE"]
+            ms = []
+            for it in range(args.warmup + args.steps):
+                t.reset()
+                for st, r in zip(streams, recs):
+                    t.submit(st.key, r)
+                t.flush(final=True)
+                if it >= args.warmup:
+                    ms.append(t.timings()["range"])
+            t.close()
+            row[name + "_ms"] = min(ms)
+            row[name + "_Grec_per_s"] = n / min(ms) / 1e6
+        log("threads %2d fns %3d: whole-tile %.3f ms, pipelined %.3f ms" % (nthr, nfn, row["whole_tile_ms"],
+                                                                           row["pipelined_ms"]))
+        points.append(row)
+        del recs
+    print(json.dumps({"form": "threads", "unit": "ms (range kernel, best of %d)" % args.steps, "points": points}),
+          flush=True)
 
 
 def _streaming_expected(w, plan_chunks, n_prod):

@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define THAPI_TALLY_ABI_VERSION 1u
+#define THAPI_TALLY_ABI_VERSION 2u
 
 /* ---- status codes ------------------------------------------------------ */
 #define THAPI_OK            0
@@ -171,14 +171,19 @@ typedef struct {
   uint64_t distinct_hosts, distinct_processes, distinct_threads;
 } thapi_tally_stats;
 
-/* Opens a handle on cfg->device.  Allocates all device tables up front
+/* Opens a handle on cfg->device: the state of an analysis of traces whose
+ * calls are tallied per API function (section 3.4, the Tally view of the
+ * section 4.3 table).  Allocates all device tables up front
  * (tallies: max_threads * n_fns * 64 B; stacks: max_threads * max_depth * 32 B).
  * *out is set only on success.  Errors: THAPI_E_INVAL (bad config),
  * THAPI_E_NOMEM, THAPI_E_DEVICE. */
 int thapi_tally_open(const thapi_tally_config *cfg, thapi_tally **out);
 
-/* Queues one chunk of one stream.  Chunks of one key are applied in submit
- * order; keys are independent.  Host input (default) is copied before the
+/* Queues one chunk of one stream: events of one (trace, host, process), the
+ * context a trace's stream carries (section 3.1; the section 1.1 record holds
+ * host, vpid and vtid), in the order they were recorded.  Chunks of one key
+ * are applied in submit order; keys are independent (the key is passed by
+ * value; its `reserved` word must be 0).  Host input (default) is copied before the
  * call returns, so the caller may reuse its buffers at once; with
  * THAPI_DEVICE_INPUT the pointers are device memory that must stay valid and
  * unmodified until a flush covering the returned ticket has returned.
@@ -189,19 +194,26 @@ int thapi_tally_open(const thapi_tally_config *cfg, thapi_tally **out);
  * read no byte outside [payload, payload + payload_bytes).
  * Thread-safe.  Errors: THAPI_E_INVAL, THAPI_E_NOMEM, THAPI_E_AGAIN,
  * THAPI_E_CAPACITY (too many streams), THAPI_E_STATE. */
-int thapi_tally_submit(thapi_tally *t, const thapi_stream_key *key,
+int thapi_tally_submit(thapi_tally *t, thapi_stream_key key,
                        const void *records, size_t record_bytes,
                        const void *payload, size_t payload_bytes, uint64_t *ticket_out);
 
 /* Runs every queued chunk up to `ticket` (THAPI_TICKET_ALL: all) through the
- * GPU pipeline and waits for it.  THAPI_FLUSH_FINAL also closes all streams:
+ * GPU pipeline and waits for it: each entry is matched with its exit per
+ * thread (the interval of a call, section 3.3) and the call is added to its
+ * (thread, function) tally (section 3.4); calls open at a chunk's end stay on
+ * the device until a later chunk closes them, so a trace can be analysed while
+ * it is still written (section 6).  THAPI_FLUSH_FINAL also closes all streams:
  * open entries become unclosed_final and no further submit is accepted.
  * Errors: THAPI_E_DEPTH, THAPI_E_CAPACITY, THAPI_E_MALFORMED (STRICT),
  * THAPI_E_INVAL (VAR16 device input with a payload size mismatch),
  * THAPI_E_DEVICE, THAPI_E_STATE. */
 int thapi_tally_flush(thapi_tally *t, uint64_t ticket, uint32_t flags);
 
-/* Reads the tally of everything flushed so far for one scope and trace
+/* Reads the tally of everything flushed so far (calls, and total, min and
+ * max of inclusive and self time per function: the columns of the section
+ * 4.3 table, whose header counts hosts, processes and threads) for one scope
+ * and trace
  * (THAPI_ALL = all traces), in canonical order (trace, host, pid, tid,
  * row_kind, id).  rows may be NULL when capacity is 0 (size query).
  * *n_rows receives the number of rows of the scope; if it exceeds capacity,

@@ -674,9 +674,9 @@ uint64_t packed_events(const uint8_t *buf, uint64_t nbytes, const uint64_t *inde
 }
 }  // namespace
 
-int thapi_tally_submit(thapi_tally *t, const thapi_stream_key *key, const void *records, size_t record_bytes,
+int thapi_tally_submit(thapi_tally *t, thapi_stream_key key, const void *records, size_t record_bytes,
                        const void *payload, size_t payload_bytes, uint64_t *ticket_out) {
-  if (!t || !key || key->reserved) return THAPI_E_INVAL;
+  if (!t || key.reserved) return THAPI_E_INVAL;
   const uint32_t rs = record_size(t);
   if (record_bytes % rs) return THAPI_E_INVAL;
   if (record_bytes && !records) return THAPI_E_INVAL;
@@ -717,7 +717,7 @@ int thapi_tally_submit(thapi_tally *t, const thapi_stream_key *key, const void *
   if (pk && dev_in && ((uintptr_t)payload & 7)) return THAPI_E_INVAL;
   std::unique_lock<std::mutex> lk(t->mu);
   t->gen++;
-  SKey sk{key->trace_id, key->host_id, key->pid};
+  SKey sk{key.trace_id, key.host_id, key.pid};
   auto it = t->stream_idx.find(sk);
   uint32_t sidx;
   if (it == t->stream_idx.end()) {

@@ -16,7 +16,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libthapi_tally.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 FMT_FIXED24, FMT_VAR16, FMT_PACKED = 1, 2, 3
 ROLE_COPY, ROLE_CREATE, ROLE_RELEASE = 1, 2, 3
 DIR_H2H, DIR_H2D, DIR_D2H, DIR_D2D = 0, 1, 2, 3
@@ -100,7 +100,7 @@ def load():
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.c_void_p
     lib.thapi_tally_open.argtypes = [ctypes.POINTER(Config), ctypes.POINTER(P)]
-    lib.thapi_tally_submit.argtypes = [P, ctypes.POINTER(StreamKey), P, ctypes.c_size_t, P, ctypes.c_size_t,
+    lib.thapi_tally_submit.argtypes = [P, StreamKey, P, ctypes.c_size_t, P, ctypes.c_size_t,
                                        ctypes.POINTER(ctypes.c_uint64)]
     lib.thapi_tally_flush.argtypes = [P, ctypes.c_uint64, ctypes.c_uint32]
     lib.thapi_tally_flush_noalloc.argtypes = [P, ctypes.c_uint64, ctypes.c_uint32]
@@ -198,7 +198,7 @@ class Tally:
         rp, rb, rk = _ptr_and_bytes(records)
         pp, pb, pk = _ptr_and_bytes(payload)
         ticket = ctypes.c_uint64(0)
-        _check(self._lib.thapi_tally_submit(self._h, ctypes.byref(k), rp, rb, pp, pb, ctypes.byref(ticket)),
+        _check(self._lib.thapi_tally_submit(self._h, k, rp, rb, pp, pb, ctypes.byref(ticket)),
                "submit")
         if self.flags & DEVICE_INPUT:
             self._keep.append((rk, pk))   # device buffers must outlive the flush
@@ -210,7 +210,7 @@ class Tally:
         rp, rb, _ = _ptr_and_bytes(records)
         pp, pb, _ = _ptr_and_bytes(payload)
         ticket = ctypes.c_uint64(0)
-        return self._lib.thapi_tally_submit(self._h, ctypes.byref(k), rp, rb, pp, pb, ctypes.byref(ticket))
+        return self._lib.thapi_tally_submit(self._h, k, rp, rb, pp, pb, ctypes.byref(ticket))
 
     def flush(self, ticket=TICKET_ALL, final=False):
         rc = self._lib.thapi_tally_flush(self._h, ticket, FLUSH_FINAL if final else 0)

@@ -78,8 +78,13 @@ def test_strerror_and_argument_errors_without_gpu(lib):
     c = tally.Config()
     c.abi_version = 999
     assert lib.thapi_tally_open(ctypes.byref(c), ctypes.byref(h)) == tally.E_INVAL
+    # version 1 passed the stream key to submit by pointer; it is refused
     c.abi_version = 1
-    c.format = 3
+    c.format = 1
+    c.n_fns = 10
+    assert lib.thapi_tally_open(ctypes.byref(c), ctypes.byref(h)) == tally.E_INVAL
+    c.abi_version = tally.ABI_VERSION
+    c.format = 9
     assert lib.thapi_tally_open(ctypes.byref(c), ctypes.byref(h)) == tally.E_INVAL
     c.format = 1
     c.n_fns = 10
@@ -104,7 +109,7 @@ def test_service_with_graph_is_rejected_without_gpu(lib):
     from paper_2504_03683_amd import tally
     h = ctypes.c_void_p()
     c = tally.Config()
-    c.abi_version = 1
+    c.abi_version = tally.ABI_VERSION
     c.format = 1
     c.n_fns = 4
     c.flags = tally.SERVICE | tally.GRAPH

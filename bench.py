@@ -9,6 +9,10 @@ layered stack: 12 processes x 8 threads, 200 functions in three layers,
 100 M API records plus ~10 M device-kernel records (FIXED24, ~2.64 GB).
 
 Prints ONE JSON line.  `value` is events/s (every record consumed counts).
+Beside the headline, the line carries the batched form against the per-trace
+form (`batched_vs_per_trace`), the variable-length workload at full size
+(`var16_full`) and one streaming point at 20 GB/s offered
+(`streaming_20GBps`), each checked against the oracle.
 `roofline` rates the dominant kernel (the range kernel) by its algorithmic
 bytes (24 B per record read + 64 B per tally row written) over its average
 duration, measured with HIP events on the launch stream.  `cpu_baseline`
@@ -176,6 +180,10 @@ def main():
     ap.add_argument("--rates", default="2,5,10,20", help="streaming: offered GB/s per point")
     ap.add_argument("--seconds", type=float, default=10.0, help="streaming: measured seconds per point")
     ap.add_argument("--no-plain", action="store_true", help="streaming: leave out the plain-form comparison")
+    ap.add_argument("--no-var16", action="store_true",
+                    help="plain form: leave out the full-size variable-length workload with its parity check")
+    ap.add_argument("--no-streaming", action="store_true",
+                    help="plain form: leave out the streaming service point (20 GB/s offered) with its parity check")
     ap.add_argument("--no-per-trace", action="store_true",
                     help="batched: leave out the per-trace comparison (for profiling the batched flush alone)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -324,7 +332,68 @@ def main():
     del recs, pays
     if not args.no_batched:
         out["batched_vs_per_trace"] = run_batched(args, stream, steps=min(args.steps, 10), warmup=2, autotune=True)
+    if not args.no_var16 and args.config == 1:
+        out["var16_full"] = run_var16_full(stream)
+    if not args.no_streaming and args.config == 1:
+        pts, _, exact, n_prod = run_streaming(1.0, [20.0], 3.0, False, True)
+        out["streaming_20GBps"] = dict(pts[0], seconds=3.0, producers=n_prod,
+                                       workload="64 processes x 64 threads, FIXED24 chunks 64KiB-8MiB, "
+                                                "open-loop Poisson arrivals, host input, 16 GiB budget")
     print(json.dumps(out), flush=True)
+
+
+def run_var16_full(stream, steps=10, warmup=2):
+    """The variable-length workload at full size (50 M records, device input):
+    ms per step and events/s of the plain step, and parity of the thread rows
+    and counters against the oracle."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import synth
+    from paper_2504_03683_amd import tally as T
+
+    w = synth.config(2)
+    dev = torch.device("cuda:0")
+    data = [(torch.from_numpy(s.records).to(dev), torch.from_numpy(s.payload).to(dev)) for s in w.streams]
+    tl = T.Tally(w.fmt, w.n_fns, w.n_kernel_ids, max_depth=8, max_threads=1024, max_streams=64,
+                 flags=T.DEVICE_INPUT | T.PROFILE, has_size=w.has_size, stream=stream)
+    rowbuf = torch.zeros(1024 * w.n_fns * T.ROW_DTYPE.itemsize, dtype=torch.uint8,
+                         pin_memory=True).numpy().view(T.ROW_DTYPE)
+
+    def step():
+        tl.reset()
+        for s, (r, p) in zip(w.streams, data):
+            tl.submit(s.key, r, p)
+        tl.flush(final=True)
+        return tl.read(T.SCOPE_THREAD, out=rowbuf)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    rng = []
+    for _ in range(steps):
+        rows, stats = step()
+        rng.append(tl.timings()["range"])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    rows = rows.copy()
+    tl.close()
+    del data
+    o = oracle.run_workload(w, max_depth=8)
+    want, ws = o.rows(oracle.SCOPE_THREAD), o.stats()
+    o.close()
+    ok = rows.shape == want.shape and np.array_equal(rows, want)
+    ok = ok and all(stats[k] == ws[k] for k in T.STAT_NAMES if k != "dropped_records")
+    n = w.n_records
+    sub = {"workload": WORKLOADS[2], "records": n, "input_bytes": w.record_bytes + w.payload_bytes,
+           "ms_per_step": ms, "events_per_s": n / (ms * 1e-3), "range_kernel_ms": sum(rng) / len(rng),
+           "parity": "bit-exact" if ok else "MISMATCH"}
+    log("VAR16 full size: %.3f ms/step, parity %s" % (ms, sub["parity"]))
+    return sub
 
 
 def copy_calibration():
@@ -817,10 +886,12 @@ def _streaming_expected(w, plan_chunks, n_prod):
     return rows[order], stats
 
 
-def bench_streaming(args):
-    """Open-loop Poisson arrivals into the service; latency = completion - scheduled arrival.
-    The same chunk schedule is then fed to the plain form (one submit + flush per chunk,
-    one consumer), and every service run is checked against the oracle."""
+def run_streaming(scale, rates, seconds, plain, parity):
+    """Open-loop Poisson arrivals into the service at each rate; latency =
+    completion - scheduled arrival.  With `plain`, the same chunk schedule is
+    then fed to the plain form (one submit + flush per chunk, one consumer);
+    with `parity`, every service run is checked against the oracle.  Returns
+    (points, total wall seconds, all bit-exact, producers)."""
     import threading
 
     import numpy as np
@@ -829,17 +900,16 @@ def bench_streaming(args):
     from paper_2504_03683_amd import tally as T
 
     t0 = time.time()
-    w = synth.config(4, scale=args.scale)
+    w = synth.config(4, scale=scale)
     log("generated streaming pool: %d processes, %.2f GB in %.1fs" % (len(w.streams), w.record_bytes / 1e9,
                                                                      time.time() - t0))
-    rates = [float(x) for x in args.rates.split(",") if x]
     n_prod = 4
     points = []
     total_wall = 0.0
     all_exact = True
     for ri, rate in enumerate(rates):
         rng = np.random.default_rng(1000 + ri)
-        dur = args.seconds + 0.5
+        dur = seconds + 0.5
         # chunk plan per producer: (arrival time, process, byte offset, size)
         sizes_rng = np.random.default_rng(2000 + ri)
         offered = rate * 1e9 * dur
@@ -931,18 +1001,26 @@ def bench_streaming(args):
         pt, rows, st, wall = run_form(True)
         total_wall += wall
         pt = dict({"offered_GBps": rate}, **pt)
-        if not args.no_parity:
+        if parity:
             want, wst = _streaming_expected(w, [c for pl in plans for c in pl], n_prod)
             ok = rows.shape == want.shape and np.array_equal(rows, want)
             ok = ok and all(st[k] == wst[k] for k in T.STAT_NAMES if k != "dropped_records")
             pt["parity"] = "bit-exact" if ok else "MISMATCH"
             all_exact = all_exact and ok
         log("rate %.1f GB/s, service: %s" % (rate, json.dumps(pt)))
-        if not args.no_plain:
+        if plain:
             pp, _, _, _ = run_form(False)
             log("rate %.1f GB/s, plain: %s" % (rate, json.dumps(pp)))
             pt["plain_one_chunk_per_flush"] = pp
         points.append(pt)
+    return points, total_wall, all_exact, n_prod
+
+
+def bench_streaming(args):
+    """The streaming sweep (service at each offered rate, the plain form beside it)."""
+    rates = [float(x) for x in args.rates.split(",") if x]
+    points, total_wall, all_exact, n_prod = run_streaming(args.scale, rates, args.seconds, not args.no_plain,
+                                                          not args.no_parity)
     best = max(points, key=lambda p: p["events_per_s"])
     out = base_line(len(points), 0, 1e3 * total_wall / len(points), best["events_per_s"], {
         "workload": "streaming: 64 processes x 64 threads, FIXED24 chunks 64KiB-8MiB (log-uniform), "

@@ -290,7 +290,8 @@ int thapi_tally_service_info(thapi_tally *t, uint64_t *info, int n);
  * little-endian byte blob: every stream's key, dropped records and counters;
  * every thread's (stream, tid), open calls (its carried stack), flags and
  * last timestamp; every non-empty (thread, fn) tally and (stream, kernel)
- * tally.  Layout, in order:
+ * tally.  (The payload-role tables -- copy rows and the handle join -- and
+ * the intervals of the last flush are not part of it.)  Layout, in order:
  *   header  16 x u32: magic "THTALLY1" (2 words), version 1, format, n_fns,
  *           n_kernel_ids, max_depth, n_streams, n_threads, n_frames, n_rows,
  *           n_krows, finalized (0/1), 3 x 0

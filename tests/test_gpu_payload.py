@@ -266,3 +266,40 @@ def test_packed_service(T):
         o.finish()
         _compare(t, o)
     o.close()
+
+
+def test_packed_intervals_and_graph(T):
+    """Packed chunks with THAPI_INTERVALS (every tallied call of the decoded
+    events becomes an interval) and with THAPI_GRAPH (the pipeline after the
+    decode replayed from a graph over two flushes of the same shape)."""
+    import torch
+    from tests.test_gpu_intervals import canon
+    say("case: packed chunks with intervals, and with graph replay")
+    w, roles = _layered(0.004, 700)
+    packs = [synth.pack(s, 32) for s in w.streams]
+    o = oracle.Oracle(2, 200, 64, 8, w.has_size)
+    o.keep_intervals()
+    for s, (b, ix) in zip(w.streams, packs):
+        assert o.submit_packed(s.key, b, ix) == 0
+    o.finish()
+    keep = [(_dev(b), _dev(ix.view(np.uint8))) for b, ix in packs]
+    with T.Tally(T.FMT_PACKED, 200, 64, max_depth=8, max_threads=1024, max_streams=64,
+                 flags=T.DEVICE_INPUT | T.INTERVALS, has_size=w.has_size) as t:
+        for s, (b, ix) in zip(w.streams, keep):
+            t.submit(s.key, b, ix)
+        t.flush(final=True)
+        assert np.array_equal(t.read(1)[0], o.rows(1))
+        got = canon(t.intervals())
+    want = o.intervals()
+    assert len(got) == len(want) > 10000 and np.array_equal(got, want)
+    with T.Tally(T.FMT_PACKED, 200, 64, max_depth=8, max_threads=1024, max_streams=64,
+                 flags=T.DEVICE_INPUT | T.GRAPH, has_size=w.has_size) as t:
+        for rep in range(2):
+            t.reset()
+            for s, (b, ix) in zip(w.streams, keep):
+                t.submit(s.key, b, ix)
+            t.flush(final=True)
+            torch.cuda.synchronize()
+            for sc in (1, 2, 3, 4):
+                assert np.array_equal(t.read(sc)[0], o.rows(sc)), (rep, sc)
+    o.close()

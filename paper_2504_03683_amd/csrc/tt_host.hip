@@ -401,8 +401,17 @@ void free_all(thapi_tally *t) {
 
 // Picks the range kernel's tile and LDS tally size for the format and depth:
 // the largest tile and tally that fit the LDS, preferring a full tally (2048
-// entries) over a larger tile.  THAPI_TALLY_SHAPE="T,E[,rpc[,pipe]]"
-// overrides the choice (used to tune the launch shape).
+// entries) over a larger tile, then as many more tally entries (in steps of
+// 64, up to TALLY_E_MAX) as the rest of the LDS holds: more (thread, fn) keys
+// stay in LDS instead of overflowing to the global table.
+// THAPI_TALLY_SHAPE="T,E[,rpc[,pipe]]" overrides the choice (used to tune
+// the launch shape).
+constexpr uint32_t TALLY_E_MAX = 4096;
+uint32_t grow_tally(const thapi_tally *t, uint32_t T, uint32_t E, uint32_t KL) {
+  const uint32_t D = t->cfg.max_depth;
+  while (E + 64 <= TALLY_E_MAX && range_lds_bytes(T, E + 64, KL, D, kfmt(t)) + 256 <= t->lds_limit) E += 64;
+  return E;
+}
 Shape pick_shape(const thapi_tally *t) {
   Shape s{};
   const uint32_t D = t->cfg.max_depth;
@@ -420,7 +429,7 @@ Shape pick_shape(const thapi_tally *t) {
     unsigned T = 0, E = 0, rpc = 1, pipe = 1;
     const int n = sscanf(env, "%u,%u,%u,%u", &T, &E, &rpc, &pipe);
     const bool t_ok = T == 1024 || T == 2048 || (T == 4096 && fmt == 1);   // (4096: FIXED24 only)
-    if (n >= 2 && t_ok && E >= 64 && (E & (E - 1)) == 0 && rpc >= 1 && rpc <= 64 && pipe <= 1 && fits(T, E)) {
+    if (n >= 2 && t_ok && E >= 64 && E % 64 == 0 && rpc >= 1 && rpc <= 64 && pipe <= 1 && fits(T, E)) {
       s.rpc = rpc;
       s.pipe = pipe;
       return s;
@@ -429,7 +438,10 @@ Shape pick_shape(const thapi_tally *t) {
   const uint32_t cand[][2] = {{2048, 2048}, {1024, 2048}, {2048, 1024}, {1024, 1024},
                               {1024, 512}, {1024, 256}, {1024, 128}, {1024, 64}};
   for (auto &c : cand)
-    if (fits(c[0], c[1])) return s;
+    if (fits(c[0], c[1])) {
+      if (c[1] == 2048) fits(c[0], grow_tally(t, c[0], c[1], s.KL));
+      return s;
+    }
   s.T = 0;
   return s;
 }
@@ -1673,13 +1685,16 @@ int thapi_tally_autotune(thapi_tally *t, uint32_t reps, uint32_t *chosen) {
   HIPCHK(hipEventCreate(&e1));
   float best_ms = -1;
   Shape best = t->shape;
-  const uint32_t Ts[] = {4096, 2048, 1024}, Es[] = {2048, 1024}, rpcs[] = {1, 2, 4}, pipes[] = {0, 1};
+  const uint32_t Ts[] = {4096, 2048, 1024}, Es[] = {0, 2048, 1024}, rpcs[] = {1, 2, 4}, pipes[] = {0, 1};
   int rc = THAPI_OK;
   for (uint32_t T : Ts)
-    for (uint32_t E : Es)
+    for (uint32_t E0 : Es)
       for (uint32_t rpc : rpcs)
       for (uint32_t pipe : pipes) {
         if (T == 4096 && fmt != 1) continue;   // (FIXED24 only)
+        // (E0 = 0: the most entries beyond 2048 that fit; skipped when none do)
+        const uint32_t E = E0 ? E0 : grow_tally(t, T, 2048, t->shape.KL);
+        if (!E0 && E == 2048) continue;
         Shape sh = t->shape;
         const size_t b = range_lds_bytes(T, E, sh.KL, D, fmt);
         if (b + 256 > t->lds_limit) continue;

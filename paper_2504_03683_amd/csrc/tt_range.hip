@@ -243,9 +243,9 @@ __device__ inline void tally_call(const RangeLds &L, uint32_t E, const Tables &t
     if (E > d0) {
       const uint32_t key = (slot << 16) | fn;
       const uint32_t span = E - d0;
-      // (E is a power of two: with no direct rows the table is all of it, and
-      // the top bits of a multiplicative hash index it)
-      h = d0 ? d0 + hash32(key) % span : (key * 0x9E3779B1u) >> (32 - (31 - __builtin_clz(E)));
+      // (a multiplicative hash mapped onto the span by a multiply-shift, so
+      // the span need not be a power of two)
+      h = d0 + (uint32_t)(((uint64_t)(key * 0x9E3779B1u) * span) >> 32);
       const uint32_t probes = span < TALLY_PROBES ? span : TALLY_PROBES;
       for (uint32_t probe = 0; probe < probes; probe++) {
         const uint32_t k = tal[h].key;

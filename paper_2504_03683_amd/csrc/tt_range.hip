@@ -83,7 +83,8 @@ struct RangeLds {
   uint32_t *wcnt, *soff;
   uint32_t *newtid, *newbucket;
   uint32_t *misc;   // [0] nslots, [1] new ids, [2] nd, [3] builder barrier, [5] tiles built x producer waves,
-                    // [7..8] nslots per half, [16..] tiles walked per walking wave
+                    // [7..8] nslots per half, [9] threads left to extra passes, [10] LDS tally has
+                    // filled up, [16..] tiles walked per walking wave
   uint32_t *cnt;    // [ST_N] range-local counters
   uint32_t nd;      // slots of the direct-mapped tally region, chosen per range at its first tile
   uint32_t *wsum;   // [RNW] per-wave payload sums
@@ -219,8 +220,13 @@ __host__ __device__ inline uint32_t direct_slots(uint32_t n_fns, uint32_t E) {
   return d < (uint32_t)S_MAX ? d : (uint32_t)S_MAX;
 }
 
-// Probes of the LDS tally hash before a key falls back to the global tally.
-constexpr uint32_t TALLY_PROBES = 16;
+// Positions of the LDS tally hash a key may take (linear probing) before its
+// call falls back to the global tally; once some key of the range has found
+// none, later calls probe only the first TALLY_PROBES_FULL of them (each
+// probe is a dependent LDS round trip, and in a table that has filled up the
+// keys that probe far are mostly not in it).
+constexpr uint32_t TALLY_PROBES = 8;
+constexpr uint32_t TALLY_PROBES_FULL = 2;
 
 // Adds one completed call to the (slot, fn) entry of the LDS tally.
 // Durations that do not
@@ -241,21 +247,28 @@ __device__ inline void tally_call(const RangeLds &L, uint32_t E, const Tables &t
   } else {
     const uint32_t d0 = nd * tb.n_fns;
     if (E > d0) {
+      // a key's positions [p, p + reach) never wrap: the first comes from a
+      // multiplicative hash mapped by a multiply-shift onto the span - reach
+      // + 1 starts (so the span need not be a power of two); a key sits
+      // before the first free position of its sequence, since entries are
+      // never freed
       const uint32_t key = (slot << 16) | fn;
       const uint32_t span = E - d0;
-      // (a multiplicative hash mapped onto the span by a multiply-shift, so
-      // the span need not be a power of two)
-      h = d0 + (uint32_t)(((uint64_t)(key * 0x9E3779B1u) * span) >> 32);
-      const uint32_t probes = span < TALLY_PROBES ? span : TALLY_PROBES;
-      for (uint32_t probe = 0; probe < probes; probe++) {
-        const uint32_t k = tal[h].key;
+      const uint32_t reach = span < TALLY_PROBES ? span : TALLY_PROBES;
+      const uint32_t full = __hip_atomic_load(&L.misc[10], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      uint32_t p = d0 + (uint32_t)(((uint64_t)(key * 0x9E3779B1u) * (span - reach + 1)) >> 32);
+      const uint32_t probes = full && reach > TALLY_PROBES_FULL ? TALLY_PROBES_FULL : reach;
+      for (uint32_t i = 0; i < probes; i++, p++) {
+        const uint32_t k = tal[p].key;
         if (k == key) { found = true; break; }
         if (k == EMPTY32) {
-          const uint32_t old = atomicCAS(&tal[h].key, EMPTY32, key);
+          const uint32_t old = atomicCAS(&tal[p].key, EMPTY32, key);
           if (old == EMPTY32 || old == key) { found = true; break; }
         }
-        h = h + 1 < E ? h + 1 : d0;
       }
+      if (found) h = p;
+      else if (!full)   // no room among the key's positions: the table has filled up
+        __hip_atomic_store(&L.misc[10], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
   }
   if (found) {

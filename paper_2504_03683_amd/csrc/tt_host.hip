@@ -160,6 +160,7 @@ struct Chunk {
   void *owned;       // staged device copy (host input), freed after its flush
   uint64_t owned_bytes;
   bool in_arena;     // service mode: the staged copy lives in the device arena
+  bool in_hin;       // host input, no service: the staged copy lives in the host-input arena
   bool in_ring;      // service mode: the bytes went through the pinned staging ring
   bool ready;        // service mode: the copy to the device is enqueued (or complete)
   int ev;            // service mode: event recorded after the copy (index into the pool), or -1
@@ -314,6 +315,14 @@ struct thapi_tally {
   uint8_t *ring = nullptr;                            // pinned staging ring, min(budget, RING_MAX) bytes
   Fifo rfifo;
   std::vector<hipEvent_t> ev_pool;                    // copy-completion events
+  // host input without the service: chunks are staged one after another in a
+  // grow-only device arena that is reused once none of them is live any more
+  // (so a steady submit/flush cycle allocates nothing); a chunk that does not
+  // fit gets a buffer of its own.  hin_live counts every staged host-input
+  // byte, hin_in the arena's, hin_want the most ever live at once.
+  uint8_t *hin = nullptr;
+  uint64_t hin_cap = 0, hin_top = 0, hin_in = 0, hin_live = 0, hin_want = 0;
+  hipStream_t hst = nullptr;                          // its copies
   std::vector<int> ev_free;
   uint64_t done_upto = 0;                             // every ticket <= this one is tallied
   std::vector<uint64_t> done_ns;                      // [ticket] CLOCK_MONOTONIC ns of its batch's completion
@@ -392,6 +401,8 @@ void free_all(thapi_tally *t) {
   for (auto &e : t->ev) if (e) hipEventDestroy(e);
   if (t->gexec) { hipGraphExecDestroy(t->gexec); t->gexec = nullptr; }
   if (t->arena) { hipFree(t->arena); t->arena = nullptr; }
+  if (t->hin) { hipFree(t->hin); t->hin = nullptr; t->hin_cap = 0; }
+  if (t->hst) { hipStreamDestroy(t->hst); t->hst = nullptr; }
   if (t->ring) { hipHostFree(t->ring); t->ring = nullptr; }
   for (auto &s : t->cst) if (s) { hipStreamDestroy(s); s = nullptr; }
   for (auto &e : t->ev_pool) if (e) hipEventDestroy(e);
@@ -645,9 +656,15 @@ void release_chunk(thapi_tally *t, const Chunk &c) {
     if (c.in_ring) t->rfifo.release_front();
     if (c.ev >= 0) t->ev_free.push_back(c.ev);
     t->budget_used -= c.owned_bytes;
+  } else if (c.in_hin) {
+    t->budget_used -= c.owned_bytes;
+    t->hin_live -= c.owned_bytes;
+    t->hin_in -= c.owned_bytes;
+    if (!t->hin_in) t->hin_top = 0;
   } else if (c.owned) {
     hipFree(c.owned);
     t->budget_used -= c.owned_bytes;
+    t->hin_live -= c.owned_bytes;
   }
 }
 
@@ -832,20 +849,48 @@ int thapi_tally_submit(thapi_tally *t, thapi_stream_key key, const void *records
       if (t->failed) return THAPI_E_STATE;
     }
     t->budget_used += bytes;
-    lk.unlock();
+    t->hin_live += bytes;
+    t->hin_want = std::max(t->hin_want, t->hin_live);
+    hipError_t e = hipSuccess;
+    if (!t->hst) e = hipStreamCreateWithFlags(&t->hst, hipStreamNonBlocking);
+    if (e == hipSuccess && !t->hin_in && t->hin_cap < t->hin_want) {
+      // nothing staged in the arena: grow it to the most host input held at once so far
+      if (t->hin) hipFree(t->hin);
+      t->hin = nullptr;
+      t->hin_cap = 0;
+      const uint64_t want = (t->hin_want + (1ull << 20) - 1) & ~((1ull << 20) - 1);
+      if (hipMalloc((void **)&t->hin, want) == hipSuccess) t->hin_cap = want;
+      else { hipGetLastError(); t->hin = nullptr; }
+    }
     void *d = nullptr;
-    hipError_t e = hipMalloc(&d, bytes);
-    if (e == hipSuccess) e = hipMemcpy(d, records, record_bytes, hipMemcpyHostToDevice);
+    const uint64_t at = (t->hin_top + 255) & ~255ull;
+    if (e == hipSuccess && t->hin && at + bytes <= t->hin_cap) {
+      d = t->hin + at;
+      t->hin_top = at + bytes;
+      t->hin_in += bytes;
+      c.in_hin = true;
+    }
+    lk.unlock();
+    if (e == hipSuccess && !d) e = hipMalloc(&d, bytes);
+    if (e == hipSuccess) e = hipMemcpyAsync(d, records, record_bytes, hipMemcpyHostToDevice, t->hst);
     if (e == hipSuccess && payload_bytes)
-      e = hipMemcpy((uint8_t *)d + ((record_bytes + 15) / 16 * 16), payload, payload_bytes, hipMemcpyHostToDevice);
+      e = hipMemcpyAsync((uint8_t *)d + ((record_bytes + 15) / 16 * 16), payload, payload_bytes,
+                         hipMemcpyHostToDevice, t->hst);
+    if (e == hipSuccess) e = hipStreamSynchronize(t->hst);
     lk.lock();
     if (e != hipSuccess) {
-      if (d) hipFree(d);
+      if (c.in_hin) {
+        t->hin_in -= bytes;
+        if (!t->hin_in) t->hin_top = 0;
+      } else if (d) {
+        hipFree(d);
+      }
       t->budget_used -= bytes;
+      t->hin_live -= bytes;
       t->cv.notify_all();
       return e == hipErrorOutOfMemory ? THAPI_E_NOMEM : hip_fail(t, e);
     }
-    c.owned = d;
+    c.owned = c.in_hin ? nullptr : d;
     c.owned_bytes = bytes;
     c.rec = (const uint8_t *)d;
     c.pay = payload_bytes ? (const uint8_t *)d + ((record_bytes + 15) / 16 * 16) : nullptr;

@@ -235,8 +235,9 @@ int thapi_tally_read(thapi_tally *t, uint32_t scope, uint32_t trace_id,
 int thapi_tally_reset(thapi_tally *t);
 
 /* Batched form: times the pipeline on the chunks queued right now under each
- * candidate launch shape -- records in the LDS tile region (1024, 2048), LDS
- * tally entries (2048, 1024), work-list ranges per CU (1, 2, 4) and the wave
+ * candidate launch shape -- records in the LDS tile region (1024, 2048, and
+ * 4096 for FIXED24), LDS tally entries (every entry the LDS holds beyond 2048,
+ * 2048, 1024), work-list ranges per CU (1, 2, 4, 8, 16) and the wave
  * schedule (0: all waves build a tile, then walk it; 1: half the waves build
  * the next tile while the other half walks the previous one) -- and keeps the fastest
  * for this workload class (device, format, max_depth, and the log2 buckets of

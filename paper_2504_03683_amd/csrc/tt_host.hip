@@ -1730,7 +1730,7 @@ int thapi_tally_autotune(thapi_tally *t, uint32_t reps, uint32_t *chosen) {
   HIPCHK(hipEventCreate(&e1));
   float best_ms = -1;
   Shape best = t->shape;
-  const uint32_t Ts[] = {4096, 2048, 1024}, Es[] = {0, 2048, 1024}, rpcs[] = {1, 2, 4}, pipes[] = {0, 1};
+  const uint32_t Ts[] = {4096, 2048, 1024}, Es[] = {0, 2048, 1024}, rpcs[] = {1, 2, 4, 8, 16}, pipes[] = {0, 1};
   int rc = THAPI_OK;
   for (uint32_t T : Ts)
     for (uint32_t E0 : Es)

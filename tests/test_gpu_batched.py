@@ -44,7 +44,8 @@ def c2():
 
 
 SHAPES = ["1024,1024,4,0", "2048,2048,2,0", "1024,2048,1,0", "2048,1024,3,0", "2048,2048,1,1", "1024,1024,2,1",
-          "2048,1024,4,1", "4096,1024,1,0", "4096,1024,4,0", "4096,1024,2,1", "4096,1024,1,1"]
+          "2048,1024,4,1", "4096,1024,1,0", "4096,1024,4,0", "4096,1024,2,1", "4096,1024,1,1", "2048,2560,8,0",
+          "1024,2048,16,1"]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
@@ -123,7 +124,7 @@ def test_autotune_and_cache(c3, tmp_path):
         chosen = t.autotune(reps=1)
         # tiles of 1024, 2048 or (FIXED24) 4096 records; 1024, 2048 or every LDS
         # entry left (a multiple of 64, at most 4096) for the tally
-        assert chosen[0] in (1024, 2048, 4096) and chosen[2] in (1, 2, 4)
+        assert chosen[0] in (1024, 2048, 4096) and chosen[2] in (1, 2, 4, 8, 16)
         assert chosen[1] in (1024, 2048) or (chosen[1] % 64 == 0 and 2048 < chosen[1] <= 4096)
         assert chosen[3] in (0, 1)
         t.flush(final=True)

@@ -78,9 +78,12 @@ def profiled_traffic():
     import re
     csrc = os.path.join(ROOT, "paper_2504_03683_amd", "csrc")
     h = hashlib.sha256()
-    for name in ("tt_range.hip", "tt_common.h"):
-        with open(os.path.join(csrc, name), "rb") as fh:
-            h.update(fh.read())
+    try:
+        for name in ("tt_range.hip", "tt_common.h"):
+            with open(os.path.join(csrc, name), "rb") as fh:
+                h.update(fh.read())
+    except OSError:
+        return None
     try:
         with open(os.path.join(ROOT, "profiles", "k_range_layered_110M.md")) as fh:
             text = fh.read()

@@ -159,7 +159,19 @@ struct Tables {
   CIval *civ;                  // calls closed by the combine
   uint32_t *civ_n;             // their count (zero at launch)
   uint32_t civ_cap;
+  // partial tallies of the current flush: a range whose threads all have
+  // direct-mapped LDS rows and stream ordinals below PART_ORDS writes its rows
+  // here with plain stores ([range][ordinal][n_fns] LDS tally entries,
+  // part_gslot[range][ordinal] their global slots, part_mask[range] the
+  // ordinals present, 0 when the range used global atomics instead), and a
+  // merge after the combine adds each row over the stream's ranges once.
+  // Ranges from part_ranges on (all of them when it is 0) use the atomics.
+  uint8_t *part;
+  uint32_t *part_gslot;
+  uint32_t *part_mask;
+  uint32_t part_ranges;
 };
+constexpr uint32_t PART_ORDS = 16;
 
 // Payload analytics tables (tt_payload.hip).  hs: 0 free, else stream + 1;
 // hk: the slot's handle, EMPTY64 until written.

@@ -46,6 +46,8 @@ hipError_t launch_combine(const uint32_t *spans, uint32_t n_spans, const RHdr *r
                           const OItem *ro, const uint32_t *rnslots, const Tables &tb, const uint32_t *clist,
                           hipStream_t st);
 hipError_t launch_final(const Tables &tb, uint32_t max_threads, hipStream_t st);
+size_t part_range_bytes(uint32_t n_fns, int fmt);
+hipError_t launch_part_merge(int fmt, const uint32_t *spans, uint32_t n_spans, const Tables &tb, hipStream_t st);
 hipError_t launch_iv_out(const Tables &tb, const uint64_t *ivbase, const RHdr *rhdr, uint32_t n_ranges,
                          const uint32_t *rnslots, const uint64_t *off, const uint32_t *skeys, void *out,
                          hipStream_t st);
@@ -277,6 +279,7 @@ struct thapi_tally {
   // THAPI_INTERVALS: the current flush's interval buffers (see Tables), the
   // public records of the last intervals() call and its offsets / keys
   DevBuf iv, iv_n, iv_h0, iv_snap, civ, civ_n, ivout, ivaux;
+  DevBuf part, part_gslot, part_mask;                  // partial tallies of the current flush (see Tables)
   uint32_t iv_nranges = 0;                            // summary rows of the last flush
   std::vector<uint64_t> iv_bases;                     // their first IvRec
   bool iv_valid = false;                              // the interval buffers hold the last flush's
@@ -299,7 +302,7 @@ struct thapi_tally {
   std::map<std::string, std::array<uint32_t, 4>> tuned;  // autotuned {T, E, rpc, pipe} per workload class
   bool flushed_any = false;
   hipGraphExec_t gexec = nullptr;                     // THAPI_GRAPH: the captured pipeline
-  std::array<uint64_t, 24> gsig{};
+  std::array<uint64_t, 26> gsig{};
   uint64_t graph_builds = 0, graph_launches = 0;
   std::string cache_path;
 
@@ -391,7 +394,8 @@ void free_all(thapi_tally *t) {
   DevBuf *bs[] = {&t->plan_pack, &t->rhdr, &t->ru, &t->ro, &t->rnslots, &t->rmore, &t->wide_pack, &t->paylen, &t->keys, &t->vals, &t->keys2,
                   &t->vals2, &t->gbeg, &t->gend, &t->cnt, &t->off, &t->read_pack, &t->rows, &t->tstats,
                   &t->merge_buf, &t->iv, &t->iv_n, &t->iv_h0, &t->iv_snap, &t->civ, &t->civ_n, &t->ivout,
-                  &t->ivaux, &t->pk_scr, &t->pk_hdr, &t->pk_heap, &t->hstat};
+                  &t->ivaux, &t->pk_scr, &t->pk_hdr, &t->pk_heap, &t->hstat, &t->part, &t->part_gslot,
+                  &t->part_mask};
   for (DevBuf *b : bs) b->release();
   for (auto &c : t->queue) if (c.owned) hipFree(c.owned);
   t->queue.clear();
@@ -1049,6 +1053,7 @@ PlanSizes plan_sizes(const thapi_tally *t, const Plan &pl) {
 // handle's grow-only buffers, or -- with `scratch` -- consecutive 256-byte
 // aligned parts of that device array, which the caller has checked is large
 // enough (as it has the pinned staging).
+constexpr size_t PART_MAX_BYTES = 1ull << 30;   // partial tallies of one flush at most
 hipError_t upload_plan(thapi_tally *t, const Plan &pl, uint8_t *scratch = nullptr) {
   const PlanSizes z = plan_sizes(t, pl);
   hipError_t e;
@@ -1065,6 +1070,7 @@ hipError_t upload_plan(thapi_tally *t, const Plan &pl, uint8_t *scratch = nullpt
     fb.rnslots = (uint32_t *)carve(z.rnslots);
     fb.rmore = (uint32_t *)carve(z.rmore);
     fb.paylen = (uint64_t *)carve(z.paylen);
+    t->tb.part_ranges = 0;   // (the ranges add their tallies with global atomics)
   } else {
     UPCHK(t->rhdr.ensure(z.rhdr));
     UPCHK(t->ru.ensure(z.ru));
@@ -1081,6 +1087,19 @@ hipError_t upload_plan(thapi_tally *t, const Plan &pl, uint8_t *scratch = nullpt
     fb.rnslots = t->rnslots.as<uint32_t>();
     fb.rmore = t->rmore.as<uint32_t>();
     fb.paylen = t->paylen.as<uint64_t>();
+    // partial tallies for as many ranges as PART_MAX_BYTES holds
+    const size_t per = part_range_bytes(t->cfg.n_fns, kfmt(t));
+    const uint64_t np = std::min<uint64_t>(pl.ranges.size(), PART_MAX_BYTES / per);
+    t->tb.part_ranges = 0;
+    if (np) {
+      UPCHK(t->part.ensure(per * np));
+      UPCHK(t->part_gslot.ensure(4ull * PART_ORDS * np));
+      UPCHK(t->part_mask.ensure(4ull * np));
+      t->tb.part = t->part.as<uint8_t>();
+      t->tb.part_gslot = t->part_gslot.as<uint32_t>();
+      t->tb.part_mask = t->part_mask.as<uint32_t>();
+      t->tb.part_ranges = (uint32_t)np;
+    }
   }
   // the work queue's head (zero) travels with the work list
   static const uint32_t zero = 0;
@@ -1153,6 +1172,7 @@ hipError_t launch_pipeline(thapi_tally *t, const Plan &pl, const Shape &sh, bool
     TE(TM_RANGE);
     TB(TM_COMBINE);
     LPCHK(launch_combine(fb.spans, nSp, fb.rhdr, fb.ru, fb.ro, fb.rnslots, t->tb, nullptr, t->st));
+    LPCHK(launch_part_merge(kfmt(t), fb.spans, nSp, t->tb, t->st));
     TE(TM_COMBINE);
   }
   if (final) {
@@ -1171,7 +1191,7 @@ hipError_t launch_pipeline(thapi_tally *t, const Plan &pl, const Shape &sh, bool
 hipError_t run_pipeline(thapi_tally *t, const Plan &pl, const Shape &sh, bool final) {
   const bool prof = (t->cfg.flags & THAPI_PROFILE) != 0;
   if (!(t->cfg.flags & THAPI_GRAPH)) return launch_pipeline(t, pl, sh, final, prof);
-  const std::array<uint64_t, 24> sig = {pl.slicefirst.empty() ? 0 : pl.slicefirst.back(),
+  const std::array<uint64_t, 26> sig = {pl.slicefirst.empty() ? 0 : pl.slicefirst.back(),
                                         (uint64_t)(uintptr_t)t->fb.slicefirst,
                                         pl.ranges.size(), pl.segs.size(), pl.spans.size(), sh.T, sh.E,
                                         sh.rpc | ((uint64_t)sh.pipe << 32), final ? 1u : 0u,
@@ -1182,7 +1202,8 @@ hipError_t run_pipeline(thapi_tally *t, const Plan &pl, const Shape &sh, bool fi
                                         (uint64_t)(uintptr_t)t->fb.ranges, (uint64_t)(uintptr_t)t->fb.order,
                                         (uint64_t)(uintptr_t)t->fb.rhdr, (uint64_t)(uintptr_t)t->fb.ru,
                                         (uint64_t)(uintptr_t)t->fb.ro, (uint64_t)(uintptr_t)t->fb.rnslots,
-                                        (uint64_t)(uintptr_t)t->fb.spans, (uint64_t)(uintptr_t)t->fb.paylen};
+                                        (uint64_t)(uintptr_t)t->fb.spans, (uint64_t)(uintptr_t)t->fb.paylen,
+                                        (uint64_t)(uintptr_t)t->tb.part, t->tb.part_ranges};
   hipError_t e;
   if (!t->gexec || sig != t->gsig) {
     if (t->gexec) { hipGraphExecDestroy(t->gexec); t->gexec = nullptr; }

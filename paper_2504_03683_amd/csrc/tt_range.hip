@@ -84,7 +84,7 @@ struct RangeLds {
   uint32_t *newtid, *newbucket;
   uint32_t *misc;   // [0] nslots, [1] new ids, [2] nd, [3] builder barrier, [5] tiles built x producer waves,
                     // [7..8] nslots per half, [9] threads left to extra passes, [10] LDS tally has
-                    // filled up, [16..] tiles walked per walking wave
+                    // filled up, [11] ordinals of the partial tally, [16..] tiles walked per walking wave
   uint32_t *cnt;    // [ST_N] range-local counters
   uint32_t nd;      // slots of the direct-mapped tally region, chosen per range at its first tile
   uint32_t *wsum;   // [RNW] per-wave payload sums
@@ -1318,6 +1318,7 @@ __device__ __forceinline__ void range_body(RangeLds &L, const Seg *__restrict__ 
     hd.flags = r.flags;
     hd.pad = 0; hd.pad2 = 0;
     rhdr[sbase + s] = hd;
+    if (!XP) L.newtid[s] = r.gslot < tb.max_threads ? tb.th_ord[r.gslot] : EMPTY32;   // (for the partial tally)
     const uint32_t no = hd.n_o < D ? hd.n_o : D;
     for (uint32_t k = 0; k < no; k++) {
       OItem *o = &ro[(sbase + s) * D + k];
@@ -1330,7 +1331,35 @@ __device__ __forceinline__ void range_body(RangeLds &L, const Seg *__restrict__ 
     }
   }
   const uint32_t nd = L.nd, d0 = nd * tb.n_fns;
-  for (uint32_t i = tid; i < E; i += RWG) {
+  // a range whose threads all have direct-mapped rows and stream ordinals
+  // below PART_ORDS stores its rows as a partial tally (merged per row after
+  // the combine); any other range adds its entries with global atomics
+  uint32_t pmask = 0;
+  if (!XP && rid < tb.part_ranges) {
+    __syncthreads();
+    if (tid == 0) {
+      uint32_t m = 0;
+      bool ok = nslots <= nd;
+      for (uint32_t s = 0; ok && s < nslots; s++) {
+        const uint32_t o = L.newtid[s];
+        if (o < PART_ORDS) m |= 1u << o;
+        else ok = false;
+      }
+      L.misc[11] = ok ? m : 0u;
+      tb.part_mask[rid] = ok ? m : 0u;
+    }
+    __syncthreads();
+    pmask = L.misc[11];
+  }
+  if (pmask) {
+    TE *const dst = (TE *)tb.part + (size_t)rid * PART_ORDS * tb.n_fns;
+    for (uint32_t i = tid; i < nslots * tb.n_fns; i += RWG) {
+      const uint32_t s = i / tb.n_fns, fn = i - s * tb.n_fns;
+      dst[(size_t)L.newtid[s] * tb.n_fns + fn] = tal[i];
+    }
+    if ((uint32_t)tid < nslots) tb.part_gslot[rid * PART_ORDS + L.newtid[tid]] = L.srec[tid].gslot;
+  }
+  for (uint32_t i = pmask ? E : (uint32_t)tid; i < E; i += RWG) {
     uint32_t s, fn;
     const TE &te = tal[i];
     if (i < d0) {
@@ -1465,6 +1494,80 @@ __global__ __launch_bounds__(PO_WG) void k_range_payoff(const Seg *__restrict__ 
 // --------------------------------------------------------------- launchers
 // Allows every range-kernel variant up to max_lds_bytes of dynamic LDS (set
 // once, outside any stream capture).
+// Merge of the partial tallies: one lane per (stream, ordinal, fn) row sums
+// the row over the stream's ranges that stored it (count and sums, 32-bit
+// min / max with the LDS tally's sentinels) and adds the result to the global
+// row once.  spans[3 j .. 3 j + 2] = {stream, first range, end range}.
+template <int FMT>
+__global__ __launch_bounds__(256) void k_part_merge(const uint32_t *__restrict__ spans, uint32_t n_spans, Tables tb) {
+  typedef typename TEntOf<FMT>::T TE;
+  const uint32_t idx = blockIdx.x * 256 + threadIdx.x;
+  if (idx >= PART_ORDS * tb.n_fns) return;
+  const uint32_t ord = idx / tb.n_fns, fn = idx - ord * tb.n_fns;
+  const TE *const part = (const TE *)tb.part;
+  for (uint32_t sp = blockIdx.y; sp < n_spans; sp += gridDim.y) {
+    const uint32_t r0 = spans[3 * sp + 1], r1e = spans[3 * sp + 2];
+    const uint32_t r1 = r1e < tb.part_ranges ? r1e : tb.part_ranges;
+    uint64_t cnt = 0, isum = 0, ssum = 0, bsum = 0;
+    uint32_t imin = EMPTY32, imax = 0, smin = EMPTY32, smax = 0, g = EMPTY32;
+    // (four ranges' entries in flight at once; an entry its range never
+    // touched holds a zero count and sums and the min / max sentinels, so it
+    // adds nothing)
+    for (uint32_t r = r0; r < r1; r += 4) {
+      TE e[4];
+      uint32_t gk[4];
+#pragma unroll
+      for (uint32_t k = 0; k < 4; k++) {
+        const bool in = r + k < r1 && ((tb.part_mask[r + k] >> ord) & 1u);
+        gk[k] = EMPTY32;
+        if (in) {
+          e[k] = part[((size_t)(r + k) * PART_ORDS + ord) * tb.n_fns + fn];
+          gk[k] = tb.part_gslot[(r + k) * PART_ORDS + ord];
+        } else {
+          e[k].cnt = 0; e[k].isum = 0; e[k].ssum = 0;
+          e[k].imin = EMPTY32; e[k].imax = 0; e[k].smin = EMPTY32; e[k].smax = 0;
+          if constexpr (FMT == 2) e[k].bsum = 0;
+        }
+      }
+#pragma unroll
+      for (uint32_t k = 0; k < 4; k++) {
+        if (gk[k] != EMPTY32) g = gk[k];
+        cnt += e[k].cnt;
+        isum += e[k].isum;
+        ssum += e[k].ssum;
+        if constexpr (FMT == 2) bsum += e[k].bsum;
+        imin = e[k].imin < imin ? e[k].imin : imin;
+        imax = e[k].imax > imax ? e[k].imax : imax;
+        smin = e[k].smin < smin ? e[k].smin : smin;
+        smax = e[k].smax > smax ? e[k].smax : smax;
+      }
+    }
+    if (!cnt || g >= tb.max_threads) continue;
+    Tally *row = &tb.tally[(size_t)g * tb.n_fns + fn];
+    g_add64(&row->count, cnt);
+    g_add64(&row->incl_sum, isum);
+    g_add64(&row->self_sum, ssum);
+    if (bsum) g_add64(&row->bytes_sum, bsum);
+    if (imin != EMPTY32) g_min64(&row->incl_min, imin);
+    if (imax) g_max64(&row->incl_max, imax);
+    if (smin != EMPTY32) g_min64(&row->self_min, smin);
+    if (smax) g_max64(&row->self_max, smax);
+  }
+}
+
+// Bytes of one range's partial tally.
+size_t part_range_bytes(uint32_t n_fns, int fmt) {
+  return (size_t)PART_ORDS * n_fns * (fmt == 2 ? sizeof(TEnt2) : sizeof(TEnt1));
+}
+
+hipError_t launch_part_merge(int fmt, const uint32_t *spans, uint32_t n_spans, const Tables &tb, hipStream_t st) {
+  if (!tb.part_ranges || !n_spans) return hipSuccess;
+  const dim3 grid((PART_ORDS * tb.n_fns + 255) / 256, n_spans < 65535u ? n_spans : 65535u);
+  if (fmt == 2) hipLaunchKernelGGL(k_part_merge<2>, grid, dim3(256), 0, st, spans, n_spans, tb);
+  else hipLaunchKernelGGL(k_part_merge<1>, grid, dim3(256), 0, st, spans, n_spans, tb);
+  return hipGetLastError();
+}
+
 hipError_t prepare_range_kernels(uint32_t max_lds_bytes) {
   const void *ks[] = {
 #define TT_K(F, R, P, I, X) (const void *)k_range<F, R, P, I, X>

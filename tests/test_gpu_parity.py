@@ -7,7 +7,7 @@ import pytest
 import oracle
 import synth
 from tests.parity import Case, assert_same, case_from_workload, run_gpu, run_oracle, say
-from tests.records import ENTRY, EXIT, KERNEL, fixed24, u64, var16
+from tests.records import ENTRY, EXIT, KERNEL, fixed24, random_trees, u64, var16
 
 pytestmark = pytest.mark.gpu
 T0 = synth.T0_NS
@@ -213,6 +213,26 @@ def test_many_threads_one_stream(n_rec, split):
     if split > 1:
         c.flush_after = [0]
     check(c)
+
+
+@pytest.mark.parametrize("split", [1, 4])
+def test_partial_and_atomic_range_tallies(split):
+    """One stream whose first half comes from 16 threads and second half from
+    20 (the same 16 and four more): the ranges of the first half store their
+    tally rows as partial rows (every thread has a direct-mapped row and a
+    stream ordinal below 16), those of the second half add theirs with global
+    atomics, so the rows of the first 16 threads receive both."""
+    say("case: partial and atomic range tallies in one stream, %d chunks" % split)
+    a = random_trees(31, 16, 9000, 40, tid_base=900, max_depth=6, t0=T0)
+    t1 = max(e[0] for e in a) + 1000
+    b = random_trees(32, 20, 7000, 40, tid_base=900, max_depth=6, t0=t1)
+    rec = fixed24([e[:4] for e in a] + [e[:4] for e in b])
+    n = rec.size // 24
+    cuts = [n * k // split for k in range(split + 1)]
+    subs = [((0, 0, 91), rec[24 * x:24 * y], None) for x, y in zip(cuts, cuts[1:])]
+    c = Case(1, 40, 0, subs, flush_after=[0] if split > 1 else [], max_depth=16)
+    check(c)
+    assert n > 500_000
 
 
 @pytest.mark.parametrize("flush_between", [False, True])

@@ -154,7 +154,7 @@ def _ptr_and_bytes(a):
     if a is None:
         return None, 0, None
     if hasattr(a, "data_ptr"):   # torch tensor (device input)
-        return (a.data_ptr() or None), a.numel() * a.element_size(), a
+        return (a.data_ptr() or None), a.nbytes, a
     a = np.ascontiguousarray(a)
     return (a.ctypes.data if a.size else None), a.nbytes, a
 
@@ -192,14 +192,24 @@ class Tally:
         self._h = ctypes.c_void_p()
         _check(self._lib.thapi_tally_open(ctypes.byref(c), ctypes.byref(self._h)), "open")
         self._keep = []
+        self._submit_fn = self._lib.thapi_tally_submit
+        self._keys = {}   # stream key tuple -> its StreamKey (built once)
+
+    def _key(self, key):
+        try:
+            k = self._keys.get(key)
+        except TypeError:   # (an unhashable key, e.g. a list)
+            return StreamKey(key[0], key[1], key[2], 0)
+        if k is None:
+            k = StreamKey(key[0], key[1], key[2], 0)
+            self._keys[key] = k
+        return k
 
     def submit(self, key, records, payload=None):
-        k = StreamKey(key[0], key[1], key[2], 0)
         rp, rb, rk = _ptr_and_bytes(records)
         pp, pb, pk = _ptr_and_bytes(payload)
         ticket = ctypes.c_uint64(0)
-        _check(self._lib.thapi_tally_submit(self._h, k, rp, rb, pp, pb, ctypes.byref(ticket)),
-               "submit")
+        _check(self._submit_fn(self._h, self._key(key), rp, rb, pp, pb, ctypes.byref(ticket)), "submit")
         if self.flags & DEVICE_INPUT:
             self._keep.append((rk, pk))   # device buffers must outlive the flush
         return ticket.value

@@ -123,9 +123,10 @@ def test_autotune_and_cache(c3, tmp_path):
             t.submit(key, rec, pay)
         chosen = t.autotune(reps=1)
         # tiles of 1024, 2048 or (FIXED24) 4096 records; 1024, 2048 or every LDS
-        # entry left (a multiple of 64, at most 4096) for the tally
+        # entry left (a multiple of 64, at most 4096; beside 4096-record tiles,
+        # grown from 1024) for the tally
         assert chosen[0] in (1024, 2048, 4096) and chosen[2] in (1, 2, 4, 8, 16)
-        assert chosen[1] in (1024, 2048) or (chosen[1] % 64 == 0 and 2048 < chosen[1] <= 4096)
+        assert chosen[1] in (1024, 2048) or (chosen[1] % 64 == 0 and 1024 < chosen[1] <= 4096)
         assert chosen[3] in (0, 1)
         t.flush(final=True)
         assert_same(read_out(t, c), o)

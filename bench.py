@@ -73,13 +73,14 @@ def log(msg):
 
 def profiled_traffic():
     """HBM bytes per range-kernel launch from the committed counter summary, if
-    it was taken on the range kernel source as it is now (else None)."""
+    it was taken on the range kernel source and the host code that picks its
+    launch shape as they are now (else None)."""
     import hashlib
     import re
     csrc = os.path.join(ROOT, "paper_2504_03683_amd", "csrc")
     h = hashlib.sha256()
     try:
-        for name in ("tt_range.hip", "tt_common.h"):
+        for name in ("tt_range.hip", "tt_common.h", "tt_host.hip"):
             with open(os.path.join(csrc, name), "rb") as fh:
                 h.update(fh.read())
     except OSError:

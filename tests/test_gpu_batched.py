@@ -45,7 +45,11 @@ def c2():
 
 SHAPES = ["1024,1024,4,0", "2048,2048,2,0", "1024,2048,1,0", "2048,1024,3,0", "2048,2048,1,1", "1024,1024,2,1",
           "2048,1024,4,1", "4096,1024,1,0", "4096,1024,4,0", "4096,1024,2,1", "4096,1024,1,1", "2048,2560,8,0",
-          "1024,2048,16,1"]
+          "1024,2048,16,1",
+          # 4096-record tiles beside every tally entry the LDS has left at depth 8
+          # (the layered workload's own shape), and beside exactly 8 threads x 200
+          # fns of direct-mapped rows
+          "4096,1984,1,1", "4096,1600,2,1", "4096,1984,8,0"]
 
 
 @pytest.mark.parametrize("shape", SHAPES)

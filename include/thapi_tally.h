@@ -252,6 +252,16 @@ int thapi_tally_reset(thapi_tally *t);
  * could take the work), THAPI_E_DEVICE. */
 int thapi_tally_autotune(thapi_tally *t, uint32_t reps, uint32_t *chosen);
 
+/* Measurement helper, not part of the tally: the launch shape the last flush
+ * chose, shape[0..3] = {T, E, rpc, pipe} as for thapi_tally_autotune.  The
+ * shape is the tuned one of the flush's workload class when there is one.
+ * Otherwise it is the one that the environment variable THAPI_TALLY_SHAPE,
+ * read at open as "T,E[,rpc[,pipe]]", names, provided that it is a valid
+ * shape and fits the LDS (a shape that does not is ignored).  Otherwise it is
+ * the default.  Errors: THAPI_E_INVAL (a NULL argument), THAPI_E_STATE (no
+ * flush since open). */
+int thapi_tally_last_shape(thapi_tally *t, uint32_t *shape);
+
 /* Streaming form (THAPI_SERVICE).  Aggregation on the node while the trace
  * is still being produced (section 3, On-node Processing, builds aggregates
  * from temporarily stored traces; section 6 names tracing and analysis run

@@ -264,6 +264,7 @@ struct thapi_tally {
   bool shape_forced = false;                          // THAPI_TALLY_SHAPE gave the shape
   uint64_t seen_threads = 0, seen_streams = 0;        // threads and streams at the end of the last flush
   uint32_t e4096 = 0;                                 // FIXED24: most tally entries beside a 4096-record tile (0: none)
+  uint32_t last_shape[4] = {0, 0, 0, 0};              // {T, E, rpc, pipe} of the last flush (T = 0: none yet)
 
   DevBuf rhdr, ru, ro, rnslots, rmore, paylen;
   DevBuf wide_pack;                                   // the extra passes' work list
@@ -1318,6 +1319,7 @@ namespace {
 Shape prepare_batch(thapi_tally *t, std::vector<Chunk> &work, Plan &pl, uint64_t max_ranges = 0) {
   std::stable_sort(work.begin(), work.end(), [](const Chunk &a, const Chunk &b) { return a.stream < b.stream; });
   const Shape sh = shape_for(t, work);
+  t->last_shape[0] = sh.T; t->last_shape[1] = sh.E; t->last_shape[2] = sh.rpc; t->last_shape[3] = sh.pipe;
   plan_work(t, work, sh, pl, max_ranges);
   return sh;
 }
@@ -1747,6 +1749,14 @@ int thapi_tally_service_info(thapi_tally *t, uint64_t *info, int n) {
   const int m = std::min(n, 6);
   for (int k = 0; k < m; k++) info[k] = v[k];
   return m;
+}
+
+int thapi_tally_last_shape(thapi_tally *t, uint32_t *shape) {
+  if (!t || !shape) return THAPI_E_INVAL;
+  std::lock_guard<std::mutex> run(t->run_mu);
+  if (!t->last_shape[0]) return THAPI_E_STATE;
+  for (int k = 0; k < 4; k++) shape[k] = t->last_shape[k];
+  return THAPI_OK;
 }
 
 int thapi_tally_autotune(thapi_tally *t, uint32_t reps, uint32_t *chosen) {

@@ -39,7 +39,7 @@ ENTRY_POINTS = ["thapi_tally_open", "thapi_tally_submit", "thapi_tally_flush", "
                 "thapi_tally_autotune", "thapi_tally_ticket_done", "thapi_tally_service_info",
                 "thapi_tally_export", "thapi_tally_merge", "thapi_tally_flush_noalloc", "thapi_tally_intervals",
                 "thapi_tally_set_roles", "thapi_tally_copies", "thapi_tally_handles",
-                "thapi_tally_read_bandwidth"]
+                "thapi_tally_read_bandwidth", "thapi_tally_last_shape"]
 NOALLOC_SCRATCH_BYTES = 32 << 20
 
 ROW_DTYPE = np.dtype([
@@ -120,6 +120,7 @@ def load():
     lib.thapi_tally_strerror.restype = ctypes.c_char_p
     lib.thapi_tally_timings.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.c_int]
     lib.thapi_tally_autotune.argtypes = [P, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32)]
+    lib.thapi_tally_last_shape.argtypes = [P, ctypes.POINTER(ctypes.c_uint32)]
     lib.thapi_tally_ticket_done.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]
     lib.thapi_tally_service_info.argtypes = [P, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int]
     for n in ENTRY_POINTS:
@@ -347,6 +348,12 @@ class Tally:
         """Times the queued chunks under each candidate launch shape; returns the chosen (T, E, rpc, pipe)."""
         out = (ctypes.c_uint32 * 4)()
         _check(self._lib.thapi_tally_autotune(self._h, reps, out), "autotune")
+        return tuple(out)
+
+    def last_shape(self):
+        """The launch shape (T, E, rpc, pipe) the last flush chose."""
+        out = (ctypes.c_uint32 * 4)()
+        _check(self._lib.thapi_tally_last_shape(self._h, out), "last_shape")
         return tuple(out)
 
     def timings(self):

@@ -95,6 +95,7 @@ def run_gpu(c: Case, device_input=False, max_threads=4096, max_streams=1024, ext
         t.flush(final=c.final)
         out = read_out(t, c)
         out["timings"] = t.timings()
+        out["shape"] = t.last_shape()
     return out
 
 

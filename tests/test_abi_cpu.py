@@ -92,6 +92,7 @@ def test_strerror_and_argument_errors_without_gpu(lib):
     assert lib.thapi_tally_open(ctypes.byref(c), ctypes.byref(h)) == tally.E_INVAL
     assert lib.thapi_tally_flush(None, 0, 0) == tally.E_INVAL
     assert lib.thapi_tally_flush_noalloc(None, 0, 0) == tally.E_INVAL
+    assert lib.thapi_tally_last_shape(None, None) == tally.E_INVAL
     assert lib.thapi_tally_close(None) == tally.E_INVAL
 
 

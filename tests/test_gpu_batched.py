@@ -55,9 +55,12 @@ SHAPES = ["1024,1024,4,0", "2048,2048,2,0", "1024,2048,1,0", "2048,1024,3,0", "2
 @pytest.mark.parametrize("shape", SHAPES)
 def test_launch_shapes(shape, c3, c1, monkeypatch):
     monkeypatch.setenv("THAPI_TALLY_SHAPE", shape)
+    want = tuple(int(x) for x in shape.split(","))
     for name, (c, o) in (("batched 256 traces", c3), ("layered, 3 chunks per stream", c1)):
         say("case: %s, shape %s" % (name, shape))
-        assert_same(run_gpu(c, max_threads=65536, max_streams=4096), o)
+        g = run_gpu(c, max_threads=65536, max_streams=4096)
+        assert g["shape"] == want, "the flush ran shape %s, not the forced one" % (g["shape"],)
+        assert_same(g, o)
 
 
 @pytest.mark.parametrize("shape", ["1024,2048,2,1", "2048,1024,1,0", "1024,1024,3,0", "2048,1024,2,1"])
@@ -67,7 +70,44 @@ def test_launch_shapes_var16(shape, c2, monkeypatch):
     monkeypatch.setenv("THAPI_TALLY_SHAPE", shape)
     c, o = c2
     say("case: layered VAR16, 2 chunks per stream, shape %s" % shape)
-    assert_same(run_gpu(c, max_threads=4096, max_streams=256), o)
+    g = run_gpu(c, max_threads=4096, max_streams=256)
+    assert g["shape"] == tuple(int(x) for x in shape.split(",")), g["shape"]
+    assert_same(g, o)
+
+
+def test_default_shape_follows_threads_per_stream(c1, c3, monkeypatch):
+    """Without a tuned or forced shape, a handle's first flush runs the
+    pipelined schedule on 2048-record tiles, and later flushes follow the
+    threads per stream seen so far.
+    * The 8 API threads x 200 fns of a layered stream all get direct-mapped
+      rows in the largest tally beside a 4096-record tile, so that tile is used.
+    * The batched traces average about 35 threads, more than ten, so the
+      whole-tile schedule is used.
+    Before any flush there is no shape to report.  Each flush is checked
+    against the oracle."""
+    from paper_2504_03683_amd import tally as T
+    monkeypatch.delenv("THAPI_TALLY_SHAPE", raising=False)
+    for name, (c, o) in (("layered", c1), ("batched 256 traces", c3)):
+        with T.Tally(c.fmt, c.n_fns, c.n_kid, max_depth=c.max_depth, max_threads=65536, max_streams=4096,
+                     has_size=c.has_size) as t:
+            with pytest.raises(T.TallyError) as err:
+                t.last_shape()
+            assert err.value.code == T.E_STATE
+            shapes = []
+            for k in range(2):
+                say("case: default shape, %s, flush %d" % (name, k))
+                t.reset()
+                for key, rec, pay in c.subs:
+                    t.submit(key, rec, pay)
+                t.flush(final=True)
+                shapes.append(t.last_shape())
+                assert_same(read_out(t, c), o)
+        assert shapes[0][0] == 2048 and shapes[0][3] == 1, shapes
+        T2, E2, rpc2, pipe2 = shapes[1]
+        if name == "layered":
+            assert T2 == 4096 and pipe2 == 1 and 8 * c.n_fns <= E2 <= 4096 and E2 % 64 == 0, shapes
+        else:
+            assert T2 == 2048 and pipe2 == 0, shapes
 
 
 def test_batched_equals_per_trace(c3):

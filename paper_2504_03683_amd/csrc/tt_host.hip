@@ -261,7 +261,7 @@ struct thapi_tally {
        *d_tally = nullptr, *d_ktally = nullptr, *d_cstate = nullptr, *d_cstack = nullptr, *d_sstats = nullptr,
        *d_err = nullptr, *d_hs = nullptr, *d_thord = nullptr, *d_snth = nullptr;
   Shape shape{};
-  bool shape_forced = false;                          // THAPI_TALLY_SHAPE gave the shape
+  bool shape_forced = false;                          // THAPI_TALLY_SHAPE gave a shape that fits
   uint64_t seen_threads = 0, seen_streams = 0;        // threads and streams at the end of the last flush
   uint32_t e4096 = 0;                                 // FIXED24: most tally entries beside a 4096-record tile (0: none)
   uint32_t last_shape[4] = {0, 0, 0, 0};              // {T, E, rpc, pipe} of the last flush (T = 0: none yet)
@@ -422,20 +422,22 @@ void free_all(thapi_tally *t) {
 // 64, up to TALLY_E_MAX) as the rest of the LDS holds: more (thread, fn) keys
 // stay in LDS instead of overflowing to the global table.
 // THAPI_TALLY_SHAPE="T,E[,rpc[,pipe]]" overrides the choice (used to tune
-// the launch shape).
+// the launch shape); one that is not valid or does not fit is ignored, and
+// the default then follows the threads per stream as without it.
 constexpr uint32_t TALLY_E_MAX = 4096;
 uint32_t grow_tally(const thapi_tally *t, uint32_t T, uint32_t E, uint32_t KL) {
   const uint32_t D = t->cfg.max_depth;
   while (E + 64 <= TALLY_E_MAX && range_lds_bytes(T, E + 64, KL, D, kfmt(t)) + 256 <= t->lds_limit) E += 64;
   return E;
 }
-Shape pick_shape(const thapi_tally *t) {
+Shape pick_shape(const thapi_tally *t, bool *forced) {
   Shape s{};
   const uint32_t D = t->cfg.max_depth;
   const int fmt = kfmt(t);
   s.KL = std::min<uint32_t>(t->cfg.n_kernel_ids, KL_MAX);
   s.rpc = 1;
   s.pipe = 1;   // producer and walker waves overlap (the faster schedule on the layered workload)
+  *forced = false;
   auto fits = [&](uint32_t T, uint32_t E) {
     size_t b = range_lds_bytes(T, E, s.KL, D, fmt);
     if (b + 256 > t->lds_limit) return false;  // (plus the kernel's static LDS)
@@ -449,6 +451,7 @@ Shape pick_shape(const thapi_tally *t) {
     if (n >= 2 && t_ok && E >= 64 && E % 64 == 0 && rpc >= 1 && rpc <= 64 && pipe <= 1 && fits(T, E)) {
       s.rpc = rpc;
       s.pipe = pipe;
+      *forced = true;
       return s;
     }
   }
@@ -597,11 +600,10 @@ int thapi_tally_open(const thapi_tally_config *cfg, thapi_tally **out) {
       return bail(THAPI_E_DEVICE);
     tb.has_size = (const uint8_t *)t->d_hs;
   }
-  t->shape = pick_shape(t);
+  t->shape = pick_shape(t, &t->shape_forced);
   if (kfmt(t) == 1 && range_lds_bytes(4096, 1024, t->shape.KL, c.max_depth, 1) + 256 <= t->lds_limit)
     t->e4096 = grow_tally(t, 4096, 1024, t->shape.KL);
   if (!t->shape.T) return bail(THAPI_E_INVAL);
-  t->shape_forced = getenv("THAPI_TALLY_SHAPE") != nullptr;
   {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, c.device) == hipSuccess) t->arch = prop.gcnArchName;

@@ -110,6 +110,28 @@ def test_default_shape_follows_threads_per_stream(c1, c3, monkeypatch):
             assert T2 == 2048 and pipe2 == 0, shapes
 
 
+def test_shape_that_does_not_fit_is_ignored(c1, monkeypatch):
+    """A forced shape whose tile and tally do not fit in LDS is ignored: the
+    flushes run the default shapes, 4096-record tiles included, and match the
+    oracle."""
+    from paper_2504_03683_amd import tally as T
+    monkeypatch.setenv("THAPI_TALLY_SHAPE", "4096,4096,1,1")
+    c, o = c1
+    with T.Tally(c.fmt, c.n_fns, c.n_kid, max_depth=c.max_depth, max_threads=65536, max_streams=4096,
+                 has_size=c.has_size) as t:
+        shapes = []
+        for k in range(2):
+            say("case: layered, shape 4096,4096,1,1 (does not fit), flush %d" % k)
+            t.reset()
+            for key, rec, pay in c.subs:
+                t.submit(key, rec, pay)
+            t.flush(final=True)
+            shapes.append(t.last_shape())
+            assert_same(read_out(t, c), o)
+    assert shapes[0][0] == 2048 and shapes[0][1] < 4096, shapes
+    assert shapes[1][0] == 4096 and shapes[1][1] < 4096 and shapes[1][3] == 1, shapes
+
+
 def test_batched_equals_per_trace(c3):
     """One flush over all traces gives, per trace, the rows of that trace tallied alone."""
     from paper_2504_03683_amd import tally as T
